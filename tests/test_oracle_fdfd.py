@@ -1,0 +1,157 @@
+"""Pins for the oracle's FDFD operator, PML and sparse solve (CPU only).
+
+Each test checks the oracle against something other than itself: a closed
+form, an exact discrete identity, a larger domain, or a dense solve.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle.fdfd as fd
+import workloads
+
+H = 1.0 / 20.0
+K0 = 2.0 * math.pi
+
+
+def _line_field(eps, npml, nx=400, i0=200):
+    L, s = fd.assemble(nx, 1, npml, H, np.full((1, nx), eps), K0,
+                       periodic_y=True, pml_y=False)
+    J = np.zeros(nx, complex)
+    J[i0] = 1.0
+    return fd.Solver(L, s).solve(fd.rhs(J, K0))
+
+
+@pytest.mark.parametrize("eps,npml,tol", [
+    (1.0, 8, 6e-4), (1.0, 12, 1.2e-4), (1.0, 16, 4e-5),
+    (2.2, 8, 6e-4), (2.2, 12, 1.2e-4), (2.2, 16, 4e-5),
+    # ~6 cells per wavelength inside eps=11.7: the graded layer reflects more
+    # (measured 1.0e-2, 3.9e-4, 1.1e-4)
+    (11.7, 8, 2.5e-2), (11.7, 12, 8e-4), (11.7, 16, 2.5e-4)])
+def test_1d_closed_form(eps, npml, tol):
+    """1D discrete Green function of the 3-point stencil (periodic y, Ny=1).
+
+    For (E_{i+1} - 2E_i + E_{i-1})/h^2 + k0^2 eps E_i = i k0 delta_{i,i0} the
+    exact outgoing solution is E_i = A exp(-i kappa h |i-i0|) with
+    cos(kappa h) = 1 - k0^2 eps h^2 / 2 and A = -k0 h^2 / (2 sin(kappa h)).
+    The PML-terminated field must match it up to the layer's discretization
+    reflection (measured ~1.6e-4, 3e-5, 1e-5 at 8, 12, 16 cells for eps=1) and must
+    decay inside the layer (a wrong stretch sign grows instead).
+    """
+    nx, i0 = 400, 200
+    E = _line_field(eps, npml, nx, i0)
+    kh = math.acos(1.0 - K0 * K0 * eps * H * H / 2.0)
+    A = -K0 * H * H / (2.0 * math.sin(kh))
+    i = np.arange(nx)
+    Ex = A * np.exp(-1j * kh * np.abs(i - i0))
+    sl = slice(npml + 2, nx - npml - 2)
+    err = np.max(np.abs(E[sl] - Ex[sl])) / abs(A)
+    assert err < tol
+    assert abs(E[0]) < 1e-2 * abs(A) and abs(E[-1]) < 1e-2 * abs(A)
+
+
+def test_1d_reflection_decreases_with_thickness():
+    """Thicker graded PML reflects less (discretization reflection)."""
+    errs = []
+    for npml in (6, 10, 16):
+        E = _line_field(1.0, npml)
+        kh = math.acos(1.0 - K0 * K0 * H * H / 2.0)
+        A = -K0 * H * H / (2.0 * math.sin(kh))
+        i = np.arange(400)
+        Ex = A * np.exp(-1j * kh * np.abs(i - 200))
+        sl = slice(npml + 2, 400 - npml - 2)
+        errs.append(np.max(np.abs(E[sl] - Ex[sl])))
+    assert errs[0] > errs[1] > errs[2]
+
+
+def _energy_terms(E, J, nx, ny, box, k0, h):
+    i0, j0, i1, j1 = box
+    E2 = E.reshape(ny, nx)
+    J2 = J.reshape(ny, nx)
+    lhs = k0 * h * h * np.real(np.sum(np.conj(E2[j0:j1, i0:i1]) * J2[j0:j1, i0:i1]))
+    flux = 0.0
+    for j in range(j0, j1):
+        flux += np.imag(np.conj(E2[j, i0]) * E2[j, i0 - 1])
+        flux += np.imag(np.conj(E2[j, i1 - 1]) * E2[j, i1])
+    for i in range(i0, i1):
+        flux += np.imag(np.conj(E2[j0, i]) * E2[j0 - 1, i])
+        flux += np.imag(np.conj(E2[j1 - 1, i]) * E2[j1, i])
+    return lhs, flux
+
+
+def test_energy_balance():
+    """Exact discrete power balance of the 5-point stencil (summation by parts).
+
+    In a box whose stencil never touches the PML and whose eps is real,
+    k0 h^2 Re sum conj(E) J over the box equals the sum over boundary
+    neighbour pairs (a inside, b outside) of Im(conj(E_a) E_b), to round-off.
+    A source-free dielectric box has zero net flux.
+    """
+    p = workloads.config0()
+    bits = p.init_bits
+    eps = fd.total_eps(p, bits)
+    E = fd.solve(p.nx, p.ny, p.npml, p.h, eps, p.k0[0], p.src[0])
+    J = p.src[0]
+    # box around the source, containing the static block and design
+    lhs, flux = _energy_terms(E, J, p.nx, p.ny, (9, 9, 39, 39), p.k0[0], p.h)
+    assert abs(lhs) > 0
+    assert abs(lhs - flux) < 1e-10 * abs(lhs)
+    # source-free box around the design region only
+    lhs2, flux2 = _energy_terms(E, J, p.nx, p.ny, (18, 18, 30, 30), p.k0[0], p.h)
+    assert lhs2 == 0.0
+    assert abs(flux2) < 1e-10 * abs(lhs)
+
+
+def test_pml_reflection_vs_4x_domain():
+    """A point-source field on 64^2 matches the 4x larger domain's field in the
+    interior up to the PML reflection level (measured 4e-5 at 8 cells,
+    9e-6 at 12 cells relative to the peak)."""
+    def pt(n, npml, src):
+        eps = np.ones((n, n))
+        J = np.zeros(n * n, complex)
+        J[src[1] * n + src[0]] = 1
+        L, s = fd.assemble(n, n, npml, H, eps, K0)
+        return fd.Solver(L, s).solve(fd.rhs(J, K0)).reshape(n, n)
+    for npml, tol in ((8, 1.5e-4), (12, 3e-5)):
+        n = 64
+        E = pt(n, npml, (32, 32))
+        N = 4 * n
+        off = (N - n) // 2
+        sub = pt(N, npml, (32 + off, 32 + off))[off:off + n, off:off + n]
+        sl = slice(npml + 2, n - npml - 2)
+        d = np.abs(E[sl, sl] - sub[sl, sl])
+        assert d.max() / np.abs(sub[sl, sl]).max() < tol
+
+
+def test_operator_symmetric():
+    """diag(s_x s_y) L is complex symmetric (PML included)."""
+    p = workloads.tiny(seed=3, n=24, npml=5, side=4)
+    L, s = fd.assemble(p.nx, p.ny, p.npml, p.h, p.eps_static, p.k0[0])
+    A = (np.diag(s) @ L.toarray())
+    assert np.max(np.abs(A - A.T)) < 1e-12 * np.max(np.abs(A))
+    # the unscaled operator is not symmetric inside the PML
+    Ld = L.toarray()
+    assert np.max(np.abs(Ld - Ld.T)) > 1e-6 * np.max(np.abs(Ld))
+
+
+def test_dense_bruteforce():
+    """Sparse LU + refinement equals a dense numpy solve of the same system."""
+    p = workloads.tiny(seed=1, n=20, npml=4, side=3)
+    eps = fd.total_eps(p, p.init_bits)
+    L, s = fd.assemble(p.nx, p.ny, p.npml, p.h, eps, p.k0[0])
+    b = fd.rhs(p.src[0], p.k0[0])
+    E = fd.Solver(L, s).solve(b)
+    Ed = np.linalg.solve(L.toarray(), b)
+    assert np.max(np.abs(E - Ed)) < 1e-12 * np.max(np.abs(Ed))
+
+
+def test_orderings_agree():
+    """Two fill orderings (COLAMD vs NATURAL) give the same field to << 1e-10."""
+    p = workloads.tiny(seed=2, n=40, npml=6, side=6)
+    eps = fd.total_eps(p, p.init_bits)
+    L, s = fd.assemble(p.nx, p.ny, p.npml, p.h, eps, p.k0[0])
+    b = fd.rhs(p.src[0], p.k0[0])
+    E1 = fd.Solver(L, s, "COLAMD").solve(b)
+    E2 = fd.Solver(L, s, "NATURAL").solve(b)
+    assert np.max(np.abs(E1 - E2)) < 1e-13 * np.max(np.abs(E1))
