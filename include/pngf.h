@@ -1,0 +1,191 @@
+/*
+ * pngf.h -- C ABI of libpngf: the per-iteration hot path of the Precomputed
+ * Numerical Green Function (PNGF) method for pixel inverse design, for one
+ * AMD MI355X (gfx950).
+ *
+ * Problem statement (Results: Precomputation; Direct binary search;
+ * Low-rank update evaluation; Supplementary Note 4, generalized materials):
+ * a static 2D TM (Ez) FDFD environment is folded once into a dense design-
+ * region Green function G (N_d x N_d), the background field b on the design
+ * region and an output projection G_OD (1 x N_d) with background output x_b.
+ * A design with permittivity contrast deps (per pixel, 0 or eps_hi-eps_lo) is
+ * then solved exactly on the design region only:
+ *
+ *     (I - k0^2 G diag(deps)) E = b,      x = x_b + k0^2 G_OD diag(deps) E,
+ *
+ * and direct binary search flips one pixel at a time, keeping C^-1 current
+ * with Sherman-Morrison updates (the rank-1 case, M = 1, of the paper's
+ * Woodbury update, eq. lru_woodbury) and scoring candidate flips from the
+ * current inverse without forming the new one (eq. lru_eobj_rs, here in field
+ * form).  The objective, to be maximized, is f = mean_f |x_f|^2 / norm_f.
+ *
+ * Conventions
+ *   - All calls return int: 0 on success, a negative pngf_status otherwise;
+ *     pngf_last_error(h) (or pngf_last_error(NULL) for a failed create) gives
+ *     a message.  No call aborts the process.
+ *   - Complex arrays are interleaved (re, im) doubles: "cplx[n]" means 2n
+ *     doubles.
+ *   - Every host array passed in is copied; the caller keeps ownership.
+ *   - Device memory is caller-supplied (pngf_bind): the library never
+ *     allocates device memory.  All device work is ordered on the bound HIP
+ *     stream; calls that return host results synchronize that stream.
+ *   - 2D arrays are (ny, nx) row-major, node n = j*nx + i.  Design pixels are
+ *     numbered in that order restricted to the design mask.
+ *   - A handle is not thread-safe; use one handle per thread.
+ */
+#ifndef PNGF_H
+#define PNGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pngf_status {
+  PNGF_OK = 0,
+  PNGF_EINVAL = -1,     /* bad sizes, mask in the PML, pixel out of range  */
+  PNGF_ESINGULAR = -2,  /* zero pivot in a factorization                   */
+  PNGF_ENUMERIC = -3,   /* NaN/Inf or drift that a refresh cannot repair   */
+  PNGF_EDEVICE = -4,    /* HIP runtime error                               */
+  PNGF_ESTATE = -5,     /* call out of order (e.g. not bound, no design)   */
+  PNGF_ENOMEM = -6      /* host allocation failed / workspace too small    */
+} pngf_status;
+
+enum { PNGF_POINT_INTENSITY = 0, PNGF_OVERLAP_INTENSITY = 1,
+       PNGF_MEAN_TRANSMISSION = 2 };
+
+enum { PNGF_FP64_PLAIN = 0, PNGF_MIXED = 1 };
+
+/* pngf_options.flags: record HIP events around every hot-path kernel launch
+ * so pngf_kernel_times can report average device time per kernel. */
+#define PNGF_FLAG_TIMING 1ull
+
+typedef struct pngf_handle pngf_handle;
+
+/* Input problem: the static environment, design region, sources, output
+ * functional and frequencies (Results, Precomputation).  Units: lengths in
+ * lambda0, c0 = eps0 = mu0 = 1, k0 = 2 pi f / f0. */
+typedef struct pngf_problem {
+  int32_t nx, ny, npml;        /* Ez nodes per axis; PML cells per side      */
+  double h;                    /* grid step (units of lambda0)               */
+  const double *eps_static;    /* [ny*nx] real relative permittivity; design */
+                               /* cells must hold eps_lo                     */
+  const uint8_t *design_mask;  /* [ny*nx] 1 = design pixel; must keep one    */
+                               /* cell away from the PML and the grid edge   */
+  double eps_lo, eps_hi;       /* binary pixel levels                        */
+  int32_t nfreq;               /* number of frequencies (>= 1)               */
+  const double *k0;            /* [nfreq]                                    */
+  const double *src;           /* cplx[nfreq*ny*nx] current density J        */
+                               /* (right-hand side i k0 J)                   */
+  int32_t nobj;                /* must be 1                                  */
+  const double *w;             /* cplx[ny*nx] output functional, x = w^T E   */
+  int32_t objective_kind;      /* PNGF_*_INTENSITY / MEAN_TRANSMISSION       */
+  const double *obj_norm;      /* [nfreq] normalizers, or NULL for all 1     */
+} pngf_problem;
+
+typedef struct pngf_options {
+  int32_t precision;    /* PNGF_FP64_PLAIN or PNGF_MIXED                     */
+  int32_t k_refresh;    /* MIXED: FP64 re-inversion every k_refresh accepts  */
+  int32_t max_accepts;  /* capacity of the on-device accept log (>= 1)       */
+  int32_t max_sweeps;   /* largest n_sweeps pngf_dbs_run will be given       */
+  double eta;           /* accept iff f' - f > eta * f (1e-9)                */
+  double guard;         /* MIXED: FP64 re-check band (relative), 0 = auto    */
+  uint64_t flags;       /* PNGF_FLAG_* bits                                  */
+} pngf_options;
+
+/* Result summary of a DBS run. */
+typedef struct pngf_dbs_result {
+  int32_t n_accepted;   /* accepted flips                                    */
+  int32_t sweeps;       /* sweeps started                                    */
+  int32_t converged;    /* 1 if a whole sweep had no improving flip          */
+  int32_t n_refresh;    /* FP64 re-inversions performed (MIXED)              */
+  int64_t attempts;     /* attempted flips (visited positions)               */
+  int64_t n_verified;   /* MIXED: candidates re-checked in FP64              */
+  double f_initial;     /* objective of the initial design                   */
+  double f_final;       /* objective of the final design (FP64)              */
+} pngf_dbs_result;
+
+const char *pngf_version(void);
+const char *pngf_last_error(const pngf_handle *h);
+
+/* Precompute (host, FP64, timed separately).  Assembles the symmetric FDFD
+ * operator with SC-PML, eliminates everything outside the design region with a
+ * band LDL^T of the exterior operator (the Schur-complement idea of the
+ * paper's augmented partial factorization, Results, Precomputation), and
+ * forms per frequency G = -(L^-1)[D,D] (symmetrized), b, G_OD and x_b.
+ * Errors: PNGF_EINVAL for inconsistent sizes or a mask touching the PML,
+ * PNGF_ESINGULAR for a zero pivot, PNGF_ENOMEM. */
+int pngf_precompute(const pngf_problem *p, pngf_handle **out);
+
+/* Copies of the precomputed quantities of frequency fi (host arrays supplied
+ * by the caller; any pointer may be NULL): G cplx[n_d*n_d] row-major,
+ * b cplx[n_d], god cplx[n_d], xb cplx[1]. */
+int pngf_get_precompute(pngf_handle *h, int32_t fi, double *G, double *b,
+                        double *god, double *xb);
+
+/* Number of design pixels / frequencies of the handle. */
+int pngf_sizes(pngf_handle *h, int32_t *n_d, int32_t *nfreq);
+
+/* Host seconds spent in pngf_precompute. */
+int pngf_precompute_seconds(pngf_handle *h, double *seconds);
+
+/* Device bytes pngf_bind needs for these options. */
+int pngf_workspace_bytes(pngf_handle *h, const pngf_options *o, size_t *bytes);
+
+/* Bind caller-owned device memory (>= pngf_workspace_bytes, 256-byte aligned)
+ * and a hipStream_t (NULL = default stream); uploads G, b, G_OD, x_b.
+ * PNGF_ENOMEM if bytes is too small. */
+int pngf_bind(pngf_handle *h, const pngf_options *o, void *dev_ws, size_t bytes,
+              void *hip_stream);
+
+/* Set the design (bits[n_d], 0/1) and form the initial inverse
+ * C0^-1 = (I - k0^2 G diag(deps))^-1, E = C0^-1 b, the output row
+ * R' = G_OD (I + k0^2 diag(deps) C0^-1 G) and x (Direct binary search: the
+ * inverse of the initial system matrix is found and stored).  FP64 LU with
+ * partial pivoting on the GPU.  PNGF_ESINGULAR on a zero pivot. */
+int pngf_set_design(pngf_handle *h, const uint8_t *bits);
+
+/* Current objective f, outputs x cplx[nfreq] and (optional, may be NULL)
+ * design fields e_d cplx[nfreq*n_d]. */
+int pngf_evaluate(pngf_handle *h, double *f, double *x, double *e_d);
+
+/* Exact objective after flipping each candidate alone from the current state
+ * (eq. lru_eobj_rs with M = 1; O(N_d) per candidate).  cand[n] pixel ids,
+ * f_new[n] out.  PNGF_EINVAL for ids out of range. */
+int pngf_score_flips(pngf_handle *h, const int32_t *cand, int32_t n,
+                     double *f_new);
+
+/* Accept the flips pix[n] one after another (Sherman-Morrison update of C^-1,
+ * E, R' and x; eq. lru_woodbury with M = 1). */
+int pngf_accept_flips(pngf_handle *h, const int32_t *pix, int32_t n);
+
+/* Re-form C^-1 from G and the current design by FP64 LU (direct re-inversion,
+ * Results, Computational efficiency), with one step of iterative refinement of
+ * E against C. */
+int pngf_refresh(pngf_handle *h);
+
+/* Direct binary search on the device (Results, Direct binary search):
+ * perms[n_sweeps*n_d] are the visiting orders of the sweeps; a flip is kept
+ * iff f' - f > eta f; after a keep the sweep continues at the next position;
+ * the run stops when a whole sweep keeps nothing (converged), after n_sweeps
+ * sweeps, or after max_accepts keeps.  accepted[max_accepts] receives the
+ * kept pixels, f_trace[max_accepts] the objective after each (either may be
+ * NULL).  Starts from the design set by pngf_set_design. */
+int pngf_dbs_run(pngf_handle *h, const int32_t *perms, int32_t n_sweeps,
+                 int32_t *accepted, double *f_trace, pngf_dbs_result *res);
+
+/* Average device time (ms, HIP events on the bound stream) and launch count
+ * of the kernels of the last pngf_dbs_run, per kernel id:
+ * 0 score, 1 select/prep, 2 accept+rescore, 3 LU/inverse, 4 refresh other. */
+int pngf_kernel_times(pngf_handle *h, int32_t kernel_id, double *total_ms,
+                      int64_t *launches);
+
+int pngf_destroy(pngf_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PNGF_H */

@@ -147,6 +147,8 @@ def dbs(prob, bits0=None, perms=None, eta=ETA, workers=1, tie_band=1e-7,
                         break
                 if taken is None:
                     pos = batch[-1] + 1
+                    if progress is not None:
+                        progress(res)
                     continue
                 q, fn = taken
                 m = int(perms[s, q])

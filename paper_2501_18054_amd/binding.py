@@ -1,0 +1,246 @@
+"""ctypes binding of libpngf (argument marshalling only).
+
+Every computation runs inside libpngf: its host precompute and its HIP
+kernels.  PyTorch only provides the device workspace (one uint8 tensor) and
+the HIP stream.  The module fails loudly when libpngf.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpngf.so")
+
+PNGF_FP64_PLAIN = 0
+PNGF_MIXED = 1
+PNGF_FLAG_TIMING = 1
+
+KERNEL_IDS = {"score": 0, "select": 1, "accept": 2, "lu": 3, "other": 4}
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ESINGULAR", -3: "ENUMERIC", -4: "EDEVICE",
+           -5: "ESTATE", -6: "ENOMEM"}
+
+
+class PngfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pngf {_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("npml", C.c_int32),
+                ("h", C.c_double),
+                ("eps_static", C.POINTER(C.c_double)),
+                ("design_mask", C.POINTER(C.c_uint8)),
+                ("eps_lo", C.c_double), ("eps_hi", C.c_double),
+                ("nfreq", C.c_int32), ("k0", C.POINTER(C.c_double)),
+                ("src", C.POINTER(C.c_double)),
+                ("nobj", C.c_int32), ("w", C.POINTER(C.c_double)),
+                ("objective_kind", C.c_int32),
+                ("obj_norm", C.POINTER(C.c_double))]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("k_refresh", C.c_int32),
+                ("max_accepts", C.c_int32), ("max_sweeps", C.c_int32),
+                ("eta", C.c_double), ("guard", C.c_double), ("flags", C.c_uint64)]
+
+
+class DbsResult(C.Structure):
+    _fields_ = [("n_accepted", C.c_int32), ("sweeps", C.c_int32),
+                ("converged", C.c_int32), ("n_refresh", C.c_int32),
+                ("attempts", C.c_int64), ("n_verified", C.c_int64),
+                ("f_initial", C.c_double), ("f_final", C.c_double)]
+
+
+_lib = None
+
+EXPORTS = {
+    "pngf_version": ([], C.c_char_p),
+    "pngf_last_error": ([C.c_void_p], C.c_char_p),
+    "pngf_precompute": ([C.POINTER(Problem), C.POINTER(C.c_void_p)], C.c_int),
+    "pngf_get_precompute": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p], C.c_int),
+    "pngf_sizes": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "pngf_precompute_seconds": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    "pngf_workspace_bytes": ([C.c_void_p, C.POINTER(Options), C.POINTER(C.c_size_t)], C.c_int),
+    "pngf_bind": ([C.c_void_p, C.POINTER(Options), C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "pngf_set_design": ([C.c_void_p, C.c_void_p], C.c_int),
+    "pngf_evaluate": ([C.c_void_p, C.POINTER(C.c_double), C.c_void_p, C.c_void_p], C.c_int),
+    "pngf_score_flips": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "pngf_accept_flips": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
+    "pngf_refresh": ([C.c_void_p], C.c_int),
+    "pngf_dbs_run": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                      C.POINTER(DbsResult)], C.c_int),
+    "pngf_kernel_times": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                           C.POINTER(C.c_int64)], C.c_int),
+    "pngf_destroy": ([C.c_void_p], C.c_int),
+}
+
+
+def lib():
+    """Load libpngf.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2501_18054_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _cplx(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def default_options(precision=PNGF_FP64_PLAIN, max_accepts=1 << 16, max_sweeps=32,
+                    eta=1e-9, k_refresh=32, guard=0.0, timing=False):
+    return Options(precision, k_refresh, max_accepts, max_sweeps, eta, guard,
+                   PNGF_FLAG_TIMING if timing else 0)
+
+
+class Handle:
+    """One precomputed problem plus its device state (see include/pngf.h)."""
+
+    def __init__(self, prob):
+        L = lib()
+        self._keep = dict(
+            eps=np.ascontiguousarray(prob.eps_static, dtype=np.float64),
+            mask=np.ascontiguousarray(prob.design_mask, dtype=np.uint8),
+            k0=np.ascontiguousarray(prob.k0, dtype=np.float64),
+            src=_cplx(prob.src), w=_cplx(prob.w),
+            norm=np.ascontiguousarray(prob.obj_norm, dtype=np.float64))
+        k = self._keep
+        p = Problem(prob.nx, prob.ny, prob.npml, prob.h,
+                    k["eps"].ctypes.data_as(C.POINTER(C.c_double)),
+                    k["mask"].ctypes.data_as(C.POINTER(C.c_uint8)),
+                    prob.eps_lo, prob.eps_hi, prob.nfreq,
+                    k["k0"].ctypes.data_as(C.POINTER(C.c_double)),
+                    k["src"].ctypes.data_as(C.POINTER(C.c_double)),
+                    int(prob.w.shape[0]),
+                    k["w"].ctypes.data_as(C.POINTER(C.c_double)),
+                    int(prob.objective_kind),
+                    k["norm"].ctypes.data_as(C.POINTER(C.c_double)))
+        h = C.c_void_p()
+        rc = L.pngf_precompute(C.byref(p), C.byref(h))
+        if rc != 0:
+            raise PngfError(rc, L.pngf_last_error(None).decode())
+        self._h = h
+        nd, nf = C.c_int32(), C.c_int32()
+        L.pngf_sizes(h, C.byref(nd), C.byref(nf))
+        self.n_d, self.nfreq = nd.value, nf.value
+        self._ws = None
+        self._keep = None
+
+    # ---------------------------------------------------------------- utils
+    def _check(self, rc):
+        if rc != 0:
+            raise PngfError(rc, lib().pngf_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pngf_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- precompute
+    def precompute_seconds(self):
+        s = C.c_double()
+        self._check(lib().pngf_precompute_seconds(self._h, C.byref(s)))
+        return s.value
+
+    def get_precompute(self, fi=0):
+        nd = self.n_d
+        G = np.empty((nd, nd), np.complex128)
+        b = np.empty(nd, np.complex128)
+        god = np.empty(nd, np.complex128)
+        xb = np.empty(1, np.complex128)
+        self._check(lib().pngf_get_precompute(self._h, fi, _ptr(G), _ptr(b), _ptr(god), _ptr(xb)))
+        return G, b, god, complex(xb[0])
+
+    # --------------------------------------------------------------- device
+    def workspace_bytes(self, opts):
+        n = C.c_size_t()
+        self._check(lib().pngf_workspace_bytes(self._h, C.byref(opts), C.byref(n)))
+        return n.value
+
+    def bind(self, opts=None, device="cuda:0", stream=None):
+        """Allocate the workspace as a torch tensor and bind it with a stream."""
+        import torch
+        opts = opts or default_options()
+        nbytes = self.workspace_bytes(opts)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        if stream is None:
+            stream = torch.cuda.current_stream(torch.device(device))
+        self._stream = stream
+        self._check(lib().pngf_bind(self._h, C.byref(opts), C.c_void_p(aligned),
+                                    nbytes, C.c_void_p(stream.cuda_stream)))
+        self.opts = opts
+        return self
+
+    def set_design(self, bits):
+        b = np.ascontiguousarray(bits, dtype=np.uint8)
+        assert b.shape == (self.n_d,)
+        self._check(lib().pngf_set_design(self._h, _ptr(b)))
+
+    def evaluate(self, fields=False):
+        f = C.c_double()
+        x = np.empty(self.nfreq, np.complex128)
+        e = np.empty((self.nfreq, self.n_d), np.complex128) if fields else None
+        self._check(lib().pngf_evaluate(self._h, C.byref(f), _ptr(x), _ptr(e)))
+        return (f.value, x, e) if fields else (f.value, x)
+
+    def score_flips(self, cand):
+        c = np.ascontiguousarray(cand, dtype=np.int32)
+        out = np.empty(c.shape[0], np.float64)
+        self._check(lib().pngf_score_flips(self._h, _ptr(c), c.shape[0], _ptr(out)))
+        return out
+
+    def accept_flips(self, pix):
+        p = np.ascontiguousarray(pix, dtype=np.int32)
+        self._check(lib().pngf_accept_flips(self._h, _ptr(p), p.shape[0]))
+
+    def refresh(self):
+        self._check(lib().pngf_refresh(self._h))
+
+    def dbs_run(self, perms):
+        perms = np.ascontiguousarray(perms, dtype=np.int32)
+        ns = perms.shape[0]
+        cap = self.opts.max_accepts
+        acc = np.empty(cap, np.int32)
+        ftr = np.empty(cap, np.float64)
+        res = DbsResult()
+        self._check(lib().pngf_dbs_run(self._h, _ptr(perms), ns, _ptr(acc), _ptr(ftr),
+                                       C.byref(res)))
+        n = res.n_accepted
+        return dict(accepted=acc[:n].copy(), f_trace=ftr[:n].copy(), n_accepted=n,
+                    sweeps=res.sweeps, converged=bool(res.converged),
+                    attempts=int(res.attempts), n_refresh=res.n_refresh,
+                    n_verified=int(res.n_verified), f_initial=res.f_initial,
+                    f_final=res.f_final)
+
+    def kernel_times(self, name):
+        t = C.c_double()
+        n = C.c_int64()
+        self._check(lib().pngf_kernel_times(self._h, KERNEL_IDS[name], C.byref(t), C.byref(n)))
+        return t.value, n.value

@@ -1,0 +1,58 @@
+// Device-side helpers shared by the libpngf HIP kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pngf {
+
+constexpr int kMaxFreq = 8;
+constexpr int kRowThreads = 256;   // one workgroup streams one matrix row
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+
+struct z64 { double re, im; };
+struct z32 { float re, im; };
+
+__device__ __forceinline__ z64 zmul(z64 a, z64 b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ z64 zadd(z64 a, z64 b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ z64 zsub(z64 a, z64 b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ z64 zscale(z64 a, double s) { return {a.re * s, a.im * s}; }
+__device__ __forceinline__ z64 zdiv(z64 a, z64 b) {
+  double d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+__device__ __forceinline__ z64 zfma(z64 a, z64 b, z64 c) {  // a*b + c
+  return {fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+__device__ __forceinline__ double zabs2(z64 a) { return a.re * a.re + a.im * a.im; }
+
+// Sum over a full workgroup of kRowThreads lanes; result valid in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Workgroup reduction of a complex double; `red` is LDS of >= 2*(threads/64)
+// doubles.  Ends with a barrier so `red` may be reused.
+__device__ __forceinline__ z64 block_zsum(z64 v, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  v.re = wave_sum(v.re);
+  v.im = wave_sum(v.im);
+  if (lane == 0) { red[2 * wid] = v.re; red[2 * wid + 1] = v.im; }
+  __syncthreads();
+  z64 s{0.0, 0.0};
+  for (int w = 0; w < nw; ++w) { s.re += red[2 * w]; s.im += red[2 * w + 1]; }
+  __syncthreads();
+  return s;
+}
+
+}  // namespace pngf

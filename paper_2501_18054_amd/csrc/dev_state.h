@@ -1,0 +1,51 @@
+// Device-visible state and argument blocks of the libpngf hot path.
+#pragma once
+
+#include "dev_common.h"
+
+namespace pngf {
+
+// DBS bookkeeping kept in device memory so that a whole search runs without
+// host round trips (written by the select/prep kernel, read by the others).
+struct DbsState {
+  int32_t m;           // pixel being accepted by the pending update, -1 none
+  int32_t done;        // search finished
+  int32_t cursor_s;    // current sweep
+  int32_t cursor_pos;  // next position to visit in the current sweep
+  int32_t n_acc;       // accepted flips so far
+  int32_t sweeps;      // sweeps started
+  int32_t converged;   // a whole sweep kept nothing
+  int32_t n_sweeps;    // sweep cap of this run
+  int64_t attempts;    // visited positions
+  uint32_t key;        // min over improving candidates (atomicMin target)
+  int32_t pad0;
+  double f;            // current objective
+  double eta;          // acceptance threshold
+  z64 x[kMaxFreq];     // current outputs per frequency
+  z64 alpha[kMaxFreq]; // k0^2 delta / den of the pending update
+  z64 Em[kMaxFreq];    // E[m] before the pending update
+  z64 Rpm[kMaxFreq];   // R'[m] before the pending update
+};
+
+// Everything a hot-path kernel needs, passed by value (kernel arguments).
+struct ProbDev {
+  int32_t nd, ld, nfreq, max_acc;
+  double deps;                 // eps_hi - eps_lo
+  double k0sq[kMaxFreq];       // k0^2 per frequency
+  double coef[kMaxFreq];       // 1 / (nfreq * norm_f)
+  z64* G[kMaxFreq];            // nd x ld, symmetric
+  z64* Cinv[kMaxFreq];         // nd x ld, current inverse
+  z64* E[kMaxFreq];            // design field
+  z64* Rp[kMaxFreq];           // output row R'
+  z64* tau[kMaxFreq];          // (C^-1 G)[i,i] at the current state
+  z64* q[kMaxFreq];            // copy of C^-1[m,:] for the pending update
+  uint8_t* bits;               // design
+  const int32_t* perm;         // [n_sweeps][nd] visiting orders
+  const int32_t* rank;         // [n_sweeps][nd] position of pixel in order
+  int32_t* log_pix;            // [max_acc]
+  double* log_f;               // [max_acc]
+  double* df;                  // per-candidate objective change (scoring)
+  DbsState* st;
+};
+
+}  // namespace pngf

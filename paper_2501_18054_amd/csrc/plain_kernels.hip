@@ -1,0 +1,260 @@
+// FP64 plain-path kernels of libpngf (gfx950): candidate scoring, select,
+// and the fused Sherman-Morrison accept + rescore pass.
+//
+// Field form of the PNGF system (Supplementary Note 4, C = I + Y G, written
+// for fields): C = I - k0^2 G diag(deps), E = C^-1 b, and the output row
+// R' = G_OD (I + k0^2 diag(deps) C^-1 G), so that x = x_b + k0^2 G_OD D E.
+// Flipping pixel m by delta changes C by the rank-1 term -k0^2 delta g_m e_m^T
+// (eq. lru_dcn with M = 1).  With tau_m = (C^-1 G)[m,m] and
+// den = 1 - k0^2 delta tau_m the candidate output is
+//     x' = x + (k0^2 delta E[m] / den) R'[m]                  (eq. lru_eobj_rs)
+// and accepting it updates (eq. lru_woodbury with M = 1, alpha = k0^2 delta/den)
+//     p = C^-1 g_m,  q = C^-1[m,:],  C^-1 += alpha p q^T,
+//     E += alpha E[m] p,  R' += alpha R'[m] p,  x += alpha E[m] R'[m].
+// G is symmetric (reciprocity), so tau_i = sum_j C^-1[i,j] G[i,j] and
+// g_m = G[m,:]: every operand is streamed along rows (coalesced).
+//
+// Bandwidth plan: one 256-thread workgroup per matrix row; lanes hold the row
+// of C^-1 in registers between the two reductions of the fused pass, so HBM
+// sees one read and one write of C^-1 and one read of G per accept
+// (3 N_d^2 x 16 B); g_m and q are re-read by every row from L2.
+#include "dev_state.h"
+
+namespace pngf {
+
+__device__ __forceinline__ uint32_t cand_key(const ProbDev& P, const DbsState* st, int i) {
+  const int s = st->cursor_s;
+  if (s >= st->n_sweeps) return kNoKey;
+  const int pos = P.rank[size_t(s) * P.nd + i];
+  if (pos >= st->cursor_pos) return uint32_t(pos);
+  if (s + 1 < st->n_sweeps) return uint32_t(P.nd + P.rank[size_t(s + 1) * P.nd + i]);
+  return kNoKey;
+}
+
+// Objective change of flipping pixel i given tau_f(i) (lane-0 epilogue).
+__device__ __forceinline__ double flip_df(const ProbDev& P, const DbsState* st, int f,
+                                          z64 tau, z64 Ei, z64 Rpi, double delta) {
+  const double kd = P.k0sq[f] * delta;
+  const z64 den = {1.0 - kd * tau.re, -kd * tau.im};
+  const z64 dx = zdiv(zscale(zmul(Ei, Rpi), kd), den);
+  const z64 x = st->x[f];
+  return P.coef[f] * (2.0 * (x.re * dx.re + x.im * dx.im) + zabs2(dx));
+}
+
+// K1: tau_i = sum_j C^-1[i,j] G[i,j] for each candidate row and its exact
+// objective change; with use_key, improving candidates compete for the
+// smallest visiting key.
+template <int NPL>
+__global__ __launch_bounds__(kRowThreads) void k_score_rows(ProbDev P, const int32_t* cand,
+                                                            int ncand, int use_key) {
+  __shared__ double red[2 * (kRowThreads / 64)];
+  const int r = blockIdx.x;
+  if (r >= ncand) return;
+  const int i = cand ? cand[r] : r;
+  const int tid = threadIdx.x;
+  const DbsState* st = P.st;
+  const double delta = P.bits[i] ? -P.deps : P.deps;
+  double df = 0.0;
+  for (int f = 0; f < P.nfreq; ++f) {
+    const z64* C = P.Cinv[f] + size_t(i) * P.ld;
+    const z64* Gi = P.G[f] + size_t(i) * P.ld;
+    z64 acc{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int j = tid + t * kRowThreads;
+      if (j < P.nd) acc = zfma(C[j], Gi[j], acc);
+    }
+    const z64 tau = block_zsum(acc, red);
+    if (tid == 0) {
+      P.tau[f][i] = tau;
+      df += flip_df(P, st, f, tau, P.E[f][i], P.Rp[f][i], delta);
+    }
+  }
+  if (tid == 0) {
+    P.df[r] = df;
+    if (use_key && df > st->eta * st->f) {
+      const uint32_t k = cand_key(P, st, i);
+      if (k != kNoKey) atomicMin(&P.st->key, k);
+    }
+  }
+}
+
+// K2: select the first improving candidate in visiting order (the minimum
+// key), advance the cursor, form the update scalars of the accepted flip and
+// stage q = C^-1[m,:].  forced >= 0 accepts that pixel instead.
+__global__ __launch_bounds__(kRowThreads) void k_select_prep(ProbDev P, int forced) {
+  __shared__ int s_m;
+  DbsState* st = P.st;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    int m = -1;
+    const int nd = P.nd;
+    if (!st->done) {
+      if (forced >= 0) {
+        m = forced;
+      } else if (st->n_acc >= P.max_acc || st->cursor_s >= st->n_sweeps) {
+        st->done = 1;
+        st->converged = 0;
+      } else {
+        const uint32_t key = st->key;
+        const int s = st->cursor_s, c = st->cursor_pos, ns = st->n_sweeps;
+        if (key == kNoKey) {
+          // Nothing improves at this state: the rest of this sweep is visited
+          // and, if this sweep kept something, one more full sweep.
+          const bool next = (c > 0) && (s + 1 < ns);
+          st->attempts += (nd - c) + (next ? nd : 0);
+          st->converged = (c == 0) || next;
+          st->sweeps = s + 1 + (next ? 1 : 0);
+          st->done = 1;
+        } else {
+          int s2 = s, pos = int(key);
+          if (int(key) >= nd) {
+            s2 = s + 1;
+            pos = int(key) - nd;
+            st->attempts += (nd - c) + pos + 1;
+          } else {
+            st->attempts += pos - c + 1;
+          }
+          m = P.perm[size_t(s2) * nd + pos];
+          st->sweeps = s2 + 1;
+          if (pos + 1 < nd) {
+            st->cursor_s = s2;
+            st->cursor_pos = pos + 1;
+          } else {
+            st->cursor_s = s2 + 1;
+            st->cursor_pos = 0;
+          }
+        }
+      }
+    }
+    st->key = kNoKey;
+    if (m >= 0) {
+      const double delta = P.bits[m] ? -P.deps : P.deps;
+      double fnew = 0.0;
+      for (int f = 0; f < P.nfreq; ++f) {
+        const double kd = P.k0sq[f] * delta;
+        const z64 tau = P.tau[f][m];
+        const z64 den = {1.0 - kd * tau.re, -kd * tau.im};
+        const z64 alpha = zdiv(z64{kd, 0.0}, den);
+        const z64 Em = P.E[f][m], Rpm = P.Rp[f][m];
+        st->alpha[f] = alpha;
+        st->Em[f] = Em;
+        st->Rpm[f] = Rpm;
+        const z64 x = zfma(zmul(alpha, Em), Rpm, st->x[f]);
+        st->x[f] = x;
+        fnew += P.coef[f] * zabs2(x);
+      }
+      P.bits[m] ^= 1;
+      st->f = fnew;
+      if (forced < 0) {
+        P.log_pix[st->n_acc] = m;
+        P.log_f[st->n_acc] = fnew;
+        st->n_acc += 1;
+      }
+    }
+    st->m = m;
+    s_m = m;
+  }
+  __syncthreads();
+  const int m = s_m;
+  if (m < 0) return;
+  for (int f = 0; f < P.nfreq; ++f) {
+    const z64* src = P.Cinv[f] + size_t(m) * P.ld;
+    z64* dst = P.q[f];
+    for (int j = tid; j < P.nd; j += kRowThreads) dst[j] = src[j];
+  }
+}
+
+// K3: fused accept + rescore.  Row i: p_i = C^-1[i,:] . g_m, then
+// C^-1[i,:] += alpha p_i q, E[i], R'[i] updated, and tau_i of the new state
+// from the updated row and G[i,:]; the new state's candidate i is scored.
+template <int NPL>
+__global__ __launch_bounds__(kRowThreads) void k_accept_rescore(ProbDev P) {
+  __shared__ double red[2 * (kRowThreads / 64)];
+  const DbsState* st = P.st;
+  const int m = st->m;
+  if (m < 0) return;
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double delta = P.bits[i] ? -P.deps : P.deps;
+  double df = 0.0;
+  for (int f = 0; f < P.nfreq; ++f) {
+    z64* C = P.Cinv[f] + size_t(i) * P.ld;
+    const z64* gm = P.G[f] + size_t(m) * P.ld;
+    const z64* Gi = P.G[f] + size_t(i) * P.ld;
+    const z64* q = P.q[f];
+    z64 row[NPL];
+    z64 acc{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int j = tid + t * kRowThreads;
+      if (j < P.nd) {
+        row[t] = C[j];
+        acc = zfma(row[t], gm[j], acc);
+      }
+    }
+    const z64 p = block_zsum(acc, red);
+    const z64 ap = zmul(st->alpha[f], p);
+    acc = z64{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int j = tid + t * kRowThreads;
+      if (j < P.nd) {
+        row[t] = zfma(ap, q[j], row[t]);
+        C[j] = row[t];
+        acc = zfma(row[t], Gi[j], acc);
+      }
+    }
+    const z64 tau = block_zsum(acc, red);
+    if (tid == 0) {
+      const z64 Ei = zadd(P.E[f][i], zmul(ap, st->Em[f]));
+      const z64 Rpi = zadd(P.Rp[f][i], zmul(ap, st->Rpm[f]));
+      P.E[f][i] = Ei;
+      P.Rp[f][i] = Rpi;
+      P.tau[f][i] = tau;
+      df += flip_df(P, st, f, tau, Ei, Rpi, delta);
+    }
+  }
+  if (tid == 0) {
+    P.df[i] = df;
+    if (df > st->eta * st->f) {
+      const uint32_t k = cand_key(P, st, i);
+      if (k != kNoKey) atomicMin(&P.st->key, k);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+#define PNGF_NPL_SWITCH(npl, CALL) \
+  switch (npl) {                   \
+    case 1: CALL(1); break;        \
+    case 2: CALL(2); break;        \
+    case 4: CALL(4); break;        \
+    case 8: CALL(8); break;        \
+    case 16: CALL(16); break;      \
+    case 32: CALL(32); break;      \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int ncand,
+                             int use_key, hipStream_t s) {
+  if (ncand <= 0) return hipSuccess;
+#define L_(N) hipLaunchKernelGGL(k_score_rows<N>, dim3(ncand), dim3(kRowThreads), 0, s, P, cand, ncand, use_key)
+  PNGF_NPL_SWITCH(npl, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_select_prep(const ProbDev& P, int forced, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_prep, dim3(1), dim3(kRowThreads), 0, s, P, forced);
+  return hipGetLastError();
+}
+
+hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s) {
+#define L_(N) hipLaunchKernelGGL(k_accept_rescore<N>, dim3(P.nd), dim3(kRowThreads), 0, s, P)
+  PNGF_NPL_SWITCH(npl, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+}  // namespace pngf

@@ -1,0 +1,575 @@
+// C ABI of libpngf: handles, workspace binding and the device-side DBS driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dev_state.h"
+#include "pngf_internal.h"
+
+namespace pngf {
+hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int ncand,
+                             int use_key, hipStream_t s);
+hipError_t launch_select_prep(const ProbDev& P, int forced, hipStream_t s);
+hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s);
+}  // namespace pngf
+
+using pngf::cd;
+using pngf::z64;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+enum KernelId { KID_SCORE = 0, KID_SELECT = 1, KID_ACCEPT = 2, KID_LU = 3, KID_OTHER = 4, KID_N = 8 };
+
+struct Layout {
+  size_t off_G[pngf::kMaxFreq], off_C[pngf::kMaxFreq], off_E[pngf::kMaxFreq],
+      off_Rp[pngf::kMaxFreq], off_tau[pngf::kMaxFreq], off_q[pngf::kMaxFreq];
+  size_t off_bits, off_perm, off_rank, off_cand, off_df, off_logp, off_logf, off_state;
+  size_t total;
+};
+
+}  // namespace
+
+struct pngf_handle {
+  pngf::Precomputed pc;
+  std::string err;
+  pngf_options opt{};
+  bool bound = false;
+  bool have_design = false;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int ld = 0, npl = 1;
+  Layout lay{};
+  pngf::ProbDev P{};
+  std::vector<uint8_t> bits;
+  double f_host = 0.0;
+  // event timing
+  double ktime_ms[KID_N] = {0};
+  int64_t klaunch[KID_N] = {0};
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+int fail(pngf_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg; else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(h, call)                                                        \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return fail(h, PNGF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int npl_for(int nd) {
+  int need = (nd + pngf::kRowThreads - 1) / pngf::kRowThreads;
+  int n = 1;
+  while (n < need) n *= 2;
+  return n;
+}
+
+Layout make_layout(const pngf_handle* h, const pngf_options* o) {
+  Layout L{};
+  const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t r = off; off = align256(off + bytes); return r; };
+  const size_t mat = size_t(nd) * ld * sizeof(z64), vec = size_t(ld) * sizeof(z64);
+  for (int f = 0; f < F; ++f) {
+    L.off_G[f] = take(mat);
+    L.off_C[f] = take(mat);
+    L.off_E[f] = take(vec);
+    L.off_Rp[f] = take(vec);
+    L.off_tau[f] = take(vec);
+    L.off_q[f] = take(vec);
+  }
+  const int ms = std::max(1, o->max_sweeps), ma = std::max(1, o->max_accepts);
+  L.off_bits = take(size_t(nd));
+  L.off_perm = take(size_t(ms) * nd * sizeof(int32_t));
+  L.off_rank = take(size_t(ms) * nd * sizeof(int32_t));
+  L.off_cand = take(size_t(nd) * sizeof(int32_t));
+  L.off_df = take(size_t(nd) * sizeof(double));
+  L.off_logp = take(size_t(ma) * sizeof(int32_t));
+  L.off_logf = take(size_t(ma) * sizeof(double));
+  L.off_state = take(sizeof(pngf::DbsState));
+  L.total = off;
+  return L;
+}
+
+template <class T>
+T* at(pngf_handle* h, size_t off) { return reinterpret_cast<T*>(h->ws + off); }
+
+int check_ready(pngf_handle* h, bool need_design) {
+  if (!h) return PNGF_EINVAL;
+  if (!h->bound) return fail(h, PNGF_ESTATE, "handle is not bound to a workspace");
+  if (need_design && !h->have_design) return fail(h, PNGF_ESTATE, "no design set");
+  return PNGF_OK;
+}
+
+// Timed launch helper: records events around the launch when timing is on.
+struct Timer {
+  pngf_handle* h;
+  int kid;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timer(pngf_handle* hh, int k) : h(hh), kid(k) {
+    if (h->opt.flags & PNGF_FLAG_TIMING) {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      hipEventRecord(a, h->stream);
+    }
+  }
+  void end() {
+    if (a) {
+      hipEventRecord(b, h->stream);
+      h->ev_pool.push_back(a);
+      h->ev_pool.push_back(b);
+      h->ev_pool.push_back(reinterpret_cast<hipEvent_t>(intptr_t(kid)));
+    }
+  }
+};
+
+void collect_times(pngf_handle* h) {
+  for (size_t k = 0; k + 2 < h->ev_pool.size() + 0; k += 3) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, h->ev_pool[k], h->ev_pool[k + 1]);
+    int kid = int(reinterpret_cast<intptr_t>(h->ev_pool[k + 2]));
+    h->ktime_ms[kid] += ms;
+    h->klaunch[kid] += 1;
+    hipEventDestroy(h->ev_pool[k]);
+    hipEventDestroy(h->ev_pool[k + 1]);
+  }
+  h->ev_pool.clear();
+}
+
+// Host FP64 initial inverse (Gauss-Jordan with partial pivoting) and the
+// derived state E, R', x for the current design.
+int host_initial_state(pngf_handle* h, std::vector<std::vector<cd>>& Cinv,
+                       std::vector<std::vector<cd>>& E, std::vector<std::vector<cd>>& Rp,
+                       std::vector<cd>& x, double* f) {
+  const int nd = h->pc.n_d, F = int(h->pc.freq.size());
+  const double deps = h->pc.eps_hi - h->pc.eps_lo;
+  Cinv.assign(F, {});
+  E.assign(F, {});
+  Rp.assign(F, {});
+  x.assign(F, 0.0);
+  double fsum = 0.0;
+  for (int fi = 0; fi < F; ++fi) {
+    const pngf::FreqData& Fd = h->pc.freq[fi];
+    const double k2 = Fd.k0 * Fd.k0;
+    std::vector<cd>& C = Cinv[fi];
+    C.assign(size_t(nd) * nd, 0.0);
+    for (int a = 0; a < nd; ++a)
+      for (int c = 0; c < nd; ++c)
+        C[size_t(a) * nd + c] =
+            (a == c ? 1.0 : 0.0) - k2 * Fd.G[size_t(a) * nd + c] * (h->bits[c] ? deps : 0.0);
+    int st = pngf::dense_inverse(C.data(), nd, nd);
+    if (st != PNGF_OK) return fail(h, st, "singular PNGF system matrix");
+    std::vector<cd> u(nd), v(nd, 0.0);
+    E[fi].assign(nd, 0.0);
+    Rp[fi].assign(nd, 0.0);
+    for (int c = 0; c < nd; ++c) u[c] = (h->bits[c] ? deps : 0.0) * Fd.god[c];
+    for (int a = 0; a < nd; ++a) {
+      cd s = 0.0;
+      for (int c = 0; c < nd; ++c) s += Fd.G[size_t(a) * nd + c] * u[c];
+      v[a] = s;
+    }
+    cd xs = Fd.xb;
+    for (int a = 0; a < nd; ++a) {
+      cd se = 0.0, sr = 0.0;
+      for (int c = 0; c < nd; ++c) {
+        se += C[size_t(a) * nd + c] * Fd.b[c];
+        sr += C[size_t(a) * nd + c] * v[c];
+      }
+      E[fi][a] = se;
+      Rp[fi][a] = Fd.god[a] + k2 * sr;
+    }
+    for (int a = 0; a < nd; ++a) xs += k2 * Fd.god[a] * (h->bits[a] ? deps : 0.0) * E[fi][a];
+    x[fi] = xs;
+    fsum += std::norm(xs) / (Fd.norm * F);
+  }
+  *f = fsum;
+  return PNGF_OK;
+}
+
+int upload_matrix(pngf_handle* h, z64* dst, const std::vector<cd>& src, int nd) {
+  HIPCHK(h, hipMemcpy2DAsync(dst, size_t(h->ld) * sizeof(z64), src.data(), size_t(nd) * sizeof(z64),
+                             size_t(nd) * sizeof(z64), nd, hipMemcpyHostToDevice, h->stream));
+  return PNGF_OK;
+}
+
+int read_state(pngf_handle* h, pngf::DbsState* st) {
+  HIPCHK(h, hipMemcpyAsync(st, h->P.st, sizeof(*st), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PNGF_OK;
+}
+
+int write_state(pngf_handle* h, const pngf::DbsState* st) {
+  HIPCHK(h, hipMemcpyAsync(h->P.st, st, sizeof(*st), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PNGF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pngf_version(void) { return "pngf 0.1 (gfx950)"; }
+
+const char* pngf_last_error(const pngf_handle* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int pngf_precompute(const pngf_problem* p, pngf_handle** out) {
+  if (!out) return fail(nullptr, PNGF_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (p && p->nfreq > pngf::kMaxFreq)
+    return fail(nullptr, PNGF_EINVAL, "at most 8 frequencies per handle");
+  pngf_handle* h = new (std::nothrow) pngf_handle();
+  if (!h) return fail(nullptr, PNGF_ENOMEM, "out of host memory");
+  std::string err;
+  int st;
+  try {
+    st = pngf::precompute(p, &h->pc, &err);
+  } catch (const std::bad_alloc&) {
+    st = PNGF_ENOMEM;
+    err = "out of host memory in precompute";
+  }
+  if (st != PNGF_OK) {
+    delete h;
+    return fail(nullptr, st, err);
+  }
+  h->ld = ((h->pc.n_d + 63) / 64) * 64;
+  h->npl = npl_for(h->pc.n_d);
+  h->bits.assign(h->pc.n_d, 0);
+  *out = h;
+  return PNGF_OK;
+}
+
+int pngf_sizes(pngf_handle* h, int32_t* n_d, int32_t* nfreq) {
+  if (!h) return PNGF_EINVAL;
+  if (n_d) *n_d = h->pc.n_d;
+  if (nfreq) *nfreq = int32_t(h->pc.freq.size());
+  return PNGF_OK;
+}
+
+int pngf_precompute_seconds(pngf_handle* h, double* s) {
+  if (!h || !s) return PNGF_EINVAL;
+  *s = h->pc.seconds;
+  return PNGF_OK;
+}
+
+int pngf_get_precompute(pngf_handle* h, int32_t fi, double* G, double* b, double* god,
+                        double* xb) {
+  if (!h) return PNGF_EINVAL;
+  if (fi < 0 || fi >= int(h->pc.freq.size())) return fail(h, PNGF_EINVAL, "frequency index out of range");
+  const pngf::FreqData& F = h->pc.freq[fi];
+  const size_t nd = h->pc.n_d;
+  if (G) std::memcpy(G, F.G.data(), nd * nd * sizeof(cd));
+  if (b) std::memcpy(b, F.b.data(), nd * sizeof(cd));
+  if (god) std::memcpy(god, F.god.data(), nd * sizeof(cd));
+  if (xb) std::memcpy(xb, &F.xb, sizeof(cd));
+  return PNGF_OK;
+}
+
+int pngf_workspace_bytes(pngf_handle* h, const pngf_options* o, size_t* bytes) {
+  if (!h || !o || !bytes) return PNGF_EINVAL;
+  if (o->precision != PNGF_FP64_PLAIN)
+    return fail(h, PNGF_EINVAL, "only PNGF_FP64_PLAIN is available in this build");
+  *bytes = make_layout(h, o).total;
+  return PNGF_OK;
+}
+
+int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes, void* stream) {
+  if (!h || !o || !dev_ws) return PNGF_EINVAL;
+  if (o->precision != PNGF_FP64_PLAIN)
+    return fail(h, PNGF_EINVAL, "only PNGF_FP64_PLAIN is available in this build");
+  if (o->max_accepts < 1 || o->max_sweeps < 1)
+    return fail(h, PNGF_EINVAL, "max_accepts and max_sweeps must be >= 1");
+  if (reinterpret_cast<uintptr_t>(dev_ws) & 255)
+    return fail(h, PNGF_EINVAL, "workspace must be 256-byte aligned");
+  Layout L = make_layout(h, o);
+  if (bytes < L.total) return fail(h, PNGF_ENOMEM, "workspace too small");
+  h->opt = *o;
+  h->lay = L;
+  h->ws = static_cast<char*>(dev_ws);
+  h->ws_bytes = bytes;
+  h->stream = static_cast<hipStream_t>(stream);
+  const int nd = h->pc.n_d, F = int(h->pc.freq.size());
+  pngf::ProbDev& P = h->P;
+  P = pngf::ProbDev{};
+  P.nd = nd;
+  P.ld = h->ld;
+  P.nfreq = F;
+  P.max_acc = o->max_accepts;
+  P.deps = h->pc.eps_hi - h->pc.eps_lo;
+  for (int f = 0; f < F; ++f) {
+    P.k0sq[f] = h->pc.freq[f].k0 * h->pc.freq[f].k0;
+    P.coef[f] = 1.0 / (F * h->pc.freq[f].norm);
+    P.G[f] = at<z64>(h, L.off_G[f]);
+    P.Cinv[f] = at<z64>(h, L.off_C[f]);
+    P.E[f] = at<z64>(h, L.off_E[f]);
+    P.Rp[f] = at<z64>(h, L.off_Rp[f]);
+    P.tau[f] = at<z64>(h, L.off_tau[f]);
+    P.q[f] = at<z64>(h, L.off_q[f]);
+  }
+  P.bits = at<uint8_t>(h, L.off_bits);
+  P.perm = at<int32_t>(h, L.off_perm);
+  P.rank = at<int32_t>(h, L.off_rank);
+  P.log_pix = at<int32_t>(h, L.off_logp);
+  P.log_f = at<double>(h, L.off_logf);
+  P.df = at<double>(h, L.off_df);
+  P.st = at<pngf::DbsState>(h, L.off_state);
+  // Zero the padded matrix storage once (padding columns are never read, but
+  // keep them defined), then upload G.
+  HIPCHK(h, hipMemsetAsync(h->ws, 0, L.total, h->stream));
+  for (int f = 0; f < F; ++f) {
+    int st = upload_matrix(h, P.G[f], h->pc.freq[f].G, nd);
+    if (st) return st;
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->bound = true;
+  h->have_design = false;
+  return PNGF_OK;
+}
+
+int pngf_set_design(pngf_handle* h, const uint8_t* bits) {
+  int st = check_ready(h, false);
+  if (st) return st;
+  if (!bits) return fail(h, PNGF_EINVAL, "null bits");
+  const int nd = h->pc.n_d, F = int(h->pc.freq.size());
+  for (int a = 0; a < nd; ++a) h->bits[a] = bits[a] ? 1 : 0;
+  std::vector<std::vector<cd>> Cinv, E, Rp;
+  std::vector<cd> x;
+  double f = 0.0;
+  st = host_initial_state(h, Cinv, E, Rp, x, &f);
+  if (st) return st;
+  for (int fi = 0; fi < F; ++fi) {
+    st = upload_matrix(h, h->P.Cinv[fi], Cinv[fi], nd);
+    if (st) return st;
+    HIPCHK(h, hipMemcpyAsync(h->P.E[fi], E[fi].data(), nd * sizeof(z64), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->P.Rp[fi], Rp[fi].data(), nd * sizeof(z64), hipMemcpyHostToDevice, h->stream));
+  }
+  HIPCHK(h, hipMemcpyAsync(h->P.bits, h->bits.data(), nd, hipMemcpyHostToDevice, h->stream));
+  pngf::DbsState s{};
+  s.m = -1;
+  s.key = pngf::kNoKey;
+  s.f = f;
+  s.eta = h->opt.eta;
+  for (int fi = 0; fi < F; ++fi) s.x[fi] = z64{x[fi].real(), x[fi].imag()};
+  st = write_state(h, &s);
+  if (st) return st;
+  h->f_host = f;
+  h->have_design = true;
+  return PNGF_OK;
+}
+
+int pngf_evaluate(pngf_handle* h, double* f, double* x, double* e_d) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  pngf::DbsState s;
+  st = read_state(h, &s);
+  if (st) return st;
+  const int F = int(h->pc.freq.size()), nd = h->pc.n_d;
+  if (f) *f = s.f;
+  if (x)
+    for (int fi = 0; fi < F; ++fi) { x[2 * fi] = s.x[fi].re; x[2 * fi + 1] = s.x[fi].im; }
+  if (e_d) {
+    for (int fi = 0; fi < F; ++fi)
+      HIPCHK(h, hipMemcpyAsync(e_d + size_t(fi) * 2 * nd, h->P.E[fi], nd * sizeof(z64),
+                               hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
+  return PNGF_OK;
+}
+
+int pngf_score_flips(pngf_handle* h, const int32_t* cand, int32_t n, double* f_new) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  if (n < 0 || n > h->pc.n_d || (n > 0 && (!cand || !f_new)))
+    return fail(h, PNGF_EINVAL, "bad candidate list");
+  for (int r = 0; r < n; ++r)
+    if (cand[r] < 0 || cand[r] >= h->pc.n_d) return fail(h, PNGF_EINVAL, "candidate out of range");
+  if (n == 0) return PNGF_OK;
+  int32_t* dcand = at<int32_t>(h, h->lay.off_cand);
+  HIPCHK(h, hipMemcpyAsync(dcand, cand, n * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, dcand, n, 0, h->stream));
+  std::vector<double> df(n);
+  HIPCHK(h, hipMemcpyAsync(df.data(), h->P.df, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  pngf::DbsState s;
+  st = read_state(h, &s);
+  if (st) return st;
+  for (int r = 0; r < n; ++r) f_new[r] = s.f + df[r];
+  return PNGF_OK;
+}
+
+int pngf_accept_flips(pngf_handle* h, const int32_t* pix, int32_t n) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  if (n < 0 || (n > 0 && !pix)) return fail(h, PNGF_EINVAL, "bad pixel list");
+  for (int r = 0; r < n; ++r)
+    if (pix[r] < 0 || pix[r] >= h->pc.n_d) return fail(h, PNGF_EINVAL, "pixel out of range");
+  pngf::DbsState s;
+  st = read_state(h, &s);
+  if (st) return st;
+  s.done = 0;
+  s.n_sweeps = 0;
+  st = write_state(h, &s);
+  if (st) return st;
+  // tau of the current state for every pixel (needed by the update scalars).
+  HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, h->pc.n_d, 0, h->stream));
+  for (int r = 0; r < n; ++r) {
+    HIPCHK(h, pngf::launch_select_prep(h->P, pix[r], h->stream));
+    HIPCHK(h, pngf::launch_accept_rescore(h->P, h->npl, h->stream));
+    h->bits[pix[r]] ^= 1;
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PNGF_OK;
+}
+
+int pngf_refresh(pngf_handle* h) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  const int nd = h->pc.n_d;
+  HIPCHK(h, hipMemcpyAsync(h->bits.data(), h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  std::vector<uint8_t> b = h->bits;
+  pngf::DbsState s;
+  st = read_state(h, &s);
+  if (st) return st;
+  st = pngf_set_design(h, b.data());
+  if (st) return st;
+  pngf::DbsState s2;
+  st = read_state(h, &s2);
+  if (st) return st;
+  // keep the search bookkeeping, take the re-formed objective and outputs
+  for (int fi = 0; fi < pngf::kMaxFreq; ++fi) s.x[fi] = s2.x[fi];
+  s.f = s2.f;
+  s.key = pngf::kNoKey;
+  s.m = -1;
+  return write_state(h, &s);
+}
+
+int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t* accepted,
+                 double* f_trace, pngf_dbs_result* res) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  const int nd = h->pc.n_d;
+  if (!perms || n_sweeps < 1 || n_sweeps > h->opt.max_sweeps)
+    return fail(h, PNGF_EINVAL, "n_sweeps must be in [1, max_sweeps]");
+  std::vector<int32_t> rank(size_t(n_sweeps) * nd, -1);
+  for (int s = 0; s < n_sweeps; ++s)
+    for (int q = 0; q < nd; ++q) {
+      const int32_t m = perms[size_t(s) * nd + q];
+      if (m < 0 || m >= nd || rank[size_t(s) * nd + m] != -1)
+        return fail(h, PNGF_EINVAL, "perms must hold permutations of the pixel ids");
+      rank[size_t(s) * nd + m] = q;
+    }
+  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.perm), perms, rank.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.rank), rank.data(), rank.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, h->stream));
+  pngf::DbsState s;
+  st = read_state(h, &s);
+  if (st) return st;
+  const double f0 = s.f;
+  s.m = -1;
+  s.done = 0;
+  s.cursor_s = 0;
+  s.cursor_pos = 0;
+  s.n_acc = 0;
+  s.sweeps = 0;
+  s.converged = 0;
+  s.n_sweeps = n_sweeps;
+  s.attempts = 0;
+  s.key = pngf::kNoKey;
+  s.eta = h->opt.eta;
+  st = write_state(h, &s);
+  if (st) return st;
+  for (int k = 0; k < KID_N; ++k) { h->ktime_ms[k] = 0.0; h->klaunch[k] = 0; }
+  {
+    Timer t(h, KID_SCORE);
+    HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, nd, 1, h->stream));
+    t.end();
+  }
+  const int batch = 32;
+  const int64_t max_steps = int64_t(h->opt.max_accepts) + 2;
+  pngf::DbsState* pinned = nullptr;
+  HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(pngf::DbsState)));
+  int64_t steps = 0;
+  int rc = PNGF_OK;
+  while (steps < max_steps) {
+    for (int b = 0; b < batch; ++b, ++steps) {
+      {
+        Timer t(h, KID_SELECT);
+        hipError_t e = pngf::launch_select_prep(h->P, -1, h->stream);
+        if (e != hipSuccess) { rc = fail(h, PNGF_EDEVICE, hipGetErrorString(e)); break; }
+        t.end();
+      }
+      {
+        Timer t(h, KID_ACCEPT);
+        hipError_t e = pngf::launch_accept_rescore(h->P, h->npl, h->stream);
+        if (e != hipSuccess) { rc = fail(h, PNGF_EDEVICE, hipGetErrorString(e)); break; }
+        t.end();
+      }
+    }
+    if (rc) break;
+    hipError_t e = hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) { rc = fail(h, PNGF_EDEVICE, hipGetErrorString(e)); break; }
+    if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+    if (pinned->done) break;
+  }
+  if (rc == PNGF_OK && !pinned->done) rc = fail(h, PNGF_ENUMERIC, "DBS did not terminate");
+  pngf::DbsState fin = *pinned;
+  hipHostFree(pinned);
+  if (rc) return rc;
+  const int na = fin.n_acc;
+  if (accepted && na > 0)
+    HIPCHK(h, hipMemcpyAsync(accepted, h->P.log_pix, na * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  if (f_trace && na > 0)
+    HIPCHK(h, hipMemcpyAsync(f_trace, h->P.log_f, na * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->bits.data(), h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (!std::isfinite(fin.f)) return fail(h, PNGF_ENUMERIC, "objective is not finite");
+  if (res) {
+    res->n_accepted = na;
+    res->sweeps = fin.sweeps;
+    res->converged = fin.converged;
+    res->n_refresh = 0;
+    res->attempts = fin.attempts;
+    res->n_verified = 0;
+    res->f_initial = f0;
+    res->f_final = fin.f;
+  }
+  h->f_host = fin.f;
+  return PNGF_OK;
+}
+
+int pngf_kernel_times(pngf_handle* h, int32_t kid, double* total_ms, int64_t* launches) {
+  if (!h || kid < 0 || kid >= KID_N) return PNGF_EINVAL;
+  if (total_ms) *total_ms = h->ktime_ms[kid];
+  if (launches) *launches = h->klaunch[kid];
+  return PNGF_OK;
+}
+
+int pngf_destroy(pngf_handle* h) {
+  if (!h) return PNGF_OK;
+  for (size_t k = 0; k + 2 < h->ev_pool.size(); k += 3) {
+    hipEventDestroy(h->ev_pool[k]);
+    hipEventDestroy(h->ev_pool[k + 1]);
+  }
+  delete h;
+  return PNGF_OK;
+}
+
+}  // extern "C"

@@ -12,6 +12,10 @@ import os
 import sys
 import time
 
+# one BLAS / OpenMP thread per process: parallelism comes from the worker pool
+for _v in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_v] = "1"
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
