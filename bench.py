@@ -18,6 +18,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+def log(msg):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
 METRIC = "flip evals/s + time-to-design, mixed vs FP64 plain, ≤1e-6 rel objective err"
 HBM_PEAK_GBS = 8000.0
 
@@ -58,9 +63,11 @@ def main():
     import paper_2501_18054_amd as P
 
     prob = workloads.config1()
+    log("precompute (host) ...")
     t0 = time.perf_counter()
     h = P.Handle(prob)
     t_pre = time.perf_counter() - t0
+    log(f"precompute done in {t_pre:.1f} s; binding")
     h.bind(P.default_options(max_accepts=8192, max_sweeps=8, timing=True))
     stream = torch.cuda.current_stream()
 
@@ -68,13 +75,15 @@ def main():
         h.set_design(prob.init_bits)
         return h.dbs_run(prob.perms)
 
-    for _ in range(a.warmup):
-        one_run()
+    for w in range(a.warmup):
+        r = one_run()
+        log(f"warmup run {w}: {r['n_accepted']} accepts, {r['attempts']} attempts")
     torch.cuda.synchronize()
     results = []
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for k in range(a.steps):
         results.append(one_run())
+        log(f"timed run {k} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     attempts = sum(r["attempts"] for r in results)
@@ -110,6 +119,7 @@ def main():
                     "score_avg_us": 1e3 * t_sc / max(n_sc, 1)},
     }
     if not a.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(prob)
     h.close()
     print(json.dumps(out))

@@ -82,9 +82,16 @@ EXPORTS = {
 
 
 def lib():
-    """Load libpngf.so (built in-tree); raise if it is missing."""
+    """Load libpngf.so (built in-tree); raise if it is missing.
+
+    torch is imported first so that its HIP runtime is the one libpngf binds
+    to (the dynamic linker matches libpngf's libamdhip64.so.7 dependency to the
+    already-loaded copy by SONAME); two HIP runtimes in one process would not
+    share devices, memory or streams.
+    """
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (loads the process-wide HIP runtime)
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2501_18054_amd.build`")

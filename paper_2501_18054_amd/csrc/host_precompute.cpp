@@ -93,47 +93,57 @@ Operator build_operator(const Grid& g, const std::vector<double>& eps, double k0
 
 // Band LDL^T (no pivoting) of a complex-symmetric matrix with lower bandwidth
 // bw.  band[k*(bw+1) + t] holds A(k+t, k) on entry and L(k+t, k) (t > 0) /
-// D(k) (t = 0) on exit.
+// D(k) (t = 0) on exit.  Blocked by kLdlNb columns: a block is factored
+// serially with its updates confined to the block, then the columns the block
+// reaches (up to bw beyond it) receive the deferred rank-kLdlNb update in
+// parallel, one OpenMP region per block.
+constexpr int kLdlNb = 32;
+
 int band_ldlt(std::vector<cd>& band, int64_t N, int bw) {
   const int W = bw + 1;
-  std::vector<cd> l(W);
-  int status = PNGF_OK;
-#pragma omp parallel
-  {
-    for (int64_t k = 0; k < N; ++k) {
-#pragma omp single
-      {
-        cd d = band[k * W];
-        if (std::abs(d) == 0.0 || !std::isfinite(d.real()) || !std::isfinite(d.imag())) {
-          status = PNGF_ESINGULAR;
-          d = 1.0;
-        }
-        cd inv = 1.0 / d;
-        const int tmax = int(std::min<int64_t>(bw, N - 1 - k));
-        for (int t = 1; t <= tmax; ++t) l[t] = band[k * W + t] * inv;
-        for (int t = tmax + 1; t <= bw; ++t) l[t] = 0.0;
-      }
+  std::vector<cd> a(W);
+  for (int64_t k0 = 0; k0 < N; k0 += kLdlNb) {
+    const int64_t kend = std::min<int64_t>(N, k0 + kLdlNb);
+    for (int64_t k = k0; k < kend; ++k) {
       const cd d = band[k * W];
+      if (std::abs(d) == 0.0 || !std::isfinite(d.real()) || !std::isfinite(d.imag()))
+        return PNGF_ESINGULAR;
+      const cd inv = 1.0 / d;
       const int tmax = int(std::min<int64_t>(bw, N - 1 - k));
-#pragma omp for schedule(static, 8)
       for (int t = 1; t <= tmax; ++t) {
-        const cd lt = l[t];
-        if (lt == cd(0.0, 0.0)) continue;
-        const cd at = lt * d;
-        cd* row = &band[(k + t) * W];
-        // A(k+t2, k+t) -= l(t2) * d * l(t) for t2 = t..tmax
-        const double ar = at.real(), ai = at.imag();
-        for (int t2 = t; t2 <= tmax; ++t2) {
-          const double lr = l[t2].real(), li = l[t2].imag();
-          double* r = reinterpret_cast<double*>(&row[t2 - t]);
-          r[0] -= lr * ar - li * ai;
-          r[1] -= lr * ai + li * ar;
+        a[t] = band[k * W + t];
+        band[k * W + t] = a[t] * inv;
+      }
+      const int tin = int(std::min<int64_t>(tmax, kend - 1 - k));
+      for (int t = 1; t <= tin; ++t) {
+        const cd at = a[t];
+        if (at == cd(0.0, 0.0)) continue;
+        cd* col = &band[(k + t) * W];
+        const cd* lk = &band[k * W];
+        for (int t2 = t; t2 <= tmax; ++t2) col[t2 - t] -= lk[t2] * at;
+      }
+    }
+    const int64_t jmax = std::min<int64_t>(N, kend + bw);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = kend; j < jmax; ++j) {
+      cd* col = &band[j * W];
+      for (int64_t c = std::max<int64_t>(k0, j - bw); c < kend; ++c) {
+        const cd* Lc = &band[c * W];
+        const cd ld = Lc[j - c] * Lc[0];
+        if (ld == cd(0.0, 0.0)) continue;
+        const int64_t imax = std::min<int64_t>(c + bw, N - 1);
+        const double lr = ld.real(), li = ld.imag();
+        double* out = reinterpret_cast<double*>(col);
+        const double* lc = reinterpret_cast<const double*>(Lc);
+        for (int64_t i = j; i <= imax; ++i) {
+          const double xr = lc[2 * (i - c)], xi = lc[2 * (i - c) + 1];
+          out[2 * (i - j)] -= xr * lr - xi * li;
+          out[2 * (i - j) + 1] -= xr * li + xi * lr;
         }
-        band[k * W + t] = lt;
       }
     }
   }
-  return status;
+  return PNGF_OK;
 }
 
 // Y <- L^-1 Y for the unit lower band factor; Y is N x K row-major.

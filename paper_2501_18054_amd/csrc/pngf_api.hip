@@ -16,6 +16,15 @@ hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int
                              int use_key, hipStream_t s);
 hipError_t launch_select_prep(const ProbDev& P, int forced, hipStream_t s);
 hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s);
+hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const uint8_t* bits,
+                          double k2d, z64* B1, int32_t* piv, int32_t* inv_p, int32_t* used,
+                          int32_t* status, hipStream_t s);
+hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t* bits, double ds,
+                       z64 alpha, z64 beta, const z64* w, double gamma, const z64* w2, z64* y,
+                       hipStream_t s);
+hipError_t launch_output(const ProbDev& P, int f, const z64* god, z64 xb, int last,
+                         hipStream_t s);
+constexpr int kGjNbHost = 16;
 }  // namespace pngf
 
 using pngf::cd;
@@ -32,7 +41,9 @@ enum KernelId { KID_SCORE = 0, KID_SELECT = 1, KID_ACCEPT = 2, KID_LU = 3, KID_O
 struct Layout {
   size_t off_G[pngf::kMaxFreq], off_C[pngf::kMaxFreq], off_E[pngf::kMaxFreq],
       off_Rp[pngf::kMaxFreq], off_tau[pngf::kMaxFreq], off_q[pngf::kMaxFreq];
+  size_t off_b[pngf::kMaxFreq], off_god[pngf::kMaxFreq];
   size_t off_bits, off_perm, off_rank, off_cand, off_df, off_logp, off_logf, off_state;
+  size_t off_S, off_B1, off_piv, off_invp, off_used, off_status, off_u, off_r;
   size_t total;
 };
 
@@ -92,7 +103,17 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_Rp[f] = take(vec);
     L.off_tau[f] = take(vec);
     L.off_q[f] = take(vec);
+    L.off_b[f] = take(vec);
+    L.off_god[f] = take(vec);
   }
+  L.off_S = take(mat);
+  L.off_B1 = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
+  L.off_piv = take(size_t(nd) * sizeof(int32_t));
+  L.off_invp = take(size_t(nd) * sizeof(int32_t));
+  L.off_used = take(size_t(nd) * sizeof(int32_t));
+  L.off_status = take(sizeof(int32_t));
+  L.off_u = take(vec);
+  L.off_r = take(vec);
   const int ms = std::max(1, o->max_sweeps), ma = std::max(1, o->max_accepts);
   L.off_bits = take(size_t(nd));
   L.off_perm = take(size_t(ms) * nd * sizeof(int32_t));
@@ -151,53 +172,56 @@ void collect_times(pngf_handle* h) {
   h->ev_pool.clear();
 }
 
-// Host FP64 initial inverse (Gauss-Jordan with partial pivoting) and the
-// derived state E, R', x for the current design.
-int host_initial_state(pngf_handle* h, std::vector<std::vector<cd>>& Cinv,
-                       std::vector<std::vector<cd>>& E, std::vector<std::vector<cd>>& Rp,
-                       std::vector<cd>& x, double* f) {
-  const int nd = h->pc.n_d, F = int(h->pc.freq.size());
-  const double deps = h->pc.eps_hi - h->pc.eps_lo;
-  Cinv.assign(F, {});
-  E.assign(F, {});
-  Rp.assign(F, {});
-  x.assign(F, 0.0);
-  double fsum = 0.0;
-  for (int fi = 0; fi < F; ++fi) {
-    const pngf::FreqData& Fd = h->pc.freq[fi];
-    const double k2 = Fd.k0 * Fd.k0;
-    std::vector<cd>& C = Cinv[fi];
-    C.assign(size_t(nd) * nd, 0.0);
-    for (int a = 0; a < nd; ++a)
-      for (int c = 0; c < nd; ++c)
-        C[size_t(a) * nd + c] =
-            (a == c ? 1.0 : 0.0) - k2 * Fd.G[size_t(a) * nd + c] * (h->bits[c] ? deps : 0.0);
-    int st = pngf::dense_inverse(C.data(), nd, nd);
-    if (st != PNGF_OK) return fail(h, st, "singular PNGF system matrix");
-    std::vector<cd> u(nd), v(nd, 0.0);
-    E[fi].assign(nd, 0.0);
-    Rp[fi].assign(nd, 0.0);
-    for (int c = 0; c < nd; ++c) u[c] = (h->bits[c] ? deps : 0.0) * Fd.god[c];
-    for (int a = 0; a < nd; ++a) {
-      cd s = 0.0;
-      for (int c = 0; c < nd; ++c) s += Fd.G[size_t(a) * nd + c] * u[c];
-      v[a] = s;
+// Re-form C^-1 (FP64, on the device) from G and the device design bits for
+// every frequency, then E = C^-1 b with one refinement step against C, the
+// output row R' = G_OD + k0^2 C^-1 G diag(deps) G_OD and x, f.
+int device_reinvert(pngf_handle* h) {
+  const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
+  const Layout& L = h->lay;
+  pngf::ProbDev& P = h->P;
+  z64* S = at<z64>(h, L.off_S);
+  z64* B1 = at<z64>(h, L.off_B1);
+  int32_t* piv = at<int32_t>(h, L.off_piv);
+  int32_t* invp = at<int32_t>(h, L.off_invp);
+  int32_t* used = at<int32_t>(h, L.off_used);
+  int32_t* status = at<int32_t>(h, L.off_status);
+  z64* u = at<z64>(h, L.off_u);
+  z64* r = at<z64>(h, L.off_r);
+  const z64 one{1.0, 0.0}, zero{0.0, 0.0};
+  HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
+  for (int f = 0; f < F; ++f) {
+    const double k2 = P.k0sq[f];
+    const z64* b = at<z64>(h, L.off_b[f]);
+    const z64* god = at<z64>(h, L.off_god[f]);
+    {
+      Timer t(h, KID_LU);
+      HIPCHK(h, pngf::launch_inverse(S, P.Cinv[f], P.G[f], nd, ld, P.bits, k2 * P.deps, B1, piv,
+                                     invp, used, status, h->stream));
+      t.end();
     }
-    cd xs = Fd.xb;
-    for (int a = 0; a < nd; ++a) {
-      cd se = 0.0, sr = 0.0;
-      for (int c = 0; c < nd; ++c) {
-        se += C[size_t(a) * nd + c] * Fd.b[c];
-        sr += C[size_t(a) * nd + c] * v[c];
-      }
-      E[fi][a] = se;
-      Rp[fi][a] = Fd.god[a] + k2 * sr;
-    }
-    for (int a = 0; a < nd; ++a) xs += k2 * Fd.god[a] * (h->bits[a] ? deps : 0.0) * E[fi][a];
-    x[fi] = xs;
-    fsum += std::norm(xs) / (Fd.norm * F);
+    Timer t(h, KID_OTHER);
+    // E = C^-1 b
+    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, b, nullptr, 0.0, one, zero, nullptr, 0.0,
+                                nullptr, P.E[f], h->stream));
+    // r = b - E + k0^2 G diag(deps) E ;  E += C^-1 r
+    HIPCHK(h, pngf::launch_gemv(P.G[f], ld, nd, P.E[f], P.bits, P.deps, z64{k2, 0.0}, one, b,
+                                -1.0, P.E[f], r, h->stream));
+    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, r, nullptr, 0.0, one, one, P.E[f], 0.0,
+                                nullptr, P.E[f], h->stream));
+    // u = G diag(deps) G_OD ; R' = G_OD + k0^2 C^-1 u
+    HIPCHK(h, pngf::launch_gemv(P.G[f], ld, nd, god, P.bits, P.deps, one, zero, nullptr, 0.0,
+                                nullptr, u, h->stream));
+    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, u, nullptr, 0.0, z64{k2, 0.0}, one, god, 0.0,
+                                nullptr, P.Rp[f], h->stream));
+    const cd xb = h->pc.freq[f].xb;
+    HIPCHK(h, pngf::launch_output(P, f, god, z64{xb.real(), xb.imag()}, f == F - 1, h->stream));
+    t.end();
   }
-  *f = fsum;
+  int32_t st_host = 0;
+  HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  if (st_host) return fail(h, PNGF_ESINGULAR, "zero pivot while inverting the PNGF system matrix");
   return PNGF_OK;
 }
 
@@ -335,6 +359,10 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   for (int f = 0; f < F; ++f) {
     int st = upload_matrix(h, P.G[f], h->pc.freq[f].G, nd);
     if (st) return st;
+    HIPCHK(h, hipMemcpyAsync(at<z64>(h, L.off_b[f]), h->pc.freq[f].b.data(), nd * sizeof(z64),
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(at<z64>(h, L.off_god[f]), h->pc.freq[f].god.data(), nd * sizeof(z64),
+                             hipMemcpyHostToDevice, h->stream));
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->bound = true;
@@ -346,29 +374,18 @@ int pngf_set_design(pngf_handle* h, const uint8_t* bits) {
   int st = check_ready(h, false);
   if (st) return st;
   if (!bits) return fail(h, PNGF_EINVAL, "null bits");
-  const int nd = h->pc.n_d, F = int(h->pc.freq.size());
+  const int nd = h->pc.n_d;
   for (int a = 0; a < nd; ++a) h->bits[a] = bits[a] ? 1 : 0;
-  std::vector<std::vector<cd>> Cinv, E, Rp;
-  std::vector<cd> x;
-  double f = 0.0;
-  st = host_initial_state(h, Cinv, E, Rp, x, &f);
-  if (st) return st;
-  for (int fi = 0; fi < F; ++fi) {
-    st = upload_matrix(h, h->P.Cinv[fi], Cinv[fi], nd);
-    if (st) return st;
-    HIPCHK(h, hipMemcpyAsync(h->P.E[fi], E[fi].data(), nd * sizeof(z64), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->P.Rp[fi], Rp[fi].data(), nd * sizeof(z64), hipMemcpyHostToDevice, h->stream));
-  }
   HIPCHK(h, hipMemcpyAsync(h->P.bits, h->bits.data(), nd, hipMemcpyHostToDevice, h->stream));
   pngf::DbsState s{};
   s.m = -1;
   s.key = pngf::kNoKey;
-  s.f = f;
   s.eta = h->opt.eta;
-  for (int fi = 0; fi < F; ++fi) s.x[fi] = z64{x[fi].real(), x[fi].imag()};
   st = write_state(h, &s);
   if (st) return st;
-  h->f_host = f;
+  h->have_design = false;
+  st = device_reinvert(h);
+  if (st) return st;
   h->have_design = true;
   return PNGF_OK;
 }
@@ -439,24 +456,8 @@ int pngf_accept_flips(pngf_handle* h, const int32_t* pix, int32_t n) {
 int pngf_refresh(pngf_handle* h) {
   int st = check_ready(h, true);
   if (st) return st;
-  const int nd = h->pc.n_d;
-  HIPCHK(h, hipMemcpyAsync(h->bits.data(), h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  std::vector<uint8_t> b = h->bits;
-  pngf::DbsState s;
-  st = read_state(h, &s);
-  if (st) return st;
-  st = pngf_set_design(h, b.data());
-  if (st) return st;
-  pngf::DbsState s2;
-  st = read_state(h, &s2);
-  if (st) return st;
-  // keep the search bookkeeping, take the re-formed objective and outputs
-  for (int fi = 0; fi < pngf::kMaxFreq; ++fi) s.x[fi] = s2.x[fi];
-  s.f = s2.f;
-  s.key = pngf::kNoKey;
-  s.m = -1;
-  return write_state(h, &s);
+  // The search bookkeeping in the device state is kept; x and f are re-formed.
+  return device_reinvert(h);
 }
 
 int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t* accepted,
