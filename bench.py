@@ -63,6 +63,12 @@ def main():
     import paper_2501_18054_amd as P
 
     prob = workloads.config1()
+    cpu = None
+    if not a.no_cpu_baseline:
+        # before any GPU initialization: the oracle's process pool forks
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(prob)
+        log(f"cpu baseline: {cpu['value']:.3f} flip evals/s on {cpu['cores']} cores")
     log("precompute (host) ...")
     t0 = time.perf_counter()
     h = P.Handle(prob)
@@ -118,9 +124,8 @@ def main():
         "kernels": {"accept_rescore_avg_us": 1e3 * avg_acc_ms, "accept_launches": n_acc,
                     "score_avg_us": 1e3 * t_sc / max(n_sc, 1)},
     }
-    if not a.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(prob)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     h.close()
     print(json.dumps(out))
 

@@ -68,7 +68,12 @@ def _eval_bits(prob, ops, bits):
 
 
 def _worker_init(prob):
-    os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+    # one BLAS thread per worker process: the pool provides the parallelism
+    try:
+        from threadpoolctl import threadpool_limits
+        _W["limits"] = threadpool_limits(1)
+    except ImportError:
+        pass
     _W["prob"] = prob
     _W["ops"] = _base_ops(prob)
 

@@ -17,8 +17,9 @@ hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int
 hipError_t launch_select_prep(const ProbDev& P, int forced, hipStream_t s);
 hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const uint8_t* bits,
-                          double k2d, z64* B1, int32_t* piv, int32_t* inv_p, int32_t* used,
-                          int32_t* status, hipStream_t s);
+                          double k2d, z64* B1, z64* Pb, int32_t* piv, int32_t* inv_p,
+                          int32_t* used, int32_t* status, int32_t* tsbuf, z64* B11inv,
+                          hipStream_t s);
 hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t* bits, double ds,
                        z64 alpha, z64 beta, const z64* w, double gamma, const z64* w2, z64* y,
                        hipStream_t s);
@@ -43,7 +44,7 @@ struct Layout {
       off_Rp[pngf::kMaxFreq], off_tau[pngf::kMaxFreq], off_q[pngf::kMaxFreq];
   size_t off_b[pngf::kMaxFreq], off_god[pngf::kMaxFreq];
   size_t off_bits, off_perm, off_rank, off_cand, off_df, off_logp, off_logf, off_state;
-  size_t off_S, off_B1, off_piv, off_invp, off_used, off_status, off_u, off_r;
+  size_t off_S, off_B1, off_Pb, off_ts, off_B11, off_piv, off_invp, off_used, off_status, off_u, off_r;
   size_t total;
 };
 
@@ -108,6 +109,9 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
   }
   L.off_S = take(mat);
   L.off_B1 = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
+  L.off_Pb = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
+  L.off_ts = take(size_t(4) * ((nd + 255) / 256) * pngf::kGjNbHost * sizeof(int32_t) + 1024);
+  L.off_B11 = take(size_t(pngf::kGjNbHost) * pngf::kGjNbHost * sizeof(z64));
   L.off_piv = take(size_t(nd) * sizeof(int32_t));
   L.off_invp = take(size_t(nd) * sizeof(int32_t));
   L.off_used = take(size_t(nd) * sizeof(int32_t));
@@ -195,8 +199,10 @@ int device_reinvert(pngf_handle* h) {
     const z64* god = at<z64>(h, L.off_god[f]);
     {
       Timer t(h, KID_LU);
-      HIPCHK(h, pngf::launch_inverse(S, P.Cinv[f], P.G[f], nd, ld, P.bits, k2 * P.deps, B1, piv,
-                                     invp, used, status, h->stream));
+      HIPCHK(h, pngf::launch_inverse(S, P.Cinv[f], P.G[f], nd, ld, P.bits, k2 * P.deps, B1,
+                                     at<z64>(h, L.off_Pb), piv, invp, used, status,
+                                     at<int32_t>(h, L.off_ts), at<z64>(h, L.off_B11),
+                                     h->stream));
       t.end();
     }
     Timer t(h, KID_OTHER);
