@@ -87,11 +87,17 @@ typedef struct pngf_problem {
 
 typedef struct pngf_options {
   int32_t precision;    /* PNGF_FP64_PLAIN or PNGF_MIXED                     */
-  int32_t k_refresh;    /* MIXED: FP64 re-inversion every k_refresh accepts  */
+  int32_t k_refresh;    /* MIXED: FP64 re-inversion every k_refresh accepts; */
+                        /* 0 = only when the FP64 residual of E drifts       */
+  int32_t k_fold;       /* MIXED: fold the deferred panel into C0^-1 once it */
+                        /* holds k_fold terms (0 = only when it is full)     */
   int32_t max_accepts;  /* capacity of the on-device accept log (>= 1)       */
   int32_t max_sweeps;   /* largest n_sweeps pngf_dbs_run will be given       */
+  int32_t reserved0;    /* 0                                                 */
   double eta;           /* accept iff f' - f > eta * f (1e-9)                */
-  double guard;         /* MIXED: FP64 re-check band (relative), 0 = auto    */
+  double guard;         /* MIXED: relative FP32 error band of a score; a     */
+                        /* candidate inside it is decided on the FP64 state; */
+                        /* 0 = calibrated at every FP64 re-inversion         */
   uint64_t flags;       /* PNGF_FLAG_* bits                                  */
 } pngf_options;
 

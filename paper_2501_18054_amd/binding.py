@@ -45,7 +45,8 @@ class Problem(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("k_refresh", C.c_int32),
-                ("max_accepts", C.c_int32), ("max_sweeps", C.c_int32),
+                ("k_fold", C.c_int32), ("max_accepts", C.c_int32),
+                ("max_sweeps", C.c_int32), ("reserved0", C.c_int32),
                 ("eta", C.c_double), ("guard", C.c_double), ("flags", C.c_uint64)]
 
 
@@ -113,8 +114,8 @@ def _cplx(a):
 
 
 def default_options(precision=PNGF_FP64_PLAIN, max_accepts=1 << 16, max_sweeps=32,
-                    eta=1e-9, k_refresh=32, guard=0.0, timing=False):
-    return Options(precision, k_refresh, max_accepts, max_sweeps, eta, guard,
+                    eta=1e-9, k_refresh=32, k_fold=0, guard=0.0, timing=False):
+    return Options(precision, k_refresh, k_fold, max_accepts, max_sweeps, 0, eta, guard,
                    PNGF_FLAG_TIMING if timing else 0)
 
 

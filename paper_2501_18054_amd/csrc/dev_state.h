@@ -25,6 +25,14 @@ struct DbsState {
   z64 alpha[kMaxFreq]; // k0^2 delta / den of the pending update
   z64 Em[kMaxFreq];    // E[m] before the pending update
   z64 Rpm[kMaxFreq];   // R'[m] before the pending update
+  // mixed precision
+  uint32_t key_maybe;  // min key over candidates inside the FP32 error band
+  int32_t need_refresh;  // 1: stop and re-form C^-1 in FP64 (2: band hit)
+  int32_t n_since;     // accepts since the last FP64 re-inversion
+  int32_t kpanel;      // deferred Sherman-Morrison terms held in the panel
+  int32_t kslot;       // panel slot of the pending update
+  int32_t exact;       // current scores come from the FP64 state
+  int64_t n_band;      // decisions that needed the FP64 state
 };
 
 // Everything a hot-path kernel needs, passed by value (kernel arguments).
@@ -46,6 +54,18 @@ struct ProbDev {
   double* log_f;               // [max_acc]
   double* df;                  // per-candidate objective change (scoring)
   DbsState* st;
+  // mixed precision (complex FP32 matrices and the deferred panel)
+  z32* C0[kMaxFreq];           // C0^-1 (complex FP32), nd x ld
+  z32* G32[kMaxFreq];          // G (complex FP32), nd x ld
+  z32* Pp[kMaxFreq];           // panel p vectors, slot k at Pp + k*ld
+  z32* Qp[kMaxFreq];           // panel q vectors, slot k at Qp + k*ld
+  z64* alph[kMaxFreq];         // alpha of each panel slot
+  z64* pcoef[kMaxFreq];        // alpha_k p_k[m] for the pending update
+  double* df32;                // FP32-path score of each candidate
+  double* dfb;                 // its error bound (before the band factor)
+  int32_t kcap;                // panel capacity
+  int32_t k_refresh;           // periodic FP64 re-inversion (0: drift-driven)
+  double band;                 // relative FP32 error band of a score
 };
 
 }  // namespace pngf

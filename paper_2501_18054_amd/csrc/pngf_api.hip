@@ -25,10 +25,19 @@ hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t*
                        hipStream_t s);
 hipError_t launch_output(const ProbDev& P, int f, const z64* god, z64 xb, int last,
                          hipStream_t s);
+hipError_t launch_mixed_step(const ProbDev& P, int npl, hipStream_t s);
+hipError_t launch_to_c64(const z64* src, z32* dst, int nd, int ld, hipStream_t s);
+hipError_t launch_fold(const ProbDev& P, int f, int kp, hipStream_t s);
+hipError_t launch_band_measure(const double* df32, const double* bnd32, const double* df64,
+                               int nd, double* out, hipStream_t s);
 constexpr int kGjNbHost = 16;
+constexpr int kPanelCap = 64;      // deferred Sherman-Morrison terms (mixed)
+constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
+constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 }  // namespace pngf
 
 using pngf::cd;
+using pngf::z32;
 using pngf::z64;
 
 namespace {
@@ -44,6 +53,9 @@ struct Layout {
       off_Rp[pngf::kMaxFreq], off_tau[pngf::kMaxFreq], off_q[pngf::kMaxFreq];
   size_t off_b[pngf::kMaxFreq], off_god[pngf::kMaxFreq];
   size_t off_bits, off_perm, off_rank, off_cand, off_df, off_logp, off_logf, off_state;
+  size_t off_C0[pngf::kMaxFreq], off_G32[pngf::kMaxFreq], off_Pp[pngf::kMaxFreq],
+      off_Qp[pngf::kMaxFreq], off_alph[pngf::kMaxFreq], off_pcoef[pngf::kMaxFreq];
+  size_t off_df32, off_dfb, off_bandout;
   size_t off_S, off_B1, off_Pb, off_ts, off_B11, off_piv, off_invp, off_used, off_status, off_u, off_r;
   size_t total;
 };
@@ -106,6 +118,20 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_q[f] = take(vec);
     L.off_b[f] = take(vec);
     L.off_god[f] = take(vec);
+  }
+  if (o->precision == PNGF_MIXED) {
+    const size_t mat32 = size_t(nd) * ld * sizeof(z32);
+    for (int f = 0; f < F; ++f) {
+      L.off_C0[f] = take(mat32);
+      L.off_G32[f] = take(mat32);
+      L.off_Pp[f] = take(size_t(pngf::kPanelCap) * ld * sizeof(z32));
+      L.off_Qp[f] = take(size_t(pngf::kPanelCap) * ld * sizeof(z32));
+      L.off_alph[f] = take(size_t(pngf::kPanelCap) * sizeof(z64));
+      L.off_pcoef[f] = take(size_t(pngf::kPanelCap) * sizeof(z64));
+    }
+    L.off_df32 = take(size_t(nd) * sizeof(double));
+    L.off_dfb = take(size_t(nd) * sizeof(double));
+    L.off_bandout = take(sizeof(double));
   }
   L.off_S = take(mat);
   L.off_B1 = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
@@ -249,6 +275,172 @@ int write_state(pngf_handle* h, const pngf::DbsState* st) {
   return PNGF_OK;
 }
 
+
+// FP64 plain search: select + fused accept/rescore, batches of device steps
+// between host checks of the done flag.
+int run_plain(pngf_handle* h, pngf::DbsState* pinned) {
+  const int nd = h->pc.n_d;
+  {
+    Timer t(h, KID_SCORE);
+    HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, nd, 1, h->stream));
+    t.end();
+  }
+  const int batch = 32;
+  const int64_t max_steps = int64_t(h->opt.max_accepts) + 2;
+  int64_t steps = 0;
+  while (steps < max_steps) {
+    for (int b = 0; b < batch; ++b, ++steps) {
+      {
+        Timer t(h, KID_SELECT);
+        HIPCHK(h, pngf::launch_select_prep(h->P, -1, h->stream));
+        t.end();
+      }
+      {
+        Timer t(h, KID_ACCEPT);
+        HIPCHK(h, pngf::launch_accept_rescore(h->P, h->npl, h->stream));
+        t.end();
+      }
+    }
+    HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+    if (pinned->done) return PNGF_OK;
+  }
+  return fail(h, PNGF_ENUMERIC, "DBS did not terminate");
+}
+
+// Re-form the FP64 state, cast C0^-1 to complex FP32, rescore every candidate
+// in FP64 (exact key) and, when the previous scores were FP32, measure their
+// error against the FP64 scores to set the error band.
+int mixed_refresh(pngf_handle* h, bool measure) {
+  const int nd = h->pc.n_d, F = int(h->pc.freq.size());
+  int st = device_reinvert(h);
+  if (st) return st;
+  for (int f = 0; f < F; ++f)
+    HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
+  pngf::DbsState s;
+  st = read_state(h, &s);
+  if (st) return st;
+  s.kpanel = 0;
+  s.n_since = 0;
+  s.exact = 1;
+  s.need_refresh = 0;
+  s.key = pngf::kNoKey;
+  s.key_maybe = pngf::kNoKey;
+  s.m = -1;
+  st = write_state(h, &s);
+  if (st) return st;
+  {
+    Timer t(h, KID_SCORE);
+    HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, nd, 1, h->stream));
+    t.end();
+  }
+  if (measure) {
+    double* out = at<double>(h, h->lay.off_bandout);
+    HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd, out, h->stream));
+    double meas = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&meas, out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (std::isfinite(meas) && h->opt.guard <= 0.0)
+      h->P.band = std::min(1e-2, std::max(1e-6, 100.0 * meas));
+  }
+  return PNGF_OK;
+}
+
+// FP64 residual |b - C E| / |b| of frequency 0 (drift monitor).
+int mixed_residual(pngf_handle* h, double* ratio) {
+  const int nd = h->pc.n_d;
+  const Layout& L = h->lay;
+  pngf::ProbDev& P = h->P;
+  z64* r = at<z64>(h, L.off_r);
+  const z64* b = at<z64>(h, L.off_b[0]);
+  HIPCHK(h, pngf::launch_gemv(P.G[0], h->ld, nd, P.E[0], P.bits, P.deps, z64{P.k0sq[0], 0.0},
+                              z64{1.0, 0.0}, b, -1.0, P.E[0], r, h->stream));
+  std::vector<z64> rh(nd), bh(nd);
+  HIPCHK(h, hipMemcpyAsync(rh.data(), r, nd * sizeof(z64), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(bh.data(), b, nd * sizeof(z64), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  double nr = 0.0, nb = 0.0;
+  for (int i = 0; i < nd; ++i) {
+    nr += rh[i].re * rh[i].re + rh[i].im * rh[i].im;
+    nb += bh[i].re * bh[i].re + bh[i].im * bh[i].im;
+  }
+  *ratio = std::sqrt(nr / std::max(nb, 1e-300));
+  return PNGF_OK;
+}
+
+// Mixed search: complex-FP32 steps in batches; between batches the host
+// re-inverts in FP64 when the device asks (interval, full panel, a band hit),
+// folds the panel into C0^-1 on the matrix cores, or checks the drift.
+int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_t* n_band) {
+  const int nd = h->pc.n_d, F = int(h->pc.freq.size());
+  for (int f = 0; f < F; ++f)
+    HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
+  pngf::DbsState s;
+  int st = read_state(h, &s);
+  if (st) return st;
+  s.kpanel = 0;
+  s.n_since = 0;
+  s.exact = 1;
+  s.need_refresh = 0;
+  s.key_maybe = pngf::kNoKey;
+  s.n_band = 0;
+  st = write_state(h, &s);
+  if (st) return st;
+  {
+    Timer t(h, KID_SCORE);
+    HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, nd, 1, h->stream));
+    t.end();
+  }
+  const int64_t max_rounds = 4 * int64_t(h->opt.max_accepts) + 64;
+  for (int64_t round = 0; round < max_rounds; ++round) {
+    for (int b = 0; b < pngf::kMixedBatch; ++b) {
+      Timer t(h, KID_ACCEPT);
+      HIPCHK(h, pngf::launch_mixed_step(h->P, h->npl, h->stream));
+      t.end();
+    }
+    HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+    if (pinned->done) break;
+    bool refresh = pinned->need_refresh != 0;
+    const bool band_hit = pinned->need_refresh == 2;
+    if (!refresh && h->opt.k_refresh == 0 && !pinned->exact) {
+      double ratio = 0.0;
+      st = mixed_residual(h, &ratio);
+      if (st) return st;
+      refresh = ratio > pngf::kDriftTol;
+    }
+    if (refresh) {
+      st = mixed_refresh(h, !pinned->exact);
+      if (st) return st;
+      *n_refresh += 1;
+      if (band_hit) *n_band += 1;
+    } else if (pinned->kpanel >= pngf::kPanelCap - pngf::kMixedBatch ||
+               (h->opt.k_fold > 0 && pinned->kpanel >= h->opt.k_fold)) {
+      Timer t(h, KID_OTHER);
+      for (int f = 0; f < F; ++f) HIPCHK(h, pngf::launch_fold(h->P, f, pinned->kpanel, h->stream));
+      t.end();
+      pngf::DbsState s2;
+      st = read_state(h, &s2);
+      if (st) return st;
+      s2.kpanel = 0;
+      st = write_state(h, &s2);
+      if (st) return st;
+    }
+  }
+  if (!pinned->done) return fail(h, PNGF_ENUMERIC, "DBS did not terminate");
+  // Final objective in FP64: re-form the state of the converged design.
+  st = device_reinvert(h);
+  if (st) return st;
+  HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
+                           h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PNGF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -313,16 +505,17 @@ int pngf_get_precompute(pngf_handle* h, int32_t fi, double* G, double* b, double
 
 int pngf_workspace_bytes(pngf_handle* h, const pngf_options* o, size_t* bytes) {
   if (!h || !o || !bytes) return PNGF_EINVAL;
-  if (o->precision != PNGF_FP64_PLAIN)
-    return fail(h, PNGF_EINVAL, "only PNGF_FP64_PLAIN is available in this build");
+  if (o->precision != PNGF_FP64_PLAIN && o->precision != PNGF_MIXED)
+    return fail(h, PNGF_EINVAL, "precision must be PNGF_FP64_PLAIN or PNGF_MIXED");
   *bytes = make_layout(h, o).total;
   return PNGF_OK;
 }
 
 int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes, void* stream) {
   if (!h || !o || !dev_ws) return PNGF_EINVAL;
-  if (o->precision != PNGF_FP64_PLAIN)
-    return fail(h, PNGF_EINVAL, "only PNGF_FP64_PLAIN is available in this build");
+  if (o->precision != PNGF_FP64_PLAIN && o->precision != PNGF_MIXED)
+    return fail(h, PNGF_EINVAL, "precision must be PNGF_FP64_PLAIN or PNGF_MIXED");
+  if (o->k_refresh < 0 || o->k_fold < 0) return fail(h, PNGF_EINVAL, "k_refresh and k_fold must be >= 0");
   if (o->max_accepts < 1 || o->max_sweeps < 1)
     return fail(h, PNGF_EINVAL, "max_accepts and max_sweeps must be >= 1");
   if (reinterpret_cast<uintptr_t>(dev_ws) & 255)
@@ -359,6 +552,21 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   P.log_f = at<double>(h, L.off_logf);
   P.df = at<double>(h, L.off_df);
   P.st = at<pngf::DbsState>(h, L.off_state);
+  P.kcap = pngf::kPanelCap;
+  P.k_refresh = o->k_refresh;
+  P.band = (o->guard > 0.0) ? o->guard : 1e-3;
+  if (o->precision == PNGF_MIXED) {
+    for (int f = 0; f < F; ++f) {
+      P.C0[f] = at<z32>(h, L.off_C0[f]);
+      P.G32[f] = at<z32>(h, L.off_G32[f]);
+      P.Pp[f] = at<z32>(h, L.off_Pp[f]);
+      P.Qp[f] = at<z32>(h, L.off_Qp[f]);
+      P.alph[f] = at<z64>(h, L.off_alph[f]);
+      P.pcoef[f] = at<z64>(h, L.off_pcoef[f]);
+    }
+    P.df32 = at<double>(h, L.off_df32);
+    P.dfb = at<double>(h, L.off_dfb);
+  }
   // Zero the padded matrix storage once (padding columns are never read, but
   // keep them defined), then upload G.
   HIPCHK(h, hipMemsetAsync(h->ws, 0, L.total, h->stream));
@@ -370,6 +578,8 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
     HIPCHK(h, hipMemcpyAsync(at<z64>(h, L.off_god[f]), h->pc.freq[f].god.data(), nd * sizeof(z64),
                              hipMemcpyHostToDevice, h->stream));
   }
+  if (o->precision == PNGF_MIXED)
+    for (int f = 0; f < F; ++f) HIPCHK(h, pngf::launch_to_c64(P.G[f], P.G32[f], nd, h->ld, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->bound = true;
   h->have_design = false;
@@ -503,40 +713,11 @@ int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t
   st = write_state(h, &s);
   if (st) return st;
   for (int k = 0; k < KID_N; ++k) { h->ktime_ms[k] = 0.0; h->klaunch[k] = 0; }
-  {
-    Timer t(h, KID_SCORE);
-    HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, nd, 1, h->stream));
-    t.end();
-  }
-  const int batch = 32;
-  const int64_t max_steps = int64_t(h->opt.max_accepts) + 2;
   pngf::DbsState* pinned = nullptr;
   HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(pngf::DbsState)));
-  int64_t steps = 0;
-  int rc = PNGF_OK;
-  while (steps < max_steps) {
-    for (int b = 0; b < batch; ++b, ++steps) {
-      {
-        Timer t(h, KID_SELECT);
-        hipError_t e = pngf::launch_select_prep(h->P, -1, h->stream);
-        if (e != hipSuccess) { rc = fail(h, PNGF_EDEVICE, hipGetErrorString(e)); break; }
-        t.end();
-      }
-      {
-        Timer t(h, KID_ACCEPT);
-        hipError_t e = pngf::launch_accept_rescore(h->P, h->npl, h->stream);
-        if (e != hipSuccess) { rc = fail(h, PNGF_EDEVICE, hipGetErrorString(e)); break; }
-        t.end();
-      }
-    }
-    if (rc) break;
-    hipError_t e = hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) { rc = fail(h, PNGF_EDEVICE, hipGetErrorString(e)); break; }
-    if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
-    if (pinned->done) break;
-  }
-  if (rc == PNGF_OK && !pinned->done) rc = fail(h, PNGF_ENUMERIC, "DBS did not terminate");
+  int64_t n_refresh = 0, n_band = 0;
+  int rc = (h->opt.precision == PNGF_MIXED) ? run_mixed(h, pinned, &n_refresh, &n_band)
+                                            : run_plain(h, pinned);
   pngf::DbsState fin = *pinned;
   hipHostFree(pinned);
   if (rc) return rc;
@@ -547,14 +728,15 @@ int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t
     HIPCHK(h, hipMemcpyAsync(f_trace, h->P.log_f, na * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipMemcpyAsync(h->bits.data(), h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
   if (!std::isfinite(fin.f)) return fail(h, PNGF_ENUMERIC, "objective is not finite");
   if (res) {
     res->n_accepted = na;
     res->sweeps = fin.sweeps;
     res->converged = fin.converged;
-    res->n_refresh = 0;
+    res->n_refresh = int32_t(n_refresh);
     res->attempts = fin.attempts;
-    res->n_verified = 0;
+    res->n_verified = n_band;
     res->f_initial = f0;
     res->f_final = fin.f;
   }
