@@ -182,9 +182,11 @@ int pngf_refresh(pngf_handle *h);
 int pngf_dbs_run(pngf_handle *h, const int32_t *perms, int32_t n_sweeps,
                  int32_t *accepted, double *f_trace, pngf_dbs_result *res);
 
-/* Average device time (ms, HIP events on the bound stream) and launch count
- * of the kernels of the last pngf_dbs_run, per kernel id:
- * 0 score, 1 select/prep, 2 accept+rescore, 3 LU/inverse, 4 refresh other. */
+/* Total device time (ms, HIP events on the bound stream; needs
+ * PNGF_FLAG_TIMING) and launch count of the kernels of the last pngf_dbs_run,
+ * per kernel id: 0 full scoring pass, 1 select, 2 accept (+ rescore),
+ * 3 FP64 inversion, 4 other re-inversion work (GEMVs, outputs), 5 panel fold,
+ * 6 mixed-path q row. */
 int pngf_kernel_times(pngf_handle *h, int32_t kernel_id, double *total_ms,
                       int64_t *launches);
 

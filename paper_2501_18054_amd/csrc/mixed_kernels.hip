@@ -309,9 +309,17 @@ __global__ __launch_bounds__(256) void k_band_measure(const double* df32, const 
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_mixed_step(const ProbDev& P, int npl, hipStream_t s) {
+hipError_t launch_mixed_select(const ProbDev& P, hipStream_t s) {
   hipLaunchKernelGGL(k_mixed_select, dim3(1), dim3(kRowThreads), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_mixed_q(const ProbDev& P, hipStream_t s) {
   hipLaunchKernelGGL(k_mixed_q, dim3((P.nd + 255) / 256), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_mixed_accept(const ProbDev& P, int npl, hipStream_t s) {
   switch (npl) {
     case 1: hipLaunchKernelGGL(k_mixed_accept<1>, dim3(P.nd), dim3(kRowThreads), 0, s, P); break;
     case 2: hipLaunchKernelGGL(k_mixed_accept<2>, dim3(P.nd), dim3(kRowThreads), 0, s, P); break;

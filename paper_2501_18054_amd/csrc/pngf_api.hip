@@ -25,7 +25,9 @@ hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t*
                        hipStream_t s);
 hipError_t launch_output(const ProbDev& P, int f, const z64* god, z64 xb, int last,
                          hipStream_t s);
-hipError_t launch_mixed_step(const ProbDev& P, int npl, hipStream_t s);
+hipError_t launch_mixed_select(const ProbDev& P, hipStream_t s);
+hipError_t launch_mixed_q(const ProbDev& P, hipStream_t s);
+hipError_t launch_mixed_accept(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_to_c64(const z64* src, z32* dst, int nd, int ld, hipStream_t s);
 hipError_t launch_fold(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_band_measure(const double* df32, const double* bnd32, const double* df64,
@@ -46,7 +48,8 @@ thread_local std::string g_create_error;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-enum KernelId { KID_SCORE = 0, KID_SELECT = 1, KID_ACCEPT = 2, KID_LU = 3, KID_OTHER = 4, KID_N = 8 };
+enum KernelId { KID_SCORE = 0, KID_SELECT = 1, KID_ACCEPT = 2, KID_LU = 3, KID_OTHER = 4,
+                KID_FOLD = 5, KID_MIXQ = 6, KID_N = 8 };
 
 struct Layout {
   size_t off_G[pngf::kMaxFreq], off_C[pngf::kMaxFreq], off_E[pngf::kMaxFreq],
@@ -394,11 +397,29 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
     t.end();
   }
   const int64_t max_rounds = 4 * int64_t(h->opt.max_accepts) + 64;
+  int64_t since = 0, kpan = 0;   // host view of n_since / kpanel
   for (int64_t round = 0; round < max_rounds; ++round) {
-    for (int b = 0; b < pngf::kMixedBatch; ++b) {
-      Timer t(h, KID_ACCEPT);
-      HIPCHK(h, pngf::launch_mixed_step(h->P, h->npl, h->stream));
-      t.end();
+    // stop the batch where a periodic re-inversion or a fold is due, so that
+    // no launch of the batch finds the search paused
+    int nb = pngf::kMixedBatch;
+    if (h->opt.k_refresh > 0) nb = int(std::min<int64_t>(nb, std::max<int64_t>(1, h->opt.k_refresh - since)));
+    if (h->opt.k_fold > 0) nb = int(std::min<int64_t>(nb, std::max<int64_t>(1, h->opt.k_fold - kpan)));
+    for (int b = 0; b < nb; ++b) {
+      {
+        Timer t(h, KID_SELECT);
+        HIPCHK(h, pngf::launch_mixed_select(h->P, h->stream));
+        t.end();
+      }
+      {
+        Timer t(h, KID_MIXQ);
+        HIPCHK(h, pngf::launch_mixed_q(h->P, h->stream));
+        t.end();
+      }
+      {
+        Timer t(h, KID_ACCEPT);
+        HIPCHK(h, pngf::launch_mixed_accept(h->P, h->npl, h->stream));
+        t.end();
+      }
     }
     HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
                              h->stream));
@@ -413,14 +434,17 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
       if (st) return st;
       refresh = ratio > pngf::kDriftTol;
     }
+    since = pinned->n_since;
+    kpan = pinned->kpanel;
     if (refresh) {
       st = mixed_refresh(h, !pinned->exact);
       if (st) return st;
       *n_refresh += 1;
       if (band_hit) *n_band += 1;
+      since = kpan = 0;
     } else if (pinned->kpanel >= pngf::kPanelCap - pngf::kMixedBatch ||
                (h->opt.k_fold > 0 && pinned->kpanel >= h->opt.k_fold)) {
-      Timer t(h, KID_OTHER);
+      Timer t(h, KID_FOLD);
       for (int f = 0; f < F; ++f) HIPCHK(h, pngf::launch_fold(h->P, f, pinned->kpanel, h->stream));
       t.end();
       pngf::DbsState s2;
@@ -429,6 +453,7 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
       s2.kpanel = 0;
       st = write_state(h, &s2);
       if (st) return st;
+      kpan = 0;
     }
   }
   if (!pinned->done) return fail(h, PNGF_ENUMERIC, "DBS did not terminate");
