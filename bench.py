@@ -100,7 +100,7 @@ def kernel_table(kt, nd, mixed):
             continue
         e = {"launches": n, "total_ms": tms, "avg_us": 1e3 * tms / n}
         if k == "accept":
-            b = 2 * mat8 if mixed else 3 * mat16
+            b = mat8 if mixed else 3 * mat16
             e["bytes_per_launch"] = b
             e["GB_s"] = b / (tms / n * 1e-3) / 1e9
         if k == "lu":

@@ -33,6 +33,9 @@ struct DbsState {
   int32_t kslot;       // panel slot of the pending update
   int32_t exact;       // current scores come from the FP64 state
   int64_t n_band;      // decisions that needed the FP64 state
+  int32_t flips;       // updates since the buffers were last normalized
+                       // (odd: the current vectors/matrix live in the B set)
+  int32_t pad1;
 };
 
 // Everything a hot-path kernel needs, passed by value (kernel arguments).
@@ -66,6 +69,16 @@ struct ProbDev {
   int32_t kcap;                // panel capacity
   int32_t k_refresh;           // periodic FP64 re-inversion (0: drift-driven)
   double band;                 // relative FP32 error band of a score
+  // second buffer set for the one-kernel-per-step search: a step reads one
+  // set and writes the other, so no workgroup reads what another writes
+  z64* CinvB[kMaxFreq];
+  z64* EB[kMaxFreq];
+  z64* RpB[kMaxFreq];
+  z64* tauB[kMaxFreq];
+  uint8_t* bitsB;
+  DbsState* stB;               // state of odd steps
+  uint32_t* keys;              // [6]: sure keys in slots 0-2, band keys in 3-5
+  int32_t* pm;                 // pixel of each panel slot (mixed)
 };
 
 }  // namespace pngf

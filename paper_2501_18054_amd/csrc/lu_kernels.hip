@@ -1,49 +1,54 @@
 // FP64 direct inversion of the PNGF system matrix on the GPU (gfx950).
 //
-// Used for the initial inverse C0^-1 = [(I - k0^2 G diag(deps))]^-1 (Direct
-// binary search: the inverse of the initial system matrix is found and stored)
-// and for the periodic re-inversion that bounds the drift of long chains of
-// low-rank updates (Computational efficiency: direct re-inversion instead of
-// Woodbury when many unknowns have changed).
+// Used for the initial inverse C0^-1 (Direct binary search: the inverse of the
+// initial system matrix is found and stored) and for the periodic
+// re-inversion that bounds the drift of long chains of low-rank updates
+// (Computational efficiency: direct re-inversion instead of Woodbury when many
+// unknowns have changed).
 //
-// Method: blocked Gauss-Jordan elimination with partial pivoting, in place.
-// Pivoting is virtual (rows are never moved): column k picks the unused row
-// p_k with the largest |entry|, so the elimination is that of Pi A with
-// (Pi A)[k,:] = A[p_k,:], and the in-place result M satisfies
-// (Pi A)^-1 [k,:] = M[p_k,:].  Since A^-1 = (Pi A)^-1 Pi, the final gather is
-//     A^-1[i, p_l] = M[p_i, l].
-// Blocking (panel width nb): the panel columns [k0, k0+nb) are reduced by one
-// workgroup (pivot search, pivot-row scaling and elimination inside the panel,
-// giving [-B01 B11^-1; B11^-1; -B21 B11^-1] in place); then every column
-// outside the panel is updated by the rank-nb product
-//     M[r, j] = (r is a pivot of this panel ? 0 : M[r, j]) + P[r,:] B1[:, j],
-// where B1 holds the panel's pivot rows before the update.  On gfx950 the
-// FP64 matrix-core rate equals the FP64 vector rate (78.6 TFLOP/s), and at
-// nb = 16 the update is HBM-bound, so it runs on the vector ALUs.
+// Structure.  C = I - k0^2 G diag(deps) has an identity column for every pixel
+// with deps = 0.  With S the pixels at eps_hi and Z the others,
+//     C = [[K, 0], [W, I]],  K = I - k0^2 deps G[S,S],  W = -k0^2 deps G[Z,S],
+//     C^-1 = [[K^-1, 0], [k0^2 deps G[Z,S] K^-1, I]],
+// so only K (|S| ~ N_d/2) is inverted, and the Z rows are one GEMM.  This is
+// the field-form counterpart of the paper's system (I - P) + P G, whose rows
+// for empty tiles are identity rows (Results, Numerical Green's functions).
+//
+// K^-1 by blocked Gauss-Jordan elimination with partial pivoting, in place.
+// Pivoting is virtual (rows never move): column k uses pivot row p_k, so the
+// elimination is that of Pi K with (Pi K)[k,:] = K[p_k,:], the in-place result
+// M satisfies (Pi K)^-1[k,:] = M[p_k,:], and K^-1[i, p_l] = M[p_i, l].
+// A panel of kGjNb columns picks its pivot rows by tournament pivoting
+// (Grigori-Demmel-Xiang CALU): groups of rows each propose kGjNb rows by
+// partial-pivoting elimination, proposals are reduced again until one group
+// remains; the winners' block B11 is inverted and every row is reduced
+// independently, giving the Gauss-Jordan panel [-B01 B11^-1; B11^-1;
+// -B21 B11^-1].  Every column outside the panel then gets the rank-kGjNb
+// update M[r,j] = (r pivot of this panel ? 0 : M[r,j]) + P[r,:] B1[:,j] with
+// B1 the panel's pivot rows before the update.  On gfx950 the FP64
+// matrix-core rate equals the FP64 vector rate (78.6 TFLOP/s), and at this
+// panel width the update is HBM-bound, so it runs on the vector ALUs.
 #include "dev_state.h"
 
 namespace pngf {
 
 constexpr int kGjNb = 16;
 constexpr int kUpdRows = 32;
+constexpr int kTsRows = 1024;              // candidate rows per tournament group
+constexpr int kTsFan = kTsRows / kGjNb;    // proposals merged per group
 
-// S = I - k0^2 G diag(deps) (rows of length nd, stride ld); clears pivot marks.
-__global__ __launch_bounds__(256) void k_build_system(z64* S, const z64* G, int nd, int ld,
-                                                      const uint8_t* bits, double k2d,
-                                                      int32_t* used) {
-  const int i = blockIdx.y;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j < nd) {
-    const double s = bits[j] ? -k2d : 0.0;
-    z64 g = G[size_t(i) * ld + j];
-    z64 v = {g.re * s + (i == j ? 1.0 : 0.0), g.im * s};
-    S[size_t(i) * ld + j] = v;
-  }
-  if (i == 0 && j < nd) used[j] = 0;
+// K[a][b] = delta_ab - k2d G[s_a][s_b]; clears the pivot marks.
+__global__ __launch_bounds__(256) void k_gather_K(z64* K, const z64* G, int ld, const int32_t* sidx,
+                                                  int ns, double k2d, int32_t* used) {
+  const int a = blockIdx.y;
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= ns) return;
+  const z64 g = G[size_t(sidx[a]) * ld + sidx[b]];
+  K[size_t(a) * ld + b] = z64{(a == b ? 1.0 : 0.0) - k2d * g.re, -k2d * g.im};
+  if (a == 0) used[b] = 0;
 }
 
-// Panel columns [k0, k0+ncols) of S gathered into a contiguous n x kGjNb
-// buffer (row r at Pb[r*kGjNb]) so the panel reduction streams whole rows.
+// Panel columns [k0, k0+ncols) gathered into a contiguous n x kGjNb buffer.
 __global__ __launch_bounds__(256) void k_gj_panel_in(const z64* S, int ld, int n, int k0,
                                                      int ncols, z64* Pb) {
   const int e = blockIdx.x * 256 + threadIdx.x;
@@ -51,108 +56,105 @@ __global__ __launch_bounds__(256) void k_gj_panel_in(const z64* S, int ld, int n
   if (r < n) Pb[e] = (c < ncols) ? S[size_t(r) * ld + k0 + c] : z64{0.0, 0.0};
 }
 
-__global__ __launch_bounds__(256) void k_gj_panel_out(z64* S, int ld, int n, int k0, int ncols,
-                                                      const z64* Pb) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  const int r = e / kGjNb, c = e % kGjNb;
-  if (r < n && c < ncols) S[size_t(r) * ld + k0 + c] = Pb[e];
+// Packed (|a|^2, slot) key for the pivot search: FP32 magnitude bits in the
+// high word (monotonic for non-negative floats), the complemented slot in the
+// low word so that ties prefer the smaller slot.
+__device__ __forceinline__ uint64_t piv_key(float a, int slot) {
+  return (uint64_t(__float_as_uint(a)) << 32) | uint64_t(0xFFFFFFFFu - uint32_t(slot));
 }
 
-// ---- panel by tournament pivoting ------------------------------------------
-// The panel's kGjNb pivot rows are chosen by a reduction tree of partial-
-// pivoting eliminations (tournament pivoting, Grigori-Demmel-Xiang CALU):
-// every group of <= kTsRows candidate rows is reduced by Gaussian elimination
-// with partial pivoting on its panel entries and proposes the rows it pivoted
-// on; groups of proposals are reduced again until one group remains.  The
-// winners B11 (kGjNb x kGjNb) are inverted, and every row is then reduced
-// independently: pivot rows get B11^-1, the others -B_r B11^-1, which is the
-// Gauss-Jordan panel [-B01 B11^-1; B11^-1; -B21 B11^-1].
-constexpr int kTsRows = 256;      // candidate rows per group (one per thread)
-constexpr int kTsFan = kTsRows / kGjNb;  // proposals merged per group
-
-// One group per workgroup.  level0: the group is rows [g*kTsRows, ...) minus
-// rows already used as pivots; otherwise the proposals of groups
-// [g*kTsFan, (g+1)*kTsFan) of the previous level.  Writes the group's
-// proposals (in pivot order) to out[g*kGjNb + c] and their count to cnt_out[g].
-// final_: also writes piv/used and B11^-1 (row c <-> column k0+c).
-__global__ __launch_bounds__(256) void k_tsel(const z64* Pb, int n, int k0, int ncols, int level0,
-                                              const int32_t* in, const int32_t* cnt_in,
-                                              int ngroups_in, int32_t* out, int32_t* cnt_out,
-                                              int final_, int32_t* piv, int32_t* used,
-                                              z64* B11inv, int32_t* status) {
-  __shared__ z64 A[kTsRows][kGjNb + 1];   // +1: conflict-free LDS rows
+// One tournament group per workgroup, one candidate row per thread.  The
+// pivot search runs on a complex-FP32 copy of the panel rows in LDS: it only
+// chooses which rows pivot (the reduction itself is done in FP64 by
+// k_tapply from the original rows).  level0: slot t is row g*kTsRows+t unless
+// already a pivot; otherwise proposal t%kGjNb of group g*kTsFan+t/kGjNb.
+// Writes the group's proposals (in pivot order) and their count.  final_:
+// writes piv, used and B11^-1 (row c <-> column k0+c), inverted in FP64.
+__global__ __launch_bounds__(kTsRows) void k_tsel(const z64* Pb, int n, int k0, int ncols,
+                                                  int level0, const int32_t* in,
+                                                  const int32_t* cnt_in, int ngroups_in,
+                                                  int32_t* out, int32_t* cnt_out, int final_,
+                                                  int32_t* piv, int32_t* used, z64* B11inv,
+                                                  int32_t* status) {
+  __shared__ z32 A[kTsRows][kGjNb + 1];   // +1: conflict-free LDS rows
   __shared__ int idx[kTsRows];
-  __shared__ int alive[kTsRows];
-  __shared__ int s_m;
   __shared__ int sel[kGjNb];
-  __shared__ double s_val[256 / 64];
-  __shared__ int s_idx[256 / 64];
-  __shared__ z64 W[kGjNb][2 * kGjNb];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __shared__ uint64_t wkey[kTsRows / 64];
+  __shared__ int s_p, s_m;
+  __shared__ z64 W[kGjNb][2 * kGjNb + 1];
+  __shared__ z64 fcol[kGjNb];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int g = blockIdx.x;
-  // Slot tid holds one candidate: row g*kTsRows+tid (level 0, if not yet a
-  // pivot) or proposal tid%kGjNb of group g*kTsFan+tid/kGjNb.
-  {
-    int row = -1;
-    if (level0) {
-      const int r = g * kTsRows + tid;
-      if (r < n && !used[r]) row = r;
-    } else {
-      const int q = g * kTsFan + tid / kGjNb, t = tid % kGjNb;
-      if (q < ngroups_in && t < cnt_in[q]) row = in[q * kGjNb + t];
+  int row = -1;
+  if (level0) {
+    const int r = g * kTsRows + t;
+    if (r < n && !used[r]) row = r;
+  } else {
+    const int grp = g * kTsFan + t / kGjNb, u = t % kGjNb;
+    if (grp < ngroups_in && u < cnt_in[grp]) row = in[grp * kGjNb + u];
+  }
+  idx[t] = row;
+  bool alive = row >= 0;
+#pragma unroll
+  for (int c = 0; c < kGjNb; ++c) {
+    z32 v{0.f, 0.f};
+    if (alive && c < ncols) {
+      const z64 x = Pb[size_t(row) * kGjNb + c];
+      v = z32{float(x.re), float(x.im)};
     }
-    idx[tid] = row;
-    alive[tid] = row >= 0 ? 1 : 0;
-    const int cnt = __syncthreads_count(row >= 0);
-    if (tid == 0) s_m = cnt;
+    A[t][c] = v;
   }
+  const int cnt = __syncthreads_count(alive);
+  if (t == 0) s_m = cnt;
   __syncthreads();
-  const int m = s_m;
-  for (int e = tid; e < kTsRows * kGjNb; e += 256) {
-    const int i = e / kGjNb, c = e % kGjNb;
-    A[i][c] = (idx[i] >= 0) ? Pb[size_t(idx[i]) * kGjNb + c] : z64{0.0, 0.0};
-  }
-  __syncthreads();
-  const int nsel = min(ncols, m);
+  const int nsel = min(ncols, s_m);
   for (int c = 0; c < nsel; ++c) {
-    double best = -1.0;
-    int bi = kTsRows;
-    if (alive[tid]) { best = zabs2(A[tid][c]); bi = tid; }
+    uint64_t key = 0;
+    if (alive) {
+      const z32 v = A[t][c];
+      key = piv_key(v.re * v.re + v.im * v.im, t);
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      const uint64_t ok = static_cast<uint64_t>(__shfl_xor(static_cast<long long>(key), o, 64));
+      key = ok > key ? ok : key;
     }
-    if (lane == 0) { s_val[wid] = best; s_idx[wid] = bi; }
+    if (lane == 0) wkey[wid] = key;
     __syncthreads();
-    if (tid == 0) {
-      double b = s_val[0];
-      int p = s_idx[0];
-      for (int w = 1; w < 4; ++w)
-        if (s_val[w] > b || (s_val[w] == b && s_idx[w] < p)) { b = s_val[w]; p = s_idx[w]; }
-      if (p >= kTsRows) p = 0;
-      if (final_ && !(b > 0.0)) atomicOr(status, 1);
+    if (t == 0) {
+      uint64_t k = wkey[0];
+      for (int w = 1; w < kTsRows / 64; ++w) k = wkey[w] > k ? wkey[w] : k;
+      const int p = int(0xFFFFFFFFu - uint32_t(k & 0xFFFFFFFFu));
       sel[c] = p;
-      alive[p] = 0;
+      s_p = p;
+      if (final_ && !((k >> 32) > 0)) atomicOr(status, 1);
     }
     __syncthreads();
-    const int p = sel[c];
-    // eliminate column c from the remaining rows of the group (c' > c only)
-    if (alive[tid]) {
-      const z64 piv_v = A[p][c];
-      const double d = zabs2(piv_v);
-      const z64 l = (d > 0.0) ? zdiv(A[tid][c], piv_v) : z64{0.0, 0.0};
-      for (int cc = c + 1; cc < kGjNb; ++cc) A[tid][cc] = zsub(A[tid][cc], zmul(l, A[p][cc]));
+    const int p = s_p;
+    if (t == p) alive = false;
+    if (alive) {
+      const z32 pv = A[p][c];
+      const float d = pv.re * pv.re + pv.im * pv.im;
+      const z32 a = A[t][c];
+      // l = a / pv
+      const z32 l = d > 0.f ? z32{(a.re * pv.re + a.im * pv.im) / d, (a.im * pv.re - a.re * pv.im) / d}
+                            : z32{0.f, 0.f};
+      for (int cc = c + 1; cc < kGjNb; ++cc) {
+        const z32 u = A[p][cc];
+        z32 x = A[t][cc];
+        x.re -= l.re * u.re - l.im * u.im;
+        x.im -= l.re * u.im + l.im * u.re;
+        A[t][cc] = x;
+      }
     }
     __syncthreads();
   }
-  if (tid < nsel) out[g * kGjNb + tid] = idx[sel[tid]];
-  if (tid == 0) cnt_out[g] = nsel;
+  if (t < nsel) out[g * kGjNb + t] = idx[sel[t]];
+  if (t == 0) cnt_out[g] = nsel;
   if (!final_) return;
-  // B11 from the untouched panel rows of the winners, inverted by Gauss-Jordan
-  // in the winners' order (their elimination above needed no interchange).
-  for (int e = tid; e < kGjNb * 2 * kGjNb; e += 256) {
+  // B11 from the FP64 panel rows of the winners, inverted by Gauss-Jordan in
+  // the winners' order (their elimination above needed no interchange).
+  for (int e = t; e < kGjNb * 2 * kGjNb; e += kTsRows) {
     const int r = e / (2 * kGjNb), c = e % (2 * kGjNb);
     z64 v{0.0, 0.0};
     if (c < kGjNb) {
@@ -164,28 +166,27 @@ __global__ __launch_bounds__(256) void k_tsel(const z64* Pb, int n, int k0, int 
     W[r][c] = v;
   }
   __syncthreads();
-  __shared__ z64 fcol[kGjNb];
   for (int c = 0; c < kGjNb; ++c) {
     const z64 pv = W[c][c];
     const z64 inv = (zabs2(pv) > 0.0) ? zdiv(z64{1.0, 0.0}, pv) : z64{0.0, 0.0};
     __syncthreads();
-    if (tid < 2 * kGjNb) W[c][tid] = zmul(W[c][tid], inv);
-    if (tid < kGjNb) fcol[tid] = W[tid][c];
+    if (t < 2 * kGjNb) W[c][t] = zmul(W[c][t], inv);
+    if (t < kGjNb) fcol[t] = W[t][c];
     __syncthreads();
-    for (int e = tid; e < kGjNb * 2 * kGjNb; e += 256) {
+    for (int e = t; e < kGjNb * 2 * kGjNb; e += kTsRows) {
       const int r = e / (2 * kGjNb), cc = e % (2 * kGjNb);
       if (r != c) W[r][cc] = zsub(W[r][cc], zmul(fcol[r], W[c][cc]));
     }
     __syncthreads();
   }
-  for (int e = tid; e < kGjNb * kGjNb; e += 256) {
+  for (int e = t; e < kGjNb * kGjNb; e += kTsRows) {
     const int r = e / kGjNb, c = e % kGjNb;
     B11inv[e] = W[r][kGjNb + c];
   }
-  if (tid < nsel) {
-    const int row = idx[sel[tid]];
-    piv[k0 + tid] = row;
-    used[row] = k0 + tid + 1;
+  if (t < nsel) {
+    const int rw = idx[sel[t]];
+    piv[k0 + t] = rw;
+    used[rw] = k0 + t + 1;
   }
 }
 
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(256) void k_tapply(z64* Pb, int n, int k0, int ncol
   const int rr = tid / kGjNb, cc = tid % kGjNb;
   const int r = blockIdx.x * (256 / kGjNb) + rr;
   Bi[rr][cc] = B11inv[tid];
-  R[rr][cc] = (r < n) ? Pb[size_t(r) * kGjNb + cc] : z64{0.0, 0.0};
+  R[rr][cc] = (r < n && cc < ncols) ? Pb[size_t(r) * kGjNb + cc] : z64{0.0, 0.0};
   __syncthreads();
   if (r >= n) return;
   const int u = used[r] - 1;
@@ -224,10 +225,12 @@ __global__ __launch_bounds__(256) void k_gj_copy_rows(const z64* S, int ld, int 
   if (c < ncols && j < n) B1[size_t(c) * ld + j] = S[size_t(piv[k0 + c]) * ld + j];
 }
 
-// Rank-ncols update of every column outside the panel.
+// Rank-ncols update of every column outside the panel; the panel columns get
+// their reduced values back from Pb, and the next panel's columns (updated
+// here) are also gathered into Pn.
 __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0, int ncols,
                                                    const z64* B1, const int32_t* used,
-                                                   const z64* Pb) {
+                                                   const z64* Pb, z64* Pn) {
   __shared__ z64 Pt[kUpdRows][kGjNb];
   __shared__ int isp[kUpdRows];
   const int tid = threadIdx.x;
@@ -244,17 +247,24 @@ __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0
   }
   __syncthreads();
   const int j = blockIdx.x * 256 + tid;
-  if (j >= n || (j >= k0 && j < k0 + ncols)) return;
+  if (j >= n) return;
+  const int rmax = min(kUpdRows, n - r0);
+  if (j >= k0 && j < k0 + ncols) {
+    for (int rr = 0; rr < rmax; ++rr) S[size_t(r0 + rr) * ld + j] = Pt[rr][j - k0];
+    return;
+  }
+  const int nxt = k0 + kGjNb;
+  const bool in_next = (j >= nxt && j < nxt + kGjNb);
   z64 b[kGjNb];
 #pragma unroll
   for (int c = 0; c < kGjNb; ++c) b[c] = (c < ncols) ? B1[size_t(c) * ld + j] : z64{0.0, 0.0};
-  const int rmax = min(kUpdRows, n - r0);
   for (int rr = 0; rr < rmax; ++rr) {
     z64* dst = S + size_t(r0 + rr) * ld + j;
     z64 acc = isp[rr] ? z64{0.0, 0.0} : *dst;
 #pragma unroll
     for (int c = 0; c < kGjNb; ++c) acc = zfma(Pt[rr][c], b[c], acc);
     *dst = acc;
+    if (in_next) Pn[size_t(r0 + rr) * kGjNb + (j - nxt)] = acc;
   }
 }
 
@@ -264,12 +274,74 @@ __global__ __launch_bounds__(256) void k_gj_invperm(const int32_t* piv, int32_t*
   if (l < n) inv_p[piv[l]] = l;
 }
 
-// A^-1[i, j] = M[p_i, inv_p[j]]
-__global__ __launch_bounds__(256) void k_gj_finalize(const z64* M, z64* Ainv, int ld, int n,
-                                                     const int32_t* piv, const int32_t* inv_p) {
+// C^-1 rows of S: C^-1[s_a, j] = K^-1[a, pos[j]] = M[p_a][inv_p[pos[j]]] for
+// j in S, 0 otherwise.  Rows of Z: identity on Z columns (the S columns come
+// from k_zrows).  One row per blockIdx.y.
+__global__ __launch_bounds__(256) void k_scatter_inverse(const z64* M, z64* Cinv, int ld, int nd,
+                                                         const int32_t* pos, const int32_t* piv,
+                                                         const int32_t* inv_p) {
   const int i = blockIdx.y;
   const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j < n) Ainv[size_t(i) * ld + j] = M[size_t(piv[i]) * ld + inv_p[j]];
+  if (j >= nd) return;
+  const int a = pos[i], bj = pos[j];
+  z64 v{0.0, 0.0};
+  if (a >= 0) {
+    if (bj >= 0) v = M[size_t(piv[a]) * ld + inv_p[bj]];
+    Cinv[size_t(i) * ld + j] = v;
+  } else if (bj < 0) {
+    Cinv[size_t(i) * ld + j] = z64{i == j ? 1.0 : 0.0, 0.0};
+  }
+}
+
+// Z rows, S columns: C^-1[z_c, s_b] = k2d sum_a G[z_c, s_a] K^-1[a, b], with
+// K^-1[a, b] read from the S rows of C^-1 already written (C^-1[s_a, s_b]).
+// 64x64 output tile per workgroup, 4x4 per thread, k-steps of 16 through LDS.
+__global__ __launch_bounds__(256) void k_zrows(const z64* G, z64* Cinv, int ld, const int32_t* sidx,
+                                               const int32_t* zidx, int ns, int nz, double k2d) {
+  __shared__ z64 As[64][17];
+  __shared__ z64 Bs[16][65];
+  const int tid = threadIdx.x;
+  const int tr = tid / 16, tc = tid % 16;
+  const int c0 = blockIdx.y * 64, b0 = blockIdx.x * 64;
+  z64 acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = z64{0.0, 0.0};
+  for (int a0 = 0; a0 < ns; a0 += 16) {
+    for (int e = tid; e < 64 * 16; e += 256) {
+      const int r = e / 16, k = e % 16;
+      const int zc = c0 + r, a = a0 + k;
+      As[r][k] = (zc < nz && a < ns) ? G[size_t(zidx[zc]) * ld + sidx[a]] : z64{0.0, 0.0};
+      const int k2 = e / 64, cb = e % 64;
+      const int a2 = a0 + k2, b = b0 + cb;
+      Bs[k2][cb] = (a2 < ns && b < ns) ? Cinv[size_t(sidx[a2]) * ld + sidx[b]] : z64{0.0, 0.0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      z64 av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = As[tr + 16 * u][k];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = Bs[k][tc + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = zfma(av[u], bv[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int zc = c0 + tr + 16 * u;
+    if (zc >= nz) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + tc + 16 * v;
+      if (b < ns) Cinv[size_t(zidx[zc]) * ld + sidx[b]] = zscale(acc[u][v], k2d);
+    }
+  }
 }
 
 // y[i] = beta w[i] + gamma w2[i] + alpha sum_j A[i,j] d_j v[j], with
@@ -317,31 +389,34 @@ __global__ __launch_bounds__(kRowThreads) void k_output(ProbDev P, int f, const 
   }
 }
 
+
 // ------------------------------------------------------------------ launchers
-hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const uint8_t* bits,
-                          double k2d, z64* B1, z64* Pb, int32_t* piv, int32_t* inv_p,
-                          int32_t* used, int32_t* status, int32_t* tsbuf, z64* B11inv,
-                          hipStream_t s) {
-  // tournament buffers: two proposal lists and two count lists
-  const int g0 = (nd + kTsRows - 1) / kTsRows;
-  int32_t* candA = tsbuf;
-  int32_t* candB = tsbuf + g0 * kGjNb;
-  int32_t* cntA = tsbuf + 2 * g0 * kGjNb;
-  int32_t* cntB = cntA + g0;
-  const dim3 gcols((nd + 255) / 256);
-  hipLaunchKernelGGL(k_build_system, dim3(gcols.x, nd), dim3(256), 0, s, S, G, nd, ld, bits, k2d,
-                     used);
-  for (int k0 = 0; k0 < nd; k0 += kGjNb) {
-    const int nc = min(kGjNb, nd - k0);
-    const dim3 gpan((nd * kGjNb + 255) / 256);
-    hipLaunchKernelGGL(k_gj_panel_in, gpan, dim3(256), 0, s, S, ld, nd, k0, nc, Pb);
-    {
+// C^-1 of C = I - k2d G diag(bits) into Cinv.  sidx/zidx/pos describe S and Z
+// (pos[i] = index of i in S, or -1).  S, Pb, Pn, B1 are scratch.
+hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const int32_t* sidx,
+                          const int32_t* zidx, const int32_t* pos, int ns, double k2d, z64* B1,
+                          z64* Pb, z64* Pn, int32_t* piv, int32_t* inv_p, int32_t* used,
+                          int32_t* status, int32_t* tsbuf, z64* B11inv, hipStream_t s) {
+  const int nz = nd - ns;
+  if (ns > 0) {
+    const int g0 = (ns + kTsRows - 1) / kTsRows;
+    int32_t* candA = tsbuf;
+    int32_t* candB = tsbuf + g0 * kGjNb;
+    int32_t* cntA = tsbuf + 2 * g0 * kGjNb;
+    int32_t* cntB = cntA + g0;
+    const dim3 gcols((ns + 255) / 256);
+    hipLaunchKernelGGL(k_gather_K, dim3(gcols.x, ns), dim3(256), 0, s, S, G, ld, sidx, ns, k2d,
+                       used);
+    hipLaunchKernelGGL(k_gj_panel_in, dim3((ns * kGjNb + 255) / 256), dim3(256), 0, s, S, ld, ns,
+                       0, min(kGjNb, ns), Pb);
+    for (int k0 = 0; k0 < ns; k0 += kGjNb) {
+      const int nc = min(kGjNb, ns - k0);
       int groups = g0;
       int32_t *cin = nullptr, *nin = nullptr, *cout = candA, *nout = cntA;
       int level0 = 1, ngin = 0;
       while (true) {
         const int fin = (groups == 1) ? 1 : 0;
-        hipLaunchKernelGGL(k_tsel, dim3(groups), dim3(256), 0, s, Pb, nd, k0, nc, level0, cin,
+        hipLaunchKernelGGL(k_tsel, dim3(groups), dim3(kTsRows), 0, s, Pb, ns, k0, nc, level0, cin,
                            nin, ngin, cout, nout, fin, piv, used, B11inv, status);
         if (fin) break;
         level0 = 0;
@@ -352,18 +427,23 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
         nout = (nout == cntA) ? cntB : cntA;
         groups = (groups + kTsFan - 1) / kTsFan;
       }
-      hipLaunchKernelGGL(k_tapply, dim3((nd + 15) / 16), dim3(256), 0, s, Pb, nd, k0, nc, used,
+      hipLaunchKernelGGL(k_tapply, dim3((ns + 15) / 16), dim3(256), 0, s, Pb, ns, k0, nc, used,
                          B11inv);
+      hipLaunchKernelGGL(k_gj_copy_rows, dim3(gcols.x, nc), dim3(256), 0, s, S, ld, ns, k0, nc,
+                         piv, B1);
+      hipLaunchKernelGGL(k_gj_update, dim3(gcols.x, (ns + kUpdRows - 1) / kUpdRows), dim3(256), 0,
+                         s, S, ld, ns, k0, nc, B1, used, Pb, Pn);
+      z64* t = Pb;
+      Pb = Pn;
+      Pn = t;
     }
-    hipLaunchKernelGGL(k_gj_copy_rows, dim3(gcols.x, nc), dim3(256), 0, s, S, ld, nd, k0, nc,
-                       piv, B1);
-    hipLaunchKernelGGL(k_gj_update, dim3(gcols.x, (nd + kUpdRows - 1) / kUpdRows), dim3(256), 0,
-                       s, S, ld, nd, k0, nc, B1, used, Pb);
-    hipLaunchKernelGGL(k_gj_panel_out, gpan, dim3(256), 0, s, S, ld, nd, k0, nc, Pb);
+    hipLaunchKernelGGL(k_gj_invperm, dim3(gcols.x), dim3(256), 0, s, piv, inv_p, ns);
   }
-  hipLaunchKernelGGL(k_gj_invperm, dim3(gcols.x), dim3(256), 0, s, piv, inv_p, nd);
-  hipLaunchKernelGGL(k_gj_finalize, dim3(gcols.x, nd), dim3(256), 0, s, S, Cinv, ld, nd, piv,
-                     inv_p);
+  const dim3 grow((nd + 255) / 256, nd);
+  hipLaunchKernelGGL(k_scatter_inverse, grow, dim3(256), 0, s, S, Cinv, ld, nd, pos, piv, inv_p);
+  if (ns > 0 && nz > 0)
+    hipLaunchKernelGGL(k_zrows, dim3((ns + 63) / 64, (nz + 63) / 64), dim3(256), 0, s, G, Cinv, ld,
+                       sidx, zidx, ns, nz, k2d);
   return hipGetLastError();
 }
 

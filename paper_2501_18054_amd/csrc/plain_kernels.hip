@@ -42,11 +42,11 @@ __device__ __forceinline__ double flip_df(const ProbDev& P, const DbsState* st, 
 }
 
 // K1: tau_i = sum_j C^-1[i,j] G[i,j] for each candidate row and its exact
-// objective change; with use_key, improving candidates compete for the
-// smallest visiting key.
+// objective change; with keyp, improving candidates compete for the smallest
+// visiting key.
 template <int NPL>
 __global__ __launch_bounds__(kRowThreads) void k_score_rows(ProbDev P, const int32_t* cand,
-                                                            int ncand, int use_key) {
+                                                            int ncand, uint32_t* keyp) {
   __shared__ double red[2 * (kRowThreads / 64)];
   const int r = blockIdx.x;
   if (r >= ncand) return;
@@ -72,9 +72,9 @@ __global__ __launch_bounds__(kRowThreads) void k_score_rows(ProbDev P, const int
   }
   if (tid == 0) {
     P.df[r] = df;
-    if (use_key && df > st->eta * st->f) {
+    if (keyp && df > st->eta * st->f) {
       const uint32_t k = cand_key(P, st, i);
-      if (k != kNoKey) atomicMin(&P.st->key, k);
+      if (k != kNoKey) atomicMin(keyp, k);
     }
   }
 }
@@ -237,9 +237,9 @@ __global__ __launch_bounds__(kRowThreads) void k_accept_rescore(ProbDev P) {
   }
 
 hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int ncand,
-                             int use_key, hipStream_t s) {
+                             uint32_t* keyp, hipStream_t s) {
   if (ncand <= 0) return hipSuccess;
-#define L_(N) hipLaunchKernelGGL(k_score_rows<N>, dim3(ncand), dim3(kRowThreads), 0, s, P, cand, ncand, use_key)
+#define L_(N) hipLaunchKernelGGL(k_score_rows<N>, dim3(ncand), dim3(kRowThreads), 0, s, P, cand, ncand, keyp)
   PNGF_NPL_SWITCH(npl, L_)
 #undef L_
   return hipGetLastError();

@@ -13,21 +13,21 @@
 
 namespace pngf {
 hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int ncand,
-                             int use_key, hipStream_t s);
+                             uint32_t* keyp, hipStream_t s);
+hipError_t launch_plain_step(const ProbDev& P, int npl, int step, hipStream_t s);
+hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s);
+hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_select_prep(const ProbDev& P, int forced, hipStream_t s);
 hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s);
-hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const uint8_t* bits,
-                          double k2d, z64* B1, z64* Pb, int32_t* piv, int32_t* inv_p,
-                          int32_t* used, int32_t* status, int32_t* tsbuf, z64* B11inv,
-                          hipStream_t s);
+hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const int32_t* sidx,
+                          const int32_t* zidx, const int32_t* pos, int ns, double k2d, z64* B1,
+                          z64* Pb, z64* Pn, int32_t* piv, int32_t* inv_p, int32_t* used,
+                          int32_t* status, int32_t* tsbuf, z64* B11inv, hipStream_t s);
 hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t* bits, double ds,
                        z64 alpha, z64 beta, const z64* w, double gamma, const z64* w2, z64* y,
                        hipStream_t s);
 hipError_t launch_output(const ProbDev& P, int f, const z64* god, z64 xb, int last,
                          hipStream_t s);
-hipError_t launch_mixed_select(const ProbDev& P, hipStream_t s);
-hipError_t launch_mixed_q(const ProbDev& P, hipStream_t s);
-hipError_t launch_mixed_accept(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_to_c64(const z64* src, z32* dst, int nd, int ld, hipStream_t s);
 hipError_t launch_fold(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_band_measure(const double* df32, const double* bnd32, const double* df64,
@@ -59,6 +59,10 @@ struct Layout {
   size_t off_C0[pngf::kMaxFreq], off_G32[pngf::kMaxFreq], off_Pp[pngf::kMaxFreq],
       off_Qp[pngf::kMaxFreq], off_alph[pngf::kMaxFreq], off_pcoef[pngf::kMaxFreq];
   size_t off_df32, off_dfb, off_bandout;
+  size_t off_Pn, off_sidx, off_zidx, off_pos;
+  size_t off_CB[pngf::kMaxFreq], off_EB[pngf::kMaxFreq], off_RpB[pngf::kMaxFreq],
+      off_tauB[pngf::kMaxFreq];
+  size_t off_bitsB, off_stateB, off_keys, off_pm;
   size_t off_S, off_B1, off_Pb, off_ts, off_B11, off_piv, off_invp, off_used, off_status, off_u, off_r;
   size_t total;
 };
@@ -121,7 +125,15 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_q[f] = take(vec);
     L.off_b[f] = take(vec);
     L.off_god[f] = take(vec);
+    if (o->precision == PNGF_FP64_PLAIN) L.off_CB[f] = take(mat);
+    L.off_EB[f] = take(vec);
+    L.off_RpB[f] = take(vec);
+    L.off_tauB[f] = take(vec);
   }
+  L.off_bitsB = take(size_t(nd));
+  L.off_stateB = take(sizeof(pngf::DbsState));
+  L.off_keys = take(6 * sizeof(uint32_t));
+  L.off_pm = take(size_t(pngf::kPanelCap) * sizeof(int32_t));
   if (o->precision == PNGF_MIXED) {
     const size_t mat32 = size_t(nd) * ld * sizeof(z32);
     for (int f = 0; f < F; ++f) {
@@ -139,7 +151,11 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
   L.off_S = take(mat);
   L.off_B1 = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
   L.off_Pb = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
-  L.off_ts = take(size_t(4) * ((nd + 255) / 256) * pngf::kGjNbHost * sizeof(int32_t) + 1024);
+  L.off_Pn = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
+  L.off_sidx = take(size_t(nd) * sizeof(int32_t));
+  L.off_zidx = take(size_t(nd) * sizeof(int32_t));
+  L.off_pos = take(size_t(nd) * sizeof(int32_t));
+  L.off_ts = take(size_t(4) * ((nd + 1023) / 1024) * pngf::kGjNbHost * sizeof(int32_t) + 1024);
   L.off_B11 = take(size_t(pngf::kGjNbHost) * pngf::kGjNbHost * sizeof(z64));
   L.off_piv = take(size_t(nd) * sizeof(int32_t));
   L.off_invp = take(size_t(nd) * sizeof(int32_t));
@@ -222,14 +238,32 @@ int device_reinvert(pngf_handle* h) {
   z64* r = at<z64>(h, L.off_r);
   const z64 one{1.0, 0.0}, zero{0.0, 0.0};
   HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
+  // S (pixels at eps_hi) and Z from the device design bits
+  HIPCHK(h, hipMemcpyAsync(h->bits.data(), P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  std::vector<int32_t> sidx, zidx, pos(nd, -1);
+  for (int i = 0; i < nd; ++i) {
+    if (h->bits[i]) { pos[i] = int32_t(sidx.size()); sidx.push_back(i); }
+    else zidx.push_back(i);
+  }
+  const int ns = int(sidx.size());
+  int32_t* d_sidx = at<int32_t>(h, L.off_sidx);
+  int32_t* d_zidx = at<int32_t>(h, L.off_zidx);
+  int32_t* d_pos = at<int32_t>(h, L.off_pos);
+  if (ns > 0)
+    HIPCHK(h, hipMemcpyAsync(d_sidx, sidx.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  if (nd - ns > 0)
+    HIPCHK(h, hipMemcpyAsync(d_zidx, zidx.data(), (nd - ns) * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(d_pos, pos.data(), nd * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   for (int f = 0; f < F; ++f) {
     const double k2 = P.k0sq[f];
     const z64* b = at<z64>(h, L.off_b[f]);
     const z64* god = at<z64>(h, L.off_god[f]);
     {
       Timer t(h, KID_LU);
-      HIPCHK(h, pngf::launch_inverse(S, P.Cinv[f], P.G[f], nd, ld, P.bits, k2 * P.deps, B1,
-                                     at<z64>(h, L.off_Pb), piv, invp, used, status,
+      HIPCHK(h, pngf::launch_inverse(S, P.Cinv[f], P.G[f], nd, ld, d_sidx, d_zidx, d_pos, ns,
+                                     k2 * P.deps, B1, at<z64>(h, L.off_Pb),
+                                     at<z64>(h, L.off_Pn), piv, invp, used, status,
                                      at<int32_t>(h, L.off_ts), at<z64>(h, L.off_B11),
                                      h->stream));
       t.end();
@@ -279,35 +313,61 @@ int write_state(pngf_handle* h, const pngf::DbsState* st) {
 }
 
 
-// FP64 plain search: select + fused accept/rescore, batches of device steps
-// between host checks of the done flag.
-int run_plain(pngf_handle* h, pngf::DbsState* pinned) {
-  const int nd = h->pc.n_d;
-  {
-    Timer t(h, KID_SCORE);
-    HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, nd, 1, h->stream));
+// Reset the rotating key slots and score every candidate of the current
+// (normalized) state into slot 0; the next step of the search is step 0.
+int start_segment(pngf_handle* h) {
+  const uint32_t none[6] = {pngf::kNoKey, pngf::kNoKey, pngf::kNoKey,
+                            pngf::kNoKey, pngf::kNoKey, pngf::kNoKey};
+  HIPCHK(h, hipMemcpyAsync(h->P.keys, none, sizeof(none), hipMemcpyHostToDevice, h->stream));
+  Timer t(h, KID_SCORE);
+  HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, h->pc.n_d, h->P.keys, h->stream));
+  t.end();
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PNGF_OK;
+}
+
+// After an even number of steps the state is back in the A slot; if an odd
+// number of updates happened the current vectors/matrix are in the B set:
+// swap the roles so that A is current again.
+int normalize(pngf_handle* h, pngf::DbsState* st) {
+  if (!(st->flips & 1)) return PNGF_OK;
+  pngf::ProbDev& P = h->P;
+  for (int f = 0; f < P.nfreq; ++f) {
+    if (P.CinvB[f]) std::swap(P.Cinv[f], P.CinvB[f]);
+    std::swap(P.E[f], P.EB[f]);
+    std::swap(P.Rp[f], P.RpB[f]);
+    std::swap(P.tau[f], P.tauB[f]);
+  }
+  std::swap(P.bits, P.bitsB);
+  st->flips = 0;
+  return write_state(h, st);
+}
+
+// Run `n` (even) steps starting at step index t0, then read the state.
+template <class L>
+int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinned) {
+  for (int b = 0; b < n; ++b) {
+    Timer t(h, KID_ACCEPT);
+    HIPCHK(h, launch(h->P, h->npl, int(t0 + b), h->stream));
     t.end();
   }
+  HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
+                           h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  return normalize(h, pinned);
+}
+
+// FP64 plain search: one fused step kernel per accepted flip, batches of
+// device steps between host checks of the done flag.
+int run_plain(pngf_handle* h, pngf::DbsState* pinned) {
+  int st = start_segment(h);
+  if (st) return st;
   const int batch = 32;
   const int64_t max_steps = int64_t(h->opt.max_accepts) + 2;
-  int64_t steps = 0;
-  while (steps < max_steps) {
-    for (int b = 0; b < batch; ++b, ++steps) {
-      {
-        Timer t(h, KID_SELECT);
-        HIPCHK(h, pngf::launch_select_prep(h->P, -1, h->stream));
-        t.end();
-      }
-      {
-        Timer t(h, KID_ACCEPT);
-        HIPCHK(h, pngf::launch_accept_rescore(h->P, h->npl, h->stream));
-        t.end();
-      }
-    }
-    HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
-                             h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  for (int64_t t = 0; t < max_steps + batch; t += batch) {
+    st = run_steps(h, pngf::launch_plain_step, t, batch, pinned);
+    if (st) return st;
     if (pinned->done) return PNGF_OK;
   }
   return fail(h, PNGF_ENUMERIC, "DBS did not terminate");
@@ -329,16 +389,12 @@ int mixed_refresh(pngf_handle* h, bool measure) {
   s.n_since = 0;
   s.exact = 1;
   s.need_refresh = 0;
-  s.key = pngf::kNoKey;
-  s.key_maybe = pngf::kNoKey;
   s.m = -1;
+  s.flips = 0;
   st = write_state(h, &s);
   if (st) return st;
-  {
-    Timer t(h, KID_SCORE);
-    HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, nd, 1, h->stream));
-    t.end();
-  }
+  st = start_segment(h);
+  if (st) return st;
   if (measure) {
     double* out = at<double>(h, h->lay.off_bandout);
     HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd, out, h->stream));
@@ -387,44 +443,25 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
   s.n_since = 0;
   s.exact = 1;
   s.need_refresh = 0;
-  s.key_maybe = pngf::kNoKey;
   s.n_band = 0;
+  s.flips = 0;
   st = write_state(h, &s);
   if (st) return st;
-  {
-    Timer t(h, KID_SCORE);
-    HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, nd, 1, h->stream));
-    t.end();
-  }
+  st = start_segment(h);
+  if (st) return st;
   const int64_t max_rounds = 4 * int64_t(h->opt.max_accepts) + 64;
+  int64_t t = 0;                 // step index within the segment
   int64_t since = 0, kpan = 0;   // host view of n_since / kpanel
   for (int64_t round = 0; round < max_rounds; ++round) {
-    // stop the batch where a periodic re-inversion or a fold is due, so that
-    // no launch of the batch finds the search paused
+    // end the batch where a periodic re-inversion or a fold is due, so that
+    // few launches of the batch find the search paused; batches stay even
     int nb = pngf::kMixedBatch;
     if (h->opt.k_refresh > 0) nb = int(std::min<int64_t>(nb, std::max<int64_t>(1, h->opt.k_refresh - since)));
     if (h->opt.k_fold > 0) nb = int(std::min<int64_t>(nb, std::max<int64_t>(1, h->opt.k_fold - kpan)));
-    for (int b = 0; b < nb; ++b) {
-      {
-        Timer t(h, KID_SELECT);
-        HIPCHK(h, pngf::launch_mixed_select(h->P, h->stream));
-        t.end();
-      }
-      {
-        Timer t(h, KID_MIXQ);
-        HIPCHK(h, pngf::launch_mixed_q(h->P, h->stream));
-        t.end();
-      }
-      {
-        Timer t(h, KID_ACCEPT);
-        HIPCHK(h, pngf::launch_mixed_accept(h->P, h->npl, h->stream));
-        t.end();
-      }
-    }
-    HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
-                             h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+    nb += nb & 1;
+    st = run_steps(h, pngf::launch_mixed_step, t, nb, pinned);
+    if (st) return st;
+    t += nb;
     if (pinned->done) break;
     bool refresh = pinned->need_refresh != 0;
     const bool band_hit = pinned->need_refresh == 2;
@@ -442,11 +479,15 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
       *n_refresh += 1;
       if (band_hit) *n_band += 1;
       since = kpan = 0;
+      t = 0;
     } else if (pinned->kpanel >= pngf::kPanelCap - pngf::kMixedBatch ||
                (h->opt.k_fold > 0 && pinned->kpanel >= h->opt.k_fold)) {
-      Timer t(h, KID_FOLD);
-      for (int f = 0; f < F; ++f) HIPCHK(h, pngf::launch_fold(h->P, f, pinned->kpanel, h->stream));
-      t.end();
+      Timer tm(h, KID_FOLD);
+      for (int f = 0; f < F; ++f) {
+        HIPCHK(h, pngf::launch_fold_q(h->P, f, pinned->kpanel, h->stream));
+        HIPCHK(h, pngf::launch_fold(h->P, f, pinned->kpanel, h->stream));
+      }
+      tm.end();
       pngf::DbsState s2;
       st = read_state(h, &s2);
       if (st) return st;
@@ -577,6 +618,16 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   P.log_f = at<double>(h, L.off_logf);
   P.df = at<double>(h, L.off_df);
   P.st = at<pngf::DbsState>(h, L.off_state);
+  for (int f = 0; f < F; ++f) {
+    P.CinvB[f] = (o->precision == PNGF_FP64_PLAIN) ? at<z64>(h, L.off_CB[f]) : nullptr;
+    P.EB[f] = at<z64>(h, L.off_EB[f]);
+    P.RpB[f] = at<z64>(h, L.off_RpB[f]);
+    P.tauB[f] = at<z64>(h, L.off_tauB[f]);
+  }
+  P.bitsB = at<uint8_t>(h, L.off_bitsB);
+  P.stB = at<pngf::DbsState>(h, L.off_stateB);
+  P.keys = at<uint32_t>(h, L.off_keys);
+  P.pm = at<int32_t>(h, L.off_pm);
   P.kcap = pngf::kPanelCap;
   P.k_refresh = o->k_refresh;
   P.band = (o->guard > 0.0) ? o->guard : 1e-3;
@@ -660,7 +711,7 @@ int pngf_score_flips(pngf_handle* h, const int32_t* cand, int32_t n, double* f_n
   if (n == 0) return PNGF_OK;
   int32_t* dcand = at<int32_t>(h, h->lay.off_cand);
   HIPCHK(h, hipMemcpyAsync(dcand, cand, n * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, dcand, n, 0, h->stream));
+  HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, dcand, n, nullptr, h->stream));
   std::vector<double> df(n);
   HIPCHK(h, hipMemcpyAsync(df.data(), h->P.df, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   pngf::DbsState s;
@@ -684,7 +735,7 @@ int pngf_accept_flips(pngf_handle* h, const int32_t* pix, int32_t n) {
   st = write_state(h, &s);
   if (st) return st;
   // tau of the current state for every pixel (needed by the update scalars).
-  HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, h->pc.n_d, 0, h->stream));
+  HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, h->pc.n_d, nullptr, h->stream));
   for (int r = 0; r < n; ++r) {
     HIPCHK(h, pngf::launch_select_prep(h->P, pix[r], h->stream));
     HIPCHK(h, pngf::launch_accept_rescore(h->P, h->npl, h->stream));

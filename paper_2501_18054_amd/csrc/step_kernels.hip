@@ -1,0 +1,429 @@
+// One-kernel-per-step DBS kernels of libpngf (gfx950).
+//
+// Step t of a search is a single launch.  Every workgroup first decodes the
+// pending decision from the previous step's result (the minimum visiting key,
+// Results, Direct binary search: first improving flip in the visiting order)
+// and forms the update scalars itself; workgroup 0 also writes the next device
+// state.  Then workgroup i applies the accepted flip to row i and scores
+// candidate i of the new state.  A step reads one buffer set (state, vectors,
+// design bits and, on the FP64 path, C^-1) and writes the other, and the
+// visiting keys rotate through three slots, so no workgroup reads anything
+// another workgroup of the same launch writes.
+//
+// FP64 path (Sherman-Morrison, eq. lru_woodbury with M = 1):
+//     C^-1_out[i,:] = C^-1_in[i,:] + alpha p_i q,  p_i = C^-1_in[i,:] . g_m,
+//     q = C^-1_in[m,:],  then tau_i = C^-1_out[i,:] . G[i,:]  (3 N_d^2 x 16 B).
+// Mixed path (complex-FP32 C0^-1, deferred panel):
+//     p_i = C0^-1[i,:] . g_m + sum_k alpha_k p_k[m] p_k[i],
+//     tau_i += alpha p_i^2   (reciprocity: (G q)_i = p_i),      (N_d^2 x 8 B)
+// with p appended to the panel; E, R', tau stay FP64.
+#include "dev_state.h"
+
+namespace pngf {
+
+__device__ __forceinline__ z64 up32(z32 a) { return {double(a.re), double(a.im)}; }
+
+// Decision context shared by a workgroup.
+struct StepCtx {
+  int m, dpar, slot;
+  int cs, cp, ns;     // cursor of the new state
+  double f, eta;
+  z64 alpha[kMaxFreq], Em[kMaxFreq], Rpm[kMaxFreq], x[kMaxFreq];
+};
+
+// Scalar view of the fields a step changes (a local copy of the whole state
+// would live in scratch memory).
+struct StepScalars {
+  int32_t done, need_refresh, cursor_s, cursor_pos, n_acc, sweeps, converged, n_sweeps;
+  int32_t n_since, kpanel, exact, flips;
+  int64_t attempts;
+  double f, eta;
+};
+
+// Decode the minimum key of the previous step into an accepted pixel and
+// advance the cursor (same rules as the sequential search).  Returns m or -1
+// (search ended: done/converged set).
+__device__ inline int decode_key(StepScalars& st, uint32_t key, const ProbDev& P) {
+  const int nd = P.nd;
+  const int s = st.cursor_s, c = st.cursor_pos, ns = st.n_sweeps;
+  if (key == kNoKey) {
+    const bool next = (c > 0) && (s + 1 < ns);
+    st.attempts += (nd - c) + (next ? nd : 0);
+    st.converged = (c == 0) || next;
+    st.sweeps = s + 1 + (next ? 1 : 0);
+    st.done = 1;
+    return -1;
+  }
+  int s2 = s, pos = int(key);
+  if (int(key) >= nd) {
+    s2 = s + 1;
+    pos = int(key) - nd;
+    st.attempts += (nd - c) + pos + 1;
+  } else {
+    st.attempts += pos - c + 1;
+  }
+  const int m = P.perm[size_t(s2) * nd + pos];
+  st.sweeps = s2 + 1;
+  if (pos + 1 < nd) {
+    st.cursor_s = s2;
+    st.cursor_pos = pos + 1;
+  } else {
+    st.cursor_s = s2 + 1;
+    st.cursor_pos = 0;
+  }
+  return m;
+}
+
+__device__ __forceinline__ uint32_t step_key(const ProbDev& P, const StepCtx& c, int i) {
+  if (c.cs >= c.ns) return kNoKey;
+  const int pos = P.rank[size_t(c.cs) * P.nd + i];
+  if (pos >= c.cp) return uint32_t(pos);
+  if (c.cs + 1 < c.ns) return uint32_t(P.nd + P.rank[size_t(c.cs + 1) * P.nd + i]);
+  return kNoKey;
+}
+
+// Thread 0: read the state of this step, decide, fill the context; workgroup 0
+// publishes the next state and clears the key slot two steps ahead.
+__device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool mixed,
+                                   StepCtx& c) {
+  const DbsState* sin = spar ? P.stB : P.st;
+  DbsState* sout = spar ? P.st : P.stB;
+  StepScalars st;
+  st.done = sin->done;
+  st.need_refresh = sin->need_refresh;
+  st.cursor_s = sin->cursor_s;
+  st.cursor_pos = sin->cursor_pos;
+  st.n_acc = sin->n_acc;
+  st.sweeps = sin->sweeps;
+  st.converged = sin->converged;
+  st.n_sweeps = sin->n_sweeps;
+  st.n_since = sin->n_since;
+  st.kpanel = sin->kpanel;
+  st.exact = sin->exact;
+  st.flips = sin->flips;
+  st.attempts = sin->attempts;
+  st.f = sin->f;
+  st.eta = sin->eta;
+  const int dpar = spar;   // an updating step reads the set of its own parity
+  const uint32_t key = P.keys[kslot];
+  const uint32_t km = P.keys[3 + kslot];
+  int m = -1, slot = -1;
+  if (!st.done && !st.need_refresh) {
+    if (st.n_acc >= P.max_acc || st.cursor_s >= st.n_sweeps) {
+      st.done = 1;
+      st.converged = 0;
+    } else if (mixed && !st.exact && km != kNoKey && (key == kNoKey || km < key)) {
+      st.need_refresh = 2;   // a band candidate comes first: decide on FP64 state
+    } else if (mixed && !st.exact &&
+               ((P.k_refresh > 0 && st.n_since >= P.k_refresh) || st.kpanel >= P.kcap)) {
+      st.need_refresh = 1;
+    } else {
+      m = decode_key(st, key, P);
+    }
+  }
+  if (m >= 0) {
+    const uint8_t* bin = dpar ? P.bitsB : P.bits;
+    const double delta = bin[m] ? -P.deps : P.deps;
+    double fnew = 0.0;
+    for (int f = 0; f < P.nfreq; ++f) {
+      const double kd = P.k0sq[f] * delta;
+      const z64 tau = (dpar ? P.tauB : P.tau)[f][m];
+      const z64 den = {1.0 - kd * tau.re, -kd * tau.im};
+      const z64 alpha = zdiv(z64{kd, 0.0}, den);
+      const z64 Em = (dpar ? P.EB : P.E)[f][m], Rpm = (dpar ? P.RpB : P.Rp)[f][m];
+      c.alpha[f] = alpha;
+      c.Em[f] = Em;
+      c.Rpm[f] = Rpm;
+      const z64 x = zfma(zmul(alpha, Em), Rpm, sin->x[f]);
+      c.x[f] = x;
+      fnew += P.coef[f] * zabs2(x);
+    }
+    st.f = fnew;
+    st.n_acc += 1;
+    st.flips += 1;
+    if (mixed) {
+      slot = st.kpanel;
+      st.kpanel = slot + 1;
+      st.n_since += 1;
+      st.exact = 0;
+    }
+  } else {
+    for (int f = 0; f < P.nfreq; ++f) c.x[f] = sin->x[f];
+  }
+  c.m = m;
+  c.dpar = dpar;
+  c.slot = slot;
+  c.cs = st.cursor_s;
+  c.cp = st.cursor_pos;
+  c.ns = st.n_sweeps;
+  c.f = st.f;
+  c.eta = st.eta;
+  if (blockIdx.x == 0) {
+    // next state: copy, then overwrite what this step changed
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(sin);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(sout);
+    for (int w = 0; w < int(sizeof(DbsState) / 8); ++w) dst[w] = src[w];
+    sout->done = st.done;
+    sout->need_refresh = st.need_refresh;
+    sout->cursor_s = st.cursor_s;
+    sout->cursor_pos = st.cursor_pos;
+    sout->n_acc = st.n_acc;
+    sout->sweeps = st.sweeps;
+    sout->converged = st.converged;
+    sout->n_since = st.n_since;
+    sout->kpanel = st.kpanel;
+    sout->exact = st.exact;
+    sout->flips = st.flips;
+    sout->attempts = st.attempts;
+    sout->f = st.f;
+    sout->m = m;
+    sout->kslot = slot;
+    for (int f = 0; f < P.nfreq; ++f) sout->x[f] = c.x[f];
+    const int clr = (kslot + 2) % 3;
+    P.keys[clr] = kNoKey;
+    P.keys[3 + clr] = kNoKey;
+    if (m >= 0) {
+      P.log_pix[st.n_acc - 1] = m;
+      P.log_f[st.n_acc - 1] = st.f;
+      if (mixed) {
+        P.pm[slot] = m;
+        for (int f = 0; f < P.nfreq; ++f) P.alph[f][slot] = c.alpha[f];
+      }
+    }
+  }
+}
+
+// Objective change of candidate i of the new state, its FP32 error bound.
+__device__ __forceinline__ void score_terms(const ProbDev& P, const StepCtx& c, int f, z64 tau,
+                                            z64 Ei, z64 Rpi, double delta, double& df,
+                                            double& bnd) {
+  const double kd = P.k0sq[f] * delta;
+  const z64 den = {1.0 - kd * tau.re, -kd * tau.im};
+  const z64 dx = zdiv(zscale(zmul(Ei, Rpi), kd), den);
+  const z64 x = c.x[f];
+  const double adx2 = zabs2(dx);
+  df += P.coef[f] * (2.0 * (x.re * dx.re + x.im * dx.im) + adx2);
+  bnd += P.coef[f] * (2.0 * sqrt(zabs2(x) * adx2) + adx2);
+}
+
+// Every step that updates reads the buffer set of its own parity (a segment
+// starts at step 0 with the A set current, and each update flips the set), so
+// row i of C^-1 and of G is streamed before the decision is known.
+template <int NPL>
+__global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar, int kslot) {
+  __shared__ StepCtx c;
+  __shared__ double red[2 * (kRowThreads / 64)];
+  const int tid = threadIdx.x;
+  const int i = blockIdx.x;
+  const int dp = spar;
+  z64 row[NPL], grow[NPL];
+  if (P.nfreq == 1) {
+    const z64* ci = (dp ? P.CinvB : P.Cinv)[0] + size_t(i) * P.ld;
+    const z64* Gi = P.G[0] + size_t(i) * P.ld;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int j = tid + t * kRowThreads;
+      if (j < P.nd) { row[t] = ci[j]; grow[t] = Gi[j]; }
+    }
+  }
+  if (tid == 0) step_decide(P, spar, kslot, false, c);
+  __syncthreads();
+  const int m = c.m;
+  if (m < 0) return;
+  const uint8_t* bin = dp ? P.bitsB : P.bits;
+  uint8_t* bout = dp ? P.bits : P.bitsB;
+  const uint8_t bit = bin[i] ^ (i == m ? 1 : 0);
+  const double delta = bit ? -P.deps : P.deps;
+  double df = 0.0, bnd = 0.0;
+  for (int f = 0; f < P.nfreq; ++f) {
+    const z64* Cin = (dp ? P.CinvB : P.Cinv)[f];
+    z64* Cout = (dp ? P.Cinv : P.CinvB)[f];
+    const z64* ci = Cin + size_t(i) * P.ld;
+    const z64* q = Cin + size_t(m) * P.ld;
+    const z64* gm = P.G[f] + size_t(m) * P.ld;
+    const z64* Gi = P.G[f] + size_t(i) * P.ld;
+    z64* co = Cout + size_t(i) * P.ld;
+    if (f > 0 || P.nfreq != 1) {   // frequency 0 was preloaded only when alone
+#pragma unroll
+      for (int t = 0; t < NPL; ++t) {
+        const int j = tid + t * kRowThreads;
+        if (j < P.nd) { row[t] = ci[j]; grow[t] = Gi[j]; }
+      }
+    }
+    z64 acc{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int j = tid + t * kRowThreads;
+      if (j < P.nd) acc = zfma(row[t], gm[j], acc);
+    }
+    const z64 p = block_zsum(acc, red);
+    const z64 ap = zmul(c.alpha[f], p);
+    acc = z64{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int j = tid + t * kRowThreads;
+      if (j < P.nd) {
+        row[t] = zfma(ap, q[j], row[t]);
+        co[j] = row[t];
+        acc = zfma(row[t], grow[t], acc);
+      }
+    }
+    const z64 tau = block_zsum(acc, red);
+    if (tid == 0) {
+      const z64 Ei = zadd((dp ? P.EB : P.E)[f][i], zmul(ap, c.Em[f]));
+      const z64 Rpi = zadd((dp ? P.RpB : P.Rp)[f][i], zmul(ap, c.Rpm[f]));
+      (dp ? P.E : P.EB)[f][i] = Ei;
+      (dp ? P.Rp : P.RpB)[f][i] = Rpi;
+      (dp ? P.tau : P.tauB)[f][i] = tau;
+      score_terms(P, c, f, tau, Ei, Rpi, delta, df, bnd);
+    }
+  }
+  if (tid == 0) {
+    bout[i] = bit;
+    P.df[i] = df;
+    if (df > c.eta * c.f) {
+      const uint32_t k = step_key(P, c, i);
+      if (k != kNoKey) atomicMin(&P.keys[(kslot + 1) % 3], k);
+    }
+  }
+}
+
+template <int NPL>
+__global__ __launch_bounds__(kRowThreads) void k_mixed_step(ProbDev P, int spar, int kslot) {
+  __shared__ StepCtx c;
+  __shared__ z64 pc[kMaxFreq][64];
+  __shared__ float red[2 * (kRowThreads / 64)];
+  const int tid = threadIdx.x;
+  const int i = blockIdx.x;
+  z32 crow[NPL];
+  if (P.nfreq == 1) {
+    const z32* c0 = P.C0[0] + size_t(i) * P.ld;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int j = tid + t * kRowThreads;
+      if (j < P.nd) crow[t] = c0[j];
+    }
+  }
+  if (tid == 0) step_decide(P, spar, kslot, true, c);
+  __syncthreads();
+  const int m = c.m;
+  if (m < 0) return;
+  const int slot = c.slot;
+  // panel coefficients alpha_k p_k[m] (reciprocity: q_k . g_m = p_k[m])
+  if (tid < slot)
+    for (int f = 0; f < P.nfreq; ++f)
+      pc[f][tid] = zmul(P.alph[f][tid], up32(P.Pp[f][size_t(tid) * P.ld + m]));
+  __syncthreads();
+  const int dp = spar;
+  const uint8_t* bin = dp ? P.bitsB : P.bits;
+  uint8_t* bout = dp ? P.bits : P.bitsB;
+  const uint8_t bit = bin[i] ^ (i == m ? 1 : 0);
+  const double delta = bit ? -P.deps : P.deps;
+  double df = 0.0, bnd = 0.0;
+  const int lane = tid & 63, wid = tid >> 6;
+  for (int f = 0; f < P.nfreq; ++f) {
+    const z32* c0 = P.C0[f] + size_t(i) * P.ld;
+    const z32* gm = P.G32[f] + size_t(m) * P.ld;
+    if (f > 0 || P.nfreq != 1) {   // frequency 0 was preloaded only when alone
+#pragma unroll
+      for (int t = 0; t < NPL; ++t) {
+        const int j = tid + t * kRowThreads;
+        if (j < P.nd) crow[t] = c0[j];
+      }
+    }
+    float pr = 0.f, pi = 0.f;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int j = tid + t * kRowThreads;
+      if (j < P.nd) {
+        const z32 a = crow[t], b = gm[j];
+        pr = fmaf(a.re, b.re, fmaf(-a.im, b.im, pr));
+        pi = fmaf(a.re, b.im, fmaf(a.im, b.re, pi));
+      }
+    }
+    if (tid < slot) {
+      const z64 cc = pc[f][tid];
+      const z32 pk = P.Pp[f][size_t(tid) * P.ld + i];
+      pr += float(cc.re * pk.re - cc.im * pk.im);
+      pi += float(cc.re * pk.im + cc.im * pk.re);
+    }
+    pr = wave_sumf(pr);
+    pi = wave_sumf(pi);
+    if (lane == 0) { red[2 * wid] = pr; red[2 * wid + 1] = pi; }
+    __syncthreads();
+    if (tid == 0) {
+      pr = pi = 0.f;
+      for (int w = 0; w < kRowThreads / 64; ++w) { pr += red[2 * w]; pi += red[2 * w + 1]; }
+      P.Pp[f][size_t(slot) * P.ld + i] = z32{pr, pi};
+      const z64 p = {double(pr), double(pi)};
+      const z64 ap = zmul(c.alpha[f], p);
+      const z64 Ei = zadd((dp ? P.EB : P.E)[f][i], zmul(ap, c.Em[f]));
+      const z64 Rpi = zadd((dp ? P.RpB : P.Rp)[f][i], zmul(ap, c.Rpm[f]));
+      const z64 tau = zadd((dp ? P.tauB : P.tau)[f][i], zmul(ap, p));
+      (dp ? P.E : P.EB)[f][i] = Ei;
+      (dp ? P.Rp : P.RpB)[f][i] = Rpi;
+      (dp ? P.tau : P.tauB)[f][i] = tau;
+      score_terms(P, c, f, tau, Ei, Rpi, delta, df, bnd);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    bout[i] = bit;
+    P.df32[i] = df;
+    P.dfb[i] = bnd;
+    const double margin = df - c.eta * c.f;
+    const double band = P.band * bnd;
+    if (margin >= -band) {
+      const uint32_t k = step_key(P, c, i);
+      if (k != kNoKey) atomicMin(&P.keys[(margin > band ? 0 : 3) + (kslot + 1) % 3], k);
+    }
+  }
+}
+
+// Panel q vectors rebuilt for a fold: q_k = C0^-1[m_k,:] + sum_{l<k} alpha_l
+// p_l[m_k] q_l (the row m_k of the inverse in force when slot k was made).
+__global__ __launch_bounds__(256) void k_fold_q(ProbDev P, int f, int kp) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= P.nd) return;
+  const z32* Pp = P.Pp[f];
+  z32* Qp = P.Qp[f];
+  for (int k = 0; k < kp; ++k) {
+    const int mk = P.pm[k];
+    z64 acc = up32(P.C0[f][size_t(mk) * P.ld + j]);
+    for (int l = 0; l < k; ++l) {
+      const z64 cf = zmul(P.alph[f][l], up32(Pp[size_t(l) * P.ld + mk]));
+      acc = zfma(cf, up32(Qp[size_t(l) * P.ld + j]), acc);
+    }
+    Qp[size_t(k) * P.ld + j] = z32{float(acc.re), float(acc.im)};
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+#define PNGF_STEP_SWITCH(KERNEL, npl, ...)                                                      \
+  switch (npl) {                                                                               \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                                  \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                                  \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                                  \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                                  \
+    case 16: hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__); break;                                \
+    case 32: hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__); break;                                \
+    default: return hipErrorInvalidValue;                                                      \
+  }
+
+hipError_t launch_plain_step(const ProbDev& P, int npl, int step, hipStream_t s) {
+  PNGF_STEP_SWITCH(k_plain_step, npl, dim3(P.nd), dim3(kRowThreads), 0, s, P, step & 1, step % 3)
+  return hipGetLastError();
+}
+
+hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s) {
+  PNGF_STEP_SWITCH(k_mixed_step, npl, dim3(P.nd), dim3(kRowThreads), 0, s, P, step & 1, step % 3)
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s) {
+  if (kp <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_q, dim3((P.nd + 255) / 256), dim3(256), 0, s, P, f, kp);
+  return hipGetLastError();
+}
+
+}  // namespace pngf
