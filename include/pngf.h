@@ -192,6 +192,52 @@ int pngf_kernel_times(pngf_handle *h, int32_t kernel_id, double *total_ms,
 
 int pngf_destroy(pngf_handle *h);
 
+/* ---- batches (many independent problems advanced together) -------------
+ * The per-frequency and per-design systems are independent (Results,
+ * Computational efficiency), so a batch advances every problem by one DBS
+ * step per launch: one workgroup per row of every active problem (or a
+ * persistent grid striding over them), captured as a hipGraph of 6 steps
+ * that is replayed until every problem has converged.  FP64 re-inversions
+ * (MIXED) are done per problem between replays.  Results equal the solo
+ * pngf_dbs_run of each problem. */
+typedef struct pngf_batch pngf_batch;
+
+/* handles[n]: distinct, each bound (same precision, same stream) before
+ * pngf_batch_bind; each needs pngf_set_design before pngf_batch_dbs_run.
+ * The batch does not own the handles. */
+int pngf_batch_create(pngf_handle *const *handles, int32_t n, pngf_batch **out);
+const char *pngf_batch_last_error(const pngf_batch *b);
+
+/* Device bytes of the batch workspace (problem descriptors and states). */
+int pngf_batch_workspace_bytes(pngf_batch *b, size_t *bytes);
+
+/* Bind caller-owned device memory (256-byte aligned) and the stream every
+ * handle is bound to; it must not be the legacy default stream (the steps are
+ * captured as a hipGraph).  PNGF_EINVAL otherwise. */
+int pngf_batch_bind(pngf_batch *b, void *dev_ws, size_t bytes, void *hip_stream);
+
+/* Launch shape: 0 = one workgroup per row, g > 0 = persistent grid of g
+ * workgroups (the autotuner's choice can be stored and set here). */
+int pngf_batch_set_grid(pngf_batch *b, int32_t grid);
+
+/* Run DBS on every problem: perms[p] / n_sweeps[p] as for pngf_dbs_run;
+ * accepted[p], f_trace[p] (capacity max_accepts of handle p, may be NULL) and
+ * results[p] receive each problem's outcome.  autotune != 0 times the
+ * candidate launch shapes on the first replays (identical arithmetic) and
+ * keeps the fastest; pngf_batch_tuning reports the timings. */
+int pngf_batch_dbs_run(pngf_batch *b, const int32_t *const *perms, const int32_t *n_sweeps,
+                       int32_t *const *accepted, double *const *f_trace,
+                       pngf_dbs_result *results, int32_t autotune);
+
+/* Autotuner record of the last run: grids[k] and device ms per step. */
+int pngf_batch_tuning(pngf_batch *b, int32_t *grids, double *ms_per_step, int32_t cap,
+                      int32_t *n);
+
+/* Device ms per batched step of the last replay (HIP events). */
+int pngf_batch_ms_per_step(pngf_batch *b, double *ms);
+
+int pngf_batch_destroy(pngf_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

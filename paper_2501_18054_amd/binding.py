@@ -80,6 +80,17 @@ EXPORTS = {
     "pngf_kernel_times": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double),
                            C.POINTER(C.c_int64)], C.c_int),
     "pngf_destroy": ([C.c_void_p], C.c_int),
+    "pngf_batch_create": ([C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
+    "pngf_batch_last_error": ([C.c_void_p], C.c_char_p),
+    "pngf_batch_workspace_bytes": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
+    "pngf_batch_bind": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "pngf_batch_set_grid": ([C.c_void_p, C.c_int32], C.c_int),
+    "pngf_batch_dbs_run": ([C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p, C.POINTER(C.c_void_p),
+                            C.POINTER(C.c_void_p), C.c_void_p, C.c_int32], C.c_int),
+    "pngf_batch_tuning": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                           C.POINTER(C.c_int32)], C.c_int),
+    "pngf_batch_ms_per_step": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    "pngf_batch_destroy": ([C.c_void_p], C.c_int),
 }
 
 
@@ -253,3 +264,78 @@ class Handle:
         n = C.c_int64()
         self._check(lib().pngf_kernel_times(self._h, KERNEL_IDS[name], C.byref(t), C.byref(n)))
         return t.value, n.value
+
+
+class Batch:
+    """Many handles advanced together (see the batch section of pngf.h)."""
+
+    def __init__(self, handles, stream=None):
+        import torch
+        L = lib()
+        self.handles = list(handles)
+        arr = (C.c_void_p * len(self.handles))(*[h._h for h in self.handles])
+        b = C.c_void_p()
+        rc = L.pngf_batch_create(arr, len(self.handles), C.byref(b))
+        if rc != 0:
+            raise PngfError(rc, L.pngf_batch_last_error(None).decode())
+        self._b = b
+        n = C.c_size_t()
+        self._check(L.pngf_batch_workspace_bytes(b, C.byref(n)))
+        self._ws = torch.empty(n.value + 256, dtype=torch.uint8, device="cuda:0")
+        aligned = (self._ws.data_ptr() + 255) & ~255
+        stream = stream or self.handles[0]._stream
+        self._check(L.pngf_batch_bind(b, C.c_void_p(aligned), n.value,
+                                      C.c_void_p(stream.cuda_stream)))
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PngfError(rc, lib().pngf_batch_last_error(self._b).decode())
+
+    def set_grid(self, grid):
+        self._check(lib().pngf_batch_set_grid(self._b, int(grid)))
+
+    def dbs_run(self, perms, autotune=False):
+        n = len(self.handles)
+        ps = [np.ascontiguousarray(p, dtype=np.int32) for p in perms]
+        ns = np.array([p.shape[0] for p in ps], dtype=np.int32)
+        accs = [np.empty(h.opts.max_accepts, np.int32) for h in self.handles]
+        ftrs = [np.empty(h.opts.max_accepts, np.float64) for h in self.handles]
+        res = (DbsResult * n)()
+        pp = (C.c_void_p * n)(*[p.ctypes.data for p in ps])
+        ap = (C.c_void_p * n)(*[a.ctypes.data for a in accs])
+        fp = (C.c_void_p * n)(*[f.ctypes.data for f in ftrs])
+        self._check(lib().pngf_batch_dbs_run(self._b, pp, _ptr(ns), ap, fp, C.byref(res),
+                                             1 if autotune else 0))
+        out = []
+        for k in range(n):
+            r = res[k]
+            m = r.n_accepted
+            out.append(dict(accepted=accs[k][:m].copy(), f_trace=ftrs[k][:m].copy(),
+                            n_accepted=m, sweeps=r.sweeps, converged=bool(r.converged),
+                            attempts=int(r.attempts), n_refresh=r.n_refresh,
+                            n_verified=int(r.n_verified), f_initial=r.f_initial,
+                            f_final=r.f_final))
+        return out
+
+    def tuning(self):
+        g = np.empty(16, np.int32)
+        ms = np.empty(16, np.float64)
+        n = C.c_int32()
+        self._check(lib().pngf_batch_tuning(self._b, _ptr(g), _ptr(ms), 16, C.byref(n)))
+        return list(zip(g[:n.value].tolist(), ms[:n.value].tolist()))
+
+    def ms_per_step(self):
+        v = C.c_double()
+        self._check(lib().pngf_batch_ms_per_step(self._b, C.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().pngf_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

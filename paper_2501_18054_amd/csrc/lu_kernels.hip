@@ -33,7 +33,7 @@
 namespace pngf {
 
 constexpr int kGjNb = 16;
-constexpr int kUpdRows = 32;
+constexpr int kUpdRows = 16;
 constexpr int kTsRows = 1024;              // candidate rows per tournament group
 constexpr int kTsFan = kTsRows / kGjNb;    // proposals merged per group
 
@@ -192,12 +192,22 @@ __global__ __launch_bounds__(kTsRows) void k_tsel(const z64* Pb, int n, int k0, 
 
 // Every panel row reduced by B11^-1: pivot rows (used[r]-1 in the panel) get
 // their row of B11^-1, the others -B_r B11^-1.  A workgroup handles 16 rows,
-// one thread per output entry.
+// one thread per output entry.  Workgroups past the panel rows copy the
+// panel's pivot rows of S into B1 (their values before the update).
 __global__ __launch_bounds__(256) void k_tapply(z64* Pb, int n, int k0, int ncols,
-                                                const int32_t* used, const z64* B11inv) {
+                                                const int32_t* used, const z64* B11inv,
+                                                const z64* S, int ld, const int32_t* piv,
+                                                z64* B1, int napply) {
   __shared__ z64 Bi[kGjNb][kGjNb];
   __shared__ z64 R[256 / kGjNb][kGjNb + 1];
   const int tid = threadIdx.x;
+  if (int(blockIdx.x) >= napply) {
+    // B1[c, j] = S[piv[k0+c], j]
+    const int e = (blockIdx.x - napply) * 256 + tid;
+    const int c = e / n, j = e % n;
+    if (c < ncols) B1[size_t(c) * ld + j] = S[size_t(piv[k0 + c]) * ld + j];
+    return;
+  }
   const int rr = tid / kGjNb, cc = tid % kGjNb;
   const int r = blockIdx.x * (256 / kGjNb) + rr;
   Bi[rr][cc] = B11inv[tid];
@@ -217,21 +227,14 @@ __global__ __launch_bounds__(256) void k_tapply(z64* Pb, int n, int k0, int ncol
   Pb[size_t(r) * kGjNb + cc] = (cc < ncols) ? out : z64{0.0, 0.0};
 }
 
-// B1[c, :] = S[piv[k0+c], :] (the panel's pivot rows before the update).
-__global__ __launch_bounds__(256) void k_gj_copy_rows(const z64* S, int ld, int n, int k0,
-                                                      int ncols, const int32_t* piv, z64* B1) {
-  const int c = blockIdx.y;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (c < ncols && j < n) B1[size_t(c) * ld + j] = S[size_t(piv[k0 + c]) * ld + j];
-}
-
 // Rank-ncols update of every column outside the panel; the panel columns get
 // their reduced values back from Pb, and the next panel's columns (updated
-// here) are also gathered into Pn.
+// here) are also gathered into Pn.  A workgroup covers 64 columns x
+// kUpdRows rows; thread (g, c) owns column c and rows g, g+4, ...
 __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0, int ncols,
                                                    const z64* B1, const int32_t* used,
                                                    const z64* Pb, z64* Pn) {
-  __shared__ z64 Pt[kUpdRows][kGjNb];
+  __shared__ z64 Pt[kUpdRows][kGjNb + 1];
   __shared__ int isp[kUpdRows];
   const int tid = threadIdx.x;
   const int r0 = blockIdx.y * kUpdRows;
@@ -246,11 +249,12 @@ __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0
     isp[tid] = (u >= k0 && u < k0 + ncols) ? 1 : 0;
   }
   __syncthreads();
-  const int j = blockIdx.x * 256 + tid;
+  const int j = blockIdx.x * 64 + (tid & 63);
+  const int rg = tid >> 6;
   if (j >= n) return;
-  const int rmax = min(kUpdRows, n - r0);
   if (j >= k0 && j < k0 + ncols) {
-    for (int rr = 0; rr < rmax; ++rr) S[size_t(r0 + rr) * ld + j] = Pt[rr][j - k0];
+    for (int rr = rg; rr < kUpdRows && r0 + rr < n; rr += 4)
+      S[size_t(r0 + rr) * ld + j] = Pt[rr][j - k0];
     return;
   }
   const int nxt = k0 + kGjNb;
@@ -258,7 +262,7 @@ __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0
   z64 b[kGjNb];
 #pragma unroll
   for (int c = 0; c < kGjNb; ++c) b[c] = (c < ncols) ? B1[size_t(c) * ld + j] : z64{0.0, 0.0};
-  for (int rr = 0; rr < rmax; ++rr) {
+  for (int rr = rg; rr < kUpdRows && r0 + rr < n; rr += 4) {
     z64* dst = S + size_t(r0 + rr) * ld + j;
     z64 acc = isp[rr] ? z64{0.0, 0.0} : *dst;
 #pragma unroll
@@ -427,12 +431,12 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
         nout = (nout == cntA) ? cntB : cntA;
         groups = (groups + kTsFan - 1) / kTsFan;
       }
-      hipLaunchKernelGGL(k_tapply, dim3((ns + 15) / 16), dim3(256), 0, s, Pb, ns, k0, nc, used,
-                         B11inv);
-      hipLaunchKernelGGL(k_gj_copy_rows, dim3(gcols.x, nc), dim3(256), 0, s, S, ld, ns, k0, nc,
-                         piv, B1);
-      hipLaunchKernelGGL(k_gj_update, dim3(gcols.x, (ns + kUpdRows - 1) / kUpdRows), dim3(256), 0,
-                         s, S, ld, ns, k0, nc, B1, used, Pb, Pn);
+      const int napply = (ns + 15) / 16;
+      const int ncopy = (nc * ns + 255) / 256;
+      hipLaunchKernelGGL(k_tapply, dim3(napply + ncopy), dim3(256), 0, s, Pb, ns, k0, nc, used,
+                         B11inv, S, ld, piv, B1, napply);
+      hipLaunchKernelGGL(k_gj_update, dim3((ns + 63) / 64, (ns + kUpdRows - 1) / kUpdRows),
+                         dim3(256), 0, s, S, ld, ns, k0, nc, B1, used, Pb, Pn);
       z64* t = Pb;
       Pb = Pn;
       Pn = t;

@@ -17,6 +17,8 @@ hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int
 hipError_t launch_plain_step(const ProbDev& P, int npl, int step, hipStream_t s);
 hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s);
 hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
+hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
+                             int grid, int npl, int mixed, int step, hipStream_t s);
 hipError_t launch_select_prep(const ProbDev& P, int forced, hipStream_t s);
 hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const int32_t* sidx,
@@ -36,6 +38,7 @@ constexpr int kGjNbHost = 16;
 constexpr int kPanelCap = 64;      // deferred Sherman-Morrison terms (mixed)
 constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
+constexpr int kDriftEvery = 32;    // accepts between drift checks
 }  // namespace pngf
 
 using pngf::cd;
@@ -452,6 +455,7 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
   const int64_t max_rounds = 4 * int64_t(h->opt.max_accepts) + 64;
   int64_t t = 0;                 // step index within the segment
   int64_t since = 0, kpan = 0;   // host view of n_since / kpanel
+  int64_t checked = 0;           // n_since at the last drift check
   for (int64_t round = 0; round < max_rounds; ++round) {
     // end the batch where a periodic re-inversion or a fold is due, so that
     // few launches of the batch find the search paused; batches stay even
@@ -465,7 +469,9 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
     if (pinned->done) break;
     bool refresh = pinned->need_refresh != 0;
     const bool band_hit = pinned->need_refresh == 2;
-    if (!refresh && h->opt.k_refresh == 0 && !pinned->exact) {
+    if (!refresh && h->opt.k_refresh == 0 && !pinned->exact &&
+        pinned->n_since >= checked + pngf::kDriftEvery) {
+      checked = pinned->n_since;
       double ratio = 0.0;
       st = mixed_residual(h, &ratio);
       if (st) return st;
@@ -478,7 +484,7 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
       if (st) return st;
       *n_refresh += 1;
       if (band_hit) *n_band += 1;
-      since = kpan = 0;
+      since = kpan = checked = 0;
       t = 0;
     } else if (pinned->kpanel >= pngf::kPanelCap - pngf::kMixedBatch ||
                (h->opt.k_fold > 0 && pinned->kpanel >= h->opt.k_fold)) {
@@ -504,6 +510,78 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
   HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
                            h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PNGF_OK;
+}
+
+
+// Validate and upload the sweep orders and reset the search bookkeeping of a
+// bound handle with a design; returns the initial objective in *f0.
+int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double* f0) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  const int nd = h->pc.n_d;
+  if (!perms || n_sweeps < 1 || n_sweeps > h->opt.max_sweeps)
+    return fail(h, PNGF_EINVAL, "n_sweeps must be in [1, max_sweeps]");
+  std::vector<int32_t> rank(size_t(n_sweeps) * nd, -1);
+  for (int s = 0; s < n_sweeps; ++s)
+    for (int q = 0; q < nd; ++q) {
+      const int32_t m = perms[size_t(s) * nd + q];
+      if (m < 0 || m >= nd || rank[size_t(s) * nd + m] != -1)
+        return fail(h, PNGF_EINVAL, "perms must hold permutations of the pixel ids");
+      rank[size_t(s) * nd + m] = q;
+    }
+  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.perm), perms, rank.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.rank), rank.data(), rank.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, h->stream));
+  pngf::DbsState s;
+  st = read_state(h, &s);
+  if (st) return st;
+  *f0 = s.f;
+  s.m = -1;
+  s.done = 0;
+  s.cursor_s = 0;
+  s.cursor_pos = 0;
+  s.n_acc = 0;
+  s.sweeps = 0;
+  s.converged = 0;
+  s.n_sweeps = n_sweeps;
+  s.attempts = 0;
+  s.key = pngf::kNoKey;
+  s.eta = h->opt.eta;
+  s.need_refresh = 0;
+  s.flips = 0;
+  // every search starts from the initial error band (it is recalibrated at
+  // each FP64 re-inversion), so repeated runs are identical
+  h->P.band = (h->opt.guard > 0.0) ? h->opt.guard : 1e-3;
+  for (int k = 0; k < KID_N; ++k) { h->ktime_ms[k] = 0.0; h->klaunch[k] = 0; }
+  return write_state(h, &s);
+}
+
+// Copy the accept log and fill the result summary.
+int dbs_epilogue(pngf_handle* h, const pngf::DbsState& fin, double f0, int64_t n_refresh,
+                 int64_t n_band, int32_t* accepted, double* f_trace, pngf_dbs_result* res) {
+  const int nd = h->pc.n_d;
+  const int na = fin.n_acc;
+  if (accepted && na > 0)
+    HIPCHK(h, hipMemcpyAsync(accepted, h->P.log_pix, na * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  if (f_trace && na > 0)
+    HIPCHK(h, hipMemcpyAsync(f_trace, h->P.log_f, na * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->bits.data(), h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  if (!std::isfinite(fin.f)) return fail(h, PNGF_ENUMERIC, "objective is not finite");
+  if (res) {
+    res->n_accepted = na;
+    res->sweeps = fin.sweeps;
+    res->converged = fin.converged;
+    res->n_refresh = int32_t(n_refresh);
+    res->attempts = fin.attempts;
+    res->n_verified = n_band;
+    res->f_initial = f0;
+    res->f_final = fin.f;
+  }
+  h->f_host = fin.f;
   return PNGF_OK;
 }
 
@@ -754,41 +832,9 @@ int pngf_refresh(pngf_handle* h) {
 
 int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t* accepted,
                  double* f_trace, pngf_dbs_result* res) {
-  int st = check_ready(h, true);
+  double f0 = 0.0;
+  int st = dbs_prologue(h, perms, n_sweeps, &f0);
   if (st) return st;
-  const int nd = h->pc.n_d;
-  if (!perms || n_sweeps < 1 || n_sweeps > h->opt.max_sweeps)
-    return fail(h, PNGF_EINVAL, "n_sweeps must be in [1, max_sweeps]");
-  std::vector<int32_t> rank(size_t(n_sweeps) * nd, -1);
-  for (int s = 0; s < n_sweeps; ++s)
-    for (int q = 0; q < nd; ++q) {
-      const int32_t m = perms[size_t(s) * nd + q];
-      if (m < 0 || m >= nd || rank[size_t(s) * nd + m] != -1)
-        return fail(h, PNGF_EINVAL, "perms must hold permutations of the pixel ids");
-      rank[size_t(s) * nd + m] = q;
-    }
-  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.perm), perms, rank.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.rank), rank.data(), rank.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, h->stream));
-  pngf::DbsState s;
-  st = read_state(h, &s);
-  if (st) return st;
-  const double f0 = s.f;
-  s.m = -1;
-  s.done = 0;
-  s.cursor_s = 0;
-  s.cursor_pos = 0;
-  s.n_acc = 0;
-  s.sweeps = 0;
-  s.converged = 0;
-  s.n_sweeps = n_sweeps;
-  s.attempts = 0;
-  s.key = pngf::kNoKey;
-  s.eta = h->opt.eta;
-  st = write_state(h, &s);
-  if (st) return st;
-  for (int k = 0; k < KID_N; ++k) { h->ktime_ms[k] = 0.0; h->klaunch[k] = 0; }
   pngf::DbsState* pinned = nullptr;
   HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(pngf::DbsState)));
   int64_t n_refresh = 0, n_band = 0;
@@ -797,27 +843,7 @@ int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t
   pngf::DbsState fin = *pinned;
   hipHostFree(pinned);
   if (rc) return rc;
-  const int na = fin.n_acc;
-  if (accepted && na > 0)
-    HIPCHK(h, hipMemcpyAsync(accepted, h->P.log_pix, na * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-  if (f_trace && na > 0)
-    HIPCHK(h, hipMemcpyAsync(f_trace, h->P.log_f, na * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipMemcpyAsync(h->bits.data(), h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
-  if (!std::isfinite(fin.f)) return fail(h, PNGF_ENUMERIC, "objective is not finite");
-  if (res) {
-    res->n_accepted = na;
-    res->sweeps = fin.sweeps;
-    res->converged = fin.converged;
-    res->n_refresh = int32_t(n_refresh);
-    res->attempts = fin.attempts;
-    res->n_verified = n_band;
-    res->f_initial = f0;
-    res->f_final = fin.f;
-  }
-  h->f_host = fin.f;
-  return PNGF_OK;
+  return dbs_epilogue(h, fin, f0, n_refresh, n_band, accepted, f_trace, res);
 }
 
 int pngf_kernel_times(pngf_handle* h, int32_t kid, double* total_ms, int64_t* launches) {
@@ -834,6 +860,350 @@ int pngf_destroy(pngf_handle* h) {
     hipEventDestroy(h->ev_pool[k + 1]);
   }
   delete h;
+  return PNGF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+struct pngf_batch {
+  std::vector<pngf_handle*> hs;
+  std::string err;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  pngf::ProbDev* d_probs = nullptr;
+  int32_t* d_row0 = nullptr;
+  pngf::DbsState* d_states = nullptr;   // [2n]: A and B slot of every problem
+  int npl = 1;
+  int mixed = 0;
+  int grid = 0;                         // 0 = one workgroup per row
+  bool bound = false;
+  // captured 6-step graph for the current active set and grid
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int g_total = -1, g_grid = -1, g_nprob = -1;
+  // autotuner record
+  std::vector<int32_t> tune_grid;
+  std::vector<double> tune_ms;
+  double last_ms_per_step = 0.0;
+};
+
+namespace {
+
+int bfail(pngf_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg; else g_create_error = msg;
+  return code;
+}
+
+#define BHIPCHK(b, call)                                                       \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return bfail(b, PNGF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t batch_bytes(int n) {
+  return align256(size_t(n) * sizeof(pngf::ProbDev)) + align256(size_t(n + 1) * sizeof(int32_t)) +
+         align256(size_t(2 * n) * sizeof(pngf::DbsState));
+}
+
+void drop_graph(pngf_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->g_total = b->g_grid = b->g_nprob = -1;
+}
+
+// Upload the descriptors of the active problems and (re)capture the 6-step
+// graph (one full cycle of state parity and key slot) for the launch shape.
+int batch_prepare(pngf_batch* b, const std::vector<int>& active, int grid) {
+  std::vector<pngf::ProbDev> probs;
+  std::vector<int32_t> row0(1, 0);
+  for (int p : active) {
+    probs.push_back(b->hs[p]->P);
+    row0.push_back(row0.back() + b->hs[p]->pc.n_d);
+  }
+  const int n = int(active.size());
+  if (n == 0) return PNGF_OK;
+  BHIPCHK(b, hipMemcpyAsync(b->d_probs, probs.data(), n * sizeof(pngf::ProbDev),
+                            hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipMemcpyAsync(b->d_row0, row0.data(), (n + 1) * sizeof(int32_t),
+                            hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  const int total = row0.back();
+  if (b->exec && b->g_total == total && b->g_grid == grid && b->g_nprob == n) return PNGF_OK;
+  drop_graph(b);
+  BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  for (int t = 0; t < 6; ++t) {
+    hipError_t e = pngf::launch_batch_step(b->d_probs, b->d_row0, n, total, grid, b->npl,
+                                           b->mixed, t, b->stream);
+    if (e != hipSuccess) {
+      hipGraph_t g = nullptr;
+      hipStreamEndCapture(b->stream, &g);
+      if (g) hipGraphDestroy(g);
+      return bfail(b, PNGF_EDEVICE, std::string("batch step capture: ") + hipGetErrorString(e));
+    }
+  }
+  BHIPCHK(b, hipStreamEndCapture(b->stream, &b->graph));
+  BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  b->g_total = total;
+  b->g_grid = grid;
+  b->g_nprob = n;
+  return PNGF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pngf_batch_create(pngf_handle* const* handles, int32_t n, pngf_batch** out) {
+  if (!out) return bfail(nullptr, PNGF_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!handles || n < 1) return bfail(nullptr, PNGF_EINVAL, "need at least one handle");
+  pngf_batch* b = new (std::nothrow) pngf_batch();
+  if (!b) return bfail(nullptr, PNGF_ENOMEM, "out of host memory");
+  for (int p = 0; p < n; ++p) {
+    if (!handles[p]) { delete b; return bfail(nullptr, PNGF_EINVAL, "null handle in batch"); }
+    for (int q = 0; q < p; ++q)
+      if (handles[q] == handles[p]) { delete b; return bfail(nullptr, PNGF_EINVAL, "handle listed twice"); }
+    b->hs.push_back(handles[p]);
+  }
+  *out = b;
+  return PNGF_OK;
+}
+
+const char* pngf_batch_last_error(const pngf_batch* b) {
+  return b ? b->err.c_str() : g_create_error.c_str();
+}
+
+int pngf_batch_workspace_bytes(pngf_batch* b, size_t* bytes) {
+  if (!b || !bytes) return PNGF_EINVAL;
+  *bytes = batch_bytes(int(b->hs.size()));
+  return PNGF_OK;
+}
+
+int pngf_batch_bind(pngf_batch* b, void* dev_ws, size_t bytes, void* stream) {
+  if (!b || !dev_ws) return PNGF_EINVAL;
+  const int n = int(b->hs.size());
+  if (bytes < batch_bytes(n)) return bfail(b, PNGF_ENOMEM, "batch workspace too small");
+  if (reinterpret_cast<uintptr_t>(dev_ws) & 255)
+    return bfail(b, PNGF_EINVAL, "workspace must be 256-byte aligned");
+  if (stream == nullptr)
+    return bfail(b, PNGF_EINVAL, "a batch needs a non-default stream (graph capture)");
+  int npl = 1;
+  const int prec = b->hs[0]->opt.precision;
+  for (pngf_handle* h : b->hs) {
+    if (!h->bound) return bfail(b, PNGF_ESTATE, "every handle must be bound");
+    if (h->opt.precision != prec) return bfail(b, PNGF_EINVAL, "mixed precisions in one batch");
+    if (h->stream != static_cast<hipStream_t>(stream))
+      return bfail(b, PNGF_EINVAL, "every handle must be bound to the batch stream");
+    npl = std::max(npl, h->npl);
+  }
+  drop_graph(b);
+  b->ws = static_cast<char*>(dev_ws);
+  b->ws_bytes = bytes;
+  b->stream = static_cast<hipStream_t>(stream);
+  size_t off = 0;
+  b->d_probs = reinterpret_cast<pngf::ProbDev*>(b->ws + off);
+  off += align256(size_t(n) * sizeof(pngf::ProbDev));
+  b->d_row0 = reinterpret_cast<int32_t*>(b->ws + off);
+  off += align256(size_t(n + 1) * sizeof(int32_t));
+  b->d_states = reinterpret_cast<pngf::DbsState*>(b->ws + off);
+  b->npl = npl;
+  b->mixed = (prec == PNGF_MIXED) ? 1 : 0;
+  b->bound = true;
+  return PNGF_OK;
+}
+
+int pngf_batch_set_grid(pngf_batch* b, int32_t grid) {
+  if (!b || grid < 0) return PNGF_EINVAL;
+  b->grid = grid;
+  return PNGF_OK;
+}
+
+int pngf_batch_tuning(pngf_batch* b, int32_t* grids, double* ms_per_step, int32_t cap,
+                      int32_t* n) {
+  if (!b || !n) return PNGF_EINVAL;
+  *n = int32_t(b->tune_grid.size());
+  for (int k = 0; k < std::min<int>(cap, *n); ++k) {
+    if (grids) grids[k] = b->tune_grid[k];
+    if (ms_per_step) ms_per_step[k] = b->tune_ms[k];
+  }
+  return PNGF_OK;
+}
+
+int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t* n_sweeps,
+                       int32_t* const* accepted, double* const* f_trace,
+                       pngf_dbs_result* results, int32_t autotune) {
+  if (!b || !b->bound) return bfail(b, PNGF_ESTATE, "batch is not bound");
+  if (!perms || !n_sweeps) return bfail(b, PNGF_EINVAL, "null perms / n_sweeps");
+  const int n = int(b->hs.size());
+  std::vector<double> f0(n, 0.0);
+  std::vector<int64_t> nref(n, 0), nband(n, 0);
+  // per-problem start: prologue, FP32 copies (mixed), scoring into key slot 0
+  for (int p = 0; p < n; ++p) {
+    pngf_handle* h = b->hs[p];
+    int st = dbs_prologue(h, perms[p], n_sweeps[p], &f0[p]);
+    if (st) return bfail(b, st, std::string("problem ") + std::to_string(p) + ": " + h->err);
+    if (b->mixed) {
+      for (int f = 0; f < int(h->pc.freq.size()); ++f)
+        BHIPCHK(b, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], h->pc.n_d, h->ld, b->stream));
+      pngf::DbsState s;
+      st = read_state(h, &s);
+      if (st) return bfail(b, st, h->err);
+      s.kpanel = 0;
+      s.n_since = 0;
+      s.exact = 1;
+      s.n_band = 0;
+      st = write_state(h, &s);
+      if (st) return bfail(b, st, h->err);
+    }
+    st = start_segment(h);
+    if (st) return bfail(b, st, h->err);
+  }
+  // move every state into the batch slots (A = 2p, B = 2p+1)
+  std::vector<pngf::DbsState*> own_a(n), own_b(n);
+  for (int p = 0; p < n; ++p) {
+    pngf_handle* h = b->hs[p];
+    own_a[p] = h->P.st;
+    own_b[p] = h->P.stB;
+    BHIPCHK(b, hipMemcpyAsync(&b->d_states[2 * p], h->P.st, sizeof(pngf::DbsState),
+                              hipMemcpyDeviceToDevice, b->stream));
+    h->P.st = &b->d_states[2 * p];
+    h->P.stB = &b->d_states[2 * p + 1];
+  }
+  std::vector<int> active(n);
+  for (int p = 0; p < n; ++p) active[p] = p;
+  pngf::DbsState* host_states = nullptr;
+  BHIPCHK(b, hipHostMalloc(reinterpret_cast<void**>(&host_states), 2 * n * sizeof(pngf::DbsState)));
+  int rc = PNGF_OK;
+  // autotuner: candidate launch shapes, each timed on one 6-step replay of
+  // the live search (every shape gives bitwise the same per-row arithmetic)
+  std::vector<int> cand;
+  if (autotune) {
+    cand = {0, 8192, 4096, 2048, 1024};
+    b->tune_grid.clear();
+    b->tune_ms.clear();
+  }
+  size_t ci = 0;
+  int grid = b->grid;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  int64_t max_rounds = 0;
+  for (pngf_handle* h : b->hs) max_rounds = std::max<int64_t>(max_rounds, 4 * int64_t(h->opt.max_accepts) + 64);
+  for (int64_t round = 0; round < max_rounds && !active.empty(); ++round) {
+    const bool tuning = ci < cand.size();
+    if (tuning) grid = cand[ci];
+    rc = batch_prepare(b, active, grid);
+    if (rc) break;
+    hipEventRecord(e0, b->stream);
+    const int reps = tuning ? 1 : 2;
+    for (int r = 0; r < reps && rc == PNGF_OK; ++r) {
+      hipError_t e = hipGraphLaunch(b->exec, b->stream);
+      if (e != hipSuccess) rc = bfail(b, PNGF_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    }
+    if (rc) break;
+    hipEventRecord(e1, b->stream);
+    hipError_t e = hipMemcpyAsync(host_states, b->d_states, 2 * n * sizeof(pngf::DbsState),
+                                  hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) { rc = bfail(b, PNGF_EDEVICE, hipGetErrorString(e)); break; }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    b->last_ms_per_step = ms / (6.0 * reps);
+    if (tuning) {
+      b->tune_grid.push_back(cand[ci]);
+      b->tune_ms.push_back(ms / 6.0);
+      if (++ci == cand.size()) {
+        size_t best = 0;
+        for (size_t k = 1; k < b->tune_ms.size(); ++k)
+          if (b->tune_ms[k] < b->tune_ms[best]) best = k;
+        b->grid = grid = b->tune_grid[best];
+      }
+    }
+    std::vector<int> next;
+    bool changed = false;
+    for (int p : active) {
+      pngf_handle* h = b->hs[p];
+      pngf::DbsState& s = host_states[2 * p];
+      const bool was_odd = s.flips & 1;
+      if (normalize(h, &s)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
+      changed |= was_odd;
+      if (s.done) { changed = true; continue; }
+      if (b->mixed) {
+        bool refresh = s.need_refresh != 0;
+        const bool band_hit = s.need_refresh == 2;
+        if (!refresh && h->opt.k_refresh == 0 && !s.exact && s.n_since >= pngf::kDriftEvery) {
+          double ratio = 0.0;
+          if (mixed_residual(h, &ratio)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
+          refresh = ratio > pngf::kDriftTol;
+        }
+        if (refresh) {
+          if (mixed_refresh(h, !s.exact)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
+          nref[p] += 1;
+          if (band_hit) nband[p] += 1;
+          changed = true;
+        } else if (s.kpanel >= pngf::kPanelCap - 12 ||
+                   (h->opt.k_fold > 0 && s.kpanel >= h->opt.k_fold)) {
+          for (int f = 0; f < int(h->pc.freq.size()); ++f) {
+            if (pngf::launch_fold_q(h->P, f, s.kpanel, b->stream) != hipSuccess ||
+                pngf::launch_fold(h->P, f, s.kpanel, b->stream) != hipSuccess) {
+              rc = bfail(b, PNGF_EDEVICE, "fold launch failed");
+              break;
+            }
+          }
+          if (rc) break;
+          s.kpanel = 0;
+          if (write_state(h, &s)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
+        }
+      }
+      next.push_back(p);
+    }
+    if (rc) break;
+    if (next.size() != active.size()) changed = true;
+    active.swap(next);
+    (void)changed;   // descriptors are re-uploaded every round (pointers may swap)
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == PNGF_OK && !active.empty()) rc = bfail(b, PNGF_ENUMERIC, "batch search did not terminate");
+  // final FP64 state (mixed), results, and states back to each handle
+  for (int p = 0; p < n && rc == PNGF_OK; ++p) {
+    pngf_handle* h = b->hs[p];
+    if (b->mixed && device_reinvert(h)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
+    pngf::DbsState fin;
+    if (read_state(h, &fin)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
+    if (dbs_epilogue(h, fin, f0[p], nref[p], nband[p], accepted ? accepted[p] : nullptr,
+                     f_trace ? f_trace[p] : nullptr, results ? &results[p] : nullptr)) {
+      rc = bfail(b, PNGF_ENUMERIC, h->err);
+      break;
+    }
+  }
+  for (int p = 0; p < n; ++p) {
+    pngf_handle* h = b->hs[p];
+    if (h->P.st != own_a[p])
+      hipMemcpyAsync(own_a[p], h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToDevice, b->stream);
+    h->P.st = own_a[p];
+    h->P.stB = own_b[p];
+  }
+  hipStreamSynchronize(b->stream);
+  hipHostFree(host_states);
+  return rc;
+}
+
+int pngf_batch_ms_per_step(pngf_batch* b, double* ms) {
+  if (!b || !ms) return PNGF_EINVAL;
+  *ms = b->last_ms_per_step;
+  return PNGF_OK;
+}
+
+int pngf_batch_destroy(pngf_batch* b) {
+  if (!b) return PNGF_OK;
+  drop_graph(b);
+  delete b;
   return PNGF_OK;
 }
 

@@ -85,7 +85,7 @@ __device__ __forceinline__ uint32_t step_key(const ProbDev& P, const StepCtx& c,
 // Thread 0: read the state of this step, decide, fill the context; workgroup 0
 // publishes the next state and clears the key slot two steps ahead.
 __device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool mixed,
-                                   StepCtx& c) {
+                                   StepCtx& c, bool publish) {
   const DbsState* sin = spar ? P.stB : P.st;
   DbsState* sout = spar ? P.st : P.stB;
   StepScalars st;
@@ -127,10 +127,10 @@ __device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool m
     double fnew = 0.0;
     for (int f = 0; f < P.nfreq; ++f) {
       const double kd = P.k0sq[f] * delta;
-      const z64 tau = (dpar ? P.tauB : P.tau)[f][m];
+      const z64 tau = (dpar ? P.tauB[f] : P.tau[f])[m];
       const z64 den = {1.0 - kd * tau.re, -kd * tau.im};
       const z64 alpha = zdiv(z64{kd, 0.0}, den);
-      const z64 Em = (dpar ? P.EB : P.E)[f][m], Rpm = (dpar ? P.RpB : P.Rp)[f][m];
+      const z64 Em = (dpar ? P.EB[f] : P.E[f])[m], Rpm = (dpar ? P.RpB[f] : P.Rp[f])[m];
       c.alpha[f] = alpha;
       c.Em[f] = Em;
       c.Rpm[f] = Rpm;
@@ -158,7 +158,7 @@ __device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool m
   c.ns = st.n_sweeps;
   c.f = st.f;
   c.eta = st.eta;
-  if (blockIdx.x == 0) {
+  if (publish) {
     // next state: copy, then overwrite what this step changed
     const uint64_t* src = reinterpret_cast<const uint64_t*>(sin);
     uint64_t* dst = reinterpret_cast<uint64_t*>(sout);
@@ -210,15 +210,13 @@ __device__ __forceinline__ void score_terms(const ProbDev& P, const StepCtx& c, 
 // starts at step 0 with the A set current, and each update flips the set), so
 // row i of C^-1 and of G is streamed before the decision is known.
 template <int NPL>
-__global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar, int kslot) {
-  __shared__ StepCtx c;
+__device__ inline void plain_step_row(const ProbDev& P, int i, int spar, int kslot, StepCtx& c) {
   __shared__ double red[2 * (kRowThreads / 64)];
   const int tid = threadIdx.x;
-  const int i = blockIdx.x;
   const int dp = spar;
   z64 row[NPL], grow[NPL];
   if (P.nfreq == 1) {
-    const z64* ci = (dp ? P.CinvB : P.Cinv)[0] + size_t(i) * P.ld;
+    const z64* ci = (dp ? P.CinvB[0] : P.Cinv[0]) + size_t(i) * P.ld;
     const z64* Gi = P.G[0] + size_t(i) * P.ld;
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
@@ -226,18 +224,26 @@ __global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar,
       if (j < P.nd) { row[t] = ci[j]; grow[t] = Gi[j]; }
     }
   }
-  if (tid == 0) step_decide(P, spar, kslot, false, c);
+  // this row's vector entries, also independent of the decision
+  const uint8_t* bin = dp ? P.bitsB : P.bits;
+  uint8_t* bout = dp ? P.bits : P.bitsB;
+  z64 e0{0.0, 0.0}, r0{0.0, 0.0};
+  uint8_t b0 = 0;
+  if (tid == 0) {
+    b0 = bin[i];
+    e0 = (dp ? P.EB[0] : P.E[0])[i];
+    r0 = (dp ? P.RpB[0] : P.Rp[0])[i];
+    step_decide(P, spar, kslot, false, c, i == 0);
+  }
   __syncthreads();
   const int m = c.m;
   if (m < 0) return;
-  const uint8_t* bin = dp ? P.bitsB : P.bits;
-  uint8_t* bout = dp ? P.bits : P.bitsB;
-  const uint8_t bit = bin[i] ^ (i == m ? 1 : 0);
+  const uint8_t bit = b0 ^ (i == m ? 1 : 0);
   const double delta = bit ? -P.deps : P.deps;
   double df = 0.0, bnd = 0.0;
   for (int f = 0; f < P.nfreq; ++f) {
-    const z64* Cin = (dp ? P.CinvB : P.Cinv)[f];
-    z64* Cout = (dp ? P.Cinv : P.CinvB)[f];
+    const z64* Cin = (dp ? P.CinvB[f] : P.Cinv[f]);
+    z64* Cout = (dp ? P.Cinv[f] : P.CinvB[f]);
     const z64* ci = Cin + size_t(i) * P.ld;
     const z64* q = Cin + size_t(m) * P.ld;
     const z64* gm = P.G[f] + size_t(m) * P.ld;
@@ -270,11 +276,13 @@ __global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar,
     }
     const z64 tau = block_zsum(acc, red);
     if (tid == 0) {
-      const z64 Ei = zadd((dp ? P.EB : P.E)[f][i], zmul(ap, c.Em[f]));
-      const z64 Rpi = zadd((dp ? P.RpB : P.Rp)[f][i], zmul(ap, c.Rpm[f]));
-      (dp ? P.E : P.EB)[f][i] = Ei;
-      (dp ? P.Rp : P.RpB)[f][i] = Rpi;
-      (dp ? P.tau : P.tauB)[f][i] = tau;
+      const z64 Ein = f == 0 ? e0 : (dp ? P.EB[f] : P.E[f])[i];
+      const z64 Rin = f == 0 ? r0 : (dp ? P.RpB[f] : P.Rp[f])[i];
+      const z64 Ei = zadd(Ein, zmul(ap, c.Em[f]));
+      const z64 Rpi = zadd(Rin, zmul(ap, c.Rpm[f]));
+      (dp ? P.E[f] : P.EB[f])[i] = Ei;
+      (dp ? P.Rp[f] : P.RpB[f])[i] = Rpi;
+      (dp ? P.tau[f] : P.tauB[f])[i] = tau;
       score_terms(P, c, f, tau, Ei, Rpi, delta, df, bnd);
     }
   }
@@ -289,12 +297,9 @@ __global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar,
 }
 
 template <int NPL>
-__global__ __launch_bounds__(kRowThreads) void k_mixed_step(ProbDev P, int spar, int kslot) {
-  __shared__ StepCtx c;
-  __shared__ z64 pc[kMaxFreq][64];
-  __shared__ float red[2 * (kRowThreads / 64)];
+__device__ inline void mixed_step_row(const ProbDev& P, int i, int spar, int kslot, StepCtx& c,
+                                      z64 (*pc)[64], float* red) {
   const int tid = threadIdx.x;
-  const int i = blockIdx.x;
   z32 crow[NPL];
   if (P.nfreq == 1) {
     const z32* c0 = P.C0[0] + size_t(i) * P.ld;
@@ -304,7 +309,17 @@ __global__ __launch_bounds__(kRowThreads) void k_mixed_step(ProbDev P, int spar,
       if (j < P.nd) crow[t] = c0[j];
     }
   }
-  if (tid == 0) step_decide(P, spar, kslot, true, c);
+  const uint8_t* bin = spar ? P.bitsB : P.bits;
+  uint8_t* bout = spar ? P.bits : P.bitsB;
+  z64 e0{0.0, 0.0}, r0{0.0, 0.0}, t0{0.0, 0.0};
+  uint8_t b0 = 0;
+  if (tid == 0) {
+    b0 = bin[i];
+    e0 = (spar ? P.EB[0] : P.E[0])[i];
+    r0 = (spar ? P.RpB[0] : P.Rp[0])[i];
+    t0 = (spar ? P.tauB[0] : P.tau[0])[i];
+    step_decide(P, spar, kslot, true, c, i == 0);
+  }
   __syncthreads();
   const int m = c.m;
   if (m < 0) return;
@@ -315,9 +330,7 @@ __global__ __launch_bounds__(kRowThreads) void k_mixed_step(ProbDev P, int spar,
       pc[f][tid] = zmul(P.alph[f][tid], up32(P.Pp[f][size_t(tid) * P.ld + m]));
   __syncthreads();
   const int dp = spar;
-  const uint8_t* bin = dp ? P.bitsB : P.bits;
-  uint8_t* bout = dp ? P.bits : P.bitsB;
-  const uint8_t bit = bin[i] ^ (i == m ? 1 : 0);
+  const uint8_t bit = b0 ^ (i == m ? 1 : 0);
   const double delta = bit ? -P.deps : P.deps;
   double df = 0.0, bnd = 0.0;
   const int lane = tid & 63, wid = tid >> 6;
@@ -357,12 +370,15 @@ __global__ __launch_bounds__(kRowThreads) void k_mixed_step(ProbDev P, int spar,
       P.Pp[f][size_t(slot) * P.ld + i] = z32{pr, pi};
       const z64 p = {double(pr), double(pi)};
       const z64 ap = zmul(c.alpha[f], p);
-      const z64 Ei = zadd((dp ? P.EB : P.E)[f][i], zmul(ap, c.Em[f]));
-      const z64 Rpi = zadd((dp ? P.RpB : P.Rp)[f][i], zmul(ap, c.Rpm[f]));
-      const z64 tau = zadd((dp ? P.tauB : P.tau)[f][i], zmul(ap, p));
-      (dp ? P.E : P.EB)[f][i] = Ei;
-      (dp ? P.Rp : P.RpB)[f][i] = Rpi;
-      (dp ? P.tau : P.tauB)[f][i] = tau;
+      const z64 Ein = f == 0 ? e0 : (dp ? P.EB[f] : P.E[f])[i];
+      const z64 Rin = f == 0 ? r0 : (dp ? P.RpB[f] : P.Rp[f])[i];
+      const z64 Tin = f == 0 ? t0 : (dp ? P.tauB[f] : P.tau[f])[i];
+      const z64 Ei = zadd(Ein, zmul(ap, c.Em[f]));
+      const z64 Rpi = zadd(Rin, zmul(ap, c.Rpm[f]));
+      const z64 tau = zadd(Tin, zmul(ap, p));
+      (dp ? P.E[f] : P.EB[f])[i] = Ei;
+      (dp ? P.Rp[f] : P.RpB[f])[i] = Rpi;
+      (dp ? P.tau[f] : P.tauB[f])[i] = tau;
       score_terms(P, c, f, tau, Ei, Rpi, delta, df, bnd);
     }
     __syncthreads();
@@ -380,20 +396,67 @@ __global__ __launch_bounds__(kRowThreads) void k_mixed_step(ProbDev P, int spar,
   }
 }
 
+template <int NPL>
+__global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar, int kslot) {
+  __shared__ StepCtx c;
+  plain_step_row<NPL>(P, blockIdx.x, spar, kslot, c);
+}
+
+template <int NPL>
+__global__ __launch_bounds__(kRowThreads) void k_mixed_step(ProbDev P, int spar, int kslot) {
+  __shared__ StepCtx c;
+  __shared__ z64 pc[kMaxFreq][64];
+  __shared__ float red[2 * (kRowThreads / 64)];
+  mixed_step_row<NPL>(P, blockIdx.x, spar, kslot, c, pc, red);
+}
+
+// Batched step: one launch advances every problem of a batch by one step.
+// Work item b (a row of one problem) maps to problem p with
+// row0[p] <= b < row0[p+1]; the grid is either one workgroup per item or a
+// persistent grid that strides over the items (launch shape chosen by the
+// autotuner).  Problems are independent (Results, Computational efficiency:
+// per-frequency and per-design systems need no communication).
+template <int NPL>
+__global__ __launch_bounds__(kRowThreads) void k_batch_step(const ProbDev* probs,
+                                                            const int32_t* row0, int nprob,
+                                                            int mixed, int spar, int kslot) {
+  __shared__ StepCtx c;
+  __shared__ z64 pc[kMaxFreq][64];
+  __shared__ float redf[2 * (kRowThreads / 64)];
+  const int total = row0[nprob];
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    int lo = 0, hi = nprob - 1;       // largest p with row0[p] <= b
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (row0[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const ProbDev& P = probs[lo];
+    const int i = b - row0[lo];
+    __syncthreads();   // the previous item is done with the shared context
+    if (mixed) mixed_step_row<NPL>(P, i, spar, kslot, c, pc, redf);
+    else plain_step_row<NPL>(P, i, spar, kslot, c);
+  }
+}
+
 // Panel q vectors rebuilt for a fold: q_k = C0^-1[m_k,:] + sum_{l<k} alpha_l
 // p_l[m_k] q_l (the row m_k of the inverse in force when slot k was made).
+// The coefficients alpha_l p_l[m_k] are formed once per workgroup in LDS.
 __global__ __launch_bounds__(256) void k_fold_q(ProbDev P, int f, int kp) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= P.nd) return;
+  __shared__ z64 cf[64][65];
+  __shared__ int mk[64];
   const z32* Pp = P.Pp[f];
   z32* Qp = P.Qp[f];
+  for (int e = threadIdx.x; e < kp * kp; e += 256) {
+    const int k = e / kp, l = e % kp;
+    cf[k][l] = (l < k) ? zmul(P.alph[f][l], up32(Pp[size_t(l) * P.ld + P.pm[k]])) : z64{0.0, 0.0};
+  }
+  if (threadIdx.x < kp) mk[threadIdx.x] = P.pm[threadIdx.x];
+  __syncthreads();
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= P.nd) return;
   for (int k = 0; k < kp; ++k) {
-    const int mk = P.pm[k];
-    z64 acc = up32(P.C0[f][size_t(mk) * P.ld + j]);
-    for (int l = 0; l < k; ++l) {
-      const z64 cf = zmul(P.alph[f][l], up32(Pp[size_t(l) * P.ld + mk]));
-      acc = zfma(cf, up32(Qp[size_t(l) * P.ld + j]), acc);
-    }
+    z64 acc = up32(P.C0[f][size_t(mk[k]) * P.ld + j]);
+    for (int l = 0; l < k; ++l) acc = zfma(cf[k][l], up32(Qp[size_t(l) * P.ld + j]), acc);
     Qp[size_t(k) * P.ld + j] = z32{float(acc.re), float(acc.im)};
   }
 }
@@ -417,6 +480,15 @@ hipError_t launch_plain_step(const ProbDev& P, int npl, int step, hipStream_t s)
 
 hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s) {
   PNGF_STEP_SWITCH(k_mixed_step, npl, dim3(P.nd), dim3(kRowThreads), 0, s, P, step & 1, step % 3)
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
+                             int grid, int npl, int mixed, int step, hipStream_t s) {
+  const int g = (grid > 0 && grid < total) ? grid : total;
+  if (g <= 0) return hipSuccess;
+  PNGF_STEP_SWITCH(k_batch_step, npl, dim3(g), dim3(kRowThreads), 0, s, probs, row0, nprob, mixed,
+                   step & 1, step % 3)
   return hipGetLastError();
 }
 
