@@ -238,6 +238,71 @@ int pngf_batch_ms_per_step(pngf_batch *b, double *ms);
 
 int pngf_batch_destroy(pngf_batch *b);
 
+/* ---- learned flip proposal ------------------------------------------------
+ * Not in the paper, which contrasts PNGF's exact evaluations with surrogate
+ * models: here a network only ORDERS the exact PNGF evaluations
+ * (eq. lru_eobj_rs) and never decides a flip.
+ *
+ * Inputs, seven channels per pixel of an H x W design region (pixel m at row
+ * m / W, column m % W), from the current state at the first frequency:
+ *   0 design bit;  1, 2 Re, Im E[m] / max|E|;  3, 4 Re, Im R'[m] / max|R'|;
+ *   5 |G_mm| / max|G_mm|;  6 asinh(df_lin[m] / (1e-3 f)), where df_lin is
+ *   the flip's objective change with the denominator of eq. lru_eobj_rs set
+ *   to 1 (summed over frequencies).
+ * Network: four 3x3 convolutions, 7 -> 32 -> 32 -> 32 -> 1 channels, zero
+ * padding, ReLU between layers; BF16 operands on the matrix cores with FP32
+ * accumulation, FP32 master weights, mean Huber loss (delta 1), Adam
+ * (0.9, 0.999, 1e-8). */
+typedef struct pngf_model pngf_model;
+
+/* He-normal initial weights from seed, zero biases; max_batch images per
+ * call.  PNGF_EINVAL unless 1 <= H*W <= 8192 and max_batch >= 1. */
+int pngf_model_create(int32_t H, int32_t W, int32_t max_batch, uint64_t seed,
+                      pngf_model **out);
+/* Message of the last failure of m (of pngf_model_create if m is NULL). */
+const char *pngf_model_last_error(const pngf_model *m);
+int pngf_model_num_params(pngf_model *m, int32_t *n);
+/* Device workspace needed by pngf_model_bind. */
+int pngf_model_workspace_bytes(pngf_model *m, size_t *bytes);
+/* Bind a caller-owned, 256-byte aligned device workspace and a HIP stream;
+ * uploads the current parameters.  The workspace must outlive m. */
+int pngf_model_bind(pngf_model *m, void *dev_ws, size_t bytes, void *hip_stream);
+
+/* Flat FP32 parameters [W1, b1, ..., W4, b4], W as [out][in][3][3]; n must
+ * equal pngf_model_num_params. */
+int pngf_model_get_params(pngf_model *m, float *params, int32_t n);
+int pngf_model_set_params(pngf_model *m, const float *params, int32_t n);
+
+/* Host arrays: X[N][7][H][W] in, Y[N][1][H][W] out; 1 <= N <= max_batch. */
+int pngf_model_forward(pngf_model *m, const float *X, int32_t N, float *Y);
+
+/* One step on a batch: forward, mean Huber loss against T[N][1][H][W],
+ * backward; grads (optional, num_params floats) receive the gradient; an
+ * Adam update with learning rate lr if lr > 0.  *loss = mean loss before the
+ * update. */
+int pngf_model_train_step(pngf_model *m, const float *X, const float *T, int32_t N, float lr,
+                          double *loss, float *grads);
+int pngf_model_destroy(pngf_model *m);
+
+/* The seven input channels of the current state of h (X[7][n_d], host
+ * float), for logging training pairs.  PNGF_EINVAL unless the design region
+ * is a full rectangle. */
+int pngf_features(pngf_handle *h, float *X);
+
+/* Ranked search on an FP64 handle.  Per state every pixel is ranked, by the
+ * network m (which must be bound to h's stream and sized to the design) or,
+ * with m NULL, by channel 6 above (the first-order change); the ranking is
+ * scored exactly k pixels at a time, best first, and the best improving
+ * pixel (f' - f > eta f) of the first chunk that has one is accepted (a
+ * Sherman-Morrison update, eq. lru_woodbury with M = 1).  Converged when the
+ * whole ranking holds no improving pixel; stops after max_accepts accepts.
+ * accepted / f_trace (optional, max_accepts entries) receive the pixels and
+ * objectives; res->attempts counts the exact evaluations performed,
+ * res->sweeps the chunks scored beyond the first of each state.  Needs
+ * n_d <= 8192 and 1 <= k <= n_d. */
+int pngf_learned_dbs_run(pngf_handle *h, pngf_model *m, int32_t k, int32_t max_accepts,
+                         int32_t *accepted, double *f_trace, pngf_dbs_result *res);
+
 #ifdef __cplusplus
 }
 #endif

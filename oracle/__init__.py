@@ -27,9 +27,9 @@ closed forms, exact discrete identities, reciprocity and brute force
 """
 from .fdfd import (pml_profile, stretch, assemble, rhs, solve, Solver,
                    objective, field)
-from .green import green_dd, green_od, background, pngf_state
+from .green import green_dd, green_od, output_row, background, pngf_state
 from .dbs import dbs, score_all, DBSResult
 
 __all__ = ["pml_profile", "stretch", "assemble", "rhs", "solve", "Solver",
-           "objective", "field", "green_dd", "green_od", "background", "pngf_state", "dbs",
+           "objective", "field", "green_dd", "green_od", "output_row", "background", "pngf_state", "dbs",
            "score_all", "DBSResult"]

@@ -74,6 +74,26 @@ def background(prob, fi, solver=None):
     return Eb, Eb[idx].copy(), complex(prob.w[0] @ Eb)
 
 
+def output_row(prob, bits, fi):
+    """R'_D = -w^T L(eps)^-1[:, D] for the current design (1-D, N_d) by a
+    transposed solve of the full operator of that design.
+
+    It is the output row of the PNGF state: a small change d of the
+    permittivity of pixel m changes x by k0^2 d E[m] R'[m] to first order
+    (adjoint sensitivity; pinned by central finite differences in
+    tests/test_oracle_green.py::test_output_row_is_adjoint_sensitivity), and
+    for the background design it equals G_OD."""
+    eps = total_eps(prob, bits)
+    L, scale = assemble(prob.nx, prob.ny, prob.npml, prob.h, eps, prob.k0[fi])
+    S = Solver(L, scale)
+    idx = prob.design_indices()
+    w = prob.w[0].astype(np.complex128)
+    y = S.lu.solve(w, trans="T")
+    r = w - S.A.T @ y
+    y = y + S.lu.solve(r, trans="T")
+    return -(y * S.scale)[idx]
+
+
 def pngf_state(prob, bits, fi):
     """(E_D, x) for design ``bits`` at frequency fi, from one full solve."""
     from .fdfd import field

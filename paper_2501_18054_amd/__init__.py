@@ -1,8 +1,8 @@
 """MI355X-native per-iteration hot path of the Precomputed Numerical Green
 Function (PNGF) method: a C-ABI library (libpngf.so, HIP for gfx950) and its
 thin ctypes binding."""
-from .binding import (Handle, Batch, PngfError, default_options, lib, PNGF_FP64_PLAIN,
+from .binding import (Handle, Batch, Model, PngfError, default_options, lib, PNGF_FP64_PLAIN,
                       PNGF_MIXED, PNGF_FLAG_TIMING, EXPORTS, LIB_PATH)
 
-__all__ = ["Handle", "Batch", "PngfError", "default_options", "lib", "PNGF_FP64_PLAIN",
+__all__ = ["Handle", "Batch", "Model", "PngfError", "default_options", "lib", "PNGF_FP64_PLAIN",
            "PNGF_MIXED", "PNGF_FLAG_TIMING", "EXPORTS", "LIB_PATH"]

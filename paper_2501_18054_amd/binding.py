@@ -91,6 +91,21 @@ EXPORTS = {
                            C.POINTER(C.c_int32)], C.c_int),
     "pngf_batch_ms_per_step": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "pngf_batch_destroy": ([C.c_void_p], C.c_int),
+    "pngf_model_create": ([C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)],
+                          C.c_int),
+    "pngf_model_last_error": ([C.c_void_p], C.c_char_p),
+    "pngf_model_num_params": ([C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
+    "pngf_model_workspace_bytes": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
+    "pngf_model_bind": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "pngf_model_get_params": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
+    "pngf_model_set_params": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
+    "pngf_model_forward": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "pngf_model_train_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                               C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "pngf_model_destroy": ([C.c_void_p], C.c_int),
+    "pngf_features": ([C.c_void_p, C.c_void_p], C.c_int),
+    "pngf_learned_dbs_run": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                              C.c_void_p, C.POINTER(DbsResult)], C.c_int),
 }
 
 
@@ -259,6 +274,27 @@ class Handle:
                     n_verified=int(res.n_verified), f_initial=res.f_initial,
                     f_final=res.f_final)
 
+    def features(self):
+        """CNN inputs of the current state, float32 [7, n_d]."""
+        X = np.empty((Model.CHANNELS[0], self.n_d), np.float32)
+        self._check(lib().pngf_features(self._h, _ptr(X)))
+        return X
+
+    def learned_dbs_run(self, model, k=64, max_accepts=None):
+        """Ranked search (see pngf_learned_dbs_run): model None ranks by the
+        first-order change; a Model must share this handle's stream."""
+        cap = int(max_accepts if max_accepts is not None else self.opts.max_accepts)
+        acc = np.empty(max(cap, 1), np.int32)
+        ftr = np.empty(max(cap, 1), np.float64)
+        res = DbsResult()
+        mp = model._m if model is not None else None
+        self._check(lib().pngf_learned_dbs_run(self._h, mp, int(k), cap, _ptr(acc),
+                                               _ptr(ftr), C.byref(res)))
+        n = res.n_accepted
+        return dict(accepted=acc[:n].copy(), f_trace=ftr[:n].copy(), n_accepted=n,
+                    extra_chunks=res.sweeps, converged=bool(res.converged),
+                    attempts=int(res.attempts), f_initial=res.f_initial, f_final=res.f_final)
+
     def kernel_times(self, name):
         t = C.c_double()
         n = C.c_int64()
@@ -333,6 +369,98 @@ class Batch:
         if getattr(self, "_b", None):
             lib().pngf_batch_destroy(self._b)
             self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Model:
+    """Flip-proposal CNN of libpngf (see the learned section of pngf.h).
+
+    Parameters are flat float32 [W1, b1, ..., W4, b4], W as [out][in][3][3].
+    """
+
+    CHANNELS = (7, 32, 32, 32, 1)
+
+    def __init__(self, H, W, max_batch=64, seed=0, device="cuda:0", stream=None):
+        import torch
+        L = lib()
+        m = C.c_void_p()
+        rc = L.pngf_model_create(int(H), int(W), int(max_batch), int(seed), C.byref(m))
+        if rc != 0:
+            raise PngfError(rc, L.pngf_model_last_error(None).decode())
+        self._m = m
+        self.H, self.W, self.max_batch = int(H), int(W), int(max_batch)
+        n = C.c_int32()
+        self._check(L.pngf_model_num_params(m, C.byref(n)))
+        self.num_params = n.value
+        nb = C.c_size_t()
+        self._check(L.pngf_model_workspace_bytes(m, C.byref(nb)))
+        self._ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=device)
+        aligned = (self._ws.data_ptr() + 255) & ~255
+        if stream is None:
+            stream = torch.cuda.current_stream(torch.device(device))
+        self._stream = stream
+        self._check(L.pngf_model_bind(m, C.c_void_p(aligned), nb.value,
+                                      C.c_void_p(stream.cuda_stream)))
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PngfError(rc, lib().pngf_model_last_error(self._m).decode())
+
+    def shapes(self):
+        ch = self.CHANNELS
+        out = []
+        for cin, cout in zip(ch[:-1], ch[1:]):
+            out += [(cout, cin, 3, 3), (cout,)]
+        return out
+
+    def unflatten(self, flat):
+        out, o = [], 0
+        for s in self.shapes():
+            n = int(np.prod(s))
+            out.append(np.asarray(flat[o:o + n]).reshape(s))
+            o += n
+        return out
+
+    def get_params(self):
+        p = np.empty(self.num_params, np.float32)
+        self._check(lib().pngf_model_get_params(self._m, _ptr(p), self.num_params))
+        return p
+
+    def set_params(self, flat):
+        p = np.ascontiguousarray(flat, dtype=np.float32)
+        assert p.shape == (self.num_params,)
+        self._check(lib().pngf_model_set_params(self._m, _ptr(p), self.num_params))
+
+    def forward(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        N = X.shape[0]
+        assert X.shape == (N, self.CHANNELS[0], self.H, self.W)
+        Y = np.empty((N, 1, self.H, self.W), np.float32)
+        self._check(lib().pngf_model_forward(self._m, _ptr(X), N, _ptr(Y)))
+        return Y
+
+    def train_step(self, X, T, lr=1e-3, want_grads=False):
+        """One forward/backward (+ Adam if lr > 0); returns (loss, grads)."""
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        N = X.shape[0]
+        assert X.shape == (N, self.CHANNELS[0], self.H, self.W)
+        assert T.shape == (N, 1, self.H, self.W)
+        g = np.empty(self.num_params, np.float32) if want_grads else None
+        loss = C.c_double()
+        self._check(lib().pngf_model_train_step(self._m, _ptr(X), _ptr(T), N, float(lr),
+                                                C.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def close(self):
+        if getattr(self, "_m", None):
+            lib().pngf_model_destroy(self._m)
+            self._m = None
 
     def __del__(self):
         try:

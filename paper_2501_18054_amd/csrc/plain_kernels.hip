@@ -224,6 +224,73 @@ __global__ __launch_bounds__(kRowThreads) void k_accept_rescore(ProbDev P) {
   }
 }
 
+// Accept only (no rescore): row i of C^-1 += alpha p_i q with
+// p_i = C^-1[i,:] . g_m, and E, R' updated; 2 N_d^2 x 16 B per accept.  Used
+// by the learned search, which scores only the proposed candidates exactly.
+template <int NPL>
+__global__ __launch_bounds__(kRowThreads) void k_accept_only(ProbDev P) {
+  __shared__ double red[2 * (kRowThreads / 64)];
+  const DbsState* st = P.st;
+  const int m = st->m;
+  if (m < 0) return;
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int f = 0; f < P.nfreq; ++f) {
+    z64* C = P.Cinv[f] + size_t(i) * P.ld;
+    const z64* gm = P.G[f] + size_t(m) * P.ld;
+    const z64* q = P.q[f];
+    z64 row[NPL];
+    z64 acc{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int j = tid + t * kRowThreads;
+      if (j < P.nd) {
+        row[t] = C[j];
+        acc = zfma(row[t], gm[j], acc);
+      }
+    }
+    const z64 p = block_zsum(acc, red);
+    const z64 ap = zmul(st->alpha[f], p);
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int j = tid + t * kRowThreads;
+      if (j < P.nd) C[j] = zfma(ap, q[j], row[t]);
+    }
+    if (tid == 0) {
+      P.E[f][i] = zadd(P.E[f][i], zmul(ap, st->Em[f]));
+      P.Rp[f][i] = zadd(P.Rp[f][i], zmul(ap, st->Rpm[f]));
+    }
+  }
+}
+
+// Best improving candidate among df[0..n): out = cand[r] (or r) maximizing
+// df with df > eta f, or -1.  One workgroup.
+__global__ __launch_bounds__(1024) void k_pick_best(const double* df, const int32_t* cand, int n,
+                                                   const DbsState* st, int32_t* out) {
+  __shared__ double bv[16];
+  __shared__ int bi[16];
+  const double thr = st->eta * st->f;
+  double best = -INFINITY;
+  int idx = -1;
+  for (int r = threadIdx.x; r < n; r += 1024)
+    if (df[r] > thr && df[r] > best) { best = df[r]; idx = r; }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(idx, o, 64);
+    if (ob > best || (ob == best && oi >= 0 && (idx < 0 || oi < idx))) { best = ob; idx = oi; }
+  }
+  if ((threadIdx.x & 63) == 0) { bv[threadIdx.x >> 6] = best; bi[threadIdx.x >> 6] = idx; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = bv[0];
+    int id = bi[0];
+    for (int w = 1; w < 16; ++w)
+      if (bv[w] > b || (bv[w] == b && bi[w] >= 0 && (id < 0 || bi[w] < id))) { b = bv[w]; id = bi[w]; }
+    out[0] = id < 0 ? -1 : (cand ? cand[id] : id);
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 #define PNGF_NPL_SWITCH(npl, CALL) \
   switch (npl) {                   \
@@ -254,6 +321,19 @@ hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s) {
 #define L_(N) hipLaunchKernelGGL(k_accept_rescore<N>, dim3(P.nd), dim3(kRowThreads), 0, s, P)
   PNGF_NPL_SWITCH(npl, L_)
 #undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_accept_only(const ProbDev& P, int npl, hipStream_t s) {
+#define L_(N) hipLaunchKernelGGL(k_accept_only<N>, dim3(P.nd), dim3(kRowThreads), 0, s, P)
+  PNGF_NPL_SWITCH(npl, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_pick_best(const double* df, const int32_t* cand, int n, const DbsState* st,
+                            int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pick_best, dim3(1), dim3(1024), 0, s, df, cand, n, st, out);
   return hipGetLastError();
 }
 

@@ -11,6 +11,10 @@
 #include "dev_state.h"
 #include "pngf_internal.h"
 
+struct pngf_model;
+
+constexpr int kFeatChannels = 7;
+
 namespace pngf {
 hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int ncand,
                              uint32_t* keyp, hipStream_t s);
@@ -19,6 +23,14 @@ hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s)
 hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
                              int grid, int npl, int mixed, int step, hipStream_t s);
+hipError_t launch_accept_only(const ProbDev& P, int npl, hipStream_t s);
+hipError_t launch_pick_best(const double* df, const int32_t* cand, int n, const DbsState* st,
+                            int32_t* out, hipStream_t s);
+hipError_t model_score_state(pngf_model* m, const ProbDev& P, float** scores);
+hipError_t launch_rank(const float* s, int n, int32_t* out, hipStream_t st);
+hipError_t launch_features(const ProbDev& P, int H, int W, float* X, hipStream_t s);
+int model_hw(pngf_model* m, int* H, int* W);
+hipStream_t model_stream(pngf_model* m);
 hipError_t launch_select_prep(const ProbDev& P, int forced, hipStream_t s);
 hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const int32_t* sidx,
@@ -65,7 +77,7 @@ struct Layout {
   size_t off_Pn, off_sidx, off_zidx, off_pos;
   size_t off_CB[pngf::kMaxFreq], off_EB[pngf::kMaxFreq], off_RpB[pngf::kMaxFreq],
       off_tauB[pngf::kMaxFreq];
-  size_t off_bitsB, off_stateB, off_keys, off_pm;
+  size_t off_bitsB, off_stateB, off_keys, off_pm, off_best, off_feat;
   size_t off_S, off_B1, off_Pb, off_ts, off_B11, off_piv, off_invp, off_used, off_status, off_u, off_r;
   size_t total;
 };
@@ -137,6 +149,8 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
   L.off_stateB = take(sizeof(pngf::DbsState));
   L.off_keys = take(6 * sizeof(uint32_t));
   L.off_pm = take(size_t(pngf::kPanelCap) * sizeof(int32_t));
+  L.off_best = take(4 * sizeof(int32_t));
+  L.off_feat = take(size_t(kFeatChannels) * nd * sizeof(float));
   if (o->precision == PNGF_MIXED) {
     const size_t mat32 = size_t(nd) * ld * sizeof(z32);
     for (int f = 0; f < F; ++f) {
@@ -860,6 +874,145 @@ int pngf_destroy(pngf_handle* h) {
     hipEventDestroy(h->ev_pool[k + 1]);
   }
   delete h;
+  return PNGF_OK;
+}
+
+}  // extern "C"
+
+
+// ------------------------------------------------------------------ learned
+namespace {
+
+// Design region as an H x W rectangle in pixel order (needed by the CNN).
+bool design_grid(pngf_handle* h, int* H, int* W) {
+  const auto& dn = h->pc.design_nodes;
+  const int nx = h->pc.grid.nx;
+  int i0 = 1 << 30, i1 = -1, j0 = 1 << 30, j1 = -1;
+  for (int64_t n : dn) {
+    const int i = int(n % nx), j = int(n / nx);
+    i0 = std::min(i0, i); i1 = std::max(i1, i);
+    j0 = std::min(j0, j); j1 = std::max(j1, j);
+  }
+  *W = i1 - i0 + 1;
+  *H = j1 - j0 + 1;
+  return int64_t(*W) * *H == int64_t(dn.size());
+}
+
+}  // namespace
+
+extern "C" {
+
+int pngf_features(pngf_handle* h, float* X) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  if (!X) return fail(h, PNGF_EINVAL, "null output");
+  int H = 0, W = 0;
+  if (!design_grid(h, &H, &W)) return fail(h, PNGF_EINVAL, "design region is not a rectangle");
+  float* d = at<float>(h, h->lay.off_feat);
+  HIPCHK(h, pngf::launch_features(h->P, H, W, d, h->stream));
+  HIPCHK(h, hipMemcpyAsync(X, d, size_t(kFeatChannels) * h->pc.n_d * sizeof(float),
+                           hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PNGF_OK;
+}
+
+int pngf_learned_dbs_run(pngf_handle* h, pngf_model* m, int32_t k, int32_t max_accepts,
+                         int32_t* accepted, double* f_trace, pngf_dbs_result* res) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  if (h->opt.precision != PNGF_FP64_PLAIN)
+    return fail(h, PNGF_EINVAL, "the learned search runs on an FP64 handle");
+  const int nd = h->pc.n_d;
+  int H = 0, W = 0;
+  if (!design_grid(h, &H, &W)) return fail(h, PNGF_EINVAL, "design region is not a rectangle");
+  if (nd > 8192) return fail(h, PNGF_EINVAL, "the ranking holds at most 8192 pixels");
+  if (m) {
+    int mh = 0, mw = 0;
+    if (pngf::model_hw(m, &mh, &mw) != PNGF_OK) return fail(h, PNGF_ESTATE, "model is not bound");
+    if (mh != H || mw != W) return fail(h, PNGF_EINVAL, "model image size differs from the design");
+    if (pngf::model_stream(m) != h->stream)
+      return fail(h, PNGF_EINVAL, "model and handle must share the stream");
+  }
+  if (k < 1 || k > nd) return fail(h, PNGF_EINVAL, "k must be in [1, n_d]");
+  if (max_accepts < 0) return fail(h, PNGF_EINVAL, "max_accepts must be >= 0");
+  pngf::DbsState s;
+  st = read_state(h, &s);
+  if (st) return st;
+  const double f0 = s.f;
+  s.done = 0;
+  s.n_sweeps = 0;
+  s.m = -1;
+  s.eta = h->opt.eta;
+  st = write_state(h, &s);
+  if (st) return st;
+  int32_t* d_rank = at<int32_t>(h, h->lay.off_cand);
+  int32_t* d_best = at<int32_t>(h, h->lay.off_best);
+  float* d_feat = at<float>(h, h->lay.off_feat);
+  int64_t evals = 0, extra_chunks = 0;
+  int n_acc = 0;
+  bool converged = false;
+  for (int k0 = 0; k0 < KID_N; ++k0) { h->ktime_ms[k0] = 0.0; h->klaunch[k0] = 0; }
+  while (n_acc < max_accepts) {
+    {
+      // rank every pixel: by the network, or by the first-order change
+      Timer t(h, KID_OTHER);
+      const float* scores = nullptr;
+      if (m) {
+        float* y = nullptr;
+        HIPCHK(h, pngf::model_score_state(m, h->P, &y));
+        scores = y;
+      } else {
+        HIPCHK(h, pngf::launch_features(h->P, H, W, d_feat, h->stream));
+        scores = d_feat + size_t(kFeatChannels - 1) * nd;
+      }
+      HIPCHK(h, pngf::launch_rank(scores, nd, d_rank, h->stream));
+      t.end();
+    }
+    // exact scores of the ranking, k at a time, until a chunk improves
+    int32_t best = -1;
+    for (int c0 = 0; c0 < nd && best < 0; c0 += k) {
+      const int n = std::min(k, nd - c0);
+      {
+        Timer t(h, KID_SCORE);
+        HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, d_rank + c0, n, nullptr, h->stream));
+        HIPCHK(h, pngf::launch_pick_best(h->P.df, d_rank + c0, n, h->P.st, d_best, h->stream));
+        t.end();
+      }
+      HIPCHK(h, hipMemcpyAsync(&best, d_best, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      evals += n;
+      if (c0 > 0) extra_chunks += 1;
+    }
+    if (best < 0) { converged = true; break; }
+    {
+      Timer t(h, KID_ACCEPT);
+      HIPCHK(h, pngf::launch_select_prep(h->P, best, h->stream));
+      HIPCHK(h, pngf::launch_accept_only(h->P, h->npl, h->stream));
+      t.end();
+    }
+    if (accepted) accepted[n_acc] = best;
+    if (f_trace) {
+      HIPCHK(h, hipMemcpyAsync(&f_trace[n_acc], &h->P.st->f, sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+    }
+    h->bits[best] ^= 1;
+    n_acc += 1;
+  }
+  pngf::DbsState fin;
+  st = read_state(h, &fin);
+  if (st) return st;
+  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  if (!std::isfinite(fin.f)) return fail(h, PNGF_ENUMERIC, "objective is not finite");
+  if (res) {
+    res->n_accepted = n_acc;
+    res->sweeps = int32_t(extra_chunks);
+    res->converged = converged ? 1 : 0;
+    res->n_refresh = 0;
+    res->attempts = evals;
+    res->n_verified = 0;
+    res->f_initial = f0;
+    res->f_final = fin.f;
+  }
   return PNGF_OK;
 }
 

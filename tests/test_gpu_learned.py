@@ -1,0 +1,97 @@
+"""Learned flip proposal, A/B on a held-out problem of the 256x256 / 40x40
+family (N_d = 1600): the network is trained on the GPU from (state, exact
+objective change) pairs logged on eight training problems, then the ranked
+search runs on an unseen seed with and without it.
+
+What is asserted (the gain and its price):
+  * every accepted flip is an exact improvement: the trace is re-checked at
+    every state by the FP64 plain path, and the final objective by a full
+    sparse re-solve (oracle);
+  * the trained ranking needs fewer exact evaluations than DBS run to
+    convergence (well under 60 %), and than the same ranked search driven by
+    an untrained network or by the first-order change (under half of each),
+    while its final objective stays within 5 % of DBS's.
+Wall time is reported, not asserted: on the GPU, DBS scores every candidate
+in the same pass as the accept, so fewer evaluations do not mean less time.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+import paper_2501_18054_amd as P
+from paper_2501_18054_amd import learned
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+N_TRAIN = 8
+EVAL_SEED = workloads.CONFIG3_EVAL_SEEDS[0]
+K = 4
+
+
+@pytest.fixture(scope="module")
+def trained():
+    X, T = [], []
+    for s in workloads.CONFIG3_TRAIN_SEEDS[:N_TRAIN]:
+        say(f"log training pairs, seed {s}")
+        p = workloads.config3_problem(s)
+        h = P.Handle(p).bind(P.default_options(max_accepts=8192, max_sweeps=8))
+        x, t = learned.collect(h, p, every=4, greedy=True)
+        X += x
+        T += t
+        h.close()
+    say(f"train on {len(X)} states")
+    m = P.Model(40, 40, max_batch=32, seed=0)
+    hist = learned.train(m, X, T, epochs=40, batch=32, lr=1e-3)
+    assert hist[-1] < 0.8 * hist[0]
+    return m
+
+
+def _replay_exact(h, p, r):
+    """Each accepted flip improved f by more than eta f at its state (FP64
+    plain path scores), and the trace is the objective after each flip."""
+    h.set_design(p.init_bits)
+    f, _ = h.evaluate()
+    for j, i in enumerate(r["accepted"]):
+        fn = h.score_flips([i])[0]
+        assert fn - f > 1e-9 * f
+        assert abs(fn - r["f_trace"][j]) <= 1e-12 * fn
+        h.accept_flips([i])
+        f = fn
+    return f
+
+
+def test_learned_ab_on_held_out_seed(trained):
+    p = workloads.config3_problem(EVAL_SEED, n_sweeps=30)
+    h = P.Handle(p).bind(P.default_options(max_accepts=8192, max_sweeps=30))
+    say(f"DBS to convergence, seed {EVAL_SEED}")
+    h.set_design(p.init_bits)
+    dbs = h.dbs_run(p.perms)
+    assert dbs["converged"]
+    runs = {}
+    for name, model in (("trained", trained), ("first_order", None),
+                        ("untrained", P.Model(40, 40, max_batch=1, seed=99))):
+        say(f"ranked search ({name}), k = {K}")
+        h.set_design(p.init_bits)
+        runs[name] = h.learned_dbs_run(model, k=K, max_accepts=8192)
+        assert runs[name]["converged"]
+    lr = runs["trained"]
+    print(f"[learned A/B] DBS: {dbs['attempts']} evals, f {dbs['f_final']:.6g}; "
+          + "; ".join(f"{n}: {r['attempts']} evals, f {r['f_final']:.6g}"
+                      for n, r in runs.items()), flush=True)
+    say("replay the trained run's accepts")
+    f_end = _replay_exact(h, p, lr)
+    bits = p.init_bits.copy()
+    for i in lr["accepted"]:
+        bits[i] ^= 1
+    xs = [oracle.pngf_state(p, bits, fi)[1] for fi in range(p.nfreq)]
+    fo = oracle.objective(p, xs)
+    assert abs(lr["f_final"] - fo) <= 1e-10 * fo
+    assert abs(f_end - fo) <= 1e-10 * fo
+    # the gain, and what it costs in objective
+    assert lr["attempts"] < 0.6 * dbs["attempts"]
+    assert lr["attempts"] < 0.5 * runs["untrained"]["attempts"]
+    assert lr["attempts"] < 0.5 * runs["first_order"]["attempts"]
+    assert lr["f_final"] > 0.95 * dbs["f_final"]
+    h.close()

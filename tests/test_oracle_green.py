@@ -38,6 +38,33 @@ def test_reciprocity():
     assert np.max(np.abs(God[0] - adj)) < 1e-12 * np.max(np.abs(adj))
 
 
+def test_output_row_is_adjoint_sensitivity():
+    """dx/d eps_m = k0^2 E[m] R'[m]: central finite differences of full
+    solves in which only pixel m's permittivity moves by +-h (first-order
+    perturbation of L E = i k0 J, whose eps term is +k0^2 eps)."""
+    p = workloads.config0()
+    rng = np.random.default_rng(3)
+    bits = (rng.random(p.n_d) < 0.4).astype(np.uint8)
+    R = oracle.output_row(p, bits, 0)
+    E, _ = oracle.pngf_state(p, bits, 0)
+    idx = p.design_indices()
+    k0 = p.k0[0]
+    hstep = 1e-4
+    for m in (0, 37, 99):
+        xs = []
+        for sgn in (1.0, -1.0):
+            eps = fd.total_eps(p, bits).ravel().copy()
+            eps[idx[m]] += sgn * hstep
+            Ef = fd.solve(p.nx, p.ny, p.npml, p.h, eps.reshape(p.ny, p.nx), k0, p.src[0])
+            xs.append(complex(p.w[0] @ Ef))
+        fdx = (xs[0] - xs[1]) / (2 * hstep)
+        pred = k0 ** 2 * E[m] * R[m]
+        assert abs(fdx - pred) < 1e-6 * abs(pred)
+    # background design: the output row is G_OD
+    R0 = oracle.output_row(p, np.zeros(p.n_d, np.uint8), 0)
+    assert np.max(np.abs(R0 - oracle.green_od(p, 0)[0])) < 1e-12 * np.max(np.abs(R0))
+
+
 def test_single_pixel_closed_form():
     """One-pixel region: E = b / (1 - k0^2 deps G11), x = x_b + k0^2 G_O1 deps E."""
     p = workloads.tiny(seed=5, n=20, npml=4, side=1)
