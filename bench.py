@@ -77,7 +77,7 @@ def run_form(P, h, prob, opts, steps, warmup, name):
     dt = time.perf_counter() - t0
     log(f"{name}: {steps} timed runs in {dt:.3f} s")
     kt = {k: h.kernel_times(k) for k in ("score", "select", "accept", "lu", "other", "fold",
-                                         "mixed_q")}
+                                         "mixed_q", "wood")}
     return results, dt, kt
 
 

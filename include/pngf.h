@@ -87,8 +87,11 @@ typedef struct pngf_problem {
 
 typedef struct pngf_options {
   int32_t precision;    /* PNGF_FP64_PLAIN or PNGF_MIXED                     */
-  int32_t k_refresh;    /* MIXED: FP64 re-inversion every k_refresh accepts; */
-                        /* 0 = only when the FP64 residual of E drifts       */
+  int32_t k_refresh;    /* MIXED: FP64 refresh every k_refresh accepts;      */
+                        /* 0 = only when the FP64 residual of E drifts.  A   */
+                        /* refresh is a block-Woodbury update of the FP64    */
+                        /* inverse of the last refresh (exact to rounding),  */
+                        /* or a full re-inversion if > 64 pixels changed     */
   int32_t k_fold;       /* MIXED: fold the deferred panel into C0^-1 once it */
                         /* holds k_fold terms (0 = only when it is full)     */
   int32_t max_accepts;  /* capacity of the on-device accept log (>= 1)       */
@@ -106,7 +109,7 @@ typedef struct pngf_dbs_result {
   int32_t n_accepted;   /* accepted flips                                    */
   int32_t sweeps;       /* sweeps started                                    */
   int32_t converged;    /* 1 if a whole sweep had no improving flip          */
-  int32_t n_refresh;    /* FP64 re-inversions performed (MIXED)              */
+  int32_t n_refresh;    /* FP64 refreshes performed (MIXED)                  */
   int64_t attempts;     /* attempted flips (visited positions)               */
   int64_t n_verified;   /* MIXED: candidates re-checked in FP64              */
   double f_initial;     /* objective of the initial design                   */
@@ -186,7 +189,7 @@ int pngf_dbs_run(pngf_handle *h, const int32_t *perms, int32_t n_sweeps,
  * PNGF_FLAG_TIMING) and launch count of the kernels of the last pngf_dbs_run,
  * per kernel id: 0 full scoring pass, 1 select, 2 accept (+ rescore),
  * 3 FP64 inversion, 4 other re-inversion work (GEMVs, outputs), 5 panel fold,
- * 6 mixed-path q row. */
+ * 6 mixed-path q row, 7 FP64 block-Woodbury refresh (mixed path). */
 int pngf_kernel_times(pngf_handle *h, int32_t kernel_id, double *total_ms,
                       int64_t *launches);
 

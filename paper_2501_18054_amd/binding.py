@@ -19,7 +19,7 @@ PNGF_MIXED = 1
 PNGF_FLAG_TIMING = 1
 
 KERNEL_IDS = {"score": 0, "select": 1, "accept": 2, "lu": 3, "other": 4, "fold": 5,
-              "mixed_q": 6}
+              "mixed_q": 6, "wood": 7}
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ESINGULAR", -3: "ENUMERIC", -4: "EDEVICE",
            -5: "ESTATE", -6: "ENOMEM"}

@@ -1,0 +1,319 @@
+// Complex FP64 GEMM on the gfx950 matrix cores, and the small kernels of the
+// FP64 block-Woodbury refresh of C^-1.
+//
+// GEMM: C = beta C + alpha A B with A (M x K, row-major) and B either K x N
+// row-major or given by rows of R (B[k][n] = R[rb[n]][k], the transposed
+// product of the reciprocity-symmetric operands used here).  A complex
+// product is four real v_mfma_f64_16x16x4f64 products into separate real and
+// imaginary accumulators.  Operand layouts of the 16x16x4 FP64 instruction:
+// lane l holds A[l%16][l/16] and B[l/16][l%16]; accumulator register r holds
+// D[l/16 + 4r][l%16] (measured: unlike the FP32 16x16x4 form, rows interleave).  Four waves per workgroup in a 2 x 2 arrangement, each
+// owning WM x WN 16x16 blocks; K is staged through LDS 16 at a time.  A
+// skinny product splits K over gridDim.z into a workspace reduced in a fixed
+// order (deterministic).
+//
+// Block Woodbury (eq. lru_woodbury with M = |F|): after the pixels F flip,
+// C_new = C_ref - U V^T with U = k0^2 G[:,F] diag(delta_F), V = I[:,F], so
+//     C_new^-1 = C_ref^-1 + P Cap^-1 Q,   P = C_ref^-1 U,  Q = C_ref^-1[F,:],
+//     Cap = I - Q U = I - P[F,:].
+#include <algorithm>
+
+#include "dev_state.h"
+
+namespace pngf {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGemmBK = 16;
+
+template <int WM, int WN, bool TRANSB>
+__global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A, int lda,
+                                               const z64* B, int ldb, const int32_t* rb, z64* C,
+                                               int ldc, z64 alpha, z64 beta, int kchunk,
+                                               z64* work) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  __shared__ double sAr[BM][kGemmBK + 1], sAi[BM][kGemmBK + 1];
+  __shared__ double sBr[kGemmBK][BN + 1], sBi[kGemmBK][BN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  d4 accr[WM][WN], acci[WM][WN];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b) {
+      accr[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      acci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int k0 = kbeg; k0 < kend; k0 += kGemmBK) {
+    for (int e = tid; e < BM * kGemmBK; e += 256) {
+      const int r = e >> 4, c = e & 15;
+      const int gr = m0 + r, gc = k0 + c;
+      z64 v{0.0, 0.0};
+      if (gr < M && gc < kend) v = A[size_t(gr) * lda + gc];
+      sAr[r][c] = v.re;
+      sAi[r][c] = v.im;
+    }
+    if (TRANSB) {
+      for (int e = tid; e < BN * kGemmBK; e += 256) {
+        const int n = e >> 4, c = e & 15;
+        const int gn = n0 + n, gc = k0 + c;
+        z64 v{0.0, 0.0};
+        if (gn < N && gc < kend) v = B[size_t(rb ? rb[gn] : gn) * ldb + gc];
+        sBr[c][n] = v.re;
+        sBi[c][n] = v.im;
+      }
+    } else {
+      for (int e = tid; e < BN * kGemmBK; e += 256) {
+        const int r = e / BN, n = e % BN;
+        const int gr = k0 + r, gn = n0 + n;
+        z64 v{0.0, 0.0};
+        if (gr < kend && gn < N) v = B[size_t(gr) * ldb + gn];
+        sBr[r][n] = v.re;
+        sBi[r][n] = v.im;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGemmBK; kk += 4) {
+      double ar[WM], ai[WM], br[WN], bi[WN];
+#pragma unroll
+      for (int a = 0; a < WM; ++a) {
+        const int r = wm * 16 * WM + a * 16 + i16;
+        ar[a] = sAr[r][kk + k4];
+        ai[a] = sAi[r][kk + k4];
+      }
+#pragma unroll
+      for (int b = 0; b < WN; ++b) {
+        const int n = wn * 16 * WN + b * 16 + i16;
+        br[b] = sBr[kk + k4][n];
+        bi[b] = sBi[kk + k4][n];
+      }
+#pragma unroll
+      for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          accr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], accr[a][b], 0, 0, 0);
+          accr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], bi[b], accr[a][b], 0, 0, 0);
+          acci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], acci[a][b], 0, 0, 0);
+          acci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], acci[a][b], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  const bool beta0 = beta.re == 0.0 && beta.im == 0.0;
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 16 * WM + a * 16 + k4 + 4 * r;
+        const int col = n0 + wn * 16 * WN + b * 16 + i16;
+        if (row >= M || col >= N) continue;
+        const z64 v{accr[a][b][r], acci[a][b][r]};
+        if (work) {
+          work[(size_t(blockIdx.z) * M + row) * N + col] = v;
+        } else {
+          z64* c = C + size_t(row) * ldc + col;
+          const z64 av = zmul(alpha, v);
+          *c = beta0 ? av : zfma(beta, *c, av);
+        }
+      }
+}
+
+// C = beta C + alpha sum_z work[z] (fixed summation order).
+__global__ __launch_bounds__(256) void k_zgemm_reduce(int M, int N, int nz, const z64* work,
+                                                      z64* C, int ldc, z64 alpha, z64 beta) {
+  const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= size_t(M) * N) return;
+  const int row = int(e / N), col = int(e % N);
+  z64 s{0.0, 0.0};
+  for (int z = 0; z < nz; ++z) s = zadd(s, work[size_t(z) * M * N + e]);
+  z64* c = C + size_t(row) * ldc + col;
+  const z64 av = zmul(alpha, s);
+  *c = (beta.re == 0.0 && beta.im == 0.0) ? av : zfma(beta, *c, av);
+}
+
+// dst[a][:] = src[rows[a]][:] for a < k (n columns).
+__global__ __launch_bounds__(256) void k_gather_rows(const z64* src, int lds, const int32_t* rows,
+                                                     int n, z64* dst, int ldd) {
+  const int a = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < n) dst[size_t(a) * ldd + j] = src[size_t(rows[a]) * lds + j];
+}
+
+// P[:, c] *= s_c for the N_d x k panel P (s_c = k0^2 delta_c), then
+// Cap[a][c] = delta_ac - P[F_a][c].
+__global__ __launch_bounds__(256) void k_wood_scale(z64* P, int ldp, int nd, int k,
+                                                    const double* s) {
+  const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= size_t(nd) * k) return;
+  const int i = int(e / k), c = int(e % k);
+  P[size_t(i) * ldp + c] = zscale(P[size_t(i) * ldp + c], s[c]);
+}
+__global__ __launch_bounds__(256) void k_wood_cap(const z64* P, int ldp, const int32_t* F, int k,
+                                                  z64* Cap) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= k * k) return;
+  const int a = e / k, c = e % k;
+  const z64 p = P[size_t(F[a]) * ldp + c];
+  Cap[e] = z64{(a == c ? 1.0 : 0.0) - p.re, -p.im};
+}
+
+// In-place inverse of a k x k complex matrix (k <= kSmallInv) by Gauss-Jordan
+// elimination with partial pivoting and physical row interchanges; the
+// column interchanges they imply are undone at the end in reverse order.
+// One workgroup; the matrix lives in LDS.  status is set on a zero pivot.
+constexpr int kSmallInv = 64;
+
+__global__ __launch_bounds__(256) void k_small_inverse(z64* A, int k, int32_t* status) {
+  __shared__ double Mr[kSmallInv][kSmallInv + 1], Mi[kSmallInv][kSmallInv + 1];
+  __shared__ double fr[kSmallInv], fi[kSmallInv];
+  __shared__ int perm[kSmallInv];
+  __shared__ int s_p;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < k * k; e += 256) {
+    Mr[e / k][e % k] = A[e].re;
+    Mi[e / k][e % k] = A[e].im;
+  }
+  __syncthreads();
+  for (int c = 0; c < k; ++c) {
+    // pivot: largest |M[r][c]| over r >= c (the first of equals)
+    if (tid < 64) {
+      double best = -1.0;
+      int bidx = k;
+      for (int r = c + tid; r < k; r += 64) {
+        const double a = Mr[r][c] * Mr[r][c] + Mi[r][c] * Mi[r][c];
+        if (a > best) { best = a; bidx = r; }
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bidx, o, 64);
+        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+      }
+      if (tid == 0) {
+        if (!(best > 0.0)) {
+          atomicOr(status, 1);
+          bidx = c;
+        }
+        s_p = bidx;
+        perm[c] = bidx;
+      }
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != c)
+      for (int j = tid; j < k; j += 256) {
+        double t = Mr[c][j]; Mr[c][j] = Mr[p][j]; Mr[p][j] = t;
+        t = Mi[c][j]; Mi[c][j] = Mi[p][j]; Mi[p][j] = t;
+      }
+    __syncthreads();
+    // pivot row: M[c][c] <- 1 / piv, M[c][j] <- M[c][j] / piv; save column c
+    const z64 inv = zdiv(z64{1.0, 0.0}, z64{Mr[c][c], Mi[c][c]});
+    for (int r = tid; r < k; r += 256) { fr[r] = Mr[r][c]; fi[r] = Mi[r][c]; }
+    __syncthreads();
+    for (int j = tid; j < k; j += 256) {
+      const z64 v = (j == c) ? inv : zmul(z64{Mr[c][j], Mi[c][j]}, inv);
+      Mr[c][j] = v.re;
+      Mi[c][j] = v.im;
+    }
+    __syncthreads();
+    // other rows: M[r][j] <- (j == c ? 0 : M[r][j]) - f_r M[c][j]
+    for (int e = tid; e < k * k; e += 256) {
+      const int r = e / k, j = e % k;
+      if (r == c) continue;
+      const z64 pr{Mr[c][j], Mi[c][j]};
+      const z64 old = (j == c) ? z64{0.0, 0.0} : z64{Mr[r][j], Mi[r][j]};
+      const z64 v = zsub(old, zmul(z64{fr[r], fi[r]}, pr));
+      Mr[r][j] = v.re;
+      Mi[r][j] = v.im;
+    }
+    __syncthreads();
+  }
+  // undo the column interchanges, last first
+  for (int c = k - 1; c >= 0; --c) {
+    const int p = perm[c];
+    if (p != c)
+      for (int r = tid; r < k; r += 256) {
+        double t = Mr[r][c]; Mr[r][c] = Mr[r][p]; Mr[r][p] = t;
+        t = Mi[r][c]; Mi[r][c] = Mi[r][p]; Mi[r][p] = t;
+      }
+    __syncthreads();
+  }
+  for (int e = tid; e < k * k; e += 256) {
+    A[e].re = Mr[e / k][e % k];
+    A[e].im = Mi[e / k][e % k];
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+// C = beta C + alpha A op(B); transb: B[k][n] = R[rb ? rb[n] : n][k].
+// work (>= splits * M * N entries) is used when splits > 1.
+hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
+                        bool transb, const int32_t* rb, z64* C, int ldc, z64 alpha, z64 beta,
+                        int splits, z64* work, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (K <= 0) return hipErrorInvalidValue;
+  splits = std::max(1, std::min(splits, (K + kGemmBK - 1) / kGemmBK));
+  if (splits > 1 && !work) return hipErrorInvalidValue;
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + kGemmBK - 1) / kGemmBK * kGemmBK;
+  splits = (K + kchunk - 1) / kchunk;
+  z64* wk = splits > 1 ? work : nullptr;
+  const bool big = M >= 512 && N >= 512;
+  if (big) {
+    dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
+    if (transb)
+      hipLaunchKernelGGL((k_zgemm<2, 2, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                         rb, C, ldc, alpha, beta, kchunk, wk);
+    else
+      hipLaunchKernelGGL((k_zgemm<2, 2, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                         rb, C, ldc, alpha, beta, kchunk, wk);
+  } else {
+    dim3 grid((N + 31) / 32, (M + 31) / 32, splits);
+    if (transb)
+      hipLaunchKernelGGL((k_zgemm<1, 1, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                         rb, C, ldc, alpha, beta, kchunk, wk);
+    else
+      hipLaunchKernelGGL((k_zgemm<1, 1, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                         rb, C, ldc, alpha, beta, kchunk, wk);
+  }
+  if (splits > 1) {
+    const size_t n = size_t(M) * N;
+    hipLaunchKernelGGL(k_zgemm_reduce, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, M, N,
+                       splits, work, C, ldc, alpha, beta);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int k, int n, z64* dst,
+                              int ldd, hipStream_t s) {
+  if (k <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, dim3((n + 255) / 256, k), dim3(256), 0, s, src, lds, rows, n,
+                     dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, const double* sc,
+                           z64* Cap, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  const size_t n = size_t(nd) * k;
+  hipLaunchKernelGGL(k_wood_scale, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, P, ldp, nd, k,
+                     sc);
+  hipLaunchKernelGGL(k_wood_cap, dim3((k * k + 255) / 256), dim3(256), 0, s, P, ldp, F, k, Cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_inverse(z64* A, int k, int32_t* status, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  if (k > kSmallInv) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_small_inverse, dim3(1), dim3(256), 0, s, A, k, status);
+  return hipGetLastError();
+}
+
+}  // namespace pngf

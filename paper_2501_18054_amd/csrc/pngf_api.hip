@@ -24,6 +24,14 @@ hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
                              int grid, int npl, int mixed, int step, hipStream_t s);
 hipError_t launch_accept_only(const ProbDev& P, int npl, hipStream_t s);
+hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
+                        bool transb, const int32_t* rb, z64* C, int ldc, z64 alpha, z64 beta,
+                        int splits, z64* work, hipStream_t s);
+hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int k, int n, z64* dst,
+                              int ldd, hipStream_t s);
+hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, const double* sc,
+                           z64* Cap, hipStream_t s);
+hipError_t launch_small_inverse(z64* A, int k, int32_t* status, hipStream_t s);
 hipError_t launch_pick_best(const double* df, const int32_t* cand, int n, const DbsState* st,
                             int32_t* out, hipStream_t s);
 hipError_t model_score_state(pngf_model* m, const ProbDev& P, float** scores);
@@ -50,6 +58,8 @@ constexpr int kGjNbHost = 16;
 constexpr int kPanelCap = 64;      // deferred Sherman-Morrison terms (mixed)
 constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
+constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
+constexpr int kWoodSplits = 8;     // split-K factor of its skinny GEMM
 constexpr int kDriftEvery = 32;    // accepts between drift checks
 }  // namespace pngf
 
@@ -64,7 +74,7 @@ thread_local std::string g_create_error;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 enum KernelId { KID_SCORE = 0, KID_SELECT = 1, KID_ACCEPT = 2, KID_LU = 3, KID_OTHER = 4,
-                KID_FOLD = 5, KID_MIXQ = 6, KID_N = 8 };
+                KID_FOLD = 5, KID_MIXQ = 6, KID_WOOD = 7, KID_N = 8 };
 
 struct Layout {
   size_t off_G[pngf::kMaxFreq], off_C[pngf::kMaxFreq], off_E[pngf::kMaxFreq],
@@ -79,6 +89,7 @@ struct Layout {
       off_tauB[pngf::kMaxFreq];
   size_t off_bitsB, off_stateB, off_keys, off_pm, off_best, off_feat;
   size_t off_S, off_B1, off_Pb, off_ts, off_B11, off_piv, off_invp, off_used, off_status, off_u, off_r;
+  size_t off_wP, off_wQ, off_wW, off_wCap, off_wF, off_wS, off_wWork;
   size_t total;
 };
 
@@ -97,6 +108,7 @@ struct pngf_handle {
   Layout lay{};
   pngf::ProbDev P{};
   std::vector<uint8_t> bits;
+  std::vector<uint8_t> bits_ref;   // design whose FP64 inverse C^-1 holds (mixed runs)
   double f_host = 0.0;
   // event timing
   double ktime_ms[KID_N] = {0};
@@ -164,6 +176,15 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_df32 = take(size_t(nd) * sizeof(double));
     L.off_dfb = take(size_t(nd) * sizeof(double));
     L.off_bandout = take(sizeof(double));
+    // FP64 block-Woodbury refresh: panel, rows, capacitance, split-K partials
+    const size_t kw = size_t(pngf::kWoodMax);
+    L.off_wP = take(size_t(nd) * kw * sizeof(z64));
+    L.off_wQ = take(kw * nd * sizeof(z64));
+    L.off_wW = take(kw * nd * sizeof(z64));
+    L.off_wCap = take(kw * kw * sizeof(z64));
+    L.off_wF = take(kw * sizeof(int32_t));
+    L.off_wS = take(kw * sizeof(double));
+    L.off_wWork = take(size_t(pngf::kWoodSplits) * nd * kw * sizeof(z64));
   }
   L.off_S = take(mat);
   L.off_B1 = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
@@ -241,6 +262,41 @@ void collect_times(pngf_handle* h) {
 // Re-form C^-1 (FP64, on the device) from G and the device design bits for
 // every frequency, then E = C^-1 b with one refinement step against C, the
 // output row R' = G_OD + k0^2 C^-1 G diag(deps) G_OD and x, f.
+// E = C^-1 b with one step of FP64 iterative refinement against C, then
+// R' = G_OD (I + k0^2 D C^-1 G) = G_OD + k0^2 C^-1 (G D G_OD) (reciprocity)
+// and the outputs, for the design in P.bits and the C^-1 in P.Cinv.
+int reform_fields(pngf_handle* h) {
+  const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
+  const Layout& L = h->lay;
+  pngf::ProbDev& P = h->P;
+  z64* u = at<z64>(h, L.off_u);
+  z64* r = at<z64>(h, L.off_r);
+  const z64 one{1.0, 0.0}, zero{0.0, 0.0};
+  for (int f = 0; f < F; ++f) {
+    const double k2 = P.k0sq[f];
+    const z64* b = at<z64>(h, L.off_b[f]);
+    const z64* god = at<z64>(h, L.off_god[f]);
+    Timer t(h, KID_OTHER);
+    // E = C^-1 b
+    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, b, nullptr, 0.0, one, zero, nullptr, 0.0,
+                                nullptr, P.E[f], h->stream));
+    // r = b - E + k0^2 G diag(deps) E ;  E += C^-1 r
+    HIPCHK(h, pngf::launch_gemv(P.G[f], ld, nd, P.E[f], P.bits, P.deps, z64{k2, 0.0}, one, b,
+                                -1.0, P.E[f], r, h->stream));
+    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, r, nullptr, 0.0, one, one, P.E[f], 0.0,
+                                nullptr, P.E[f], h->stream));
+    // u = G diag(deps) G_OD ; R' = G_OD + k0^2 C^-1 u
+    HIPCHK(h, pngf::launch_gemv(P.G[f], ld, nd, god, P.bits, P.deps, one, zero, nullptr, 0.0,
+                                nullptr, u, h->stream));
+    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, u, nullptr, 0.0, z64{k2, 0.0}, one, god, 0.0,
+                                nullptr, P.Rp[f], h->stream));
+    const cd xb = h->pc.freq[f].xb;
+    HIPCHK(h, pngf::launch_output(P, f, god, z64{xb.real(), xb.imag()}, f == F - 1, h->stream));
+    t.end();
+  }
+  return PNGF_OK;
+}
+
 int device_reinvert(pngf_handle* h) {
   const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
   const Layout& L = h->lay;
@@ -251,9 +307,6 @@ int device_reinvert(pngf_handle* h) {
   int32_t* invp = at<int32_t>(h, L.off_invp);
   int32_t* used = at<int32_t>(h, L.off_used);
   int32_t* status = at<int32_t>(h, L.off_status);
-  z64* u = at<z64>(h, L.off_u);
-  z64* r = at<z64>(h, L.off_r);
-  const z64 one{1.0, 0.0}, zero{0.0, 0.0};
   HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
   // S (pixels at eps_hi) and Z from the device design bits
   HIPCHK(h, hipMemcpyAsync(h->bits.data(), P.bits, nd, hipMemcpyDeviceToHost, h->stream));
@@ -274,40 +327,89 @@ int device_reinvert(pngf_handle* h) {
   HIPCHK(h, hipMemcpyAsync(d_pos, pos.data(), nd * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   for (int f = 0; f < F; ++f) {
     const double k2 = P.k0sq[f];
-    const z64* b = at<z64>(h, L.off_b[f]);
-    const z64* god = at<z64>(h, L.off_god[f]);
-    {
-      Timer t(h, KID_LU);
-      HIPCHK(h, pngf::launch_inverse(S, P.Cinv[f], P.G[f], nd, ld, d_sidx, d_zidx, d_pos, ns,
-                                     k2 * P.deps, B1, at<z64>(h, L.off_Pb),
-                                     at<z64>(h, L.off_Pn), piv, invp, used, status,
-                                     at<int32_t>(h, L.off_ts), at<z64>(h, L.off_B11),
-                                     h->stream));
-      t.end();
-    }
-    Timer t(h, KID_OTHER);
-    // E = C^-1 b
-    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, b, nullptr, 0.0, one, zero, nullptr, 0.0,
-                                nullptr, P.E[f], h->stream));
-    // r = b - E + k0^2 G diag(deps) E ;  E += C^-1 r
-    HIPCHK(h, pngf::launch_gemv(P.G[f], ld, nd, P.E[f], P.bits, P.deps, z64{k2, 0.0}, one, b,
-                                -1.0, P.E[f], r, h->stream));
-    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, r, nullptr, 0.0, one, one, P.E[f], 0.0,
-                                nullptr, P.E[f], h->stream));
-    // u = G diag(deps) G_OD ; R' = G_OD + k0^2 C^-1 u
-    HIPCHK(h, pngf::launch_gemv(P.G[f], ld, nd, god, P.bits, P.deps, one, zero, nullptr, 0.0,
-                                nullptr, u, h->stream));
-    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, u, nullptr, 0.0, z64{k2, 0.0}, one, god, 0.0,
-                                nullptr, P.Rp[f], h->stream));
-    const cd xb = h->pc.freq[f].xb;
-    HIPCHK(h, pngf::launch_output(P, f, god, z64{xb.real(), xb.imag()}, f == F - 1, h->stream));
+    Timer t(h, KID_LU);
+    HIPCHK(h, pngf::launch_inverse(S, P.Cinv[f], P.G[f], nd, ld, d_sidx, d_zidx, d_pos, ns,
+                                   k2 * P.deps, B1, at<z64>(h, L.off_Pb),
+                                   at<z64>(h, L.off_Pn), piv, invp, used, status,
+                                   at<int32_t>(h, L.off_ts), at<z64>(h, L.off_B11),
+                                   h->stream));
     t.end();
   }
+  int st = reform_fields(h);
+  if (st) return st;
   int32_t st_host = 0;
   HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
   if (st_host) return fail(h, PNGF_ESINGULAR, "zero pivot while inverting the PNGF system matrix");
+  h->bits_ref = h->bits;
+  return PNGF_OK;
+}
+
+// FP64 refresh of C^-1 for the design in P.bits from the FP64 inverse of the
+// design bits_ref (a mixed search leaves P.Cinv untouched between refreshes):
+// with F the pixels that differ, a block-Woodbury update (eq. lru_woodbury,
+// M = |F|) on the matrix cores, exact up to FP64 rounding; a full
+// re-inversion when F is larger than kWoodMax or its capacitance matrix is
+// singular.  Then E (with one refinement step), R' and x are re-formed.
+int fp64_refresh(pngf_handle* h) {
+  const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
+  const Layout& L = h->lay;
+  pngf::ProbDev& P = h->P;
+  if (h->opt.precision != PNGF_MIXED || h->bits_ref.size() != size_t(nd)) return device_reinvert(h);
+  std::vector<uint8_t> cur(nd);
+  HIPCHK(h, hipMemcpyAsync(cur.data(), P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  std::vector<int32_t> fl;
+  for (int i = 0; i < nd; ++i)
+    if (cur[i] != h->bits_ref[i]) fl.push_back(i);
+  const int k = int(fl.size());
+  if (k > pngf::kWoodMax) return device_reinvert(h);
+  if (k > 0) {
+    int32_t* dF = at<int32_t>(h, L.off_wF);
+    double* dS = at<double>(h, L.off_wS);
+    z64* wP = at<z64>(h, L.off_wP);
+    z64* wQ = at<z64>(h, L.off_wQ);
+    z64* wW = at<z64>(h, L.off_wW);
+    z64* cap = at<z64>(h, L.off_wCap);
+    z64* work = at<z64>(h, L.off_wWork);
+    int32_t* status = at<int32_t>(h, L.off_status);
+    std::vector<double> sc(size_t(F) * k);
+    for (int f = 0; f < F; ++f)
+      for (int c = 0; c < k; ++c)
+        sc[size_t(f) * k + c] = P.k0sq[f] * (cur[fl[c]] ? P.deps : -P.deps);
+    HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
+    HIPCHK(h, hipMemcpyAsync(dF, fl.data(), k * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    const z64 one{1.0, 0.0}, zero{0.0, 0.0};
+    for (int f = 0; f < F; ++f) {
+      Timer t(h, KID_WOOD);
+      HIPCHK(h, hipMemcpyAsync(dS, sc.data() + size_t(f) * k, k * sizeof(double),
+                               hipMemcpyHostToDevice, h->stream));
+      // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T)
+      HIPCHK(h, pngf::launch_zgemm(nd, k, nd, P.Cinv[f], ld, P.G[f], ld, true, dF, wP, k, one,
+                                   zero, pngf::kWoodSplits, work, h->stream));
+      HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS, cap, h->stream));
+      HIPCHK(h, pngf::launch_small_inverse(cap, k, status, h->stream));
+      // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
+      HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, h->stream));
+      HIPCHK(h, pngf::launch_zgemm(k, nd, k, cap, k, wQ, nd, false, nullptr, wW, nd, one, zero, 1,
+                                   nullptr, h->stream));
+      HIPCHK(h, pngf::launch_zgemm(nd, nd, k, wP, k, wW, nd, false, nullptr, P.Cinv[f], ld, one,
+                                   one, 1, nullptr, h->stream));
+      t.end();
+      // the host copies above read sc while the stream runs: wait per frequency
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    int32_t st_host = 0;
+    HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (st_host) return device_reinvert(h);
+  }
+  int st = reform_fields(h);
+  if (st) return st;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  h->bits_ref = cur;
   return PNGF_OK;
 }
 
@@ -390,12 +492,22 @@ int run_plain(pngf_handle* h, pngf::DbsState* pinned) {
   return fail(h, PNGF_ENUMERIC, "DBS did not terminate");
 }
 
+// At rest P.Cinv is the FP64 inverse of the current design: record that
+// design as the base of the block-Woodbury refreshes of a mixed search.
+int capture_ref_bits(pngf_handle* h) {
+  h->bits_ref.resize(h->pc.n_d);
+  HIPCHK(h, hipMemcpyAsync(h->bits_ref.data(), h->P.bits, h->pc.n_d, hipMemcpyDeviceToHost,
+                           h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PNGF_OK;
+}
+
 // Re-form the FP64 state, cast C0^-1 to complex FP32, rescore every candidate
 // in FP64 (exact key) and, when the previous scores were FP32, measure their
 // error against the FP64 scores to set the error band.
 int mixed_refresh(pngf_handle* h, bool measure) {
   const int nd = h->pc.n_d, F = int(h->pc.freq.size());
-  int st = device_reinvert(h);
+  int st = fp64_refresh(h);
   if (st) return st;
   for (int f = 0; f < F; ++f)
     HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
@@ -451,6 +563,8 @@ int mixed_residual(pngf_handle* h, double* ratio) {
 // folds the panel into C0^-1 on the matrix cores, or checks the drift.
 int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_t* n_band) {
   const int nd = h->pc.n_d, F = int(h->pc.freq.size());
+  int st0 = capture_ref_bits(h);
+  if (st0) return st0;
   for (int f = 0; f < F; ++f)
     HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
   pngf::DbsState s;
@@ -519,7 +633,7 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
   }
   if (!pinned->done) return fail(h, PNGF_ENUMERIC, "DBS did not terminate");
   // Final objective in FP64: re-form the state of the converged design.
-  st = device_reinvert(h);
+  st = fp64_refresh(h);
   if (st) return st;
   HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
                            h->stream));
@@ -1201,6 +1315,8 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
     int st = dbs_prologue(h, perms[p], n_sweeps[p], &f0[p]);
     if (st) return bfail(b, st, std::string("problem ") + std::to_string(p) + ": " + h->err);
     if (b->mixed) {
+      st = capture_ref_bits(h);
+      if (st) return bfail(b, st, h->err);
       for (int f = 0; f < int(h->pc.freq.size()); ++f)
         BHIPCHK(b, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], h->pc.n_d, h->ld, b->stream));
       pngf::DbsState s;
@@ -1326,7 +1442,7 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
   // final FP64 state (mixed), results, and states back to each handle
   for (int p = 0; p < n && rc == PNGF_OK; ++p) {
     pngf_handle* h = b->hs[p];
-    if (b->mixed && device_reinvert(h)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
+    if (b->mixed && fp64_refresh(h)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
     pngf::DbsState fin;
     if (read_state(h, &fin)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
     if (dbs_epilogue(h, fin, f0[p], nref[p], nband[p], accepted ? accepted[p] : nullptr,
