@@ -149,14 +149,15 @@ def main():
     for name, opts, mixed in (
             ("plain", P.default_options(**base), False),
             ("mixed", P.default_options(precision=P.PNGF_MIXED, k_refresh=32, **base), True),
-            ("mixed_drift", P.default_options(precision=P.PNGF_MIXED, k_refresh=0, **base), True)):
+            ("mixed_drift", P.default_options(precision=P.PNGF_MIXED, k_refresh=0, **base), True),
+            ("rform", P.default_options(precision=P.PNGF_RFORM, **base), False)):
         res, dt, kt = run_form(P, h, prob, opts, a.steps, a.warmup, name)
         s = summarize(res, dt, a.steps)
         s["kernels"] = kernel_table(kt, nd, mixed)
         s["accepted_seq"] = res[-1]["accepted"]
         forms[name] = s
     ref = forms["plain"]
-    for name in ("mixed", "mixed_drift"):
+    for name in ("mixed", "mixed_drift", "rform"):
         f = forms[name]
         f["same_sequence_as_plain"] = bool((f["accepted_seq"] == ref["accepted_seq"]).all()) \
             if len(f["accepted_seq"]) == len(ref["accepted_seq"]) else False

@@ -56,7 +56,18 @@ typedef enum pngf_status {
 enum { PNGF_POINT_INTENSITY = 0, PNGF_OVERLAP_INTENSITY = 1,
        PNGF_MEAN_TRANSMISSION = 2 };
 
-enum { PNGF_FP64_PLAIN = 0, PNGF_MIXED = 1 };
+/* PNGF_FP64_PLAIN: FP64 C^-1 kept current by a Sherman-Morrison update per
+ *   accept (eq. lru_woodbury, M = 1); every candidate scored from C^-1 and G.
+ * PNGF_MIXED: complex-FP32 C0^-1 with a deferred panel, FP64 refreshes and
+ *   FP64 decisions inside the FP32 error band.
+ * PNGF_RFORM: FP64 reduced scoring, not in the paper.  By reciprocity
+ *   T = C^-1 G is complex symmetric, so an accept of pixel m changes it by
+ *   alpha p p^T with p = T[:, m]; from T0 = C^-1 G at the run start and a
+ *   panel of the p vectors, every candidate is scored from diag(T), E, R' in
+ *   O(1) and an accept costs O(N_d k) instead of O(N_d^2).  Exact (same
+ *   accepted sequence as the other forms).  Only pngf_dbs_run uses the
+ *   R-form; the other calls bring C^-1 up to date first. */
+enum { PNGF_FP64_PLAIN = 0, PNGF_MIXED = 1, PNGF_RFORM = 2 };
 
 /* pngf_options.flags: record HIP events around every hot-path kernel launch
  * so pngf_kernel_times can report average device time per kernel. */
@@ -93,7 +104,9 @@ typedef struct pngf_options {
                         /* inverse of the last refresh (exact to rounding),  */
                         /* or a full re-inversion if > 64 pixels changed     */
   int32_t k_fold;       /* MIXED: fold the deferred panel into C0^-1 once it */
-                        /* holds k_fold terms (0 = only when it is full)     */
+                        /* holds k_fold terms (0 = only when it is full);    */
+                        /* RFORM: panel capacity before a fold into T0       */
+                        /* (0 = 512)                                         */
   int32_t max_accepts;  /* capacity of the on-device accept log (>= 1)       */
   int32_t max_sweeps;   /* largest n_sweeps pngf_dbs_run will be given       */
   int32_t reserved0;    /* 0                                                 */

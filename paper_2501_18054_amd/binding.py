@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libpngf.so")
 
 PNGF_FP64_PLAIN = 0
 PNGF_MIXED = 1
+PNGF_RFORM = 2
 PNGF_FLAG_TIMING = 1
 
 KERNEL_IDS = {"score": 0, "select": 1, "accept": 2, "lu": 3, "other": 4, "fold": 5,

@@ -78,7 +78,11 @@ struct ProbDev {
   uint8_t* bitsB;
   DbsState* stB;               // state of odd steps
   uint32_t* keys;              // [6]: sure keys in slots 0-2, band keys in 3-5
-  int32_t* pm;                 // pixel of each panel slot (mixed)
+  int32_t* pm;                 // pixel of each panel slot (mixed, R-form)
+  // R-form: T0 = C^-1 G at the run start (nd x ld, symmetric) and the FP64
+  // panel of columns p_k = T[:, m_k], slot k at Up + k*ld
+  z64* T0[kMaxFreq];
+  z64* Up[kMaxFreq];
 };
 
 }  // namespace pngf

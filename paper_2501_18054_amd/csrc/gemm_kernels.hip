@@ -1,9 +1,11 @@
 // Complex FP64 GEMM on the gfx950 matrix cores, and the small kernels of the
 // FP64 block-Woodbury refresh of C^-1.
 //
-// GEMM: C = beta C + alpha A B with A (M x K, row-major) and B either K x N
-// row-major or given by rows of R (B[k][n] = R[rb[n]][k], the transposed
-// product of the reciprocity-symmetric operands used here).  A complex
+// GEMM: C = beta C + alpha A B with A (M x K, row-major, optionally with
+// gathered columns A[i][k] = A'[i][ca[k]]) and B either K x N row-major
+// (optionally with gathered rows B[k][n] = B'[rb[k]][n]) or given by rows of
+// R (B[k][n] = R[rb[n]][k], the transposed product of the
+// reciprocity-symmetric operands used here).  A complex
 // product is four real v_mfma_f64_16x16x4f64 products into separate real and
 // imaginary accumulators.  Operand layouts of the 16x16x4 FP64 instruction:
 // lane l holds A[l%16][l/16] and B[l/16][l%16]; accumulator register r holds
@@ -28,9 +30,9 @@ constexpr int kGemmBK = 16;
 
 template <int WM, int WN, bool TRANSB>
 __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A, int lda,
-                                               const z64* B, int ldb, const int32_t* rb, z64* C,
-                                               int ldc, z64 alpha, z64 beta, int kchunk,
-                                               z64* work) {
+                                               const int32_t* ca, const z64* B, int ldb,
+                                               const int32_t* rb, z64* C, int ldc, z64 alpha,
+                                               z64 beta, int kchunk, z64* work) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   __shared__ double sAr[BM][kGemmBK + 1], sAi[BM][kGemmBK + 1];
   __shared__ double sBr[kGemmBK][BN + 1], sBi[kGemmBK][BN + 1];
@@ -53,7 +55,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A
       const int r = e >> 4, c = e & 15;
       const int gr = m0 + r, gc = k0 + c;
       z64 v{0.0, 0.0};
-      if (gr < M && gc < kend) v = A[size_t(gr) * lda + gc];
+      if (gr < M && gc < kend) v = A[size_t(gr) * lda + (ca ? ca[gc] : gc)];
       sAr[r][c] = v.re;
       sAi[r][c] = v.im;
     }
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A
         const int r = e / BN, n = e % BN;
         const int gr = k0 + r, gn = n0 + n;
         z64 v{0.0, 0.0};
-        if (gr < kend && gn < N) v = B[size_t(gr) * ldb + gn];
+        if (gr < kend && gn < N) v = B[size_t(rb ? rb[gr] : gr) * ldb + gn];
         sBr[r][n] = v.re;
         sBi[r][n] = v.im;
       }
@@ -252,11 +254,12 @@ __global__ __launch_bounds__(256) void k_small_inverse(z64* A, int k, int32_t* s
 }
 
 // ------------------------------------------------------------------ launchers
-// C = beta C + alpha A op(B); transb: B[k][n] = R[rb ? rb[n] : n][k].
+// C = beta C + alpha A op(B); A[i][k] = A'[i][ca ? ca[k] : k]; transb:
+// B[k][n] = R[rb ? rb[n] : n][k], else B[k][n] = B'[rb ? rb[k] : k][n].
 // work (>= splits * M * N entries) is used when splits > 1.
-hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
-                        bool transb, const int32_t* rb, z64* C, int ldc, z64 alpha, z64 beta,
-                        int splits, z64* work, hipStream_t s) {
+hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_t* ca,
+                        const z64* B, int ldb, bool transb, const int32_t* rb, z64* C, int ldc,
+                        z64 alpha, z64 beta, int splits, z64* work, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (K <= 0) return hipErrorInvalidValue;
   splits = std::max(1, std::min(splits, (K + kGemmBK - 1) / kGemmBK));
@@ -269,19 +272,19 @@ hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const z64* B
   if (big) {
     dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
     if (transb)
-      hipLaunchKernelGGL((k_zgemm<2, 2, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
-                         rb, C, ldc, alpha, beta, kchunk, wk);
+      hipLaunchKernelGGL((k_zgemm<2, 2, true>), grid, dim3(256), 0, s, M, N, K, A, lda, ca, B,
+                         ldb, rb, C, ldc, alpha, beta, kchunk, wk);
     else
-      hipLaunchKernelGGL((k_zgemm<2, 2, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
-                         rb, C, ldc, alpha, beta, kchunk, wk);
+      hipLaunchKernelGGL((k_zgemm<2, 2, false>), grid, dim3(256), 0, s, M, N, K, A, lda, ca, B,
+                         ldb, rb, C, ldc, alpha, beta, kchunk, wk);
   } else {
     dim3 grid((N + 31) / 32, (M + 31) / 32, splits);
     if (transb)
-      hipLaunchKernelGGL((k_zgemm<1, 1, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
-                         rb, C, ldc, alpha, beta, kchunk, wk);
+      hipLaunchKernelGGL((k_zgemm<1, 1, true>), grid, dim3(256), 0, s, M, N, K, A, lda, ca, B,
+                         ldb, rb, C, ldc, alpha, beta, kchunk, wk);
     else
-      hipLaunchKernelGGL((k_zgemm<1, 1, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
-                         rb, C, ldc, alpha, beta, kchunk, wk);
+      hipLaunchKernelGGL((k_zgemm<1, 1, false>), grid, dim3(256), 0, s, M, N, K, A, lda, ca, B,
+                         ldb, rb, C, ldc, alpha, beta, kchunk, wk);
   }
   if (splits > 1) {
     const size_t n = size_t(M) * N;

@@ -24,9 +24,13 @@ hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
                              int grid, int npl, int mixed, int step, hipStream_t s);
 hipError_t launch_accept_only(const ProbDev& P, int npl, hipStream_t s);
-hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
-                        bool transb, const int32_t* rb, z64* C, int ldc, z64 alpha, z64 beta,
-                        int splits, z64* work, hipStream_t s);
+hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_t* ca,
+                        const z64* B, int ldb, bool transb, const int32_t* rb, z64* C, int ldc,
+                        z64 alpha, z64 beta, int splits, z64* work, hipStream_t s);
+hipError_t launch_rform_step(const ProbDev& P, int npl, int step, hipStream_t s);
+hipError_t launch_rform_score(const ProbDev& P, hipStream_t s);
+hipError_t launch_rform_ut(const ProbDev& P, int f, int kp, z64* Ut, hipStream_t s);
+hipError_t launch_rform_t0_init(const ProbDev& P, int f, hipStream_t s);
 hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int k, int n, z64* dst,
                               int ldd, hipStream_t s);
 hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, const double* sc,
@@ -60,6 +64,7 @@ constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
 constexpr int kWoodSplits = 8;     // split-K factor of its skinny GEMM
+constexpr int kRPanel = 512;       // R-form panel capacity before a fold into T0
 constexpr int kDriftEvery = 32;    // accepts between drift checks
 }  // namespace pngf
 
@@ -90,6 +95,7 @@ struct Layout {
   size_t off_bitsB, off_stateB, off_keys, off_pm, off_best, off_feat;
   size_t off_S, off_B1, off_Pb, off_ts, off_B11, off_piv, off_invp, off_used, off_status, off_u, off_r;
   size_t off_wP, off_wQ, off_wW, off_wCap, off_wF, off_wS, off_wWork;
+  size_t off_T[pngf::kMaxFreq], off_Up[pngf::kMaxFreq], off_ralph[pngf::kMaxFreq], off_rpm, off_Ut;
   size_t total;
 };
 
@@ -109,6 +115,7 @@ struct pngf_handle {
   pngf::ProbDev P{};
   std::vector<uint8_t> bits;
   std::vector<uint8_t> bits_ref;   // design whose FP64 inverse C^-1 holds (mixed runs)
+  bool cinv_stale = false;         // an R-form search moved the design past C^-1
   double f_host = 0.0;
   // event timing
   double ktime_ms[KID_N] = {0};
@@ -176,6 +183,18 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_df32 = take(size_t(nd) * sizeof(double));
     L.off_dfb = take(size_t(nd) * sizeof(double));
     L.off_bandout = take(sizeof(double));
+  }
+  if (o->precision == PNGF_RFORM) {
+    const size_t kr = size_t(pngf::kRPanel);
+    for (int f = 0; f < F; ++f) {
+      L.off_T[f] = take(mat);
+      L.off_Up[f] = take(kr * ld * sizeof(z64));
+      L.off_ralph[f] = take(kr * sizeof(z64));
+    }
+    L.off_rpm = take(kr * sizeof(int32_t));
+    L.off_Ut = take(size_t(nd) * kr * sizeof(z64));
+  }
+  if (o->precision != PNGF_FP64_PLAIN) {
     // FP64 block-Woodbury refresh: panel, rows, capacitance, split-K partials
     const size_t kw = size_t(pngf::kWoodMax);
     L.off_wP = take(size_t(nd) * kw * sizeof(z64));
@@ -343,6 +362,7 @@ int device_reinvert(pngf_handle* h) {
   if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
   if (st_host) return fail(h, PNGF_ESINGULAR, "zero pivot while inverting the PNGF system matrix");
   h->bits_ref = h->bits;
+  h->cinv_stale = false;
   return PNGF_OK;
 }
 
@@ -356,7 +376,8 @@ int fp64_refresh(pngf_handle* h) {
   const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
   const Layout& L = h->lay;
   pngf::ProbDev& P = h->P;
-  if (h->opt.precision != PNGF_MIXED || h->bits_ref.size() != size_t(nd)) return device_reinvert(h);
+  if (h->opt.precision == PNGF_FP64_PLAIN || h->bits_ref.size() != size_t(nd))
+    return device_reinvert(h);
   std::vector<uint8_t> cur(nd);
   HIPCHK(h, hipMemcpyAsync(cur.data(), P.bits, nd, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -386,16 +407,16 @@ int fp64_refresh(pngf_handle* h) {
       HIPCHK(h, hipMemcpyAsync(dS, sc.data() + size_t(f) * k, k * sizeof(double),
                                hipMemcpyHostToDevice, h->stream));
       // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T)
-      HIPCHK(h, pngf::launch_zgemm(nd, k, nd, P.Cinv[f], ld, P.G[f], ld, true, dF, wP, k, one,
-                                   zero, pngf::kWoodSplits, work, h->stream));
+      HIPCHK(h, pngf::launch_zgemm(nd, k, nd, P.Cinv[f], ld, nullptr, P.G[f], ld, true, dF, wP, k,
+                                   one, zero, pngf::kWoodSplits, work, h->stream));
       HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS, cap, h->stream));
       HIPCHK(h, pngf::launch_small_inverse(cap, k, status, h->stream));
       // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
       HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, h->stream));
-      HIPCHK(h, pngf::launch_zgemm(k, nd, k, cap, k, wQ, nd, false, nullptr, wW, nd, one, zero, 1,
-                                   nullptr, h->stream));
-      HIPCHK(h, pngf::launch_zgemm(nd, nd, k, wP, k, wW, nd, false, nullptr, P.Cinv[f], ld, one,
-                                   one, 1, nullptr, h->stream));
+      HIPCHK(h, pngf::launch_zgemm(k, nd, k, cap, k, nullptr, wQ, nd, false, nullptr, wW, nd, one,
+                                   zero, 1, nullptr, h->stream));
+      HIPCHK(h, pngf::launch_zgemm(nd, nd, k, wP, k, nullptr, wW, nd, false, nullptr, P.Cinv[f],
+                                   ld, one, one, 1, nullptr, h->stream));
       t.end();
       // the host copies above read sc while the stream runs: wait per frequency
       HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -410,6 +431,7 @@ int fp64_refresh(pngf_handle* h) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
   h->bits_ref = cur;
+  h->cinv_stale = false;
   return PNGF_OK;
 }
 
@@ -642,6 +664,106 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
 }
 
 
+// An R-form search leaves C^-1 at the design of its start: bring it to the
+// current design (block Woodbury, or a re-inversion) before a call needs it.
+int ensure_cinv(pngf_handle* h) {
+  if (!h->cinv_stale) return PNGF_OK;
+  return fp64_refresh(h);
+}
+
+// T0 = C^-1 G for the current design: rows of G for pixels at eps_lo, then
+// T0 += C^-1[:,S] G[S,:] over the pixels S at eps_hi (identity columns of
+// C^-1 elsewhere), on the FP64 matrix cores.
+int build_t0(pngf_handle* h) {
+  const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
+  pngf::ProbDev& P = h->P;
+  std::vector<int32_t> sidx;
+  for (int i = 0; i < nd; ++i)
+    if (h->bits_ref[i]) sidx.push_back(i);
+  const int ns = int(sidx.size());
+  int32_t* d_sidx = at<int32_t>(h, h->lay.off_sidx);
+  if (ns > 0)
+    HIPCHK(h, hipMemcpyAsync(d_sidx, sidx.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice,
+                             h->stream));
+  for (int f = 0; f < F; ++f) {
+    Timer t(h, KID_LU);
+    HIPCHK(h, pngf::launch_rform_t0_init(P, f, h->stream));
+    if (ns > 0)
+      HIPCHK(h, pngf::launch_zgemm(nd, nd, ns, P.Cinv[f], ld, d_sidx, P.G[f], ld, false, d_sidx,
+                                   P.T0[f], ld, z64{1.0, 0.0}, z64{1.0, 0.0}, 1, nullptr,
+                                   h->stream));
+    t.end();
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));   // sidx (host) was read by the copy
+  return PNGF_OK;
+}
+
+// Fold the R-form panel into T0 (T0 += Ut U) and empty it.
+int rform_fold(pngf_handle* h, int kp) {
+  const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
+  pngf::ProbDev& P = h->P;
+  z64* Ut = at<z64>(h, h->lay.off_Ut);
+  for (int f = 0; f < F; ++f) {
+    Timer t(h, KID_FOLD);
+    HIPCHK(h, pngf::launch_rform_ut(P, f, kp, Ut, h->stream));
+    HIPCHK(h, pngf::launch_zgemm(nd, nd, kp, Ut, kp, nullptr, P.Up[f], ld, false, nullptr,
+                                 P.T0[f], ld, z64{1.0, 0.0}, z64{1.0, 0.0}, 1, nullptr,
+                                 h->stream));
+    t.end();
+  }
+  return PNGF_OK;
+}
+
+// R-form search (FP64, exact): T0 once, then one O(N_d k) step kernel per
+// accepted flip; the panel is folded into T0 when it is full.
+int run_rform(pngf_handle* h, pngf::DbsState* pinned) {
+  int st = ensure_cinv(h);
+  if (st) return st;
+  st = capture_ref_bits(h);
+  if (st) return st;
+  st = build_t0(h);
+  if (st) return st;
+  pngf::DbsState s;
+  st = read_state(h, &s);
+  if (st) return st;
+  s.kpanel = 0;
+  s.n_since = 0;
+  s.exact = 1;
+  s.need_refresh = 0;
+  s.flips = 0;
+  st = write_state(h, &s);
+  if (st) return st;
+  st = start_segment(h);   // tau of the start state (from C^-1) and the first keys
+  if (st) return st;
+  h->cinv_stale = true;
+  const int batch = 32;
+  const int64_t max_rounds = 4 * int64_t(h->opt.max_accepts) + 64;
+  int64_t t = 0;
+  for (int64_t round = 0; round < max_rounds; ++round) {
+    st = run_steps(h, pngf::launch_rform_step, t, batch, pinned);
+    if (st) return st;
+    t += batch;
+    if (pinned->done) return PNGF_OK;
+    if (pinned->need_refresh) {
+      st = rform_fold(h, pinned->kpanel);
+      if (st) return st;
+      pinned->kpanel = 0;
+      pinned->need_refresh = 0;
+      pinned->exact = 1;
+      st = write_state(h, pinned);
+      if (st) return st;
+      const uint32_t none[6] = {pngf::kNoKey, pngf::kNoKey, pngf::kNoKey,
+                                pngf::kNoKey, pngf::kNoKey, pngf::kNoKey};
+      HIPCHK(h, hipMemcpyAsync(h->P.keys, none, sizeof(none), hipMemcpyHostToDevice, h->stream));
+      HIPCHK(h, pngf::launch_rform_score(h->P, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      t = 0;
+    }
+  }
+  return fail(h, PNGF_ENUMERIC, "DBS did not terminate");
+}
+
+
 // Validate and upload the sweep orders and reset the search bookkeeping of a
 // bound handle with a design; returns the initial objective in *f0.
 int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double* f0) {
@@ -777,16 +899,16 @@ int pngf_get_precompute(pngf_handle* h, int32_t fi, double* G, double* b, double
 
 int pngf_workspace_bytes(pngf_handle* h, const pngf_options* o, size_t* bytes) {
   if (!h || !o || !bytes) return PNGF_EINVAL;
-  if (o->precision != PNGF_FP64_PLAIN && o->precision != PNGF_MIXED)
-    return fail(h, PNGF_EINVAL, "precision must be PNGF_FP64_PLAIN or PNGF_MIXED");
+  if (o->precision != PNGF_FP64_PLAIN && o->precision != PNGF_MIXED && o->precision != PNGF_RFORM)
+    return fail(h, PNGF_EINVAL, "precision must be PNGF_FP64_PLAIN, PNGF_MIXED or PNGF_RFORM");
   *bytes = make_layout(h, o).total;
   return PNGF_OK;
 }
 
 int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes, void* stream) {
   if (!h || !o || !dev_ws) return PNGF_EINVAL;
-  if (o->precision != PNGF_FP64_PLAIN && o->precision != PNGF_MIXED)
-    return fail(h, PNGF_EINVAL, "precision must be PNGF_FP64_PLAIN or PNGF_MIXED");
+  if (o->precision != PNGF_FP64_PLAIN && o->precision != PNGF_MIXED && o->precision != PNGF_RFORM)
+    return fail(h, PNGF_EINVAL, "precision must be PNGF_FP64_PLAIN, PNGF_MIXED or PNGF_RFORM");
   if (o->k_refresh < 0 || o->k_fold < 0) return fail(h, PNGF_EINVAL, "k_refresh and k_fold must be >= 0");
   if (o->max_accepts < 1 || o->max_sweeps < 1)
     return fail(h, PNGF_EINVAL, "max_accepts and max_sweeps must be >= 1");
@@ -849,6 +971,17 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
     P.df32 = at<double>(h, L.off_df32);
     P.dfb = at<double>(h, L.off_dfb);
   }
+  if (o->precision == PNGF_RFORM) {
+    for (int f = 0; f < F; ++f) {
+      P.T0[f] = at<z64>(h, L.off_T[f]);
+      P.Up[f] = at<z64>(h, L.off_Up[f]);
+      P.alph[f] = at<z64>(h, L.off_ralph[f]);
+    }
+    P.pm = at<int32_t>(h, L.off_rpm);
+    P.kcap = o->k_fold > 0 ? std::min(o->k_fold, pngf::kRPanel) : pngf::kRPanel;
+    P.k_refresh = 0;
+  }
+  h->cinv_stale = false;
   // Zero the padded matrix storage once (padding columns are never read, but
   // keep them defined), then upload G.
   HIPCHK(h, hipMemsetAsync(h->ws, 0, L.total, h->stream));
@@ -910,6 +1043,8 @@ int pngf_evaluate(pngf_handle* h, double* f, double* x, double* e_d) {
 int pngf_score_flips(pngf_handle* h, const int32_t* cand, int32_t n, double* f_new) {
   int st = check_ready(h, true);
   if (st) return st;
+  st = ensure_cinv(h);
+  if (st) return st;
   if (n < 0 || n > h->pc.n_d || (n > 0 && (!cand || !f_new)))
     return fail(h, PNGF_EINVAL, "bad candidate list");
   for (int r = 0; r < n; ++r)
@@ -929,6 +1064,8 @@ int pngf_score_flips(pngf_handle* h, const int32_t* cand, int32_t n, double* f_n
 
 int pngf_accept_flips(pngf_handle* h, const int32_t* pix, int32_t n) {
   int st = check_ready(h, true);
+  if (st) return st;
+  st = ensure_cinv(h);
   if (st) return st;
   if (n < 0 || (n > 0 && !pix)) return fail(h, PNGF_EINVAL, "bad pixel list");
   for (int r = 0; r < n; ++r)
@@ -966,8 +1103,9 @@ int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t
   pngf::DbsState* pinned = nullptr;
   HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(pngf::DbsState)));
   int64_t n_refresh = 0, n_band = 0;
-  int rc = (h->opt.precision == PNGF_MIXED) ? run_mixed(h, pinned, &n_refresh, &n_band)
-                                            : run_plain(h, pinned);
+  int rc = (h->opt.precision == PNGF_MIXED)   ? run_mixed(h, pinned, &n_refresh, &n_band)
+           : (h->opt.precision == PNGF_RFORM) ? run_rform(h, pinned)
+                                              : run_plain(h, pinned);
   pngf::DbsState fin = *pinned;
   hipHostFree(pinned);
   if (rc) return rc;
@@ -1264,6 +1402,8 @@ int pngf_batch_bind(pngf_batch* b, void* dev_ws, size_t bytes, void* stream) {
   for (pngf_handle* h : b->hs) {
     if (!h->bound) return bfail(b, PNGF_ESTATE, "every handle must be bound");
     if (h->opt.precision != prec) return bfail(b, PNGF_EINVAL, "mixed precisions in one batch");
+    if (h->opt.precision == PNGF_RFORM)
+      return bfail(b, PNGF_EINVAL, "batches run FP64 plain or mixed handles");
     if (h->stream != static_cast<hipStream_t>(stream))
       return bfail(b, PNGF_EINVAL, "every handle must be bound to the batch stream");
     npl = std::max(npl, h->npl);

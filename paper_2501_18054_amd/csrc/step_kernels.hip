@@ -17,19 +17,23 @@
 //     p_i = C0^-1[i,:] . g_m + sum_k alpha_k p_k[m] p_k[i],
 //     tau_i += alpha p_i^2   (reciprocity: (G q)_i = p_i),      (N_d^2 x 8 B)
 // with p appended to the panel; E, R', tau stay FP64.
+// R-form (reduced exact scoring): by reciprocity T = C^-1 G is symmetric and
+// the accept of m changes it by alpha p p^T with p = T[:, m], so
+//     p_i = T0[m, i] + sum_k alpha_k p_k[m] p_k[i],   tau_i += alpha p_i^2,
+// with T0 = C^-1 G of the run start and the p_k kept in an FP64 panel: a
+// step moves O(N_d k) bytes instead of O(N_d^2), all in FP64.
 #include "dev_state.h"
 
 namespace pngf {
 
 __device__ __forceinline__ z64 up32(z32 a) { return {double(a.re), double(a.im)}; }
 
-// Decision context shared by a workgroup.
-struct StepCtx {
-  int m, dpar, slot;
-  int cs, cp, ns;     // cursor of the new state
-  double f, eta;
-  z64 alpha[kMaxFreq], Em[kMaxFreq], Rpm[kMaxFreq], x[kMaxFreq];
-};
+// The preloaded value for frequency 0, else a load (by value: selecting
+// between a local and a global lvalue would force the local into scratch).
+__device__ __forceinline__ z64 pick0(int f, z64 pre, const z64* p) {
+  if (f == 0) return pre;
+  return *p;
+}
 
 // Scalar view of the fields a step changes (a local copy of the whole state
 // would live in scratch memory).
@@ -38,6 +42,16 @@ struct StepScalars {
   int32_t n_since, kpanel, exact, flips;
   int64_t attempts;
   double f, eta;
+};
+
+// Decision context shared by a workgroup (LDS), including the changed scalars
+// of the next state for the publishing workgroup.
+struct StepCtx {
+  int m, dpar, slot;
+  int cs, cp, ns;     // cursor of the new state
+  double f, eta;
+  z64 alpha[kMaxFreq], Em[kMaxFreq], Rpm[kMaxFreq], x[kMaxFreq];
+  StepScalars st;
 };
 
 // Decode the minimum key of the previous step into an accepted pixel and
@@ -82,10 +96,9 @@ __device__ __forceinline__ uint32_t step_key(const ProbDev& P, const StepCtx& c,
   return kNoKey;
 }
 
-// Thread 0: read the state of this step, decide, fill the context; workgroup 0
-// publishes the next state and clears the key slot two steps ahead.
+// Thread 0: read the state of this step, decide, fill the context.
 __device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool mixed,
-                                   StepCtx& c, bool publish) {
+                                   StepCtx& c) {
   const DbsState* sin = spar ? P.stB : P.st;
   DbsState* sout = spar ? P.st : P.stB;
   StepScalars st;
@@ -158,11 +171,25 @@ __device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool m
   c.ns = st.n_sweeps;
   c.f = st.f;
   c.eta = st.eta;
-  if (publish) {
-    // next state: copy, then overwrite what this step changed
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(sin);
-    uint64_t* dst = reinterpret_cast<uint64_t*>(sout);
-    for (int w = 0; w < int(sizeof(DbsState) / 8); ++w) dst[w] = src[w];
+  c.st = st;
+}
+
+// The publishing workgroup (all its threads, after the barrier that follows
+// step_decide): the next state is the input state with this step's changes;
+// the copy is spread over the workgroup, the changes written by thread 0.
+// Also clears the key slot two steps ahead and logs the accept.
+__device__ inline void step_publish(const ProbDev& P, int spar, int kslot, bool mixed,
+                                    const StepCtx& c) {
+  const DbsState* sin = spar ? P.stB : P.st;
+  DbsState* sout = spar ? P.st : P.stB;
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(sin);
+  uint64_t* dst = reinterpret_cast<uint64_t*>(sout);
+  constexpr int nw = int(sizeof(DbsState) / 8);
+  for (int w = threadIdx.x; w < nw; w += blockDim.x) dst[w] = src[w];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const StepScalars& st = c.st;
+    const int m = c.m, slot = c.slot;
     sout->done = st.done;
     sout->need_refresh = st.need_refresh;
     sout->cursor_s = st.cursor_s;
@@ -233,9 +260,10 @@ __device__ inline void plain_step_row(const ProbDev& P, int i, int spar, int ksl
     b0 = bin[i];
     e0 = (dp ? P.EB[0] : P.E[0])[i];
     r0 = (dp ? P.RpB[0] : P.Rp[0])[i];
-    step_decide(P, spar, kslot, false, c, i == 0);
+    step_decide(P, spar, kslot, false, c);
   }
   __syncthreads();
+  if (i == 0) step_publish(P, spar, kslot, false, c);
   const int m = c.m;
   if (m < 0) return;
   const uint8_t bit = b0 ^ (i == m ? 1 : 0);
@@ -276,8 +304,8 @@ __device__ inline void plain_step_row(const ProbDev& P, int i, int spar, int ksl
     }
     const z64 tau = block_zsum(acc, red);
     if (tid == 0) {
-      const z64 Ein = f == 0 ? e0 : (dp ? P.EB[f] : P.E[f])[i];
-      const z64 Rin = f == 0 ? r0 : (dp ? P.RpB[f] : P.Rp[f])[i];
+      const z64 Ein = pick0(f, e0, (dp ? P.EB[f] : P.E[f]) + i);
+      const z64 Rin = pick0(f, r0, (dp ? P.RpB[f] : P.Rp[f]) + i);
       const z64 Ei = zadd(Ein, zmul(ap, c.Em[f]));
       const z64 Rpi = zadd(Rin, zmul(ap, c.Rpm[f]));
       (dp ? P.E[f] : P.EB[f])[i] = Ei;
@@ -318,9 +346,10 @@ __device__ inline void mixed_step_row(const ProbDev& P, int i, int spar, int ksl
     e0 = (spar ? P.EB[0] : P.E[0])[i];
     r0 = (spar ? P.RpB[0] : P.Rp[0])[i];
     t0 = (spar ? P.tauB[0] : P.tau[0])[i];
-    step_decide(P, spar, kslot, true, c, i == 0);
+    step_decide(P, spar, kslot, true, c);
   }
   __syncthreads();
+  if (i == 0) step_publish(P, spar, kslot, true, c);
   const int m = c.m;
   if (m < 0) return;
   const int slot = c.slot;
@@ -370,9 +399,9 @@ __device__ inline void mixed_step_row(const ProbDev& P, int i, int spar, int ksl
       P.Pp[f][size_t(slot) * P.ld + i] = z32{pr, pi};
       const z64 p = {double(pr), double(pi)};
       const z64 ap = zmul(c.alpha[f], p);
-      const z64 Ein = f == 0 ? e0 : (dp ? P.EB[f] : P.E[f])[i];
-      const z64 Rin = f == 0 ? r0 : (dp ? P.RpB[f] : P.Rp[f])[i];
-      const z64 Tin = f == 0 ? t0 : (dp ? P.tauB[f] : P.tau[f])[i];
+      const z64 Ein = pick0(f, e0, (dp ? P.EB[f] : P.E[f]) + i);
+      const z64 Rin = pick0(f, r0, (dp ? P.RpB[f] : P.Rp[f]) + i);
+      const z64 Tin = pick0(f, t0, (dp ? P.tauB[f] : P.tau[f]) + i);
       const z64 Ei = zadd(Ein, zmul(ap, c.Em[f]));
       const z64 Rpi = zadd(Rin, zmul(ap, c.Rpm[f]));
       const z64 tau = zadd(Tin, zmul(ap, p));
@@ -461,6 +490,125 @@ __global__ __launch_bounds__(256) void k_fold_q(ProbDev P, int f, int kp) {
   }
 }
 
+// R-form step: 64 rows per workgroup, one row per lane; the four waves split
+// the panel sum over slots (fixed combination order).
+constexpr int kRRows = 64;
+constexpr int kRCoef = 256;   // panel coefficients staged in LDS at a time
+
+__global__ __launch_bounds__(256) void k_rform_step(ProbDev P, int spar, int kslot) {
+  __shared__ StepCtx c;
+  __shared__ z64 cf[kRCoef];
+  __shared__ z64 part[4][kRRows];
+  const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+  const int i = blockIdx.x * kRRows + lane;
+  const bool own = (q == 0) && (i < P.nd);
+  const int dp = spar;
+  // this row's vectors do not depend on the decision
+  z64 e0{0.0, 0.0}, r0{0.0, 0.0}, t0{0.0, 0.0};
+  uint8_t b0 = 0;
+  if (own) {
+    b0 = (dp ? P.bitsB : P.bits)[i];
+    e0 = (dp ? P.EB[0] : P.E[0])[i];
+    r0 = (dp ? P.RpB[0] : P.Rp[0])[i];
+    t0 = (dp ? P.tauB[0] : P.tau[0])[i];
+  }
+  if (tid == 0) step_decide(P, spar, kslot, true, c);
+  __syncthreads();
+  if (blockIdx.x == 0) step_publish(P, spar, kslot, true, c);
+  const int m = c.m;
+  if (m < 0) return;
+  const int slot = c.slot;
+  const uint8_t bit = b0 ^ (i == m ? 1 : 0);
+  const double delta = bit ? -P.deps : P.deps;
+  double df = 0.0, bnd = 0.0;
+  for (int f = 0; f < P.nfreq; ++f) {
+    const z64* U = P.Up[f];
+    z64 acc{0.0, 0.0};
+    for (int j0 = 0; j0 < slot; j0 += kRCoef) {
+      const int nj = min(kRCoef, slot - j0);
+      __syncthreads();   // the previous chunk of coefficients is consumed
+      for (int j = tid; j < nj; j += 256)
+        cf[j] = zmul(P.alph[f][j0 + j], U[size_t(j0 + j) * P.ld + m]);
+      __syncthreads();
+      if (i < P.nd)
+        for (int j = q; j < nj; j += 4) acc = zfma(cf[j], U[size_t(j0 + j) * P.ld + i], acc);
+    }
+    part[q][lane] = acc;
+    __syncthreads();
+    if (own) {
+      const z64 s01 = zadd(part[0][lane], part[1][lane]);
+      const z64 s23 = zadd(part[2][lane], part[3][lane]);
+      const z64 p = zadd(P.T0[f][size_t(m) * P.ld + i], zadd(s01, s23));
+      P.Up[f][size_t(slot) * P.ld + i] = p;
+      const z64 ap = zmul(c.alpha[f], p);
+      const z64 Ein = pick0(f, e0, (dp ? P.EB[f] : P.E[f]) + i);
+      const z64 Rin = pick0(f, r0, (dp ? P.RpB[f] : P.Rp[f]) + i);
+      const z64 Tin = pick0(f, t0, (dp ? P.tauB[f] : P.tau[f]) + i);
+      const z64 Ei = zadd(Ein, zmul(ap, c.Em[f]));
+      const z64 Rpi = zadd(Rin, zmul(ap, c.Rpm[f]));
+      const z64 tau = zadd(Tin, zmul(ap, p));
+      (dp ? P.E[f] : P.EB[f])[i] = Ei;
+      (dp ? P.Rp[f] : P.RpB[f])[i] = Rpi;
+      (dp ? P.tau[f] : P.tauB[f])[i] = tau;
+      score_terms(P, c, f, tau, Ei, Rpi, delta, df, bnd);
+    }
+    __syncthreads();   // part is reused by the next frequency
+  }
+  if (own) {
+    (dp ? P.bits : P.bitsB)[i] = bit;
+    P.df[i] = df;
+    if (df > c.eta * c.f) {
+      const uint32_t k = step_key(P, c, i);
+      if (k != kNoKey) atomicMin(&P.keys[(kslot + 1) % 3], k);
+    }
+  }
+}
+
+// Scores of every candidate from the maintained tau, E, R' (current A set)
+// into key slot 0: the start of a segment after the panel was folded.
+__global__ __launch_bounds__(256) void k_rform_score(ProbDev P) {
+  __shared__ StepCtx c;
+  if (threadIdx.x == 0) {
+    const DbsState* s = P.st;
+    c.cs = s->cursor_s;
+    c.cp = s->cursor_pos;
+    c.ns = s->n_sweeps;
+    c.f = s->f;
+    c.eta = s->eta;
+    for (int f = 0; f < P.nfreq; ++f) c.x[f] = s->x[f];
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= P.nd) return;
+  const double delta = P.bits[i] ? -P.deps : P.deps;
+  double df = 0.0, bnd = 0.0;
+  for (int f = 0; f < P.nfreq; ++f)
+    score_terms(P, c, f, P.tau[f][i], P.E[f][i], P.Rp[f][i], delta, df, bnd);
+  P.df[i] = df;
+  if (df > c.eta * c.f) {
+    const uint32_t k = step_key(P, c, i);
+    if (k != kNoKey) atomicMin(&P.keys[0], k);
+  }
+}
+
+// Ut[i][k] = alpha_k p_k[i] (N_d x kp), the left factor of the panel fold
+// T0 += Ut U.
+__global__ __launch_bounds__(256) void k_rform_ut(ProbDev P, int f, int kp, z64* Ut) {
+  const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= size_t(P.nd) * kp) return;
+  const int i = int(e / kp), k = int(e % kp);
+  Ut[e] = zmul(P.alph[f][k], P.Up[f][size_t(k) * P.ld + i]);
+}
+
+// T0 rows: G[i,:] for pixels at eps_lo, zero for pixels at eps_hi (the
+// identity columns of C^-1 contribute G[Z,:]; the GEMM adds C^-1[:,S] G[S,:]).
+__global__ __launch_bounds__(256) void k_rform_t0_init(ProbDev P, int f) {
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= P.nd) return;
+  P.T0[f][size_t(i) * P.ld + j] = P.bits[i] ? z64{0.0, 0.0} : P.G[f][size_t(i) * P.ld + j];
+}
+
 // ------------------------------------------------------------------ launchers
 #define PNGF_STEP_SWITCH(KERNEL, npl, ...)                                                      \
   switch (npl) {                                                                               \
@@ -489,6 +637,30 @@ hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int npro
   if (g <= 0) return hipSuccess;
   PNGF_STEP_SWITCH(k_batch_step, npl, dim3(g), dim3(kRowThreads), 0, s, probs, row0, nprob, mixed,
                    step & 1, step % 3)
+  return hipGetLastError();
+}
+
+hipError_t launch_rform_step(const ProbDev& P, int npl, int step, hipStream_t s) {
+  (void)npl;
+  hipLaunchKernelGGL(k_rform_step, dim3((P.nd + kRRows - 1) / kRRows), dim3(256), 0, s, P,
+                     step & 1, step % 3);
+  return hipGetLastError();
+}
+
+hipError_t launch_rform_score(const ProbDev& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_rform_score, dim3((P.nd + 255) / 256), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_rform_ut(const ProbDev& P, int f, int kp, z64* Ut, hipStream_t s) {
+  if (kp <= 0) return hipSuccess;
+  const size_t n = size_t(P.nd) * kp;
+  hipLaunchKernelGGL(k_rform_ut, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, P, f, kp, Ut);
+  return hipGetLastError();
+}
+
+hipError_t launch_rform_t0_init(const ProbDev& P, int f, hipStream_t s) {
+  hipLaunchKernelGGL(k_rform_t0_init, dim3((P.nd + 255) / 256, P.nd), dim3(256), 0, s, P, f);
   return hipGetLastError();
 }
 
