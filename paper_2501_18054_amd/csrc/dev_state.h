@@ -38,6 +38,14 @@ struct DbsState {
   int32_t pad1;
 };
 
+// Optional index maps of a complex GEMM (nullptr = identity):
+//   A[i][k] = A'[ra[i]][ca[k]],  B[k][n] = B'[rb[k]][cb[n]] (transposed form:
+//   B[k][n] = R[rb[n]][cb[k]]),  C'[rc[i]][cc[n]] receives C[i][n].
+struct GemmIdx {
+  const int32_t *ra = nullptr, *ca = nullptr, *rb = nullptr, *cb = nullptr;
+  const int32_t *rc = nullptr, *cc = nullptr;
+};
+
 // Everything a hot-path kernel needs, passed by value (kernel arguments).
 struct ProbDev {
   int32_t nd, ld, nfreq, max_acc;

@@ -28,11 +28,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGemmBK = 16;
 
+
 template <int WM, int WN, bool TRANSB>
 __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A, int lda,
-                                               const int32_t* ca, const z64* B, int ldb,
-                                               const int32_t* rb, z64* C, int ldc, z64 alpha,
-                                               z64 beta, int kchunk, z64* work) {
+                                               const z64* B, int ldb, z64* C, int ldc,
+                                               GemmIdx ix, z64 alpha, z64 beta, int kchunk,
+                                               z64* work) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   __shared__ double sAr[BM][kGemmBK + 1], sAi[BM][kGemmBK + 1];
   __shared__ double sBr[kGemmBK][BN + 1], sBi[kGemmBK][BN + 1];
@@ -50,35 +51,60 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A
       accr[a][b] = d4{0.0, 0.0, 0.0, 0.0};
       acci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     }
-  for (int k0 = kbeg; k0 < kend; k0 += kGemmBK) {
-    for (int e = tid; e < BM * kGemmBK; e += 256) {
+  // the next K chunk is fetched into registers while the current one is
+  // multiplied out of LDS
+  constexpr int kAe = BM * kGemmBK / 256, kBe = BN * kGemmBK / 256;
+  z64 ra[kAe], rbv[kBe];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < kAe; ++q) {
+      const int e = tid + 256 * q;
       const int r = e >> 4, c = e & 15;
       const int gr = m0 + r, gc = k0 + c;
       z64 v{0.0, 0.0};
-      if (gr < M && gc < kend) v = A[size_t(gr) * lda + (ca ? ca[gc] : gc)];
-      sAr[r][c] = v.re;
-      sAi[r][c] = v.im;
+      if (gr < M && gc < kend)
+        v = A[size_t(ix.ra ? ix.ra[gr] : gr) * lda + (ix.ca ? ix.ca[gc] : gc)];
+      ra[q] = v;
     }
-    if (TRANSB) {
-      for (int e = tid; e < BN * kGemmBK; e += 256) {
+#pragma unroll
+    for (int q = 0; q < kBe; ++q) {
+      const int e = tid + 256 * q;
+      z64 v{0.0, 0.0};
+      if (TRANSB) {
         const int n = e >> 4, c = e & 15;
         const int gn = n0 + n, gc = k0 + c;
-        z64 v{0.0, 0.0};
-        if (gn < N && gc < kend) v = B[size_t(rb ? rb[gn] : gn) * ldb + gc];
-        sBr[c][n] = v.re;
-        sBi[c][n] = v.im;
-      }
-    } else {
-      for (int e = tid; e < BN * kGemmBK; e += 256) {
+        if (gn < N && gc < kend)
+          v = B[size_t(ix.rb ? ix.rb[gn] : gn) * ldb + (ix.cb ? ix.cb[gc] : gc)];
+      } else {
         const int r = e / BN, n = e % BN;
         const int gr = k0 + r, gn = n0 + n;
-        z64 v{0.0, 0.0};
-        if (gr < kend && gn < N) v = B[size_t(rb ? rb[gr] : gr) * ldb + gn];
-        sBr[r][n] = v.re;
-        sBi[r][n] = v.im;
+        if (gr < kend && gn < N)
+          v = B[size_t(ix.rb ? ix.rb[gr] : gr) * ldb + (ix.cb ? ix.cb[gn] : gn)];
+      }
+      rbv[q] = v;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kGemmBK) {
+#pragma unroll
+    for (int q = 0; q < kAe; ++q) {
+      const int e = tid + 256 * q;
+      sAr[e >> 4][e & 15] = ra[q].re;
+      sAi[e >> 4][e & 15] = ra[q].im;
+    }
+#pragma unroll
+    for (int q = 0; q < kBe; ++q) {
+      const int e = tid + 256 * q;
+      if (TRANSB) {
+        sBr[e & 15][e >> 4] = rbv[q].re;
+        sBi[e & 15][e >> 4] = rbv[q].im;
+      } else {
+        sBr[e / BN][e % BN] = rbv[q].re;
+        sBi[e / BN][e % BN] = rbv[q].im;
       }
     }
     __syncthreads();
+    if (k0 + kGemmBK < kend) fetch(k0 + kGemmBK);
 #pragma unroll
     for (int kk = 0; kk < kGemmBK; kk += 4) {
       double ar[WM], ai[WM], br[WN], bi[WN];
@@ -120,7 +146,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A
         if (work) {
           work[(size_t(blockIdx.z) * M + row) * N + col] = v;
         } else {
-          z64* c = C + size_t(row) * ldc + col;
+          z64* c = C + size_t(ix.rc ? ix.rc[row] : row) * ldc + (ix.cc ? ix.cc[col] : col);
           const z64 av = zmul(alpha, v);
           *c = beta0 ? av : zfma(beta, *c, av);
         }
@@ -129,13 +155,14 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A
 
 // C = beta C + alpha sum_z work[z] (fixed summation order).
 __global__ __launch_bounds__(256) void k_zgemm_reduce(int M, int N, int nz, const z64* work,
-                                                      z64* C, int ldc, z64 alpha, z64 beta) {
+                                                      z64* C, int ldc, GemmIdx ix, z64 alpha,
+                                                      z64 beta) {
   const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
   if (e >= size_t(M) * N) return;
   const int row = int(e / N), col = int(e % N);
   z64 s{0.0, 0.0};
   for (int z = 0; z < nz; ++z) s = zadd(s, work[size_t(z) * M * N + e]);
-  z64* c = C + size_t(row) * ldc + col;
+  z64* c = C + size_t(ix.rc ? ix.rc[row] : row) * ldc + (ix.cc ? ix.cc[col] : col);
   const z64 av = zmul(alpha, s);
   *c = (beta.re == 0.0 && beta.im == 0.0) ? av : zfma(beta, *c, av);
 }
@@ -254,12 +281,11 @@ __global__ __launch_bounds__(256) void k_small_inverse(z64* A, int k, int32_t* s
 }
 
 // ------------------------------------------------------------------ launchers
-// C = beta C + alpha A op(B); A[i][k] = A'[i][ca ? ca[k] : k]; transb:
-// B[k][n] = R[rb ? rb[n] : n][k], else B[k][n] = B'[rb ? rb[k] : k][n].
+// C = beta C + alpha A op(B) with the index maps of ix (see GemmIdx).
 // work (>= splits * M * N entries) is used when splits > 1.
-hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_t* ca,
-                        const z64* B, int ldb, bool transb, const int32_t* rb, z64* C, int ldc,
-                        z64 alpha, z64 beta, int splits, z64* work, hipStream_t s) {
+hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
+                           bool transb, z64* C, int ldc, const GemmIdx& ix, z64 alpha, z64 beta,
+                           int splits, z64* work, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (K <= 0) return hipErrorInvalidValue;
   splits = std::max(1, std::min(splits, (K + kGemmBK - 1) / kGemmBK));
@@ -272,26 +298,37 @@ hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_
   if (big) {
     dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
     if (transb)
-      hipLaunchKernelGGL((k_zgemm<2, 2, true>), grid, dim3(256), 0, s, M, N, K, A, lda, ca, B,
-                         ldb, rb, C, ldc, alpha, beta, kchunk, wk);
+      hipLaunchKernelGGL((k_zgemm<2, 2, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
+                         ldc, ix, alpha, beta, kchunk, wk);
     else
-      hipLaunchKernelGGL((k_zgemm<2, 2, false>), grid, dim3(256), 0, s, M, N, K, A, lda, ca, B,
-                         ldb, rb, C, ldc, alpha, beta, kchunk, wk);
+      hipLaunchKernelGGL((k_zgemm<2, 2, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
+                         ldc, ix, alpha, beta, kchunk, wk);
   } else {
     dim3 grid((N + 31) / 32, (M + 31) / 32, splits);
     if (transb)
-      hipLaunchKernelGGL((k_zgemm<1, 1, true>), grid, dim3(256), 0, s, M, N, K, A, lda, ca, B,
-                         ldb, rb, C, ldc, alpha, beta, kchunk, wk);
+      hipLaunchKernelGGL((k_zgemm<1, 1, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
+                         ldc, ix, alpha, beta, kchunk, wk);
     else
-      hipLaunchKernelGGL((k_zgemm<1, 1, false>), grid, dim3(256), 0, s, M, N, K, A, lda, ca, B,
-                         ldb, rb, C, ldc, alpha, beta, kchunk, wk);
+      hipLaunchKernelGGL((k_zgemm<1, 1, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
+                         ldc, ix, alpha, beta, kchunk, wk);
   }
   if (splits > 1) {
     const size_t n = size_t(M) * N;
     hipLaunchKernelGGL(k_zgemm_reduce, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, M, N,
-                       splits, work, C, ldc, alpha, beta);
+                       splits, work, C, ldc, ix, alpha, beta);
   }
   return hipGetLastError();
+}
+
+// Common case: column gather of A (ca) and row gather of B (rb: rows of R
+// by n when transb, rows of B by k otherwise).
+hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_t* ca,
+                        const z64* B, int ldb, bool transb, const int32_t* rb, z64* C, int ldc,
+                        z64 alpha, z64 beta, int splits, z64* work, hipStream_t s) {
+  GemmIdx ix;
+  ix.ca = ca;
+  ix.rb = rb;
+  return launch_zgemm_ix(M, N, K, A, lda, B, ldb, transb, C, ldc, ix, alpha, beta, splits, work, s);
 }
 
 hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int k, int n, z64* dst,

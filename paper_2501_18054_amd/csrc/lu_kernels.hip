@@ -32,6 +32,10 @@
 
 namespace pngf {
 
+hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
+                           bool transb, z64* C, int ldc, const GemmIdx& ix, z64 alpha, z64 beta,
+                           int splits, z64* work, hipStream_t s);
+
 constexpr int kGjNb = 16;
 constexpr int kUpdRows = 16;
 constexpr int kTsRows = 1024;              // candidate rows per tournament group
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(256) void k_gj_invperm(const int32_t* piv, int32_t*
 
 // C^-1 rows of S: C^-1[s_a, j] = K^-1[a, pos[j]] = M[p_a][inv_p[pos[j]]] for
 // j in S, 0 otherwise.  Rows of Z: identity on Z columns (the S columns come
-// from k_zrows).  One row per blockIdx.y.
+// from the Z-rows GEMM).  One row per blockIdx.y.
 __global__ __launch_bounds__(256) void k_scatter_inverse(const z64* M, z64* Cinv, int ld, int nd,
                                                          const int32_t* pos, const int32_t* piv,
                                                          const int32_t* inv_p) {
@@ -294,57 +298,6 @@ __global__ __launch_bounds__(256) void k_scatter_inverse(const z64* M, z64* Cinv
     Cinv[size_t(i) * ld + j] = v;
   } else if (bj < 0) {
     Cinv[size_t(i) * ld + j] = z64{i == j ? 1.0 : 0.0, 0.0};
-  }
-}
-
-// Z rows, S columns: C^-1[z_c, s_b] = k2d sum_a G[z_c, s_a] K^-1[a, b], with
-// K^-1[a, b] read from the S rows of C^-1 already written (C^-1[s_a, s_b]).
-// 64x64 output tile per workgroup, 4x4 per thread, k-steps of 16 through LDS.
-__global__ __launch_bounds__(256) void k_zrows(const z64* G, z64* Cinv, int ld, const int32_t* sidx,
-                                               const int32_t* zidx, int ns, int nz, double k2d) {
-  __shared__ z64 As[64][17];
-  __shared__ z64 Bs[16][65];
-  const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;
-  const int c0 = blockIdx.y * 64, b0 = blockIdx.x * 64;
-  z64 acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = z64{0.0, 0.0};
-  for (int a0 = 0; a0 < ns; a0 += 16) {
-    for (int e = tid; e < 64 * 16; e += 256) {
-      const int r = e / 16, k = e % 16;
-      const int zc = c0 + r, a = a0 + k;
-      As[r][k] = (zc < nz && a < ns) ? G[size_t(zidx[zc]) * ld + sidx[a]] : z64{0.0, 0.0};
-      const int k2 = e / 64, cb = e % 64;
-      const int a2 = a0 + k2, b = b0 + cb;
-      Bs[k2][cb] = (a2 < ns && b < ns) ? Cinv[size_t(sidx[a2]) * ld + sidx[b]] : z64{0.0, 0.0};
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      z64 av[4], bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = As[tr + 16 * u][k];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = Bs[k][tc + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = zfma(av[u], bv[v], acc[u][v]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int zc = c0 + tr + 16 * u;
-    if (zc >= nz) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = b0 + tc + 16 * v;
-      if (b < ns) Cinv[size_t(zidx[zc]) * ld + sidx[b]] = zscale(acc[u][v], k2d);
-    }
   }
 }
 
@@ -445,10 +398,21 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
   }
   const dim3 grow((nd + 255) / 256, nd);
   hipLaunchKernelGGL(k_scatter_inverse, grow, dim3(256), 0, s, S, Cinv, ld, nd, pos, piv, inv_p);
-  if (ns > 0 && nz > 0)
-    hipLaunchKernelGGL(k_zrows, dim3((ns + 63) / 64, (nz + 63) / 64), dim3(256), 0, s, G, Cinv, ld,
-                       sidx, zidx, ns, nz, k2d);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ns > 0 && nz > 0) {
+    // C^-1[Z, S] = k2d G[Z, S] C^-1[S, S] on the FP64 matrix cores
+    GemmIdx ix;
+    ix.ra = zidx;
+    ix.ca = sidx;
+    ix.rb = sidx;
+    ix.cb = sidx;
+    ix.rc = zidx;
+    ix.cc = sidx;
+    e = launch_zgemm_ix(nz, ns, ns, G, ld, Cinv, ld, false, Cinv, ld, ix, z64{k2d, 0.0},
+                        z64{0.0, 0.0}, 1, nullptr, s);
+  }
+  return e;
 }
 
 hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t* bits, double ds,

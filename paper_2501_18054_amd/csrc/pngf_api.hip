@@ -736,7 +736,7 @@ int run_rform(pngf_handle* h, pngf::DbsState* pinned) {
   st = start_segment(h);   // tau of the start state (from C^-1) and the first keys
   if (st) return st;
   h->cinv_stale = true;
-  const int batch = 32;
+  const int batch = 64;   // steps are cheap: fewer host checks
   const int64_t max_rounds = 4 * int64_t(h->opt.max_accepts) + 64;
   int64_t t = 0;
   for (int64_t round = 0; round < max_rounds; ++round) {
