@@ -8,7 +8,21 @@ namespace pngf {
 
 constexpr int kMaxFreq = 8;
 constexpr int kRowThreads = 256;   // one workgroup streams one matrix row
+constexpr int kMixRows = 8;        // rows per workgroup of the mixed step (two per wave)
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+
+// Visiting keys: the place of a candidate in the visiting order (its
+// position in the current sweep, or N_d + its position in the next sweep) in
+// the high bits and the pixel in the low kKeyPixBits, so the minimum key
+// names its pixel without a lookup.
+constexpr int kKeyPixBits = 14;
+constexpr uint32_t kKeyPixMask = (1u << kKeyPixBits) - 1u;
+constexpr int kMaxPixels = 1 << kKeyPixBits;
+__device__ __forceinline__ uint32_t pack_key(int vis, int pixel) {
+  return (uint32_t(vis) << kKeyPixBits) | uint32_t(pixel);
+}
+__device__ __forceinline__ int key_vis(uint32_t k) { return int(k >> kKeyPixBits); }
+__device__ __forceinline__ int key_pixel(uint32_t k) { return int(k & kKeyPixMask); }
 
 struct z64 { double re, im; };
 struct z32 { float re, im; };

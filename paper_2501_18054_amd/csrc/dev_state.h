@@ -46,6 +46,17 @@ struct GemmIdx {
   const int32_t *rc = nullptr, *cc = nullptr;
 };
 
+// One output of a two-product GEMV pass:
+//   y[i] = beta w[i] + gamma w2[i] + alpha sum_j A[i,j] d_j v[j].
+struct GemvOut {
+  const z64* v;
+  z64 alpha, beta;
+  const z64* w;
+  double gamma;
+  const z64* w2;
+  z64* y;
+};
+
 // Everything a hot-path kernel needs, passed by value (kernel arguments).
 struct ProbDev {
   int32_t nd, ld, nfreq, max_acc;

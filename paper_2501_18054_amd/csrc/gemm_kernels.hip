@@ -198,14 +198,15 @@ __global__ __launch_bounds__(256) void k_wood_cap(const z64* P, int ldp, const i
 // column interchanges they imply are undone at the end in reverse order.
 // One workgroup; the matrix lives in LDS.  status is set on a zero pivot.
 constexpr int kSmallInv = 64;
+constexpr int kSmallInvThreads = 256;
 
-__global__ __launch_bounds__(256) void k_small_inverse(z64* A, int k, int32_t* status) {
+__global__ __launch_bounds__(kSmallInvThreads) void k_small_inverse(z64* A, int k, int32_t* status) {
   __shared__ double Mr[kSmallInv][kSmallInv + 1], Mi[kSmallInv][kSmallInv + 1];
   __shared__ double fr[kSmallInv], fi[kSmallInv];
   __shared__ int perm[kSmallInv];
   __shared__ int s_p;
   const int tid = threadIdx.x;
-  for (int e = tid; e < k * k; e += 256) {
+  for (int e = tid; e < k * k; e += kSmallInvThreads) {
     Mr[e / k][e % k] = A[e].re;
     Mi[e / k][e % k] = A[e].im;
   }
@@ -237,23 +238,23 @@ __global__ __launch_bounds__(256) void k_small_inverse(z64* A, int k, int32_t* s
     __syncthreads();
     const int p = s_p;
     if (p != c)
-      for (int j = tid; j < k; j += 256) {
+      for (int j = tid; j < k; j += kSmallInvThreads) {
         double t = Mr[c][j]; Mr[c][j] = Mr[p][j]; Mr[p][j] = t;
         t = Mi[c][j]; Mi[c][j] = Mi[p][j]; Mi[p][j] = t;
       }
     __syncthreads();
     // pivot row: M[c][c] <- 1 / piv, M[c][j] <- M[c][j] / piv; save column c
     const z64 inv = zdiv(z64{1.0, 0.0}, z64{Mr[c][c], Mi[c][c]});
-    for (int r = tid; r < k; r += 256) { fr[r] = Mr[r][c]; fi[r] = Mi[r][c]; }
+    for (int r = tid; r < k; r += kSmallInvThreads) { fr[r] = Mr[r][c]; fi[r] = Mi[r][c]; }
     __syncthreads();
-    for (int j = tid; j < k; j += 256) {
+    for (int j = tid; j < k; j += kSmallInvThreads) {
       const z64 v = (j == c) ? inv : zmul(z64{Mr[c][j], Mi[c][j]}, inv);
       Mr[c][j] = v.re;
       Mi[c][j] = v.im;
     }
     __syncthreads();
     // other rows: M[r][j] <- (j == c ? 0 : M[r][j]) - f_r M[c][j]
-    for (int e = tid; e < k * k; e += 256) {
+    for (int e = tid; e < k * k; e += kSmallInvThreads) {
       const int r = e / k, j = e % k;
       if (r == c) continue;
       const z64 pr{Mr[c][j], Mi[c][j]};
@@ -268,13 +269,13 @@ __global__ __launch_bounds__(256) void k_small_inverse(z64* A, int k, int32_t* s
   for (int c = k - 1; c >= 0; --c) {
     const int p = perm[c];
     if (p != c)
-      for (int r = tid; r < k; r += 256) {
+      for (int r = tid; r < k; r += kSmallInvThreads) {
         double t = Mr[r][c]; Mr[r][c] = Mr[r][p]; Mr[r][p] = t;
         t = Mi[r][c]; Mi[r][c] = Mi[r][p]; Mi[r][p] = t;
       }
     __syncthreads();
   }
-  for (int e = tid; e < k * k; e += 256) {
+  for (int e = tid; e < k * k; e += kSmallInvThreads) {
     A[e].re = Mr[e / k][e % k];
     A[e].im = Mi[e / k][e % k];
   }
@@ -352,7 +353,7 @@ hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, con
 hipError_t launch_small_inverse(z64* A, int k, int32_t* status, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   if (k > kSmallInv) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_small_inverse, dim3(1), dim3(256), 0, s, A, k, status);
+  hipLaunchKernelGGL(k_small_inverse, dim3(1), dim3(kSmallInvThreads), 0, s, A, k, status);
   return hipGetLastError();
 }
 

@@ -326,6 +326,35 @@ __global__ __launch_bounds__(kRowThreads) void k_gemv(const z64* A, int ld, int 
   }
 }
 
+// Two products with one pass over A: for o in {o1, o2},
+// o.y[i] = o.beta o.w[i] + o.gamma o.w2[i] + o.alpha sum_j A[i,j] d_j o.v[j]
+// (d as in k_gemv).  o.y may alias o.w.
+__global__ __launch_bounds__(kRowThreads) void k_gemv2(const z64* A, int ld, int n,
+                                                       const uint8_t* bits, double ds, GemvOut o1,
+                                                       GemvOut o2) {
+  __shared__ double red[2 * (kRowThreads / 64)];
+  const int i = blockIdx.x;
+  const z64* a = A + size_t(i) * ld;
+  z64 acc1{0.0, 0.0}, acc2{0.0, 0.0};
+  for (int j = threadIdx.x; j < n; j += kRowThreads) {
+    const double dj = bits ? (bits[j] ? ds : 0.0) : 1.0;
+    const z64 aj = a[j];
+    acc1 = zfma(aj, zscale(o1.v[j], dj), acc1);
+    acc2 = zfma(aj, zscale(o2.v[j], dj), acc2);
+  }
+  const z64 s1 = block_zsum(acc1, red);
+  const z64 s2 = block_zsum(acc2, red);
+  if (threadIdx.x == 0) {
+    for (int h = 0; h < 2; ++h) {
+      const GemvOut& o = h ? o2 : o1;
+      z64 out = zmul(o.alpha, h ? s2 : s1);
+      if (o.w) out = zfma(o.beta, o.w[i], out);
+      if (o.w2) out = zadd(out, zscale(o.w2[i], o.gamma));
+      o.y[i] = out;
+    }
+  }
+}
+
 // x = x_b + k0^2 sum_j god[j] deps_j E[j]; writes x into the DBS state slot f
 // and (on the last frequency) the objective.  One workgroup.
 __global__ __launch_bounds__(kRowThreads) void k_output(ProbDev P, int f, const z64* god, z64 xb,
@@ -420,6 +449,12 @@ hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t*
                        hipStream_t s) {
   hipLaunchKernelGGL(k_gemv, dim3(n), dim3(kRowThreads), 0, s, A, ld, n, v, bits, ds, alpha, beta,
                      w, gamma, w2, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv2(const z64* A, int ld, int n, const uint8_t* bits, double ds,
+                        const GemvOut& o1, const GemvOut& o2, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv2, dim3(n), dim3(kRowThreads), 0, s, A, ld, n, bits, ds, o1, o2);
   return hipGetLastError();
 }
 

@@ -20,15 +20,6 @@ namespace pngf {
 __device__ __forceinline__ z64 up(z32 a) { return {double(a.re), double(a.im)}; }
 __device__ __forceinline__ z32 down(z64 a) { return {float(a.re), float(a.im)}; }
 
-__device__ __forceinline__ uint32_t mkey(const ProbDev& P, const DbsState* st, int i) {
-  const int s = st->cursor_s;
-  if (s >= st->n_sweeps) return kNoKey;
-  const int pos = P.rank[size_t(s) * P.nd + i];
-  if (pos >= st->cursor_pos) return uint32_t(pos);
-  if (s + 1 < st->n_sweeps) return uint32_t(P.nd + P.rank[size_t(s + 1) * P.nd + i]);
-  return kNoKey;
-}
-
 // C0^-1 <- complex FP32 copy of a complex FP64 matrix (nd x ld rows).
 __global__ __launch_bounds__(256) void k_to_c64(const z64* src, z32* dst, int nd, int ld) {
   const int i = blockIdx.y;

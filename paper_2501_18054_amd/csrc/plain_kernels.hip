@@ -26,8 +26,8 @@ __device__ __forceinline__ uint32_t cand_key(const ProbDev& P, const DbsState* s
   const int s = st->cursor_s;
   if (s >= st->n_sweeps) return kNoKey;
   const int pos = P.rank[size_t(s) * P.nd + i];
-  if (pos >= st->cursor_pos) return uint32_t(pos);
-  if (s + 1 < st->n_sweeps) return uint32_t(P.nd + P.rank[size_t(s + 1) * P.nd + i]);
+  if (pos >= st->cursor_pos) return pack_key(pos, i);
+  if (s + 1 < st->n_sweeps) return pack_key(P.nd + P.rank[size_t(s + 1) * P.nd + i], i);
   return kNoKey;
 }
 
@@ -107,15 +107,15 @@ __global__ __launch_bounds__(kRowThreads) void k_select_prep(ProbDev P, int forc
           st->sweeps = s + 1 + (next ? 1 : 0);
           st->done = 1;
         } else {
-          int s2 = s, pos = int(key);
-          if (int(key) >= nd) {
+          int s2 = s, pos = key_vis(key);
+          if (pos >= nd) {
             s2 = s + 1;
-            pos = int(key) - nd;
+            pos -= nd;
             st->attempts += (nd - c) + pos + 1;
           } else {
             st->attempts += pos - c + 1;
           }
-          m = P.perm[size_t(s2) * nd + pos];
+          m = key_pixel(key);
           st->sweeps = s2 + 1;
           if (pos + 1 < nd) {
             st->cursor_s = s2;
@@ -291,6 +291,20 @@ __global__ __launch_bounds__(1024) void k_pick_best(const double* df, const int3
   }
 }
 
+// Start of a search segment: every key slot empty; with reset_panel also an
+// empty panel and exact (FP64-derived) scores, no pending update.
+__global__ void k_segment_start(DbsState* st, uint32_t* keys, int reset_panel) {
+  if (threadIdx.x < 6) keys[threadIdx.x] = kNoKey;
+  if (threadIdx.x == 0 && reset_panel) {
+    st->m = -1;
+    st->kpanel = 0;
+    st->n_since = 0;
+    st->exact = 1;
+    st->need_refresh = 0;
+    st->flips = 0;
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 #define PNGF_NPL_SWITCH(npl, CALL) \
   switch (npl) {                   \
@@ -309,6 +323,11 @@ hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int
 #define L_(N) hipLaunchKernelGGL(k_score_rows<N>, dim3(ncand), dim3(kRowThreads), 0, s, P, cand, ncand, keyp)
   PNGF_NPL_SWITCH(npl, L_)
 #undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_start(const ProbDev& P, int reset_panel, hipStream_t s) {
+  hipLaunchKernelGGL(k_segment_start, dim3(1), dim3(64), 0, s, P.st, P.keys, reset_panel);
   return hipGetLastError();
 }
 

@@ -24,6 +24,8 @@ hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
                              int grid, int npl, int mixed, int step, hipStream_t s);
 hipError_t launch_accept_only(const ProbDev& P, int npl, hipStream_t s);
+hipError_t launch_gemv2(const z64* A, int ld, int n, const uint8_t* bits, double ds,
+                        const GemvOut& o1, const GemvOut& o2, hipStream_t s);
 hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_t* ca,
                         const z64* B, int ldb, bool transb, const int32_t* rb, z64* C, int ldc,
                         z64 alpha, z64 beta, int splits, z64* work, hipStream_t s);
@@ -44,6 +46,7 @@ hipError_t launch_features(const ProbDev& P, int H, int W, float* X, hipStream_t
 int model_hw(pngf_model* m, int* H, int* W);
 hipStream_t model_stream(pngf_model* m);
 hipError_t launch_select_prep(const ProbDev& P, int forced, hipStream_t s);
+hipError_t launch_segment_start(const ProbDev& P, int reset_panel, hipStream_t s);
 hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const int32_t* sidx,
                           const int32_t* zidx, const int32_t* pos, int ns, double k2d, z64* B1,
@@ -202,7 +205,7 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_wW = take(kw * nd * sizeof(z64));
     L.off_wCap = take(kw * kw * sizeof(z64));
     L.off_wF = take(kw * sizeof(int32_t));
-    L.off_wS = take(kw * sizeof(double));
+    L.off_wS = take(size_t(F) * kw * sizeof(double));
     L.off_wWork = take(size_t(pngf::kWoodSplits) * nd * kw * sizeof(z64));
   }
   L.off_S = take(mat);
@@ -299,16 +302,14 @@ int reform_fields(pngf_handle* h) {
     // E = C^-1 b
     HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, b, nullptr, 0.0, one, zero, nullptr, 0.0,
                                 nullptr, P.E[f], h->stream));
-    // r = b - E + k0^2 G diag(deps) E ;  E += C^-1 r
-    HIPCHK(h, pngf::launch_gemv(P.G[f], ld, nd, P.E[f], P.bits, P.deps, z64{k2, 0.0}, one, b,
-                                -1.0, P.E[f], r, h->stream));
-    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, r, nullptr, 0.0, one, one, P.E[f], 0.0,
-                                nullptr, P.E[f], h->stream));
-    // u = G diag(deps) G_OD ; R' = G_OD + k0^2 C^-1 u
-    HIPCHK(h, pngf::launch_gemv(P.G[f], ld, nd, god, P.bits, P.deps, one, zero, nullptr, 0.0,
-                                nullptr, u, h->stream));
-    HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, u, nullptr, 0.0, z64{k2, 0.0}, one, god, 0.0,
-                                nullptr, P.Rp[f], h->stream));
+    // one pass over G:  r = b - E + k0^2 G diag(deps) E,  u = G diag(deps) G_OD
+    const pngf::GemvOut o_r{P.E[f], z64{k2, 0.0}, one, b, -1.0, P.E[f], r};
+    const pngf::GemvOut o_u{god, one, zero, nullptr, 0.0, nullptr, u};
+    HIPCHK(h, pngf::launch_gemv2(P.G[f], ld, nd, P.bits, P.deps, o_r, o_u, h->stream));
+    // one pass over C^-1:  E += C^-1 r,  R' = G_OD + k0^2 C^-1 u
+    const pngf::GemvOut o_e{r, one, one, P.E[f], 0.0, nullptr, P.E[f]};
+    const pngf::GemvOut o_p{u, z64{k2, 0.0}, one, god, 0.0, nullptr, P.Rp[f]};
+    HIPCHK(h, pngf::launch_gemv2(P.Cinv[f], ld, nd, nullptr, 0.0, o_e, o_p, h->stream));
     const cd xb = h->pc.freq[f].xb;
     HIPCHK(h, pngf::launch_output(P, f, god, z64{xb.real(), xb.imag()}, f == F - 1, h->stream));
     t.end();
@@ -401,15 +402,15 @@ int fp64_refresh(pngf_handle* h) {
         sc[size_t(f) * k + c] = P.k0sq[f] * (cur[fl[c]] ? P.deps : -P.deps);
     HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
     HIPCHK(h, hipMemcpyAsync(dF, fl.data(), k * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(dS, sc.data(), size_t(F) * k * sizeof(double), hipMemcpyHostToDevice,
+                             h->stream));
     const z64 one{1.0, 0.0}, zero{0.0, 0.0};
     for (int f = 0; f < F; ++f) {
       Timer t(h, KID_WOOD);
-      HIPCHK(h, hipMemcpyAsync(dS, sc.data() + size_t(f) * k, k * sizeof(double),
-                               hipMemcpyHostToDevice, h->stream));
       // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T)
       HIPCHK(h, pngf::launch_zgemm(nd, k, nd, P.Cinv[f], ld, nullptr, P.G[f], ld, true, dF, wP, k,
                                    one, zero, pngf::kWoodSplits, work, h->stream));
-      HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS, cap, h->stream));
+      HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS + size_t(f) * k, cap, h->stream));
       HIPCHK(h, pngf::launch_small_inverse(cap, k, status, h->stream));
       // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
       HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, h->stream));
@@ -418,9 +419,8 @@ int fp64_refresh(pngf_handle* h) {
       HIPCHK(h, pngf::launch_zgemm(nd, nd, k, wP, k, nullptr, wW, nd, false, nullptr, P.Cinv[f],
                                    ld, one, one, 1, nullptr, h->stream));
       t.end();
-      // the host copies above read sc while the stream runs: wait per frequency
-      HIPCHK(h, hipStreamSynchronize(h->stream));
     }
+    // (this wait also ends the host copies' reads of fl and sc)
     int32_t st_host = 0;
     HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -428,8 +428,6 @@ int fp64_refresh(pngf_handle* h) {
   }
   int st = reform_fields(h);
   if (st) return st;
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
   h->bits_ref = cur;
   h->cinv_stale = false;
   return PNGF_OK;
@@ -454,16 +452,14 @@ int write_state(pngf_handle* h, const pngf::DbsState* st) {
 }
 
 
-// Reset the rotating key slots and score every candidate of the current
-// (normalized) state into slot 0; the next step of the search is step 0.
-int start_segment(pngf_handle* h) {
-  const uint32_t none[6] = {pngf::kNoKey, pngf::kNoKey, pngf::kNoKey,
-                            pngf::kNoKey, pngf::kNoKey, pngf::kNoKey};
-  HIPCHK(h, hipMemcpyAsync(h->P.keys, none, sizeof(none), hipMemcpyHostToDevice, h->stream));
+// Reset the rotating key slots (and, if asked, the panel bookkeeping of the
+// state) and score every candidate of the current (normalized) state into
+// slot 0; the next step of the search is step 0.  Stream-ordered, no wait.
+int start_segment(pngf_handle* h, bool reset_panel = false) {
+  HIPCHK(h, pngf::launch_segment_start(h->P, reset_panel ? 1 : 0, h->stream));
   Timer t(h, KID_SCORE);
   HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, h->pc.n_d, h->P.keys, h->stream));
   t.end();
-  HIPCHK(h, hipStreamSynchronize(h->stream));
   return PNGF_OK;
 }
 
@@ -533,18 +529,7 @@ int mixed_refresh(pngf_handle* h, bool measure) {
   if (st) return st;
   for (int f = 0; f < F; ++f)
     HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
-  pngf::DbsState s;
-  st = read_state(h, &s);
-  if (st) return st;
-  s.kpanel = 0;
-  s.n_since = 0;
-  s.exact = 1;
-  s.need_refresh = 0;
-  s.m = -1;
-  s.flips = 0;
-  st = write_state(h, &s);
-  if (st) return st;
-  st = start_segment(h);
+  st = start_segment(h, true);
   if (st) return st;
   if (measure) {
     double* out = at<double>(h, h->lay.off_bandout);
@@ -912,6 +897,7 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   if (o->k_refresh < 0 || o->k_fold < 0) return fail(h, PNGF_EINVAL, "k_refresh and k_fold must be >= 0");
   if (o->max_accepts < 1 || o->max_sweeps < 1)
     return fail(h, PNGF_EINVAL, "max_accepts and max_sweeps must be >= 1");
+  if (h->pc.n_d > pngf::kMaxPixels) return fail(h, PNGF_EINVAL, "at most 16384 design pixels");
   if (reinterpret_cast<uintptr_t>(dev_ws) & 255)
     return fail(h, PNGF_EINVAL, "workspace must be 256-byte aligned");
   Layout L = make_layout(h, o);
@@ -1328,7 +1314,8 @@ int batch_prepare(pngf_batch* b, const std::vector<int>& active, int grid) {
   std::vector<int32_t> row0(1, 0);
   for (int p : active) {
     probs.push_back(b->hs[p]->P);
-    row0.push_back(row0.back() + b->hs[p]->pc.n_d);
+    const int nd = b->hs[p]->pc.n_d;   // work items: rows (FP64), row groups (mixed)
+    row0.push_back(row0.back() + (b->mixed ? (nd + pngf::kMixRows - 1) / pngf::kMixRows : nd));
   }
   const int n = int(active.size());
   if (n == 0) return PNGF_OK;

@@ -68,15 +68,15 @@ __device__ inline int decode_key(StepScalars& st, uint32_t key, const ProbDev& P
     st.done = 1;
     return -1;
   }
-  int s2 = s, pos = int(key);
-  if (int(key) >= nd) {
+  int s2 = s, pos = key_vis(key);
+  if (pos >= nd) {
     s2 = s + 1;
-    pos = int(key) - nd;
+    pos -= nd;
     st.attempts += (nd - c) + pos + 1;
   } else {
     st.attempts += pos - c + 1;
   }
-  const int m = P.perm[size_t(s2) * nd + pos];
+  const int m = key_pixel(key);
   st.sweeps = s2 + 1;
   if (pos + 1 < nd) {
     st.cursor_s = s2;
@@ -91,8 +91,8 @@ __device__ inline int decode_key(StepScalars& st, uint32_t key, const ProbDev& P
 __device__ __forceinline__ uint32_t step_key(const ProbDev& P, const StepCtx& c, int i) {
   if (c.cs >= c.ns) return kNoKey;
   const int pos = P.rank[size_t(c.cs) * P.nd + i];
-  if (pos >= c.cp) return uint32_t(pos);
-  if (c.cs + 1 < c.ns) return uint32_t(P.nd + P.rank[size_t(c.cs + 1) * P.nd + i]);
+  if (pos >= c.cp) return pack_key(pos, i);
+  if (c.cs + 1 < c.ns) return pack_key(P.nd + P.rank[size_t(c.cs + 1) * P.nd + i], i);
   return kNoKey;
 }
 
@@ -324,32 +324,53 @@ __device__ inline void plain_step_row(const ProbDev& P, int i, int spar, int ksl
   }
 }
 
-template <int NPL>
-__device__ inline void mixed_step_row(const ProbDev& P, int i, int spar, int kslot, StepCtx& c,
-                                      z64 (*pc)[64], float* red) {
-  const int tid = threadIdx.x;
-  z32 crow[NPL];
-  if (P.nfreq == 1) {
-    const z32* c0 = P.C0[0] + size_t(i) * P.ld;
+// Mixed step over a group of kMixRows rows: each wave handles two rows and
+// streams their C0^-1 rows against g_m (read once for both), then lane 0 of
+// the wave forms p, updates E, R', tau in FP64 and scores the two
+// candidates.  The first kMixPre column chunks of the two rows are fetched
+// before the decision.
+constexpr int kMixPre = 4;
+
+__device__ inline void mixed_step_group(const ProbDev& P, int g, int spar, int kslot, StepCtx& c,
+                                        z64 (*pc)[64], bool publish) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ra = g * kMixRows + 2 * w, rb = ra + 1;
+  const bool va = ra < P.nd, vb = rb < P.nd;
+  const int dp = spar;
+  const bool pre = P.nfreq == 1;
+  z32 pa[kMixPre], pb[kMixPre];
 #pragma unroll
-    for (int t = 0; t < NPL; ++t) {
-      const int j = tid + t * kRowThreads;
-      if (j < P.nd) crow[t] = c0[j];
+  for (int q = 0; q < kMixPre; ++q) {
+    const int j = lane + 64 * q;
+    pa[q] = z32{0.f, 0.f};
+    pb[q] = z32{0.f, 0.f};
+    if (pre && j < P.nd) {
+      if (va) pa[q] = P.C0[0][size_t(ra) * P.ld + j];
+      if (vb) pb[q] = P.C0[0][size_t(rb) * P.ld + j];
     }
   }
-  const uint8_t* bin = spar ? P.bitsB : P.bits;
-  uint8_t* bout = spar ? P.bits : P.bitsB;
-  z64 e0{0.0, 0.0}, r0{0.0, 0.0}, t0{0.0, 0.0};
-  uint8_t b0 = 0;
-  if (tid == 0) {
-    b0 = bin[i];
-    e0 = (spar ? P.EB[0] : P.E[0])[i];
-    r0 = (spar ? P.RpB[0] : P.Rp[0])[i];
-    t0 = (spar ? P.tauB[0] : P.tau[0])[i];
-    step_decide(P, spar, kslot, true, c);
+  // this pair's vectors (frequency 0), independent of the decision
+  const uint8_t* bin = dp ? P.bitsB : P.bits;
+  uint8_t* bout = dp ? P.bits : P.bitsB;
+  z64 e0a{0.0, 0.0}, r0a{0.0, 0.0}, t0a{0.0, 0.0}, e0b{0.0, 0.0}, r0b{0.0, 0.0}, t0b{0.0, 0.0};
+  uint8_t b0a = 0, b0b = 0;
+  if (lane == 0) {
+    if (va) {
+      b0a = bin[ra];
+      e0a = (dp ? P.EB[0] : P.E[0])[ra];
+      r0a = (dp ? P.RpB[0] : P.Rp[0])[ra];
+      t0a = (dp ? P.tauB[0] : P.tau[0])[ra];
+    }
+    if (vb) {
+      b0b = bin[rb];
+      e0b = (dp ? P.EB[0] : P.E[0])[rb];
+      r0b = (dp ? P.RpB[0] : P.Rp[0])[rb];
+      t0b = (dp ? P.tauB[0] : P.tau[0])[rb];
+    }
   }
+  if (tid == 0) step_decide(P, spar, kslot, true, c);
   __syncthreads();
-  if (i == 0) step_publish(P, spar, kslot, true, c);
+  if (publish) step_publish(P, spar, kslot, true, c);
   const int m = c.m;
   if (m < 0) return;
   const int slot = c.slot;
@@ -358,69 +379,95 @@ __device__ inline void mixed_step_row(const ProbDev& P, int i, int spar, int ksl
     for (int f = 0; f < P.nfreq; ++f)
       pc[f][tid] = zmul(P.alph[f][tid], up32(P.Pp[f][size_t(tid) * P.ld + m]));
   __syncthreads();
-  const int dp = spar;
-  const uint8_t bit = b0 ^ (i == m ? 1 : 0);
-  const double delta = bit ? -P.deps : P.deps;
-  double df = 0.0, bnd = 0.0;
-  const int lane = tid & 63, wid = tid >> 6;
+  const uint8_t bita = b0a ^ (ra == m ? 1 : 0), bitb = b0b ^ (rb == m ? 1 : 0);
+  const double dla = bita ? -P.deps : P.deps, dlb = bitb ? -P.deps : P.deps;
+  double dfa = 0.0, bnda = 0.0, dfb = 0.0, bndb = 0.0;
   for (int f = 0; f < P.nfreq; ++f) {
-    const z32* c0 = P.C0[f] + size_t(i) * P.ld;
+    const z32* ca = P.C0[f] + size_t(ra) * P.ld;
+    const z32* cb = P.C0[f] + size_t(rb) * P.ld;
     const z32* gm = P.G32[f] + size_t(m) * P.ld;
-    if (f > 0 || P.nfreq != 1) {   // frequency 0 was preloaded only when alone
+    float par = 0.f, pai = 0.f, pbr = 0.f, pbi = 0.f;
+    int j0 = 0;
+    if (pre) {
 #pragma unroll
-      for (int t = 0; t < NPL; ++t) {
-        const int j = tid + t * kRowThreads;
-        if (j < P.nd) crow[t] = c0[j];
+      for (int q = 0; q < kMixPre; ++q) {
+        const int j = lane + 64 * q;
+        if (j < P.nd) {
+          const z32 gv = gm[j];
+          par = fmaf(pa[q].re, gv.re, fmaf(-pa[q].im, gv.im, par));
+          pai = fmaf(pa[q].re, gv.im, fmaf(pa[q].im, gv.re, pai));
+          pbr = fmaf(pb[q].re, gv.re, fmaf(-pb[q].im, gv.im, pbr));
+          pbi = fmaf(pb[q].re, gv.im, fmaf(pb[q].im, gv.re, pbi));
+        }
+      }
+      j0 = 64 * kMixPre;
+    }
+#pragma unroll 4
+    for (int j = j0 + lane; j < P.nd; j += 64) {
+      const z32 gv = gm[j];
+      const z32 av = va ? ca[j] : z32{0.f, 0.f};
+      const z32 bv = vb ? cb[j] : z32{0.f, 0.f};
+      par = fmaf(av.re, gv.re, fmaf(-av.im, gv.im, par));
+      pai = fmaf(av.re, gv.im, fmaf(av.im, gv.re, pai));
+      pbr = fmaf(bv.re, gv.re, fmaf(-bv.im, gv.im, pbr));
+      pbi = fmaf(bv.re, gv.im, fmaf(bv.im, gv.re, pbi));
+    }
+    if (lane < slot) {
+      const z64 cc = pc[f][lane];
+      if (va) {
+        const z32 pk = P.Pp[f][size_t(lane) * P.ld + ra];
+        par += float(cc.re * pk.re - cc.im * pk.im);
+        pai += float(cc.re * pk.im + cc.im * pk.re);
+      }
+      if (vb) {
+        const z32 pk = P.Pp[f][size_t(lane) * P.ld + rb];
+        pbr += float(cc.re * pk.re - cc.im * pk.im);
+        pbi += float(cc.re * pk.im + cc.im * pk.re);
       }
     }
-    float pr = 0.f, pi = 0.f;
-#pragma unroll
-    for (int t = 0; t < NPL; ++t) {
-      const int j = tid + t * kRowThreads;
-      if (j < P.nd) {
-        const z32 a = crow[t], b = gm[j];
-        pr = fmaf(a.re, b.re, fmaf(-a.im, b.im, pr));
-        pi = fmaf(a.re, b.im, fmaf(a.im, b.re, pi));
+    par = wave_sumf(par);
+    pai = wave_sumf(pai);
+    pbr = wave_sumf(pbr);
+    pbi = wave_sumf(pbi);
+    if (lane == 0) {
+      for (int h = 0; h < 2; ++h) {
+        const int r = h ? rb : ra;
+        if (!(h ? vb : va)) continue;
+        const z32 p32{h ? pbr : par, h ? pbi : pai};
+        P.Pp[f][size_t(slot) * P.ld + r] = p32;
+        const z64 p = up32(p32);
+        const z64 ap = zmul(c.alpha[f], p);
+        const z64* ebuf = (dp ? P.EB[f] : P.E[f]);
+        const z64* rbuf = (dp ? P.RpB[f] : P.Rp[f]);
+        const z64* tbuf = (dp ? P.tauB[f] : P.tau[f]);
+        const z64 Ein = pick0(f, h ? e0b : e0a, ebuf + r);
+        const z64 Rin = pick0(f, h ? r0b : r0a, rbuf + r);
+        const z64 Tin = pick0(f, h ? t0b : t0a, tbuf + r);
+        const z64 Ei = zadd(Ein, zmul(ap, c.Em[f]));
+        const z64 Rpi = zadd(Rin, zmul(ap, c.Rpm[f]));
+        const z64 tau = zadd(Tin, zmul(ap, p));
+        (dp ? P.E[f] : P.EB[f])[r] = Ei;
+        (dp ? P.Rp[f] : P.RpB[f])[r] = Rpi;
+        (dp ? P.tau[f] : P.tauB[f])[r] = tau;
+        if (h) score_terms(P, c, f, tau, Ei, Rpi, dlb, dfb, bndb);
+        else score_terms(P, c, f, tau, Ei, Rpi, dla, dfa, bnda);
       }
     }
-    if (tid < slot) {
-      const z64 cc = pc[f][tid];
-      const z32 pk = P.Pp[f][size_t(tid) * P.ld + i];
-      pr += float(cc.re * pk.re - cc.im * pk.im);
-      pi += float(cc.re * pk.im + cc.im * pk.re);
-    }
-    pr = wave_sumf(pr);
-    pi = wave_sumf(pi);
-    if (lane == 0) { red[2 * wid] = pr; red[2 * wid + 1] = pi; }
-    __syncthreads();
-    if (tid == 0) {
-      pr = pi = 0.f;
-      for (int w = 0; w < kRowThreads / 64; ++w) { pr += red[2 * w]; pi += red[2 * w + 1]; }
-      P.Pp[f][size_t(slot) * P.ld + i] = z32{pr, pi};
-      const z64 p = {double(pr), double(pi)};
-      const z64 ap = zmul(c.alpha[f], p);
-      const z64 Ein = pick0(f, e0, (dp ? P.EB[f] : P.E[f]) + i);
-      const z64 Rin = pick0(f, r0, (dp ? P.RpB[f] : P.Rp[f]) + i);
-      const z64 Tin = pick0(f, t0, (dp ? P.tauB[f] : P.tau[f]) + i);
-      const z64 Ei = zadd(Ein, zmul(ap, c.Em[f]));
-      const z64 Rpi = zadd(Rin, zmul(ap, c.Rpm[f]));
-      const z64 tau = zadd(Tin, zmul(ap, p));
-      (dp ? P.E[f] : P.EB[f])[i] = Ei;
-      (dp ? P.Rp[f] : P.RpB[f])[i] = Rpi;
-      (dp ? P.tau[f] : P.tauB[f])[i] = tau;
-      score_terms(P, c, f, tau, Ei, Rpi, delta, df, bnd);
-    }
-    __syncthreads();
   }
-  if (tid == 0) {
-    bout[i] = bit;
-    P.df32[i] = df;
-    P.dfb[i] = bnd;
-    const double margin = df - c.eta * c.f;
-    const double band = P.band * bnd;
-    if (margin >= -band) {
-      const uint32_t k = step_key(P, c, i);
-      if (k != kNoKey) atomicMin(&P.keys[(margin > band ? 0 : 3) + (kslot + 1) % 3], k);
+  if (lane == 0) {
+    for (int h = 0; h < 2; ++h) {
+      const int r = h ? rb : ra;
+      if (!(h ? vb : va)) continue;
+      const double df = h ? dfb : dfa, bnd = h ? bndb : bnda;
+      bout[r] = h ? bitb : bita;
+      P.df32[r] = df;
+      P.dfb[r] = bnd;
+      const double margin = df - c.eta * c.f;
+      const double band = P.band * bnd;
+      if (margin >= -band) {
+        const uint32_t k = step_key(P, c, r);
+        if (k != kNoKey) atomicMin(&P.keys[(margin > band ? 0 : 3) + (kslot + 1) % 3], k);
+      }
     }
   }
 }
@@ -431,27 +478,25 @@ __global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar,
   plain_step_row<NPL>(P, blockIdx.x, spar, kslot, c);
 }
 
-template <int NPL>
-__global__ __launch_bounds__(kRowThreads) void k_mixed_step(ProbDev P, int spar, int kslot) {
+__global__ __launch_bounds__(256) void k_mixed_step(ProbDev P, int spar, int kslot) {
   __shared__ StepCtx c;
   __shared__ z64 pc[kMaxFreq][64];
-  __shared__ float red[2 * (kRowThreads / 64)];
-  mixed_step_row<NPL>(P, blockIdx.x, spar, kslot, c, pc, red);
+  mixed_step_group(P, blockIdx.x, spar, kslot, c, pc, blockIdx.x == 0);
 }
 
 // Batched step: one launch advances every problem of a batch by one step.
-// Work item b (a row of one problem) maps to problem p with
-// row0[p] <= b < row0[p+1]; the grid is either one workgroup per item or a
-// persistent grid that strides over the items (launch shape chosen by the
-// autotuner).  Problems are independent (Results, Computational efficiency:
-// per-frequency and per-design systems need no communication).
+// Work item b (a row of one problem on the FP64 path, a group of kMixRows
+// rows on the mixed path) maps to problem p with row0[p] <= b < row0[p+1];
+// the grid is either one workgroup per item or a persistent grid that
+// strides over the items (launch shape chosen by the autotuner).  Problems
+// are independent (Results, Computational efficiency: per-frequency and
+// per-design systems need no communication).
 template <int NPL>
 __global__ __launch_bounds__(kRowThreads) void k_batch_step(const ProbDev* probs,
                                                             const int32_t* row0, int nprob,
                                                             int mixed, int spar, int kslot) {
   __shared__ StepCtx c;
   __shared__ z64 pc[kMaxFreq][64];
-  __shared__ float redf[2 * (kRowThreads / 64)];
   const int total = row0[nprob];
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
     int lo = 0, hi = nprob - 1;       // largest p with row0[p] <= b
@@ -462,7 +507,7 @@ __global__ __launch_bounds__(kRowThreads) void k_batch_step(const ProbDev* probs
     const ProbDev& P = probs[lo];
     const int i = b - row0[lo];
     __syncthreads();   // the previous item is done with the shared context
-    if (mixed) mixed_step_row<NPL>(P, i, spar, kslot, c, pc, redf);
+    if (mixed) mixed_step_group(P, i, spar, kslot, c, pc, i == 0);
     else plain_step_row<NPL>(P, i, spar, kslot, c);
   }
 }
@@ -523,6 +568,9 @@ __global__ __launch_bounds__(256) void k_rform_step(ProbDev P, int spar, int ksl
   double df = 0.0, bnd = 0.0;
   for (int f = 0; f < P.nfreq; ++f) {
     const z64* U = P.Up[f];
+    // T0[m, i] is issued before the panel terms so the loads overlap
+    z64 tmi{0.0, 0.0};
+    if (own) tmi = P.T0[f][size_t(m) * P.ld + i];
     z64 acc{0.0, 0.0};
     for (int j0 = 0; j0 < slot; j0 += kRCoef) {
       const int nj = min(kRCoef, slot - j0);
@@ -530,15 +578,26 @@ __global__ __launch_bounds__(256) void k_rform_step(ProbDev P, int spar, int ksl
       for (int j = tid; j < nj; j += 256)
         cf[j] = zmul(P.alph[f][j0 + j], U[size_t(j0 + j) * P.ld + m]);
       __syncthreads();
-      if (i < P.nd)
-        for (int j = q; j < nj; j += 4) acc = zfma(cf[j], U[size_t(j0 + j) * P.ld + i], acc);
+      if (i < P.nd) {
+        // four independent partial sums keep several panel loads in flight
+        z64 a1{0.0, 0.0}, a2{0.0, 0.0}, a3{0.0, 0.0};
+        int j = q;
+        for (; j + 12 < nj; j += 16) {
+          acc = zfma(cf[j], U[size_t(j0 + j) * P.ld + i], acc);
+          a1 = zfma(cf[j + 4], U[size_t(j0 + j + 4) * P.ld + i], a1);
+          a2 = zfma(cf[j + 8], U[size_t(j0 + j + 8) * P.ld + i], a2);
+          a3 = zfma(cf[j + 12], U[size_t(j0 + j + 12) * P.ld + i], a3);
+        }
+        for (; j < nj; j += 4) acc = zfma(cf[j], U[size_t(j0 + j) * P.ld + i], acc);
+        acc = zadd(zadd(acc, a1), zadd(a2, a3));
+      }
     }
     part[q][lane] = acc;
     __syncthreads();
     if (own) {
       const z64 s01 = zadd(part[0][lane], part[1][lane]);
       const z64 s23 = zadd(part[2][lane], part[3][lane]);
-      const z64 p = zadd(P.T0[f][size_t(m) * P.ld + i], zadd(s01, s23));
+      const z64 p = zadd(tmi, zadd(s01, s23));
       P.Up[f][size_t(slot) * P.ld + i] = p;
       const z64 ap = zmul(c.alpha[f], p);
       const z64 Ein = pick0(f, e0, (dp ? P.EB[f] : P.E[f]) + i);
@@ -627,7 +686,9 @@ hipError_t launch_plain_step(const ProbDev& P, int npl, int step, hipStream_t s)
 }
 
 hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s) {
-  PNGF_STEP_SWITCH(k_mixed_step, npl, dim3(P.nd), dim3(kRowThreads), 0, s, P, step & 1, step % 3)
+  (void)npl;
+  hipLaunchKernelGGL(k_mixed_step, dim3((P.nd + kMixRows - 1) / kMixRows), dim3(256), 0, s, P,
+                     step & 1, step % 3);
   return hipGetLastError();
 }
 
