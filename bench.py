@@ -2,24 +2,30 @@
 
 A step is one complete direct-binary-search run on the 256x256 grid /
 40x40-pixel workload (N_d = 1600, eps in {1, 11.7}, Gaussian line source to a
-Gaussian-overlap output, five sweeps): FP64 initial inverse, scoring of every
-candidate, selection, Sherman-Morrison accepts, re-inversions, until the sweep
-cap or convergence.  Three forms run on the same input:
+Gaussian-overlap output, five sweeps): the FP64 initial inverse of the start
+design, scoring of every candidate, selection, accepts and refreshes until the
+sweep cap or convergence.  Every form runs on the same resident input and must
+reproduce the same accepted sequence:
 
-  * mixed  (headline): complex-FP32 scoring/updates with a deferred panel,
-    FP64 re-inversion every 32 accepts, FP64 decisions inside the error band;
-  * plain:  FP64 fused accept + rescore;
-  * mixed_drift: as mixed, re-inverting only when the FP64 residual drifts.
+  * mixed (headline `value`): complex-FP32 C0^-1 with a deferred panel, FP64
+    refresh every 32 accepts, FP64 decisions inside the FP32 error band;
+  * plain: FP64 C^-1 with a fused Sherman-Morrison accept + rescore per step;
+  * mixed_drift: as mixed, refreshing only when the FP64 residual drifts;
+  * rform: FP64 reduced scoring from T0 = C^-1 G and a panel of T columns;
+  * learned: the ranked exact search driven by a CNN trained here on other
+    seeds (exact evaluations counted; training is not timed).
 
 `value` is attempted flip evaluations per second of the mixed form over the K
-timed runs; ms_per_step is its time-to-design.  Inputs (G, b, G_OD, x_b) are
+timed runs and ms_per_step its time-to-design.  Inputs (G, b, G_OD, x_b) are
 resident in HBM before timing starts; the host precompute is reported
-separately.  Every form must reproduce the same accepted sequence; the
-objective error of the mixed form is reported against the FP64 plain form.
+separately.  Per-kernel times are HIP events recorded around every launch on
+the library's stream during the timed runs (events come from a reused pool).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-learned]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +37,9 @@ sys.path.insert(0, ROOT)
 METRIC = "flip evals/s + time-to-design, mixed vs FP64 plain, ≤1e-6 rel objective err"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+KERNELS = ("score", "select", "accept", "lu", "other", "fold", "mixed_q", "wood")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mixed_step_n1600_traffic.json")
+STEP_SOURCE = os.path.join(ROOT, "paper_2501_18054_amd", "csrc", "step_kernels.hip")
 
 
 def log(msg):
@@ -40,13 +49,13 @@ def log(msg):
 
 def cpu_baseline(prob):
     """Oracle (full sparse re-solve per candidate) on the host cores, on a
-    bounded sample: candidate evaluations at the initial design, evaluated by
-    a process pool over the available cores."""
+    bounded sample: candidate evaluations at the initial design, by a process
+    pool over the available cores (at most 16)."""
     import numpy as np
     import oracle
     cores = len(os.sched_getaffinity(0))
     workers = max(1, min(cores, 16))
-    n = 2 * workers
+    n = 8 * workers
     cands = np.arange(n)
     t0 = time.perf_counter()
     oracle.score_all(prob, prob.init_bits, cands, workers=workers)
@@ -56,10 +65,7 @@ def cpu_baseline(prob):
                       f"LU re-solve of the {prob.nx}x{prob.ny} FDFD system; {dt:.1f} s wall"}
 
 
-def run_form(P, h, prob, opts, opts_timed, steps, warmup, name):
-    """Time `steps` whole runs with event timing off (wall clock around the
-    loop, inputs resident), then one more run with HIP events around every
-    launch for the per-kernel table."""
+def run_form(h, prob, opts, steps, warmup, name):
     import torch
     h.bind(opts)
 
@@ -70,7 +76,7 @@ def run_form(P, h, prob, opts, opts_timed, steps, warmup, name):
     for w in range(warmup):
         r = one_run()
         log(f"{name}: warmup {w}: {r['n_accepted']} accepts, {r['attempts']} attempts, "
-            f"{r['n_refresh']} re-inversions")
+            f"{r['n_refresh']} refreshes")
     torch.cuda.synchronize()
     results = []
     t0 = time.perf_counter()
@@ -79,10 +85,7 @@ def run_form(P, h, prob, opts, opts_timed, steps, warmup, name):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"{name}: {steps} timed runs in {dt:.3f} s")
-    h.bind(opts_timed)
-    one_run()
-    kt = {k: h.kernel_times(k) for k in ("score", "select", "accept", "lu", "other", "fold",
-                                         "mixed_q", "wood")}
+    kt = {k: h.kernel_times(k) for k in KERNELS}   # the last timed run
     return results, dt, kt
 
 
@@ -91,33 +94,100 @@ def summarize(results, dt, steps):
     r0 = results[-1]
     return {"flip_evals_per_s": attempts / dt, "time_to_design_ms": 1e3 * dt / steps,
             "accepts": r0["n_accepted"], "attempts": r0["attempts"], "sweeps": r0["sweeps"],
-            "re_inversions": r0["n_refresh"], "band_decisions": r0["n_verified"],
+            "refreshes": r0["n_refresh"], "band_decisions": r0["n_verified"],
             "f_final": r0["f_final"], "f_initial": r0["f_initial"]}
 
 
-def kernel_table(kt, nd, mixed):
-    """Per-kernel average launch time (us) and algorithmic rate of one run."""
-    mat16 = nd * nd * 16.0
-    mat8 = nd * nd * 8.0
+def kernel_table(kt, nd, ns, form, accepts):
+    """Average launch time (us) and the algorithmic rate of each kernel class.
+
+    Algorithmic work per launch (N_d pixels, n_S pixels at eps_hi):
+      accept  plain 3 N_d^2 16 B (read + write C^-1, read G); mixed N_d^2 8 B
+              (C0^-1 stream); rform (k_avg + 8) N_d 16 B (T0 row, panel,
+              vectors), k_avg = accepts / 2
+      score   2 N_d^2 16 B
+      lu      rform: the T0 build, 8 N_d^2 n_S flop; otherwise the inversion,
+              8 n_S^2 N_d flop (K^-1 and the Z rows)
+      wood    2 x 8 N_d^2 k flop with k = 32 changed pixels
+    """
     out = {}
     for k, (tms, n) in kt.items():
         if n == 0:
             continue
         e = {"launches": n, "total_ms": tms, "avg_us": 1e3 * tms / n}
+        b = fl = None
         if k == "accept":
-            b = mat8 if mixed else 3 * mat16
+            b = {"plain": 3 * nd * nd * 16.0, "mixed": nd * nd * 8.0,
+                 "rform": (accepts / 2 + 8) * nd * 16.0}[form]
+        elif k == "score":
+            b = 2 * nd * nd * 16.0
+        elif k == "lu":
+            fl = 8.0 * nd * nd * ns if form == "rform" else 8.0 * ns * ns * nd
+        elif k == "wood":
+            fl = 2 * 8.0 * nd * nd * 32
+        if b is not None:
             e["bytes_per_launch"] = b
             e["GB_s"] = b / (tms / n * 1e-3) / 1e9
-        if k == "lu":
-            fl = 8.0 * nd ** 3
+        if fl is not None:
             e["flop_per_launch"] = fl
             e["TFLOP_s"] = fl / (tms / n * 1e-3) / 1e12
-        if k == "score":
-            b = 2 * mat16
-            e["bytes_per_launch"] = b
-            e["GB_s"] = b / (tms / n * 1e-3) / 1e9
         out[k] = e
     return out
+
+
+def traffic_for(kernel_name):
+    """Counter-measured HBM bytes per launch of the headline step kernel from
+    the committed rocprofv3 summary, or None if it was taken from another
+    version of the kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    with open(STEP_SOURCE, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    if t.get("source_sha256") != digest or t.get("kernel") != kernel_name:
+        return None
+    return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
+
+
+def learned_form(P, h, prob, steps, k=4):
+    """Train the proposal network on other seeds of the same family (not
+    timed), then time the ranked exact search on this workload."""
+    import torch
+    import workloads
+    from paper_2501_18054_amd import learned
+    t0 = time.perf_counter()
+    X, T = [], []
+    for s in workloads.CONFIG3_TRAIN_SEEDS[:6]:
+        p = workloads.config3_problem(s)
+        hh = P.Handle(p).bind(P.default_options(max_accepts=8192, max_sweeps=8))
+        x, t = learned.collect(hh, p, every=4, greedy=True)
+        X += x
+        T += t
+        hh.close()
+    side = prob.design_side
+    model = P.Model(side, side, max_batch=32, seed=0)
+    hist = learned.train(model, X, T, epochs=40, batch=32, lr=1e-3)
+    t_train = time.perf_counter() - t0
+    log(f"learned: trained on {len(X)} states in {t_train:.1f} s (loss {hist[0]:.3f} -> "
+        f"{hist[-1]:.3f})")
+    h.bind(P.default_options(max_accepts=8192, max_sweeps=8))
+    h.set_design(prob.init_bits)
+    h.learned_dbs_run(model, k=k)
+    torch.cuda.synchronize()
+    res = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h.set_design(prob.init_bits)
+        res.append(h.learned_dbs_run(model, k=k))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = res[-1]
+    model.close()
+    return {"exact_evals_per_s": sum(x["attempts"] for x in res) / dt,
+            "time_to_design_ms": 1e3 * dt / steps, "exact_evals": r["attempts"],
+            "accepts": r["n_accepted"], "converged": r["converged"], "k": k,
+            "f_final": r["f_final"], "train_s": t_train, "train_states": len(X)}
 
 
 def main():
@@ -126,6 +196,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: this build measures one GPU only (the hot path runs on one "
@@ -149,40 +220,42 @@ def main():
     t_pre = time.perf_counter() - t0
     log(f"precompute done in {t_pre:.2f} s")
     nd = h.n_d
+    ns = int(prob.init_bits.sum())
     forms = {}
-    for name, kw, mixed in (
-            ("plain", {}, False),
-            ("mixed", dict(precision=P.PNGF_MIXED, k_refresh=32), True),
-            ("mixed_drift", dict(precision=P.PNGF_MIXED, k_refresh=0), True),
-            ("rform", dict(precision=P.PNGF_RFORM), False)):
-        opts = P.default_options(max_accepts=8192, max_sweeps=8, timing=False, **kw)
-        opts_t = P.default_options(max_accepts=8192, max_sweeps=8, timing=True, **kw)
-        res, dt, kt = run_form(P, h, prob, opts, opts_t, a.steps, a.warmup, name)
+    seqs = {}
+    for name, kw in (("plain", {}),
+                     ("mixed", dict(precision=P.PNGF_MIXED, k_refresh=32)),
+                     ("mixed_drift", dict(precision=P.PNGF_MIXED, k_refresh=0)),
+                     ("rform", dict(precision=P.PNGF_RFORM))):
+        opts = P.default_options(max_accepts=8192, max_sweeps=8, timing=True, **kw)
+        res, dt, kt = run_form(h, prob, opts, a.steps, a.warmup, name)
         s = summarize(res, dt, a.steps)
-        s["kernels"] = kernel_table(kt, nd, mixed)
-        s["accepted_seq"] = res[-1]["accepted"]
+        form = "mixed" if name.startswith("mixed") else name
+        s["kernels"] = kernel_table(kt, nd, ns, form, s["accepts"])
+        seqs[name] = res[-1]["accepted"]
         forms[name] = s
     ref = forms["plain"]
     for name in ("mixed", "mixed_drift", "rform"):
         f = forms[name]
-        f["same_sequence_as_plain"] = bool((f["accepted_seq"] == ref["accepted_seq"]).all()) \
-            if len(f["accepted_seq"]) == len(ref["accepted_seq"]) else False
+        f["same_sequence_as_plain"] = bool(len(seqs[name]) == len(seqs["plain"]) and
+                                           (seqs[name] == seqs["plain"]).all())
         f["objective_rel_err_vs_plain"] = abs(f["f_final"] - ref["f_final"]) / ref["f_final"]
-    for f in forms.values():
-        del f["accepted_seq"]
+    if not a.no_learned:
+        forms["learned"] = learned_form(P, h, prob, a.steps)
+        forms["learned"]["objective_rel_to_plain"] = forms["learned"]["f_final"] / ref["f_final"]
     head = forms["mixed"]
-    # dominant kernel of the headline form (largest total device time)
     ks = head["kernels"]
     dom = max(ks, key=lambda k: ks[k]["total_ms"])
     if "GB_s" in ks[dom]:
         roof = {"bound": "hbm", "achieved": ks[dom]["GB_s"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ks[dom]["GB_s"] / HBM_PEAK_GBS}
-    elif "TFLOP_s" in ks[dom]:
-        roof = {"bound": "mfma", "achieved": ks[dom]["TFLOP_s"], "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ks[dom]["TFLOP_s"] / FP64_PEAK_TFLOPS}
+                "unit": "GB/s", "frac": ks[dom]["GB_s"] / HBM_PEAK_GBS,
+                "traffic": traffic_for("k_mixed_step") if dom == "accept" else None}
     else:
-        roof = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None}
-    roof.update({"traffic": None, "kernel": dom, "avg_us": ks[dom]["avg_us"]})
+        roof = {"bound": "mfma", "achieved": ks[dom].get("TFLOP_s"), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": (ks[dom].get("TFLOP_s") or 0.0) / FP64_PEAK_TFLOPS,
+                "traffic": None}
+    roof.update({"kernel": {"accept": "k_mixed_step"}.get(dom, dom),
+                 "avg_us": ks[dom]["avg_us"]})
     out = {
         "metric": METRIC,
         "value": head["flip_evals_per_s"],
@@ -193,7 +266,7 @@ def main():
         "dtype": "c64 + f64", "data": "synthetic",
         "config": {"workload": "2D TM FDFD 256x256, 12-cell PML, 40x40 design (N_d=1600), "
                                "eps {1,11.7}, Gaussian line source -> Gaussian overlap, "
-                               "5 sweeps, FP64 re-inversion every 32 accepts",
+                               "5 sweeps; mixed form: FP64 refresh every 32 accepts",
                    "n_d": nd},
         "objective_rel_err_vs_plain": head["objective_rel_err_vs_plain"],
         "precompute_s": t_pre,

@@ -123,7 +123,8 @@ struct pngf_handle {
   // event timing
   double ktime_ms[KID_N] = {0};
   int64_t klaunch[KID_N] = {0};
-  std::vector<hipEvent_t> ev_pool;
+  std::vector<hipEvent_t> ev_pool;   // recorded (start, end, kernel id) triples
+  std::vector<hipEvent_t> ev_free;   // created events ready for reuse
 };
 
 namespace {
@@ -251,10 +252,20 @@ struct Timer {
   pngf_handle* h;
   int kid;
   hipEvent_t a = nullptr, b = nullptr;
+  static hipEvent_t take(pngf_handle* h) {
+    hipEvent_t e = nullptr;
+    if (!h->ev_free.empty()) {
+      e = h->ev_free.back();
+      h->ev_free.pop_back();
+    } else {
+      hipEventCreate(&e);
+    }
+    return e;
+  }
   Timer(pngf_handle* hh, int k) : h(hh), kid(k) {
     if (h->opt.flags & PNGF_FLAG_TIMING) {
-      hipEventCreate(&a);
-      hipEventCreate(&b);
+      a = take(h);
+      b = take(h);
       hipEventRecord(a, h->stream);
     }
   }
@@ -267,7 +278,6 @@ struct Timer {
     }
   }
 };
-
 void collect_times(pngf_handle* h) {
   for (size_t k = 0; k + 2 < h->ev_pool.size() + 0; k += 3) {
     float ms = 0.f;
@@ -275,15 +285,12 @@ void collect_times(pngf_handle* h) {
     int kid = int(reinterpret_cast<intptr_t>(h->ev_pool[k + 2]));
     h->ktime_ms[kid] += ms;
     h->klaunch[kid] += 1;
-    hipEventDestroy(h->ev_pool[k]);
-    hipEventDestroy(h->ev_pool[k + 1]);
+    h->ev_free.push_back(h->ev_pool[k]);
+    h->ev_free.push_back(h->ev_pool[k + 1]);
   }
   h->ev_pool.clear();
 }
 
-// Re-form C^-1 (FP64, on the device) from G and the device design bits for
-// every frequency, then E = C^-1 b with one refinement step against C, the
-// output row R' = G_OD + k0^2 C^-1 G diag(deps) G_OD and x, f.
 // E = C^-1 b with one step of FP64 iterative refinement against C, then
 // R' = G_OD (I + k0^2 D C^-1 G) = G_OD + k0^2 C^-1 (G D G_OD) (reciprocity)
 // and the outputs, for the design in P.bits and the C^-1 in P.Cinv.
@@ -317,6 +324,8 @@ int reform_fields(pngf_handle* h) {
   return PNGF_OK;
 }
 
+// Re-form C^-1 (FP64, on the device) from G and the device design bits for
+// every frequency, then E, R', x and f (reform_fields).
 int device_reinvert(pngf_handle* h) {
   const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
   const Layout& L = h->lay;
@@ -1111,6 +1120,7 @@ int pngf_destroy(pngf_handle* h) {
     hipEventDestroy(h->ev_pool[k]);
     hipEventDestroy(h->ev_pool[k + 1]);
   }
+  for (hipEvent_t e : h->ev_free) hipEventDestroy(e);
   delete h;
   return PNGF_OK;
 }
