@@ -125,6 +125,7 @@ struct pngf_handle {
   int64_t klaunch[KID_N] = {0};
   std::vector<hipEvent_t> ev_pool;   // recorded (start, end, kernel id) triples
   std::vector<hipEvent_t> ev_free;   // created events ready for reuse
+  int32_t nacc_seen = 0;             // accepts counted by the step timing so far
 };
 
 namespace {
@@ -269,12 +270,13 @@ struct Timer {
       hipEventRecord(a, h->stream);
     }
   }
-  void end() {
+  // count: launches of the kernel class between the two events
+  void end(int count = 1) {
     if (a) {
       hipEventRecord(b, h->stream);
       h->ev_pool.push_back(a);
       h->ev_pool.push_back(b);
-      h->ev_pool.push_back(reinterpret_cast<hipEvent_t>(intptr_t(kid)));
+      h->ev_pool.push_back(reinterpret_cast<hipEvent_t>(intptr_t(kid) | (intptr_t(count) << 8)));
     }
   }
 };
@@ -282,9 +284,10 @@ void collect_times(pngf_handle* h) {
   for (size_t k = 0; k + 2 < h->ev_pool.size() + 0; k += 3) {
     float ms = 0.f;
     hipEventElapsedTime(&ms, h->ev_pool[k], h->ev_pool[k + 1]);
-    int kid = int(reinterpret_cast<intptr_t>(h->ev_pool[k + 2]));
+    const intptr_t tag = reinterpret_cast<intptr_t>(h->ev_pool[k + 2]);
+    const int kid = int(tag & 0xFF);
     h->ktime_ms[kid] += ms;
-    h->klaunch[kid] += 1;
+    h->klaunch[kid] += int64_t(tag >> 8);
     h->ev_free.push_back(h->ev_pool[k]);
     h->ev_free.push_back(h->ev_pool[k + 1]);
   }
@@ -492,14 +495,21 @@ int normalize(pngf_handle* h, pngf::DbsState* st) {
 // Run `n` (even) steps starting at step index t0, then read the state.
 template <class L>
 int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinned) {
-  for (int b = 0; b < n; ++b) {
-    Timer t(h, KID_ACCEPT);
-    HIPCHK(h, launch(h->P, h->npl, int(t0 + b), h->stream));
-    t.end();
-  }
+  // one event pair around the back-to-back step launches (the average per
+  // launch includes the gaps between them)
+  Timer t(h, KID_ACCEPT);
+  for (int b = 0; b < n; ++b) HIPCHK(h, launch(h->P, h->npl, int(t0 + b), h->stream));
+  t.end(n);
   HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
                            h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  // count only the launches that accepted a flip (the interval also holds
+  // the cheap launches that found the search paused or finished)
+  if (!h->ev_pool.empty()) {
+    const int acc = std::max(0, pinned->n_acc - h->nacc_seen);
+    h->ev_pool.back() = reinterpret_cast<hipEvent_t>(intptr_t(KID_ACCEPT) | (intptr_t(acc) << 8));
+  }
+  h->nacc_seen = pinned->n_acc;
   if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
   return normalize(h, pinned);
 }
@@ -799,6 +809,7 @@ int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double*
   // each FP64 re-inversion), so repeated runs are identical
   h->P.band = (h->opt.guard > 0.0) ? h->opt.guard : 1e-3;
   for (int k = 0; k < KID_N; ++k) { h->ktime_ms[k] = 0.0; h->klaunch[k] = 0; }
+  h->nacc_seen = 0;
   return write_state(h, &s);
 }
 

@@ -1,0 +1,126 @@
+"""Counter-measured memory traffic of a kernel, for the roofline report.
+
+Two rocprofv3 counter runs of the benchmark (FETCH_SIZE, then WRITE_SIZE,
+in KiB per dispatch) give the bytes a kernel moves between L2 and the memory
+fabric.  Each counter is scaled by what it reads for a plain device-to-device
+copy of known size (``copy``), and the result is written to profiles/ as a
+short summary plus a JSON record that bench.py uses while the kernel source
+is unchanged.
+
+    rocprofv3 --pmc FETCH_SIZE -d OUT/cf -o run -- python -m paper_2501_18054_amd.profiling copy
+    rocprofv3 --pmc WRITE_SIZE -d OUT/cw -o run -- python -m paper_2501_18054_amd.profiling copy
+    rocprofv3 --pmc FETCH_SIZE -d OUT/bf -o run -- python bench.py ...
+    rocprofv3 --pmc WRITE_SIZE -d OUT/bw -o run -- python bench.py ...
+    python -m paper_2501_18054_amd.profiling summarize --dir OUT --kernel k_mixed_step ...
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+
+COPY_BYTES = 256 << 20
+COPY_REPS = 5
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+def copy():
+    import torch
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(COPY_REPS):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"copied {COPY_REPS} x {COPY_BYTES} bytes", flush=True)
+
+
+def _counter_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _per_dispatch(rows, counter, name_part):
+    """Counter value (summed over its instances) per dispatch of kernels whose
+    name contains name_part."""
+    acc = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter or name_part not in r.get("Kernel_Name", ""):
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+    return list(acc.values())
+
+
+def summarize(a):
+    cf = _per_dispatch(_counter_rows(os.path.join(a.dir, "cf")), "FETCH_SIZE", a.copy_kernel)
+    cw = _per_dispatch(_counter_rows(os.path.join(a.dir, "cw")), "WRITE_SIZE", a.copy_kernel)
+    bf = _per_dispatch(_counter_rows(os.path.join(a.dir, "bf")), "FETCH_SIZE", a.kernel)
+    bw = _per_dispatch(_counter_rows(os.path.join(a.dir, "bw")), "WRITE_SIZE", a.kernel)
+    kib = COPY_BYTES / 1024.0
+    f_fetch = kib / statistics.median(cf)
+    f_write = kib / statistics.median(cw)
+    # launches that did work (the others found the search paused or finished)
+    thr = 0.05 * max(bf)
+    bf_w = [v for v in bf if v > thr]
+    fetch = statistics.mean(bf_w) * 1024.0 * f_fetch
+    write = statistics.median(bw) * 1024.0 * f_write
+    with open(a.source, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    rec = {"kernel": a.kernel, "workload": a.workload, "fetch_bytes_per_launch": fetch,
+           "write_bytes_per_launch": write, "algorithmic_bytes_per_launch": a.alg_bytes,
+           "copy_scale_fetch": f_fetch, "copy_scale_write": f_write,
+           "dispatches_fetch": len(bf_w), "dispatches_write": len(bw),
+           "source": os.path.relpath(a.source, ROOT), "source_sha256": digest}
+    base = os.path.join(ROOT, "profiles", a.out)
+    with open(base + ".json", "w") as fh:
+        json.dump(rec, fh, indent=1)
+    with open(base + ".md", "w") as fh:
+        fh.write(f"# Memory traffic of `{a.kernel}`: {a.workload}\n\n")
+        fh.write("Commands (repository root, one MI355X, each counter in its own run):\n\n")
+        for c in a.commands:
+            fh.write(f"    {c}\n")
+        fh.write("\n| quantity | value |\n|---|---|\n")
+        fh.write(f"| copy calibration: FETCH_SIZE scale | {f_fetch:.4f} |\n")
+        fh.write(f"| copy calibration: WRITE_SIZE scale | {f_write:.4f} |\n")
+        fh.write(f"| working dispatches counted | {len(bf_w)} (fetch), {len(bw)} (write) |\n")
+        fh.write(f"| fetched bytes per launch | {fetch / 1e6:.2f} MB |\n")
+        fh.write(f"| written bytes per launch | {write / 1e6:.2f} MB |\n")
+        fh.write(f"| algorithmic bytes per launch | {a.alg_bytes / 1e6:.2f} MB |\n")
+        fh.write(f"| traffic / algorithmic | {(fetch + write) / a.alg_bytes:.3f} |\n")
+    print(json.dumps(rec, indent=1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    sub.add_parser("copy")
+    s = sub.add_parser("summarize")
+    s.add_argument("--dir", required=True)
+    s.add_argument("--kernel", required=True)
+    s.add_argument("--copy-kernel", default="copy")
+    s.add_argument("--workload", required=True)
+    s.add_argument("--alg-bytes", type=float, required=True)
+    s.add_argument("--source", required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--commands", nargs="*", default=[])
+    a = ap.parse_args()
+    if a.cmd == "copy":
+        copy()
+    else:
+        summarize(a)
+
+
+if __name__ == "__main__":
+    main()
