@@ -13,7 +13,10 @@ reproduce the same accepted sequence:
   * mixed_drift: as mixed, refreshing only when the FP64 residual drifts;
   * rform: FP64 reduced scoring from T0 = C^-1 G and a panel of T columns;
   * learned: the ranked exact search driven by a CNN trained here on other
-    seeds (exact evaluations counted; training is not timed).
+    seeds (exact evaluations counted; training is not timed);
+  * batch (a separate workload): eight problems of the batching family
+    advanced together, one launch per step, against the same problems run
+    one after the other.
 
 `value` is attempted flip evaluations per second of the mixed form over the K
 timed runs and ms_per_step its time-to-design.  Inputs (G, b, G_OD, x_b) are
@@ -22,7 +25,7 @@ separately.  Per-kernel times are HIP events recorded around every launch on
 the library's stream during the timed runs (events come from a reused pool).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--no-learned]
+                    [--no-learned] [--no-batch]
 """
 import argparse
 import hashlib
@@ -190,6 +193,56 @@ def learned_form(P, h, prob, steps, k=4):
             "f_final": r["f_final"], "train_s": t_train, "train_states": len(X)}
 
 
+def batch_form(P, steps, seeds=range(1000, 1008)):
+    """The batching workload's first problems (uneven N_d, 1-4 frequencies,
+    mixed form): one launch per step over all of them (hipGraph replays,
+    autotuned launch shape) against the same problems run one after the
+    other.  Both include each problem's FP64 initial inverse."""
+    import torch
+    import workloads
+    probs = [workloads.config2_problem(s) for s in seeds]
+    stream = torch.cuda.Stream()
+    opts = P.default_options(precision=P.PNGF_MIXED, k_refresh=32, max_accepts=8192,
+                             max_sweeps=20)
+    hs = [P.Handle(p).bind(opts, stream=stream) for p in probs]
+
+    def solo():
+        return [(h.set_design(p.init_bits), h.dbs_run(p.perms))[1] for h, p in zip(hs, probs)]
+
+    b = P.Batch(hs)
+
+    def batched(tune=False):
+        for h, p in zip(hs, probs):
+            h.set_design(p.init_bits)
+        return b.dbs_run([p.perms for p in probs], autotune=tune)
+
+    solo()
+    batched(tune=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rs = solo()
+    torch.cuda.synchronize()
+    t_solo = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rb = batched()
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / steps
+    att = sum(r["attempts"] for r in rb)
+    same = all(x["accepted"].tolist() == y["accepted"].tolist() for x, y in zip(rb, rs))
+    out = {"problems": len(probs), "n_d": [h.n_d for h in hs],
+           "frequencies": [p.nfreq for p in probs], "attempts": att,
+           "batched_ms": 1e3 * t_b, "solo_ms": 1e3 * t_solo,
+           "batched_flip_evals_per_s": att / t_b, "solo_flip_evals_per_s": att / t_solo,
+           "ms_per_batched_step": b.ms_per_step(), "tuning": b.tuning(),
+           "same_sequences_as_solo": same}
+    b.close()
+    for h in hs:
+        h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +250,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: this build measures one GPU only (the hot path runs on one "
@@ -240,6 +294,11 @@ def main():
         f["same_sequence_as_plain"] = bool(len(seqs[name]) == len(seqs["plain"]) and
                                            (seqs[name] == seqs["plain"]).all())
         f["objective_rel_err_vs_plain"] = abs(f["f_final"] - ref["f_final"]) / ref["f_final"]
+    if not a.no_batch:
+        log("batch ...")
+        forms["batch"] = batch_form(P, max(1, a.steps // 2))
+        log(f"batch: {forms['batch']['batched_ms']:.1f} ms batched vs "
+            f"{forms['batch']['solo_ms']:.1f} ms one after the other")
     if not a.no_learned:
         forms["learned"] = learned_form(P, h, prob, a.steps)
         forms["learned"]["objective_rel_to_plain"] = forms["learned"]["f_final"] / ref["f_final"]
