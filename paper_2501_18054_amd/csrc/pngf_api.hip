@@ -1517,7 +1517,7 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
     rc = batch_prepare(b, active, grid);
     if (rc) break;
     hipEventRecord(e0, b->stream);
-    const int reps = tuning ? 1 : 2;
+    const int reps = tuning ? 1 : 5;   // 30 steps per round: about one refresh interval
     for (int r = 0; r < reps && rc == PNGF_OK; ++r) {
       hipError_t e = hipGraphLaunch(b->exec, b->stream);
       if (e != hipSuccess) rc = bfail(b, PNGF_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));

@@ -491,10 +491,10 @@ __global__ __launch_bounds__(256) void k_mixed_step(ProbDev P, int spar, int ksl
 // strides over the items (launch shape chosen by the autotuner).  Problems
 // are independent (Results, Computational efficiency: per-frequency and
 // per-design systems need no communication).
-template <int NPL>
+template <int NPL, bool MIXED>
 __global__ __launch_bounds__(kRowThreads) void k_batch_step(const ProbDev* probs,
                                                             const int32_t* row0, int nprob,
-                                                            int mixed, int spar, int kslot) {
+                                                            int spar, int kslot) {
   __shared__ StepCtx c;
   __shared__ z64 pc[kMaxFreq][64];
   const int total = row0[nprob];
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(kRowThreads) void k_batch_step(const ProbDev* probs
     const ProbDev& P = probs[lo];
     const int i = b - row0[lo];
     __syncthreads();   // the previous item is done with the shared context
-    if (mixed) mixed_step_group(P, i, spar, kslot, c, pc, i == 0);
+    if (MIXED) mixed_step_group(P, i, spar, kslot, c, pc, i == 0);
     else plain_step_row<NPL>(P, i, spar, kslot, c);
   }
 }
@@ -696,8 +696,25 @@ hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int npro
                              int grid, int npl, int mixed, int step, hipStream_t s) {
   const int g = (grid > 0 && grid < total) ? grid : total;
   if (g <= 0) return hipSuccess;
-  PNGF_STEP_SWITCH(k_batch_step, npl, dim3(g), dim3(kRowThreads), 0, s, probs, row0, nprob, mixed,
-                   step & 1, step % 3)
+  if (mixed) {
+    // separate instantiation: the mixed path needs far fewer registers
+    hipLaunchKernelGGL((k_batch_step<1, true>), dim3(g), dim3(kRowThreads), 0, s, probs, row0,
+                       nprob, step & 1, step % 3);
+    return hipGetLastError();
+  }
+#define L_(N)                                                                          \
+  hipLaunchKernelGGL((k_batch_step<N, false>), dim3(g), dim3(kRowThreads), 0, s, probs, row0, \
+                     nprob, step & 1, step % 3)
+  switch (npl) {
+    case 1: L_(1); break;
+    case 2: L_(2); break;
+    case 4: L_(4); break;
+    case 8: L_(8); break;
+    case 16: L_(16); break;
+    case 32: L_(32); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef L_
   return hipGetLastError();
 }
 
