@@ -26,10 +26,12 @@ closed forms, exact discrete identities, reciprocity and brute force
 (see each function's docstring for which pin covers it).
 """
 from .fdfd import (pml_profile, stretch, assemble, rhs, solve, Solver,
-                   objective, field)
-from .green import green_dd, green_od, output_row, background, pngf_state
+                   objective, field, metal_nodes, pec_system, total_operator)
+from .green import (green_dd, green_od, output_row, background, pngf_state,
+                    equivalent_current, pec_state)
 from .dbs import dbs, score_all, DBSResult
 
 __all__ = ["pml_profile", "stretch", "assemble", "rhs", "solve", "Solver",
-           "objective", "field", "green_dd", "green_od", "output_row", "background", "pngf_state", "dbs",
+           "objective", "field", "metal_nodes", "pec_system", "total_operator", "green_dd", "green_od", "output_row", "background", "pngf_state", "equivalent_current",
+           "pec_state", "dbs",
            "score_all", "DBSResult"]

@@ -18,7 +18,7 @@ where the paper is silent:
 
 Every candidate objective f' is obtained by assembling the FDFD operator of
 the candidate design and solving it (sparse LU + one refinement step) at every
-frequency.  Candidates ahead of the cursor may be evaluated speculatively in a
+frequency; PEC pixels enter that operator as Ez = 0 on their nodes.  Candidates ahead of the cursor may be evaluated speculatively in a
 process pool; the decisions are those of the sequential loop.
 
 Pins: tests/test_oracle_dbs.py checks, by independent full solves, that every
@@ -34,7 +34,7 @@ import os
 import numpy as np
 import scipy.sparse as sp
 
-from .fdfd import Solver, assemble, rhs, total_eps, objective
+from .fdfd import Solver, assemble, rhs, total_eps, objective, metal_nodes, pec_system, PEC
 
 ETA = 1e-9
 
@@ -57,12 +57,17 @@ def _eval_bits(prob, ops, bits):
     deps = np.where(np.asarray(bits) != 0, prob.eps_hi - prob.eps_lo, 0.0)
     xs = np.empty(prob.nfreq, dtype=np.complex128)
     N = prob.nx * prob.ny
+    metal = metal_nodes(prob, bits)
     for fi, (Lb, scale) in enumerate(ops):
         k0 = prob.k0[fi]
-        d = np.zeros(N, dtype=np.complex128)
-        d[idx] = k0 * k0 * deps
-        L = sp.csc_matrix(Lb + sp.diags(d))
-        E = Solver(L, scale).solve(rhs(prob.src[fi], k0))
+        b = rhs(prob.src[fi], k0)
+        if getattr(prob, "pixel_kind", 0) == PEC:
+            L, b = pec_system(Lb, b, metal)
+        else:
+            d = np.zeros(N, dtype=np.complex128)
+            d[idx] = k0 * k0 * deps
+            L = sp.csc_matrix(Lb + sp.diags(d))
+        E = Solver(L, scale).solve(b)
         xs[fi] = prob.w[0] @ E
     return objective(prob, xs), xs
 

@@ -142,11 +142,49 @@ def total_eps(prob, bits):
     return eps.reshape(prob.ny, prob.nx)
 
 
+PEC = 1
+
+
+def metal_nodes(prob, bits):
+    """Flat node ids of the design pixels that are perfect conductors (empty
+    unless the problem has PEC pixels)."""
+    if getattr(prob, "pixel_kind", 0) != PEC:
+        return np.zeros(0, dtype=np.int64)
+    return prob.design_indices()[np.asarray(bits) != 0]
+
+
+def pec_system(L, b, nodes):
+    """Impose Ez = 0 on ``nodes`` (perfect electric conductor, the sigma ->
+    infinity limit of Results, Numerical Green's functions): with K the
+    diagonal 0/1 mask of the free nodes, K L K + (I - K) and K b.  The rows
+    and columns of the conductor nodes become identity rows and columns, the
+    rest of the system is untouched, and symmetry is kept."""
+    N = L.shape[0]
+    keep = np.ones(N)
+    keep[np.asarray(nodes, dtype=np.int64)] = 0.0
+    K = sp.diags(keep)
+    Lp = sp.csc_matrix(K @ L @ K + sp.diags(1.0 - keep))
+    return Lp, keep * b
+
+
+def total_operator(prob, bits, fi):
+    """(L, scale, right-hand side) of the full system of design ``bits`` at
+    frequency fi: dielectric pixels enter through eps, PEC pixels as Ez = 0."""
+    k0 = prob.k0[fi]
+    b = rhs(prob.src[fi], k0)
+    if getattr(prob, "pixel_kind", 0) == PEC:
+        eps = total_eps(prob, np.zeros(prob.n_d, dtype=np.uint8))
+        L, scale = assemble(prob.nx, prob.ny, prob.npml, prob.h, eps, k0)
+        L, b = pec_system(L, b, metal_nodes(prob, bits))
+        return L, scale, b
+    L, scale = assemble(prob.nx, prob.ny, prob.npml, prob.h, total_eps(prob, bits), k0)
+    return L, scale, b
+
+
 def field(prob, bits, fi, refine=1):
     """Full-domain Ez at frequency index fi for the design ``bits``."""
-    eps = total_eps(prob, bits)
-    return solve(prob.nx, prob.ny, prob.npml, prob.h, eps, prob.k0[fi],
-                  prob.src[fi], refine)
+    L, scale, b = total_operator(prob, bits, fi)
+    return Solver(L, scale).solve(b, refine)
 
 
 def objective(prob, xs):

@@ -94,6 +94,35 @@ def output_row(prob, bits, fi):
     return -(y * S.scale)[idx]
 
 
+def equivalent_current(prob, bits, fi):
+    """(E full field, j on the design pixels) for a design of PEC pixels.
+
+    Current equivalence (Results, Numerical Green's functions; Supplementary
+    Note 1): the conductors are replaced by a current on their nodes that,
+    radiating in the background environment, gives the same field.  From the
+    Dirichlet solution E of the full system, that current is the residual of
+    the background operator, j = (i k0 J - L_b E) restricted to the design;
+    it vanishes on open pixels, and E_D = b + G_DD j (G_DD = -(L_b^-1)[D, D])
+    holds by construction.  In the paper's convention (e = e_inc - G j) the
+    current is -j here."""
+    from .fdfd import field, rhs
+    E = field(prob, bits, fi)
+    eps = total_eps(prob, np.zeros(prob.n_d, dtype=np.uint8))
+    Lb, _ = assemble(prob.nx, prob.ny, prob.npml, prob.h, eps, prob.k0[fi])
+    r = rhs(prob.src[fi], prob.k0[fi]) - Lb @ E
+    return E, r[prob.design_indices()].copy()
+
+
+def pec_state(prob, bits, fi):
+    """(z, x) of a PEC design: z = E_D on open pixels and the equivalent
+    current j (see equivalent_current) on conducting pixels, x = w^T E."""
+    E, j = equivalent_current(prob, bits, fi)
+    idx = prob.design_indices()
+    on = np.asarray(bits) != 0
+    z = np.where(on, j, E[idx])
+    return z, complex(prob.w[0] @ E)
+
+
 def pngf_state(prob, bits, fi):
     """(E_D, x) for design ``bits`` at frequency fi, from one full solve."""
     from .fdfd import field

@@ -15,7 +15,8 @@ Conventions (shared by every consumer):
   * Design pixels are enumerated in the same row-major order restricted to
     the design mask; pixel m <-> m-th nonzero of design_mask.ravel().
   * Design bit p_m = 1 means eps_hi, 0 means eps_lo; eps_static holds eps_lo
-    on design cells.
+    on design cells.  For problems with pixel_kind == PEC, bit 1 means a
+    perfectly conducting pixel (Ez = 0 on that node) and eps_hi is unused.
   * All randomness comes from numpy Generator(PCG64(...)) keyed on the seed.
 
 The five standard workloads follow the stated test configurations:
@@ -25,6 +26,8 @@ The five standard workloads follow the stated test configurations:
   2: 48 problems of uneven size and 1-4 frequencies (batching).
   3: config-1-type problems with training / held-out seeds (learned proposer).
   4: 640x640 grid, 80x80 design, eight frequencies, normalized transmission.
+plus ``metal`` / ``tiny_metal``: the same kind of problem with perfectly
+conducting (PEC) pixels, the paper's own device type.
 """
 from __future__ import annotations
 
@@ -36,6 +39,9 @@ import numpy as np
 POINT_INTENSITY = 0
 OVERLAP_INTENSITY = 1
 MEAN_TRANSMISSION = 2
+
+DIELECTRIC = 0
+PEC = 1
 
 
 @dataclass
@@ -62,6 +68,7 @@ class Problem:
     design_origin: tuple = (0, 0)   # (i0, j0) of the square design region
     design_side: int = 0
     log: list = field(default_factory=list)
+    pixel_kind: int = DIELECTRIC    # DIELECTRIC (eps_lo/eps_hi) or PEC pixels
 
     @property
     def nfreq(self) -> int:
@@ -281,6 +288,35 @@ def tiny(seed: int = 0, n: int = 20, npml: int = 4, side: int = 3,
         src_pts=[(sx, n // 2, n // 2 + 1)], out_pts=[(ox, n // 2, n // 2 + 1)],
         src_profile=one, out_profile=one, objective_kind=POINT_INTENSITY,
         n_sweeps=n_sweeps, feature=feat, rng=rng)
+
+
+def metal(seed: int = 5, n: int = 96, side: int = 24, nfreq: int = 1,
+          n_sweeps: int = 3, fill: float = 0.3) -> Problem:
+    """Pixelated metal device: 96x96 grid, 10-cell PML, 24x24 design of PEC
+    pixels on eps_lo = 1, one dielectric block outside the design, point
+    source -> point |Ez|^2; about 30% of the pixels start as metal."""
+    rng = _rng(seed, 5)
+    i0 = (n - side) // 2
+    k0s = [2.0 * math.pi * (1.0 + 0.04 * f) for f in range(nfreq)]
+    one = lambda m: np.ones(m)
+    p = _square_problem(
+        f"metal_s{seed}", seed, n, 10, 1.0 / 20.0, side, 1.0, k0s,
+        src_pts=[(i0 - 8, n // 2, n // 2 + 1)], out_pts=[(i0 + side + 8, n // 2, n // 2 + 1)],
+        src_profile=one, out_profile=one, objective_kind=POINT_INTENSITY,
+        n_sweeps=n_sweeps, feature=_block_feature(), rng=rng)
+    p.init_bits = (_rng(seed, 55).random(p.n_d) < fill).astype(np.uint8)
+    p.pixel_kind = PEC
+    return p
+
+
+def tiny_metal(seed: int = 0, n: int = 20, npml: int = 4, side: int = 3,
+               nfreq: int = 1, n_sweeps: int = 3) -> Problem:
+    """tiny() with PEC pixels."""
+    p = tiny(seed=seed, n=n, npml=npml, side=side, eps_hi=1.0, nfreq=nfreq,
+             n_sweeps=n_sweeps)
+    p.name = f"tiny_metal_s{seed}"
+    p.pixel_kind = PEC
+    return p
 
 
 def make_config(i: int, seed=None):
