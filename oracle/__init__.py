@@ -15,6 +15,8 @@ What it computes is the plain definition of what the PNGF path computes:
 * ``green`` -- the design-region numerical Green function and the output
   projection, column by column from full-system solves (Results,
   Precomputation: e_opt = B^T A^-1 B j_opt and x_obj = G_obj j + x_inc).
+* ``gradient`` -- df/d eps per pixel by the adjoint method on the full
+  system (Supplementary Note 5, eq. supp_grad_chainrule).
 * ``dbs``   -- direct binary search in which every candidate design is scored
   by re-solving the whole sparse system (Results, Direct binary search
   optimization).  PNGF is exact at the discrete level (Results, Numerical
@@ -30,8 +32,9 @@ from .fdfd import (pml_profile, stretch, assemble, rhs, solve, Solver,
 from .green import (green_dd, green_od, output_row, background, pngf_state,
                     equivalent_current, pec_state)
 from .dbs import dbs, score_all, DBSResult
+from .gradient import gradient
 
 __all__ = ["pml_profile", "stretch", "assemble", "rhs", "solve", "Solver",
            "objective", "field", "metal_nodes", "pec_system", "total_operator", "green_dd", "green_od", "output_row", "background", "pngf_state", "equivalent_current",
            "pec_state", "dbs",
-           "score_all", "DBSResult"]
+           "score_all", "DBSResult", "gradient"]

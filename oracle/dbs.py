@@ -99,15 +99,25 @@ class DBSResult:
     near_ties: list = dfield(default_factory=list)  # (sweep, pos, pixel, margin)
 
 
-def score_all(prob, bits, cands=None, workers=1):
-    """f' for flipping each candidate (full re-solve each); returns array."""
+def _flip(bits, cand, tiles):
+    """Copy of bits with candidate ``cand`` flipped: one pixel, or every pixel
+    of tile ``cand`` when ``tiles`` ((n_tiles, M), -1 padded) is given."""
+    b = bits.copy()
+    if tiles is None:
+        b[cand] ^= 1
+    else:
+        row = np.asarray(tiles[cand])
+        b[row[row >= 0]] ^= 1
+    return b
+
+
+def score_all(prob, bits, cands=None, workers=1, tiles=None):
+    """f' for flipping each candidate (full re-solve each); returns array.
+    Candidates are pixels, or tiles of pixels flipped together."""
     bits = np.asarray(bits, dtype=np.uint8)
-    cands = np.arange(prob.n_d) if cands is None else np.asarray(cands)
-    designs = []
-    for m in cands:
-        b = bits.copy()
-        b[m] ^= 1
-        designs.append(b)
+    n = prob.n_d if tiles is None else len(tiles)
+    cands = np.arange(n) if cands is None else np.asarray(cands)
+    designs = [_flip(bits, m, tiles) for m in cands]
     if workers <= 1:
         ops = _base_ops(prob)
         return np.array([_eval_bits(prob, ops, b)[0] for b in designs])
@@ -117,8 +127,11 @@ def score_all(prob, bits, cands=None, workers=1):
 
 
 def dbs(prob, bits0=None, perms=None, eta=ETA, workers=1, tie_band=1e-7,
-        progress=None):
-    """Run DBS on ``prob``; returns a DBSResult."""
+        progress=None, tiles=None):
+    """Run DBS on ``prob``; returns a DBSResult.  With ``tiles`` ((n_tiles, M)
+    pixel ids, -1 padded) a candidate is a tile whose pixels all flip
+    together (a rank-M update in the paper's terms, eq. lru_dcn), ``perms``
+    order the tiles and the accepted entries name tiles."""
     bits = np.array(prob.init_bits if bits0 is None else bits0, dtype=np.uint8)
     perms = prob.perms if perms is None else np.asarray(perms)
     ops = _base_ops(prob)
@@ -137,11 +150,7 @@ def dbs(prob, bits0=None, perms=None, eta=ETA, workers=1, tie_band=1e-7,
             while pos < n:
                 width = workers if pool is not None else 1
                 batch = list(range(pos, min(n, pos + width)))
-                designs = []
-                for q in batch:
-                    b = bits.copy()
-                    b[perms[s, q]] ^= 1
-                    designs.append(b)
+                designs = [_flip(bits, perms[s, q], tiles) for q in batch]
                 if pool is not None:
                     fs = pool.map(_worker_eval, designs, chunksize=1)
                 else:
@@ -162,7 +171,7 @@ def dbs(prob, bits0=None, perms=None, eta=ETA, workers=1, tie_band=1e-7,
                     continue
                 q, fn = taken
                 m = int(perms[s, q])
-                bits[m] ^= 1
+                bits = _flip(bits, m, tiles)
                 f = fn
                 res.accepted.append((s, q, m, fn))
                 any_acc = True

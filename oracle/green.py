@@ -101,15 +101,15 @@ def equivalent_current(prob, bits, fi):
     Note 1): the conductors are replaced by a current on their nodes that,
     radiating in the background environment, gives the same field.  From the
     Dirichlet solution E of the full system, that current is the residual of
-    the background operator, j = (i k0 J - L_b E) restricted to the design;
-    it vanishes on open pixels, and E_D = b + G_DD j (G_DD = -(L_b^-1)[D, D])
-    holds by construction.  In the paper's convention (e = e_inc - G j) the
-    current is -j here."""
+    the background operator, j = (L_b E - i k0 J) restricted to the design,
+    in the paper's sign convention (field = e_inc - G j with G = G_DD =
+    -(L_b^-1)[D, D]): it vanishes on open pixels and E_D = b - G_DD j holds
+    by construction."""
     from .fdfd import field, rhs
     E = field(prob, bits, fi)
     eps = total_eps(prob, np.zeros(prob.n_d, dtype=np.uint8))
     Lb, _ = assemble(prob.nx, prob.ny, prob.npml, prob.h, eps, prob.k0[fi])
-    r = rhs(prob.src[fi], prob.k0[fi]) - Lb @ E
+    r = Lb @ E - rhs(prob.src[fi], prob.k0[fi])
     return E, r[prob.design_indices()].copy()
 
 

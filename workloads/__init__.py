@@ -27,7 +27,9 @@ The five standard workloads follow the stated test configurations:
   3: config-1-type problems with training / held-out seeds (learned proposer).
   4: 640x640 grid, 80x80 design, eight frequencies, normalized transmission.
 plus ``metal`` / ``tiny_metal``: the same kind of problem with perfectly
-conducting (PEC) pixels, the paper's own device type.
+conducting (PEC) pixels, the paper's own device type; and ``tiles1`` /
+``with_tiles``: searches whose flips are groups of M pixels (tiles of several
+nodes, optionally tied by mirror symmetry).
 """
 from __future__ import annotations
 
@@ -69,6 +71,8 @@ class Problem:
     design_side: int = 0
     log: list = field(default_factory=list)
     pixel_kind: int = DIELECTRIC    # DIELECTRIC (eps_lo/eps_hi) or PEC pixels
+    tiles: np.ndarray = None        # optional (n_tiles, M) pixel groups, -1 padded
+    tile_perms: np.ndarray = None   # (n_sweeps, n_tiles) visiting orders of the tiles
 
     @property
     def nfreq(self) -> int:
@@ -317,6 +321,56 @@ def tiny_metal(seed: int = 0, n: int = 20, npml: int = 4, side: int = 3,
     p.name = f"tiny_metal_s{seed}"
     p.pixel_kind = PEC
     return p
+
+
+def tile_groups(side: int, a: int, mirror: bool = False) -> np.ndarray:
+    """Pixel groups flipped together, for a side x side design region: a x a
+    blocks of pixels (ragged at the far edges when a does not divide side);
+    with ``mirror`` each block is tied to its mirror image about the region's
+    vertical axis (a design kept symmetric in x).  Returns (n_groups, M) int32
+    pixel ids, -1 padded, in row-major block order."""
+    nb = (side + a - 1) // a
+    blocks = {}
+    for bj in range(nb):
+        for bi in range(nb):
+            pix = [j * side + i for j in range(bj * a, min(side, bj * a + a))
+                   for i in range(bi * a, min(side, bi * a + a))]
+            blocks[(bi, bj)] = pix
+    groups = []
+    for bj in range(nb):
+        for bi in range(nb):
+            if mirror:
+                mi = nb - 1 - bi
+                if mi < bi:
+                    continue
+                pix = blocks[(bi, bj)] + (blocks[(mi, bj)] if mi != bi else [])
+            else:
+                pix = blocks[(bi, bj)]
+            groups.append(pix)
+    M = max(len(g) for g in groups)
+    out = np.full((len(groups), M), -1, dtype=np.int32)
+    for t, g in enumerate(groups):
+        out[t, :len(g)] = g
+    return out
+
+
+def with_tiles(p: Problem, a: int, mirror: bool = False, n_sweeps=None) -> Problem:
+    """Attach tile groups (tile_groups) and per-sweep visiting orders of the
+    groups to a square-design problem."""
+    side = p.design_side
+    p.tiles = tile_groups(side, a, mirror)
+    ns = p.n_sweeps if n_sweeps is None else n_sweeps
+    nt = p.tiles.shape[0]
+    p.tile_perms = np.stack([_rng(p.seed, 8000 + s).permutation(nt).astype(np.int32)
+                             for s in range(ns)]) if ns > 0 else np.zeros((0, nt), np.int32)
+    p.name = f"{p.name}_tiles{a}{'m' if mirror else ''}"
+    return p
+
+
+def tiles1(seed: int = 1) -> Problem:
+    """Workload 1 (40x40 design) searched over 4x4-pixel tiles (M = 16, 100
+    tiles), five sweeps."""
+    return with_tiles(config1(seed, n_sweeps=5), 4)
 
 
 def make_config(i: int, seed=None):
