@@ -14,6 +14,8 @@ reproduce the same accepted sequence:
   * rform: FP64 reduced scoring from T0 = C^-1 G and a panel of T columns;
   * learned: the ranked exact search driven by a CNN trained here on other
     seeds (exact evaluations counted; training is not timed);
+  * tiles: the same workload searched over 4x4-pixel tiles (rank-16 updates;
+    its own sequence, not comparable with the pixel search);
   * batch (a separate workload): 24 problems of the batching family
     advanced together, one launch per step, against the same problems run
     one after the other.
@@ -153,6 +155,48 @@ def traffic_for(kernel_name):
     return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
 
 
+def tile_form(P, h, steps, warmup):
+    """The same workload searched over 100 tiles of 4x4 pixels (M = 16, rank-16
+    Woodbury scores and accepts, FP64 P-form), on the handle's resident
+    inputs.  A step is one complete tile search from the start design."""
+    import torch
+    import workloads
+    pt = workloads.tiles1()
+    m = pt.tiles.shape[1]
+    h.bind(P.default_options(max_accepts=8192, max_sweeps=8, max_tile=m, timing=True))
+
+    def one_run():
+        h.set_design(pt.init_bits)
+        return h.tile_dbs_run(pt.tiles, pt.tile_perms)
+
+    for _ in range(warmup):
+        one_run()
+    torch.cuda.synchronize()
+    res = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res.append(one_run())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = res[-1]
+    nd = h.n_d
+    out = {"tiles": int(pt.tiles.shape[0]), "M": int(m),
+           "tile_evals_per_s": sum(x["attempts"] for x in res) / dt,
+           "time_to_design_ms": 1e3 * dt / steps, "accepts": r["n_accepted"],
+           "attempts": r["attempts"], "converged": r["converged"], "f_final": r["f_final"]}
+    tms, n = h.kernel_times("tile")
+    if n:
+        # one scoring pass reads every tile's rows of C^-1 and G: 2 N_d^2 16 B
+        out["tile_score_avg_us"] = 1e3 * tms / n
+        out["tile_score_GB_s"] = 2 * nd * nd * 16.0 / (tms / n * 1e-3) / 1e9
+    wms, wn = h.kernel_times("wood")
+    if wn:
+        out["woodbury_accept_avg_us"] = 1e3 * wms / wn
+    log(f"tiles: {out['accepts']} accepts, {out['attempts']} attempts, "
+        f"{out['time_to_design_ms']:.1f} ms per design")
+    return out
+
+
 def learned_form(P, h, prob, steps, k=4):
     """Train the proposal network on other seeds of the same family (not
     timed), then time the ranked exact search on this workload."""
@@ -288,6 +332,7 @@ def main():
         s["kernels"] = kernel_table(kt, nd, ns, form, s["accepts"])
         seqs[name] = res[-1]["accepted"]
         forms[name] = s
+    forms["tiles"] = tile_form(P, h, a.steps, a.warmup)
     ref = forms["plain"]
     for name in ("mixed", "mixed_drift", "rform"):
         f = forms[name]

@@ -19,6 +19,20 @@
  * current inverse without forming the new one (eq. lru_eobj_rs, here in field
  * form).  The objective, to be maximized, is f = mean_f |x_f|^2 / norm_f.
  *
+ * Perfectly conducting pixels (pixel_kind PNGF_PIXEL_PEC; the paper's own
+ * devices, eq. currequiv_j_disc): with P = diag(bits) the paper solves
+ * [(I - P) + P G] j = P e_inc.  Its transpose is a field-form matrix,
+ *
+ *     (I - P + P G)^T = I - kappa (G - I) P   with kappa = -1,
+ *
+ * and z = (I - kappa (G - I) P)^-1 b holds the total field on open pixels
+ * and the paper's equivalent current j on conducting ones (field there is
+ * zero; on the design region the field is b - G j), with
+ * x = x_b + kappa G_OD P z.  So a PEC problem runs on the same kernels with
+ * G - I in place of G and kappa = -1 in place of k0^2 deps at every
+ * frequency; the paper's rank-M update (eq. lru_dcn, U = Q^T H_P,
+ * V = Q (G - I)) is the transpose of the column update applied here.
+ *
  * Conventions
  *   - All calls return int: 0 on success, a negative pngf_status otherwise;
  *     pngf_last_error(h) (or pngf_last_error(NULL) for a failed create) gives
@@ -55,6 +69,11 @@ typedef enum pngf_status {
 
 enum { PNGF_POINT_INTENSITY = 0, PNGF_OVERLAP_INTENSITY = 1,
        PNGF_MEAN_TRANSMISSION = 2 };
+
+/* pngf_problem.pixel_kind: a design bit selects eps_hi over eps_lo
+ * (dielectric), or a perfect conductor (Ez = 0 on the pixel's node) over
+ * eps_lo (PEC; eps_hi is then unused). */
+enum { PNGF_PIXEL_DIELECTRIC = 0, PNGF_PIXEL_PEC = 1 };
 
 /* PNGF_FP64_PLAIN: FP64 C^-1 kept current by a Sherman-Morrison update per
  *   accept (eq. lru_woodbury, M = 1); every candidate scored from C^-1 and G.
@@ -94,6 +113,7 @@ typedef struct pngf_problem {
   const double *w;             /* cplx[ny*nx] output functional, x = w^T E   */
   int32_t objective_kind;      /* PNGF_*_INTENSITY / MEAN_TRANSMISSION       */
   const double *obj_norm;      /* [nfreq] normalizers, or NULL for all 1     */
+  int32_t pixel_kind;          /* PNGF_PIXEL_DIELECTRIC or PNGF_PIXEL_PEC    */
 } pngf_problem;
 
 typedef struct pngf_options {
@@ -102,14 +122,19 @@ typedef struct pngf_options {
                         /* 0 = only when the FP64 residual of E drifts.  A   */
                         /* refresh is a block-Woodbury update of the FP64    */
                         /* inverse of the last refresh (exact to rounding),  */
-                        /* or a full re-inversion if > 64 pixels changed     */
+                        /* or a full re-inversion if > 64 pixels changed.    */
+                        /* RFORM: every min(k_refresh, 64) accepts C^-1 is   */
+                        /* refreshed that way and T0, E, R', x re-formed     */
+                        /* from it, which bounds the growth of rounding in   */
+                        /* the panel sums; 0 = never                         */
   int32_t k_fold;       /* MIXED: fold the deferred panel into C0^-1 once it */
                         /* holds k_fold terms (0 = only when it is full);    */
                         /* RFORM: panel capacity before a fold into T0       */
                         /* (0 = 512)                                         */
   int32_t max_accepts;  /* capacity of the on-device accept log (>= 1)       */
   int32_t max_sweeps;   /* largest n_sweeps pngf_dbs_run will be given       */
-  int32_t reserved0;    /* 0                                                 */
+  int32_t max_tile;     /* PLAIN: largest tile (pixels flipped together,     */
+                        /* <= 64) pngf_tile_dbs_run will be given; 0 = none  */
   double eta;           /* accept iff f' - f > eta * f (1e-9)                */
   double guard;         /* MIXED: relative FP32 error band of a score; a     */
                         /* candidate inside it is decided on the FP64 state; */
@@ -137,8 +162,10 @@ const char *pngf_last_error(const pngf_handle *h);
  * band LDL^T of the exterior operator (the Schur-complement idea of the
  * paper's augmented partial factorization, Results, Precomputation), and
  * forms per frequency G = -(L^-1)[D,D] (symmetrized), b, G_OD and x_b.
- * Errors: PNGF_EINVAL for inconsistent sizes or a mask touching the PML,
- * PNGF_ESINGULAR for a zero pivot, PNGF_ENOMEM. */
+ * G, b, G_OD and x_b depend only on the environment, so they are the same
+ * for both pixel kinds.
+ * Errors: PNGF_EINVAL for inconsistent sizes, a mask touching the PML or an
+ * unknown pixel_kind, PNGF_ESINGULAR for a zero pivot, PNGF_ENOMEM. */
 int pngf_precompute(const pngf_problem *p, pngf_handle **out);
 
 /* Copies of the precomputed quantities of frequency fi (host arrays supplied
@@ -163,14 +190,17 @@ int pngf_bind(pngf_handle *h, const pngf_options *o, void *dev_ws, size_t bytes,
               void *hip_stream);
 
 /* Set the design (bits[n_d], 0/1) and form the initial inverse
- * C0^-1 = (I - k0^2 G diag(deps))^-1, E = C0^-1 b, the output row
+ * C0^-1 = (I - k0^2 G diag(deps))^-1 (its PEC counterpart above), E = C0^-1 b,
+ * the output row
  * R' = G_OD (I + k0^2 diag(deps) C0^-1 G) and x (Direct binary search: the
  * inverse of the initial system matrix is found and stored).  FP64 LU with
  * partial pivoting on the GPU.  PNGF_ESINGULAR on a zero pivot. */
 int pngf_set_design(pngf_handle *h, const uint8_t *bits);
 
 /* Current objective f, outputs x cplx[nfreq] and (optional, may be NULL)
- * design fields e_d cplx[nfreq*n_d]. */
+ * design fields e_d cplx[nfreq*n_d].  With PEC pixels e_d holds z: the total
+ * field on open pixels, the equivalent current j (design-region field
+ * b - G j) on conducting ones. */
 int pngf_evaluate(pngf_handle *h, double *f, double *x, double *e_d);
 
 /* Exact objective after flipping each candidate alone from the current state
@@ -179,9 +209,26 @@ int pngf_evaluate(pngf_handle *h, double *f, double *x, double *e_d);
 int pngf_score_flips(pngf_handle *h, const int32_t *cand, int32_t n,
                      double *f_new);
 
+/* Gradient of the objective with respect to the relative permittivity of
+ * every pixel at the current design (Supplementary Note 5,
+ * eq. supp_grad_chainrule): grad[m] = df/d eps_m = sum_f 2 Re[conj(x_f)
+ * dx_f/d eps_m] / (nfreq norm_f) with dx_f/d eps_m = k0^2 E_f[m] R'_f[m]
+ * (R' is the adjoint row of the current design).  O(N_d nfreq) from the
+ * maintained state, no solve.  grad[n_d] host out.  PNGF_EINVAL for PEC
+ * pixels (a conductor has no permittivity to vary). */
+int pngf_gradient(pngf_handle *h, double *grad);
+
 /* Accept the flips pix[n] one after another (Sherman-Morrison update of C^-1,
  * E, R' and x; eq. lru_woodbury with M = 1). */
 int pngf_accept_flips(pngf_handle *h, const int32_t *pix, int32_t n);
+
+/* Flip the distinct pixels pix[n] together: one exact block-Woodbury update
+ * of C^-1 per 64 pixels (eq. lru_woodbury with M = n, on the matrix cores),
+ * then E, R' and x re-formed from C^-1 (three matrix passes).  This is the
+ * sparse design update of a level-set step (Supplementary Note 6: the M
+ * pixels that cross the boundary change at once).  FP64_PLAIN or RFORM
+ * handles; PNGF_EINVAL for MIXED, ids out of range or repeated. */
+int pngf_flip_set(pngf_handle *h, const int32_t *pix, int32_t n);
 
 /* Re-form C^-1 from G and the current design by FP64 LU (direct re-inversion,
  * Results, Computational efficiency), with one step of iterative refinement of
@@ -198,11 +245,30 @@ int pngf_refresh(pngf_handle *h);
 int pngf_dbs_run(pngf_handle *h, const int32_t *perms, int32_t n_sweeps,
                  int32_t *accepted, double *f_trace, pngf_dbs_result *res);
 
+/* Direct binary search over tiles: groups of pixels flipped together, the
+ * paper's multi-DOF tiles (M field components per tile) and symmetry-tied
+ * tile groups, a rank-M update (eq. lru_dcn).  tiles[n_tiles*m] holds each
+ * tile's pixel ids, distinct within a tile, padded at the end with -1 (at
+ * least one id per tile); perms[n_sweeps*n_tiles] order the tiles per sweep.
+ * Every tile is scored exactly from the current FP64 state by the rank-M
+ * Woodbury identity (eqs. lru_woodbury, lru_eobj_rs: an M x M block of
+ * C^-1 G and an M x M solve per tile); the first improving tile in visiting
+ * order (f' - f > eta f) is accepted by a block-Woodbury update of C^-1 on
+ * the matrix cores, after which E, R' and x are re-formed.  Sweep,
+ * convergence and stop rules as pngf_dbs_run; accepted[] receives tile ids.
+ * Needs an FP64_PLAIN handle bound with max_tile >= m, 1 <= m <= 64,
+ * 1 <= n_tiles <= n_d, n_tiles * Mpad^2 <= 512 n_d (Mpad = 16, 32 or 64, the
+ * smallest >= m), n_sweeps <= max_sweeps; PNGF_EINVAL otherwise. */
+int pngf_tile_dbs_run(pngf_handle *h, const int32_t *tiles, int32_t n_tiles, int32_t m,
+                      const int32_t *perms, int32_t n_sweeps, int32_t *accepted,
+                      double *f_trace, pngf_dbs_result *res);
+
 /* Total device time (ms, HIP events on the bound stream; needs
  * PNGF_FLAG_TIMING) and launch count of the kernels of the last pngf_dbs_run,
  * per kernel id: 0 full scoring pass, 1 select, 2 accept (+ rescore),
  * 3 FP64 inversion, 4 other re-inversion work (GEMVs, outputs), 5 panel fold,
- * 6 mixed-path q row, 7 FP64 block-Woodbury refresh (mixed path). */
+ * 6 mixed-path q row, 7 FP64 block-Woodbury update (mixed refresh, tile
+ * accept), 8 tile scoring. */
 int pngf_kernel_times(pngf_handle *h, int32_t kernel_id, double *total_ms,
                       int64_t *launches);
 

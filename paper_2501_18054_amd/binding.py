@@ -18,9 +18,11 @@ PNGF_FP64_PLAIN = 0
 PNGF_MIXED = 1
 PNGF_RFORM = 2
 PNGF_FLAG_TIMING = 1
+PNGF_PIXEL_DIELECTRIC = 0
+PNGF_PIXEL_PEC = 1
 
 KERNEL_IDS = {"score": 0, "select": 1, "accept": 2, "lu": 3, "other": 4, "fold": 5,
-              "mixed_q": 6, "wood": 7}
+              "mixed_q": 6, "wood": 7, "tile": 8}
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ESINGULAR", -3: "ENUMERIC", -4: "EDEVICE",
            -5: "ESTATE", -6: "ENOMEM"}
@@ -42,13 +44,14 @@ class Problem(C.Structure):
                 ("src", C.POINTER(C.c_double)),
                 ("nobj", C.c_int32), ("w", C.POINTER(C.c_double)),
                 ("objective_kind", C.c_int32),
-                ("obj_norm", C.POINTER(C.c_double))]
+                ("obj_norm", C.POINTER(C.c_double)),
+                ("pixel_kind", C.c_int32)]
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("k_refresh", C.c_int32),
                 ("k_fold", C.c_int32), ("max_accepts", C.c_int32),
-                ("max_sweeps", C.c_int32), ("reserved0", C.c_int32),
+                ("max_sweeps", C.c_int32), ("max_tile", C.c_int32),
                 ("eta", C.c_double), ("guard", C.c_double), ("flags", C.c_uint64)]
 
 
@@ -74,6 +77,10 @@ EXPORTS = {
     "pngf_set_design": ([C.c_void_p, C.c_void_p], C.c_int),
     "pngf_evaluate": ([C.c_void_p, C.POINTER(C.c_double), C.c_void_p, C.c_void_p], C.c_int),
     "pngf_score_flips": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "pngf_gradient": ([C.c_void_p, C.c_void_p], C.c_int),
+    "pngf_flip_set": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
+    "pngf_tile_dbs_run": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                           C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "pngf_accept_flips": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "pngf_refresh": ([C.c_void_p], C.c_int),
     "pngf_dbs_run": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
@@ -142,8 +149,12 @@ def _cplx(a):
 
 
 def default_options(precision=PNGF_FP64_PLAIN, max_accepts=1 << 16, max_sweeps=32,
-                    eta=1e-9, k_refresh=32, k_fold=0, guard=0.0, timing=False):
-    return Options(precision, k_refresh, k_fold, max_accepts, max_sweeps, 0, eta, guard,
+                    eta=1e-9, k_refresh=None, k_fold=0, guard=0.0, timing=False, max_tile=0):
+    """Options of pngf_bind; k_refresh defaults to 32 for the mixed form and
+    to 0 (no re-anchoring) for the others."""
+    if k_refresh is None:
+        k_refresh = 32 if precision == PNGF_MIXED else 0
+    return Options(precision, k_refresh, k_fold, max_accepts, max_sweeps, max_tile, eta, guard,
                    PNGF_FLAG_TIMING if timing else 0)
 
 
@@ -168,7 +179,8 @@ class Handle:
                     int(prob.w.shape[0]),
                     k["w"].ctypes.data_as(C.POINTER(C.c_double)),
                     int(prob.objective_kind),
-                    k["norm"].ctypes.data_as(C.POINTER(C.c_double)))
+                    k["norm"].ctypes.data_as(C.POINTER(C.c_double)),
+                    int(getattr(prob, "pixel_kind", PNGF_PIXEL_DIELECTRIC)))
         h = C.c_void_p()
         rc = L.pngf_precompute(C.byref(p), C.byref(h))
         if rc != 0:
@@ -252,6 +264,17 @@ class Handle:
         self._check(lib().pngf_score_flips(self._h, _ptr(c), c.shape[0], _ptr(out)))
         return out
 
+    def gradient(self):
+        """df/d eps_m for every pixel at the current design (pngf_gradient)."""
+        out = np.empty(self.n_d, np.float64)
+        self._check(lib().pngf_gradient(self._h, _ptr(out)))
+        return out
+
+    def flip_set(self, pix):
+        """Flip the distinct pixels pix together (pngf_flip_set)."""
+        p = np.ascontiguousarray(pix, dtype=np.int32)
+        self._check(lib().pngf_flip_set(self._h, _ptr(p), p.shape[0]))
+
     def accept_flips(self, pix):
         p = np.ascontiguousarray(pix, dtype=np.int32)
         self._check(lib().pngf_accept_flips(self._h, _ptr(p), p.shape[0]))
@@ -274,6 +297,25 @@ class Handle:
                     attempts=int(res.attempts), n_refresh=res.n_refresh,
                     n_verified=int(res.n_verified), f_initial=res.f_initial,
                     f_final=res.f_final)
+
+    def tile_dbs_run(self, tiles, perms):
+        """Search over tiles of pixels flipped together (pngf_tile_dbs_run):
+        tiles (n_tiles, M) pixel ids, -1 padded; perms (n_sweeps, n_tiles)."""
+        tiles = np.ascontiguousarray(tiles, dtype=np.int32)
+        perms = np.ascontiguousarray(perms, dtype=np.int32)
+        nt, m = tiles.shape
+        cap = self.opts.max_accepts
+        acc = np.empty(cap, np.int32)
+        ftr = np.empty(cap, np.float64)
+        res = DbsResult()
+        self._check(lib().pngf_tile_dbs_run(self._h, _ptr(tiles), nt, m, _ptr(perms),
+                                            perms.shape[0], _ptr(acc), _ptr(ftr),
+                                            C.byref(res)))
+        n = res.n_accepted
+        return dict(accepted=acc[:n].copy(), f_trace=ftr[:n].copy(), n_accepted=n,
+                    sweeps=res.sweeps, converged=bool(res.converged),
+                    attempts=int(res.attempts), n_refresh=res.n_refresh,
+                    f_initial=res.f_initial, f_final=res.f_final)
 
     def features(self):
         """CNN inputs of the current state, float32 [7, n_d]."""

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpngf.so")
-SOURCES = ["host_precompute.cpp", "pngf_api.hip", "plain_kernels.hip", "lu_kernels.hip", "mixed_kernels.hip", "step_kernels.hip", "cnn.hip", "gemm_kernels.hip"]
+SOURCES = ["host_precompute.cpp", "pngf_api.hip", "plain_kernels.hip", "lu_kernels.hip", "mixed_kernels.hip", "step_kernels.hip", "cnn.hip", "gemm_kernels.hip", "tile_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

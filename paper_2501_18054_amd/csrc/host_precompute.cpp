@@ -238,11 +238,16 @@ int precompute(const pngf_problem* p, Precomputed* out, std::string* err) {
     *err = "need nfreq >= 1 and nobj == 1";
     return PNGF_EINVAL;
   }
+  if (p->pixel_kind != PNGF_PIXEL_DIELECTRIC && p->pixel_kind != PNGF_PIXEL_PEC) {
+    *err = "unknown pixel_kind";
+    return PNGF_EINVAL;
+  }
   Grid g{p->nx, p->ny, p->npml, p->h};
   const int64_t N = int64_t(g.nx) * g.ny;
   out->grid = g;
   out->eps_lo = p->eps_lo;
   out->eps_hi = p->eps_hi;
+  out->pec = p->pixel_kind == PNGF_PIXEL_PEC;
   out->design_nodes.clear();
   std::vector<int> pix_of(N, -1);
   for (int64_t n = 0; n < N; ++n) {

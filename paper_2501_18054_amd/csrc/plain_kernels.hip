@@ -350,6 +350,30 @@ hipError_t launch_accept_only(const ProbDev& P, int npl, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Gradient of f with respect to the relative permittivity of every pixel
+// (Supplementary Note 5, eq. supp_grad_chainrule, in field form): a change d
+// of eps at pixel m changes x_f by k0^2 d E_f[m] R'_f[m] to first order (R'
+// is the adjoint row of the current design), and with the Wirtinger
+// derivative conj(x_f) of |x_f|^2,
+//     df/deps_m = sum_f coef_f 2 Re[conj(x_f) k0^2 E_f[m] R'_f[m]].
+// O(N_d F) from the maintained E and R'; one thread per pixel.
+__global__ __launch_bounds__(256) void k_gradient(ProbDev P, double* out) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= P.nd) return;
+  double g = 0.0;
+  for (int f = 0; f < P.nfreq; ++f) {
+    const z64 v = zmul(P.E[f][m], P.Rp[f][m]);
+    const z64 x = P.st->x[f];
+    g += P.coef[f] * 2.0 * P.k0sq[f] * (x.re * v.re + x.im * v.im);
+  }
+  out[m] = g;
+}
+
+hipError_t launch_gradient(const ProbDev& P, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gradient, dim3((P.nd + 255) / 256), dim3(256), 0, s, P, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_pick_best(const double* df, const int32_t* cand, int n, const DbsState* st,
                             int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_pick_best, dim3(1), dim3(1024), 0, s, df, cand, n, st, out);

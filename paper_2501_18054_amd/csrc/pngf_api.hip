@@ -38,6 +38,10 @@ hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int 
 hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, const double* sc,
                            z64* Cap, hipStream_t s);
 hipError_t launch_small_inverse(z64* A, int k, int32_t* status, hipStream_t s);
+hipError_t launch_gradient(const ProbDev& P, double* out, hipStream_t s);
+hipError_t launch_tile_score(const ProbDev& P, const int32_t* tiles, int ntiles, int m, int ks,
+                             z64* part, double* out, hipStream_t s);
+int tile_rows(int m);
 hipError_t launch_pick_best(const double* df, const int32_t* cand, int n, const DbsState* st,
                             int32_t* out, hipStream_t s);
 hipError_t model_score_state(pngf_model* m, const ProbDev& P, float** scores);
@@ -66,6 +70,8 @@ constexpr int kPanelCap = 64;      // deferred Sherman-Morrison terms (mixed)
 constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
+constexpr int kTilePartPerPixel = 512;   // tile-score partial blocks (complex) per pixel
+constexpr int kTileSlicesMax = 8;        // K slices of one tile's block
 constexpr int kWoodSplits = 8;     // split-K factor of its skinny GEMM
 constexpr int kRPanel = 512;       // R-form panel capacity before a fold into T0
 constexpr int kDriftEvery = 32;    // accepts between drift checks
@@ -82,7 +88,7 @@ thread_local std::string g_create_error;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 enum KernelId { KID_SCORE = 0, KID_SELECT = 1, KID_ACCEPT = 2, KID_LU = 3, KID_OTHER = 4,
-                KID_FOLD = 5, KID_MIXQ = 6, KID_WOOD = 7, KID_N = 8 };
+                KID_FOLD = 5, KID_MIXQ = 6, KID_WOOD = 7, KID_TILE = 8, KID_N = 9 };
 
 struct Layout {
   size_t off_G[pngf::kMaxFreq], off_C[pngf::kMaxFreq], off_E[pngf::kMaxFreq],
@@ -97,7 +103,7 @@ struct Layout {
       off_tauB[pngf::kMaxFreq];
   size_t off_bitsB, off_stateB, off_keys, off_pm, off_best, off_feat;
   size_t off_S, off_B1, off_Pb, off_ts, off_B11, off_piv, off_invp, off_used, off_status, off_u, off_r;
-  size_t off_wP, off_wQ, off_wW, off_wCap, off_wF, off_wS, off_wWork;
+  size_t off_wP, off_wQ, off_wW, off_wCap, off_wF, off_wS, off_wWork, off_tiles, off_tpart;
   size_t off_T[pngf::kMaxFreq], off_Up[pngf::kMaxFreq], off_ralph[pngf::kMaxFreq], off_rpm, off_Ut;
   size_t total;
 };
@@ -199,8 +205,13 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_rpm = take(kr * sizeof(int32_t));
     L.off_Ut = take(size_t(nd) * kr * sizeof(z64));
   }
-  if (o->precision != PNGF_FP64_PLAIN) {
-    // FP64 block-Woodbury refresh: panel, rows, capacitance, split-K partials
+  if (o->precision == PNGF_FP64_PLAIN && o->max_tile > 0) {
+    L.off_tiles = take(size_t(nd) * o->max_tile * sizeof(int32_t));
+    L.off_tpart = take(size_t(nd) * pngf::kTilePartPerPixel * sizeof(z64));
+  }
+  {
+    // FP64 block-Woodbury update (mixed refresh, tile accept, pixel sets):
+    // panel, rows, capacitance, split-K partials
     const size_t kw = size_t(pngf::kWoodMax);
     L.off_wP = take(size_t(nd) * kw * sizeof(z64));
     L.off_wQ = take(kw * nd * sizeof(z64));
@@ -379,6 +390,58 @@ int device_reinvert(pngf_handle* h) {
   return PNGF_OK;
 }
 
+// Block-Woodbury update of the FP64 inverse in P.Cinv (eq. lru_woodbury,
+// M = fl.size() <= kWoodMax) for the pixels fl, whose bits in cur are their
+// new values: C^-1 += P W with P = C^-1 G[:,F] diag(k0^2 delta_F) and
+// W = Cap^-1 C^-1[F,:], Cap the M x M capacitance matrix, on the matrix
+// cores.  *singular reports a singular Cap (C^-1 is then not usable).  Ends
+// with a wait.
+int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::vector<uint8_t>& cur,
+                    bool* singular) {
+  const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
+  const Layout& L = h->lay;
+  pngf::ProbDev& P = h->P;
+  const int k = int(fl.size());
+  int32_t* dF = at<int32_t>(h, L.off_wF);
+  double* dS = at<double>(h, L.off_wS);
+  z64* wP = at<z64>(h, L.off_wP);
+  z64* wQ = at<z64>(h, L.off_wQ);
+  z64* wW = at<z64>(h, L.off_wW);
+  z64* cap = at<z64>(h, L.off_wCap);
+  z64* work = at<z64>(h, L.off_wWork);
+  int32_t* status = at<int32_t>(h, L.off_status);
+  std::vector<double> sc(size_t(F) * k);
+  for (int f = 0; f < F; ++f)
+    for (int c = 0; c < k; ++c)
+      sc[size_t(f) * k + c] = P.k0sq[f] * (cur[fl[c]] ? P.deps : -P.deps);
+  HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
+  HIPCHK(h, hipMemcpyAsync(dF, fl.data(), k * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(dS, sc.data(), size_t(F) * k * sizeof(double), hipMemcpyHostToDevice,
+                           h->stream));
+  const z64 one{1.0, 0.0}, zero{0.0, 0.0};
+  for (int f = 0; f < F; ++f) {
+    Timer t(h, KID_WOOD);
+    // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T)
+    HIPCHK(h, pngf::launch_zgemm(nd, k, nd, P.Cinv[f], ld, nullptr, P.G[f], ld, true, dF, wP, k,
+                                 one, zero, pngf::kWoodSplits, work, h->stream));
+    HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS + size_t(f) * k, cap, h->stream));
+    HIPCHK(h, pngf::launch_small_inverse(cap, k, status, h->stream));
+    // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
+    HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, h->stream));
+    HIPCHK(h, pngf::launch_zgemm(k, nd, k, cap, k, nullptr, wQ, nd, false, nullptr, wW, nd, one,
+                                 zero, 1, nullptr, h->stream));
+    HIPCHK(h, pngf::launch_zgemm(nd, nd, k, wP, k, nullptr, wW, nd, false, nullptr, P.Cinv[f],
+                                 ld, one, one, 1, nullptr, h->stream));
+    t.end();
+  }
+  // (this wait also ends the host copies' reads of fl and sc)
+  int32_t st_host = 0;
+  HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *singular = st_host != 0;
+  return PNGF_OK;
+}
+
 // FP64 refresh of C^-1 for the design in P.bits from the FP64 inverse of the
 // design bits_ref (a mixed search leaves P.Cinv untouched between refreshes):
 // with F the pixels that differ, a block-Woodbury update (eq. lru_woodbury,
@@ -386,8 +449,7 @@ int device_reinvert(pngf_handle* h) {
 // re-inversion when F is larger than kWoodMax or its capacitance matrix is
 // singular.  Then E (with one refinement step), R' and x are re-formed.
 int fp64_refresh(pngf_handle* h) {
-  const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
-  const Layout& L = h->lay;
+  const int nd = h->pc.n_d;
   pngf::ProbDev& P = h->P;
   if (h->opt.precision == PNGF_FP64_PLAIN || h->bits_ref.size() != size_t(nd))
     return device_reinvert(h);
@@ -400,43 +462,10 @@ int fp64_refresh(pngf_handle* h) {
   const int k = int(fl.size());
   if (k > pngf::kWoodMax) return device_reinvert(h);
   if (k > 0) {
-    int32_t* dF = at<int32_t>(h, L.off_wF);
-    double* dS = at<double>(h, L.off_wS);
-    z64* wP = at<z64>(h, L.off_wP);
-    z64* wQ = at<z64>(h, L.off_wQ);
-    z64* wW = at<z64>(h, L.off_wW);
-    z64* cap = at<z64>(h, L.off_wCap);
-    z64* work = at<z64>(h, L.off_wWork);
-    int32_t* status = at<int32_t>(h, L.off_status);
-    std::vector<double> sc(size_t(F) * k);
-    for (int f = 0; f < F; ++f)
-      for (int c = 0; c < k; ++c)
-        sc[size_t(f) * k + c] = P.k0sq[f] * (cur[fl[c]] ? P.deps : -P.deps);
-    HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
-    HIPCHK(h, hipMemcpyAsync(dF, fl.data(), k * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(dS, sc.data(), size_t(F) * k * sizeof(double), hipMemcpyHostToDevice,
-                             h->stream));
-    const z64 one{1.0, 0.0}, zero{0.0, 0.0};
-    for (int f = 0; f < F; ++f) {
-      Timer t(h, KID_WOOD);
-      // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T)
-      HIPCHK(h, pngf::launch_zgemm(nd, k, nd, P.Cinv[f], ld, nullptr, P.G[f], ld, true, dF, wP, k,
-                                   one, zero, pngf::kWoodSplits, work, h->stream));
-      HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS + size_t(f) * k, cap, h->stream));
-      HIPCHK(h, pngf::launch_small_inverse(cap, k, status, h->stream));
-      // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
-      HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, h->stream));
-      HIPCHK(h, pngf::launch_zgemm(k, nd, k, cap, k, nullptr, wQ, nd, false, nullptr, wW, nd, one,
-                                   zero, 1, nullptr, h->stream));
-      HIPCHK(h, pngf::launch_zgemm(nd, nd, k, wP, k, nullptr, wW, nd, false, nullptr, P.Cinv[f],
-                                   ld, one, one, 1, nullptr, h->stream));
-      t.end();
-    }
-    // (this wait also ends the host copies' reads of fl and sc)
-    int32_t st_host = 0;
-    HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (st_host) return device_reinvert(h);
+    bool singular = false;
+    int st = woodbury_update(h, fl, cur, &singular);
+    if (st) return st;
+    if (singular) return device_reinvert(h);
   }
   int st = reform_fields(h);
   if (st) return st;
@@ -719,7 +748,9 @@ int rform_fold(pngf_handle* h, int kp) {
 }
 
 // R-form search (FP64, exact): T0 once, then one O(N_d k) step kernel per
-// accepted flip; the panel is folded into T0 when it is full.
+// accepted flip; the panel is folded into T0 when it is full, and with
+// k_refresh > 0 the whole state is re-anchored on an FP64 C^-1 every
+// k_refresh accepts.
 int run_rform(pngf_handle* h, pngf::DbsState* pinned) {
   int st = ensure_cinv(h);
   if (st) return st;
@@ -748,7 +779,29 @@ int run_rform(pngf_handle* h, pngf::DbsState* pinned) {
     if (st) return st;
     t += batch;
     if (pinned->done) return PNGF_OK;
-    if (pinned->need_refresh) {
+    if (pinned->need_refresh && h->P.k_refresh > 0 && pinned->n_since >= h->P.k_refresh) {
+      // re-anchor: C^-1 for the current design by an FP64 block-Woodbury
+      // update, E, R' and x re-formed from it, T0 rebuilt, every candidate
+      // rescored from C^-1 (the panel's rank-1 terms are dropped)
+      st = fp64_refresh(h);
+      if (st) return st;
+      st = capture_ref_bits(h);
+      if (st) return st;
+      st = build_t0(h);
+      if (st) return st;
+      h->cinv_stale = true;
+      st = read_state(h, pinned);
+      if (st) return st;
+      pinned->kpanel = 0;
+      pinned->n_since = 0;
+      pinned->need_refresh = 0;
+      pinned->exact = 1;
+      st = write_state(h, pinned);
+      if (st) return st;
+      st = start_segment(h);
+      if (st) return st;
+      t = 0;
+    } else if (pinned->need_refresh) {
       st = rform_fold(h, pinned->kpanel);
       if (st) return st;
       pinned->kpanel = 0;
@@ -906,6 +959,8 @@ int pngf_workspace_bytes(pngf_handle* h, const pngf_options* o, size_t* bytes) {
   if (!h || !o || !bytes) return PNGF_EINVAL;
   if (o->precision != PNGF_FP64_PLAIN && o->precision != PNGF_MIXED && o->precision != PNGF_RFORM)
     return fail(h, PNGF_EINVAL, "precision must be PNGF_FP64_PLAIN, PNGF_MIXED or PNGF_RFORM");
+  if (o->max_tile < 0 || o->max_tile > pngf::kWoodMax)
+    return fail(h, PNGF_EINVAL, "max_tile must be in [0, 64]");
   *bytes = make_layout(h, o).total;
   return PNGF_OK;
 }
@@ -917,6 +972,9 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   if (o->k_refresh < 0 || o->k_fold < 0) return fail(h, PNGF_EINVAL, "k_refresh and k_fold must be >= 0");
   if (o->max_accepts < 1 || o->max_sweeps < 1)
     return fail(h, PNGF_EINVAL, "max_accepts and max_sweeps must be >= 1");
+  if (o->max_tile < 0 || o->max_tile > pngf::kWoodMax ||
+      (o->max_tile > 0 && o->precision != PNGF_FP64_PLAIN))
+    return fail(h, PNGF_EINVAL, "max_tile must be in [0, 64], and 0 unless PNGF_FP64_PLAIN");
   if (h->pc.n_d > pngf::kMaxPixels) return fail(h, PNGF_EINVAL, "at most 16384 design pixels");
   if (reinterpret_cast<uintptr_t>(dev_ws) & 255)
     return fail(h, PNGF_EINVAL, "workspace must be 256-byte aligned");
@@ -934,9 +992,12 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   P.ld = h->ld;
   P.nfreq = F;
   P.max_acc = o->max_accepts;
-  P.deps = h->pc.eps_hi - h->pc.eps_lo;
+  // PEC pixels: the transposed j-form is a field-form system with G - I in
+  // place of G and kappa = -1 in place of k0^2 deps (eq. currequiv_j_disc).
+  const bool pec = h->pc.pec;
+  P.deps = pec ? -1.0 : h->pc.eps_hi - h->pc.eps_lo;
   for (int f = 0; f < F; ++f) {
-    P.k0sq[f] = h->pc.freq[f].k0 * h->pc.freq[f].k0;
+    P.k0sq[f] = pec ? 1.0 : h->pc.freq[f].k0 * h->pc.freq[f].k0;
     P.coef[f] = 1.0 / (F * h->pc.freq[f].norm);
     P.G[f] = at<z64>(h, L.off_G[f]);
     P.Cinv[f] = at<z64>(h, L.off_C[f]);
@@ -985,14 +1046,22 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
     }
     P.pm = at<int32_t>(h, L.off_rpm);
     P.kcap = o->k_fold > 0 ? std::min(o->k_fold, pngf::kRPanel) : pngf::kRPanel;
-    P.k_refresh = 0;
+    P.k_refresh = std::min(o->k_refresh, pngf::kWoodMax);
   }
   h->cinv_stale = false;
   // Zero the padded matrix storage once (padding columns are never read, but
   // keep them defined), then upload G.
   HIPCHK(h, hipMemsetAsync(h->ws, 0, L.total, h->stream));
   for (int f = 0; f < F; ++f) {
-    int st = upload_matrix(h, P.G[f], h->pc.freq[f].G, nd);
+    int st;
+    if (pec) {
+      std::vector<cd> Gt(h->pc.freq[f].G);
+      for (int m = 0; m < nd; ++m) Gt[size_t(m) * nd + m] -= 1.0;
+      st = upload_matrix(h, P.G[f], Gt, nd);
+      if (!st) HIPCHK(h, hipStreamSynchronize(h->stream));   // Gt is released next
+    } else {
+      st = upload_matrix(h, P.G[f], h->pc.freq[f].G, nd);
+    }
     if (st) return st;
     HIPCHK(h, hipMemcpyAsync(at<z64>(h, L.off_b[f]), h->pc.freq[f].b.data(), nd * sizeof(z64),
                              hipMemcpyHostToDevice, h->stream));
@@ -1044,6 +1113,50 @@ int pngf_evaluate(pngf_handle* h, double* f, double* x, double* e_d) {
     HIPCHK(h, hipStreamSynchronize(h->stream));
   }
   return PNGF_OK;
+}
+
+int pngf_gradient(pngf_handle* h, double* grad) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  if (!grad) return fail(h, PNGF_EINVAL, "null output");
+  if (h->pc.pec) return fail(h, PNGF_EINVAL, "no permittivity gradient for PEC pixels");
+  double* d = at<double>(h, h->lay.off_df);
+  HIPCHK(h, pngf::launch_gradient(h->P, d, h->stream));
+  HIPCHK(h, hipMemcpyAsync(grad, d, h->pc.n_d * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return PNGF_OK;
+}
+
+int pngf_flip_set(pngf_handle* h, const int32_t* pix, int32_t n) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  if (h->opt.precision == PNGF_MIXED)
+    return fail(h, PNGF_EINVAL, "pixel sets need an FP64_PLAIN or RFORM handle");
+  const int nd = h->pc.n_d;
+  if (n < 0 || (n > 0 && !pix)) return fail(h, PNGF_EINVAL, "bad pixel list");
+  std::vector<uint8_t> seen(nd, 0);
+  for (int r = 0; r < n; ++r) {
+    if (pix[r] < 0 || pix[r] >= nd) return fail(h, PNGF_EINVAL, "pixel out of range");
+    if (seen[pix[r]]++) return fail(h, PNGF_EINVAL, "repeated pixel");
+  }
+  st = ensure_cinv(h);
+  if (st) return st;
+  if (n == 0) return PNGF_OK;
+  HIPCHK(h, hipMemcpyAsync(h->bits.data(), h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int r = 0; r < n; ++r) h->bits[pix[r]] ^= 1;
+  HIPCHK(h, hipMemcpyAsync(h->P.bits, h->bits.data(), nd, hipMemcpyHostToDevice, h->stream));
+  // blocks of at most kWoodMax pixels, each one exact rank-M update
+  bool singular = false;
+  for (int r0 = 0; r0 < n && !singular; r0 += pngf::kWoodMax) {
+    std::vector<int32_t> blk(pix + r0, pix + std::min(n, r0 + pngf::kWoodMax));
+    st = woodbury_update(h, blk, h->bits, &singular);
+    if (st) return st;
+  }
+  st = singular ? device_reinvert(h) : reform_fields(h);
+  if (st) return st;
+  h->cinv_stale = false;
+  return capture_ref_bits(h);
 }
 
 int pngf_score_flips(pngf_handle* h, const int32_t* cand, int32_t n, double* f_new) {
@@ -1116,6 +1229,140 @@ int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t
   hipHostFree(pinned);
   if (rc) return rc;
   return dbs_epilogue(h, fin, f0, n_refresh, n_band, accepted, f_trace, res);
+}
+
+int pngf_tile_dbs_run(pngf_handle* h, const int32_t* tiles, int32_t n_tiles, int32_t m,
+                      const int32_t* perms, int32_t n_sweeps, int32_t* accepted, double* f_trace,
+                      pngf_dbs_result* res) {
+  int st = check_ready(h, true);
+  if (st) return st;
+  const int nd = h->pc.n_d;
+  if (h->opt.precision != PNGF_FP64_PLAIN)
+    return fail(h, PNGF_EINVAL, "the tile search runs on an FP64_PLAIN handle");
+  if (m < 1 || m > h->opt.max_tile)
+    return fail(h, PNGF_EINVAL, "tile size must be in [1, max_tile]");
+  if (!tiles || n_tiles < 1 || n_tiles > nd) return fail(h, PNGF_EINVAL, "n_tiles must be in [1, n_d]");
+  const size_t mr = size_t(pngf::tile_rows(m));
+  const size_t cap = size_t(nd) * pngf::kTilePartPerPixel;
+  if (size_t(n_tiles) * mr * mr > cap)
+    return fail(h, PNGF_EINVAL, "n_tiles * Mpad^2 must not exceed 512 n_d (Mpad = 16, 32 or 64)");
+  // K slices per tile block: enough workgroups to stream the whole chip
+  const int nchunk = (nd + 31) / 32;
+  const int ks = int(std::max<size_t>(1, std::min<size_t>({size_t(pngf::kTileSlicesMax),
+      cap / (size_t(n_tiles) * mr * mr), size_t(nchunk), size_t((2048 + n_tiles - 1) / n_tiles)})));
+  if (!perms || n_sweeps < 1 || n_sweeps > h->opt.max_sweeps)
+    return fail(h, PNGF_EINVAL, "n_sweeps must be in [1, max_sweeps]");
+  std::vector<std::vector<int32_t>> members(n_tiles);
+  {
+    std::vector<int32_t> seen(nd, -1);
+    for (int t = 0; t < n_tiles; ++t) {
+      bool pad = false;
+      for (int c = 0; c < m; ++c) {
+        const int32_t p = tiles[size_t(t) * m + c];
+        if (p == -1) { pad = true; continue; }
+        if (pad || p < 0 || p >= nd || seen[p] == t)
+          return fail(h, PNGF_EINVAL, "tiles: distinct pixel ids, -1 only as trailing padding");
+        seen[p] = t;
+        members[t].push_back(p);
+      }
+      if (members[t].empty()) return fail(h, PNGF_EINVAL, "tiles: every tile needs a pixel");
+    }
+    std::vector<int32_t> chk(n_tiles);
+    for (int s = 0; s < n_sweeps; ++s) {
+      std::fill(chk.begin(), chk.end(), 0);
+      for (int q = 0; q < n_tiles; ++q) {
+        const int32_t t = perms[size_t(s) * n_tiles + q];
+        if (t < 0 || t >= n_tiles || chk[t]++)
+          return fail(h, PNGF_EINVAL, "perms must hold permutations of the tile ids");
+      }
+    }
+  }
+  int32_t* dtiles = at<int32_t>(h, h->lay.off_tiles);
+  double* ddf = at<double>(h, h->lay.off_df);
+  HIPCHK(h, hipMemcpyAsync(dtiles, tiles, size_t(n_tiles) * m * sizeof(int32_t),
+                           hipMemcpyHostToDevice, h->stream));
+  for (int k = 0; k < KID_N; ++k) { h->ktime_ms[k] = 0.0; h->klaunch[k] = 0; }
+  pngf::DbsState s0;
+  st = read_state(h, &s0);
+  if (st) return st;
+  HIPCHK(h, hipMemcpyAsync(h->bits.data(), h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const double f0 = s0.f;
+  double f = f0;
+  const double eta = h->opt.eta;
+  std::vector<double> df(n_tiles);
+  std::vector<int32_t> acc_log;
+  std::vector<double> f_log;
+  int64_t attempts = 0;
+  int sweeps = 0, n_reinv = 0;
+  bool converged = false, fresh = false;
+  // the sequential search of the paper: scores stay valid until an accept
+  for (int s = 0; s < n_sweeps && !converged; ++s) {
+    if (int(acc_log.size()) >= h->opt.max_accepts) break;
+    sweeps = s + 1;
+    bool any = false;
+    int pos = 0;
+    while (pos < n_tiles) {
+      if (!fresh) {
+        Timer t(h, KID_TILE);
+        HIPCHK(h, pngf::launch_tile_score(h->P, dtiles, n_tiles, m, ks,
+                                          at<z64>(h, h->lay.off_tpart), ddf, h->stream));
+        t.end();
+        HIPCHK(h, hipMemcpyAsync(df.data(), ddf, n_tiles * sizeof(double), hipMemcpyDeviceToHost,
+                                 h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        fresh = true;
+      }
+      int q = pos;
+      for (; q < n_tiles; ++q) {
+        ++attempts;
+        if (df[perms[size_t(s) * n_tiles + q]] > eta * f) break;
+      }
+      if (q == n_tiles) break;
+      // accept tile perms[s][q]: flip its pixels, update C^-1, re-form fields
+      const int32_t t = perms[size_t(s) * n_tiles + q];
+      for (int32_t p : members[t]) h->bits[p] ^= 1;
+      HIPCHK(h, hipMemcpyAsync(h->P.bits, h->bits.data(), nd, hipMemcpyHostToDevice, h->stream));
+      bool singular = false;
+      st = woodbury_update(h, members[t], h->bits, &singular);
+      if (st) return st;
+      if (singular) {
+        st = device_reinvert(h);
+        if (st) return st;
+        ++n_reinv;
+      } else {
+        st = reform_fields(h);
+        if (st) return st;
+      }
+      pngf::DbsState sn;
+      st = read_state(h, &sn);
+      if (st) return st;
+      f = sn.f;
+      if (!std::isfinite(f)) return fail(h, PNGF_ENUMERIC, "objective is not finite");
+      acc_log.push_back(t);
+      f_log.push_back(f);
+      fresh = false;
+      any = true;
+      pos = q + 1;
+      if (int(acc_log.size()) >= h->opt.max_accepts) break;
+    }
+    if (!any) converged = true;
+  }
+  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  const int na = int(acc_log.size());
+  if (accepted && na) std::memcpy(accepted, acc_log.data(), na * sizeof(int32_t));
+  if (f_trace && na) std::memcpy(f_trace, f_log.data(), na * sizeof(double));
+  if (res) {
+    res->n_accepted = na;
+    res->sweeps = sweeps;
+    res->converged = converged ? 1 : 0;
+    res->n_refresh = n_reinv;
+    res->attempts = attempts;
+    res->n_verified = 0;
+    res->f_initial = f0;
+    res->f_final = f;
+  }
+  return PNGF_OK;
 }
 
 int pngf_kernel_times(pngf_handle* h, int32_t kid, double* total_ms, int64_t* launches) {

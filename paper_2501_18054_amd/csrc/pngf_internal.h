@@ -33,6 +33,7 @@ struct Precomputed {
   Grid grid;
   int n_d = 0;
   double eps_lo = 1.0, eps_hi = 1.0;
+  bool pec = false;                    // PEC pixels (pixel_kind PNGF_PIXEL_PEC)
   std::vector<int64_t> design_nodes;   // flat node ids of pixels, pixel order
   std::vector<FreqData> freq;
   double seconds = 0.0;

@@ -16,7 +16,9 @@ def say(msg):
 
 
 def golden(i):
-    path = os.path.join(GOLDEN, f"dbs_config{i}.json")
+    """Golden trajectory of workload i (an int) or of a named one ("metal")."""
+    tag = i if isinstance(i, str) else f"config{i}"
+    path = os.path.join(GOLDEN, f"dbs_{tag}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:

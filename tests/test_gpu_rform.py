@@ -4,7 +4,8 @@ oracle's FP64 trajectory.
 
 Bar: identical accepted-flip sequence and attempt count, per-step objectives
 within 1e-10 relative, fields of the final design within 1e-10 of a fresh
-full solve.  Small panel capacities force many folds of the panel into T0.
+full solve.  Small panel capacities force many folds of the panel into T0;
+k_refresh re-anchors the state on an FP64 C^-1 (alone and between folds).
 """
 import numpy as np
 import pytest
@@ -52,14 +53,14 @@ def test_rform_config0_identical():
     h.close()
 
 
-@pytest.mark.parametrize("k_fold", [0, 7, 64])
-def test_rform_config1_identical(k_fold):
+@pytest.mark.parametrize("k_fold,k_refresh", [(0, 0), (7, 0), (64, 0), (0, 32), (16, 40)])
+def test_rform_config1_identical(k_fold, k_refresh):
     g = golden(1)
     if g is None:
         pytest.skip("golden trajectory for workload 1 not generated")
     p = workloads.config1()
-    say(f"config1 rform panel capacity {k_fold or 512}")
-    h, res = _rform(p, k_fold=k_fold)
+    say(f"config1 rform panel capacity {k_fold or 512}, re-anchor every {k_refresh}")
+    h, res = _rform(p, k_fold=k_fold, k_refresh=k_refresh)
     _check(res, g)
     f, x, E = h.evaluate(fields=True)
     Eo, xo = oracle.pngf_state(p, _final_bits(p, res), 0)

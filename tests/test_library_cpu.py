@@ -112,3 +112,17 @@ def test_unbound_calls_fail_cleanly():
         h.set_design(np.zeros(4, np.uint8))
     assert e.value.code == -5
     h.close()
+
+
+def test_precompute_pec_pixels():
+    """PEC pixels share the environment's G, b, G_OD, x_b; an unknown pixel
+    kind is rejected."""
+    p = workloads.tiny_metal(seed=8, n=20, side=3)
+    h = P.Handle(p)
+    G, b, god, xb = h.get_precompute(0)
+    assert np.max(np.abs(G - oracle.green_dd(p, 0))) < 1e-10 * np.max(np.abs(G))
+    h.close()
+    p.pixel_kind = 7
+    with pytest.raises(P.PngfError) as e:
+        P.Handle(p)
+    assert e.value.code == -1

@@ -55,16 +55,15 @@ def test_pec_is_the_large_conductivity_limit():
 
 
 def test_current_satisfies_the_paper_j_form():
-    """[(I-P) + P G] j = P e_inc and x = x_inc + G_obj j, with the paper's
-    sign convention (field = e_inc - G j): j = -j_oracle, G_obj = -G_OD."""
+    """[(I-P) + P G] j = P e_inc and x = x_inc + G_obj j in the paper's sign
+    convention (field = e_inc - G j), where G_obj = -G_OD."""
     p = workloads.tiny_metal(seed=22, n=22, side=4)
     G, God, b, xb = _pieces(p)
     rng = np.random.default_rng(7)
     for _ in range(3):
         bits = (rng.random(p.n_d) < 0.5).astype(np.uint8)
         P = np.diag(bits.astype(float))
-        E, jo = oracle.equivalent_current(p, bits, 0)
-        j = -jo
+        E, j = oracle.equivalent_current(p, bits, 0)
         C = (np.eye(p.n_d) - P) + P @ G
         lhs = C @ j
         assert np.max(np.abs(lhs - P @ b)) < 1e-10 * np.max(np.abs(b))
@@ -77,16 +76,16 @@ def test_current_satisfies_the_paper_j_form():
 
 
 def test_single_pec_pixel_closed_form():
-    """One conductor m: G_mm j_m = -b_m, E_D = b + G[:, m] j_m,
-    x = x_b + G_OD[m] j_m."""
+    """One conductor m: G_mm j_m = b_m, E_D = b - G[:, m] j_m,
+    x = x_b - G_OD[m] j_m."""
     p = workloads.tiny_metal(seed=23, n=20, side=3)
     G, God, b, xb = _pieces(p)
     for m in (0, 4, 8):
         bits = np.zeros(p.n_d, np.uint8)
         bits[m] = 1
-        jm = -b[m] / G[m, m]
-        Ed = b + G[:, m] * jm
-        x = xb + God[m] * jm
+        jm = b[m] / G[m, m]
+        Ed = b - G[:, m] * jm
+        x = xb - God[m] * jm
         z, xf = oracle.pec_state(p, bits, 0)
         zref = Ed.copy()
         zref[m] = jm
@@ -95,21 +94,21 @@ def test_single_pec_pixel_closed_form():
 
 
 def test_two_pec_pixels_closed_form():
-    """Two conductors a, c: the 2x2 system G_SS j_S = -b_S by Cramer's rule."""
+    """Two conductors a, c: the 2x2 system G_SS j_S = b_S by Cramer's rule."""
     p = workloads.tiny_metal(seed=24, n=20, side=3)
     G, God, b, xb = _pieces(p)
     a, c = 1, 7
     bits = np.zeros(p.n_d, np.uint8)
     bits[[a, c]] = 1
     det = G[a, a] * G[c, c] - G[a, c] * G[c, a]
-    ja = (-b[a] * G[c, c] + b[c] * G[a, c]) / det
-    jc = (-b[c] * G[a, a] + b[a] * G[c, a]) / det
-    Ed = b + G[:, a] * ja + G[:, c] * jc
+    ja = (b[a] * G[c, c] - b[c] * G[a, c]) / det
+    jc = (b[c] * G[a, a] - b[a] * G[c, a]) / det
+    Ed = b - G[:, a] * ja - G[:, c] * jc
     z, xf = oracle.pec_state(p, bits, 0)
     assert abs(z[a] - ja) < 1e-11 * abs(ja) and abs(z[c] - jc) < 1e-11 * abs(jc)
     others = np.setdiff1d(np.arange(p.n_d), [a, c])
     assert np.max(np.abs(z[others] - Ed[others])) < 1e-11 * np.max(np.abs(Ed))
-    assert abs(xb + God[a] * ja + God[c] * jc - xf) < 1e-11 * abs(xf)
+    assert abs(xb - God[a] * ja - God[c] * jc - xf) < 1e-11 * abs(xf)
 
 
 def test_no_conductor_is_the_background():
