@@ -71,7 +71,7 @@ constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
 constexpr int kTilePartPerPixel = 512;   // tile-score partial blocks (complex) per pixel
-constexpr int kTileSlicesMax = 8;        // K slices of one tile's block
+constexpr int kTileSlicesMax = 32;       // K slices of one tile's block
 constexpr int kWoodSplits = 8;     // split-K factor of its skinny GEMM
 constexpr int kRPanel = 512;       // R-form panel capacity before a fold into T0
 constexpr int kDriftEvery = 32;    // accepts between drift checks
@@ -1249,7 +1249,7 @@ int pngf_tile_dbs_run(pngf_handle* h, const int32_t* tiles, int32_t n_tiles, int
   // K slices per tile block: enough workgroups to stream the whole chip
   const int nchunk = (nd + 31) / 32;
   const int ks = int(std::max<size_t>(1, std::min<size_t>({size_t(pngf::kTileSlicesMax),
-      cap / (size_t(n_tiles) * mr * mr), size_t(nchunk), size_t((2048 + n_tiles - 1) / n_tiles)})));
+      cap / (size_t(n_tiles) * mr * mr), size_t(nchunk), size_t((4096 + n_tiles - 1) / n_tiles)})));
   if (!perms || n_sweeps < 1 || n_sweeps > h->opt.max_sweeps)
     return fail(h, PNGF_EINVAL, "n_sweeps must be in [1, max_sweeps]");
   std::vector<std::vector<int32_t>> members(n_tiles);

@@ -472,6 +472,156 @@ __device__ inline void mixed_step_group(const ProbDev& P, int g, int spar, int k
   }
 }
 
+// Single-frequency mixed step for rows of at most 64 PRE columns, with the
+// decision split from the streaming: wave 0 only decides (its thread 0 issues
+// no loads ahead of the state and key reads, whose wait would otherwise also
+// cover every earlier load of the wave), while waves 1-4 load their two
+// C0^-1 rows whole into registers meanwhile.  After the decision the g_m
+// chunks are issued together, so the GEMV costs about one memory round trip.
+// Same arithmetic as mixed_step_group (FP32 products, FP64 vectors).
+constexpr int kSplitThreads = 64 * (1 + kMixRows / 2);
+
+template <int PRE>
+__global__ __launch_bounds__(kSplitThreads) void k_mixed_step_split(ProbDev P, int spar,
+                                                                    int kslot) {
+  __shared__ StepCtx c;
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const bool worker = w > 0;
+  const int ra = g * kMixRows + 2 * (w - 1), rb = ra + 1;
+  const bool va = worker && ra < P.nd, vb = worker && rb < P.nd;
+  const int dp = spar;
+  z32 pa[PRE], pb[PRE];
+#pragma unroll
+  for (int q = 0; q < PRE; ++q) {
+    const int j = lane + 64 * q;
+    pa[q] = z32{0.f, 0.f};
+    pb[q] = z32{0.f, 0.f};
+    if (j < P.nd) {
+      if (va) pa[q] = P.C0[0][size_t(ra) * P.ld + j];
+      if (vb) pb[q] = P.C0[0][size_t(rb) * P.ld + j];
+    }
+  }
+  const uint8_t* bin = dp ? P.bitsB : P.bits;
+  uint8_t* bout = dp ? P.bits : P.bitsB;
+  z64 e0a{0.0, 0.0}, r0a{0.0, 0.0}, t0a{0.0, 0.0}, e0b{0.0, 0.0}, r0b{0.0, 0.0}, t0b{0.0, 0.0};
+  uint8_t b0a = 0, b0b = 0;
+  // visiting positions of the two rows in the sweeps the new cursor can be
+  // in (the decision moves it by at most two sweeps): the key of a row needs
+  // its position in the cursor's sweep and, behind the cursor, in the next
+  int s0 = 0, rka[4] = {0, 0, 0, 0}, rkb[4] = {0, 0, 0, 0};
+  if (lane == 0 && worker) {
+    const DbsState* sin = spar ? P.stB : P.st;
+    s0 = sin->cursor_s;
+    const int ns = sin->n_sweeps;
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      if (s0 + d < ns) {
+        if (va) rka[d] = P.rank[size_t(s0 + d) * P.nd + ra];
+        if (vb) rkb[d] = P.rank[size_t(s0 + d) * P.nd + rb];
+      }
+  }
+  if (lane == 0 && worker) {
+    if (va) {
+      b0a = bin[ra];
+      e0a = (dp ? P.EB[0] : P.E[0])[ra];
+      r0a = (dp ? P.RpB[0] : P.Rp[0])[ra];
+      t0a = (dp ? P.tauB[0] : P.tau[0])[ra];
+    }
+    if (vb) {
+      b0b = bin[rb];
+      e0b = (dp ? P.EB[0] : P.E[0])[rb];
+      r0b = (dp ? P.RpB[0] : P.Rp[0])[rb];
+      t0b = (dp ? P.tauB[0] : P.tau[0])[rb];
+    }
+  }
+  if (tid == 0) step_decide(P, spar, kslot, true, c);
+  __syncthreads();
+  if (g == 0) step_publish(P, spar, kslot, true, c);
+  const int m = c.m;
+  if (m < 0 || !worker) return;
+  const int slot = c.slot;
+  // panel coefficient alpha_k p_k[m] of this lane's slot (reciprocity:
+  // q_k . g_m = p_k[m]), loaded with the g_m chunks
+  z64 cc{0.0, 0.0};
+  if (lane < slot) cc = zmul(P.alph[0][lane], up32(P.Pp[0][size_t(lane) * P.ld + m]));
+  const z32* gm = P.G32[0] + size_t(m) * P.ld;
+  z32 gv[PRE];
+#pragma unroll
+  for (int q = 0; q < PRE; ++q) {
+    const int j = lane + 64 * q;
+    gv[q] = j < P.nd ? gm[j] : z32{0.f, 0.f};
+  }
+  float par = 0.f, pai = 0.f, pbr = 0.f, pbi = 0.f;
+#pragma unroll
+  for (int q = 0; q < PRE; ++q) {
+    par = fmaf(pa[q].re, gv[q].re, fmaf(-pa[q].im, gv[q].im, par));
+    pai = fmaf(pa[q].re, gv[q].im, fmaf(pa[q].im, gv[q].re, pai));
+    pbr = fmaf(pb[q].re, gv[q].re, fmaf(-pb[q].im, gv[q].im, pbr));
+    pbi = fmaf(pb[q].re, gv[q].im, fmaf(pb[q].im, gv[q].re, pbi));
+  }
+  if (lane < slot) {
+    if (va) {
+      const z32 pk = P.Pp[0][size_t(lane) * P.ld + ra];
+      par += float(cc.re * pk.re - cc.im * pk.im);
+      pai += float(cc.re * pk.im + cc.im * pk.re);
+    }
+    if (vb) {
+      const z32 pk = P.Pp[0][size_t(lane) * P.ld + rb];
+      pbr += float(cc.re * pk.re - cc.im * pk.im);
+      pbi += float(cc.re * pk.im + cc.im * pk.re);
+    }
+  }
+  par = wave_sumf(par);
+  pai = wave_sumf(pai);
+  pbr = wave_sumf(pbr);
+  pbi = wave_sumf(pbi);
+  if (lane != 0) return;
+  const uint8_t bita = b0a ^ (ra == m ? 1 : 0), bitb = b0b ^ (rb == m ? 1 : 0);
+  for (int h = 0; h < 2; ++h) {
+    const int r = h ? rb : ra;
+    if (!(h ? vb : va)) continue;
+    const z32 p32{h ? pbr : par, h ? pbi : pai};
+    P.Pp[0][size_t(slot) * P.ld + r] = p32;
+    const z64 p = up32(p32);
+    const z64 ap = zmul(c.alpha[0], p);
+    const z64 Ei = zadd(h ? e0b : e0a, zmul(ap, c.Em[0]));
+    const z64 Rpi = zadd(h ? r0b : r0a, zmul(ap, c.Rpm[0]));
+    const z64 tau = zadd(h ? t0b : t0a, zmul(ap, p));
+    (dp ? P.E[0] : P.EB[0])[r] = Ei;
+    (dp ? P.Rp[0] : P.RpB[0])[r] = Rpi;
+    (dp ? P.tau[0] : P.tauB[0])[r] = tau;
+    const uint8_t bit = h ? bitb : bita;
+    double df = 0.0, bnd = 0.0;
+    score_terms(P, c, 0, tau, Ei, Rpi, bit ? -P.deps : P.deps, df, bnd);
+    bout[r] = bit;
+    P.df32[r] = df;
+    P.dfb[r] = bnd;
+    const double margin = df - c.eta * c.f;
+    const double band = P.band * bnd;
+    if (margin >= -band && c.cs < c.ns) {
+      // step_key from the prefetched positions (c.cs - s0 is 0, 1 or 2)
+      const int* rk = h ? rkb : rka;
+      const int d = c.cs - s0;
+      int pos = -1;
+#pragma unroll
+      for (int u = 0; u < 3; ++u)
+        if (u == d) pos = rk[u];
+      uint32_t k = kNoKey;
+      if (pos >= c.cp) {
+        k = pack_key(pos, r);
+      } else if (c.cs + 1 < c.ns) {
+        int nxt = 0;
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (u == d) nxt = rk[u + 1];
+        k = pack_key(P.nd + nxt, r);
+      }
+      if (k != kNoKey) atomicMin(&P.keys[(margin > band ? 0 : 3) + (kslot + 1) % 3], k);
+    }
+  }
+}
+
 template <int NPL>
 __global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar, int kslot) {
   __shared__ StepCtx c;
@@ -687,8 +837,16 @@ hipError_t launch_plain_step(const ProbDev& P, int npl, int step, hipStream_t s)
 
 hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s) {
   (void)npl;
-  hipLaunchKernelGGL(k_mixed_step, dim3((P.nd + kMixRows - 1) / kMixRows), dim3(256), 0, s, P,
-                     step & 1, step % 3);
+  const dim3 grid((P.nd + kMixRows - 1) / kMixRows);
+  const int sp = step & 1, ks = step % 3;
+  if (P.nfreq == 1 && P.nd <= 64 * 8)
+    hipLaunchKernelGGL(k_mixed_step_split<8>, grid, dim3(kSplitThreads), 0, s, P, sp, ks);
+  else if (P.nfreq == 1 && P.nd <= 64 * 16)
+    hipLaunchKernelGGL(k_mixed_step_split<16>, grid, dim3(kSplitThreads), 0, s, P, sp, ks);
+  else if (P.nfreq == 1 && P.nd <= 64 * 32)
+    hipLaunchKernelGGL(k_mixed_step_split<32>, grid, dim3(kSplitThreads), 0, s, P, sp, ks);
+  else
+    hipLaunchKernelGGL(k_mixed_step, grid, dim3(256), 0, s, P, sp, ks);
   return hipGetLastError();
 }
 

@@ -22,7 +22,8 @@
 //     Slicing K gives ntiles x KS workgroups, so the chain of chunk loads of
 //     one workgroup is short and the whole chip streams.
 //   k_tile_solve: workgroup t sums the slices, solves (I - T_SS D) y = E[S]
-//     by Gauss-Jordan with partial pivoting in LDS, and adds
+//     by Gauss-Jordan with partial pivoting in LDS (pivot rows recorded, not
+//     swapped: two barriers per column), and adds
 //     dx = sum_i R'[s_i] d_i y_i,  df_f = coef (2 Re(conj(x) dx) + |dx|^2)
 //     to the tile's score.  A singular capacitance gives NaN (never accepted).
 #include "dev_state.h"
@@ -138,14 +139,15 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_solve(ProbDev P, const in
   __shared__ z64 Ax[MR * LDA];
   __shared__ int pix[MR];
   __shared__ double dsc[MR];
-  __shared__ z64 fac[MR];
-  __shared__ int s_piv;
+  __shared__ int rowof[MR];   // physical row of the pivot of each column
+  __shared__ int used[MR];
   __shared__ int s_bad;
   const int t = blockIdx.x;
   if (t >= ntiles) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int ti = tid >> 4, tj = tid & 15;
   if (tid == 0) s_bad = 0;
+  if (tid < MR) used[tid] = 0;
   const int mt = tile_load_pix<MR>(tiles, t, m, pix);
   if (tid < MR) {
     const int p = pix[tid];
@@ -161,6 +163,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_solve(ProbDev P, const in
       const int i = ti + 16 * a, j = tj + 16 * b;
       if (i < mt && j < mt) {
         z64 v{0.0, 0.0};
+#pragma unroll 8
         for (int s = 0; s < ks; ++s) v = zadd(v, pb[size_t(s) * MR * MR + i * MR + j]);
         const double dj = dsc[j];
         v = z64{-v.re * dj, -v.im * dj};
@@ -170,13 +173,17 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_solve(ProbDev P, const in
     }
   if (tid < mt) Ax[tid * LDA + mt] = P.E[f][pix[tid]];
   __syncthreads();
+  // Gauss-Jordan with partial pivoting; pivot rows are recorded instead of
+  // swapped, and every thread forms its own row's factor, so a column costs
+  // two barriers.
   for (int c = 0; c < mt; ++c) {
     if (wid == 0) {
       double best = -1.0;
-      int bi = c;
-      for (int i = c + lane; i < mt; i += 64) {
+      int bi = MR;
+      for (int i = lane; i < mt; i += 64) {
+        if (used[i]) continue;
         const double v = zabs2(Ax[i * LDA + c]);
-        if (v > best) { best = v; bi = i; }
+        if (v > best || (v == best && i < bi)) { best = v; bi = i; }
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
@@ -185,39 +192,38 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_solve(ProbDev P, const in
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
       if (lane == 0) {
-        s_piv = bi;
-        if (!(best > 0.0)) s_bad = 1;
+        if (!(best > 0.0) || bi >= mt) {
+          s_bad = 1;
+          bi = 0;
+          for (int i = 0; i < mt; ++i)
+            if (!used[i]) { bi = i; break; }
+        }
+        rowof[c] = bi;
+        used[bi] = 1;
       }
     }
     __syncthreads();
-    const int p = s_piv;
-    if (p != c)
-      for (int j = tid; j <= mt; j += kTileThreads) {
-        const z64 tmp = Ax[c * LDA + j];
-        Ax[c * LDA + j] = Ax[p * LDA + j];
-        Ax[p * LDA + j] = tmp;
-      }
-    __syncthreads();
-    if (tid < mt && tid != c) {
-      const z64 piv = Ax[c * LDA + c];
-      fac[tid] = zabs2(piv) > 0.0 ? zdiv(Ax[tid * LDA + c], piv) : z64{0.0, 0.0};
-    }
-    __syncthreads();
+    const int pr = rowof[c];
+    const z64 piv = Ax[pr * LDA + c];
+    const bool ok = zabs2(piv) > 0.0;
     const int w = mt - c;  // columns c+1 .. mt (rhs included)
     for (int e = tid; e < mt * w; e += kTileThreads) {
       const int i = e / w, j = c + 1 + e % w;
-      if (i != c) Ax[i * LDA + j] = zsub(Ax[i * LDA + j], zmul(fac[i], Ax[c * LDA + j]));
+      if (i != pr && ok) {
+        const z64 fac = zdiv(Ax[i * LDA + c], piv);
+        Ax[i * LDA + j] = zsub(Ax[i * LDA + j], zmul(fac, Ax[pr * LDA + j]));
+      }
     }
     __syncthreads();
   }
-  // dx = sum_i R'[s_i] d_i y_i with y_i = rhs_i / pivot_i (Gauss-Jordan swaps
-  // equations, not unknowns, so unknown i stays pixel pix[i])
+  // dx = sum_c R'[s_c] d_c y_c with y_c = rhs / pivot of column c's pivot row
   if (wid == 0) {
     z64 dx{0.0, 0.0};
-    for (int i = lane; i < mt; i += 64) {
-      const z64 piv = Ax[i * LDA + i];
-      const z64 y = zabs2(piv) > 0.0 ? zdiv(Ax[i * LDA + mt], piv) : z64{0.0, 0.0};
-      dx = zadd(dx, zscale(zmul(P.Rp[f][pix[i]], y), dsc[i]));
+    for (int cc = lane; cc < mt; cc += 64) {
+      const int r = rowof[cc];
+      const z64 piv = Ax[r * LDA + cc];
+      const z64 y = zabs2(piv) > 0.0 ? zdiv(Ax[r * LDA + mt], piv) : z64{0.0, 0.0};
+      dx = zadd(dx, zscale(zmul(P.Rp[f][pix[cc]], y), dsc[cc]));
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
