@@ -193,31 +193,35 @@ __global__ __launch_bounds__(256) void k_wood_cap(const z64* P, int ldp, const i
   Cap[e] = z64{(a == c ? 1.0 : 0.0) - p.re, -p.im};
 }
 
-// In-place inverse of a k x k complex matrix (k <= kSmallInv) by Gauss-Jordan
-// elimination with partial pivoting and physical row interchanges; the
-// column interchanges they imply are undone at the end in reverse order.
-// One workgroup; the matrix lives in LDS.  status is set on a zero pivot.
+// Inverse of a k x k complex matrix (k <= kSmallInv), in place in A, by
+// Gauss-Jordan elimination with partial pivoting.  One workgroup; the matrix
+// ping-pongs between two LDS copies, so a column costs two barriers: wave 0
+// picks the pivot row p, then every thread writes one entry of the next copy,
+// with rows c and p exchanged on the way (M[c] <- M[p] / piv with 1 / piv in
+// column c; M[r] <- M[r] - M[r][c] M[c] / piv with -M[r][c] / piv in column c).
+// The column interchanges implied by the row exchanges are undone at the end
+// in one pass.  status is set on a zero pivot.
 constexpr int kSmallInv = 64;
 constexpr int kSmallInvThreads = 256;
 
 __global__ __launch_bounds__(kSmallInvThreads) void k_small_inverse(z64* A, int k, int32_t* status) {
-  __shared__ double Mr[kSmallInv][kSmallInv + 1], Mi[kSmallInv][kSmallInv + 1];
-  __shared__ double fr[kSmallInv], fi[kSmallInv];
+  __shared__ z64 M[2][kSmallInv][kSmallInv + 1];
   __shared__ int perm[kSmallInv];
+  __shared__ int cmap[kSmallInv];
   __shared__ int s_p;
   const int tid = threadIdx.x;
-  for (int e = tid; e < k * k; e += kSmallInvThreads) {
-    Mr[e / k][e % k] = A[e].re;
-    Mi[e / k][e % k] = A[e].im;
-  }
+  for (int e = tid; e < k * k; e += kSmallInvThreads) M[0][e / k][e % k] = A[e];
   __syncthreads();
+  int cur = 0;
   for (int c = 0; c < k; ++c) {
-    // pivot: largest |M[r][c]| over r >= c (the first of equals)
+    const z64 (*X)[kSmallInv + 1] = M[cur];
+    z64 (*Y)[kSmallInv + 1] = M[cur ^ 1];
+    // pivot: largest |X[r][c]| over r >= c (the first of equals)
     if (tid < 64) {
       double best = -1.0;
       int bidx = k;
       for (int r = c + tid; r < k; r += 64) {
-        const double a = Mr[r][c] * Mr[r][c] + Mi[r][c] * Mi[r][c];
+        const double a = zabs2(X[r][c]);
         if (a > best) { best = a; bidx = r; }
       }
 #pragma unroll
@@ -237,48 +241,36 @@ __global__ __launch_bounds__(kSmallInvThreads) void k_small_inverse(z64* A, int 
     }
     __syncthreads();
     const int p = s_p;
-    if (p != c)
-      for (int j = tid; j < k; j += kSmallInvThreads) {
-        double t = Mr[c][j]; Mr[c][j] = Mr[p][j]; Mr[p][j] = t;
-        t = Mi[c][j]; Mi[c][j] = Mi[p][j]; Mi[p][j] = t;
-      }
-    __syncthreads();
-    // pivot row: M[c][c] <- 1 / piv, M[c][j] <- M[c][j] / piv; save column c
-    const z64 inv = zdiv(z64{1.0, 0.0}, z64{Mr[c][c], Mi[c][c]});
-    for (int r = tid; r < k; r += kSmallInvThreads) { fr[r] = Mr[r][c]; fi[r] = Mi[r][c]; }
-    __syncthreads();
-    for (int j = tid; j < k; j += kSmallInvThreads) {
-      const z64 v = (j == c) ? inv : zmul(z64{Mr[c][j], Mi[c][j]}, inv);
-      Mr[c][j] = v.re;
-      Mi[c][j] = v.im;
-    }
-    __syncthreads();
-    // other rows: M[r][j] <- (j == c ? 0 : M[r][j]) - f_r M[c][j]
+    const z64 piv = X[p][c];
+    const z64 inv = zabs2(piv) > 0.0 ? zdiv(z64{1.0, 0.0}, piv) : z64{0.0, 0.0};
     for (int e = tid; e < k * k; e += kSmallInvThreads) {
       const int r = e / k, j = e % k;
-      if (r == c) continue;
-      const z64 pr{Mr[c][j], Mi[c][j]};
-      const z64 old = (j == c) ? z64{0.0, 0.0} : z64{Mr[r][j], Mi[r][j]};
-      const z64 v = zsub(old, zmul(z64{fr[r], fi[r]}, pr));
-      Mr[r][j] = v.re;
-      Mi[r][j] = v.im;
+      const z64 prow = (j == c) ? inv : zmul(X[p][j], inv);   // new pivot row
+      if (r == c) {
+        Y[c][j] = prow;
+      } else {
+        const int sr = (r == p) ? c : r;      // row r of the exchanged matrix
+        const z64 f = X[sr][c];
+        const z64 old = (j == c) ? z64{0.0, 0.0} : X[sr][j];
+        Y[r][j] = zsub(old, zmul(f, prow));
+      }
     }
     __syncthreads();
+    cur ^= 1;
   }
-  // undo the column interchanges, last first
-  for (int c = k - 1; c >= 0; --c) {
-    const int p = perm[c];
-    if (p != c)
-      for (int r = tid; r < k; r += kSmallInvThreads) {
-        double t = Mr[r][c]; Mr[r][c] = Mr[r][p]; Mr[r][p] = t;
-        t = Mi[r][c]; Mi[r][c] = Mi[r][p]; Mi[r][p] = t;
-      }
-    __syncthreads();
+  // the row exchanges of columns c (rows c, perm[c]) become column exchanges
+  // of the inverse, undone last first: cmap[j] = source column of column j
+  if (tid == 0) {
+    for (int j = 0; j < k; ++j) cmap[j] = j;
+    for (int c = k - 1; c >= 0; --c) {
+      const int q = perm[c];
+      const int tmp = cmap[c];
+      cmap[c] = cmap[q];
+      cmap[q] = tmp;
+    }
   }
-  for (int e = tid; e < k * k; e += kSmallInvThreads) {
-    A[e].re = Mr[e / k][e % k];
-    A[e].im = Mi[e / k][e % k];
-  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += kSmallInvThreads) A[e] = M[cur][e / k][cmap[e % k]];
 }
 
 // ------------------------------------------------------------------ launchers
