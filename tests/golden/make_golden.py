@@ -1,10 +1,11 @@
 """Writes the golden DBS trajectories from the CPU oracle (full re-solves).
 
 Calls only ``oracle`` and ``workloads``.  Usage:
-    python tests/golden/make_golden.py 0 [1] [metal] [tiles1] [--workers N]
+    python tests/golden/make_golden.py 0 [1] [metal] [tiles1] [config4_scaled] [--workers N]
 Writes tests/golden/dbs_config{i}.json (dbs_metal.json for the PEC-pixel
 workload ``workloads.metal()``, dbs_tiles1.json for the 4x4-tile search
-``workloads.tiles1()``, whose accepted entries name tiles) with the accepted flips
+``workloads.tiles1()``, whose accepted entries name tiles, dbs_config4_scaled.json
+for the eight-frequency ``workloads.config4_scaled()``) with the accepted flips
 (sweep, position, pixel, f_new), the initial and final objective, the number
 of attempted flips, and any near-ties within 1e-7 of the acceptance threshold.
 """
@@ -31,7 +32,8 @@ def main():
     ap.add_argument("--workers", type=int, default=1)
     a = ap.parse_args()
     for c in a.configs:
-        named = {"metal": workloads.metal, "tiles1": workloads.tiles1}
+        named = {"metal": workloads.metal, "tiles1": workloads.tiles1,
+                 "config4_scaled": workloads.config4_scaled}
         p = named[c]() if c in named else workloads.make_config(int(c))
         tag = c if c in named else f"config{c}"
         tk = {} if p.tiles is None else {"perms": p.tile_perms, "tiles": p.tiles}

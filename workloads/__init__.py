@@ -276,6 +276,24 @@ def config4(seed: int = 4, n_sweeps: int = 20) -> Problem:
         n_sweeps=n_sweeps, feature=_slab_feature(scale=640.0 / 256.0), rng=rng)
 
 
+def config4_scaled(seed: int = 4, n: int = 160, side: int = 24, n_sweeps: int = 2) -> Problem:
+    """Workload 4's broadband setting at a size the oracle can search: h =
+    lambda0/25, 16-cell PML, eight frequencies over 0.9-1.1 f0, Gaussian line
+    source and overlap output scaled with the design, mean over frequencies,
+    slab background scaled like workload 4; a 160x160 grid with a 24x24
+    design instead of 640x640 with 80x80."""
+    rng = _rng(seed, 44)
+    i0 = (n - side) // 2
+    j0 = i0
+    k0s = [2.0 * math.pi * (0.9 + 0.2 * i / 7.0) for i in range(8)]
+    g = lambda m: _gaussian(m, 12.0 * side / 80.0)
+    return _square_problem(
+        "config4_scaled", seed, n, 16, 1.0 / 25.0, side, 11.7, k0s,
+        src_pts=[(i0 - 20, j0, j0 + side)], out_pts=[(i0 + side + 20, j0, j0 + side)],
+        src_profile=g, out_profile=g, objective_kind=MEAN_TRANSMISSION,
+        n_sweeps=n_sweeps, feature=_slab_feature(scale=n / 256.0), rng=rng)
+
+
 def tiny(seed: int = 0, n: int = 20, npml: int = 4, side: int = 3,
          eps_hi: float = 4.0, nfreq: int = 1, n_sweeps: int = 3,
          static_block: bool = True) -> Problem:
