@@ -16,6 +16,8 @@ reproduce the same accepted sequence:
     seeds (exact evaluations counted; training is not timed);
   * tiles: the same workload searched over 4x4-pixel tiles (rank-16 updates;
     its own sequence, not comparable with the pixel search);
+  * broadband (a separate workload): eight frequencies over a 20% band on a
+    160x160 grid with a 24x24 design, plain against mixed;
   * batch (a separate workload): 24 problems of the batching family
     advanced together, one launch per step, against the same problems run
     one after the other.
@@ -202,6 +204,44 @@ def tile_form(P, h, steps, warmup):
     return out
 
 
+def broadband_form(P, steps, warmup):
+    """Workload 4's eight-frequency setting at reduced size (160x160 grid,
+    24x24 design): plain FP64 and mixed forms from the same start design; one
+    launch per step covers all eight frequencies."""
+    import workloads
+    pb = workloads.config4_scaled()
+    t0 = time.perf_counter()
+    hb = P.Handle(pb)
+    t_pre = time.perf_counter() - t0
+    hb.bind(P.default_options())
+    hb.set_design(pb.init_bits)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        hb.set_design(pb.init_bits)
+    torch.cuda.synchronize()
+    t_inv = (time.perf_counter() - t0) / 3
+    out = {"n_d": hb.n_d, "frequencies": pb.nfreq, "precompute_s": t_pre,
+           "set_design_ms": 1e3 * t_inv}
+    seqs = {}
+    for name, kw in (("plain", {}), ("mixed", dict(precision=P.PNGF_MIXED, k_refresh=32))):
+        opts = P.default_options(max_accepts=8192, max_sweeps=8, timing=True, **kw)
+        res, dt, kt = run_form(hb, pb, opts, steps, warmup, "broadband " + name)
+        s = summarize(res, dt, steps)
+        out[name] = {k: s[k] for k in ("flip_evals_per_s", "time_to_design_ms", "accepts",
+                                       "attempts", "f_final", "refreshes")}
+        # per-kernel times of the last run; bytes are those of one frequency
+        out[name]["kernels"] = {k: {"launches": n, "total_ms": tms, "avg_us": 1e3 * tms / n}
+                                for k, (tms, n) in kt.items() if n}
+        seqs[name] = res[-1]["accepted"]
+    out["same_sequence"] = bool(seqs["plain"].tolist() == seqs["mixed"].tolist())
+    out["objective_rel_err"] = abs(out["mixed"]["f_final"] - out["plain"]["f_final"]) / \
+        out["plain"]["f_final"]
+    hb.close()
+    return out
+
+
 def learned_form(P, h, prob, steps, k=4):
     """Train the proposal network on other seeds of the same family (not
     timed), then time the ranked exact search on this workload."""
@@ -338,6 +378,7 @@ def main():
         seqs[name] = res[-1]["accepted"]
         forms[name] = s
     forms["tiles"] = tile_form(P, h, a.steps, a.warmup)
+    forms["broadband"] = broadband_form(P, a.steps, a.warmup)
     ref = forms["plain"]
     for name in ("mixed", "mixed_drift", "rform"):
         f = forms[name]

@@ -330,7 +330,8 @@ int pngf_batch_destroy(pngf_batch *b);
  *   0 design bit;  1, 2 Re, Im E[m] / max|E|;  3, 4 Re, Im R'[m] / max|R'|;
  *   5 |G_mm| / max|G_mm|;  6 asinh(df_lin[m] / (1e-3 f)), where df_lin is
  *   the flip's objective change with the denominator of eq. lru_eobj_rs set
- *   to 1 (summed over frequencies).
+ *   to 1 (summed over frequencies).  With PEC pixels, E is the z vector of
+ *   pngf_evaluate and G the G - I the kernels run on.
  * Network: four 3x3 convolutions, 7 -> 32 -> 32 -> 32 -> 1 channels, zero
  * padding, ReLU between layers; BF16 operands on the matrix cores with FP32
  * accumulation, FP32 master weights, mean Huber loss (delta 1), Adam
