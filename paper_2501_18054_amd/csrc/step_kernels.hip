@@ -622,6 +622,168 @@ __global__ __launch_bounds__(kSplitThreads) void k_mixed_step_split(ProbDev P, i
   }
 }
 
+// Several-frequency mixed step for rows of at most 64 PRE columns: one
+// workgroup per row pair, wave 0 decides, worker wave 1 + f handles frequency
+// f of both rows (its C0^-1 rows of that frequency are loaded whole during the
+// decision), and the frequencies' score terms meet in LDS, where wave 1 sums
+// them and publishes the keys.  Same arithmetic as mixed_step_group.
+constexpr int kMfMaxThreads = 64 * (1 + kMaxFreq);
+
+template <int PRE>
+__global__ __launch_bounds__(kMfMaxThreads) void k_mixed_step_mf(ProbDev P, int spar, int kslot) {
+  __shared__ StepCtx c;
+  __shared__ double sdf[kMaxFreq][2], sbnd[kMaxFreq][2];
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int f = w - 1;                       // frequency of a worker wave
+  const bool worker = w > 0 && f < P.nfreq;
+  const int ra = 2 * g, rb = ra + 1;
+  const bool va = worker && ra < P.nd, vb = worker && rb < P.nd;
+  const int dp = spar;
+  const int fw = worker ? f : 0;
+  z32 pa[PRE], pb[PRE];
+#pragma unroll
+  for (int q = 0; q < PRE; ++q) {
+    const int j = lane + 64 * q;
+    pa[q] = z32{0.f, 0.f};
+    pb[q] = z32{0.f, 0.f};
+    if (j < P.nd) {
+      if (va) pa[q] = P.C0[fw][size_t(ra) * P.ld + j];
+      if (vb) pb[q] = P.C0[fw][size_t(rb) * P.ld + j];
+    }
+  }
+  const uint8_t* bin = dp ? P.bitsB : P.bits;
+  uint8_t* bout = dp ? P.bits : P.bitsB;
+  z64 ea{0.0, 0.0}, rpa{0.0, 0.0}, ta{0.0, 0.0}, eb{0.0, 0.0}, rpb{0.0, 0.0}, tb{0.0, 0.0};
+  uint8_t b0a = 0, b0b = 0;
+  int s0 = 0, rka[4] = {0, 0, 0, 0}, rkb[4] = {0, 0, 0, 0};
+  if (lane == 0 && worker) {
+    if (va) {
+      b0a = bin[ra];
+      ea = (dp ? P.EB[fw] : P.E[fw])[ra];
+      rpa = (dp ? P.RpB[fw] : P.Rp[fw])[ra];
+      ta = (dp ? P.tauB[fw] : P.tau[fw])[ra];
+    }
+    if (vb) {
+      b0b = bin[rb];
+      eb = (dp ? P.EB[fw] : P.E[fw])[rb];
+      rpb = (dp ? P.RpB[fw] : P.Rp[fw])[rb];
+      tb = (dp ? P.tauB[fw] : P.tau[fw])[rb];
+    }
+    if (f == 0) {
+      // visiting positions for the keys (see k_mixed_step_split)
+      const DbsState* sin = spar ? P.stB : P.st;
+      s0 = sin->cursor_s;
+      const int ns = sin->n_sweeps;
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (s0 + d < ns) {
+          if (va) rka[d] = P.rank[size_t(s0 + d) * P.nd + ra];
+          if (vb) rkb[d] = P.rank[size_t(s0 + d) * P.nd + rb];
+        }
+    }
+  }
+  if (tid == 0) step_decide(P, spar, kslot, true, c);
+  __syncthreads();
+  if (g == 0) step_publish(P, spar, kslot, true, c);
+  const int m = c.m;
+  if (m < 0) return;
+  const int slot = c.slot;
+  if (worker) {
+    z64 cc{0.0, 0.0};
+    if (lane < slot) cc = zmul(P.alph[f][lane], up32(P.Pp[f][size_t(lane) * P.ld + m]));
+    const z32* gm = P.G32[f] + size_t(m) * P.ld;
+    z32 gv[PRE];
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+      const int j = lane + 64 * q;
+      gv[q] = j < P.nd ? gm[j] : z32{0.f, 0.f};
+    }
+    float par = 0.f, pai = 0.f, pbr = 0.f, pbi = 0.f;
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+      par = fmaf(pa[q].re, gv[q].re, fmaf(-pa[q].im, gv[q].im, par));
+      pai = fmaf(pa[q].re, gv[q].im, fmaf(pa[q].im, gv[q].re, pai));
+      pbr = fmaf(pb[q].re, gv[q].re, fmaf(-pb[q].im, gv[q].im, pbr));
+      pbi = fmaf(pb[q].re, gv[q].im, fmaf(pb[q].im, gv[q].re, pbi));
+    }
+    if (lane < slot) {
+      if (va) {
+        const z32 pk = P.Pp[f][size_t(lane) * P.ld + ra];
+        par += float(cc.re * pk.re - cc.im * pk.im);
+        pai += float(cc.re * pk.im + cc.im * pk.re);
+      }
+      if (vb) {
+        const z32 pk = P.Pp[f][size_t(lane) * P.ld + rb];
+        pbr += float(cc.re * pk.re - cc.im * pk.im);
+        pbi += float(cc.re * pk.im + cc.im * pk.re);
+      }
+    }
+    par = wave_sumf(par);
+    pai = wave_sumf(pai);
+    pbr = wave_sumf(pbr);
+    pbi = wave_sumf(pbi);
+    if (lane == 0) {
+      const uint8_t bita = b0a ^ (ra == m ? 1 : 0), bitb = b0b ^ (rb == m ? 1 : 0);
+      for (int h = 0; h < 2; ++h) {
+        double df = 0.0, bnd = 0.0;
+        const int r = h ? rb : ra;
+        if (h ? vb : va) {
+          const z32 p32{h ? pbr : par, h ? pbi : pai};
+          P.Pp[f][size_t(slot) * P.ld + r] = p32;
+          const z64 p = up32(p32);
+          const z64 ap = zmul(c.alpha[f], p);
+          const z64 Ei = zadd(h ? eb : ea, zmul(ap, c.Em[f]));
+          const z64 Rpi = zadd(h ? rpb : rpa, zmul(ap, c.Rpm[f]));
+          const z64 tau = zadd(h ? tb : ta, zmul(ap, p));
+          (dp ? P.E[f] : P.EB[f])[r] = Ei;
+          (dp ? P.Rp[f] : P.RpB[f])[r] = Rpi;
+          (dp ? P.tau[f] : P.tauB[f])[r] = tau;
+          const uint8_t bit = h ? bitb : bita;
+          score_terms(P, c, f, tau, Ei, Rpi, bit ? -P.deps : P.deps, df, bnd);
+          if (f == 0) bout[r] = bit;
+        }
+        sdf[f][h] = df;
+        sbnd[f][h] = bnd;
+      }
+    }
+  }
+  __syncthreads();
+  if (w != 1 || lane != 0) return;
+  for (int h = 0; h < 2; ++h) {
+    const int r = h ? rb : ra;
+    if (!(h ? vb : va)) continue;
+    double df = 0.0, bnd = 0.0;
+    for (int ff = 0; ff < P.nfreq; ++ff) {
+      df += sdf[ff][h];
+      bnd += sbnd[ff][h];
+    }
+    P.df32[r] = df;
+    P.dfb[r] = bnd;
+    const double margin = df - c.eta * c.f;
+    const double band = P.band * bnd;
+    if (margin >= -band && c.cs < c.ns) {
+      const int* rk = h ? rkb : rka;
+      const int d = c.cs - s0;
+      int pos = -1;
+#pragma unroll
+      for (int u = 0; u < 3; ++u)
+        if (u == d) pos = rk[u];
+      uint32_t k = kNoKey;
+      if (pos >= c.cp) {
+        k = pack_key(pos, r);
+      } else if (c.cs + 1 < c.ns) {
+        int nxt = 0;
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (u == d) nxt = rk[u + 1];
+        k = pack_key(P.nd + nxt, r);
+      }
+      if (k != kNoKey) atomicMin(&P.keys[(margin > band ? 0 : 3) + (kslot + 1) % 3], k);
+    }
+  }
+}
+
 template <int NPL>
 __global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar, int kslot) {
   __shared__ StepCtx c;
@@ -845,6 +1007,12 @@ hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s)
     hipLaunchKernelGGL(k_mixed_step_split<16>, grid, dim3(kSplitThreads), 0, s, P, sp, ks);
   else if (P.nfreq == 1 && P.nd <= 64 * 32)
     hipLaunchKernelGGL(k_mixed_step_split<32>, grid, dim3(kSplitThreads), 0, s, P, sp, ks);
+  else if (P.nfreq > 1 && P.nd <= 64 * 8)
+    hipLaunchKernelGGL(k_mixed_step_mf<8>, dim3((P.nd + 1) / 2), dim3(64 * (1 + P.nfreq)), 0, s,
+                       P, sp, ks);
+  else if (P.nfreq > 1 && P.nd <= 64 * 16)
+    hipLaunchKernelGGL(k_mixed_step_mf<16>, dim3((P.nd + 1) / 2), dim3(64 * (1 + P.nfreq)), 0, s,
+                       P, sp, ks);
   else
     hipLaunchKernelGGL(k_mixed_step, grid, dim3(256), 0, s, P, sp, ks);
   return hipGetLastError();
