@@ -17,7 +17,8 @@ reproduce the same accepted sequence:
   * tiles: the same workload searched over 4x4-pixel tiles (rank-16 updates;
     its own sequence, not comparable with the pixel search);
   * broadband (a separate workload): eight frequencies over a 20% band on a
-    160x160 grid with a 24x24 design, plain against mixed;
+    160x160 grid with a 24x24 design, plain against mixed (refresh every 32
+    accepts, or only on drift);
   * batch (a separate workload): 24 problems of the batching family
     advanced together, one launch per step, against the same problems run
     one after the other.
@@ -225,7 +226,8 @@ def broadband_form(P, steps, warmup):
     out = {"n_d": hb.n_d, "frequencies": pb.nfreq, "precompute_s": t_pre,
            "set_design_ms": 1e3 * t_inv}
     seqs = {}
-    for name, kw in (("plain", {}), ("mixed", dict(precision=P.PNGF_MIXED, k_refresh=32))):
+    for name, kw in (("plain", {}), ("mixed", dict(precision=P.PNGF_MIXED, k_refresh=32)),
+                     ("mixed_drift", dict(precision=P.PNGF_MIXED, k_refresh=0))):
         opts = P.default_options(max_accepts=8192, max_sweeps=8, timing=True, **kw)
         res, dt, kt = run_form(hb, pb, opts, steps, warmup, "broadband " + name)
         s = summarize(res, dt, steps)
@@ -235,7 +237,8 @@ def broadband_form(P, steps, warmup):
         out[name]["kernels"] = {k: {"launches": n, "total_ms": tms, "avg_us": 1e3 * tms / n}
                                 for k, (tms, n) in kt.items() if n}
         seqs[name] = res[-1]["accepted"]
-    out["same_sequence"] = bool(seqs["plain"].tolist() == seqs["mixed"].tolist())
+    out["same_sequence"] = bool(seqs["plain"].tolist() == seqs["mixed"].tolist() ==
+                                seqs["mixed_drift"].tolist())
     out["objective_rel_err"] = abs(out["mixed"]["f_final"] - out["plain"]["f_final"]) / \
         out["plain"]["f_final"]
     hb.close()

@@ -98,12 +98,19 @@ struct Layout {
   size_t off_C0[pngf::kMaxFreq], off_G32[pngf::kMaxFreq], off_Pp[pngf::kMaxFreq],
       off_Qp[pngf::kMaxFreq], off_alph[pngf::kMaxFreq], off_pcoef[pngf::kMaxFreq];
   size_t off_df32, off_dfb, off_bandout;
-  size_t off_Pn, off_sidx, off_zidx, off_pos;
+  size_t off_sidx, off_zidx, off_pos;
   size_t off_CB[pngf::kMaxFreq], off_EB[pngf::kMaxFreq], off_RpB[pngf::kMaxFreq],
       off_tauB[pngf::kMaxFreq];
   size_t off_bitsB, off_stateB, off_keys, off_pm, off_best, off_feat;
-  size_t off_S, off_B1, off_Pb, off_ts, off_B11, off_piv, off_invp, off_used, off_status, off_u, off_r;
-  size_t off_wP, off_wQ, off_wW, off_wCap, off_wF, off_wS, off_wWork, off_tiles, off_tpart;
+  // inversion and block-Woodbury workspaces, one set per frequency (the
+  // frequencies' systems are independent and run on their own streams)
+  size_t off_S[pngf::kMaxFreq], off_B1[pngf::kMaxFreq], off_Pb[pngf::kMaxFreq],
+      off_Pn[pngf::kMaxFreq], off_ts[pngf::kMaxFreq], off_B11[pngf::kMaxFreq],
+      off_piv[pngf::kMaxFreq], off_invp[pngf::kMaxFreq], off_used[pngf::kMaxFreq];
+  size_t off_status, off_u[pngf::kMaxFreq], off_r[pngf::kMaxFreq];
+  size_t off_wP[pngf::kMaxFreq], off_wQ[pngf::kMaxFreq], off_wW[pngf::kMaxFreq],
+      off_wCap[pngf::kMaxFreq], off_wWork[pngf::kMaxFreq];
+  size_t off_wF, off_wS, off_tiles, off_tpart;
   size_t off_T[pngf::kMaxFreq], off_Up[pngf::kMaxFreq], off_ralph[pngf::kMaxFreq], off_rpm, off_Ut;
   size_t total;
 };
@@ -132,6 +139,11 @@ struct pngf_handle {
   std::vector<hipEvent_t> ev_pool;   // recorded (start, end, kernel id) triples
   std::vector<hipEvent_t> ev_free;   // created events ready for reuse
   int32_t nacc_seen = 0;             // accepts counted by the step timing so far
+  // streams of frequencies 1..F-1 for per-frequency work (default priority),
+  // with the events that fork them from and join them to the bound stream
+  std::vector<hipStream_t> aux;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
 };
 
 namespace {
@@ -213,29 +225,35 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     // FP64 block-Woodbury update (mixed refresh, tile accept, pixel sets):
     // panel, rows, capacitance, split-K partials
     const size_t kw = size_t(pngf::kWoodMax);
-    L.off_wP = take(size_t(nd) * kw * sizeof(z64));
-    L.off_wQ = take(kw * nd * sizeof(z64));
-    L.off_wW = take(kw * nd * sizeof(z64));
-    L.off_wCap = take(kw * kw * sizeof(z64));
+    for (int f = 0; f < F; ++f) {
+      L.off_wP[f] = take(size_t(nd) * kw * sizeof(z64));
+      L.off_wQ[f] = take(kw * nd * sizeof(z64));
+      L.off_wW[f] = take(kw * nd * sizeof(z64));
+      L.off_wCap[f] = take(kw * kw * sizeof(z64));
+      L.off_wWork[f] = take(size_t(pngf::kWoodSplits) * nd * kw * sizeof(z64));
+    }
     L.off_wF = take(kw * sizeof(int32_t));
     L.off_wS = take(size_t(F) * kw * sizeof(double));
-    L.off_wWork = take(size_t(pngf::kWoodSplits) * nd * kw * sizeof(z64));
   }
-  L.off_S = take(mat);
-  L.off_B1 = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
-  L.off_Pb = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
-  L.off_Pn = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
+  for (int f = 0; f < F; ++f) {
+    L.off_S[f] = take(mat);
+    L.off_B1[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
+    L.off_Pb[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
+    L.off_Pn[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
+    L.off_ts[f] = take(size_t(4) * ((nd + 1023) / 1024) * pngf::kGjNbHost * sizeof(int32_t) + 1024);
+    L.off_B11[f] = take(size_t(pngf::kGjNbHost) * pngf::kGjNbHost * sizeof(z64));
+    L.off_piv[f] = take(size_t(nd) * sizeof(int32_t));
+    L.off_invp[f] = take(size_t(nd) * sizeof(int32_t));
+    L.off_used[f] = take(size_t(nd) * sizeof(int32_t));
+  }
   L.off_sidx = take(size_t(nd) * sizeof(int32_t));
   L.off_zidx = take(size_t(nd) * sizeof(int32_t));
   L.off_pos = take(size_t(nd) * sizeof(int32_t));
-  L.off_ts = take(size_t(4) * ((nd + 1023) / 1024) * pngf::kGjNbHost * sizeof(int32_t) + 1024);
-  L.off_B11 = take(size_t(pngf::kGjNbHost) * pngf::kGjNbHost * sizeof(z64));
-  L.off_piv = take(size_t(nd) * sizeof(int32_t));
-  L.off_invp = take(size_t(nd) * sizeof(int32_t));
-  L.off_used = take(size_t(nd) * sizeof(int32_t));
   L.off_status = take(sizeof(int32_t));
-  L.off_u = take(vec);
-  L.off_r = take(vec);
+  for (int f = 0; f < F; ++f) {
+    L.off_u[f] = take(vec);
+    L.off_r[f] = take(vec);
+  }
   const int ms = std::max(1, o->max_sweeps), ma = std::max(1, o->max_accepts);
   L.off_bits = take(size_t(nd));
   L.off_perm = take(size_t(ms) * nd * sizeof(int32_t));
@@ -257,6 +275,34 @@ int check_ready(pngf_handle* h, bool need_design) {
   if (!h->bound) return fail(h, PNGF_ESTATE, "handle is not bound to a workspace");
   if (need_design && !h->have_design) return fail(h, PNGF_ESTATE, "no design set");
   return PNGF_OK;
+}
+
+hipStream_t fstream(pngf_handle* h, int f) { return f == 0 ? h->stream : h->aux[f - 1]; }
+
+// Make the frequency streams wait for the work queued so far on the bound
+// stream, and the bound stream for everything the frequency streams queue.
+int fork_streams(pngf_handle* h) {
+  if (h->aux.empty()) return PNGF_OK;
+  HIPCHK(h, hipEventRecord(h->ev_fork, h->stream));
+  for (hipStream_t a : h->aux) HIPCHK(h, hipStreamWaitEvent(a, h->ev_fork, 0));
+  return PNGF_OK;
+}
+
+int join_streams(pngf_handle* h) {
+  for (size_t k = 0; k < h->aux.size(); ++k) {
+    HIPCHK(h, hipEventRecord(h->ev_join[k], h->aux[k]));
+    HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_join[k], 0));
+  }
+  return PNGF_OK;
+}
+
+void release_streams(pngf_handle* h) {
+  for (hipStream_t a : h->aux) (void)hipStreamDestroy(a);
+  for (hipEvent_t e : h->ev_join) (void)hipEventDestroy(e);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  h->aux.clear();
+  h->ev_join.clear();
+  h->ev_fork = nullptr;
 }
 
 // Timed launch helper: records events around the launch when timing is on.
@@ -312,13 +358,15 @@ int reform_fields(pngf_handle* h) {
   const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
   const Layout& L = h->lay;
   pngf::ProbDev& P = h->P;
-  z64* u = at<z64>(h, L.off_u);
-  z64* r = at<z64>(h, L.off_r);
   const z64 one{1.0, 0.0}, zero{0.0, 0.0};
+  // sequential on the bound stream: each GEMV pass already spans the chip
+  // (frequency streams measured slower here than in order)
   for (int f = 0; f < F; ++f) {
     const double k2 = P.k0sq[f];
     const z64* b = at<z64>(h, L.off_b[f]);
     const z64* god = at<z64>(h, L.off_god[f]);
+    z64* u = at<z64>(h, L.off_u[f]);
+    z64* r = at<z64>(h, L.off_r[f]);
     Timer t(h, KID_OTHER);
     // E = C^-1 b
     HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, b, nullptr, 0.0, one, zero, nullptr, 0.0,
@@ -344,11 +392,6 @@ int device_reinvert(pngf_handle* h) {
   const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
   const Layout& L = h->lay;
   pngf::ProbDev& P = h->P;
-  z64* S = at<z64>(h, L.off_S);
-  z64* B1 = at<z64>(h, L.off_B1);
-  int32_t* piv = at<int32_t>(h, L.off_piv);
-  int32_t* invp = at<int32_t>(h, L.off_invp);
-  int32_t* used = at<int32_t>(h, L.off_used);
   int32_t* status = at<int32_t>(h, L.off_status);
   HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
   // S (pixels at eps_hi) and Z from the device design bits
@@ -368,15 +411,23 @@ int device_reinvert(pngf_handle* h) {
   if (nd - ns > 0)
     HIPCHK(h, hipMemcpyAsync(d_zidx, zidx.data(), (nd - ns) * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync(d_pos, pos.data(), nd * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-  for (int f = 0; f < F; ++f) {
-    const double k2 = P.k0sq[f];
+  {
+    // one inversion per frequency, each on its own stream (a chain of
+    // single-workgroup panel kernels: concurrent frequencies fill more CUs)
     Timer t(h, KID_LU);
-    HIPCHK(h, pngf::launch_inverse(S, P.Cinv[f], P.G[f], nd, ld, d_sidx, d_zidx, d_pos, ns,
-                                   k2 * P.deps, B1, at<z64>(h, L.off_Pb),
-                                   at<z64>(h, L.off_Pn), piv, invp, used, status,
-                                   at<int32_t>(h, L.off_ts), at<z64>(h, L.off_B11),
-                                   h->stream));
-    t.end();
+    int st = fork_streams(h);
+    if (st) return st;
+    for (int f = 0; f < F; ++f)
+      HIPCHK(h, pngf::launch_inverse(at<z64>(h, L.off_S[f]), P.Cinv[f], P.G[f], nd, ld, d_sidx,
+                                     d_zidx, d_pos, ns, P.k0sq[f] * P.deps,
+                                     at<z64>(h, L.off_B1[f]), at<z64>(h, L.off_Pb[f]),
+                                     at<z64>(h, L.off_Pn[f]), at<int32_t>(h, L.off_piv[f]),
+                                     at<int32_t>(h, L.off_invp[f]), at<int32_t>(h, L.off_used[f]),
+                                     status, at<int32_t>(h, L.off_ts[f]),
+                                     at<z64>(h, L.off_B11[f]), fstream(h, f)));
+    st = join_streams(h);
+    if (st) return st;
+    t.end(F);
   }
   int st = reform_fields(h);
   if (st) return st;
@@ -404,11 +455,6 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
   const int k = int(fl.size());
   int32_t* dF = at<int32_t>(h, L.off_wF);
   double* dS = at<double>(h, L.off_wS);
-  z64* wP = at<z64>(h, L.off_wP);
-  z64* wQ = at<z64>(h, L.off_wQ);
-  z64* wW = at<z64>(h, L.off_wW);
-  z64* cap = at<z64>(h, L.off_wCap);
-  z64* work = at<z64>(h, L.off_wWork);
   int32_t* status = at<int32_t>(h, L.off_status);
   std::vector<double> sc(size_t(F) * k);
   for (int f = 0; f < F; ++f)
@@ -419,20 +465,31 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
   HIPCHK(h, hipMemcpyAsync(dS, sc.data(), size_t(F) * k * sizeof(double), hipMemcpyHostToDevice,
                            h->stream));
   const z64 one{1.0, 0.0}, zero{0.0, 0.0};
-  for (int f = 0; f < F; ++f) {
+  {
     Timer t(h, KID_WOOD);
-    // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T)
-    HIPCHK(h, pngf::launch_zgemm(nd, k, nd, P.Cinv[f], ld, nullptr, P.G[f], ld, true, dF, wP, k,
-                                 one, zero, pngf::kWoodSplits, work, h->stream));
-    HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS + size_t(f) * k, cap, h->stream));
-    HIPCHK(h, pngf::launch_small_inverse(cap, k, status, h->stream));
-    // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
-    HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, h->stream));
-    HIPCHK(h, pngf::launch_zgemm(k, nd, k, cap, k, nullptr, wQ, nd, false, nullptr, wW, nd, one,
-                                 zero, 1, nullptr, h->stream));
-    HIPCHK(h, pngf::launch_zgemm(nd, nd, k, wP, k, nullptr, wW, nd, false, nullptr, P.Cinv[f],
-                                 ld, one, one, 1, nullptr, h->stream));
-    t.end();
+    int st = fork_streams(h);
+    if (st) return st;
+    for (int f = 0; f < F; ++f) {
+      const hipStream_t sf = fstream(h, f);
+      z64* wP = at<z64>(h, L.off_wP[f]);
+      z64* wQ = at<z64>(h, L.off_wQ[f]);
+      z64* wW = at<z64>(h, L.off_wW[f]);
+      z64* cap = at<z64>(h, L.off_wCap[f]);
+      // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T)
+      HIPCHK(h, pngf::launch_zgemm(nd, k, nd, P.Cinv[f], ld, nullptr, P.G[f], ld, true, dF, wP, k,
+                                   one, zero, pngf::kWoodSplits, at<z64>(h, L.off_wWork[f]), sf));
+      HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS + size_t(f) * k, cap, sf));
+      HIPCHK(h, pngf::launch_small_inverse(cap, k, status, sf));
+      // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
+      HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, sf));
+      HIPCHK(h, pngf::launch_zgemm(k, nd, k, cap, k, nullptr, wQ, nd, false, nullptr, wW, nd, one,
+                                   zero, 1, nullptr, sf));
+      HIPCHK(h, pngf::launch_zgemm(nd, nd, k, wP, k, nullptr, wW, nd, false, nullptr, P.Cinv[f],
+                                   ld, one, one, 1, nullptr, sf));
+    }
+    st = join_streams(h);
+    if (st) return st;
+    t.end(F);
   }
   // (this wait also ends the host copies' reads of fl and sc)
   int32_t st_host = 0;
@@ -596,7 +653,7 @@ int mixed_residual(pngf_handle* h, double* ratio) {
   const int nd = h->pc.n_d;
   const Layout& L = h->lay;
   pngf::ProbDev& P = h->P;
-  z64* r = at<z64>(h, L.off_r);
+  z64* r = at<z64>(h, L.off_r[0]);
   const z64* b = at<z64>(h, L.off_b[0]);
   HIPCHK(h, pngf::launch_gemv(P.G[0], h->ld, nd, P.E[0], P.bits, P.deps, z64{P.k0sq[0], 0.0},
                               z64{1.0, 0.0}, b, -1.0, P.E[0], r, h->stream));
@@ -986,6 +1043,18 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   h->ws_bytes = bytes;
   h->stream = static_cast<hipStream_t>(stream);
   const int nd = h->pc.n_d, F = int(h->pc.freq.size());
+  if (int(h->aux.size()) != F - 1) {
+    release_streams(h);
+    for (int f = 1; f < F; ++f) {
+      hipStream_t a = nullptr;
+      hipEvent_t e = nullptr;
+      HIPCHK(h, hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+      h->aux.push_back(a);
+      HIPCHK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      h->ev_join.push_back(e);
+    }
+    if (F > 1) HIPCHK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+  }
   pngf::ProbDev& P = h->P;
   P = pngf::ProbDev{};
   P.nd = nd;
@@ -1379,6 +1448,7 @@ int pngf_destroy(pngf_handle* h) {
     hipEventDestroy(h->ev_pool[k + 1]);
   }
   for (hipEvent_t e : h->ev_free) hipEventDestroy(e);
+  release_streams(h);
   delete h;
   return PNGF_OK;
 }
