@@ -132,6 +132,14 @@ struct pngf_handle {
   std::vector<uint8_t> bits;
   std::vector<uint8_t> bits_ref;   // design whose FP64 inverse C^-1 holds (mixed runs)
   bool cinv_stale = false;         // an R-form search moved the design past C^-1
+  // host copy of the design read with the last batch of steps (saves a
+  // round trip before the next FP64 refresh), and the host arrays a deferred
+  // block-Woodbury update copies from (kept until its wait)
+  bool bits_fresh = false;
+  uint8_t* bits_pin = nullptr;     // pinned [2][n_d]: the A and B design buffers
+  std::vector<int32_t> w_fl;
+  std::vector<double> w_sc;
+  bool wood_pending = false;       // a Woodbury status not yet read
   double f_host = 0.0;
   // event timing
   double ktime_ms[KID_N] = {0};
@@ -448,7 +456,7 @@ int device_reinvert(pngf_handle* h) {
 // cores.  *singular reports a singular Cap (C^-1 is then not usable).  Ends
 // with a wait.
 int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::vector<uint8_t>& cur,
-                    bool* singular) {
+                    bool* singular, bool defer = false) {
   const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
   const Layout& L = h->lay;
   pngf::ProbDev& P = h->P;
@@ -456,12 +464,15 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
   int32_t* dF = at<int32_t>(h, L.off_wF);
   double* dS = at<double>(h, L.off_wS);
   int32_t* status = at<int32_t>(h, L.off_status);
-  std::vector<double> sc(size_t(F) * k);
+  h->w_fl = fl;
+  std::vector<double>& sc = h->w_sc;
+  sc.assign(size_t(F) * k, 0.0);
   for (int f = 0; f < F; ++f)
     for (int c = 0; c < k; ++c)
       sc[size_t(f) * k + c] = P.k0sq[f] * (cur[fl[c]] ? P.deps : -P.deps);
   HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
-  HIPCHK(h, hipMemcpyAsync(dF, fl.data(), k * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(dF, h->w_fl.data(), k * sizeof(int32_t), hipMemcpyHostToDevice,
+                           h->stream));
   HIPCHK(h, hipMemcpyAsync(dS, sc.data(), size_t(F) * k * sizeof(double), hipMemcpyHostToDevice,
                            h->stream));
   const z64 one{1.0, 0.0}, zero{0.0, 0.0};
@@ -491,7 +502,12 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
     if (st) return st;
     t.end(F);
   }
-  // (this wait also ends the host copies' reads of fl and sc)
+  *singular = false;
+  if (defer) {
+    // the caller reads the status at its next wait (wood_pending)
+    h->wood_pending = true;
+    return PNGF_OK;
+  }
   int32_t st_host = 0;
   HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -505,14 +521,22 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
 // M = |F|) on the matrix cores, exact up to FP64 rounding; a full
 // re-inversion when F is larger than kWoodMax or its capacitance matrix is
 // singular.  Then E (with one refinement step), R' and x are re-formed.
-int fp64_refresh(pngf_handle* h) {
+// defer: the Woodbury status is left for the caller's next wait
+// (wood_pending), which must re-invert if it reports a singular update.
+int fp64_refresh(pngf_handle* h, bool defer = false) {
   const int nd = h->pc.n_d;
   pngf::ProbDev& P = h->P;
+  const bool fresh = h->bits_fresh;
+  h->bits_fresh = false;
   if (h->opt.precision == PNGF_FP64_PLAIN || h->bits_ref.size() != size_t(nd))
     return device_reinvert(h);
   std::vector<uint8_t> cur(nd);
-  HIPCHK(h, hipMemcpyAsync(cur.data(), P.bits, nd, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (fresh) {
+    cur = h->bits;
+  } else {
+    HIPCHK(h, hipMemcpyAsync(cur.data(), P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
   std::vector<int32_t> fl;
   for (int i = 0; i < nd; ++i)
     if (cur[i] != h->bits_ref[i]) fl.push_back(i);
@@ -520,7 +544,7 @@ int fp64_refresh(pngf_handle* h) {
   if (k > pngf::kWoodMax) return device_reinvert(h);
   if (k > 0) {
     bool singular = false;
-    int st = woodbury_update(h, fl, cur, &singular);
+    int st = woodbury_update(h, fl, cur, &singular, defer);
     if (st) return st;
     if (singular) return device_reinvert(h);
   }
@@ -580,15 +604,32 @@ int normalize(pngf_handle* h, pngf::DbsState* st) {
 
 // Run `n` (even) steps starting at step index t0, then read the state.
 template <class L>
-int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinned) {
+int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinned,
+              bool want_bits = false) {
   // one event pair around the back-to-back step launches (the average per
   // launch includes the gaps between them)
   Timer t(h, KID_ACCEPT);
   for (int b = 0; b < n; ++b) HIPCHK(h, launch(h->P, h->npl, int(t0 + b), h->stream));
   t.end(n);
+  h->bits_fresh = false;
+  const int nd = h->pc.n_d;
   HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
                            h->stream));
+  if (want_bits) {
+    // both design buffers, into pinned memory, with the same wait
+    if (!h->bits_pin) {
+      HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->bits_pin), 2 * size_t(nd)));
+    }
+    HIPCHK(h, hipMemcpyAsync(h->bits_pin, h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->bits_pin + nd, h->P.bitsB, nd, hipMemcpyDeviceToHost, h->stream));
+  }
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (want_bits) {
+    // the design of the last step (in the B set after an odd number of updates)
+    const uint8_t* cur = h->bits_pin + ((pinned->flips & 1) ? nd : 0);
+    h->bits.assign(cur, cur + nd);
+    h->bits_fresh = true;
+  }
   // count only the launches that accepted a flip (the interval also holds
   // the cheap launches that found the search paused or finished)
   if (!h->ev_pool.empty()) {
@@ -630,20 +671,36 @@ int capture_ref_bits(pngf_handle* h) {
 // error against the FP64 scores to set the error band.
 int mixed_refresh(pngf_handle* h, bool measure) {
   const int nd = h->pc.n_d, F = int(h->pc.freq.size());
-  int st = fp64_refresh(h);
+  h->wood_pending = false;
+  int st = fp64_refresh(h, true);
   if (st) return st;
-  for (int f = 0; f < F; ++f)
-    HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
-  st = start_segment(h, true);
-  if (st) return st;
-  if (measure) {
-    double* out = at<double>(h, h->lay.off_bandout);
-    HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd, out, h->stream));
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int f = 0; f < F; ++f)
+      HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
+    st = start_segment(h, true);
+    if (st) return st;
     double meas = 0.0;
-    HIPCHK(h, hipMemcpyAsync(&meas, out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (std::isfinite(meas) && h->opt.guard <= 0.0)
+    int32_t wst = 0;
+    if (measure) {
+      double* out = at<double>(h, h->lay.off_bandout);
+      HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd, out, h->stream));
+      HIPCHK(h, hipMemcpyAsync(&meas, out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    }
+    const bool pending = h->wood_pending;
+    if (pending)
+      HIPCHK(h, hipMemcpyAsync(&wst, at<int32_t>(h, h->lay.off_status), sizeof(int32_t),
+                               hipMemcpyDeviceToHost, h->stream));
+    if (measure || pending) HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->wood_pending = false;
+    if (pending && wst) {
+      // the deferred block-Woodbury update was singular: re-invert instead
+      st = device_reinvert(h);
+      if (st) return st;
+      continue;
+    }
+    if (measure && std::isfinite(meas) && h->opt.guard <= 0.0)
       h->P.band = std::min(1e-2, std::max(1e-6, 100.0 * meas));
+    return PNGF_OK;
   }
   return PNGF_OK;
 }
@@ -703,7 +760,9 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
     if (h->opt.k_refresh > 0) nb = int(std::min<int64_t>(nb, std::max<int64_t>(1, h->opt.k_refresh - since)));
     if (h->opt.k_fold > 0) nb = int(std::min<int64_t>(nb, std::max<int64_t>(1, h->opt.k_fold - kpan)));
     nb += nb & 1;
-    st = run_steps(h, pngf::launch_mixed_step, t, nb, pinned);
+    // read the design with the batch when it ends at a periodic refresh
+    const bool due = h->opt.k_refresh > 0 && since + nb >= h->opt.k_refresh;
+    st = run_steps(h, pngf::launch_mixed_step, t, nb, pinned, due);
     if (st) return st;
     t += nb;
     if (pinned->done) break;
@@ -1039,6 +1098,8 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   if (bytes < L.total) return fail(h, PNGF_ENOMEM, "workspace too small");
   h->opt = *o;
   h->lay = L;
+  h->bits_fresh = false;
+  h->wood_pending = false;
   h->ws = static_cast<char*>(dev_ws);
   h->ws_bytes = bytes;
   h->stream = static_cast<hipStream_t>(stream);
@@ -1151,6 +1212,7 @@ int pngf_set_design(pngf_handle* h, const uint8_t* bits) {
   if (!bits) return fail(h, PNGF_EINVAL, "null bits");
   const int nd = h->pc.n_d;
   for (int a = 0; a < nd; ++a) h->bits[a] = bits[a] ? 1 : 0;
+  h->bits_fresh = false;
   HIPCHK(h, hipMemcpyAsync(h->P.bits, h->bits.data(), nd, hipMemcpyHostToDevice, h->stream));
   pngf::DbsState s{};
   s.m = -1;
@@ -1449,6 +1511,7 @@ int pngf_destroy(pngf_handle* h) {
   }
   for (hipEvent_t e : h->ev_free) hipEventDestroy(e);
   release_streams(h);
+  if (h->bits_pin) (void)hipHostFree(h->bits_pin);
   delete h;
   return PNGF_OK;
 }

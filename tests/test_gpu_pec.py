@@ -125,3 +125,23 @@ def test_pec_batch_equals_solo():
     b.close()
     for h in hs:
         h.close()
+
+
+@pytest.mark.parametrize("fill", [0, 1])
+def test_pec_all_open_or_all_metal_start(fill):
+    """Degenerate start designs: no conductor (C = I) and every pixel a
+    conductor (C^-1 is the inverse of the whole G block)."""
+    p = workloads.tiny_metal(seed=33, n=22, side=5, nfreq=2, n_sweeps=3)
+    p.init_bits[:] = fill
+    say(f"tiny metal, every pixel {fill}")
+    r = oracle.dbs(p)
+    h = P.Handle(p).bind(P.default_options(max_accepts=512, max_sweeps=4))
+    h.set_design(p.init_bits)
+    f0, x0, Z0 = h.evaluate(fields=True)
+    zo, xo = oracle.pec_state(p, p.init_bits, 0)
+    assert rel(Z0[0], zo) < TOL
+    res = h.dbs_run(p.perms)
+    assert res["accepted"].tolist() == [a[2] for a in r.accepted]
+    assert res["attempts"] == r.attempts
+    assert abs(res["f_final"] - r.f_final) < TOL * r.f_final
+    h.close()

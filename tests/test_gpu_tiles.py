@@ -106,3 +106,18 @@ def test_tiles_errors():
     h.close()
     with pytest.raises(P.PngfError):                     # tiles need the FP64 plain form
         P.Handle(p).bind(P.default_options(precision=P.PNGF_MIXED, max_tile=4))
+
+
+def test_tile_covering_the_whole_design():
+    """One tile of every pixel (3x3 design): the search flips the whole
+    design at once or nothing."""
+    p = workloads.with_tiles(workloads.tiny(seed=91, n=20, npml=4, side=3, n_sweeps=3), 3)
+    assert p.tiles.shape == (1, 9)
+    say("single tile over the whole design")
+    r = oracle.dbs(p, perms=p.tile_perms, tiles=p.tiles)
+    h, res = _run(p)
+    assert res["accepted"].tolist() == [t for (_, _, t, _) in r.accepted]
+    assert res["attempts"] == r.attempts
+    assert res["converged"] == r.converged
+    assert abs(res["f_final"] - r.f_final) < TOL * r.f_final
+    h.close()
