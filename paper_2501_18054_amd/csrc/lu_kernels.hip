@@ -28,6 +28,8 @@
 // B1 the panel's pivot rows before the update.  On gfx950 the FP64
 // matrix-core rate equals the FP64 vector rate (78.6 TFLOP/s), and at this
 // panel width the update is HBM-bound, so it runs on the vector ALUs.
+#include <utility>
+
 #include "dev_state.h"
 
 namespace pngf {
@@ -60,6 +62,36 @@ __global__ __launch_bounds__(256) void k_gj_panel_in(const z64* S, int ld, int n
   if (r < n) Pb[e] = (c < ncols) ? S[size_t(r) * ld + k0 + c] : z64{0.0, 0.0};
 }
 
+// Gauss-Jordan column C of the wave-resident [B11 | I] (see k_tsel): the
+// pivot row C lives in half C / 8 at register C % 8.
+__device__ __forceinline__ z64 shfl_z64(z64 v, int src) {
+  return z64{__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
+}
+
+template <int C>
+__device__ __forceinline__ void b11_column(z64 (&w)[8], int hh, int j) {
+  constexpr int ph = C / 8, pr = C % 8;
+  const z64 pv = shfl_z64(w[pr], ph * 32 + C);
+  const z64 inv = (zabs2(pv) > 0.0) ? zdiv(z64{1.0, 0.0}, pv) : z64{0.0, 0.0};
+  // factors of this lane's rows: their entries in column C (same half)
+  z64 fr[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) fr[i] = shfl_z64(w[i], hh * 32 + C);
+  // scaled pivot row entry of this lane's column
+  const z64 prow = zmul(shfl_z64(w[pr], ph * 32 + j), inv);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    if (hh == ph && i == pr) w[i] = prow;
+    else w[i] = zsub(w[i], zmul(fr[i], prow));
+  }
+}
+
+template <int... Cs>
+__device__ __forceinline__ void b11_columns(z64 (&w)[8], int hh, int j,
+                                            std::integer_sequence<int, Cs...>) {
+  (b11_column<Cs>(w, hh, j), ...);
+}
+
 // Packed (|a|^2, slot) key for the pivot search: FP32 magnitude bits in the
 // high word (monotonic for non-negative floats), the complemented slot in the
 // low word so that ties prefer the smaller slot.
@@ -85,8 +117,6 @@ __global__ __launch_bounds__(kTsRows) void k_tsel(const z64* Pb, int n, int k0, 
   __shared__ int sel[kGjNb];
   __shared__ uint64_t wkey[kTsRows / 64];
   __shared__ int s_p, s_m;
-  __shared__ z64 W[kGjNb][2 * kGjNb + 1];
-  __shared__ z64 fcol[kGjNb];
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int g = blockIdx.x;
   int row = -1;
@@ -155,38 +185,30 @@ __global__ __launch_bounds__(kTsRows) void k_tsel(const z64* Pb, int n, int k0, 
   }
   if (t < nsel) out[g * kGjNb + t] = idx[sel[t]];
   if (t == 0) cnt_out[g] = nsel;
-  if (!final_) return;
+  if (!final_ || t >= 64) return;
   // B11 from the FP64 panel rows of the winners, inverted by Gauss-Jordan in
-  // the winners' order (their elimination above needed no interchange).
-  for (int e = t; e < kGjNb * 2 * kGjNb; e += kTsRows) {
-    const int r = e / (2 * kGjNb), c = e % (2 * kGjNb);
+  // the winners' order (their elimination above needed no interchange), by
+  // wave 0 alone in registers: lane (h, j) = (t / 32, t % 32) holds column j
+  // of [B11 | I] for rows 8h .. 8h+7; rows and columns pass by shuffles, so
+  // there is no barrier.
+  const int hh = t >> 5, j = t & 31;
+  z64 w[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int r = 8 * hh + i;
     z64 v{0.0, 0.0};
-    if (c < kGjNb) {
-      if (r < nsel && c < ncols) v = Pb[size_t(idx[sel[r]]) * kGjNb + c];
-      else if (r == c) v = z64{1.0, 0.0};       // padding of a ragged panel
-    } else if (c - kGjNb == r) {
+    if (j < kGjNb) {
+      if (r < nsel && j < ncols) v = Pb[size_t(idx[sel[r]]) * kGjNb + j];
+      else if (r == j) v = z64{1.0, 0.0};       // padding of a ragged panel
+    } else if (j - kGjNb == r) {
       v = z64{1.0, 0.0};
     }
-    W[r][c] = v;
+    w[i] = v;
   }
-  __syncthreads();
-  for (int c = 0; c < kGjNb; ++c) {
-    const z64 pv = W[c][c];
-    const z64 inv = (zabs2(pv) > 0.0) ? zdiv(z64{1.0, 0.0}, pv) : z64{0.0, 0.0};
-    __syncthreads();
-    if (t < 2 * kGjNb) W[c][t] = zmul(W[c][t], inv);
-    if (t < kGjNb) fcol[t] = W[t][c];
-    __syncthreads();
-    for (int e = t; e < kGjNb * 2 * kGjNb; e += kTsRows) {
-      const int r = e / (2 * kGjNb), cc = e % (2 * kGjNb);
-      if (r != c) W[r][cc] = zsub(W[r][cc], zmul(fcol[r], W[c][cc]));
-    }
-    __syncthreads();
-  }
-  for (int e = t; e < kGjNb * kGjNb; e += kTsRows) {
-    const int r = e / kGjNb, c = e % kGjNb;
-    B11inv[e] = W[r][kGjNb + c];
-  }
+  b11_columns(w, hh, j, std::make_integer_sequence<int, kGjNb>{});
+  if (j >= kGjNb)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) B11inv[(8 * hh + i) * kGjNb + (j - kGjNb)] = w[i];
   if (t < nsel) {
     const int rw = idx[sel[t]];
     piv[k0 + t] = rw;
