@@ -637,7 +637,7 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
     h->ev_pool.back() = reinterpret_cast<hipEvent_t>(intptr_t(KID_ACCEPT) | (intptr_t(acc) << 8));
   }
   h->nacc_seen = pinned->n_acc;
-  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  // (the events are read once, at the end of the search)
   return normalize(h, pinned);
 }
 
