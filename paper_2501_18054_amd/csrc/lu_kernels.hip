@@ -42,6 +42,7 @@ constexpr int kGjNb = 16;
 constexpr int kUpdRows = 16;
 constexpr int kTsRows = 1024;              // candidate rows per tournament group
 constexpr int kTsFan = kTsRows / kGjNb;    // proposals merged per group
+constexpr int kTsWgMaxRows = 64 * 64;      // one-wave level-0 groups merged by one workgroup
 
 // K[a][b] = delta_ab - k2d G[s_a][s_b]; clears the pivot marks.
 __global__ __launch_bounds__(256) void k_gather_K(z64* K, const z64* G, int ld, const int32_t* sidx,
@@ -213,6 +214,203 @@ __global__ __launch_bounds__(kTsRows) void k_tsel(const z64* Pb, int n, int k0, 
     const int rw = idx[sel[t]];
     piv[k0 + t] = rw;
     used[rw] = k0 + t + 1;
+  }
+}
+
+// Broadcast of lane p's value to the wave (p wave-uniform).
+__device__ __forceinline__ float lane_f(float v, int p) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), p));
+}
+__device__ __forceinline__ double lane_d(double v, int p) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b)), p));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b >> 32)), p));
+  return __longlong_as_double(static_cast<long long>((uint64_t(hi) << 32) | lo));
+}
+
+// Maximum over the wave: DPP exchanges within each row of 16 lanes (quad
+// swaps, then rotations by 4 and 8), then the four row maxima by readlane.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  uint32_t o;
+  o = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = o > v ? o : v;
+  o = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = o > v ? o : v;
+  o = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x124, 0xF, 0xF, false));  // row_ror 4
+  v = o > v ? o : v;
+  o = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x128, 0xF, 0xF, false));  // row_ror 8
+  v = o > v ? o : v;
+  const uint32_t a = uint32_t(__builtin_amdgcn_readlane(int(v), 0));
+  const uint32_t b = uint32_t(__builtin_amdgcn_readlane(int(v), 16));
+  const uint32_t c = uint32_t(__builtin_amdgcn_readlane(int(v), 32));
+  const uint32_t d = uint32_t(__builtin_amdgcn_readlane(int(v), 48));
+  const uint32_t ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
+// Elimination column C of a one-wave tournament group (rows in registers,
+// one per lane): the live row of largest |a_C|^2 pivots (the lowest lane on
+// ties; key 0 marks a lane with no live row), its row is broadcast by
+// readlane and every row is reduced by it.  Rows that are no longer live are
+// reduced too: nothing reads them again.
+template <int C>
+__device__ __forceinline__ void wt_column(z32 (&a)[kGjNb], bool& alive, int lane, int nsel,
+                                          int& order, bool& zero) {
+  if (C >= nsel) return;
+  const float m = a[C].re * a[C].re + a[C].im * a[C].im;
+  const uint32_t key = alive ? __float_as_uint(m) + 1u : 0u;
+  const uint32_t mx = wave_max_u32(key);
+  const unsigned long long hit = __ballot(key == mx);
+  const int p = __builtin_amdgcn_readfirstlane(__ffsll(static_cast<long long>(hit)) - 1);
+  if (mx <= 1u) zero = true;
+  if (lane == p) {
+    order = C;
+    alive = false;
+  }
+  const float pr = lane_f(a[C].re, p), pi = lane_f(a[C].im, p);
+  const float d = pr * pr + pi * pi;
+  const float sc = d > 0.f ? __builtin_amdgcn_rcpf(d) : 0.f;   // selection only: 1 ulp is enough
+  const float ir = pr * sc, ii = -pi * sc;
+  const float lr = a[C].re * ir - a[C].im * ii, li = a[C].re * ii + a[C].im * ir;
+#pragma unroll
+  for (int cc = C + 1; cc < kGjNb; ++cc) {
+    const float ur = lane_f(a[cc].re, p), ui = lane_f(a[cc].im, p);
+    a[cc].re = fmaf(li, ui, fmaf(-lr, ur, a[cc].re));
+    a[cc].im = fmaf(-li, ur, fmaf(-lr, ui, a[cc].im));
+  }
+}
+
+template <int... Cs>
+__device__ __forceinline__ void wt_columns(z32 (&a)[kGjNb], bool& alive, int lane, int nsel,
+                                           int& order, bool& zero,
+                                           std::integer_sequence<int, Cs...>) {
+  (wt_column<Cs>(a, alive, lane, nsel, order, zero), ...);
+}
+
+// One tournament group in one wave: candidate `row` of this lane (< 0: none)
+// proposes min(ncols, #candidates) pivot rows by partial pivoting on
+// complex-FP32 copies of the panel rows; writes them in pivot order to
+// out[0..count) and the count to *cnt.  Returns whether a chosen pivot had
+// magnitude zero.
+__device__ __forceinline__ bool wave_tournament(const z64* Pb, int ncols, int row, int lane,
+                                                int* out, int* cnt) {
+  z32 a[kGjNb];
+#pragma unroll
+  for (int c = 0; c < kGjNb; ++c) {
+    z32 v{0.f, 0.f};
+    if (row >= 0 && c < ncols) {
+      const z64 x = Pb[size_t(row) * kGjNb + c];
+      v = z32{float(x.re), float(x.im)};
+    }
+    a[c] = v;
+  }
+  bool alive = row >= 0;
+  const int nsel = min(ncols, int(__popcll(__ballot(alive))));
+  int order = -1;
+  bool zero = false;
+  wt_columns(a, alive, lane, nsel, order, zero, std::make_integer_sequence<int, kGjNb>{});
+  if (order >= 0) out[order] = row;
+  if (lane == 0) *cnt = nsel;
+  return zero;
+}
+
+// Gauss-Jordan column C of [B11 | I] held one column per lane (lane j holds
+// column j, rows in registers): the pivot row is every lane's own register C,
+// the factors column C come from lane C by readlane.
+template <int C>
+__device__ __forceinline__ void gj_lane_column(z64 (&w)[kGjNb]) {
+  const z64 pv{lane_d(w[C].re, C), lane_d(w[C].im, C)};
+  const z64 inv = (zabs2(pv) > 0.0) ? zdiv(z64{1.0, 0.0}, pv) : z64{0.0, 0.0};
+  const z64 prow = zmul(w[C], inv);
+#pragma unroll
+  for (int i = 0; i < kGjNb; ++i) {
+    if (i == C) continue;
+    const z64 f{lane_d(w[i].re, C), lane_d(w[i].im, C)};
+    w[i] = zsub(w[i], zmul(f, prow));
+  }
+  w[C] = prow;
+}
+
+template <int... Cs>
+__device__ __forceinline__ void gj_lane_columns(z64 (&w)[kGjNb],
+                                                std::integer_sequence<int, Cs...>) {
+  (gj_lane_column<Cs>(w), ...);
+}
+
+// Level 0 of a panel's tournament spread over the chip: workgroup g (one
+// wave) proposes up to kGjNb of the rows [64g, 64g + 64) that are not yet
+// pivots, into cand[16g ..] and cnt[g].
+__global__ __launch_bounds__(64) void k_tsel_l0(const z64* Pb, int n, int ncols,
+                                                const int32_t* used, int32_t* cand,
+                                                int32_t* cnt) {
+  const int lane = threadIdx.x, g = blockIdx.x;
+  int row = g * 64 + lane;
+  if (row >= n || used[row]) row = -1;
+  wave_tournament(Pb, ncols, row, lane, cand + g * kGjNb, cnt + g);
+}
+
+// The rest of a panel's tournament in one workgroup of nw = blockDim/64 <= 16
+// waves.  Its first level is either level 0 itself (gcand null, n <= 64 nw:
+// one group of 64 rows per wave) or a merge of the ngin <= 4 nw groups that
+// k_tsel_l0 proposed (four per wave).  Each further level merges the
+// proposals of four groups in one wave, with a barrier between levels, until
+// wave 0 holds the winners.  Wave 0 then writes piv, used and B11^-1
+// (inverted in FP64, one column per lane), and flags a zero pivot of the
+// final level in *status.
+__global__ __launch_bounds__(1024) void k_tsel_wg(const z64* Pb, int n, int k0, int ncols,
+                                                  const int32_t* gcand, const int32_t* gcnt,
+                                                  int ngin, int32_t* piv, int32_t* used,
+                                                  z64* B11inv, int32_t* status) {
+  __shared__ int prop[2][16 * kGjNb];
+  __shared__ int pcnt[2][16];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  int groups = int(blockDim.x) >> 6;
+  int row = -1;
+  if (gcand == nullptr) {
+    row = wid * 64 + lane;
+    if (row >= n || used[row]) row = -1;
+  } else {
+    const int grp = wid * 4 + lane / kGjNb, u = lane % kGjNb;
+    if (grp < ngin && u < gcnt[grp]) row = gcand[grp * kGjNb + u];
+  }
+  bool zero = wave_tournament(Pb, ncols, row, lane, &prop[0][wid * kGjNb], &pcnt[0][wid]);
+  int cur = 0;
+  while (groups > 1) {
+    __syncthreads();
+    const int ng = (groups + 3) / 4;
+    if (wid < ng) {
+      const int grp = wid * 4 + lane / kGjNb, u = lane % kGjNb;
+      const int r = (grp < groups && u < pcnt[cur][grp]) ? prop[cur][grp * kGjNb + u] : -1;
+      zero = wave_tournament(Pb, ncols, r, lane, &prop[cur ^ 1][wid * kGjNb], &pcnt[cur ^ 1][wid]);
+    }
+    cur ^= 1;
+    groups = ng;
+  }
+  __syncthreads();
+  if (wid != 0) return;
+  const int nsel = pcnt[cur][0];
+  if (zero && lane == 0) atomicOr(status, 1);
+  const int j = lane;
+  z64 w[kGjNb];
+#pragma unroll
+  for (int r = 0; r < kGjNb; ++r) {
+    z64 v{0.0, 0.0};
+    if (j < kGjNb) {
+      if (r < nsel && j < ncols) v = Pb[size_t(prop[cur][r]) * kGjNb + j];
+      else if (r == j) v = z64{1.0, 0.0};       // padding of a ragged panel
+    } else if (j - kGjNb == r) {
+      v = z64{1.0, 0.0};
+    }
+    w[r] = v;
+  }
+  gj_lane_columns(w, std::make_integer_sequence<int, kGjNb>{});
+  if (j >= kGjNb && j < 2 * kGjNb)
+#pragma unroll
+    for (int r = 0; r < kGjNb; ++r) B11inv[r * kGjNb + (j - kGjNb)] = w[r];
+  if (lane < nsel) {
+    const int rw = prop[cur][lane];
+    piv[k0 + lane] = rw;
+    used[rw] = k0 + lane + 1;
   }
 }
 
@@ -419,21 +617,33 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
                        0, min(kGjNb, ns), Pb);
     for (int k0 = 0; k0 < ns; k0 += kGjNb) {
       const int nc = min(kGjNb, ns - k0);
-      int groups = g0;
-      int32_t *cin = nullptr, *nin = nullptr, *cout = candA, *nout = cntA;
-      int level0 = 1, ngin = 0;
-      while (true) {
-        const int fin = (groups == 1) ? 1 : 0;
-        hipLaunchKernelGGL(k_tsel, dim3(groups), dim3(kTsRows), 0, s, Pb, ns, k0, nc, level0, cin,
-                           nin, ngin, cout, nout, fin, piv, used, B11inv, status);
-        if (fin) break;
-        level0 = 0;
-        cin = cout;
-        nin = nout;
-        ngin = groups;
-        cout = (cout == candA) ? candB : candA;
-        nout = (nout == cntA) ? cntB : cntA;
-        groups = (groups + kTsFan - 1) / kTsFan;
+      if (ns <= 64) {
+        hipLaunchKernelGGL(k_tsel_wg, dim3(1), dim3(64), 0, s, Pb, ns, k0, nc,
+                           static_cast<const int32_t*>(nullptr),
+                           static_cast<const int32_t*>(nullptr), 0, piv, used, B11inv, status);
+      } else if (ns <= kTsWgMaxRows) {
+        const int g = (ns + 63) / 64;
+        hipLaunchKernelGGL(k_tsel_l0, dim3(g), dim3(64), 0, s, Pb, ns, nc, used, tsbuf,
+                           tsbuf + g * kGjNb);
+        hipLaunchKernelGGL(k_tsel_wg, dim3(1), dim3(64 * ((g + 3) / 4)), 0, s, Pb, ns, k0, nc,
+                           tsbuf, tsbuf + g * kGjNb, g, piv, used, B11inv, status);
+      } else {
+        int groups = g0;
+        int32_t *cin = nullptr, *nin = nullptr, *cout = candA, *nout = cntA;
+        int level0 = 1, ngin = 0;
+        while (true) {
+          const int fin = (groups == 1) ? 1 : 0;
+          hipLaunchKernelGGL(k_tsel, dim3(groups), dim3(kTsRows), 0, s, Pb, ns, k0, nc, level0, cin,
+                             nin, ngin, cout, nout, fin, piv, used, B11inv, status);
+          if (fin) break;
+          level0 = 0;
+          cin = cout;
+          nin = nout;
+          ngin = groups;
+          cout = (cout == candA) ? candB : candA;
+          nout = (nout == cntA) ? cntB : cntA;
+          groups = (groups + kTsFan - 1) / kTsFan;
+        }
       }
       const int napply = (ns + 15) / 16;
       const int ncopy = (nc * ns + 255) / 256;
