@@ -19,9 +19,11 @@
 // elimination is that of Pi K with (Pi K)[k,:] = K[p_k,:], the in-place result
 // M satisfies (Pi K)^-1[k,:] = M[p_k,:], and K^-1[i, p_l] = M[p_i, l].
 // A panel of kGjNb columns picks its pivot rows by tournament pivoting
-// (Grigori-Demmel-Xiang CALU): groups of rows each propose kGjNb rows by
-// partial-pivoting elimination, proposals are reduced again until one group
-// remains; the winners' block B11 is inverted and every row is reduced
+// (Grigori-Demmel-Xiang CALU): groups of 64 rows, one group per wave, each
+// propose kGjNb rows by partial-pivoting elimination in registers; the
+// proposals of four groups form the next level's group until one remains
+// (the first levels one wave per workgroup across the chip, the last ones in
+// one workgroup); the winners' block B11 is inverted and every row is reduced
 // independently, giving the Gauss-Jordan panel [-B01 B11^-1; B11^-1;
 // -B21 B11^-1].  Every column outside the panel then gets the rank-kGjNb
 // update M[r,j] = (r pivot of this panel ? 0 : M[r,j]) + P[r,:] B1[:,j] with
@@ -40,9 +42,6 @@ hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64
 
 constexpr int kGjNb = 16;
 constexpr int kUpdRows = 16;
-constexpr int kTsRows = 1024;              // candidate rows per tournament group
-constexpr int kTsFan = kTsRows / kGjNb;    // proposals merged per group
-constexpr int kTsWgMaxRows = 64 * 64;      // one-wave level-0 groups merged by one workgroup
 
 // K[a][b] = delta_ab - k2d G[s_a][s_b]; clears the pivot marks.
 __global__ __launch_bounds__(256) void k_gather_K(z64* K, const z64* G, int ld, const int32_t* sidx,
@@ -61,160 +60,6 @@ __global__ __launch_bounds__(256) void k_gj_panel_in(const z64* S, int ld, int n
   const int e = blockIdx.x * 256 + threadIdx.x;
   const int r = e / kGjNb, c = e % kGjNb;
   if (r < n) Pb[e] = (c < ncols) ? S[size_t(r) * ld + k0 + c] : z64{0.0, 0.0};
-}
-
-// Gauss-Jordan column C of the wave-resident [B11 | I] (see k_tsel): the
-// pivot row C lives in half C / 8 at register C % 8.
-__device__ __forceinline__ z64 shfl_z64(z64 v, int src) {
-  return z64{__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
-}
-
-template <int C>
-__device__ __forceinline__ void b11_column(z64 (&w)[8], int hh, int j) {
-  constexpr int ph = C / 8, pr = C % 8;
-  const z64 pv = shfl_z64(w[pr], ph * 32 + C);
-  const z64 inv = (zabs2(pv) > 0.0) ? zdiv(z64{1.0, 0.0}, pv) : z64{0.0, 0.0};
-  // factors of this lane's rows: their entries in column C (same half)
-  z64 fr[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) fr[i] = shfl_z64(w[i], hh * 32 + C);
-  // scaled pivot row entry of this lane's column
-  const z64 prow = zmul(shfl_z64(w[pr], ph * 32 + j), inv);
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    if (hh == ph && i == pr) w[i] = prow;
-    else w[i] = zsub(w[i], zmul(fr[i], prow));
-  }
-}
-
-template <int... Cs>
-__device__ __forceinline__ void b11_columns(z64 (&w)[8], int hh, int j,
-                                            std::integer_sequence<int, Cs...>) {
-  (b11_column<Cs>(w, hh, j), ...);
-}
-
-// Packed (|a|^2, slot) key for the pivot search: FP32 magnitude bits in the
-// high word (monotonic for non-negative floats), the complemented slot in the
-// low word so that ties prefer the smaller slot.
-__device__ __forceinline__ uint64_t piv_key(float a, int slot) {
-  return (uint64_t(__float_as_uint(a)) << 32) | uint64_t(0xFFFFFFFFu - uint32_t(slot));
-}
-
-// One tournament group per workgroup, one candidate row per thread.  The
-// pivot search runs on a complex-FP32 copy of the panel rows in LDS: it only
-// chooses which rows pivot (the reduction itself is done in FP64 by
-// k_tapply from the original rows).  level0: slot t is row g*kTsRows+t unless
-// already a pivot; otherwise proposal t%kGjNb of group g*kTsFan+t/kGjNb.
-// Writes the group's proposals (in pivot order) and their count.  final_:
-// writes piv, used and B11^-1 (row c <-> column k0+c), inverted in FP64.
-__global__ __launch_bounds__(kTsRows) void k_tsel(const z64* Pb, int n, int k0, int ncols,
-                                                  int level0, const int32_t* in,
-                                                  const int32_t* cnt_in, int ngroups_in,
-                                                  int32_t* out, int32_t* cnt_out, int final_,
-                                                  int32_t* piv, int32_t* used, z64* B11inv,
-                                                  int32_t* status) {
-  __shared__ z32 A[kTsRows][kGjNb + 1];   // +1: conflict-free LDS rows
-  __shared__ int idx[kTsRows];
-  __shared__ int sel[kGjNb];
-  __shared__ uint64_t wkey[kTsRows / 64];
-  __shared__ int s_p, s_m;
-  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  const int g = blockIdx.x;
-  int row = -1;
-  if (level0) {
-    const int r = g * kTsRows + t;
-    if (r < n && !used[r]) row = r;
-  } else {
-    const int grp = g * kTsFan + t / kGjNb, u = t % kGjNb;
-    if (grp < ngroups_in && u < cnt_in[grp]) row = in[grp * kGjNb + u];
-  }
-  idx[t] = row;
-  bool alive = row >= 0;
-#pragma unroll
-  for (int c = 0; c < kGjNb; ++c) {
-    z32 v{0.f, 0.f};
-    if (alive && c < ncols) {
-      const z64 x = Pb[size_t(row) * kGjNb + c];
-      v = z32{float(x.re), float(x.im)};
-    }
-    A[t][c] = v;
-  }
-  const int cnt = __syncthreads_count(alive);
-  if (t == 0) s_m = cnt;
-  __syncthreads();
-  const int nsel = min(ncols, s_m);
-  for (int c = 0; c < nsel; ++c) {
-    uint64_t key = 0;
-    if (alive) {
-      const z32 v = A[t][c];
-      key = piv_key(v.re * v.re + v.im * v.im, t);
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const uint64_t ok = static_cast<uint64_t>(__shfl_xor(static_cast<long long>(key), o, 64));
-      key = ok > key ? ok : key;
-    }
-    if (lane == 0) wkey[wid] = key;
-    __syncthreads();
-    if (t == 0) {
-      uint64_t k = wkey[0];
-      for (int w = 1; w < kTsRows / 64; ++w) k = wkey[w] > k ? wkey[w] : k;
-      const int p = int(0xFFFFFFFFu - uint32_t(k & 0xFFFFFFFFu));
-      sel[c] = p;
-      s_p = p;
-      if (final_ && !((k >> 32) > 0)) atomicOr(status, 1);
-    }
-    __syncthreads();
-    const int p = s_p;
-    if (t == p) alive = false;
-    if (alive) {
-      const z32 pv = A[p][c];
-      const float d = pv.re * pv.re + pv.im * pv.im;
-      const z32 a = A[t][c];
-      // l = a / pv
-      const z32 l = d > 0.f ? z32{(a.re * pv.re + a.im * pv.im) / d, (a.im * pv.re - a.re * pv.im) / d}
-                            : z32{0.f, 0.f};
-      for (int cc = c + 1; cc < kGjNb; ++cc) {
-        const z32 u = A[p][cc];
-        z32 x = A[t][cc];
-        x.re -= l.re * u.re - l.im * u.im;
-        x.im -= l.re * u.im + l.im * u.re;
-        A[t][cc] = x;
-      }
-    }
-    __syncthreads();
-  }
-  if (t < nsel) out[g * kGjNb + t] = idx[sel[t]];
-  if (t == 0) cnt_out[g] = nsel;
-  if (!final_ || t >= 64) return;
-  // B11 from the FP64 panel rows of the winners, inverted by Gauss-Jordan in
-  // the winners' order (their elimination above needed no interchange), by
-  // wave 0 alone in registers: lane (h, j) = (t / 32, t % 32) holds column j
-  // of [B11 | I] for rows 8h .. 8h+7; rows and columns pass by shuffles, so
-  // there is no barrier.
-  const int hh = t >> 5, j = t & 31;
-  z64 w[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int r = 8 * hh + i;
-    z64 v{0.0, 0.0};
-    if (j < kGjNb) {
-      if (r < nsel && j < ncols) v = Pb[size_t(idx[sel[r]]) * kGjNb + j];
-      else if (r == j) v = z64{1.0, 0.0};       // padding of a ragged panel
-    } else if (j - kGjNb == r) {
-      v = z64{1.0, 0.0};
-    }
-    w[i] = v;
-  }
-  b11_columns(w, hh, j, std::make_integer_sequence<int, kGjNb>{});
-  if (j >= kGjNb)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) B11inv[(8 * hh + i) * kGjNb + (j - kGjNb)] = w[i];
-  if (t < nsel) {
-    const int rw = idx[sel[t]];
-    piv[k0 + t] = rw;
-    used[rw] = k0 + t + 1;
-  }
 }
 
 // Broadcast of lane p's value to the wave (p wave-uniform).
@@ -337,15 +182,23 @@ __device__ __forceinline__ void gj_lane_columns(z64 (&w)[kGjNb],
   (gj_lane_column<Cs>(w), ...);
 }
 
-// Level 0 of a panel's tournament spread over the chip: workgroup g (one
-// wave) proposes up to kGjNb of the rows [64g, 64g + 64) that are not yet
-// pivots, into cand[16g ..] and cnt[g].
-__global__ __launch_bounds__(64) void k_tsel_l0(const z64* Pb, int n, int ncols,
-                                                const int32_t* used, int32_t* cand,
-                                                int32_t* cnt) {
+// One level of a panel's tournament spread over the chip, one group per
+// one-wave workgroup g, proposals into cand[16g ..] and cnt[g].  Level 0
+// (gin null): the rows [64g, 64g + 64) that are not yet pivots; a merge
+// level: the proposals of groups 4g .. 4g+3 of the ngin in (gin, gcnt).
+__global__ __launch_bounds__(64) void k_tsel_wave(const z64* Pb, int n, int ncols,
+                                                  const int32_t* used, const int32_t* gin,
+                                                  const int32_t* gcnt, int ngin, int32_t* cand,
+                                                  int32_t* cnt) {
   const int lane = threadIdx.x, g = blockIdx.x;
-  int row = g * 64 + lane;
-  if (row >= n || used[row]) row = -1;
+  int row = -1;
+  if (gin == nullptr) {
+    row = g * 64 + lane;
+    if (row >= n || used[row]) row = -1;
+  } else {
+    const int grp = g * 4 + lane / kGjNb, u = lane % kGjNb;
+    if (grp < ngin && u < gcnt[grp]) row = gin[grp * kGjNb + u];
+  }
   wave_tournament(Pb, ncols, row, lane, cand + g * kGjNb, cnt + g);
 }
 
@@ -605,11 +458,10 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
                           int32_t* status, int32_t* tsbuf, z64* B11inv, hipStream_t s) {
   const int nz = nd - ns;
   if (ns > 0) {
-    const int g0 = (ns + kTsRows - 1) / kTsRows;
+    // two proposal lists (ids and counts) of (kGjNb + 1) ints per group
+    const int g0 = (ns + 63) / 64;
     int32_t* candA = tsbuf;
-    int32_t* candB = tsbuf + g0 * kGjNb;
-    int32_t* cntA = tsbuf + 2 * g0 * kGjNb;
-    int32_t* cntB = cntA + g0;
+    int32_t* candB = tsbuf + g0 * (kGjNb + 1);
     const dim3 gcols((ns + 255) / 256);
     hipLaunchKernelGGL(k_gather_K, dim3(gcols.x, ns), dim3(256), 0, s, S, G, ld, sidx, ns, k2d,
                        used);
@@ -621,29 +473,27 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
         hipLaunchKernelGGL(k_tsel_wg, dim3(1), dim3(64), 0, s, Pb, ns, k0, nc,
                            static_cast<const int32_t*>(nullptr),
                            static_cast<const int32_t*>(nullptr), 0, piv, used, B11inv, status);
-      } else if (ns <= kTsWgMaxRows) {
-        const int g = (ns + 63) / 64;
-        hipLaunchKernelGGL(k_tsel_l0, dim3(g), dim3(64), 0, s, Pb, ns, nc, used, tsbuf,
-                           tsbuf + g * kGjNb);
-        hipLaunchKernelGGL(k_tsel_wg, dim3(1), dim3(64 * ((g + 3) / 4)), 0, s, Pb, ns, k0, nc,
-                           tsbuf, tsbuf + g * kGjNb, g, piv, used, B11inv, status);
       } else {
-        int groups = g0;
-        int32_t *cin = nullptr, *nin = nullptr, *cout = candA, *nout = cntA;
-        int level0 = 1, ngin = 0;
-        while (true) {
-          const int fin = (groups == 1) ? 1 : 0;
-          hipLaunchKernelGGL(k_tsel, dim3(groups), dim3(kTsRows), 0, s, Pb, ns, k0, nc, level0, cin,
-                             nin, ngin, cout, nout, fin, piv, used, B11inv, status);
-          if (fin) break;
-          level0 = 0;
-          cin = cout;
-          nin = nout;
-          ngin = groups;
-          cout = (cout == candA) ? candB : candA;
-          nout = (nout == cntA) ? cntB : cntA;
-          groups = (groups + kTsFan - 1) / kTsFan;
+        // level 0, then merge levels on the chip until one workgroup's
+        // sixteen waves can merge the rest (<= 64 groups)
+        int g = (ns + 63) / 64;
+        int32_t* cand = candA;
+        int32_t* cnt = candA + g * kGjNb;
+        hipLaunchKernelGGL(k_tsel_wave, dim3(g), dim3(64), 0, s, Pb, ns, nc, used,
+                           static_cast<const int32_t*>(nullptr),
+                           static_cast<const int32_t*>(nullptr), 0, cand, cnt);
+        while (g > 64) {
+          const int ng = (g + 3) / 4;
+          int32_t* ocand = (cand == candA) ? candB : candA;
+          int32_t* ocnt = ocand + ng * kGjNb;
+          hipLaunchKernelGGL(k_tsel_wave, dim3(ng), dim3(64), 0, s, Pb, ns, nc, used, cand, cnt,
+                             g, ocand, ocnt);
+          cand = ocand;
+          cnt = ocnt;
+          g = ng;
         }
+        hipLaunchKernelGGL(k_tsel_wg, dim3(1), dim3(64 * ((g + 3) / 4)), 0, s, Pb, ns, k0, nc,
+                           cand, cnt, g, piv, used, B11inv, status);
       }
       const int napply = (ns + 15) / 16;
       const int ncopy = (nc * ns + 255) / 256;

@@ -248,11 +248,8 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_B1[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
     L.off_Pb[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
     L.off_Pn[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
-    // tournament proposals: the multi-level form's two candidate lists and
-    // counts, or the one-wave level 0's (kGjNb + 1) ints per 64 rows
-    L.off_ts[f] = take(std::max(size_t(4) * ((nd + 1023) / 1024) * pngf::kGjNbHost,
-                                size_t(pngf::kGjNbHost + 1) * ((nd + 63) / 64)) *
-                           sizeof(int32_t) + 1024);
+    // tournament proposals: two lists of (kGjNb + 1) ints per 64-row group
+    L.off_ts[f] = take(size_t(2) * (pngf::kGjNbHost + 1) * ((nd + 63) / 64) * sizeof(int32_t));
     L.off_B11[f] = take(size_t(pngf::kGjNbHost) * pngf::kGjNbHost * sizeof(z64));
     L.off_piv[f] = take(size_t(nd) * sizeof(int32_t));
     L.off_invp[f] = take(size_t(nd) * sizeof(int32_t));
