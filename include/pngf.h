@@ -91,6 +91,16 @@ enum { PNGF_FP64_PLAIN = 0, PNGF_MIXED = 1, PNGF_RFORM = 2 };
 /* pngf_options.flags: record HIP events around every hot-path kernel launch
  * so pngf_kernel_times can report average device time per kernel. */
 #define PNGF_FLAG_TIMING 1ull
+/* pngf_options.flags: run every step of the mixed search as its own kernel
+ * launch.  Without it, a single-frequency mixed search with N_d <= 2048 runs
+ * each batch of steps as one launch whose workgroups (N_d / 8, at most one
+ * per compute unit) keep their rows of C0^-1 in registers and meet at a grid
+ * barrier between steps (same arithmetic, same results); it falls back to
+ * one launch per step by itself where the grid cannot be resident at once.
+ * Its barrier waits are bounded: if the device is shared and the workgroups
+ * cannot all run, the search fails with PNGF_ENUMERIC after about a second
+ * instead of waiting for ever. */
+#define PNGF_FLAG_STEP_LAUNCHES 2ull
 
 typedef struct pngf_handle pngf_handle;
 

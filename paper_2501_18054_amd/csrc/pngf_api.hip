@@ -20,6 +20,8 @@ hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int
                              uint32_t* keyp, hipStream_t s);
 hipError_t launch_plain_step(const ProbDev& P, int npl, int step, hipStream_t s);
 hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s);
+hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint32_t* bar,
+                                int32_t* flag, int spin_limit, hipStream_t s);
 hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
                              int grid, int npl, int mixed, int step, hipStream_t s);
@@ -68,6 +70,11 @@ hipError_t launch_band_measure(const double* df32, const double* bnd32, const do
 constexpr int kGjNbHost = 16;
 constexpr int kPanelCap = 64;      // deferred Sherman-Morrison terms (mixed)
 constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
+constexpr int kPersistBatch = 32;  // steps of one persistent launch (periodic refresh)
+constexpr int kPersistSpin = 1 << 20;   // polls of a persistent-search grid barrier
+constexpr int kPersistSlotsHost = 64;   // panel slots the persistent search holds in LDS
+constexpr int kPersistBarWords = 32 * 17;   // grid-barrier words of the persistent search
+constexpr size_t kPersistBarBytes = (kPersistBarWords + 32) * sizeof(int32_t);
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
 constexpr int kTilePartPerPixel = 512;   // tile-score partial blocks (complex) per pixel
@@ -107,7 +114,7 @@ struct Layout {
   size_t off_S[pngf::kMaxFreq], off_B1[pngf::kMaxFreq], off_Pb[pngf::kMaxFreq],
       off_Pn[pngf::kMaxFreq], off_ts[pngf::kMaxFreq], off_B11[pngf::kMaxFreq],
       off_piv[pngf::kMaxFreq], off_invp[pngf::kMaxFreq], off_used[pngf::kMaxFreq];
-  size_t off_status, off_u[pngf::kMaxFreq], off_r[pngf::kMaxFreq];
+  size_t off_status, off_pbar, off_u[pngf::kMaxFreq], off_r[pngf::kMaxFreq];
   size_t off_wP[pngf::kMaxFreq], off_wQ[pngf::kMaxFreq], off_wW[pngf::kMaxFreq],
       off_wCap[pngf::kMaxFreq], off_wWork[pngf::kMaxFreq];
   size_t off_wF, off_wS, off_tiles, off_tpart;
@@ -127,6 +134,7 @@ struct pngf_handle {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int ld = 0, npl = 1;
+  bool persist_off = false;   // a cooperative launch of the persistent search failed
   Layout lay{};
   pngf::ProbDev P{};
   std::vector<uint8_t> bits;
@@ -259,6 +267,7 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
   L.off_zidx = take(size_t(nd) * sizeof(int32_t));
   L.off_pos = take(size_t(nd) * sizeof(int32_t));
   L.off_status = take(sizeof(int32_t));
+  L.off_pbar = take(pngf::kPersistBarBytes);   // grid-barrier words, then the time-out flag
   for (int f = 0; f < F; ++f) {
     L.off_u[f] = take(vec);
     L.off_r[f] = take(vec);
@@ -604,16 +613,35 @@ int normalize(pngf_handle* h, pngf::DbsState* st) {
 }
 
 // Run `n` (even) steps starting at step index t0, then read the state.
+// persist: the n steps of the mixed search as one launch of resident workgroups.
 template <class L>
 int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinned,
-              bool want_bits = false) {
+              bool want_bits = false, bool persist = false) {
   // one event pair around the back-to-back step launches (the average per
   // launch includes the gaps between them)
   Timer t(h, KID_ACCEPT);
-  for (int b = 0; b < n; ++b) HIPCHK(h, launch(h->P, h->npl, int(t0 + b), h->stream));
+  int32_t* pbar = at<int32_t>(h, h->lay.off_pbar);
+  if (persist) {
+    const hipError_t e = pngf::launch_mixed_persist(h->P, int(t0), n,
+                                                    reinterpret_cast<uint32_t*>(pbar),
+                                                    pbar + pngf::kPersistBarWords, pngf::kPersistSpin,
+                                                    h->stream);
+    if (e != hipSuccess) {
+      // the grid cannot be co-resident here: one kernel per step from now on
+      (void)hipGetLastError();
+      h->persist_off = true;
+      persist = false;
+    }
+  }
+  if (!persist)
+    for (int b = 0; b < n; ++b) HIPCHK(h, launch(h->P, h->npl, int(t0 + b), h->stream));
   t.end(n);
   h->bits_fresh = false;
   const int nd = h->pc.n_d;
+  int32_t tmo = 0;
+  if (persist)
+    HIPCHK(h, hipMemcpyAsync(&tmo, pbar + pngf::kPersistBarWords, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
                            h->stream));
   if (want_bits) {
@@ -625,6 +653,7 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
     HIPCHK(h, hipMemcpyAsync(h->bits_pin + nd, h->P.bitsB, nd, hipMemcpyDeviceToHost, h->stream));
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (tmo) return fail(h, PNGF_ENUMERIC, "a grid barrier of the persistent search timed out");
   if (want_bits) {
     // the design of the last step (in the B set after an odd number of updates)
     const uint8_t* cur = h->bits_pin + ((pinned->flips & 1) ? nd : 0);
@@ -755,17 +784,25 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
   int64_t since = 0, kpan = 0;   // host view of n_since / kpanel
   int64_t checked = 0;           // n_since at the last drift check
   for (int64_t round = 0; round < max_rounds; ++round) {
+    const bool persist = !h->persist_off && F == 1 && nd <= 2048 &&
+                         h->P.kcap <= pngf::kPersistSlotsHost &&
+                         !(h->opt.flags & PNGF_FLAG_STEP_LAUNCHES);
     // end the batch where a periodic re-inversion or a fold is due, so that
-    // few launches of the batch find the search paused; batches stay even
-    int nb = pngf::kMixedBatch;
+    // few launches of the batch find the search paused; batches stay even.
+    // Persistent batches of a periodic search run a whole refresh period
+    // (the host has nothing to check in between).
+    int nb = (persist && h->opt.k_refresh > 0) ? pngf::kPersistBatch : pngf::kMixedBatch;
     if (h->opt.k_refresh > 0) nb = int(std::min<int64_t>(nb, std::max<int64_t>(1, h->opt.k_refresh - since)));
     if (h->opt.k_fold > 0) nb = int(std::min<int64_t>(nb, std::max<int64_t>(1, h->opt.k_fold - kpan)));
     nb += nb & 1;
     // read the design with the batch when it ends at a periodic refresh
     const bool due = h->opt.k_refresh > 0 && since + nb >= h->opt.k_refresh;
-    st = run_steps(h, pngf::launch_mixed_step, t, nb, pinned, due);
+    // a persistent batch that ends at a periodic refresh runs on to the
+    // decision that asks for it (one host round trip less)
+    const int nl = (persist && due) ? nb + 2 : nb;
+    st = run_steps(h, pngf::launch_mixed_step, t, nl, pinned, due, persist);
     if (st) return st;
-    t += nb;
+    t += nl;
     if (pinned->done) break;
     bool refresh = pinned->need_refresh != 0;
     const bool band_hit = pinned->need_refresh == 2;

@@ -96,11 +96,8 @@ __device__ __forceinline__ uint32_t step_key(const ProbDev& P, const StepCtx& c,
   return kNoKey;
 }
 
-// Thread 0: read the state of this step, decide, fill the context.
-__device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool mixed,
-                                   StepCtx& c) {
-  const DbsState* sin = spar ? P.stB : P.st;
-  DbsState* sout = spar ? P.st : P.stB;
+// The state scalars of a step's input state.
+__device__ inline StepScalars load_scalars(const DbsState* sin) {
   StepScalars st;
   st.done = sin->done;
   st.need_refresh = sin->need_refresh;
@@ -117,10 +114,79 @@ __device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool m
   st.attempts = sin->attempts;
   st.f = sin->f;
   st.eta = sin->eta;
-  const int dpar = spar;   // an updating step reads the set of its own parity
-  const uint32_t key = P.keys[kslot];
-  const uint32_t km = P.keys[3 + kslot];
-  int m = -1, slot = -1;
+  return st;
+}
+
+// Loads of values that another workgroup of the same launch wrote (CO:
+// device-coherent atomic loads, which bypass the non-coherent caches).
+template <bool CO>
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t* p) {
+  if constexpr (CO) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool CO>
+__device__ __forceinline__ z64 ld_z64(const z64* p) {
+  if constexpr (CO) {
+    const uint64_t* q = reinterpret_cast<const uint64_t*>(p);
+    const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return z64{__longlong_as_double(static_cast<long long>(a)),
+               __longlong_as_double(static_cast<long long>(b))};
+  } else {
+    return *p;
+  }
+}
+template <bool CO>
+__device__ __forceinline__ z32 ld_z32(const z32* p) {
+  if constexpr (CO) {
+    const uint64_t a = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return z32{__uint_as_float(uint32_t(a)), __uint_as_float(uint32_t(a >> 32))};
+  } else {
+    return *p;
+  }
+}
+template <bool CO>
+__device__ __forceinline__ uint8_t ld_u8(const uint8_t* p) {
+  if constexpr (CO) {
+    // the aligned word holding the byte (little endian)
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    const uint32_t w = __hip_atomic_load(reinterpret_cast<const uint32_t*>(a & ~uintptr_t(3)),
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return uint8_t(w >> (8 * (a & 3)));
+  } else {
+    return *p;
+  }
+}
+
+// Stores of values that another workgroup of the same launch reads
+// (device-coherent atomic stores: written through to memory).
+__device__ __forceinline__ void st_z64c(z64* p, z64 v) {
+  uint64_t* q = reinterpret_cast<uint64_t*>(p);
+  __hip_atomic_store(q, static_cast<uint64_t>(__double_as_longlong(v.re)), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, static_cast<uint64_t>(__double_as_longlong(v.im)), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_z32c(z32* p, z32 v) {
+  const uint64_t a = uint64_t(__float_as_uint(v.re)) | (uint64_t(__float_as_uint(v.im)) << 32);
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), a, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_u8c(uint8_t* p, uint8_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_u32c(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0: decide from the input scalars st and outputs xin, fill the
+// context (c.st and c.x become the next state's).
+// First half of a decision: from the step's keys, the accepted pixel (or -1
+// with done / need_refresh set in st).
+__device__ inline int decide_pick(const ProbDev& P, bool mixed, StepScalars& st, uint32_t key,
+                                  uint32_t km) {
+  int m = -1;
   if (!st.done && !st.need_refresh) {
     if (st.n_acc >= P.max_acc || st.cursor_s >= st.n_sweeps) {
       st.done = 1;
@@ -134,20 +200,30 @@ __device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool m
       m = decode_key(st, key, P);
     }
   }
+  return m;
+}
+
+// Second half: the accepted pixel's coefficients and the new outputs; fills
+// the context (c.st and c.x become the next state's).
+template <bool CO>
+__device__ inline void decide_apply(const ProbDev& P, int dpar, bool mixed, StepScalars st, int m,
+                                    const z64* xin, StepCtx& c) {
+  int slot = -1;
   if (m >= 0) {
     const uint8_t* bin = dpar ? P.bitsB : P.bits;
-    const double delta = bin[m] ? -P.deps : P.deps;
+    const double delta = ld_u8<CO>(bin + m) ? -P.deps : P.deps;
     double fnew = 0.0;
     for (int f = 0; f < P.nfreq; ++f) {
       const double kd = P.k0sq[f] * delta;
-      const z64 tau = (dpar ? P.tauB[f] : P.tau[f])[m];
+      const z64 tau = ld_z64<CO>((dpar ? P.tauB[f] : P.tau[f]) + m);
       const z64 den = {1.0 - kd * tau.re, -kd * tau.im};
       const z64 alpha = zdiv(z64{kd, 0.0}, den);
-      const z64 Em = (dpar ? P.EB[f] : P.E[f])[m], Rpm = (dpar ? P.RpB[f] : P.Rp[f])[m];
+      const z64 Em = ld_z64<CO>((dpar ? P.EB[f] : P.E[f]) + m);
+      const z64 Rpm = ld_z64<CO>((dpar ? P.RpB[f] : P.Rp[f]) + m);
       c.alpha[f] = alpha;
       c.Em[f] = Em;
       c.Rpm[f] = Rpm;
-      const z64 x = zfma(zmul(alpha, Em), Rpm, sin->x[f]);
+      const z64 x = zfma(zmul(alpha, Em), Rpm, xin[f]);
       c.x[f] = x;
       fnew += P.coef[f] * zabs2(x);
     }
@@ -161,7 +237,7 @@ __device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool m
       st.exact = 0;
     }
   } else {
-    for (int f = 0; f < P.nfreq; ++f) c.x[f] = sin->x[f];
+    for (int f = 0; f < P.nfreq; ++f) c.x[f] = xin[f];
   }
   c.m = m;
   c.dpar = dpar;
@@ -172,6 +248,23 @@ __device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool m
   c.f = st.f;
   c.eta = st.eta;
   c.st = st;
+}
+
+// Thread 0: decide from the input scalars st and outputs xin, fill the
+// context.
+__device__ inline void decide_core(const ProbDev& P, int spar, int kslot, bool mixed,
+                                   StepScalars st, const z64* xin, StepCtx& c) {
+  const int m = decide_pick(P, mixed, st, P.keys[kslot], P.keys[3 + kslot]);
+  decide_apply<false>(P, spar, mixed, st, m, xin, c);
+}
+
+// Thread 0: read the state of this step, decide, fill the context.
+__device__ inline void step_decide(const ProbDev& P, int spar, int kslot, bool mixed,
+                                   StepCtx& c) {
+  const DbsState* sin = spar ? P.stB : P.st;
+  z64 xin[kMaxFreq];
+  for (int f = 0; f < P.nfreq; ++f) xin[f] = sin->x[f];
+  decide_core(P, spar, kslot, mixed, load_scalars(sin), xin, c);
 }
 
 // The publishing workgroup (all its threads, after the barrier that follows
@@ -622,6 +715,267 @@ __global__ __launch_bounds__(kSplitThreads) void k_mixed_step_split(ProbDev P, i
   }
 }
 
+// ------------------------------------------------------- persistent mixed search
+// The mixed form's steps of one batch (one frequency) in one launch of
+// resident workgroups, so that the C0^-1 rows stay in registers and a step
+// costs a grid barrier instead of a kernel boundary.  Each workgroup decides every step
+// itself from the same keys with its own copy of the state scalars (so the
+// decisions agree across workgroups), keeps the vectors and panel entries of
+// its eight rows in registers, and publishes for the others only what they
+// read: the accepted pixel's vectors and panel entries, and the keys.
+// Workgroup 0 logs the accepts, clears the key slot two steps ahead and
+// writes the state at the end, where the one-kernel-per-step search leaves
+// it.  Same arithmetic as k_mixed_step_split.
+constexpr int kPersistSlots = 64;     // panel slots held in LDS (>= kcap)
+
+// Grid barrier over words zeroed before the launch (kBarWords, one counter
+// per 128-byte line): workgroup g arrives on the counter of its partition
+// g % 8 (on the usual round-robin dispatch, its XCD), the last of a partition
+// on the global counter, and the last partition raises every partition's
+// release word to the barrier's generation; each workgroup polls its own
+// partition's word, so no address takes more than a partition's atomics or
+// polls.  Every wave waits for its stores and atomics (all cross-workgroup
+// data goes through device-coherent stores and loads) before its workgroup
+// arrives.  The wait is bounded: after spin_limit polls the workgroup sets
+// *flag and reports failure, and every other workgroup then fails at its
+// next barrier.
+constexpr int kBarLine = 32;                       // words per 128-byte line
+constexpr int kBarParts = 8;
+constexpr int kBarWords = kBarLine * (2 * kBarParts + 1);
+
+__device__ inline bool grid_barrier(uint32_t* bar, uint32_t gen, int spin_limit, int32_t* flag,
+                                    int* ok) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t G = gridDim.x, x = blockIdx.x % kBarParts;
+    const uint32_t nparts = G < uint32_t(kBarParts) ? G : uint32_t(kBarParts);
+    const uint32_t nx = (G - x + kBarParts - 1) / kBarParts;
+    uint32_t* sub = bar + kBarLine * x;
+    uint32_t* glob = bar + kBarLine * kBarParts;
+    uint32_t* rel = bar + kBarLine * (kBarParts + 1);
+    if (atomicAdd(sub, 1u) + 1u == gen * nx)
+      if (atomicAdd(glob, 1u) + 1u == gen * nparts)
+        for (uint32_t y = 0; y < nparts; ++y) st_u32c(rel + kBarLine * y, gen);
+    int n = 0;
+    bool good = true;
+    while (__hip_atomic_load(rel + kBarLine * x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           gen) {
+      if (++n > spin_limit) {
+        good = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (!good) atomicOr(flag, 1);
+    *ok = good ? 1 : 0;
+  }
+  __syncthreads();
+  return *ok != 0;
+}
+
+// Four waves of two rows each, one wave per SIMD, so a wave may hold up to
+// 512 registers (its rows, the g_m chunk and the rows' state).  Wave 0 also
+// decides: thread 0 picks the accepted pixel m from the keys, then thread 0
+// fetches m's vectors while lane k < slot fetches the panel entry p_k[m]
+// (the coefficient c_k = alpha_k p_k[m] every worker needs, into LDS).  In
+// each worker, lane l < 2 holds the FP64 state of row 2w + l and updates it.
+constexpr int kPersistThreads = 64 * (kMixRows / 2);
+
+template <int PRE>
+__global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P, int t0,
+                                                                     int nsteps, uint32_t* bar,
+                                                                     int32_t* flag,
+                                                                     int spin_limit) {
+  __shared__ StepCtx c;
+  __shared__ z64 alph_s[kPersistSlots];
+  __shared__ z64 cc_s[kPersistSlots];
+  __shared__ int s_ok;
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ra = g * kMixRows + 2 * w, rb = ra + 1;
+  const bool va = ra < P.nd, vb = rb < P.nd;
+  const int rown = ra + (lane & 1);           // the row of lane 0 / 1
+  const bool vown = lane < 2 && rown < P.nd;
+  // acquire: nothing of the previous launches' writes may be read stale
+  if (tid == 0) __threadfence();
+  __syncthreads();
+  z32 pa[PRE], pb[PRE];
+#pragma unroll
+  for (int q = 0; q < PRE; ++q) {
+    const int j = lane + 64 * q;
+    pa[q] = z32{0.f, 0.f};
+    pb[q] = z32{0.f, 0.f};
+    if (j < P.nd) {
+      if (va) pa[q] = P.C0[0][size_t(ra) * P.ld + j];
+      if (vb) pb[q] = P.C0[0][size_t(rb) * P.ld + j];
+    }
+  }
+  // the own row's vectors as of the batch start
+  const int sp0 = t0 & 1;
+  z64 e{0.0, 0.0}, rp{0.0, 0.0}, ta{0.0, 0.0};
+  uint8_t bit = 0;
+  if (vown) {
+    bit = (sp0 ? P.bitsB : P.bits)[rown];
+    e = (sp0 ? P.EB[0] : P.E[0])[rown];
+    rp = (sp0 ? P.RpB[0] : P.Rp[0])[rown];
+    ta = (sp0 ? P.tauB[0] : P.tau[0])[rown];
+  }
+  if (tid == 0) {
+    const DbsState* sin = sp0 ? P.stB : P.st;
+    c.st = load_scalars(sin);
+    c.x[0] = sin->x[0];
+  }
+  for (int i = tid; i < kPersistSlots; i += blockDim.x) alph_s[i] = P.alph[0][i];
+  __syncthreads();
+  // panel entries p_k[r] of the two rows for the slots filled before the batch
+  const int k_start = c.st.kpanel;
+  z32 ppa{0.f, 0.f}, ppb{0.f, 0.f};
+  if (lane < k_start) {
+    if (va) ppa = P.Pp[0][size_t(lane) * P.ld + ra];
+    if (vb) ppb = P.Pp[0][size_t(lane) * P.ld + rb];
+  }
+  int it = 0;
+  bool alive = true;
+  for (; it < nsteps; ++it) {
+    const int t = t0 + it, dp = t & 1, kslot = t % 3;
+    if (w == 0) {
+      StepScalars st = c.st;
+      int m = -1;
+      if (lane == 0)
+        m = decide_pick(P, true, st, ld_u32<true>(P.keys + kslot),
+                        ld_u32<true>(P.keys + 3 + kslot));
+      m = __shfl(m, 0, 64);
+      if (m >= 0 && lane < st.kpanel)
+        cc_s[lane] = zmul(alph_s[lane], up32(ld_z32<true>(P.Pp[0] + size_t(lane) * P.ld + m)));
+      if (lane == 0) {
+        const z64 xin = c.x[0];
+        decide_apply<true>(P, dp, true, st, m, &xin, c);
+        if (m >= 0) alph_s[c.slot] = c.alpha[0];
+      }
+    }
+    __syncthreads();
+    const int m = c.m;
+    if (g == 0 && tid == 0) {
+      const int clr = (kslot + 2) % 3;
+      st_u32c(P.keys + clr, kNoKey);
+      st_u32c(P.keys + 3 + clr, kNoKey);
+      if (m >= 0) {
+        P.log_pix[c.st.n_acc - 1] = m;
+        P.log_f[c.st.n_acc - 1] = c.st.f;
+        P.pm[c.slot] = m;
+        P.alph[0][c.slot] = c.alpha[0];
+      }
+    }
+    if (m < 0) break;
+    const int slot = c.slot;
+    {
+      const z32* gm = P.G32[0] + size_t(m) * P.ld;
+      z32 gv[PRE];
+#pragma unroll
+      for (int q = 0; q < PRE; ++q) {
+        const int j = lane + 64 * q;
+        gv[q] = j < P.nd ? gm[j] : z32{0.f, 0.f};
+      }
+      // visiting positions of the own row in the new cursor's sweep and the next
+      int pk = -1, nk = 0;
+      if (vown && c.cs < c.ns) {
+        pk = P.rank[size_t(c.cs) * P.nd + rown];
+        if (c.cs + 1 < c.ns) nk = P.rank[size_t(c.cs + 1) * P.nd + rown];
+      }
+      float par = 0.f, pai = 0.f, pbr = 0.f, pbi = 0.f;
+#pragma unroll
+      for (int q = 0; q < PRE; ++q) {
+        par = fmaf(pa[q].re, gv[q].re, fmaf(-pa[q].im, gv[q].im, par));
+        pai = fmaf(pa[q].re, gv[q].im, fmaf(pa[q].im, gv[q].re, pai));
+        pbr = fmaf(pb[q].re, gv[q].re, fmaf(-pb[q].im, gv[q].im, pbr));
+        pbi = fmaf(pb[q].re, gv[q].im, fmaf(pb[q].im, gv[q].re, pbi));
+      }
+      if (lane < slot) {
+        const z64 cc = cc_s[lane];
+        if (va) {
+          par += float(cc.re * ppa.re - cc.im * ppa.im);
+          pai += float(cc.re * ppa.im + cc.im * ppa.re);
+        }
+        if (vb) {
+          pbr += float(cc.re * ppb.re - cc.im * ppb.im);
+          pbi += float(cc.re * ppb.im + cc.im * ppb.re);
+        }
+      }
+      par = wave_sumf(par);
+      pai = wave_sumf(pai);
+      pbr = wave_sumf(pbr);
+      pbi = wave_sumf(pbi);
+      if (lane == slot) {
+        ppa = z32{par, pai};
+        ppb = z32{pbr, pbi};
+      }
+      if (vown) {
+        const int r = rown;
+        const z32 p32 = (lane & 1) ? z32{pbr, pbi} : z32{par, pai};
+        st_z32c(P.Pp[0] + size_t(slot) * P.ld + r, p32);
+        const z64 p = up32(p32);
+        const z64 ap = zmul(c.alpha[0], p);
+        e = zadd(e, zmul(ap, c.Em[0]));
+        rp = zadd(rp, zmul(ap, c.Rpm[0]));
+        ta = zadd(ta, zmul(ap, p));
+        bit = bit ^ (r == m ? 1 : 0);
+        st_z64c((dp ? P.E[0] : P.EB[0]) + r, e);
+        st_z64c((dp ? P.Rp[0] : P.RpB[0]) + r, rp);
+        st_z64c((dp ? P.tau[0] : P.tauB[0]) + r, ta);
+        double df = 0.0, bnd = 0.0;
+        score_terms(P, c, 0, ta, e, rp, bit ? -P.deps : P.deps, df, bnd);
+        st_u8c((dp ? P.bits : P.bitsB) + r, bit);
+        P.df32[r] = df;
+        P.dfb[r] = bnd;
+        const double margin = df - c.eta * c.f;
+        const double band = P.band * bnd;
+        if (margin >= -band && c.cs < c.ns) {
+          uint32_t k = kNoKey;
+          if (pk >= c.cp) k = pack_key(pk, r);
+          else if (c.cs + 1 < c.ns) k = pack_key(P.nd + nk, r);
+          if (k != kNoKey) atomicMin(&P.keys[(margin > band ? 0 : 3) + (kslot + 1) % 3], k);
+        }
+      }
+    }
+    if (!grid_barrier(bar, uint32_t(it + 1), spin_limit, flag, &s_ok)) {
+      alive = false;
+      break;
+    }
+  }
+  if (g == 0 && tid == 0 && alive) {
+    // the state where the last of nsteps one-step launches writes it
+    const DbsState* sin = sp0 ? P.stB : P.st;
+    DbsState* sout = ((t0 + nsteps - 1) & 1) ? P.st : P.stB;
+    if (sout != sin) {
+      const uint64_t* src = reinterpret_cast<const uint64_t*>(sin);
+      uint64_t* dst = reinterpret_cast<uint64_t*>(sout);
+      for (int i = 0; i < int(sizeof(DbsState) / 8); ++i) dst[i] = src[i];
+    }
+    const StepScalars& st = c.st;
+    sout->done = st.done;
+    sout->need_refresh = st.need_refresh;
+    sout->cursor_s = st.cursor_s;
+    sout->cursor_pos = st.cursor_pos;
+    sout->n_acc = st.n_acc;
+    sout->sweeps = st.sweeps;
+    sout->converged = st.converged;
+    sout->n_since = st.n_since;
+    sout->kpanel = st.kpanel;
+    sout->exact = st.exact;
+    sout->flips = st.flips;
+    sout->attempts = st.attempts;
+    sout->f = st.f;
+    sout->m = c.m;
+    sout->kslot = c.slot;
+    sout->x[0] = c.x[0];
+  }
+  // release: every write of this launch reaches memory before it ends
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) __threadfence();
+}
+
 // Several-frequency mixed step for rows of at most 64 PRE columns: one
 // workgroup per row pair, wave 0 decides, worker wave 1 + f handles frequency
 // f of both rows (its C0^-1 rows of that frequency are loaded whole during the
@@ -1016,6 +1370,49 @@ hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s)
   else
     hipLaunchKernelGGL(k_mixed_step, grid, dim3(256), 0, s, P, sp, ks);
   return hipGetLastError();
+}
+
+// The batch [t0, t0 + nsteps) of the mixed search in one launch (one
+// frequency, N_d <= 2048, kcap <= kPersistSlots) whose workgroups must all be
+// resident at once: hipErrorNotSupported when the form does not apply or the
+// grid exceeds one wave of workgroups on this device (the grid barriers would
+// then wait on workgroups not yet started; their waits are bounded in any
+// case, for devices shared with other work).  bar (kBarWords words) and flag
+// are zeroed here.
+template <int PRE>
+hipError_t launch_persist_pre(const ProbDev& P, int t0, int nsteps, uint32_t* bar, int32_t* flag,
+                              int spin_limit, hipStream_t s) {
+  static int cap[64] = {0};       // resident workgroups per device (0: not known yet)
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorNotSupported;
+  if (cap[dev] == 0) {
+    int per_cu = 0, ncu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mixed_persist<PRE>,
+                                                     kPersistThreads, 0);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    cap[dev] = per_cu * ncu > 0 ? per_cu * ncu : -1;
+  }
+  const int grid = (P.nd + kMixRows - 1) / kMixRows;
+  if (grid > cap[dev]) return hipErrorNotSupported;
+  e = hipMemsetAsync(bar, 0, kBarWords * sizeof(uint32_t), s);
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(flag, 0, sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mixed_persist<PRE>, dim3(grid), dim3(kPersistThreads), 0, s, P, t0, nsteps,
+                     bar, flag, spin_limit);
+  return hipGetLastError();
+}
+
+hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint32_t* bar,
+                                int32_t* flag, int spin_limit, hipStream_t s) {
+  if (P.nfreq != 1 || P.nd > 64 * 32 || P.kcap > kPersistSlots) return hipErrorNotSupported;
+  if (P.nd <= 64 * 8) return launch_persist_pre<8>(P, t0, nsteps, bar, flag, spin_limit, s);
+  if (P.nd <= 64 * 16) return launch_persist_pre<16>(P, t0, nsteps, bar, flag, spin_limit, s);
+  return launch_persist_pre<32>(P, t0, nsteps, bar, flag, spin_limit, s);
 }
 
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,

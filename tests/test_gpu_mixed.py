@@ -91,3 +91,30 @@ def test_mixed_then_plain_calls():
     fo = oracle.score_all(p, bits, cands)
     assert rel(fs, fo) < 1e-10
     h.close()
+
+
+@pytest.mark.parametrize("wl,k_refresh,k_fold", [("config1", 32, 0), ("config1", 0, 8),
+                                                   ("config0", 32, 0), ("metal", 32, 0)])
+def test_persistent_batches_equal_step_launches(wl, k_refresh, k_fold):
+    """One cooperative launch per batch (rows of C0^-1 held in registers,
+    grid barriers between steps) against one kernel per step, on one handle
+    (the host precompute sums in a thread-dependent order, so two handles
+    differ at 1e-17): the same arithmetic, so bit-identical searches, and a
+    second persistent search identical to the first."""
+    p = getattr(workloads, wl)()
+    say(f"{wl} mixed persistent vs per-step launches, k_refresh={k_refresh} k_fold={k_fold}")
+    h = P.Handle(p)
+    out = []
+    for step_launches in (False, True, False):
+        h.bind(P.default_options(precision=P.PNGF_MIXED, max_accepts=8192, max_sweeps=8,
+                                 k_refresh=k_refresh, k_fold=k_fold,
+                                 step_launches=step_launches))
+        h.set_design(p.init_bits)
+        out.append(h.dbs_run(p.perms))
+    for r in out[1:]:
+        assert r["accepted"].tolist() == out[0]["accepted"].tolist()
+        assert r["attempts"] == out[0]["attempts"]
+        assert r["n_refresh"] == out[0]["n_refresh"]
+        assert r["f_trace"].tolist() == out[0]["f_trace"].tolist()
+        assert r["f_final"] == out[0]["f_final"]
+    h.close()
