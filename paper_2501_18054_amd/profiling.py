@@ -71,15 +71,26 @@ def summarize(a):
     kib = COPY_BYTES / 1024.0
     f_fetch = kib / statistics.median(cf)
     f_write = kib / statistics.median(cw)
-    # launches that did work (the others found the search paused or finished)
-    thr = 0.05 * max(bf)
-    bf_w = [v for v in bf if v > thr]
-    fetch = statistics.mean(bf_w) * 1024.0 * f_fetch
-    write = statistics.median(bw) * 1024.0 * f_write
+    if a.units:
+        # a launch covers a variable number of units (a batch of steps): the
+        # run's total over its number of units
+        bf_w = bf
+        fetch = sum(bf) * 1024.0 * f_fetch / a.units
+        write = sum(bw) * 1024.0 * f_write / a.units
+    else:
+        # launches that did work (the others found the search paused or finished)
+        thr = 0.05 * max(bf)
+        bf_w = [v for v in bf if v > thr]
+        fetch = statistics.mean(bf_w) * 1024.0 * f_fetch
+        write = statistics.median(bw) * 1024.0 * f_write
+    per = a.unit_name if a.units else "launch"
     with open(a.source, "rb") as fh:
         digest = hashlib.sha256(fh.read()).hexdigest()
-    rec = {"kernel": a.kernel, "workload": a.workload, "fetch_bytes_per_launch": fetch,
-           "write_bytes_per_launch": write, "algorithmic_bytes_per_launch": a.alg_bytes,
+    rec = {"kernel": a.kernel, "workload": a.workload, "per": per, "units": a.units or None,
+           "fetch_bytes_per_launch": fetch if not a.units else None,
+           "write_bytes_per_launch": write if not a.units else None,
+           "fetch_bytes": fetch, "write_bytes": write, "algorithmic_bytes": a.alg_bytes,
+           "algorithmic_bytes_per_launch": a.alg_bytes,
            "copy_scale_fetch": f_fetch, "copy_scale_write": f_write,
            "dispatches_fetch": len(bf_w), "dispatches_write": len(bw),
            "source": os.path.relpath(a.source, ROOT), "source_sha256": digest}
@@ -95,9 +106,11 @@ def summarize(a):
         fh.write(f"| copy calibration: FETCH_SIZE scale | {f_fetch:.4f} |\n")
         fh.write(f"| copy calibration: WRITE_SIZE scale | {f_write:.4f} |\n")
         fh.write(f"| working dispatches counted | {len(bf_w)} (fetch), {len(bw)} (write) |\n")
-        fh.write(f"| fetched bytes per launch | {fetch / 1e6:.2f} MB |\n")
-        fh.write(f"| written bytes per launch | {write / 1e6:.2f} MB |\n")
-        fh.write(f"| algorithmic bytes per launch | {a.alg_bytes / 1e6:.2f} MB |\n")
+        if a.units:
+            fh.write(f"| units ({per}) in the counted run | {a.units} |\n")
+        fh.write(f"| fetched bytes per {per} | {fetch / 1e6:.3f} MB |\n")
+        fh.write(f"| written bytes per {per} | {write / 1e6:.3f} MB |\n")
+        fh.write(f"| algorithmic bytes per {per} | {a.alg_bytes / 1e6:.2f} MB |\n")
         fh.write(f"| traffic / algorithmic | {(fetch + write) / a.alg_bytes:.3f} |\n")
     print(json.dumps(rec, indent=1))
 
@@ -115,6 +128,9 @@ def main():
     s.add_argument("--source", required=True)
     s.add_argument("--out", required=True)
     s.add_argument("--commands", nargs="*", default=[])
+    s.add_argument("--units", type=int, default=0,
+                   help="divide the run's totals by this many units of work (0: per launch)")
+    s.add_argument("--unit-name", default="unit")
     a = ap.parse_args()
     if a.cmd == "copy":
         copy()
