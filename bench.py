@@ -374,11 +374,17 @@ def main():
                      ("mixed", dict(precision=P.PNGF_MIXED, k_refresh=32)),
                      ("mixed_drift", dict(precision=P.PNGF_MIXED, k_refresh=0)),
                      ("rform", dict(precision=P.PNGF_RFORM))):
-        opts = P.default_options(max_accepts=8192, max_sweeps=8, timing=True, **kw)
+        # timed runs: HIP events around the step launches only (the value and
+        # the roofline); then one run with events around every kernel class
+        # for the per-class table (its events cost time on every launch)
+        opts = P.default_options(max_accepts=8192, max_sweeps=8, timing_steps=True, **kw)
         res, dt, kt = run_form(h, prob, opts, a.steps, a.warmup, name)
+        opts_d = P.default_options(max_accepts=8192, max_sweeps=8, timing=True, **kw)
+        _, _, kt_d = run_form(h, prob, opts_d, 1, 0, name + " (events on every class)")
+        kt_d["accept"] = kt["accept"]
         s = summarize(res, dt, a.steps)
         form = "mixed" if name.startswith("mixed") else name
-        s["kernels"] = kernel_table(kt, nd, ns, form, s["accepts"])
+        s["kernels"] = kernel_table(kt_d, nd, ns, form, s["accepts"])
         seqs[name] = res[-1]["accepted"]
         forms[name] = s
     forms["tiles"] = tile_form(P, h, a.steps, a.warmup)

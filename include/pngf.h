@@ -101,6 +101,10 @@ enum { PNGF_FP64_PLAIN = 0, PNGF_MIXED = 1, PNGF_RFORM = 2 };
  * cannot all run, the search fails with PNGF_ENUMERIC after about a second
  * instead of waiting for ever. */
 #define PNGF_FLAG_STEP_LAUNCHES 2ull
+/* pngf_options.flags: like PNGF_FLAG_TIMING, but only the launches of search
+ * steps (kernel class "accept") are timed, which keeps the events' own cost
+ * off every other launch. */
+#define PNGF_FLAG_TIMING_STEPS 4ull
 
 typedef struct pngf_handle pngf_handle;
 

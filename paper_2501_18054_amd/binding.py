@@ -19,6 +19,7 @@ PNGF_MIXED = 1
 PNGF_RFORM = 2
 PNGF_FLAG_TIMING = 1
 PNGF_FLAG_STEP_LAUNCHES = 2
+PNGF_FLAG_TIMING_STEPS = 4
 PNGF_PIXEL_DIELECTRIC = 0
 PNGF_PIXEL_PEC = 1
 
@@ -151,13 +152,16 @@ def _cplx(a):
 
 def default_options(precision=PNGF_FP64_PLAIN, max_accepts=1 << 16, max_sweeps=32,
                     eta=1e-9, k_refresh=None, k_fold=0, guard=0.0, timing=False, max_tile=0,
-                    step_launches=False):
+                    step_launches=False, timing_steps=False):
     """Options of pngf_bind; k_refresh defaults to 32 for the mixed form and
     to 0 (no re-anchoring) for the others.  step_launches: one kernel launch
-    per step of the mixed search instead of one cooperative launch per batch."""
+    per step of the mixed search instead of one launch per batch.  timing:
+    events around every kernel class; timing_steps: around the step
+    launches only."""
     if k_refresh is None:
         k_refresh = 32 if precision == PNGF_MIXED else 0
-    flags = (PNGF_FLAG_TIMING if timing else 0) | (PNGF_FLAG_STEP_LAUNCHES if step_launches else 0)
+    flags = ((PNGF_FLAG_TIMING if timing else 0) | (PNGF_FLAG_STEP_LAUNCHES if step_launches else 0)
+             | (PNGF_FLAG_TIMING_STEPS if timing_steps else 0))
     return Options(precision, k_refresh, k_fold, max_accepts, max_sweeps, max_tile, eta, guard,
                    flags)
 

@@ -20,7 +20,7 @@ hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int
                              uint32_t* keyp, hipStream_t s);
 hipError_t launch_plain_step(const ProbDev& P, int npl, int step, hipStream_t s);
 hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s);
-hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint32_t* bar,
+hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint64_t* bar,
                                 int32_t* flag, int spin_limit, hipStream_t s);
 hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
@@ -73,8 +73,9 @@ constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
 constexpr int kPersistBatch = 32;  // steps of one persistent launch (periodic refresh)
 constexpr int kPersistSpin = 1 << 20;   // polls of a persistent-search grid barrier
 constexpr int kPersistSlotsHost = 64;   // panel slots the persistent search holds in LDS
-constexpr int kPersistBarWords = 32 * 17;   // grid-barrier words of the persistent search
+constexpr int kPersistBarWords = 2 * 16 * 18;   // grid-barrier words (as int32) of the persistent search
 constexpr size_t kPersistBarBytes = (kPersistBarWords + 32) * sizeof(int32_t);
+constexpr size_t kPinBytes = 16384;          // pinned scratch of small transfers
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
 constexpr int kTilePartPerPixel = 512;   // tile-score partial blocks (complex) per pixel
@@ -145,6 +146,8 @@ struct pngf_handle {
   // block-Woodbury update copies from (kept until its wait)
   bool bits_fresh = false;
   uint8_t* bits_pin = nullptr;     // pinned [2][n_d]: the A and B design buffers
+  char* pin = nullptr;             // pinned scratch of small transfers (kPinBytes)
+  hipEvent_t ev_pin = nullptr;     // recorded after the last upload from `pin`
   std::vector<int32_t> w_fl;
   std::vector<double> w_sc;
   bool wood_pending = false;       // a Woodbury status not yet read
@@ -339,7 +342,8 @@ struct Timer {
     return e;
   }
   Timer(pngf_handle* hh, int k) : h(hh), kid(k) {
-    if (h->opt.flags & PNGF_FLAG_TIMING) {
+    if ((h->opt.flags & PNGF_FLAG_TIMING) ||
+        ((h->opt.flags & PNGF_FLAG_TIMING_STEPS) && kid == KID_ACCEPT)) {
       a = take(h);
       b = take(h);
       hipEventRecord(a, h->stream);
@@ -452,7 +456,7 @@ int device_reinvert(pngf_handle* h) {
   int32_t st_host = 0;
   HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  if (h->opt.flags & (PNGF_FLAG_TIMING | PNGF_FLAG_TIMING_STEPS)) collect_times(h);
   if (st_host) return fail(h, PNGF_ESINGULAR, "zero pivot while inverting the PNGF system matrix");
   h->bits_ref = h->bits;
   h->cinv_stale = false;
@@ -481,10 +485,18 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
     for (int c = 0; c < k; ++c)
       sc[size_t(f) * k + c] = P.k0sq[f] * (cur[fl[c]] ? P.deps : -P.deps);
   HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
-  HIPCHK(h, hipMemcpyAsync(dF, h->w_fl.data(), k * sizeof(int32_t), hipMemcpyHostToDevice,
-                           h->stream));
-  HIPCHK(h, hipMemcpyAsync(dS, sc.data(), size_t(F) * k * sizeof(double), hipMemcpyHostToDevice,
-                           h->stream));
+  {
+    // through the pinned scratch, once its previous uploads are done
+    HIPCHK(h, hipEventSynchronize(h->ev_pin));
+    int32_t* pf = reinterpret_cast<int32_t*>(h->pin + 256);
+    double* ps = reinterpret_cast<double*>(h->pin + 256 + 64 * sizeof(int32_t));
+    std::copy(h->w_fl.begin(), h->w_fl.end(), pf);
+    std::copy(sc.begin(), sc.end(), ps);
+    HIPCHK(h, hipMemcpyAsync(dF, pf, k * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(dS, ps, size_t(F) * k * sizeof(double), hipMemcpyHostToDevice,
+                             h->stream));
+    HIPCHK(h, hipEventRecord(h->ev_pin, h->stream));
+  }
   const z64 one{1.0, 0.0}, zero{0.0, 0.0};
   {
     Timer t(h, KID_WOOD);
@@ -583,6 +595,13 @@ int write_state(pngf_handle* h, const pngf::DbsState* st) {
   return PNGF_OK;
 }
 
+// Stream-ordered write of a state held in pinned memory (no wait: the host
+// does not touch it before its next stream-ordered read).
+int write_state_pinned(pngf_handle* h, const pngf::DbsState* st) {
+  HIPCHK(h, hipMemcpyAsync(h->P.st, st, sizeof(*st), hipMemcpyHostToDevice, h->stream));
+  return PNGF_OK;
+}
+
 
 // Reset the rotating key slots (and, if asked, the panel bookkeeping of the
 // state) and score every candidate of the current (normalized) state into
@@ -609,7 +628,7 @@ int normalize(pngf_handle* h, pngf::DbsState* st) {
   }
   std::swap(P.bits, P.bitsB);
   st->flips = 0;
-  return write_state(h, st);
+  return write_state_pinned(h, st);
 }
 
 // Run `n` (even) steps starting at step index t0, then read the state.
@@ -623,7 +642,7 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
   int32_t* pbar = at<int32_t>(h, h->lay.off_pbar);
   if (persist) {
     const hipError_t e = pngf::launch_mixed_persist(h->P, int(t0), n,
-                                                    reinterpret_cast<uint32_t*>(pbar),
+                                                    reinterpret_cast<uint64_t*>(pbar),
                                                     pbar + pngf::kPersistBarWords, pngf::kPersistSpin,
                                                     h->stream);
     if (e != hipSuccess) {
@@ -638,9 +657,10 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
   t.end(n);
   h->bits_fresh = false;
   const int nd = h->pc.n_d;
-  int32_t tmo = 0;
+  int32_t* tmo = reinterpret_cast<int32_t*>(h->pin);
+  *tmo = 0;
   if (persist)
-    HIPCHK(h, hipMemcpyAsync(&tmo, pbar + pngf::kPersistBarWords, sizeof(int32_t),
+    HIPCHK(h, hipMemcpyAsync(tmo, pbar + pngf::kPersistBarWords, sizeof(int32_t),
                              hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
                            h->stream));
@@ -653,7 +673,12 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
     HIPCHK(h, hipMemcpyAsync(h->bits_pin + nd, h->P.bitsB, nd, hipMemcpyDeviceToHost, h->stream));
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (tmo) return fail(h, PNGF_ENUMERIC, "a grid barrier of the persistent search timed out");
+  if (*tmo) {
+    // the barrier words are left inconsistent: clear them for the next search
+    HIPCHK(h, hipMemsetAsync(pbar, 0, pngf::kPersistBarBytes, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return fail(h, PNGF_ENUMERIC, "a grid barrier of the persistent search timed out");
+  }
   if (want_bits) {
     // the design of the last step (in the B set after an odd number of updates)
     const uint8_t* cur = h->bits_pin + ((pinned->flips & 1) ? nd : 0);
@@ -709,8 +734,11 @@ int mixed_refresh(pngf_handle* h, bool measure) {
       HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
     st = start_segment(h, true);
     if (st) return st;
-    double meas = 0.0;
-    int32_t wst = 0;
+    // both read into the pinned scratch, with one wait
+    double& meas = *reinterpret_cast<double*>(h->pin + 8);
+    int32_t& wst = *reinterpret_cast<int32_t*>(h->pin + 16);
+    meas = 0.0;
+    wst = 0;
     if (measure) {
       double* out = at<double>(h, h->lay.off_bandout);
       HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd, out, h->stream));
@@ -1031,7 +1059,7 @@ int dbs_epilogue(pngf_handle* h, const pngf::DbsState& fin, double f0, int64_t n
     HIPCHK(h, hipMemcpyAsync(f_trace, h->P.log_f, na * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipMemcpyAsync(h->bits.data(), h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  if (h->opt.flags & (PNGF_FLAG_TIMING | PNGF_FLAG_TIMING_STEPS)) collect_times(h);
   if (!std::isfinite(fin.f)) return fail(h, PNGF_ENUMERIC, "objective is not finite");
   if (res) {
     res->n_accepted = na;
@@ -1238,6 +1266,11 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   }
   if (o->precision == PNGF_MIXED)
     for (int f = 0; f < F; ++f) HIPCHK(h, pngf::launch_to_c64(P.G[f], P.G32[f], nd, h->ld, h->stream));
+  // the persistent search's barrier words start at generation 0
+  HIPCHK(h, hipMemsetAsync(at<int32_t>(h, L.off_pbar), 0, pngf::kPersistBarBytes, h->stream));
+  if (!h->pin) HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->pin), pngf::kPinBytes));
+  if (!h->ev_pin) HIPCHK(h, hipEventCreateWithFlags(&h->ev_pin, hipEventDisableTiming));
+  HIPCHK(h, hipEventRecord(h->ev_pin, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->bound = true;
   h->have_design = false;
@@ -1517,7 +1550,7 @@ int pngf_tile_dbs_run(pngf_handle* h, const int32_t* tiles, int32_t n_tiles, int
     }
     if (!any) converged = true;
   }
-  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  if (h->opt.flags & (PNGF_FLAG_TIMING | PNGF_FLAG_TIMING_STEPS)) collect_times(h);
   const int na = int(acc_log.size());
   if (accepted && na) std::memcpy(accepted, acc_log.data(), na * sizeof(int32_t));
   if (f_trace && na) std::memcpy(f_trace, f_log.data(), na * sizeof(double));
@@ -1550,6 +1583,8 @@ int pngf_destroy(pngf_handle* h) {
   for (hipEvent_t e : h->ev_free) hipEventDestroy(e);
   release_streams(h);
   if (h->bits_pin) (void)hipHostFree(h->bits_pin);
+  if (h->pin) (void)hipHostFree(h->pin);
+  if (h->ev_pin) (void)hipEventDestroy(h->ev_pin);
   delete h;
   return PNGF_OK;
 }
@@ -1678,7 +1713,7 @@ int pngf_learned_dbs_run(pngf_handle* h, pngf_model* m, int32_t k, int32_t max_a
   pngf::DbsState fin;
   st = read_state(h, &fin);
   if (st) return st;
-  if (h->opt.flags & PNGF_FLAG_TIMING) collect_times(h);
+  if (h->opt.flags & (PNGF_FLAG_TIMING | PNGF_FLAG_TIMING_STEPS)) collect_times(h);
   if (!std::isfinite(fin.f)) return fail(h, PNGF_ENUMERIC, "objective is not finite");
   if (res) {
     res->n_accepted = n_acc;

@@ -728,35 +728,39 @@ __global__ __launch_bounds__(kSplitThreads) void k_mixed_step_split(ProbDev P, i
 // it.  Same arithmetic as k_mixed_step_split.
 constexpr int kPersistSlots = 64;     // panel slots held in LDS (>= kcap)
 
-// Grid barrier over words zeroed before the launch (kBarWords, one counter
-// per 128-byte line): workgroup g arrives on the counter of its partition
-// g % 8 (on the usual round-robin dispatch, its XCD), the last of a partition
-// on the global counter, and the last partition raises every partition's
-// release word to the barrier's generation; each workgroup polls its own
-// partition's word, so no address takes more than a partition's atomics or
-// polls.  Every wave waits for its stores and atomics (all cross-workgroup
-// data goes through device-coherent stores and loads) before its workgroup
-// arrives.  The wait is bounded: after spin_limit polls the workgroup sets
-// *flag and reports failure, and every other workgroup then fails at its
-// next barrier.
-constexpr int kBarLine = 32;                       // words per 128-byte line
+// Grid barrier over 64-bit words (kBarWords, one per 128-byte line; zeroed
+// when the workspace is bound): workgroup g arrives on the counter of its
+// partition g % 8 (on the usual round-robin dispatch, its XCD), the last of a
+// partition on the global counter, and the last partition raises every
+// partition's release word to the barrier's generation; each workgroup polls
+// its own partition's word, so no address takes more than a partition's
+// atomics or polls.  Generations keep counting across launches: the base is
+// read at a launch's start and advanced by workgroup 0 at its end, so no
+// launch has to clear the words.  Every wave waits for its stores and atomics
+// (all cross-workgroup data goes through device-coherent stores and loads)
+// before its workgroup arrives.  The wait is bounded: after spin_limit polls
+// the workgroup sets *flag and reports failure, and every other workgroup
+// then fails at its next barrier.
+constexpr int kBarLine = 16;                       // 64-bit words per 128-byte line
 constexpr int kBarParts = 8;
-constexpr int kBarWords = kBarLine * (2 * kBarParts + 1);
+constexpr int kBarGen = kBarLine * (2 * kBarParts + 1);   // the generation base
+constexpr int kBarWords = kBarLine * (2 * kBarParts + 2);
 
-__device__ inline bool grid_barrier(uint32_t* bar, uint32_t gen, int spin_limit, int32_t* flag,
+__device__ inline bool grid_barrier(uint64_t* bar, uint64_t gen, int spin_limit, int32_t* flag,
                                     int* ok) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t G = gridDim.x, x = blockIdx.x % kBarParts;
-    const uint32_t nparts = G < uint32_t(kBarParts) ? G : uint32_t(kBarParts);
-    const uint32_t nx = (G - x + kBarParts - 1) / kBarParts;
-    uint32_t* sub = bar + kBarLine * x;
-    uint32_t* glob = bar + kBarLine * kBarParts;
-    uint32_t* rel = bar + kBarLine * (kBarParts + 1);
-    if (atomicAdd(sub, 1u) + 1u == gen * nx)
-      if (atomicAdd(glob, 1u) + 1u == gen * nparts)
-        for (uint32_t y = 0; y < nparts; ++y) st_u32c(rel + kBarLine * y, gen);
+    const uint64_t G = gridDim.x, x = blockIdx.x % kBarParts;
+    const uint64_t nparts = G < uint64_t(kBarParts) ? G : uint64_t(kBarParts);
+    const uint64_t nx = (G - x + kBarParts - 1) / kBarParts;
+    uint64_t* sub = bar + kBarLine * x;
+    uint64_t* glob = bar + kBarLine * kBarParts;
+    uint64_t* rel = bar + kBarLine * (kBarParts + 1);
+    if (atomicAdd(reinterpret_cast<unsigned long long*>(sub), 1ull) + 1ull == gen * nx)
+      if (atomicAdd(reinterpret_cast<unsigned long long*>(glob), 1ull) + 1ull == gen * nparts)
+        for (uint64_t y = 0; y < nparts; ++y)
+          __hip_atomic_store(rel + kBarLine * y, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int n = 0;
     bool good = true;
     while (__hip_atomic_load(rel + kBarLine * x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
@@ -784,13 +788,16 @@ constexpr int kPersistThreads = 64 * (kMixRows / 2);
 
 template <int PRE>
 __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P, int t0,
-                                                                     int nsteps, uint32_t* bar,
+                                                                     int nsteps, uint64_t* bar,
                                                                      int32_t* flag,
                                                                      int spin_limit) {
   __shared__ StepCtx c;
   __shared__ z64 alph_s[kPersistSlots];
   __shared__ z64 cc_s[kPersistSlots];
+  __shared__ StepScalars s_st;
+  __shared__ int s_m;
   __shared__ int s_ok;
+  __shared__ uint64_t s_gen;
   const int g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int ra = g * kMixRows + 2 * w, rb = ra + 1;
@@ -825,6 +832,7 @@ __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P,
     const DbsState* sin = sp0 ? P.stB : P.st;
     c.st = load_scalars(sin);
     c.x[0] = sin->x[0];
+    s_gen = bar[kBarGen];
   }
   for (int i = tid; i < kPersistSlots; i += blockDim.x) alph_s[i] = P.alph[0][i];
   __syncthreads();
@@ -839,57 +847,69 @@ __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P,
   bool alive = true;
   for (; it < nsteps; ++it) {
     const int t = t0 + it, dp = t & 1, kslot = t % 3;
-    if (w == 0) {
+    // pick the accepted pixel first: the g_m loads and products of every
+    // wave then overlap the second half of the decision
+    if (tid == 0) {
       StepScalars st = c.st;
-      int m = -1;
-      if (lane == 0)
-        m = decide_pick(P, true, st, ld_u32<true>(P.keys + kslot),
+      s_m = decide_pick(P, true, st, ld_u32<true>(P.keys + kslot),
                         ld_u32<true>(P.keys + 3 + kslot));
-      m = __shfl(m, 0, 64);
-      if (m >= 0 && lane < st.kpanel)
+      s_st = st;
+    }
+    __syncthreads();
+    const int m = s_m;
+    if (m < 0) {
+      if (tid == 0) {
+        const z64 xin = c.x[0];
+        decide_apply<true>(P, dp, true, s_st, -1, &xin, c);
+        if (g == 0) {
+          const int clr = (kslot + 2) % 3;
+          st_u32c(P.keys + clr, kNoKey);
+          st_u32c(P.keys + 3 + clr, kNoKey);
+        }
+      }
+      break;
+    }
+    const z32* gm = P.G32[0] + size_t(m) * P.ld;
+    z32 gv[PRE];
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+      const int j = lane + 64 * q;
+      gv[q] = j < P.nd ? gm[j] : z32{0.f, 0.f};
+    }
+    if (w == 0) {
+      if (lane < s_st.kpanel)
         cc_s[lane] = zmul(alph_s[lane], up32(ld_z32<true>(P.Pp[0] + size_t(lane) * P.ld + m)));
       if (lane == 0) {
         const z64 xin = c.x[0];
-        decide_apply<true>(P, dp, true, st, m, &xin, c);
-        if (m >= 0) alph_s[c.slot] = c.alpha[0];
+        decide_apply<true>(P, dp, true, s_st, m, &xin, c);
+        alph_s[c.slot] = c.alpha[0];
       }
     }
+    float par = 0.f, pai = 0.f, pbr = 0.f, pbi = 0.f;
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+      par = fmaf(pa[q].re, gv[q].re, fmaf(-pa[q].im, gv[q].im, par));
+      pai = fmaf(pa[q].re, gv[q].im, fmaf(pa[q].im, gv[q].re, pai));
+      pbr = fmaf(pb[q].re, gv[q].re, fmaf(-pb[q].im, gv[q].im, pbr));
+      pbi = fmaf(pb[q].re, gv[q].im, fmaf(pb[q].im, gv[q].re, pbi));
+    }
     __syncthreads();
-    const int m = c.m;
     if (g == 0 && tid == 0) {
       const int clr = (kslot + 2) % 3;
       st_u32c(P.keys + clr, kNoKey);
       st_u32c(P.keys + 3 + clr, kNoKey);
-      if (m >= 0) {
-        P.log_pix[c.st.n_acc - 1] = m;
-        P.log_f[c.st.n_acc - 1] = c.st.f;
-        P.pm[c.slot] = m;
-        P.alph[0][c.slot] = c.alpha[0];
-      }
+      P.log_pix[c.st.n_acc - 1] = m;
+      P.log_f[c.st.n_acc - 1] = c.st.f;
+      P.pm[c.slot] = m;
+      P.alph[0][c.slot] = c.alpha[0];
     }
-    if (m < 0) break;
     const int slot = c.slot;
     {
-      const z32* gm = P.G32[0] + size_t(m) * P.ld;
-      z32 gv[PRE];
-#pragma unroll
-      for (int q = 0; q < PRE; ++q) {
-        const int j = lane + 64 * q;
-        gv[q] = j < P.nd ? gm[j] : z32{0.f, 0.f};
-      }
       // visiting positions of the own row in the new cursor's sweep and the next
       int pk = -1, nk = 0;
       if (vown && c.cs < c.ns) {
         pk = P.rank[size_t(c.cs) * P.nd + rown];
         if (c.cs + 1 < c.ns) nk = P.rank[size_t(c.cs + 1) * P.nd + rown];
-      }
-      float par = 0.f, pai = 0.f, pbr = 0.f, pbi = 0.f;
-#pragma unroll
-      for (int q = 0; q < PRE; ++q) {
-        par = fmaf(pa[q].re, gv[q].re, fmaf(-pa[q].im, gv[q].im, par));
-        pai = fmaf(pa[q].re, gv[q].im, fmaf(pa[q].im, gv[q].re, pai));
-        pbr = fmaf(pb[q].re, gv[q].re, fmaf(-pb[q].im, gv[q].im, pbr));
-        pbi = fmaf(pb[q].re, gv[q].im, fmaf(pb[q].im, gv[q].re, pbi));
       }
       if (lane < slot) {
         const z64 cc = cc_s[lane];
@@ -938,12 +958,14 @@ __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P,
         }
       }
     }
-    if (!grid_barrier(bar, uint32_t(it + 1), spin_limit, flag, &s_ok)) {
+    if (!grid_barrier(bar, s_gen + uint64_t(it + 1), spin_limit, flag, &s_ok)) {
       alive = false;
       break;
     }
   }
   if (g == 0 && tid == 0 && alive) {
+    // every workgroup met the same `it` barriers
+    bar[kBarGen] = s_gen + uint64_t(it);
     // the state where the last of nsteps one-step launches writes it
     const DbsState* sin = sp0 ? P.stB : P.st;
     DbsState* sout = ((t0 + nsteps - 1) & 1) ? P.st : P.stB;
@@ -1377,10 +1399,11 @@ hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s)
 // resident at once: hipErrorNotSupported when the form does not apply or the
 // grid exceeds one wave of workgroups on this device (the grid barriers would
 // then wait on workgroups not yet started; their waits are bounded in any
-// case, for devices shared with other work).  bar (kBarWords words) and flag
-// are zeroed here.
+// case, for devices shared with other work).  bar (kBarWords 64-bit words)
+// and flag are zeroed when the workspace is bound; a launch that timed out
+// leaves them to be cleared by the caller.
 template <int PRE>
-hipError_t launch_persist_pre(const ProbDev& P, int t0, int nsteps, uint32_t* bar, int32_t* flag,
+hipError_t launch_persist_pre(const ProbDev& P, int t0, int nsteps, uint64_t* bar, int32_t* flag,
                               int spin_limit, hipStream_t s) {
   static int cap[64] = {0};       // resident workgroups per device (0: not known yet)
   int dev = 0;
@@ -1398,16 +1421,12 @@ hipError_t launch_persist_pre(const ProbDev& P, int t0, int nsteps, uint32_t* ba
   }
   const int grid = (P.nd + kMixRows - 1) / kMixRows;
   if (grid > cap[dev]) return hipErrorNotSupported;
-  e = hipMemsetAsync(bar, 0, kBarWords * sizeof(uint32_t), s);
-  if (e != hipSuccess) return e;
-  e = hipMemsetAsync(flag, 0, sizeof(int32_t), s);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mixed_persist<PRE>, dim3(grid), dim3(kPersistThreads), 0, s, P, t0, nsteps,
                      bar, flag, spin_limit);
   return hipGetLastError();
 }
 
-hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint32_t* bar,
+hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint64_t* bar,
                                 int32_t* flag, int spin_limit, hipStream_t s) {
   if (P.nfreq != 1 || P.nd > 64 * 32 || P.kcap > kPersistSlots) return hipErrorNotSupported;
   if (P.nd <= 64 * 8) return launch_persist_pre<8>(P, t0, nsteps, bar, flag, spin_limit, s);
