@@ -746,11 +746,22 @@ constexpr int kBarParts = 8;
 constexpr int kBarGen = kBarLine * (2 * kBarParts + 1);   // the generation base
 constexpr int kBarWords = kBarLine * (2 * kBarParts + 2);
 
+// Before it arrives, thread 0 publishes the workgroup's minimum keys
+// (wkey[w] = {sure, band} of wave w) to ksure / kband.
 __device__ inline bool grid_barrier(uint64_t* bar, uint64_t gen, int spin_limit, int32_t* flag,
-                                    int* ok) {
+                                    int* ok, uint32_t* ksure, uint32_t* kband,
+                                    const uint32_t (*wkey)[2]) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    uint32_t a = kNoKey, b = kNoKey;
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) {
+      a = min(a, wkey[w][0]);
+      b = min(b, wkey[w][1]);
+    }
+    if (a != kNoKey) atomicMin(ksure, a);
+    if (b != kNoKey) atomicMin(kband, b);
+    __builtin_amdgcn_s_waitcnt(0);
     const uint64_t G = gridDim.x, x = blockIdx.x % kBarParts;
     const uint64_t nparts = G < uint64_t(kBarParts) ? G : uint64_t(kBarParts);
     const uint64_t nx = (G - x + kBarParts - 1) / kBarParts;
@@ -798,6 +809,7 @@ __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P,
   __shared__ int s_m;
   __shared__ int s_ok;
   __shared__ uint64_t s_gen;
+  __shared__ uint32_t wkey_s[kPersistThreads / 64][2];
   const int g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int ra = g * kMixRows + 2 * w, rb = ra + 1;
@@ -904,6 +916,7 @@ __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P,
       P.alph[0][c.slot] = c.alpha[0];
     }
     const int slot = c.slot;
+    uint32_t ksure = kNoKey, kband = kNoKey;
     {
       // visiting positions of the own row in the new cursor's sweep and the next
       int pk = -1, nk = 0;
@@ -954,11 +967,21 @@ __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P,
           uint32_t k = kNoKey;
           if (pk >= c.cp) k = pack_key(pk, r);
           else if (c.cs + 1 < c.ns) k = pack_key(P.nd + nk, r);
-          if (k != kNoKey) atomicMin(&P.keys[(margin > band ? 0 : 3) + (kslot + 1) % 3], k);
+          if (margin > band) ksure = k;
+          else kband = k;
         }
       }
     }
-    if (!grid_barrier(bar, s_gen + uint64_t(it + 1), spin_limit, flag, &s_ok)) {
+    // the workgroup's minimum keys (sure, band): one atomic each per
+    // workgroup instead of one per row
+    ksure = min(ksure, uint32_t(__shfl_xor(int(ksure), 1, 64)));
+    kband = min(kband, uint32_t(__shfl_xor(int(kband), 1, 64)));
+    if (lane == 0) {
+      wkey_s[w][0] = ksure;
+      wkey_s[w][1] = kband;
+    }
+    if (!grid_barrier(bar, s_gen + uint64_t(it + 1), spin_limit, flag, &s_ok,
+                      P.keys + (kslot + 1) % 3, P.keys + 3 + (kslot + 1) % 3, wkey_s)) {
       alive = false;
       break;
     }
