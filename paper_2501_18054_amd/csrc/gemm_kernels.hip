@@ -185,8 +185,9 @@ __global__ __launch_bounds__(256) void k_wood_scale(z64* P, int ldp, int nd, int
   P[size_t(i) * ldp + c] = zscale(P[size_t(i) * ldp + c], s[c]);
 }
 __global__ __launch_bounds__(256) void k_wood_cap(const z64* P, int ldp, const int32_t* F, int k,
-                                                  z64* Cap) {
+                                                  z64* Cap, int32_t* status) {
   const int e = blockIdx.x * 256 + threadIdx.x;
+  if (status && e == 0) *status = 0;   // before the capacitance inverse reports
   if (e >= k * k) return;
   const int a = e / k, c = e % k;
   const z64 p = P[size_t(F[a]) * ldp + c];
@@ -332,13 +333,15 @@ hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int 
   return hipGetLastError();
 }
 
+// status (nullable) is cleared before the capacitance matrix is formed.
 hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, const double* sc,
-                           z64* Cap, hipStream_t s) {
+                           z64* Cap, int32_t* status, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   const size_t n = size_t(nd) * k;
   hipLaunchKernelGGL(k_wood_scale, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, P, ldp, nd, k,
                      sc);
-  hipLaunchKernelGGL(k_wood_cap, dim3((k * k + 255) / 256), dim3(256), 0, s, P, ldp, F, k, Cap);
+  hipLaunchKernelGGL(k_wood_cap, dim3((k * k + 255) / 256), dim3(256), 0, s, P, ldp, F, k, Cap,
+                     status);
   return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ hipError_t launch_rform_t0_init(const ProbDev& P, int f, hipStream_t s);
 hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int k, int n, z64* dst,
                               int ldd, hipStream_t s);
 hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, const double* sc,
-                           z64* Cap, hipStream_t s);
+                           z64* Cap, int32_t* status, hipStream_t s);
 hipError_t launch_small_inverse(z64* A, int k, int32_t* status, hipStream_t s);
 hipError_t launch_gradient(const ProbDev& P, double* out, hipStream_t s);
 hipError_t launch_tile_score(const ProbDev& P, const int32_t* tiles, int ntiles, int m, int ks,
@@ -66,7 +66,7 @@ hipError_t launch_output(const ProbDev& P, int f, const z64* god, z64 xb, int la
 hipError_t launch_to_c64(const z64* src, z32* dst, int nd, int ld, hipStream_t s);
 hipError_t launch_fold(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_band_measure(const double* df32, const double* bnd32, const double* df64,
-                               int nd, double* out, hipStream_t s);
+                               int nd, double* out, const int32_t* status, hipStream_t s);
 constexpr int kGjNbHost = 16;
 constexpr int kPanelCap = 64;      // deferred Sherman-Morrison terms (mixed)
 constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
@@ -76,6 +76,8 @@ constexpr int kPersistSlotsHost = 64;   // panel slots the persistent search hol
 constexpr int kPersistBarWords = 2 * 16 * 18;   // grid-barrier words (as int32) of the persistent search
 constexpr size_t kPersistBarBytes = (kPersistBarWords + 32) * sizeof(int32_t);
 constexpr size_t kPinBytes = 16384;          // pinned scratch of small transfers
+constexpr size_t kPinUpload = 256;           // offset of the Woodbury upload in it
+constexpr size_t kPinStage = kPinBytes;      // then the batch-end read (state .. bits)
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
 constexpr int kTilePartPerPixel = 512;   // tile-score partial blocks (complex) per pixel
@@ -115,7 +117,7 @@ struct Layout {
   size_t off_S[pngf::kMaxFreq], off_B1[pngf::kMaxFreq], off_Pb[pngf::kMaxFreq],
       off_Pn[pngf::kMaxFreq], off_ts[pngf::kMaxFreq], off_B11[pngf::kMaxFreq],
       off_piv[pngf::kMaxFreq], off_invp[pngf::kMaxFreq], off_used[pngf::kMaxFreq];
-  size_t off_status, off_pbar, off_u[pngf::kMaxFreq], off_r[pngf::kMaxFreq];
+  size_t off_status, off_pbar, off_flag, off_u[pngf::kMaxFreq], off_r[pngf::kMaxFreq];
   size_t off_wP[pngf::kMaxFreq], off_wQ[pngf::kMaxFreq], off_wW[pngf::kMaxFreq],
       off_wCap[pngf::kMaxFreq], off_wWork[pngf::kMaxFreq];
   size_t off_wF, off_wS, off_tiles, off_tpart;
@@ -145,8 +147,8 @@ struct pngf_handle {
   // round trip before the next FP64 refresh), and the host arrays a deferred
   // block-Woodbury update copies from (kept until its wait)
   bool bits_fresh = false;
-  uint8_t* bits_pin = nullptr;     // pinned [2][n_d]: the A and B design buffers
-  char* pin = nullptr;             // pinned scratch of small transfers (kPinBytes)
+  char* pin = nullptr;             // pinned scratch of small transfers, then a staging area
+  size_t pin_bytes = 0;
   hipEvent_t ev_pin = nullptr;     // recorded after the last upload from `pin`
   std::vector<int32_t> w_fl;
   std::vector<double> w_sc;
@@ -206,7 +208,6 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_RpB[f] = take(vec);
     L.off_tauB[f] = take(vec);
   }
-  L.off_bitsB = take(size_t(nd));
   L.off_stateB = take(sizeof(pngf::DbsState));
   L.off_keys = take(6 * sizeof(uint32_t));
   L.off_pm = take(size_t(pngf::kPanelCap) * sizeof(int32_t));
@@ -224,7 +225,7 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     }
     L.off_df32 = take(size_t(nd) * sizeof(double));
     L.off_dfb = take(size_t(nd) * sizeof(double));
-    L.off_bandout = take(sizeof(double));
+    L.off_bandout = take(2 * sizeof(double));
   }
   if (o->precision == PNGF_RFORM) {
     const size_t kr = size_t(pngf::kRPanel);
@@ -276,14 +277,17 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_r[f] = take(vec);
   }
   const int ms = std::max(1, o->max_sweeps), ma = std::max(1, o->max_accepts);
-  L.off_bits = take(size_t(nd));
   L.off_perm = take(size_t(ms) * nd * sizeof(int32_t));
   L.off_rank = take(size_t(ms) * nd * sizeof(int32_t));
   L.off_cand = take(size_t(nd) * sizeof(int32_t));
   L.off_df = take(size_t(nd) * sizeof(double));
   L.off_logp = take(size_t(ma) * sizeof(int32_t));
   L.off_logf = take(size_t(ma) * sizeof(double));
+  // adjacent, so that one copy brings them to the host after a batch of steps
   L.off_state = take(sizeof(pngf::DbsState));
+  L.off_flag = take(sizeof(int32_t));
+  L.off_bits = take(size_t(nd));
+  L.off_bitsB = take(size_t(nd));
   L.total = off;
   return L;
 }
@@ -484,16 +488,18 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
   for (int f = 0; f < F; ++f)
     for (int c = 0; c < k; ++c)
       sc[size_t(f) * k + c] = P.k0sq[f] * (cur[fl[c]] ? P.deps : -P.deps);
-  HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
+  // one frequency: the capacitance kernel clears the status in stream order
+  if (F > 1) HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
   {
-    // through the pinned scratch, once its previous uploads are done
+    // the flips and scales in one upload through the pinned scratch (laid
+    // out like dF .. dS in the workspace), once its previous upload is done
+    const size_t gap = L.off_wS - L.off_wF;
     HIPCHK(h, hipEventSynchronize(h->ev_pin));
-    int32_t* pf = reinterpret_cast<int32_t*>(h->pin + 256);
-    double* ps = reinterpret_cast<double*>(h->pin + 256 + 64 * sizeof(int32_t));
+    int32_t* pf = reinterpret_cast<int32_t*>(h->pin + pngf::kPinUpload);
+    double* ps = reinterpret_cast<double*>(h->pin + pngf::kPinUpload + gap);
     std::copy(h->w_fl.begin(), h->w_fl.end(), pf);
     std::copy(sc.begin(), sc.end(), ps);
-    HIPCHK(h, hipMemcpyAsync(dF, pf, k * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(dS, ps, size_t(F) * k * sizeof(double), hipMemcpyHostToDevice,
+    HIPCHK(h, hipMemcpyAsync(dF, pf, gap + size_t(F) * k * sizeof(double), hipMemcpyHostToDevice,
                              h->stream));
     HIPCHK(h, hipEventRecord(h->ev_pin, h->stream));
   }
@@ -511,7 +517,8 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
       // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T)
       HIPCHK(h, pngf::launch_zgemm(nd, k, nd, P.Cinv[f], ld, nullptr, P.G[f], ld, true, dF, wP, k,
                                    one, zero, pngf::kWoodSplits, at<z64>(h, L.off_wWork[f]), sf));
-      HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS + size_t(f) * k, cap, sf));
+      HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS + size_t(f) * k, cap,
+                                      F == 1 ? status : nullptr, sf));
       HIPCHK(h, pngf::launch_small_inverse(cap, k, status, sf));
       // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
       HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, sf));
@@ -643,8 +650,8 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
   if (persist) {
     const hipError_t e = pngf::launch_mixed_persist(h->P, int(t0), n,
                                                     reinterpret_cast<uint64_t*>(pbar),
-                                                    pbar + pngf::kPersistBarWords, pngf::kPersistSpin,
-                                                    h->stream);
+                                                    at<int32_t>(h, h->lay.off_flag),
+                                                    pngf::kPersistSpin, h->stream);
     if (e != hipSuccess) {
       // the grid cannot be co-resident here: one kernel per step from now on
       (void)hipGetLastError();
@@ -657,31 +664,32 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
   t.end(n);
   h->bits_fresh = false;
   const int nd = h->pc.n_d;
-  int32_t* tmo = reinterpret_cast<int32_t*>(h->pin);
-  *tmo = 0;
-  if (persist)
-    HIPCHK(h, hipMemcpyAsync(tmo, pbar + pngf::kPersistBarWords, sizeof(int32_t),
-                             hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
-                           h->stream));
-  if (want_bits) {
-    // both design buffers, into pinned memory, with the same wait
-    if (!h->bits_pin) {
-      HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->bits_pin), 2 * size_t(nd)));
-    }
-    HIPCHK(h, hipMemcpyAsync(h->bits_pin, h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->bits_pin + nd, h->P.bitsB, nd, hipMemcpyDeviceToHost, h->stream));
-  }
+  // state, time-out flag and (when asked) both design buffers in one copy:
+  // they are adjacent in the workspace
+  const Layout& Y = h->lay;
+  char* stg = h->pin + pngf::kPinStage;
+  const size_t span = (want_bits || persist) ? (want_bits ? Y.off_bitsB + nd : Y.off_flag + 4) -
+                                                   Y.off_state
+                                             : sizeof(pngf::DbsState);
+  HIPCHK(h, hipMemcpyAsync(stg, h->ws + Y.off_state, span, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (*tmo) {
+  std::memcpy(pinned, stg, sizeof(pngf::DbsState));
+  if (persist && *reinterpret_cast<const int32_t*>(stg + (Y.off_flag - Y.off_state))) {
     // the barrier words are left inconsistent: clear them for the next search
     HIPCHK(h, hipMemsetAsync(pbar, 0, pngf::kPersistBarBytes, h->stream));
+    HIPCHK(h, hipMemsetAsync(at<int32_t>(h, Y.off_flag), 0, sizeof(int32_t), h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return fail(h, PNGF_ENUMERIC, "a grid barrier of the persistent search timed out");
   }
   if (want_bits) {
-    // the design of the last step (in the B set after an odd number of updates)
-    const uint8_t* cur = h->bits_pin + ((pinned->flips & 1) ? nd : 0);
+    // the design of the last step (in the B set after an odd number of
+    // updates); P.bits is one of the two adjacent buffers
+    const bool a_first = h->P.bits == at<uint8_t>(h, Y.off_bits);
+    const uint8_t* bits_a = reinterpret_cast<const uint8_t*>(stg) +
+                            ((a_first ? Y.off_bits : Y.off_bitsB) - Y.off_state);
+    const uint8_t* bits_b = reinterpret_cast<const uint8_t*>(stg) +
+                            ((a_first ? Y.off_bitsB : Y.off_bits) - Y.off_state);
+    const uint8_t* cur = (pinned->flips & 1) ? bits_b : bits_a;
     h->bits.assign(cur, cur + nd);
     h->bits_fresh = true;
   }
@@ -734,21 +742,27 @@ int mixed_refresh(pngf_handle* h, bool measure) {
       HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
     st = start_segment(h, true);
     if (st) return st;
-    // both read into the pinned scratch, with one wait
-    double& meas = *reinterpret_cast<double*>(h->pin + 8);
-    int32_t& wst = *reinterpret_cast<int32_t*>(h->pin + 16);
-    meas = 0.0;
-    wst = 0;
+    // read into the pinned scratch with one wait; with a measurement the
+    // band kernel also carries the Woodbury status (one copy)
+    double* mo = reinterpret_cast<double*>(h->pin + 8);
+    mo[0] = 0.0;
+    mo[1] = 0.0;
+    int32_t& wst0 = *reinterpret_cast<int32_t*>(h->pin + 24);
+    wst0 = 0;
+    const bool pending = h->wood_pending;
+    int32_t* dstatus = at<int32_t>(h, h->lay.off_status);
     if (measure) {
       double* out = at<double>(h, h->lay.off_bandout);
-      HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd, out, h->stream));
-      HIPCHK(h, hipMemcpyAsync(&meas, out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd, out,
+                                          pending ? dstatus : nullptr, h->stream));
+      HIPCHK(h, hipMemcpyAsync(mo, out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    } else if (pending) {
+      HIPCHK(h, hipMemcpyAsync(&wst0, dstatus, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               h->stream));
     }
-    const bool pending = h->wood_pending;
-    if (pending)
-      HIPCHK(h, hipMemcpyAsync(&wst, at<int32_t>(h, h->lay.off_status), sizeof(int32_t),
-                               hipMemcpyDeviceToHost, h->stream));
     if (measure || pending) HIPCHK(h, hipStreamSynchronize(h->stream));
+    const double meas = mo[0];
+    const int32_t wst = measure ? int32_t(mo[1]) : wst0;
     h->wood_pending = false;
     if (pending && wst) {
       // the deferred block-Woodbury update was singular: re-invert instead
@@ -1268,7 +1282,18 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
     for (int f = 0; f < F; ++f) HIPCHK(h, pngf::launch_to_c64(P.G[f], P.G32[f], nd, h->ld, h->stream));
   // the persistent search's barrier words start at generation 0
   HIPCHK(h, hipMemsetAsync(at<int32_t>(h, L.off_pbar), 0, pngf::kPersistBarBytes, h->stream));
-  if (!h->pin) HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->pin), pngf::kPinBytes));
+  {
+    const size_t need = pngf::kPinStage + (L.off_bitsB + nd - L.off_state);
+    if (h->pin && h->pin_bytes < need) {
+      (void)hipHostFree(h->pin);
+      h->pin = nullptr;
+    }
+    if (!h->pin) {
+      HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->pin), need));
+      h->pin_bytes = need;
+    }
+  }
+  HIPCHK(h, hipMemsetAsync(at<int32_t>(h, L.off_flag), 0, sizeof(int32_t), h->stream));
   if (!h->ev_pin) HIPCHK(h, hipEventCreateWithFlags(&h->ev_pin, hipEventDisableTiming));
   HIPCHK(h, hipEventRecord(h->ev_pin, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1582,7 +1607,6 @@ int pngf_destroy(pngf_handle* h) {
   }
   for (hipEvent_t e : h->ev_free) hipEventDestroy(e);
   release_streams(h);
-  if (h->bits_pin) (void)hipHostFree(h->bits_pin);
   if (h->pin) (void)hipHostFree(h->pin);
   if (h->ev_pin) (void)hipEventDestroy(h->ev_pin);
   delete h;
