@@ -278,13 +278,23 @@ int pngf_tile_dbs_run(pngf_handle *h, const int32_t *tiles, int32_t n_tiles, int
                       double *f_trace, pngf_dbs_result *res);
 
 /* Total device time (ms, HIP events on the bound stream; needs
- * PNGF_FLAG_TIMING) and launch count of the kernels of the last pngf_dbs_run,
+ * PNGF_FLAG_TIMING, or PNGF_FLAG_TIMING_STEPS for id 2 only) and launch
+ * count of the kernels of the last pngf_dbs_run (for id 2 of a persistent
+ * mixed search: its accepted steps),
  * per kernel id: 0 full scoring pass, 1 select, 2 accept (+ rescore),
  * 3 FP64 inversion, 4 other re-inversion work (GEMVs, outputs), 5 panel fold,
  * 6 mixed-path q row, 7 FP64 block-Woodbury update (mixed refresh, tile
  * accept), 8 tile scoring. */
 int pngf_kernel_times(pngf_handle *h, int32_t kernel_id, double *total_ms,
                       int64_t *launches);
+
+/* Bound of the persistent mixed search's grid-barrier waits: a workgroup
+ * polls at most `polls` times (default 1 << 20, about a second) before it
+ * gives up; the search then fails with PNGF_ENUMERIC, the barrier words are
+ * cleared, and the handle needs pngf_set_design before its next search.  For
+ * devices shared with other work and for tests of that path.  PNGF_EINVAL
+ * unless polls >= 1. */
+int pngf_set_persist_spin(pngf_handle *h, int32_t polls);
 
 int pngf_destroy(pngf_handle *h);
 

@@ -89,6 +89,7 @@ EXPORTS = {
                       C.POINTER(DbsResult)], C.c_int),
     "pngf_kernel_times": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double),
                            C.POINTER(C.c_int64)], C.c_int),
+    "pngf_set_persist_spin": ([C.c_void_p, C.c_int32], C.c_int),
     "pngf_destroy": ([C.c_void_p], C.c_int),
     "pngf_batch_create": ([C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
     "pngf_batch_last_error": ([C.c_void_p], C.c_char_p),
@@ -345,6 +346,10 @@ class Handle:
         return dict(accepted=acc[:n].copy(), f_trace=ftr[:n].copy(), n_accepted=n,
                     extra_chunks=res.sweeps, converged=bool(res.converged),
                     attempts=int(res.attempts), f_initial=res.f_initial, f_final=res.f_final)
+
+    def set_persist_spin(self, polls):
+        """Bound of a persistent-search grid-barrier wait, in polls."""
+        self._check(lib().pngf_set_persist_spin(self._h, int(polls)))
 
     def kernel_times(self, name):
         t = C.c_double()

@@ -137,7 +137,8 @@ struct pngf_handle {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int ld = 0, npl = 1;
-  bool persist_off = false;   // a cooperative launch of the persistent search failed
+  bool persist_off = false;   // a launch of the persistent search was refused
+  int persist_spin = pngf::kPersistSpin;   // polls of one grid-barrier wait
   Layout lay{};
   pngf::ProbDev P{};
   std::vector<uint8_t> bits;
@@ -651,7 +652,7 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
     const hipError_t e = pngf::launch_mixed_persist(h->P, int(t0), n,
                                                     reinterpret_cast<uint64_t*>(pbar),
                                                     at<int32_t>(h, h->lay.off_flag),
-                                                    pngf::kPersistSpin, h->stream);
+                                                    h->persist_spin, h->stream);
     if (e != hipSuccess) {
       // the grid cannot be co-resident here: one kernel per step from now on
       (void)hipGetLastError();
@@ -1589,6 +1590,12 @@ int pngf_tile_dbs_run(pngf_handle* h, const int32_t* tiles, int32_t n_tiles, int
     res->f_initial = f0;
     res->f_final = f;
   }
+  return PNGF_OK;
+}
+
+int pngf_set_persist_spin(pngf_handle* h, int32_t polls) {
+  if (!h || polls < 1) return PNGF_EINVAL;
+  h->persist_spin = polls;
   return PNGF_OK;
 }
 

@@ -118,3 +118,29 @@ def test_persistent_batches_equal_step_launches(wl, k_refresh, k_fold):
         assert r["f_trace"].tolist() == out[0]["f_trace"].tolist()
         assert r["f_final"] == out[0]["f_final"]
     h.close()
+
+
+def test_persistent_barrier_time_out_is_reported_and_recoverable():
+    """Failure handling of the persistent search, forced from the host: with
+    barrier waits bounded to a single poll the workgroups give up at the
+    first barrier (every kernel still exits), the search fails with
+    PNGF_ENUMERIC, and after set_design the handle searches normally again."""
+    g = golden(1)
+    if g is None:
+        pytest.skip("golden trajectory for workload 1 not generated")
+    p = workloads.config1()
+    say("config1 persistent search with one-poll barrier waits (expected to fail cleanly)")
+    h = P.Handle(p).bind(P.default_options(precision=P.PNGF_MIXED, max_accepts=8192,
+                                           max_sweeps=8))
+    h.set_persist_spin(1)
+    h.set_design(p.init_bits)
+    with pytest.raises(P.PngfError, match="timed out") as e:
+        h.dbs_run(p.perms)
+    assert e.value.code == -3   # PNGF_ENUMERIC
+    say("config1 persistent search after the time-out")
+    h.set_persist_spin(1 << 20)
+    h.set_design(p.init_bits)
+    res = h.dbs_run(p.perms)
+    _check(res, [a[2] for a in g["accepted"]], g["attempts"],
+           [a[3] for a in g["accepted"]], g["f_final"])
+    h.close()
