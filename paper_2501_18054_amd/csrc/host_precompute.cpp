@@ -337,11 +337,16 @@ int precompute(const pngf_problem* p, Precomputed* out, std::string* err) {
     }
     band_forward(band, N, bw, Y, K, first);
 
-    // M = Y^T D^-1 Y (K x K), accumulated per thread.
+    // M = Y^T D^-1 Y (K x K), accumulated per thread; the partial sums are
+    // added in thread order afterwards, so the result does not depend on
+    // which thread finishes first.
     std::vector<cd> M(size_t(K) * K, cd(0.0, 0.0));
-#pragma omp parallel
+    const int nth = omp_get_max_threads();
+    std::vector<std::vector<cd>> parts(static_cast<size_t>(nth));
+#pragma omp parallel num_threads(nth)
     {
-      std::vector<cd> Ml(size_t(K) * K, cd(0.0, 0.0));
+      std::vector<cd>& Ml = parts[size_t(omp_get_thread_num())];
+      Ml.assign(size_t(K) * K, cd(0.0, 0.0));
 #pragma omp for schedule(static)
       for (int64_t k = 0; k < N; ++k) {
         const cd* yk = &Y[k * K];
@@ -353,9 +358,10 @@ int precompute(const pngf_problem* p, Precomputed* out, std::string* err) {
           for (int c = 0; c < K; ++c) mr[c] += ya * yk[c];
         }
       }
-#pragma omp critical
-      for (size_t q = 0; q < Ml.size(); ++q) M[q] += Ml[q];
     }
+    for (const std::vector<cd>& Ml : parts)
+      for (size_t q = 0; q < Ml.size(); ++q) M[q] += Ml[q];
+    std::vector<std::vector<cd>>().swap(parts);
     std::vector<cd>().swap(Y);
     std::vector<cd>().swap(band);
 

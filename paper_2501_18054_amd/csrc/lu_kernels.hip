@@ -45,9 +45,11 @@ constexpr int kUpdRows = 16;
 
 // K[a][b] = delta_ab - k2d G[s_a][s_b]; clears the pivot marks.
 __global__ __launch_bounds__(256) void k_gather_K(z64* K, const z64* G, int ld, const int32_t* sidx,
-                                                  int ns, double k2d, int32_t* used) {
+                                                  int ns, double k2d, int32_t* used,
+                                                  int32_t* arrived) {
   const int a = blockIdx.y;
   const int b = blockIdx.x * 256 + threadIdx.x;
+  if (a == 0 && b == 0) *arrived = 0;
   if (b >= ns) return;
   const z64 g = G[size_t(sidx[a]) * ld + sidx[b]];
   K[size_t(a) * ld + b] = z64{(a == b ? 1.0 : 0.0) - k2d * g.re, -k2d * g.im};
@@ -202,6 +204,46 @@ __global__ __launch_bounds__(64) void k_tsel_wave(const z64* Pb, int n, int ncol
   wave_tournament(Pb, ncols, row, lane, cand + g * kGjNb, cnt + g);
 }
 
+// Device-coherent accesses of the proposal lists that workgroups of one
+// launch exchange (written through to memory, read around the caches).
+__device__ __forceinline__ void st_coh(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_coh(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave 0 of the workgroup that holds the winners (prop[0..nsel), in pivot
+// order): piv, used and B11^-1 (inverted in FP64, one column per lane), and
+// a zero pivot of the final level flagged in *status.
+__device__ __forceinline__ void tsel_finish(const z64* Pb, int k0, int ncols, const int* win,
+                                            int nsel, bool zero, int lane, int32_t* piv,
+                                            int32_t* used, z64* B11inv, int32_t* status) {
+  if (zero && lane == 0) atomicOr(status, 1);
+  const int j = lane;
+  z64 w[kGjNb];
+#pragma unroll
+  for (int r = 0; r < kGjNb; ++r) {
+    z64 v{0.0, 0.0};
+    if (j < kGjNb) {
+      if (r < nsel && j < ncols) v = Pb[size_t(win[r]) * kGjNb + j];
+      else if (r == j) v = z64{1.0, 0.0};       // padding of a ragged panel
+    } else if (j - kGjNb == r) {
+      v = z64{1.0, 0.0};
+    }
+    w[r] = v;
+  }
+  gj_lane_columns(w, std::make_integer_sequence<int, kGjNb>{});
+  if (j >= kGjNb && j < 2 * kGjNb)
+#pragma unroll
+    for (int r = 0; r < kGjNb; ++r) B11inv[r * kGjNb + (j - kGjNb)] = w[r];
+  if (lane < nsel) {
+    const int rw = win[lane];
+    piv[k0 + lane] = rw;
+    used[rw] = k0 + lane + 1;
+  }
+}
+
 // The rest of a panel's tournament in one workgroup of nw = blockDim/64 <= 16
 // waves.  Its first level is either level 0 itself (gcand null, n <= 64 nw:
 // one group of 64 rows per wave) or a merge of the ngin <= 4 nw groups that
@@ -241,30 +283,78 @@ __global__ __launch_bounds__(1024) void k_tsel_wg(const z64* Pb, int n, int k0, 
   }
   __syncthreads();
   if (wid != 0) return;
-  const int nsel = pcnt[cur][0];
-  if (zero && lane == 0) atomicOr(status, 1);
-  const int j = lane;
-  z64 w[kGjNb];
-#pragma unroll
-  for (int r = 0; r < kGjNb; ++r) {
-    z64 v{0.0, 0.0};
-    if (j < kGjNb) {
-      if (r < nsel && j < ncols) v = Pb[size_t(prop[cur][r]) * kGjNb + j];
-      else if (r == j) v = z64{1.0, 0.0};       // padding of a ragged panel
-    } else if (j - kGjNb == r) {
-      v = z64{1.0, 0.0};
+  tsel_finish(Pb, k0, ncols, &prop[cur][0], pcnt[cur][0], zero, lane, piv, used, B11inv, status);
+}
+
+
+// A panel's whole tournament in one launch for 64 < n <= 4096: workgroup g
+// (four waves, one per SIMD) runs level 0 on rows [256g, 256g + 256), one
+// group of 64 rows per wave, and wave 0 merges its four groups; the
+// proposals go to cand/cnt through device-coherent stores, and the last
+// workgroup to count itself in on *arrived (each waits for its stores first)
+// merges every workgroup's proposals, four groups per wave, and finishes.  It
+// also puts *arrived back to zero for the next panel.
+__global__ __launch_bounds__(256) void k_tsel_fused(const z64* Pb, int n, int k0, int ncols,
+                                                    int32_t* cand, int32_t* cnt,
+                                                    int32_t* arrived, int32_t* piv,
+                                                    int32_t* used, z64* B11inv,
+                                                    int32_t* status) {
+  __shared__ int prop[2][4 * kGjNb];
+  __shared__ int pcnt[2][4];
+  __shared__ int s_last;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6, g = blockIdx.x;
+  const int G = gridDim.x;
+  int row = g * 256 + wid * 64 + lane;
+  if (row >= n || used[row]) row = -1;
+  wave_tournament(Pb, ncols, row, lane, &prop[0][wid * kGjNb], &pcnt[0][wid]);
+  __syncthreads();
+  bool zero = false;
+  if (wid == 0) {
+    const int grp = lane / kGjNb, u = lane % kGjNb;
+    const int r = (u < pcnt[0][grp]) ? prop[0][grp * kGjNb + u] : -1;
+    zero = wave_tournament(Pb, ncols, r, lane, &prop[1][0], &pcnt[1][0]);
+    if (G > 1) {
+      const int c = pcnt[1][0];
+      if (lane < c) st_coh(cand + g * kGjNb + lane, prop[1][lane]);
+      if (lane == 0) st_coh(cnt + g, c);
+      __builtin_amdgcn_s_waitcnt(0);
+      if (lane == 0) s_last = (atomicAdd(arrived, 1) == G - 1) ? 1 : 0;
     }
-    w[r] = v;
   }
-  gj_lane_columns(w, std::make_integer_sequence<int, kGjNb>{});
-  if (j >= kGjNb && j < 2 * kGjNb)
-#pragma unroll
-    for (int r = 0; r < kGjNb; ++r) B11inv[r * kGjNb + (j - kGjNb)] = w[r];
-  if (lane < nsel) {
-    const int rw = prop[cur][lane];
-    piv[k0 + lane] = rw;
-    used[rw] = k0 + lane + 1;
+  __syncthreads();
+  if (G == 1) {
+    // one workgroup: its merge is the final level
+    if (wid == 0)
+      tsel_finish(Pb, k0, ncols, &prop[1][0], pcnt[1][0], zero, lane, piv, used, B11inv,
+                  status);
+    return;
   }
+  if (!s_last) return;
+  // the last workgroup: merge the G <= 16 proposal lists, four per wave
+  int groups = (G + 3) / 4;
+  {
+    const int grp = wid * 4 + lane / kGjNb, u = lane % kGjNb;
+    int r = -1;
+    if (wid < groups && grp < G && u < ld_coh(cnt + grp)) r = ld_coh(cand + grp * kGjNb + u);
+    if (wid < groups)
+      zero = wave_tournament(Pb, ncols, r, lane, &prop[0][wid * kGjNb], &pcnt[0][wid]);
+  }
+  int cur = 0;
+  while (groups > 1) {
+    __syncthreads();
+    const int ng = (groups + 3) / 4;
+    if (wid < ng) {
+      const int grp = wid * 4 + lane / kGjNb, u = lane % kGjNb;
+      const int r = (grp < groups && u < pcnt[cur][grp]) ? prop[cur][grp * kGjNb + u] : -1;
+      zero = wave_tournament(Pb, ncols, r, lane, &prop[cur ^ 1][wid * kGjNb], &pcnt[cur ^ 1][wid]);
+    }
+    cur ^= 1;
+    groups = ng;
+  }
+  __syncthreads();
+  if (wid != 0) return;
+  if (lane == 0) st_coh(arrived, 0);
+  tsel_finish(Pb, k0, ncols, &prop[cur][0], pcnt[cur][0], zero, lane, piv, used, B11inv, status);
 }
 
 // Every panel row reduced by B11^-1: pivot rows (used[r]-1 in the panel) get
@@ -458,13 +548,15 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
                           int32_t* status, int32_t* tsbuf, z64* B11inv, hipStream_t s) {
   const int nz = nd - ns;
   if (ns > 0) {
-    // two proposal lists (ids and counts) of (kGjNb + 1) ints per group
+    // the arrival count of the fused tournament, then two proposal lists
+    // (ids and counts) of (kGjNb + 1) ints per group
     const int g0 = (ns + 63) / 64;
-    int32_t* candA = tsbuf;
-    int32_t* candB = tsbuf + g0 * (kGjNb + 1);
+    int32_t* arrived = tsbuf;
+    int32_t* candA = tsbuf + 64;
+    int32_t* candB = candA + g0 * (kGjNb + 1);
     const dim3 gcols((ns + 255) / 256);
     hipLaunchKernelGGL(k_gather_K, dim3(gcols.x, ns), dim3(256), 0, s, S, G, ld, sidx, ns, k2d,
-                       used);
+                       used, arrived);
     hipLaunchKernelGGL(k_gj_panel_in, dim3((ns * kGjNb + 255) / 256), dim3(256), 0, s, S, ld, ns,
                        0, min(kGjNb, ns), Pb);
     for (int k0 = 0; k0 < ns; k0 += kGjNb) {
@@ -473,6 +565,10 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
         hipLaunchKernelGGL(k_tsel_wg, dim3(1), dim3(64), 0, s, Pb, ns, k0, nc,
                            static_cast<const int32_t*>(nullptr),
                            static_cast<const int32_t*>(nullptr), 0, piv, used, B11inv, status);
+      } else if (ns <= 16 * 256) {
+        const int g = (ns + 255) / 256;
+        hipLaunchKernelGGL(k_tsel_fused, dim3(g), dim3(256), 0, s, Pb, ns, k0, nc, candA,
+                           candA + g * kGjNb, arrived, piv, used, B11inv, status);
       } else {
         // level 0, then merge levels on the chip until one workgroup's
         // sixteen waves can merge the rest (<= 64 groups)
@@ -520,8 +616,15 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
     ix.cb = sidx;
     ix.rc = zidx;
     ix.cc = sidx;
+    // split K so that the grid covers the chip (about two workgroups of
+    // 64 x 64 outputs per CU); the partial products go to S, free once
+    // K^-1 has been scattered (splits * nz * ns <= nd * ld)
+    const int tiles = ((nz + 63) / 64) * ((ns + 63) / 64);
+    int splits = (512 + tiles - 1) / tiles;
+    splits = std::max(1, std::min(splits, 4));
+    while (splits > 1 && size_t(splits) * nz * ns > size_t(nd) * ld) --splits;
     e = launch_zgemm_ix(nz, ns, ns, G, ld, Cinv, ld, false, Cinv, ld, ix, z64{k2d, 0.0},
-                        z64{0.0, 0.0}, 1, nullptr, s);
+                        z64{0.0, 0.0}, splits, splits > 1 ? S : nullptr, s);
   }
   return e;
 }

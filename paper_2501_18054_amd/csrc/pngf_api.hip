@@ -261,8 +261,9 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_B1[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
     L.off_Pb[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
     L.off_Pn[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
-    // tournament proposals: two lists of (kGjNb + 1) ints per 64-row group
-    L.off_ts[f] = take(size_t(2) * (pngf::kGjNbHost + 1) * ((nd + 63) / 64) * sizeof(int32_t));
+    // tournament: an arrival count, then two proposal lists of (kGjNb + 1)
+    // ints per 64-row group
+    L.off_ts[f] = take(256 + size_t(2) * (pngf::kGjNbHost + 1) * ((nd + 63) / 64) * sizeof(int32_t));
     L.off_B11[f] = take(size_t(pngf::kGjNbHost) * pngf::kGjNbHost * sizeof(z64));
     L.off_piv[f] = take(size_t(nd) * sizeof(int32_t));
     L.off_invp[f] = take(size_t(nd) * sizeof(int32_t));
