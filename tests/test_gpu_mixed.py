@@ -96,11 +96,10 @@ def test_mixed_then_plain_calls():
 @pytest.mark.parametrize("wl,k_refresh,k_fold", [("config1", 32, 0), ("config1", 0, 8),
                                                    ("config0", 32, 0), ("metal", 32, 0)])
 def test_persistent_batches_equal_step_launches(wl, k_refresh, k_fold):
-    """One cooperative launch per batch (rows of C0^-1 held in registers,
-    grid barriers between steps) against one kernel per step, on one handle
-    (the host precompute sums in a thread-dependent order, so two handles
-    differ at 1e-17): the same arithmetic, so bit-identical searches, and a
-    second persistent search identical to the first."""
+    """One launch per batch (rows of C0^-1 held in registers, grid barriers
+    between steps) against one kernel per step, on one handle: the same
+    arithmetic, so bit-identical searches, and a second persistent search
+    identical to the first."""
     p = getattr(workloads, wl)()
     say(f"{wl} mixed persistent vs per-step launches, k_refresh={k_refresh} k_fold={k_fold}")
     h = P.Handle(p)
