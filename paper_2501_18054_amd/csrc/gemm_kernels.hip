@@ -277,9 +277,11 @@ __global__ __launch_bounds__(kSmallInvThreads) void k_small_inverse(z64* A, int 
 // ------------------------------------------------------------------ launchers
 // C = beta C + alpha A op(B) with the index maps of ix (see GemmIdx).
 // work (>= splits * M * N entries) is used when splits > 1.
+// nz_out (nullable): with more than one split, the partial products are
+// left in work (work[z][row][col], z < *nz_out) for the caller to reduce.
 hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
                            bool transb, z64* C, int ldc, const GemmIdx& ix, z64 alpha, z64 beta,
-                           int splits, z64* work, hipStream_t s) {
+                           int splits, z64* work, hipStream_t s, int* nz_out) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (K <= 0) return hipErrorInvalidValue;
   splits = std::max(1, std::min(splits, (K + kGemmBK - 1) / kGemmBK));
@@ -306,7 +308,8 @@ hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64
       hipLaunchKernelGGL((k_zgemm<1, 1, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
                          ldc, ix, alpha, beta, kchunk, wk);
   }
-  if (splits > 1) {
+  if (nz_out) *nz_out = splits > 1 ? splits : 0;
+  if (splits > 1 && !nz_out) {
     const size_t n = size_t(M) * N;
     hipLaunchKernelGGL(k_zgemm_reduce, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, M, N,
                        splits, work, C, ldc, ix, alpha, beta);
@@ -318,11 +321,48 @@ hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64
 // by n when transb, rows of B by k otherwise).
 hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_t* ca,
                         const z64* B, int ldb, bool transb, const int32_t* rb, z64* C, int ldc,
-                        z64 alpha, z64 beta, int splits, z64* work, hipStream_t s) {
+                        z64 alpha, z64 beta, int splits, z64* work, hipStream_t s, int* nz_out) {
   GemmIdx ix;
   ix.ca = ca;
   ix.rb = rb;
-  return launch_zgemm_ix(M, N, K, A, lda, B, ldb, transb, C, ldc, ix, alpha, beta, splits, work, s);
+  return launch_zgemm_ix(M, N, K, A, lda, B, ldb, transb, C, ldc, ix, alpha, beta, splits, work, s,
+                         nz_out);
+}
+
+// The block-Woodbury panel from the skinny GEMM's partial products, in one
+// pass: P[i][c] = s_c sum_z work[z][i][c] (fixed order), and the capacitance
+// matrix Cap[a][c] = delta_ac - P[F_a][c] from the same sums; status
+// (nullable) is cleared first.  Same arithmetic as k_zgemm_reduce followed
+// by k_wood_scale and k_wood_cap.
+__global__ __launch_bounds__(256) void k_wood_panel(const z64* work, int nz, int nd, int k,
+                                                    const double* sc, z64* P, int ldp,
+                                                    const int32_t* F, z64* Cap,
+                                                    int32_t* status) {
+  const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+  const size_t np = size_t(nd) * k;
+  if (status && e == 0) *status = 0;
+  if (e < np) {
+    z64 v{0.0, 0.0};
+    for (int z = 0; z < nz; ++z) v = zadd(v, work[size_t(z) * np + e]);
+    const int i = int(e / k), c = int(e % k);
+    P[size_t(i) * ldp + c] = zscale(zmul(z64{1.0, 0.0}, v), sc[c]);
+  } else if (e < np + size_t(k) * k) {
+    const int q = int(e - np), a = q / k, c = q % k;
+    const size_t src = size_t(F[a]) * k + c;
+    z64 v{0.0, 0.0};
+    for (int z = 0; z < nz; ++z) v = zadd(v, work[size_t(z) * np + src]);
+    const z64 p = zscale(zmul(z64{1.0, 0.0}, v), sc[c]);
+    Cap[q] = z64{(a == c ? 1.0 : 0.0) - p.re, -p.im};
+  }
+}
+
+hipError_t launch_wood_panel(const z64* work, int nz, int nd, int k, const double* sc, z64* P,
+                             int ldp, const int32_t* F, z64* Cap, int32_t* status, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  const size_t n = size_t(nd) * k + size_t(k) * k;
+  hipLaunchKernelGGL(k_wood_panel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, work, nz, nd,
+                     k, sc, P, ldp, F, Cap, status);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int k, int n, z64* dst,

@@ -38,7 +38,7 @@ namespace pngf {
 
 hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
                            bool transb, z64* C, int ldc, const GemmIdx& ix, z64 alpha, z64 beta,
-                           int splits, z64* work, hipStream_t s);
+                           int splits, z64* work, hipStream_t s, int* nz_out = nullptr);
 
 constexpr int kGjNb = 16;
 constexpr int kUpdRows = 16;
@@ -467,10 +467,11 @@ __global__ __launch_bounds__(256) void k_scatter_inverse(const z64* M, z64* Cinv
 // y[i] = beta w[i] + gamma w2[i] + alpha sum_j A[i,j] d_j v[j], with
 // d_j = (bits[j] ? ds : 0) when bits != nullptr, else 1.  One workgroup per
 // row; y may alias w (row i reads w[i] before writing y[i]).
+// A32 (nullable): also writes the complex-FP32 copy of the row it reads.
 __global__ __launch_bounds__(kRowThreads) void k_gemv(const z64* A, int ld, int n, const z64* v,
                                                       const uint8_t* bits, double ds, z64 alpha,
                                                       z64 beta, const z64* w, double gamma,
-                                                      const z64* w2, z64* y) {
+                                                      const z64* w2, z64* y, z32* A32) {
   __shared__ double red[2 * (kRowThreads / 64)];
   const int i = blockIdx.x;
   const z64* a = A + size_t(i) * ld;
@@ -478,7 +479,9 @@ __global__ __launch_bounds__(kRowThreads) void k_gemv(const z64* A, int ld, int 
   for (int j = threadIdx.x; j < n; j += kRowThreads) {
     z64 vj = v[j];
     if (bits) vj = zscale(vj, bits[j] ? ds : 0.0);
-    acc = zfma(a[j], vj, acc);
+    const z64 aij = a[j];
+    if (A32) A32[size_t(i) * ld + j] = z32{float(aij.re), float(aij.im)};
+    acc = zfma(aij, vj, acc);
   }
   const z64 s = block_zsum(acc, red);
   if (threadIdx.x == 0) {
@@ -631,9 +634,9 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
 
 hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t* bits, double ds,
                        z64 alpha, z64 beta, const z64* w, double gamma, const z64* w2, z64* y,
-                       hipStream_t s) {
+                       hipStream_t s, z32* A32) {
   hipLaunchKernelGGL(k_gemv, dim3(n), dim3(kRowThreads), 0, s, A, ld, n, v, bits, ds, alpha, beta,
-                     w, gamma, w2, y);
+                     w, gamma, w2, y, A32);
   return hipGetLastError();
 }
 

@@ -30,7 +30,8 @@ hipError_t launch_gemv2(const z64* A, int ld, int n, const uint8_t* bits, double
                         const GemvOut& o1, const GemvOut& o2, hipStream_t s);
 hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_t* ca,
                         const z64* B, int ldb, bool transb, const int32_t* rb, z64* C, int ldc,
-                        z64 alpha, z64 beta, int splits, z64* work, hipStream_t s);
+                        z64 alpha, z64 beta, int splits, z64* work, hipStream_t s,
+                        int* nz_out = nullptr);
 hipError_t launch_rform_step(const ProbDev& P, int npl, int step, hipStream_t s);
 hipError_t launch_rform_score(const ProbDev& P, hipStream_t s);
 hipError_t launch_rform_ut(const ProbDev& P, int f, int kp, z64* Ut, hipStream_t s);
@@ -40,6 +41,8 @@ hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int 
 hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, const double* sc,
                            z64* Cap, int32_t* status, hipStream_t s);
 hipError_t launch_small_inverse(z64* A, int k, int32_t* status, hipStream_t s);
+hipError_t launch_wood_panel(const z64* work, int nz, int nd, int k, const double* sc, z64* P,
+                             int ldp, const int32_t* F, z64* Cap, int32_t* status, hipStream_t s);
 hipError_t launch_gradient(const ProbDev& P, double* out, hipStream_t s);
 hipError_t launch_tile_score(const ProbDev& P, const int32_t* tiles, int ntiles, int m, int ks,
                              z64* part, double* out, hipStream_t s);
@@ -60,7 +63,7 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
                           int32_t* status, int32_t* tsbuf, z64* B11inv, hipStream_t s);
 hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t* bits, double ds,
                        z64 alpha, z64 beta, const z64* w, double gamma, const z64* w2, z64* y,
-                       hipStream_t s);
+                       hipStream_t s, z32* A32 = nullptr);
 hipError_t launch_output(const ProbDev& P, int f, const z64* god, z64 xb, int last,
                          hipStream_t s);
 hipError_t launch_to_c64(const z64* src, z32* dst, int nd, int ld, hipStream_t s);
@@ -139,6 +142,7 @@ struct pngf_handle {
   int ld = 0, npl = 1;
   bool persist_off = false;   // a launch of the persistent search was refused
   int persist_spin = pngf::kPersistSpin;   // polls of one grid-barrier wait
+  bool reform_c64 = false;   // reform_fields also writes C0^-1 (mixed refresh)
   Layout lay{};
   pngf::ProbDev P{};
   std::vector<uint8_t> bits;
@@ -396,9 +400,10 @@ int reform_fields(pngf_handle* h) {
     z64* u = at<z64>(h, L.off_u[f]);
     z64* r = at<z64>(h, L.off_r[f]);
     Timer t(h, KID_OTHER);
-    // E = C^-1 b
+    // E = C^-1 b (and, for a mixed refresh, C0^-1 = complex-FP32 C^-1 from
+    // the same pass)
     HIPCHK(h, pngf::launch_gemv(P.Cinv[f], ld, nd, b, nullptr, 0.0, one, zero, nullptr, 0.0,
-                                nullptr, P.E[f], h->stream));
+                                nullptr, P.E[f], h->stream, h->reform_c64 ? P.C0[f] : nullptr));
     // one pass over G:  r = b - E + k0^2 G diag(deps) E,  u = G diag(deps) G_OD
     const pngf::GemvOut o_r{P.E[f], z64{k2, 0.0}, one, b, -1.0, P.E[f], r};
     const pngf::GemvOut o_u{god, one, zero, nullptr, 0.0, nullptr, u};
@@ -516,11 +521,19 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
       z64* wQ = at<z64>(h, L.off_wQ[f]);
       z64* wW = at<z64>(h, L.off_wW[f]);
       z64* cap = at<z64>(h, L.off_wCap[f]);
-      // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T)
+      // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T): split-K
+      // partials, then one pass that reduces, scales and forms Cap
+      z64* wk = at<z64>(h, L.off_wWork[f]);
+      int nzp = 0;
       HIPCHK(h, pngf::launch_zgemm(nd, k, nd, P.Cinv[f], ld, nullptr, P.G[f], ld, true, dF, wP, k,
-                                   one, zero, pngf::kWoodSplits, at<z64>(h, L.off_wWork[f]), sf));
-      HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS + size_t(f) * k, cap,
-                                      F == 1 ? status : nullptr, sf));
+                                   one, zero, pngf::kWoodSplits, wk, sf, &nzp));
+      if (nzp > 0) {
+        HIPCHK(h, pngf::launch_wood_panel(wk, nzp, nd, k, dS + size_t(f) * k, wP, k, dF, cap,
+                                          F == 1 ? status : nullptr, sf));
+      } else {
+        HIPCHK(h, pngf::launch_wood_cap(wP, k, nd, dF, k, dS + size_t(f) * k, cap,
+                                        F == 1 ? status : nullptr, sf));
+      }
       HIPCHK(h, pngf::launch_small_inverse(cap, k, status, sf));
       // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
       HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, sf));
@@ -735,13 +748,18 @@ int capture_ref_bits(pngf_handle* h) {
 // in FP64 (exact key) and, when the previous scores were FP32, measure their
 // error against the FP64 scores to set the error band.
 int mixed_refresh(pngf_handle* h, bool measure) {
-  const int nd = h->pc.n_d, F = int(h->pc.freq.size());
+  const int nd = h->pc.n_d;
   h->wood_pending = false;
+  // every path of the refresh ends in reform_fields, whose first pass over
+  // C^-1 also writes C0^-1 while this guard lives
+  struct C64Pass {
+    pngf_handle* h;
+    explicit C64Pass(pngf_handle* hh) : h(hh) { h->reform_c64 = true; }
+    ~C64Pass() { h->reform_c64 = false; }
+  } c64pass(h);
   int st = fp64_refresh(h, true);
   if (st) return st;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int f = 0; f < F; ++f)
-      HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
     st = start_segment(h, true);
     if (st) return st;
     // read into the pinned scratch with one wait; with a measurement the
