@@ -296,6 +296,14 @@ int pngf_kernel_times(pngf_handle *h, int32_t kernel_id, double *total_ms,
  * unless polls >= 1. */
 int pngf_set_persist_spin(pngf_handle *h, int32_t polls);
 
+/* For tests of the recovery path: the next n FP64 block-Woodbury refreshes
+ * of the mixed search report their capacitance matrix as singular, so the
+ * search re-inverts C^-1 instead (as it does for a truly singular one; with
+ * the persistent search that check happens at the next launch, which then
+ * runs no step).  The search's results do not change.  PNGF_EINVAL unless
+ * n >= 0. */
+int pngf_force_singular_refresh(pngf_handle *h, int32_t n);
+
 int pngf_destroy(pngf_handle *h);
 
 /* ---- batches (many independent problems advanced together) -------------

@@ -90,6 +90,7 @@ EXPORTS = {
     "pngf_kernel_times": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double),
                            C.POINTER(C.c_int64)], C.c_int),
     "pngf_set_persist_spin": ([C.c_void_p, C.c_int32], C.c_int),
+    "pngf_force_singular_refresh": ([C.c_void_p, C.c_int32], C.c_int),
     "pngf_destroy": ([C.c_void_p], C.c_int),
     "pngf_batch_create": ([C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
     "pngf_batch_last_error": ([C.c_void_p], C.c_char_p),
@@ -346,6 +347,10 @@ class Handle:
         return dict(accepted=acc[:n].copy(), f_trace=ftr[:n].copy(), n_accepted=n,
                     extra_chunks=res.sweeps, converged=bool(res.converged),
                     attempts=int(res.attempts), f_initial=res.f_initial, f_final=res.f_final)
+
+    def force_singular_refresh(self, n):
+        """Test hook: the next n block-Woodbury refreshes report singular."""
+        self._check(lib().pngf_force_singular_refresh(self._h, int(n)))
 
     def set_persist_spin(self, polls):
         """Bound of a persistent-search grid-barrier wait, in polls."""

@@ -79,10 +79,11 @@ __global__ __launch_bounds__(256) void k_fold(ProbDev P, int f, int kp) {
 // max_i |df64_i - df32_i| / bound_i over all candidates: the FP32 error of the
 // scores just before an FP64 re-inversion, relative to their bound.
 // out[0] = the measurement; out[1] = *status (nullable) as a double, so that
-// one read brings both to the host.
+// one read brings both to the host; bandp (nullable) receives the band the
+// measurement sets, min(1e-2, max(1e-6, 100 m)) when m is finite.
 __global__ __launch_bounds__(256) void k_band_measure(const double* df32, const double* bnd32,
                                                       const double* df64, int nd, double* out,
-                                                      const int32_t* status) {
+                                                      const int32_t* status, double* bandp) {
   __shared__ double red[4];
   double mx = 0.0;
   for (int i = threadIdx.x; i < nd; i += 256) {
@@ -94,8 +95,10 @@ __global__ __launch_bounds__(256) void k_band_measure(const double* df32, const 
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
   if (threadIdx.x == 0) {
-    out[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    out[0] = m;
     out[1] = status ? double(*status) : 0.0;
+    if (bandp && isfinite(m)) *bandp = fmin(1e-2, fmax(1e-6, 100.0 * m));
   }
 }
 
@@ -113,8 +116,10 @@ hipError_t launch_fold(const ProbDev& P, int f, int kp, hipStream_t s) {
 }
 
 hipError_t launch_band_measure(const double* df32, const double* bnd32, const double* df64,
-                               int nd, double* out, const int32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_band_measure, dim3(1), dim3(256), 0, s, df32, bnd32, df64, nd, out, status);
+                               int nd, double* out, const int32_t* status, hipStream_t s,
+                               double* bandp) {
+  hipLaunchKernelGGL(k_band_measure, dim3(1), dim3(256), 0, s, df32, bnd32, df64, nd, out, status,
+                     bandp);
   return hipGetLastError();
 }
 

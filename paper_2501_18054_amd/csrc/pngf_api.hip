@@ -21,7 +21,8 @@ hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int
 hipError_t launch_plain_step(const ProbDev& P, int npl, int step, hipStream_t s);
 hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s);
 hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint64_t* bar,
-                                int32_t* flag, int spin_limit, hipStream_t s);
+                                int32_t* flag, int spin_limit, const double* bandp,
+                                const int32_t* wstat, hipStream_t s);
 hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
                              int grid, int npl, int mixed, int step, hipStream_t s);
@@ -69,7 +70,8 @@ hipError_t launch_output(const ProbDev& P, int f, const z64* god, z64 xb, int la
 hipError_t launch_to_c64(const z64* src, z32* dst, int nd, int ld, hipStream_t s);
 hipError_t launch_fold(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_band_measure(const double* df32, const double* bnd32, const double* df64,
-                               int nd, double* out, const int32_t* status, hipStream_t s);
+                               int nd, double* out, const int32_t* status, hipStream_t s,
+                               double* bandp = nullptr);
 constexpr int kGjNbHost = 16;
 constexpr int kPanelCap = 64;      // deferred Sherman-Morrison terms (mixed)
 constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
@@ -120,7 +122,7 @@ struct Layout {
   size_t off_S[pngf::kMaxFreq], off_B1[pngf::kMaxFreq], off_Pb[pngf::kMaxFreq],
       off_Pn[pngf::kMaxFreq], off_ts[pngf::kMaxFreq], off_B11[pngf::kMaxFreq],
       off_piv[pngf::kMaxFreq], off_invp[pngf::kMaxFreq], off_used[pngf::kMaxFreq];
-  size_t off_status, off_pbar, off_flag, off_u[pngf::kMaxFreq], off_r[pngf::kMaxFreq];
+  size_t off_status, off_pbar, off_flag, off_band, off_u[pngf::kMaxFreq], off_r[pngf::kMaxFreq];
   size_t off_wP[pngf::kMaxFreq], off_wQ[pngf::kMaxFreq], off_wW[pngf::kMaxFreq],
       off_wCap[pngf::kMaxFreq], off_wWork[pngf::kMaxFreq];
   size_t off_wF, off_wS, off_tiles, off_tpart;
@@ -143,6 +145,9 @@ struct pngf_handle {
   bool persist_off = false;   // a launch of the persistent search was refused
   int persist_spin = pngf::kPersistSpin;   // polls of one grid-barrier wait
   bool reform_c64 = false;   // reform_fields also writes C0^-1 (mixed refresh)
+  bool persist_ok = false;   // a persistent launch of this search has run
+  bool persist_aborted = false;   // the last one found a pending refresh singular
+  int force_singular = 0;   // block-Woodbury refreshes still to report singular (test hook)
   Layout lay{};
   pngf::ProbDev P{};
   std::vector<uint8_t> bits;
@@ -277,6 +282,7 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
   L.off_zidx = take(size_t(nd) * sizeof(int32_t));
   L.off_pos = take(size_t(nd) * sizeof(int32_t));
   L.off_status = take(sizeof(int32_t));
+  L.off_band = take(sizeof(double));   // the error band as the device holds it
   L.off_pbar = take(pngf::kPersistBarBytes);   // grid-barrier words, then the time-out flag
   for (int f = 0; f < F; ++f) {
     L.off_u[f] = take(vec);
@@ -535,6 +541,11 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
                                         F == 1 ? status : nullptr, sf));
       }
       HIPCHK(h, pngf::launch_small_inverse(cap, k, status, sf));
+      if (h->force_singular > 0 && f == F - 1) {
+        // test hook: this refresh reports a singular capacitance matrix
+        HIPCHK(h, hipMemsetAsync(status, 1, sizeof(int32_t), sf));
+        --h->force_singular;
+      }
       // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
       HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, sf));
       HIPCHK(h, pngf::launch_zgemm(k, nd, k, cap, k, nullptr, wQ, nd, false, nullptr, wW, nd, one,
@@ -663,15 +674,20 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
   Timer t(h, KID_ACCEPT);
   int32_t* pbar = at<int32_t>(h, h->lay.off_pbar);
   if (persist) {
-    const hipError_t e = pngf::launch_mixed_persist(h->P, int(t0), n,
-                                                    reinterpret_cast<uint64_t*>(pbar),
-                                                    at<int32_t>(h, h->lay.off_flag),
-                                                    h->persist_spin, h->stream);
+    const hipError_t e = pngf::launch_mixed_persist(
+        h->P, int(t0), n, reinterpret_cast<uint64_t*>(pbar), at<int32_t>(h, h->lay.off_flag),
+        h->persist_spin, at<double>(h, h->lay.off_band),
+        h->wood_pending ? at<int32_t>(h, h->lay.off_status) : nullptr, h->stream);
     if (e != hipSuccess) {
-      // the grid cannot be co-resident here: one kernel per step from now on
       (void)hipGetLastError();
+      // refreshes of this search already left the band and a refresh status
+      // on the device alone: the per-step kernels cannot take over now
+      if (h->persist_ok) return fail(h, PNGF_EDEVICE, "persistent search launch failed");
+      // the grid cannot be resident here: one kernel per step from now on
       h->persist_off = true;
       persist = false;
+    } else {
+      h->persist_ok = true;
     }
   }
   if (!persist)
@@ -689,7 +705,16 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
   HIPCHK(h, hipMemcpyAsync(stg, h->ws + Y.off_state, span, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   std::memcpy(pinned, stg, sizeof(pngf::DbsState));
-  if (persist && *reinterpret_cast<const int32_t*>(stg + (Y.off_flag - Y.off_state))) {
+  const int32_t fl = persist ? *reinterpret_cast<const int32_t*>(stg + (Y.off_flag - Y.off_state))
+                             : 0;
+  if (persist) h->wood_pending = false;   // the launch read (and acted on) the status
+  if (fl == 2) {
+    // no step ran: the refresh before it was singular; the caller re-inverts
+    HIPCHK(h, hipMemsetAsync(at<int32_t>(h, Y.off_flag), 0, sizeof(int32_t), h->stream));
+    h->persist_aborted = true;
+    return PNGF_OK;
+  }
+  if (fl) {
     // the barrier words are left inconsistent: clear them for the next search
     HIPCHK(h, hipMemsetAsync(pbar, 0, pngf::kPersistBarBytes, h->stream));
     HIPCHK(h, hipMemsetAsync(at<int32_t>(h, Y.off_flag), 0, sizeof(int32_t), h->stream));
@@ -747,7 +772,10 @@ int capture_ref_bits(pngf_handle* h) {
 // Re-form the FP64 state, cast C0^-1 to complex FP32, rescore every candidate
 // in FP64 (exact key) and, when the previous scores were FP32, measure their
 // error against the FP64 scores to set the error band.
-int mixed_refresh(pngf_handle* h, bool measure) {
+// nosync (persistent search): nothing is read back; the band goes to the
+// device word only and a pending block-Woodbury status is checked by the
+// next launch (which runs no step if it is set).
+int mixed_refresh(pngf_handle* h, bool measure, bool nosync = false) {
   const int nd = h->pc.n_d;
   h->wood_pending = false;
   // every path of the refresh ends in reform_fields, whose first pass over
@@ -759,6 +787,16 @@ int mixed_refresh(pngf_handle* h, bool measure) {
   } c64pass(h);
   int st = fp64_refresh(h, true);
   if (st) return st;
+  double* dband = (h->opt.guard <= 0.0) ? at<double>(h, h->lay.off_band) : nullptr;
+  if (nosync) {
+    st = start_segment(h, true);
+    if (st) return st;
+    if (measure && dband)
+      HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd,
+                                          at<double>(h, h->lay.off_bandout), nullptr, h->stream,
+                                          dband));
+    return PNGF_OK;
+  }
   for (int pass = 0; pass < 2; ++pass) {
     st = start_segment(h, true);
     if (st) return st;
@@ -774,7 +812,7 @@ int mixed_refresh(pngf_handle* h, bool measure) {
     if (measure) {
       double* out = at<double>(h, h->lay.off_bandout);
       HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd, out,
-                                          pending ? dstatus : nullptr, h->stream));
+                                          pending ? dstatus : nullptr, h->stream, dband));
       HIPCHK(h, hipMemcpyAsync(mo, out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     } else if (pending) {
       HIPCHK(h, hipMemcpyAsync(&wst0, dstatus, sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -864,6 +902,18 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
     const int nl = (persist && due) ? nb + 2 : nb;
     st = run_steps(h, pngf::launch_mixed_step, t, nl, pinned, due, persist);
     if (st) return st;
+    if (h->persist_aborted) {
+      // the unchecked block-Woodbury refresh before this batch was singular
+      // and the batch ran no step: re-invert and run it again
+      h->persist_aborted = false;
+      h->reform_c64 = true;
+      st = device_reinvert(h);
+      h->reform_c64 = false;
+      if (st) return st;
+      st = start_segment(h, true);
+      if (st) return st;
+      continue;
+    }
     t += nl;
     if (pinned->done) break;
     bool refresh = pinned->need_refresh != 0;
@@ -879,7 +929,8 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
     since = pinned->n_since;
     kpan = pinned->kpanel;
     if (refresh) {
-      st = mixed_refresh(h, !pinned->exact);
+      // with the persistent search running, the refresh reads nothing back
+      st = mixed_refresh(h, !pinned->exact, persist && h->persist_ok && !h->persist_off);
       if (st) return st;
       *n_refresh += 1;
       if (band_hit) *n_band += 1;
@@ -1077,8 +1128,12 @@ int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double*
   // every search starts from the initial error band (it is recalibrated at
   // each FP64 re-inversion), so repeated runs are identical
   h->P.band = (h->opt.guard > 0.0) ? h->opt.guard : 1e-3;
+  HIPCHK(h, hipMemcpyAsync(at<double>(h, h->lay.off_band), &h->P.band, sizeof(double),
+                           hipMemcpyHostToDevice, h->stream));
   for (int k = 0; k < KID_N; ++k) { h->ktime_ms[k] = 0.0; h->klaunch[k] = 0; }
   h->nacc_seen = 0;
+  h->persist_ok = false;
+  h->persist_aborted = false;
   return write_state(h, &s);
 }
 
@@ -1609,6 +1664,12 @@ int pngf_tile_dbs_run(pngf_handle* h, const int32_t* tiles, int32_t n_tiles, int
     res->f_initial = f0;
     res->f_final = f;
   }
+  return PNGF_OK;
+}
+
+int pngf_force_singular_refresh(pngf_handle* h, int32_t n) {
+  if (!h || n < 0) return PNGF_EINVAL;
+  h->force_singular = n;
   return PNGF_OK;
 }
 

@@ -801,7 +801,9 @@ template <int PRE>
 __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P, int t0,
                                                                      int nsteps, uint64_t* bar,
                                                                      int32_t* flag,
-                                                                     int spin_limit) {
+                                                                     int spin_limit,
+                                                                     const double* bandp,
+                                                                     const int32_t* wstat) {
   __shared__ StepCtx c;
   __shared__ z64 alph_s[kPersistSlots];
   __shared__ z64 cc_s[kPersistSlots];
@@ -819,6 +821,14 @@ __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P,
   // acquire: nothing of the previous launches' writes may be read stale
   if (tid == 0) __threadfence();
   __syncthreads();
+  // a block-Woodbury refresh enqueued before this launch that found its
+  // capacitance matrix singular: C0^-1 is unusable, so no step runs (every
+  // workgroup reads the same word); the host re-inverts and launches again
+  if (wstat && *wstat) {
+    if (g == 0 && tid == 0) *flag = 2;
+    return;
+  }
+  const double bandv = *bandp;   // the error band, set on the device by the last refresh
   z32 pa[PRE], pb[PRE];
 #pragma unroll
   for (int q = 0; q < PRE; ++q) {
@@ -962,7 +972,7 @@ __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P,
         P.df32[r] = df;
         P.dfb[r] = bnd;
         const double margin = df - c.eta * c.f;
-        const double band = P.band * bnd;
+        const double band = bandv * bnd;
         if (margin >= -band && c.cs < c.ns) {
           uint32_t k = kNoKey;
           if (pk >= c.cp) k = pack_key(pk, r);
@@ -1427,7 +1437,8 @@ hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s)
 // leaves them to be cleared by the caller.
 template <int PRE>
 hipError_t launch_persist_pre(const ProbDev& P, int t0, int nsteps, uint64_t* bar, int32_t* flag,
-                              int spin_limit, hipStream_t s) {
+                              int spin_limit, const double* bandp, const int32_t* wstat,
+                              hipStream_t s) {
   static int cap[64] = {0};       // resident workgroups per device (0: not known yet)
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -1445,16 +1456,21 @@ hipError_t launch_persist_pre(const ProbDev& P, int t0, int nsteps, uint64_t* ba
   const int grid = (P.nd + kMixRows - 1) / kMixRows;
   if (grid > cap[dev]) return hipErrorNotSupported;
   hipLaunchKernelGGL(k_mixed_persist<PRE>, dim3(grid), dim3(kPersistThreads), 0, s, P, t0, nsteps,
-                     bar, flag, spin_limit);
+                     bar, flag, spin_limit, bandp, wstat);
   return hipGetLastError();
 }
 
+// bandp: the device word holding the error band; wstat (nullable): the
+// status of a block-Woodbury refresh still unread by the host.
 hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint64_t* bar,
-                                int32_t* flag, int spin_limit, hipStream_t s) {
+                                int32_t* flag, int spin_limit, const double* bandp,
+                                const int32_t* wstat, hipStream_t s) {
   if (P.nfreq != 1 || P.nd > 64 * 32 || P.kcap > kPersistSlots) return hipErrorNotSupported;
-  if (P.nd <= 64 * 8) return launch_persist_pre<8>(P, t0, nsteps, bar, flag, spin_limit, s);
-  if (P.nd <= 64 * 16) return launch_persist_pre<16>(P, t0, nsteps, bar, flag, spin_limit, s);
-  return launch_persist_pre<32>(P, t0, nsteps, bar, flag, spin_limit, s);
+  if (P.nd <= 64 * 8)
+    return launch_persist_pre<8>(P, t0, nsteps, bar, flag, spin_limit, bandp, wstat, s);
+  if (P.nd <= 64 * 16)
+    return launch_persist_pre<16>(P, t0, nsteps, bar, flag, spin_limit, bandp, wstat, s);
+  return launch_persist_pre<32>(P, t0, nsteps, bar, flag, spin_limit, bandp, wstat, s);
 }
 
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,

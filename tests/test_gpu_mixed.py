@@ -143,3 +143,24 @@ def test_persistent_barrier_time_out_is_reported_and_recoverable():
     _check(res, [a[2] for a in g["accepted"]], g["attempts"],
            [a[3] for a in g["accepted"]], g["f_final"])
     h.close()
+
+
+@pytest.mark.parametrize("step_launches", [False, True])
+def test_singular_refresh_recovery(step_launches):
+    """Recovery from a singular block-Woodbury refresh, forced from the host
+    for the first two refreshes: the search re-inverts C^-1 instead (the
+    persistent search learns it at its next launch, which runs no step) and
+    still follows the oracle's trajectory."""
+    g = golden(1)
+    if g is None:
+        pytest.skip("golden trajectory for workload 1 not generated")
+    p = workloads.config1()
+    say(f"config1 mixed, first two refreshes forced singular, step_launches={step_launches}")
+    h = P.Handle(p).bind(P.default_options(precision=P.PNGF_MIXED, max_accepts=8192,
+                                           max_sweeps=8, step_launches=step_launches))
+    h.set_design(p.init_bits)
+    h.force_singular_refresh(2)
+    res = h.dbs_run(p.perms)
+    _check(res, [a[2] for a in g["accepted"]], g["attempts"],
+           [a[3] for a in g["accepted"]], g["f_final"])
+    h.close()
