@@ -27,7 +27,10 @@
 // independently, giving the Gauss-Jordan panel [-B01 B11^-1; B11^-1;
 // -B21 B11^-1].  Every column outside the panel then gets the rank-kGjNb
 // update M[r,j] = (r pivot of this panel ? 0 : M[r,j]) + P[r,:] B1[:,j] with
-// B1 the panel's pivot rows before the update.  On gfx950 the FP64
+// B1 the panel's pivot rows before the update (the reduction of the panel
+// rows happens inside the update's workgroups, and the new pivot rows wait
+// in a side buffer until the next panel's update, so no workgroup reads a
+// row another one writes).  On gfx950 the FP64
 // matrix-core rate equals the FP64 vector rate (78.6 TFLOP/s), and at this
 // panel width the update is HBM-bound, so it runs on the vector ALUs.
 #include <utility>
@@ -357,86 +360,96 @@ __global__ __launch_bounds__(256) void k_tsel_fused(const z64* Pb, int n, int k0
   tsel_finish(Pb, k0, ncols, &prop[cur][0], pcnt[cur][0], zero, lane, piv, used, B11inv, status);
 }
 
-// Every panel row reduced by B11^-1: pivot rows (used[r]-1 in the panel) get
-// their row of B11^-1, the others -B_r B11^-1.  A workgroup handles 16 rows,
-// one thread per output entry.  Workgroups past the panel rows copy the
-// panel's pivot rows of S into B1 (their values before the update).
-__global__ __launch_bounds__(256) void k_tapply(z64* Pb, int n, int k0, int ncols,
-                                                const int32_t* used, const z64* B11inv,
-                                                const z64* S, int ld, const int32_t* piv,
-                                                z64* B1, int napply) {
-  __shared__ z64 Bi[kGjNb][kGjNb];
-  __shared__ z64 R[256 / kGjNb][kGjNb + 1];
-  const int tid = threadIdx.x;
-  if (int(blockIdx.x) >= napply) {
-    // B1[c, j] = S[piv[k0+c], j]
-    const int e = (blockIdx.x - napply) * 256 + tid;
-    const int c = e / n, j = e % n;
-    if (c < ncols) B1[size_t(c) * ld + j] = S[size_t(piv[k0 + c]) * ld + j];
-    return;
-  }
-  const int rr = tid / kGjNb, cc = tid % kGjNb;
-  const int r = blockIdx.x * (256 / kGjNb) + rr;
-  Bi[rr][cc] = B11inv[tid];
-  R[rr][cc] = (r < n && cc < ncols) ? Pb[size_t(r) * kGjNb + cc] : z64{0.0, 0.0};
-  __syncthreads();
-  if (r >= n) return;
-  const int u = used[r] - 1;
-  z64 out;
-  if (u >= k0 && u < k0 + ncols) {
-    out = Bi[u - k0][cc];
-  } else {
-    z64 acc{0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < kGjNb; ++q) acc = zfma(R[rr][q], Bi[q][cc], acc);
-    out = z64{-acc.re, -acc.im};
-  }
-  Pb[size_t(r) * kGjNb + cc] = (cc < ncols) ? out : z64{0.0, 0.0};
-}
-
-// Rank-ncols update of every column outside the panel; the panel columns get
-// their reduced values back from Pb, and the next panel's columns (updated
-// here) are also gathered into Pn.  A workgroup covers 64 columns x
-// kUpdRows rows; thread (g, c) owns column c and rows g, g+4, ...
+// Rank-ncols update of one panel, with the panel's reduction by B11^-1
+// folded in: each workgroup forms the reduced panel entries Pt of its rows
+// from the gathered panel Pb (pivot rows, used[r]-1 in the panel: their row
+// of B11^-1; every other row r: -B_r B11^-1).  Every workgroup reads the
+// panel's pivot rows of S as they were before the update (b), so their new
+// values go to PRc instead of S; the previous panel's pivot rows, held in
+// PRp, are read from there and written back to S.  Panel columns get Pt; the
+// next panel's columns (updated here) are also gathered into Pn.  A
+// workgroup covers 64 columns x kUpdRows rows; thread (g, c) owns column c
+// and rows g, g+4, ...
 __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0, int ncols,
-                                                   const z64* B1, const int32_t* used,
-                                                   const z64* Pb, z64* Pn) {
+                                                   const int32_t* used, const int32_t* piv,
+                                                   const z64* B11inv, const z64* Pb,
+                                                   const z64* PRp, z64* PRc, z64* Pn) {
+  static_assert(kGjNb * kGjNb == 256, "one B11^-1 entry per thread");
+  __shared__ z64 Bi[kGjNb][kGjNb];
+  __shared__ z64 R[kUpdRows][kGjNb + 1];
   __shared__ z64 Pt[kUpdRows][kGjNb + 1];
-  __shared__ int isp[kUpdRows];
+  // 1 + c: pivot c of this panel; -(1 + c): pivot c of the previous one; 0
+  __shared__ int kind[kUpdRows];
   const int tid = threadIdx.x;
   const int r0 = blockIdx.y * kUpdRows;
+  Bi[tid / kGjNb][tid % kGjNb] = B11inv[tid];
   for (int e = tid; e < kUpdRows * kGjNb; e += 256) {
     const int rr = e / kGjNb, c = e % kGjNb;
     const int r = r0 + rr;
-    Pt[rr][c] = (r < n && c < ncols) ? Pb[size_t(r) * kGjNb + c] : z64{0.0, 0.0};
+    R[rr][c] = (r < n && c < ncols) ? Pb[size_t(r) * kGjNb + c] : z64{0.0, 0.0};
   }
   if (tid < kUpdRows) {
     const int r = r0 + tid;
     const int u = (r < n) ? used[r] - 1 : -1;
-    isp[tid] = (u >= k0 && u < k0 + ncols) ? 1 : 0;
+    int kd = 0;
+    if (u >= k0 && u < k0 + ncols) kd = 1 + (u - k0);
+    else if (u >= 0 && u >= k0 - kGjNb && u < k0) kd = -(1 + u - (k0 - kGjNb));
+    kind[tid] = kd;
+  }
+  __syncthreads();
+  for (int e = tid; e < kUpdRows * kGjNb; e += 256) {
+    const int rr = e / kGjNb, cc = e % kGjNb;
+    z64 out{0.0, 0.0};
+    if (cc < ncols) {
+      if (kind[rr] > 0) {
+        out = Bi[kind[rr] - 1][cc];
+      } else {
+        z64 acc{0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) acc = zfma(R[rr][q], Bi[q][cc], acc);
+        out = z64{-acc.re, -acc.im};
+      }
+    }
+    Pt[rr][cc] = out;
   }
   __syncthreads();
   const int j = blockIdx.x * 64 + (tid & 63);
   const int rg = tid >> 6;
   if (j >= n) return;
   if (j >= k0 && j < k0 + ncols) {
-    for (int rr = rg; rr < kUpdRows && r0 + rr < n; rr += 4)
-      S[size_t(r0 + rr) * ld + j] = Pt[rr][j - k0];
+    for (int rr = rg; rr < kUpdRows && r0 + rr < n; rr += 4) {
+      const int kd = kind[rr];
+      z64* dst = (kd > 0) ? PRc + size_t(kd - 1) * ld + j : S + size_t(r0 + rr) * ld + j;
+      *dst = Pt[rr][j - k0];
+    }
     return;
   }
   const int nxt = k0 + kGjNb;
   const bool in_next = (j >= nxt && j < nxt + kGjNb);
   z64 b[kGjNb];
 #pragma unroll
-  for (int c = 0; c < kGjNb; ++c) b[c] = (c < ncols) ? B1[size_t(c) * ld + j] : z64{0.0, 0.0};
+  for (int c = 0; c < kGjNb; ++c)
+    b[c] = (c < ncols) ? S[size_t(piv[k0 + c]) * ld + j] : z64{0.0, 0.0};
   for (int rr = rg; rr < kUpdRows && r0 + rr < n; rr += 4) {
-    z64* dst = S + size_t(r0 + rr) * ld + j;
-    z64 acc = isp[rr] ? z64{0.0, 0.0} : *dst;
+    const int kd = kind[rr];
+    z64* row = S + size_t(r0 + rr) * ld + j;
+    z64 acc{0.0, 0.0};
+    if (kd < 0) acc = PRp[size_t(-kd - 1) * ld + j];
+    else if (kd == 0) acc = *row;
 #pragma unroll
     for (int c = 0; c < kGjNb; ++c) acc = zfma(Pt[rr][c], b[c], acc);
-    *dst = acc;
+    if (kd > 0) PRc[size_t(kd - 1) * ld + j] = acc;
+    else *row = acc;
     if (in_next) Pn[size_t(r0 + rr) * kGjNb + (j - nxt)] = acc;
   }
+}
+
+// The last panel's pivot rows back from PR into S.
+__global__ __launch_bounds__(256) void k_gj_rows_back(z64* S, int ld, int n, int k0, int ncols,
+                                                      const int32_t* piv, const z64* PR) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (j < n && c < ncols) S[size_t(piv[k0 + c]) * ld + j] = PR[size_t(c) * ld + j];
 }
 
 // inv_p[p_l] = l
@@ -544,7 +557,8 @@ __global__ __launch_bounds__(kRowThreads) void k_output(ProbDev P, int f, const 
 
 // ------------------------------------------------------------------ launchers
 // C^-1 of C = I - k2d G diag(bits) into Cinv.  sidx/zidx/pos describe S and Z
-// (pos[i] = index of i in S, or -1).  S, Pb, Pn, B1 are scratch.
+// (pos[i] = index of i in S, or -1).  S, Pb, Pn are scratch, B1 (2 kGjNb x ld)
+// too.
 hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const int32_t* sidx,
                           const int32_t* zidx, const int32_t* pos, int ns, double k2d, z64* B1,
                           z64* Pb, z64* Pn, int32_t* piv, int32_t* inv_p, int32_t* used,
@@ -558,6 +572,10 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
     int32_t* candA = tsbuf + 64;
     int32_t* candB = candA + g0 * (kGjNb + 1);
     const dim3 gcols((ns + 255) / 256);
+    // pivot rows of the even and odd panels, kept out of S during the
+    // update that makes them
+    z64* PRa = B1;
+    z64* PRb = B1 + size_t(kGjNb) * ld;
     hipLaunchKernelGGL(k_gather_K, dim3(gcols.x, ns), dim3(256), 0, s, S, G, ld, sidx, ns, k2d,
                        used, arrived);
     hipLaunchKernelGGL(k_gj_panel_in, dim3((ns * kGjNb + 255) / 256), dim3(256), 0, s, S, ld, ns,
@@ -594,16 +612,17 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
         hipLaunchKernelGGL(k_tsel_wg, dim3(1), dim3(64 * ((g + 3) / 4)), 0, s, Pb, ns, k0, nc,
                            cand, cnt, g, piv, used, B11inv, status);
       }
-      const int napply = (ns + 15) / 16;
-      const int ncopy = (nc * ns + 255) / 256;
-      hipLaunchKernelGGL(k_tapply, dim3(napply + ncopy), dim3(256), 0, s, Pb, ns, k0, nc, used,
-                         B11inv, S, ld, piv, B1, napply);
+      const bool odd = (k0 / kGjNb) & 1;
       hipLaunchKernelGGL(k_gj_update, dim3((ns + 63) / 64, (ns + kUpdRows - 1) / kUpdRows),
-                         dim3(256), 0, s, S, ld, ns, k0, nc, B1, used, Pb, Pn);
+                         dim3(256), 0, s, S, ld, ns, k0, nc, used, piv, B11inv, Pb,
+                         odd ? PRa : PRb, odd ? PRb : PRa, Pn);
       z64* t = Pb;
       Pb = Pn;
       Pn = t;
     }
+    const int klast = (ns - 1) / kGjNb * kGjNb;
+    hipLaunchKernelGGL(k_gj_rows_back, dim3(gcols.x, ns - klast), dim3(256), 0, s, S, ld, ns,
+                       klast, ns - klast, piv, ((klast / kGjNb) & 1) ? PRb : PRa);
     hipLaunchKernelGGL(k_gj_invperm, dim3(gcols.x), dim3(256), 0, s, piv, inv_p, ns);
   }
   const dim3 grow((nd + 255) / 256, nd);

@@ -267,7 +267,7 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
   }
   for (int f = 0; f < F; ++f) {
     L.off_S[f] = take(mat);
-    L.off_B1[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
+    L.off_B1[f] = take(2 * size_t(pngf::kGjNbHost) * ld * sizeof(z64));
     L.off_Pb[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
     L.off_Pn[f] = take(size_t(pngf::kGjNbHost) * ld * sizeof(z64));
     // tournament: an arrival count, then two proposal lists of (kGjNb + 1)
