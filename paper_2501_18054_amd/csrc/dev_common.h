@@ -42,6 +42,34 @@ __device__ __forceinline__ z64 zfma(z64 a, z64 b, z64 c) {  // a*b + c
 }
 __device__ __forceinline__ double zabs2(z64 a) { return a.re * a.re + a.im * a.im; }
 
+// Broadcast of lane p's value to the wave (p wave-uniform).
+__device__ __forceinline__ double lane_d(double v, int p) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b)), p));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b >> 32)), p));
+  return __longlong_as_double(static_cast<long long>((uint64_t(hi) << 32) | lo));
+}
+
+// Maximum over the wave: DPP exchanges within each row of 16 lanes (quad
+// swaps, then rotations by 4 and 8), then the four row maxima by readlane.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  uint32_t o;
+  o = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = o > v ? o : v;
+  o = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = o > v ? o : v;
+  o = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x124, 0xF, 0xF, false));  // row_ror 4
+  v = o > v ? o : v;
+  o = uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x128, 0xF, 0xF, false));  // row_ror 8
+  v = o > v ? o : v;
+  const uint32_t a = uint32_t(__builtin_amdgcn_readlane(int(v), 0));
+  const uint32_t b = uint32_t(__builtin_amdgcn_readlane(int(v), 16));
+  const uint32_t c = uint32_t(__builtin_amdgcn_readlane(int(v), 32));
+  const uint32_t d = uint32_t(__builtin_amdgcn_readlane(int(v), 48));
+  const uint32_t ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
 // Sum over a full workgroup of kRowThreads lanes; result valid in every lane.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -19,6 +19,7 @@
 //     C_new^-1 = C_ref^-1 + P Cap^-1 Q,   P = C_ref^-1 U,  Q = C_ref^-1[F,:],
 //     Cap = I - Q U = I - P[F,:].
 #include <algorithm>
+#include <utility>
 
 #include "dev_state.h"
 
@@ -274,6 +275,89 @@ __global__ __launch_bounds__(kSmallInvThreads) void k_small_inverse(z64* A, int 
   for (int e = tid; e < k * k; e += kSmallInvThreads) A[e] = M[cur][e / k][cmap[e % k]];
 }
 
+// The same inverse for k <= kWaveInv by one wave, with no row ever moved:
+// column c takes as pivot p_c the row, not yet a pivot, with the largest
+// |a_rc| (compared as the float of |a_rc|^2; the first of equals), and the
+// in-place result M then satisfies A^-1[c][p_l] = M[p_c][l] (Gauss-Jordan on
+// the row-permuted matrix, its rows left where they are).  Lane (r, h) =
+// (lane % 32, lane / 32) holds entries [16h, 16h + 16) of row r in
+// registers.  Per column: the pivot by a wave maximum of (|a|^2, row) keys,
+// the scaled pivot row and every row's factor through LDS (one barrier),
+// then 16 complex updates per lane.  status is set on a zero pivot.
+constexpr int kWaveInv = 32;
+
+struct WaveInvLds {
+  z64 prow[2][kWaveInv];   // scaled pivot row, by column parity
+  z64 fac[2][kWaveInv];    // every row's entry in the pivot column
+  int pv[kWaveInv];        // pivot row of each column
+};
+
+template <int C>
+__device__ __forceinline__ void wave_inv_column(z64 (&w)[16], int k, int r, int h, int lane,
+                                                int& myq, WaveInvLds& sm, int32_t* status) {
+  if (C >= k) return;
+  constexpr int hc = C / 16, cc = C % 16, buf = C & 1;
+  uint32_t key = 0;
+  if (h == hc && r < k && myq < 0)
+    key = (__float_as_uint(float(zabs2(w[cc]))) & ~31u) | uint32_t(31 - r);
+  const int p = 31 - int(wave_max_u32(key) & 31u);
+  const int pl = p + kWaveInv * hc;
+  const z64 apc{lane_d(w[cc].re, pl), lane_d(w[cc].im, pl)};
+  const bool zero = !(zabs2(apc) > 0.0);
+  if (zero && lane == 0) atomicOr(status, 1);
+  const z64 inv = zero ? z64{0.0, 0.0} : zdiv(z64{1.0, 0.0}, apc);
+  if (r == p) {
+    // the pivot row scaled by 1/a_pc, with 1/a_pc in column C
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+      sm.prow[buf][16 * h + jj] = (16 * h + jj == C) ? inv : zmul(w[jj], inv);
+    myq = C;
+  }
+  if (h == hc) sm.fac[buf][r] = w[cc];
+  if (lane == 0) sm.pv[C] = p;
+  __syncthreads();
+  if (r == p) {
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) w[jj] = sm.prow[buf][16 * h + jj];
+  } else {
+    const z64 f = sm.fac[buf][r];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int l = 16 * h + jj;
+      const z64 old = (l == C) ? z64{0.0, 0.0} : w[jj];
+      w[jj] = zsub(old, zmul(f, sm.prow[buf][l]));
+    }
+  }
+}
+
+template <int... Cs>
+__device__ __forceinline__ void wave_inv_columns(z64 (&w)[16], int k, int r, int h, int lane,
+                                                 int& myq, WaveInvLds& sm, int32_t* status,
+                                                 std::integer_sequence<int, Cs...>) {
+  (wave_inv_column<Cs>(w, k, r, h, lane, myq, sm, status), ...);
+}
+
+__global__ __launch_bounds__(64) void k_small_inverse_wave(z64* A, int k, int32_t* status) {
+  __shared__ WaveInvLds sm;
+  const int lane = threadIdx.x;
+  const int r = lane % kWaveInv, h = lane / kWaveInv;
+  z64 w[16];
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) {
+    const int l = 16 * h + jj;
+    w[jj] = (r < k && l < k) ? A[r * k + l] : z64{0.0, 0.0};
+  }
+  int myq = -1;   // the column this lane's row is the pivot of
+  wave_inv_columns(w, k, r, h, lane, myq, sm, status, std::make_integer_sequence<int, kWaveInv>{});
+  __syncthreads();
+  if (r < k && myq >= 0)
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int l = 16 * h + jj;
+      if (l < k) A[myq * k + sm.pv[l]] = w[jj];
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 // C = beta C + alpha A op(B) with the index maps of ix (see GemmIdx).
 // work (>= splits * M * N entries) is used when splits > 1.
@@ -388,7 +472,10 @@ hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, con
 hipError_t launch_small_inverse(z64* A, int k, int32_t* status, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   if (k > kSmallInv) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_small_inverse, dim3(1), dim3(kSmallInvThreads), 0, s, A, k, status);
+  if (k <= kWaveInv)
+    hipLaunchKernelGGL(k_small_inverse_wave, dim3(1), dim3(64), 0, s, A, k, status);
+  else
+    hipLaunchKernelGGL(k_small_inverse, dim3(1), dim3(kSmallInvThreads), 0, s, A, k, status);
   return hipGetLastError();
 }
 
