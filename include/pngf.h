@@ -138,9 +138,9 @@ typedef struct pngf_options {
                         /* inverse of the last refresh (exact to rounding),  */
                         /* or a full re-inversion if > 64 pixels changed.    */
                         /* RFORM: every min(k_refresh, 64) accepts C^-1 is   */
-                        /* refreshed that way and T0, E, R', x re-formed     */
+                        /* re-inverted in FP64 and T0, E, R', x re-formed    */
                         /* from it, which bounds the growth of rounding in   */
-                        /* the panel sums; 0 = never                         */
+                        /* the incremental updates; 0 = never                */
   int32_t k_fold;       /* MIXED: fold the deferred panel into C0^-1 once it */
                         /* holds k_fold terms (0 = only when it is full);    */
                         /* RFORM: panel capacity before a fold into T0       */
@@ -171,15 +171,21 @@ typedef struct pngf_dbs_result {
 const char *pngf_version(void);
 const char *pngf_last_error(const pngf_handle *h);
 
-/* Precompute (host, FP64, timed separately).  Assembles the symmetric FDFD
- * operator with SC-PML, eliminates everything outside the design region with a
- * band LDL^T of the exterior operator (the Schur-complement idea of the
- * paper's augmented partial factorization, Results, Precomputation), and
- * forms per frequency G = -(L^-1)[D,D] (symmetrized), b, G_OD and x_b.
- * G, b, G_OD and x_b depend only on the environment, so they are the same
- * for both pixel kinds.
+/* Precompute (host, FP64, OpenMP; timed separately).  Assembles the
+ * symmetric FDFD operator with SC-PML and the source / output columns,
+ * eliminates everything outside the design region by a nested-dissection
+ * multifrontal Schur complement (the idea of the paper's augmented partial
+ * factorization, Results, Precomputation), and inverts the design-region
+ * Schur complement by nested-dissection-ordered block sweeps, giving per
+ * frequency G = -(L^-1)[D,D] (exactly symmetric), b, G_OD and x_b.  G, b,
+ * G_OD and x_b depend only on the environment, so they are the same for both
+ * pixel kinds.  Frequencies run concurrently.  With objective_kind
+ * PNGF_MEAN_TRANSMISSION each frequency's normalizer is obj_norm[f] (or 1)
+ * times the vacuum transmission |w^T E_vac|^2 of the same source (eps = 1 on
+ * the whole grid), from one more elimination.
  * Errors: PNGF_EINVAL for inconsistent sizes, a mask touching the PML or an
- * unknown pixel_kind, PNGF_ESINGULAR for a zero pivot, PNGF_ENOMEM. */
+ * unknown pixel_kind / objective_kind, PNGF_ESINGULAR for a singular pivot
+ * block, PNGF_ENUMERIC for a zero vacuum transmission, PNGF_ENOMEM. */
 int pngf_precompute(const pngf_problem *p, pngf_handle **out);
 
 /* Copies of the precomputed quantities of frequency fi (host arrays supplied
@@ -187,6 +193,12 @@ int pngf_precompute(const pngf_problem *p, pngf_handle **out);
  * b cplx[n_d], god cplx[n_d], xb cplx[1]. */
 int pngf_get_precompute(pngf_handle *h, int32_t fi, double *G, double *b,
                         double *god, double *xb);
+
+/* Objective normalizer norm_f of frequency fi (the objective is the mean
+ * over frequencies of |x_f|^2 / norm_f): obj_norm[fi] (or 1), times the
+ * vacuum transmission for PNGF_MEAN_TRANSMISSION.  Errors: PNGF_EINVAL for a
+ * NULL handle / pointer or fi out of range. */
+int pngf_objective_norm(pngf_handle *h, int32_t fi, double *norm);
 
 /* Number of design pixels / frequencies of the handle. */
 int pngf_sizes(pngf_handle *h, int32_t *n_d, int32_t *nfreq);

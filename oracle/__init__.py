@@ -28,13 +28,14 @@ closed forms, exact discrete identities, reciprocity and brute force
 (see each function's docstring for which pin covers it).
 """
 from .fdfd import (pml_profile, stretch, assemble, rhs, solve, Solver,
-                   objective, field, metal_nodes, pec_system, total_operator)
+                   objective, objective_norms, field, metal_nodes, pec_system,
+                   total_operator)
 from .green import (green_dd, green_od, output_row, background, pngf_state,
                     equivalent_current, pec_state)
 from .dbs import dbs, score_all, DBSResult
 from .gradient import gradient
 
 __all__ = ["pml_profile", "stretch", "assemble", "rhs", "solve", "Solver",
-           "objective", "field", "metal_nodes", "pec_system", "total_operator", "green_dd", "green_od", "output_row", "background", "pngf_state", "equivalent_current",
+           "objective", "objective_norms", "field", "metal_nodes", "pec_system", "total_operator", "green_dd", "green_od", "output_row", "background", "pngf_state", "equivalent_current",
            "pec_state", "dbs",
            "score_all", "DBSResult", "gradient"]

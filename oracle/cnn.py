@@ -140,17 +140,19 @@ def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 def features(prob, bits):
     """The seven input channels [7, n_d] of the design ``bits`` (FP64)."""
     from .green import green_dd, output_row, pngf_state
+    from .fdfd import objective_norms
     bits = np.asarray(bits, dtype=np.uint8)
     F = prob.nfreq
     delta = np.where(bits != 0, -1.0, 1.0) * (prob.eps_hi - prob.eps_lo)
     xs, f, df = [], 0.0, np.zeros(prob.n_d)
     E0 = R0 = None
+    norms = objective_norms(prob)
     for fi in range(F):
         E, x = pngf_state(prob, bits, fi)
         R = output_row(prob, bits, fi)
         if fi == 0:
             E0, R0 = E, R
-        c = 1.0 / (F * prob.obj_norm[fi])
+        c = 1.0 / (F * norms[fi])
         dx = prob.k0[fi] ** 2 * delta * E * R
         f += c * abs(x) ** 2
         df += c * (np.abs(x + dx) ** 2 - abs(x) ** 2)

@@ -127,11 +127,13 @@ def score_all(prob, bits, cands=None, workers=1, tiles=None):
 
 
 def dbs(prob, bits0=None, perms=None, eta=ETA, workers=1, tie_band=1e-7,
-        progress=None, tiles=None):
+        progress=None, tiles=None, max_accepts=None):
     """Run DBS on ``prob``; returns a DBSResult.  With ``tiles`` ((n_tiles, M)
     pixel ids, -1 padded) a candidate is a tile whose pixels all flip
     together (a rank-M update in the paper's terms, eq. lru_dcn), ``perms``
-    order the tiles and the accepted entries name tiles."""
+    order the tiles and the accepted entries name tiles.  With
+    ``max_accepts`` the search stops right after that many accepted flips
+    (attempts counted up to and including the last accepted one)."""
     bits = np.array(prob.init_bits if bits0 is None else bits0, dtype=np.uint8)
     perms = prob.perms if perms is None else np.asarray(perms)
     ops = _base_ops(prob)
@@ -178,6 +180,10 @@ def dbs(prob, bits0=None, perms=None, eta=ETA, workers=1, tie_band=1e-7,
                 pos = q + 1
                 if progress is not None:
                     progress(res)
+                if max_accepts is not None and len(res.accepted) >= max_accepts:
+                    break
+            if max_accepts is not None and len(res.accepted) >= max_accepts:
+                break
             if not any_acc:
                 res.converged = True
                 break

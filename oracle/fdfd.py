@@ -187,12 +187,42 @@ def field(prob, bits, fi, refine=1):
     return Solver(L, scale).solve(b, refine)
 
 
+MEAN_TRANSMISSION = 2
+
+
+def objective_norms(prob):
+    """Per-frequency normalizers norm_f of the objective.
+
+    ``obj_norm`` as given; for the mean-transmission objective each is further
+    multiplied by the vacuum transmission |w^T E_vac,f|^2, where E_vac,f is the
+    field of the same source on the same grid and PML with eps = 1 everywhere
+    (no static features, no design).  This reads the paper's per-frequency
+    transmission objectives (Supplementary Notes, Objective functions for
+    design studies: a transmission coefficient per frequency, combined by a
+    mean) as power transmitted relative to empty space.  Computed once per
+    problem object and kept on it."""
+    base = np.asarray(prob.obj_norm, dtype=np.float64)
+    if int(prob.objective_kind) != MEAN_TRANSMISSION:
+        return base
+    cached = prob.__dict__.get("_oracle_vacuum_norms")
+    if cached is None:
+        one = np.ones((prob.ny, prob.nx))
+        t = np.empty(prob.nfreq)
+        for fi in range(prob.nfreq):
+            E = solve(prob.nx, prob.ny, prob.npml, prob.h, one, prob.k0[fi], prob.src[fi])
+            t[fi] = abs(prob.w[0] @ E) ** 2
+        cached = t
+        prob.__dict__["_oracle_vacuum_norms"] = cached
+    return base * cached
+
+
 def objective(prob, xs):
     """f = mean over frequencies of |x_f|^2 / norm_f (x_f = w^T E_f, N_obj=1).
 
     Covers the point intensity |Ez|^2, the Gaussian-overlap intensity
-    |sum_y w(y) Ez(x_out, y)|^2 (no conjugate, no h factor) and the normalized
-    mean transmission; all three are to be maximized.
+    |sum_y w(y) Ez(x_out, y)|^2 (no conjugate, no h factor) and the mean
+    transmission normalized by vacuum (``objective_norms``); all three are to
+    be maximized.
     """
     xs = np.asarray(xs, dtype=np.complex128).reshape(prob.nfreq, -1)
-    return float(np.mean(np.abs(xs[:, 0]) ** 2 / prob.obj_norm))
+    return float(np.mean(np.abs(xs[:, 0]) ** 2 / objective_norms(prob)))

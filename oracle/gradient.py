@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .fdfd import Solver, assemble, rhs, total_eps
+from .fdfd import Solver, assemble, rhs, total_eps, objective_norms
 
 
 def gradient(prob, bits):
@@ -36,6 +36,7 @@ def gradient(prob, bits):
     idx = prob.design_indices()
     g = np.zeros(prob.n_d)
     w = prob.w[0].astype(np.complex128)
+    norms = objective_norms(prob)
     for fi in range(prob.nfreq):
         k0 = prob.k0[fi]
         L, scale = assemble(prob.nx, prob.ny, prob.npml, prob.h, eps, k0)
@@ -47,5 +48,5 @@ def gradient(prob, bits):
         y = y + S.lu.solve(w - S.A.T @ y, trans="T")
         adj = (y * scale)[idx]
         dx = -k0 * k0 * adj * E[idx]
-        g += 2.0 * np.real(np.conj(x) * dx) / (prob.nfreq * prob.obj_norm[fi])
+        g += 2.0 * np.real(np.conj(x) * dx) / (prob.nfreq * norms[fi])
     return g

@@ -72,6 +72,7 @@ EXPORTS = {
     "pngf_precompute": ([C.POINTER(Problem), C.POINTER(C.c_void_p)], C.c_int),
     "pngf_get_precompute": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p], C.c_int),
+    "pngf_objective_norm": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "pngf_sizes": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "pngf_precompute_seconds": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "pngf_workspace_bytes": ([C.c_void_p, C.POINTER(Options), C.POINTER(C.c_size_t)], C.c_int),
@@ -233,6 +234,11 @@ class Handle:
         xb = np.empty(1, np.complex128)
         self._check(lib().pngf_get_precompute(self._h, fi, _ptr(G), _ptr(b), _ptr(god), _ptr(xb)))
         return G, b, god, complex(xb[0])
+
+    def objective_norm(self, fi=0):
+        v = C.c_double()
+        self._check(lib().pngf_objective_norm(self._h, fi, C.byref(v)))
+        return v.value
 
     # --------------------------------------------------------------- device
     def workspace_bytes(self, opts):

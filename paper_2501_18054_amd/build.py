@@ -20,7 +20,9 @@ def build(verbose=False):
         path = os.path.join(CSRC, src)
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        # host C++ (the precompute): AVX2 + FMA, present on every x86-64 host
+        # of these GPUs; its GEMM kernel is written with those intrinsics
+        lang = ["-x", "hip"] if src.endswith(".hip") else ["-mavx2", "-mfma"]
         cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-fopenmp",
                "--offload-arch=gfx950",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1047,10 +1047,14 @@ int run_rform(pngf_handle* h, pngf::DbsState* pinned) {
     t += batch;
     if (pinned->done) return PNGF_OK;
     if (pinned->need_refresh && h->P.k_refresh > 0 && pinned->n_since >= h->P.k_refresh) {
-      // re-anchor: C^-1 for the current design by an FP64 block-Woodbury
-      // update, E, R' and x re-formed from it, T0 rebuilt, every candidate
-      // rescored from C^-1 (the panel's rank-1 terms are dropped)
-      st = fp64_refresh(h);
+      // re-anchor: C^-1 for the current design by a full FP64 re-inversion,
+      // E, R' and x re-formed from it, T0 rebuilt, every candidate rescored
+      // from C^-1 (the panel's rank-1 terms are dropped).  Not a block-
+      // Woodbury update of the previous anchor's C^-1: T0 = C^-1 G inherits
+      // C^-1's error directly, and chained Woodbury updates through an
+      // ill-conditioned capacitance matrix (conducting pixels) leave C^-1
+      // at ~1e-10 instead of ~1e-13.
+      st = device_reinvert(h);
       if (st) return st;
       st = capture_ref_bits(h);
       if (st) return st;
@@ -1223,6 +1227,13 @@ int pngf_get_precompute(pngf_handle* h, int32_t fi, double* G, double* b, double
   if (b) std::memcpy(b, F.b.data(), nd * sizeof(cd));
   if (god) std::memcpy(god, F.god.data(), nd * sizeof(cd));
   if (xb) std::memcpy(xb, &F.xb, sizeof(cd));
+  return PNGF_OK;
+}
+
+int pngf_objective_norm(pngf_handle* h, int32_t fi, double* norm) {
+  if (!h || !norm) return PNGF_EINVAL;
+  if (fi < 0 || fi >= int(h->pc.freq.size())) return fail(h, PNGF_EINVAL, "frequency index out of range");
+  *norm = h->pc.freq[fi].norm;
   return PNGF_OK;
 }
 

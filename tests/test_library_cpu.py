@@ -126,3 +126,22 @@ def test_precompute_pec_pixels():
     with pytest.raises(P.PngfError) as e:
         P.Handle(p)
     assert e.value.code == -1
+
+
+def test_objective_norm_matches_oracle():
+    """Mean-transmission normalizers (vacuum transmission per frequency) from
+    the library's own elimination against the oracle's sparse vacuum solves;
+    other objectives keep obj_norm."""
+    p = workloads.config4_scaled()
+    h = P.Handle(p)
+    want = oracle.objective_norms(p)
+    for fi in range(p.nfreq):
+        assert abs(h.objective_norm(fi) - want[fi]) < 1e-11 * want[fi]
+    h.close()
+    p = workloads.tiny(seed=4, n=16, npml=3, side=2, nfreq=2)
+    p.obj_norm = np.array([2.0, 0.5])
+    h = P.Handle(p)
+    assert [h.objective_norm(0), h.objective_norm(1)] == [2.0, 0.5]
+    with pytest.raises(P.PngfError):
+        h.objective_norm(2)
+    h.close()

@@ -155,3 +155,45 @@ def test_orderings_agree():
     E1 = fd.Solver(L, s, "COLAMD").solve(b)
     E2 = fd.Solver(L, s, "NATURAL").solve(b)
     assert np.max(np.abs(E1 - E2)) < 1e-13 * np.max(np.abs(E1))
+
+
+def _transmission_problem(seed=3, static=False):
+    p = workloads.tiny(seed=seed, n=28, npml=5, side=4, nfreq=2, static_block=static)
+    p.objective_kind = workloads.MEAN_TRANSMISSION
+    return p
+
+
+def test_vacuum_normalizer_unity_for_empty_vacuum_design():
+    """With no static feature and every pixel at eps_lo (= 1) the device is
+    vacuum, so every frequency transmits exactly its normalizer: f = 1."""
+    from oracle.dbs import _base_ops, _eval_bits
+    p = _transmission_problem()
+    assert np.all(p.eps_static == 1.0) and p.eps_lo == 1.0
+    f, xs = _eval_bits(p, _base_ops(p), np.zeros(p.n_d, np.uint8))
+    assert abs(f - 1.0) < 1e-12
+    # and a dielectric design changes it
+    f2, _ = _eval_bits(p, _base_ops(p), np.ones(p.n_d, np.uint8))
+    assert abs(f2 - 1.0) > 1e-3
+
+
+def test_vacuum_normalizer_scale_invariance():
+    """The normalized transmission does not depend on the source or output
+    amplitude (both enter numerator and normalizer), unlike the plain
+    intensity, which scales by |c J|^2 |c_w|^2."""
+    from oracle.dbs import _base_ops, _eval_bits
+    p = _transmission_problem(static=True)
+    bits = (np.arange(p.n_d) % 3 == 0).astype(np.uint8)
+    f0, _ = _eval_bits(p, _base_ops(p), bits)
+    q = _transmission_problem(static=True)
+    q.src = q.src * (0.3 - 2.0j)
+    q.w = q.w * (1.7 + 0.4j)
+    f1, _ = _eval_bits(q, _base_ops(q), bits)
+    assert abs(f1 - f0) < 1e-12 * abs(f0)
+    r = _transmission_problem(static=True)
+    r.objective_kind = workloads.POINT_INTENSITY
+    r2 = _transmission_problem(static=True)
+    r2.objective_kind = workloads.POINT_INTENSITY
+    r2.src = r2.src * (0.3 - 2.0j)
+    fa, _ = _eval_bits(r, _base_ops(r), bits)
+    fb, _ = _eval_bits(r2, _base_ops(r2), bits)
+    assert abs(fb / fa - abs(0.3 - 2.0j) ** 2) < 1e-12
