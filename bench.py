@@ -47,6 +47,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 KERNELS = ("score", "select", "accept", "lu", "other", "fold", "mixed_q", "wood")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mixed_persist_n1600_traffic.json")
+C4_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mixed_step_n6400_f8_traffic.json")
 STEP_SOURCE = os.path.join(ROOT, "paper_2501_18054_amd", "csrc", "step_kernels.hip")
 
 
@@ -71,6 +72,100 @@ def cpu_baseline(prob):
     return {"value": n / dt, "unit": "flip evals/s", "cores": workers, "kind": "oracle",
             "sample": f"{n} candidate flips of the initial design, each a full sparse "
                       f"LU re-solve of the {prob.nx}x{prob.ny} FDFD system; {dt:.1f} s wall"}
+
+
+def oracle_candidate_seconds(prob, n_cand, workers):
+    """Wall seconds of the oracle per candidate flip of prob at its initial
+    design (every frequency a full sparse LU re-solve), from n_cand sampled
+    candidates scored by a pool of `workers` processes: the extrapolation base
+    for workloads whose oracle search would take hours."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(7)
+    cands = np.sort(rng.choice(prob.n_d, n_cand, replace=False))
+    t0 = time.perf_counter()
+    oracle.score_all(prob, prob.init_bits, cands, workers=workers)
+    return (time.perf_counter() - t0) / n_cand
+
+
+def _one_candidate(args):
+    """Oracle seconds for one candidate flip of one problem (pool task)."""
+    import numpy as np
+    import oracle
+    prob, cand = args
+    t0 = time.perf_counter()
+    oracle.score_all(prob, prob.init_bits, np.array([cand]), workers=1)
+    return time.perf_counter() - t0
+
+
+def oracle_batch_seconds(probs, workers):
+    """Oracle seconds of one candidate flip of each problem (every frequency a
+    full sparse re-solve), the problems spread over a process pool."""
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_one_candidate, [(p, p.n_d // 2) for p in probs], chunksize=1)
+
+
+def cpu_pform_baseline(prob, G, b, god, xb, norm, budget_s=12.0):
+    """FP64 PNGF on the host cores (numpy / OpenBLAS), the class of the
+    paper's own CPU implementation: C^-1 of the initial design by LAPACK, then
+    direct binary search in visiting order, each attempted flip scored in
+    O(N_d) from the current C^-1 (eq. lru_eobj_rs: tau_m = (C^-1 G)[m,m] from
+    row m of C^-1 and of G, by reciprocity), each accept a Sherman-Morrison
+    rank-1 update of C^-1 (eq. lru_woodbury) and of E and R'.  Candidates
+    are scored 64 at a time in visiting order (the first improving one wins,
+    the rest of its block is discarded and not counted).  Runs the first
+    sweeps of the trajectory until budget_s; returns evaluations per second
+    and the accepted pixels (to check against the GPU's)."""
+    import numpy as np
+    nd = G.shape[0]
+    k2d = prob.k0[0] ** 2 * (prob.eps_hi - prob.eps_lo)
+    bits = prob.init_bits.astype(np.uint8).copy()
+    t0 = time.perf_counter()
+    d = k2d * bits
+    C = np.eye(nd, dtype=np.complex128) - G * d[None, :]
+    Ci = np.linalg.inv(C)
+    E = Ci @ b
+    R = god + k2d * (Ci @ (G @ (bits * god)))
+    x = xb + np.sum(god * d * E)
+    f = abs(x) ** 2 / norm
+    t_inv = time.perf_counter() - t0
+    acc, evals = [], 0
+    t1 = time.perf_counter()
+    eta = 1e-9
+    for s in range(prob.perms.shape[0]):
+        pos = 0
+        while pos < nd and time.perf_counter() - t1 < budget_s:
+            blk = prob.perms[s, pos:pos + 64]
+            delta = np.where(bits[blk] != 0, -1.0, 1.0) * k2d
+            tau = np.einsum("ij,ij->i", Ci[blk], G[blk])
+            dx = delta * E[blk] * R[blk] / (1.0 - delta * tau)
+            fn = np.abs(x + dx) ** 2 / norm
+            ok = np.flatnonzero(fn - f > eta * f)
+            if ok.size == 0:
+                evals += blk.size
+                pos += blk.size
+                continue
+            j = int(ok[0])
+            evals += j + 1
+            m = int(blk[j])
+            a = delta[j] / (1.0 - delta[j] * tau[j])
+            p = Ci @ G[m]
+            q = Ci[m].copy()
+            Ci += a * np.outer(p, q)
+            Em, Rm = E[m], R[m]
+            E += a * Em * p
+            R += a * Rm * p
+            x += a * Em * Rm
+            f = abs(x) ** 2 / norm
+            bits[m] ^= 1
+            acc.append(m)
+            pos += j + 1
+        if time.perf_counter() - t1 >= budget_s:
+            break
+    dt = time.perf_counter() - t1
+    return {"value": evals / dt, "unit": "flip evals/s", "evals": evals, "accepts": len(acc),
+            "seconds": dt, "initial_inverse_s": t_inv}, acc
 
 
 def run_form(h, prob, opts, steps, warmup, name):
@@ -149,13 +244,14 @@ def kernel_table(kt, nd, ns, form, accepts):
 HEAD_STEP_KERNEL = "k_mixed_persist"
 
 
-def traffic_for(kernel_name):
-    """Counter-measured HBM bytes per unit of work of the headline step kernel from
-    the committed rocprofv3 summary, or None if it was taken from another
-    version of the kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_for(kernel_name, path=None):
+    """Counter-measured HBM bytes per unit of work of a step kernel from the
+    committed rocprofv3 summary, or None if it was taken from another version
+    of the kernel source."""
+    path = path or TRAFFIC_FILE
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         t = json.load(fh)
     with open(STEP_SOURCE, "rb") as fh:
         digest = hashlib.sha256(fh.read()).hexdigest()
@@ -246,6 +342,84 @@ def broadband_form(P, steps, warmup):
     return out
 
 
+# the mixed step kernel of the eight-frequency N_d = 6400 workload (one launch
+# per step; every launch streams the complex-FP32 C0^-1 of all frequencies)
+C4_STEP_KERNEL = "k_mixed_step"
+
+
+def config4_form(P):
+    """Workload 4 at full size: 640x640 grid, 80x80 design (N_d = 6400),
+    eight frequencies, vacuum-normalized mean transmission.  Each form runs
+    the search from the same start design until a whole sweep keeps nothing
+    or 20 sweeps; plain FP64 once, the mixed form (FP64 refresh every 32
+    accepts) and the R-form twice; then one mixed run with events around
+    every kernel class for the roofline of its step kernel."""
+    import torch
+    import workloads
+    p = workloads.config4()
+    t0 = time.perf_counter()
+    hb = P.Handle(p)
+    out = {"n_d": hb.n_d, "frequencies": p.nfreq, "precompute_s": hb.precompute_seconds(),
+           "precompute_wall_s": time.perf_counter() - t0}
+    seqs = {}
+    for name, kw, reps in (("mixed", dict(precision=P.PNGF_MIXED, k_refresh=32), 2),
+                           ("rform", dict(precision=P.PNGF_RFORM), 2),
+                           ("plain", {}, 1)):
+        opts = P.default_options(max_accepts=16384, max_sweeps=20, timing_steps=True, **kw)
+        hb.bind(opts)
+        hb.set_design(p.init_bits)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hb.set_design(p.init_bits)
+        torch.cuda.synchronize()
+        t_inv = time.perf_counter() - t0
+        res = []
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            hb.set_design(p.init_bits)
+            res.append(hb.dbs_run(p.perms))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        r = res[-1]
+        out[name] = {"time_to_design_ms": 1e3 * dt, "flip_evals_per_s": r["attempts"] / dt,
+                     "accepts": r["n_accepted"], "attempts": r["attempts"],
+                     "sweeps": r["sweeps"], "converged": r["converged"],
+                     "refreshes": r["n_refresh"], "band_decisions": r["n_verified"],
+                     "f_initial": r["f_initial"], "f_final": r["f_final"],
+                     "initial_inverse_ms": 1e3 * t_inv, "timed_runs": reps}
+        seqs[name] = r["accepted"]
+        log(f"config4 {name}: {r['n_accepted']} accepts, {r['attempts']} attempts, "
+            f"{r['sweeps']} sweeps, {1e3 * dt:.0f} ms per design")
+    out["same_sequence"] = bool(seqs["plain"].tolist() == seqs["mixed"].tolist() ==
+                                seqs["rform"].tolist())
+    fp = out["plain"]["f_final"]
+    out["objective_rel_err_mixed_vs_plain"] = abs(out["mixed"]["f_final"] - fp) / fp
+    out["objective_rel_err_rform_vs_plain"] = abs(out["rform"]["f_final"] - fp) / fp
+    # per-class times of one mixed run (events on every launch)
+    hb.bind(P.default_options(precision=P.PNGF_MIXED, k_refresh=32, max_accepts=16384,
+                              max_sweeps=20, timing=True))
+    hb.set_design(p.init_bits)
+    r = hb.dbs_run(p.perms)
+    nd, F = hb.n_d, p.nfreq
+    kt = {k: hb.kernel_times(k) for k in KERNELS}
+    ks = {k: {"launches": n, "total_ms": tms, "avg_us": 1e3 * tms / n}
+          for k, (tms, n) in kt.items() if n}
+    out["mixed"]["kernels"] = ks
+    # the step kernel: every launch that accepts streams C0^-1 of every
+    # frequency once (F N_d^2 8 B); launches are counted per accepted flip
+    tms, n = kt["accept"]
+    if n:
+        per = tms / n * 1e-3
+        achieved = F * nd * nd * 8.0 / per / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": traffic_for(C4_STEP_KERNEL, C4_TRAFFIC_FILE),
+                           "kernel": C4_STEP_KERNEL, "avg_us": 1e6 * per,
+                           "per": "accepted flip", "bytes_per_unit": F * nd * nd * 8.0}
+    hb.close()
+    return out
+
+
 def learned_form(P, h, prob, steps, k=4):
     """Train the proposal network on other seeds of the same family (not
     timed), then time the ranked exact search on this workload."""
@@ -286,14 +460,12 @@ def learned_form(P, h, prob, steps, k=4):
             "f_final": r["f_final"], "train_s": t_train, "train_states": len(X)}
 
 
-def batch_form(P, steps, seeds=range(1000, 1024)):
-    """Half of the batching workload (24 problems, uneven N_d 256-3136, 1-4
+def batch_form(P, steps, probs):
+    """The batching workload (48 problems, uneven N_d 256-3136, 1-4
     frequencies, mixed form): one launch per step over all of them (hipGraph
     replays, autotuned launch shape) against the same problems run one after
     the other.  Both include each problem's FP64 initial inverse."""
     import torch
-    import workloads
-    probs = [workloads.config2_problem(s) for s in seeds]
     stream = torch.cuda.Stream()
     opts = P.default_options(precision=P.PNGF_MIXED, k_refresh=32, max_accepts=8192,
                              max_sweeps=20)
@@ -325,6 +497,7 @@ def batch_form(P, steps, seeds=range(1000, 1024)):
     att = sum(r["attempts"] for r in rb)
     same = all(x["accepted"].tolist() == y["accepted"].tolist() for x, y in zip(rb, rs))
     out = {"problems": len(probs), "n_d": [h.n_d for h in hs],
+           "attempts_per_problem": [int(r["attempts"]) for r in rb],
            "frequencies": [p.nfreq for p in probs], "attempts": att,
            "batched_ms": 1e3 * t_b, "solo_ms": 1e3 * t_solo,
            "batched_flip_evals_per_s": att / t_b, "solo_flip_evals_per_s": att / t_solo,
@@ -344,6 +517,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-config4", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: this build measures one GPU only (the hot path runs on one "
@@ -352,12 +526,22 @@ def main():
 
     import workloads
     prob = workloads.config1()
+    probs2 = [workloads.config2_problem(s) for s in range(1000, 1048)]
     cpu = None
+    extra_cpu = {}
+    workers = max(1, min(len(os.sched_getaffinity(0)), 16))
     if not a.no_cpu_baseline:
-        # before any GPU initialization: the oracle's process pool forks
+        # before any GPU initialization: the oracle's process pools fork
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(prob)
         log(f"cpu baseline: {cpu['value']:.3f} flip evals/s on {cpu['cores']} cores")
+        if not a.no_config4:
+            log("oracle per-candidate time, workload 4 ...")
+            c4 = workloads.config4()
+            extra_cpu["oracle_config4_candidate_s"] = oracle_candidate_seconds(c4, workers,
+                                                                               workers)
+        log("oracle per-candidate time, batching workload ...")
+        extra_cpu["oracle_config2_candidate_s"] = oracle_batch_seconds(probs2, workers)
 
     import torch  # noqa: F401
     import paper_2501_18054_amd as P
@@ -366,6 +550,24 @@ def main():
     h = P.Handle(prob)
     t_pre = time.perf_counter() - t0
     log(f"precompute done in {t_pre:.2f} s")
+    if not a.no_cpu_baseline:
+        log("cpu baseline (FP64 P-form PNGF, numpy) ...")
+        G, b, god, xb = h.get_precompute(0)
+        pf, pf_acc = cpu_pform_baseline(prob, G, b, god, xb, h.objective_norm(0))
+        del G
+        try:
+            import threadpoolctl
+            pf["cores"] = max(i["num_threads"] for i in threadpoolctl.threadpool_info())
+        except Exception:
+            pf["cores"] = len(os.sched_getaffinity(0))
+        pf["kind"] = "cpu-pngf"
+        pf["sample"] = (f"FP64 P-form PNGF (numpy/OpenBLAS) on the 256x256 workload: the "
+                        f"first {pf['evals']} attempted flips ({pf['accepts']} accepts) of "
+                        f"the search in {pf['seconds']:.1f} s, after a {pf['initial_inverse_s']:.2f} s "
+                        f"LAPACK initial inverse")
+        extra_cpu["pform_config1"] = pf
+        extra_cpu["_pform_accepted"] = pf_acc
+        log(f"cpu P-form: {pf['value']:.0f} flip evals/s on {pf['cores']} threads")
     nd = h.n_d
     ns = int(prob.init_bits.sum())
     forms = {}
@@ -389,6 +591,9 @@ def main():
         forms[name] = s
     forms["tiles"] = tile_form(P, h, a.steps, a.warmup)
     forms["broadband"] = broadband_form(P, a.steps, a.warmup)
+    if not a.no_config4:
+        log("workload 4 (640x640, N_d 6400, 8 frequencies) ...")
+        forms["config4"] = config4_form(P)
     ref = forms["plain"]
     for name in ("mixed", "mixed_drift", "rform"):
         f = forms[name]
@@ -397,7 +602,7 @@ def main():
         f["objective_rel_err_vs_plain"] = abs(f["f_final"] - ref["f_final"]) / ref["f_final"]
     if not a.no_batch:
         log("batch ...")
-        forms["batch"] = batch_form(P, 1)
+        forms["batch"] = batch_form(P, 1, probs2)
         log(f"batch: {forms['batch']['batched_ms']:.1f} ms batched vs "
             f"{forms['batch']['solo_ms']:.1f} ms one after the other")
     if not a.no_learned:
@@ -439,6 +644,35 @@ def main():
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu
+        more = {}
+        if "pform_config1" in extra_cpu:
+            pf = dict(extra_cpu["pform_config1"])
+            acc = extra_cpu["_pform_accepted"]
+            gpu_acc = seqs["plain"].tolist()
+            pf["same_accepts_as_gpu"] = bool(acc == gpu_acc[:len(acc)])
+            more["pform_config1"] = pf
+        if "oracle_config4_candidate_s" in extra_cpu and "config4" in forms:
+            tc = extra_cpu["oracle_config4_candidate_s"]
+            c4 = forms["config4"]
+            more["oracle_config4_extrapolated"] = {
+                "kind": "oracle", "cores": workers, "candidate_s": tc,
+                "sample": f"{workers} candidate flips of workload 4's initial design in a "
+                          f"pool of {workers} processes, each eight sparse LU re-solves of "
+                          f"the 409,600-node system; extrapolated to the searches' attempts",
+                "plain_search_s": tc * c4["plain"]["attempts"],
+                "flip_evals_per_s": 1.0 / tc}
+        if "oracle_config2_candidate_s" in extra_cpu and "batch" in forms:
+            ts = extra_cpu["oracle_config2_candidate_s"]
+            bt = forms["batch"]
+            att = bt["attempts_per_problem"]
+            more["oracle_config2_extrapolated"] = {
+                "kind": "oracle", "cores": workers,
+                "sample": "one candidate flip of each of the 48 problems (all its "
+                          "frequencies re-solved), the problems over a process pool; "
+                          "extrapolated to each problem's attempts in the batched run",
+                "search_s": float(sum(t * n for t, n in zip(ts, att))),
+                "serial_candidate_s_total": float(sum(ts))}
+        out["cpu_baselines"] = more
     h.close()
     print(json.dumps(out))
 

@@ -14,8 +14,9 @@
 // (16x16x16): lane l holds A[l%16][4(l/16)+v] and B[4(l/16)+v][l%16], v < 4;
 // accumulator register r holds D[4(l/16)+r][l%16].  The data gradient is the
 // same convolution with the flipped, transposed weights; the weight gradient
-// is a GEMM over pixels (M = output channel, N = K, K = pixels) with FP32
-// atomics across pixel chunks.
+// is a GEMM over pixels (M = output channel, N = K, K = pixels): each chunk of
+// pixels writes its partial tile, and a second pass adds the chunks in a fixed
+// order, so training is bit-for-bit reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -99,11 +100,13 @@ __global__ __launch_bounds__(256) void k_conv(const float* X, int Cin, int relu_
   }
 }
 
-// dW[o][k] += sum over a chunk of pixels of dZ[n,o,p] * in(n, k, p), k =
-// (c, ky, kx), in = relu(X) if relu_in; db[o] += sum dZ[n,o,p] (k-tile 0).
+// Partial weight / bias gradients of one chunk of pixels pc:
+//   part[pc][o*K + k] = sum over the chunk of dZ[n,o,p] * in(n, k, p),
+//   part[pc][Cout*K + o] = sum over the chunk of dZ[n,o,p]   (k-tile 0),
+// k = (c, ky, kx), in = relu(X) if relu_in.  Every entry is written once.
 __global__ __launch_bounds__(256) void k_wgrad(const float* dZ, const float* X, int Cin,
                                                int relu_in, int Cout, int N, int H, int W,
-                                               float* dW, int Kpad, float* db, int chunk) {
+                                               float* part, int Kpad, int chunk) {
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int ot = pad16(Cout) / 16, kt = Kpad / 16;
@@ -147,11 +150,12 @@ __global__ __launch_bounds__(256) void k_wgrad(const float* dZ, const float* X, 
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
   }
   // D[i][j] = dW[o0 + i][k0 + j], i = 4(l/16)+r, j = l%16
+  float* pp = part + size_t(pc) * (size_t(Cout) * K + Cout);
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     const int oi = ob * 16 + 4 * (lane >> 4) + rr;
     const int kj = kb * 16 + (lane & 15);
-    if (oi < Cout && kj < K) atomicAdd(&dW[size_t(oi) * K + kj], acc[rr]);
+    if (oi < Cout && kj < K) pp[size_t(oi) * K + kj] = acc[rr];
   }
   // bias gradient (FP32), once per (output tile, chunk): lanes of the first
   // k-tile sum their output channel over the chunk
@@ -160,11 +164,22 @@ __global__ __launch_bounds__(256) void k_wgrad(const float* dZ, const float* X, 
       const int x = p % W, yy0 = (p / W) % H, n = p / (W * H);
       bsum += dZ[((size_t(n) * Cout + o) * H + yy0) * W + x];
     }
-    atomicAdd(&db[o], bsum);
+    pp[size_t(Cout) * K + o] = bsum;
   }
 }
 
-// dY = clip(Y - T, -1, 1) / count (Huber, delta 1) and the loss sum.
+// g[e] = sum over chunks pc = 0, 1, ... of part[pc][e], in that order
+// (e < n = Cout*K + Cout: the layer's weights, then its biases).
+__global__ __launch_bounds__(256) void k_wsum(const float* part, int n, int nchunk, float* g) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  float s = 0.f;
+  for (int pc = 0; pc < nchunk; ++pc) s += part[size_t(pc) * n + e];
+  g[e] = s;
+}
+
+// dY = clip(Y - T, -1, 1) / count (Huber, delta 1) and the loss sum of
+// each workgroup in loss[blockIdx.x] (added in order by the host).
 __global__ __launch_bounds__(256) void k_huber(const float* Y, const float* T, float* dY, int n,
                                                float inv_count, double* loss) {
   __shared__ double red[4];
@@ -180,7 +195,7 @@ __global__ __launch_bounds__(256) void k_huber(const float* Y, const float* T, f
   for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(loss, red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) loss[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Adam on the flat FP32 parameters (Kingma & Ba).
@@ -309,6 +324,57 @@ __global__ __launch_bounds__(1024) void k_rank(const float* s, int n, int32_t* o
   for (int i = threadIdx.x; i < n; i += 1024) out[i] = id[i];
 }
 
+// Visiting keys of a state under a ranking (the ranked search): order[p] is
+// the pixel at position p; pos_of receives the inverse.  Candidate i gets the
+// key (its position, i) if it improves on f: "sure" beyond its error band,
+// "band" within it (FP32 scores of the mixed form, unless the state is exact
+// after an FP64 refresh); src 0 reads the FP64 scores P.df (plain, R-form).
+// The search visits the new ranking from its top: the state's cursor is
+// reset.  One workgroup of 1024 threads, n_d <= 8192.
+__global__ __launch_bounds__(1024) void k_ranked_keys(ProbDev P, const int32_t* order,
+                                                      int32_t* pos_of, DbsState* st, int src,
+                                                      uint32_t* key_sure, uint32_t* key_band) {
+  __shared__ uint32_t red[2][16];
+  const int n = P.nd, tid = threadIdx.x;
+  for (int p = tid; p < n; p += 1024) pos_of[order[p]] = p;
+  __syncthreads();
+  const double f = st->f, eta = st->eta;
+  const bool exact = src == 0 || st->exact;
+  uint32_t ks = kNoKey, kb = kNoKey;
+  for (int i = tid; i < n; i += 1024) {
+    const double df = exact ? P.df[i] : P.df32[i];
+    const double margin = df - eta * f;
+    const uint32_t k = pack_key(pos_of[i], i);
+    if (exact) {
+      if (margin > 0.0) ks = min(ks, k);
+    } else {
+      const double band = P.band * P.dfb[i];
+      if (margin > band) ks = min(ks, k);
+      else if (margin >= -band) kb = min(kb, k);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    ks = min(ks, uint32_t(__shfl_xor(int(ks), o, 64)));
+    kb = min(kb, uint32_t(__shfl_xor(int(kb), o, 64)));
+  }
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = ks;
+    red[1][tid >> 6] = kb;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 16; ++w) {
+      ks = min(ks, red[0][w]);
+      kb = min(kb, red[1][w]);
+    }
+    *key_sure = ks;
+    *key_band = kb;
+    st->cursor_s = 0;
+    st->cursor_pos = 0;
+  }
+}
+
 // ------------------------------------------------------------------ model
 struct Model {
   int H = 0, W = 0, maxb = 0;
@@ -329,8 +395,11 @@ struct Model {
   float* T = nullptr;                // targets [maxb][1][H][W]
   float* Z[kLayers] = {};            // pre-activations
   float* dZ[2] = {};                 // gradient ping-pong
-  double* loss = nullptr;
+  float* gpart = nullptr;            // per-chunk partial weight gradients
+  double* loss = nullptr;            // per-workgroup loss sums
 };
+
+constexpr int kWgradChunk = 256;     // pixels per partial weight gradient
 
 }  // namespace pngf
 
@@ -354,6 +423,17 @@ int mfail(pngf_model* m, int code, const std::string& msg) {
       return mfail(m, PNGF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Largest per-chunk partial gradient buffer over the layers (floats).
+size_t gpart_floats(const pngf_model* m) {
+  using namespace pngf;
+  const size_t img = size_t(m->maxb) * m->H * m->W;
+  const size_t nchunk = (img + kWgradChunk - 1) / kWgradChunk;
+  size_t mx = 0;
+  for (int l = 0; l < kLayers; ++l)
+    mx = std::max(mx, size_t(kCh[l + 1]) * kCh[l] * 9 + kCh[l + 1]);
+  return nchunk * mx;
+}
+
 size_t model_bytes(const pngf_model* m) {
   using namespace pngf;
   const size_t img = size_t(m->maxb) * m->H * m->W;
@@ -363,7 +443,8 @@ size_t model_bytes(const pngf_model* m) {
          a256(size_t(pad16(kCh[l])) * m->ktpad[l] * 2);
   b += a256(img * kCh[0] * sizeof(float)) + a256(img * sizeof(float));
   for (int l = 0; l < kLayers; ++l) b += a256(img * kCh[l + 1] * sizeof(float));
-  b += 2 * a256(img * 32 * sizeof(float)) + a256(sizeof(double));
+  b += 2 * a256(img * 32 * sizeof(float));
+  b += a256(gpart_floats(m) * sizeof(float)) + a256(((img + 255) / 256) * sizeof(double));
   return b;
 }
 
@@ -422,6 +503,14 @@ int model_hw(pngf_model* m, int* H, int* W) {
   return m->bound ? PNGF_OK : PNGF_ESTATE;
 }
 hipStream_t model_stream(pngf_model* m) { return m->stream; }
+hipError_t launch_ranked_keys(const ProbDev& P, const int32_t* order, int32_t* pos_of,
+                              DbsState* st, int src, uint32_t* key_sure, uint32_t* key_band,
+                              hipStream_t s) {
+  if (P.nd < 1 || P.nd > 8192) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ranked_keys, dim3(1), dim3(1024), 0, s, P, order, pos_of, st, src,
+                     key_sure, key_band);
+  return hipGetLastError();
+}
 hipError_t launch_features(const ProbDev& P, int H, int W, float* X, hipStream_t s) {
   if (int64_t(H) * W != P.nd) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_features, dim3(1), dim3(1024), 0, s, P, H, W, X);
@@ -505,7 +594,8 @@ int pngf_model_bind(pngf_model* m, void* dev_ws, size_t bytes, void* stream) {
   for (int l = 0; l < kLayers; ++l) m->Z[l] = reinterpret_cast<float*>(take(img * kCh[l + 1] * 4));
   m->dZ[0] = reinterpret_cast<float*>(take(img * 32 * 4));
   m->dZ[1] = reinterpret_cast<float*>(take(img * 32 * 4));
-  m->loss = reinterpret_cast<double*>(take(sizeof(double)));
+  m->gpart = reinterpret_cast<float*>(take(gpart_floats(m) * sizeof(float)));
+  m->loss = reinterpret_cast<double*>(take(((img + 255) / 256) * sizeof(double)));
   MCHK(m, hipMemsetAsync(m->ws, 0, model_bytes(m), m->stream));
   MCHK(m, hipMemcpyAsync(m->w, m->host_params.data(), size_t(m->np) * 4, hipMemcpyHostToDevice,
                          m->stream));
@@ -561,20 +651,24 @@ int pngf_model_train_step(pngf_model* m, const float* X, const float* T, int32_t
   MCHK(m, hipMemcpyAsync(m->X, X, img * kCh[0] * 4, hipMemcpyHostToDevice, m->stream));
   MCHK(m, hipMemcpyAsync(m->T, T, img * 4, hipMemcpyHostToDevice, m->stream));
   MCHK(m, forward(m, N));
-  MCHK(m, hipMemsetAsync(m->g, 0, size_t(m->np) * 4, m->stream));
-  MCHK(m, hipMemsetAsync(m->loss, 0, sizeof(double), m->stream));
   float* d = m->dZ[0];
-  hipLaunchKernelGGL(k_huber, dim3((img + 255) / 256), dim3(256), 0, m->stream,
+  const int nblk = int((img + 255) / 256);
+  hipLaunchKernelGGL(k_huber, dim3(nblk), dim3(256), 0, m->stream,
                      m->Z[kLayers - 1], m->T, d, int(img), 1.f / float(img), m->loss);
   MCHK(m, hipGetLastError());
-  const int chunk = 256;
+  const int chunk = kWgradChunk;
+  const int nchunk = int((img + chunk - 1) / chunk);
   for (int l = kLayers - 1; l >= 0; --l) {
     const float* in = l > 0 ? m->Z[l - 1] : m->X;
     const int cin = kCh[l], cout = kCh[l + 1];
-    const int waves = (pad16(cout) / 16) * (m->kpad[l] / 16) * int((img + chunk - 1) / chunk);
+    const int waves = (pad16(cout) / 16) * (m->kpad[l] / 16) * nchunk;
     hipLaunchKernelGGL(k_wgrad, dim3((waves + 3) / 4), dim3(256), 0, m->stream, d, in, cin,
-                       l > 0 ? 1 : 0, cout, N, m->H, m->W, m->g + m->off_w[l], m->kpad[l],
-                       m->g + m->off_b[l], chunk);
+                       l > 0 ? 1 : 0, cout, N, m->H, m->W, m->gpart, m->kpad[l], chunk);
+    MCHK(m, hipGetLastError());
+    // weights then biases of layer l are adjacent in the flat parameters
+    const int nl = cout * cin * 9 + cout;
+    hipLaunchKernelGGL(k_wsum, dim3((nl + 255) / 256), dim3(256), 0, m->stream, m->gpart, nl,
+                       nchunk, m->g + m->off_w[l]);
     MCHK(m, hipGetLastError());
     if (l > 0) {
       float* dn = (d == m->dZ[0]) ? m->dZ[1] : m->dZ[0];
@@ -596,9 +690,12 @@ int pngf_model_train_step(pngf_model* m, const float* X, const float* T, int32_t
     MCHK(m, hipGetLastError());
     MCHK(m, pack_all(m));
   }
-  double lsum = 0.0;
-  MCHK(m, hipMemcpyAsync(&lsum, m->loss, sizeof(double), hipMemcpyDeviceToHost, m->stream));
+  std::vector<double> lpart(nblk);
+  MCHK(m, hipMemcpyAsync(lpart.data(), m->loss, size_t(nblk) * sizeof(double),
+                         hipMemcpyDeviceToHost, m->stream));
   MCHK(m, hipStreamSynchronize(m->stream));
+  double lsum = 0.0;
+  for (double v : lpart) lsum += v;
   if (loss) *loss = lsum / double(img);
   return PNGF_OK;
 }

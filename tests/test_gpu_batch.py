@@ -82,3 +82,79 @@ def test_batch_rejects_mismatched_precision(problems, stream):
     h3.close()
     h1.close()
     h2.close()
+
+
+def _cplx(a):
+    a = np.asarray(a, dtype=np.float64)
+    return a[..., 0] + 1j * a[..., 1]
+
+
+@pytest.fixture(scope="module")
+def oracle_batch():
+    import json
+    import os
+    from gpu_util import GOLDEN
+    path = os.path.join(GOLDEN, "batch_config2.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle golden of the batched problems not generated")
+    with open(path) as fh:
+        g = json.load(fh)
+    return g, [workloads.config2_problem(q["seed"]) for q in g["problems"]]
+
+
+def _check_against_oracle(q, r, h, tol_trace):
+    assert r["accepted"].tolist() == [a[2] for a in q["accepted"]], q["seed"]
+    assert r["attempts"] == q["attempts"], q["seed"]
+    assert rel(r["f_trace"], [a[3] for a in q["accepted"]]) < tol_trace, q["seed"]
+    assert abs(r["f_final"] - q["f_final"]) < 1e-10 * q["f_final"], q["seed"]
+    f, x, E = h.evaluate(fields=True)
+    assert rel(x, _cplx(q["x"])) < 1e-10, q["seed"]
+    pix = np.asarray(q["sample_pixels"])
+    want = _cplx(q["E"]).reshape(len(x), -1)
+    for fi in range(len(x)):
+        err = np.max(np.abs(E[fi, pix] - want[fi])) / q["E_max"][fi]
+        assert err < 1e-10, (q["seed"], fi, err)
+
+
+@pytest.mark.parametrize("prec", ["plain", "mixed"])
+def test_batch_matches_oracle(oracle_batch, stream, prec):
+    """Six problems of uneven size (N_d 289-3136) and one to four
+    frequencies, advanced together in one launch per step, each against its
+    own oracle trajectory (full sparse re-solves)."""
+    g, probs = oracle_batch
+    k = g["max_accepts"]
+    say(f"batch of {len(probs)} vs oracle, {prec}")
+    kw = dict(precision=P.PNGF_MIXED, k_refresh=8) if prec == "mixed" else {}
+    handles = [P.Handle(p).bind(P.default_options(max_accepts=k, max_sweeps=2, **kw),
+                                stream=stream) for p in probs]
+    for h, p in zip(handles, probs):
+        h.set_design(p.init_bits)
+    b = P.Batch(handles)
+    out = b.dbs_run([p.perms[:2] for p in probs], autotune=True)
+    tol = 1e-6 if prec == "mixed" else 1e-10
+    for q, r, h in zip(g["problems"], out, handles):
+        _check_against_oracle(q, r, h, tol)
+    b.close()
+    for h in handles:
+        h.close()
+
+
+@pytest.mark.parametrize("prec", ["plain", "mixed", "rform"])
+def test_large_solo_searches_match_oracle(oracle_batch, prec):
+    """The same problems searched one at a time: every dispatch of the step
+    kernels at these sizes (FP64 rows of 8 and 16 per lane; the persistent
+    mixed search at one frequency and N_d <= 2048, the generic mixed step for
+    more frequencies or larger N_d, the multi-frequency step for N_d <=
+    1024; the R-form)."""
+    g, probs = oracle_batch
+    k = g["max_accepts"]
+    prc = {"plain": P.PNGF_FP64_PLAIN, "mixed": P.PNGF_MIXED, "rform": P.PNGF_RFORM}[prec]
+    kw = {"k_refresh": 8} if prec == "mixed" else {}
+    tol = 1e-6 if prec == "mixed" else 1e-10
+    for q, p in zip(g["problems"], probs):
+        say(f"solo {prec} vs oracle, seed {q['seed']} (N_d {p.n_d}, F {p.nfreq})")
+        h = P.Handle(p).bind(P.default_options(precision=prc, max_accepts=k, max_sweeps=2, **kw))
+        h.set_design(p.init_bits)
+        r = h.dbs_run(p.perms[:2])
+        _check_against_oracle(q, r, h, tol)
+        h.close()
