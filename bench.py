@@ -345,9 +345,86 @@ def broadband_form(P, steps, warmup):
 # the mixed step kernel of the eight-frequency N_d = 6400 workload (one launch
 # per step; every launch streams the complex-FP32 C0^-1 of all frequencies)
 C4_STEP_KERNEL = "k_mixed_step"
+C4_WORKLOAD = ("2D TM FDFD 640x640, 16-cell PML, h = lambda0/25, 80x80 design (N_d=6400), "
+               "eps {1,11.7}, 8 frequencies over 0.9-1.1 f0, Gaussian line source -> "
+               "vacuum-normalized mean Gaussian-mode transmission, to convergence (<= 20 sweeps)")
 
 
-def config4_form(P):
+def config4_learned(P, hb, p, c4, train_seeds=(41, 42)):
+    """The combined form on workload 4: the mixed form (complex-FP32 steps,
+    FP64 decisions in the error band, FP64 refresh every 32 accepts), all
+    eight frequencies in every launch, driven by the learned proposal (the
+    first improving pixel of the network's ranking of each state, ranked on
+    the device).  The network is trained first (not timed) on pairs logged
+    from two other seeds of the same workload.  Every accept is an exact
+    improvement; the objective of the design it reaches is re-evaluated from
+    a fresh FP64 inverse."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2501_18054_amd import learned
+    t0 = time.perf_counter()
+    X, T = [], []
+    for s in train_seeds:
+        q = workloads.config4(seed=s)
+        hq = P.Handle(q).bind(P.default_options(max_accepts=16384, max_sweeps=20))
+        x, t = learned.collect(hq, q, every=4, greedy=True)
+        X += x
+        T += t
+        hq.close()
+    model = P.Model(80, 80, max_batch=8, seed=0)
+    hist = learned.train(model, X, T, epochs=20, batch=8, lr=1e-3)
+    t_train = time.perf_counter() - t0
+    log(f"config4 learned: trained on {len(X)} states in {t_train:.1f} s "
+        f"(loss {hist[0]:.3f} -> {hist[-1]:.3f})")
+    out = {"train_s": t_train, "train_seeds": list(train_seeds)}
+    hb.bind(P.default_options(precision=P.PNGF_MIXED, k_refresh=32, max_accepts=16384,
+                              max_sweeps=20))
+    hb.set_design(p.init_bits)
+    hb.learned_dbs_run(model, k=1, max_accepts=16384)
+    res = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 2
+    for _ in range(reps):
+        hb.set_design(p.init_bits)
+        res.append(hb.learned_dbs_run(model, k=1, max_accepts=16384))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    r = res[-1]
+    bits = p.init_bits.copy()
+    for m in r["accepted"]:
+        bits[m] ^= 1
+    hb.bind(P.default_options(max_accepts=64, max_sweeps=1))
+    hb.set_design(bits)
+    f64, _ = hb.evaluate()
+    hb.bind(P.default_options(precision=P.PNGF_MIXED, k_refresh=32, max_accepts=16384,
+                              max_sweeps=20))
+    hb.set_design(p.init_bits)
+    t1 = time.perf_counter()
+    r1 = hb.learned_dbs_run(None, k=1, max_accepts=16384)
+    torch.cuda.synchronize()
+    t_fo = time.perf_counter() - t1
+    model.close()
+    fp = c4["plain"]["f_final"]
+    out.update({"time_to_design_ms": 1e3 * dt, "exact_evals": r["attempts"],
+                "exact_evals_per_s": r["attempts"] / dt, "accepts": r["n_accepted"],
+                "converged": r["converged"], "f_final": r["f_final"],
+                "objective_rel_err_vs_fp64_eval": abs(r["f_final"] - f64) / f64,
+                "objective_rel_to_plain_dbs": r["f_final"] / fp,
+                "exact_evals_rel_to_plain_dbs": r["attempts"] / c4["plain"]["attempts"],
+                "speedup_vs_plain_dbs": c4["plain"]["time_to_design_ms"] / (1e3 * dt),
+                "timed_runs": reps,
+                "first_order_ranking": {"time_to_design_ms": 1e3 * t_fo,
+                                        "exact_evals": r1["attempts"], "accepts": r1["n_accepted"],
+                                        "f_final": r1["f_final"]}})
+    log(f"config4 learned mixed: {r['n_accepted']} accepts, {r['attempts']} exact evals, "
+        f"f {r['f_final']:.6g} ({out['objective_rel_to_plain_dbs']:.4f} of plain DBS), "
+        f"{1e3 * dt:.0f} ms per design")
+    return out
+
+
+def config4_form(P, learned=True):
     """Workload 4 at full size: 640x640 grid, 80x80 design (N_d = 6400),
     eight frequencies, vacuum-normalized mean transmission.  Each form runs
     the search from the same start design until a whole sweep keeps nothing
@@ -395,6 +472,8 @@ def config4_form(P):
     fp = out["plain"]["f_final"]
     out["objective_rel_err_mixed_vs_plain"] = abs(out["mixed"]["f_final"] - fp) / fp
     out["objective_rel_err_rform_vs_plain"] = abs(out["rform"]["f_final"] - fp) / fp
+    if learned:
+        out["learned_mixed"] = config4_learned(P, hb, p, out)
     # per-class times of one mixed run (events on every launch)
     hb.bind(P.default_options(precision=P.PNGF_MIXED, k_refresh=32, max_accepts=16384,
                               max_sweeps=20, timing=True))
@@ -518,11 +597,27 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-config4", action="store_true")
+    ap.add_argument("--config4-only", action="store_true",
+                    help="run only the 640x640 / N_d 6400 / 8-frequency leg (for profiling)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: this build measures one GPU only (the hot path runs on one "
               "MI355X); multi-GPU runs are not supported", file=sys.stderr)
         sys.exit(2)
+
+    if a.config4_only:
+        import torch  # noqa: F401
+        import paper_2501_18054_amd as P
+        c4 = config4_form(P)
+        m = c4["mixed"]
+        print(json.dumps({
+            "metric": METRIC, "value": m["flip_evals_per_s"], "unit": "flip evals/s",
+            "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": m["time_to_design_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "c64 + f64", "data": "synthetic",
+            "config": {"workload": C4_WORKLOAD, "n_d": c4["n_d"]},
+            "roofline": c4.get("roofline"), "forms": {"config4": c4}}))
+        return
 
     import workloads
     prob = workloads.config1()
@@ -593,7 +688,7 @@ def main():
     forms["broadband"] = broadband_form(P, a.steps, a.warmup)
     if not a.no_config4:
         log("workload 4 (640x640, N_d 6400, 8 frequencies) ...")
-        forms["config4"] = config4_form(P)
+        forms["config4"] = config4_form(P, learned=not a.no_learned)
     ref = forms["plain"]
     for name in ("mixed", "mixed_drift", "rform"):
         f = forms[name]

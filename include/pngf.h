@@ -416,16 +416,24 @@ int pngf_model_destroy(pngf_model *m);
  * is a full rectangle. */
 int pngf_features(pngf_handle *h, float *X);
 
-/* Ranked search on an FP64 handle.  Per state every pixel is ranked, by the
- * network m (which must be bound to h's stream and sized to the design) or,
- * with m NULL, by channel 6 above (the first-order change); the ranking is
- * scored exactly k pixels at a time, best first, and the best improving
- * pixel (f' - f > eta f) of the first chunk that has one is accepted (a
- * Sherman-Morrison update, eq. lru_woodbury with M = 1).  Converged when the
- * whole ranking holds no improving pixel; stops after max_accepts accepts.
+/* Ranked search.  Per state every pixel is ranked, by the network m (which
+ * must be bound to h's stream and sized to the design) or, with m NULL, by
+ * channel 6 above (the first-order change); the ranking is scored exactly k
+ * pixels at a time, best first, and the best improving pixel (f' - f > eta
+ * f) of the first chunk that has one is accepted (a Sherman-Morrison update,
+ * eq. lru_woodbury with M = 1).  Converged when the whole ranking holds no
+ * improving pixel; stops after max_accepts accepts.
+ *   k = 1 (the first improving pixel of the ranking) runs on the device for
+ *   every precision: the search steps of pngf_dbs_run with the visiting
+ *   order replaced by the state's ranking (re-ranked after every accept, all
+ *   frequencies in each launch, no host round trip per state); the mixed
+ *   form decides in FP64 inside its error band, so every accept is exact.
+ *   max_accepts <= the bound options' max_accepts.
+ *   k > 1 needs an FP64 plain handle (chunks scored from the host).
  * accepted / f_trace (optional, max_accepts entries) receive the pixels and
- * objectives; res->attempts counts the exact evaluations performed,
- * res->sweeps the chunks scored beyond the first of each state.  Needs
+ * objectives; res->attempts counts the exact evaluations performed (ranked
+ * positions up to the accepted one, all n_d at convergence), res->sweeps the
+ * chunks scored beyond the first of each state.  Needs a rectangular design,
  * n_d <= 8192 and 1 <= k <= n_d. */
 int pngf_learned_dbs_run(pngf_handle *h, pngf_model *m, int32_t k, int32_t max_accepts,
                          int32_t *accepted, double *f_trace, pngf_dbs_result *res);

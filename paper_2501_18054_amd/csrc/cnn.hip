@@ -324,52 +324,104 @@ __global__ __launch_bounds__(1024) void k_rank(const float* s, int n, int32_t* o
   for (int i = threadIdx.x; i < n; i += 1024) out[i] = id[i];
 }
 
-// Visiting keys of a state under a ranking (the ranked search): order[p] is
-// the pixel at position p; pos_of receives the inverse.  Candidate i gets the
-// key (its position, i) if it improves on f: "sure" beyond its error band,
-// "band" within it (FP32 scores of the mixed form, unless the state is exact
-// after an FP64 refresh); src 0 reads the FP64 scores P.df (plain, R-form).
-// The search visits the new ranking from its top: the state's cursor is
-// reset.  One workgroup of 1024 threads, n_d <= 8192.
-__global__ __launch_bounds__(1024) void k_ranked_keys(ProbDev P, const int32_t* order,
-                                                      int32_t* pos_of, DbsState* st, int src,
-                                                      uint32_t* key_sure, uint32_t* key_band) {
-  __shared__ uint32_t red[2][16];
-  const int n = P.nd, tid = threadIdx.x;
-  for (int p = tid; p < n; p += 1024) pos_of[order[p]] = p;
-  __syncthreads();
+// Visiting keys of a state under a ranking (the ranked search), without
+// sorting: the ranking orders pixels by score, best first, ties by pixel
+// id, and the search takes the first improving pixel of it, i.e. the
+// improving pixel of highest score.  So per class ("sure": improving beyond
+// its error band; "band": within it) one arg-max gives the pixel, and one
+// count over the scores gives its position in the ranking (the number of
+// pixels ranked before it), which is what the key and the attempt count
+// need.  Scores: the FP32 ones of the mixed form unless the state is exact
+// after an FP64 refresh; src 0 reads the FP64 scores P.df (plain, R-form).
+// The search visits the ranking from its top: the state's cursor is reset.
+// One workgroup of 1024 threads.
+__device__ __forceinline__ bool rank_before(float sa, int a, float sb, int b) {
+  return sa > sb || (sa == sb && a < b);
+}
+
+__global__ __launch_bounds__(1024) void k_ranked_keys(ProbDev P, const float* score,
+                                                      DbsState* st, int src, uint32_t* key_sure,
+                                                      uint32_t* key_band) {
+  __shared__ float rs[2][16];
+  __shared__ int ri[2][16];
+  __shared__ int cnt[2][16];
+  __shared__ float bs[2];
+  __shared__ int bi[2];
+  const int n = P.nd, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const double f = st->f, eta = st->eta;
   const bool exact = src == 0 || st->exact;
-  uint32_t ks = kNoKey, kb = kNoKey;
+  // best-ranked candidate of each class (-1: none)
+  float s2[2] = {-INFINITY, -INFINITY};
+  int i2[2] = {-1, -1};
   for (int i = tid; i < n; i += 1024) {
     const double df = exact ? P.df[i] : P.df32[i];
     const double margin = df - eta * f;
-    const uint32_t k = pack_key(pos_of[i], i);
+    int cls = -1;
     if (exact) {
-      if (margin > 0.0) ks = min(ks, k);
+      if (margin > 0.0) cls = 0;
     } else {
       const double band = P.band * P.dfb[i];
-      if (margin > band) ks = min(ks, k);
-      else if (margin >= -band) kb = min(kb, k);
+      if (margin > band) cls = 0;
+      else if (margin >= -band) cls = 1;
+    }
+    if (cls >= 0 && (i2[cls] < 0 || rank_before(score[i], i, s2[cls], i2[cls]))) {
+      s2[cls] = score[i];
+      i2[cls] = i;
     }
   }
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    ks = min(ks, uint32_t(__shfl_xor(int(ks), o, 64)));
-    kb = min(kb, uint32_t(__shfl_xor(int(kb), o, 64)));
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const float so = __shfl_xor(s2[c], o, 64);
+      const int io = __shfl_xor(i2[c], o, 64);
+      if (io >= 0 && (i2[c] < 0 || rank_before(so, io, s2[c], i2[c]))) {
+        s2[c] = so;
+        i2[c] = io;
+      }
+    }
+    if (lane == 0) {
+      rs[c][w] = s2[c];
+      ri[c][w] = i2[c];
+    }
   }
-  if ((tid & 63) == 0) {
-    red[0][tid >> 6] = ks;
-    red[1][tid >> 6] = kb;
+  __syncthreads();
+  if (tid < 2) {
+    float sb = -INFINITY;
+    int ib = -1;
+    for (int q = 0; q < 16; ++q)
+      if (ri[tid][q] >= 0 && (ib < 0 || rank_before(rs[tid][q], ri[tid][q], sb, ib))) {
+        sb = rs[tid][q];
+        ib = ri[tid][q];
+      }
+    bs[tid] = sb;
+    bi[tid] = ib;
+  }
+  __syncthreads();
+  // positions: pixels ranked before each class's pick
+  int c2[2] = {0, 0};
+  for (int i = tid; i < n; i += 1024) {
+    const float si = score[i];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      if (bi[c] >= 0 && rank_before(si, i, bs[c], bi[c])) c2[c] += 1;
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c2[c] += __shfl_xor(c2[c], o, 64);
+    if (lane == 0) cnt[c][w] = c2[c];
   }
   __syncthreads();
   if (tid == 0) {
-    for (int w = 1; w < 16; ++w) {
-      ks = min(ks, red[0][w]);
-      kb = min(kb, red[1][w]);
+    uint32_t k[2];
+    for (int c = 0; c < 2; ++c) {
+      int tot = 0;
+      for (int q = 0; q < 16; ++q) tot += cnt[c][q];
+      k[c] = bi[c] >= 0 ? pack_key(tot, bi[c]) : kNoKey;
     }
-    *key_sure = ks;
-    *key_band = kb;
+    *key_sure = k[0];
+    *key_band = k[1];
     st->cursor_s = 0;
     st->cursor_pos = 0;
   }
@@ -503,12 +555,11 @@ int model_hw(pngf_model* m, int* H, int* W) {
   return m->bound ? PNGF_OK : PNGF_ESTATE;
 }
 hipStream_t model_stream(pngf_model* m) { return m->stream; }
-hipError_t launch_ranked_keys(const ProbDev& P, const int32_t* order, int32_t* pos_of,
-                              DbsState* st, int src, uint32_t* key_sure, uint32_t* key_band,
-                              hipStream_t s) {
-  if (P.nd < 1 || P.nd > 8192) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_ranked_keys, dim3(1), dim3(1024), 0, s, P, order, pos_of, st, src,
-                     key_sure, key_band);
+hipError_t launch_ranked_keys(const ProbDev& P, const float* score, DbsState* st, int src,
+                              uint32_t* key_sure, uint32_t* key_band, hipStream_t s) {
+  if (P.nd < 1 || P.nd > kMaxPixels) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ranked_keys, dim3(1), dim3(1024), 0, s, P, score, st, src, key_sure,
+                     key_band);
   return hipGetLastError();
 }
 hipError_t launch_features(const ProbDev& P, int H, int W, float* X, hipStream_t s) {

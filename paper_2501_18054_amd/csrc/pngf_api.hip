@@ -53,6 +53,8 @@ hipError_t launch_pick_best(const double* df, const int32_t* cand, int n, const 
 hipError_t model_score_state(pngf_model* m, const ProbDev& P, float** scores);
 hipError_t launch_rank(const float* s, int n, int32_t* out, hipStream_t st);
 hipError_t launch_features(const ProbDev& P, int H, int W, float* X, hipStream_t s);
+hipError_t launch_ranked_keys(const ProbDev& P, const float* score, DbsState* st, int src,
+                              uint32_t* key_sure, uint32_t* key_band, hipStream_t s);
 int model_hw(pngf_model* m, int* H, int* W);
 hipStream_t model_stream(pngf_model* m);
 hipError_t launch_select_prep(const ProbDev& P, int forced, hipStream_t s);
@@ -143,6 +145,11 @@ struct pngf_handle {
   size_t ws_bytes = 0;
   int ld = 0, npl = 1;
   bool persist_off = false;   // a launch of the persistent search was refused
+  // ranked search: the visiting order of every state is a fresh ranking of
+  // the pixels (by rank_model, or by the first-order change if it is null)
+  bool ranked = false;
+  pngf_model* rank_model = nullptr;
+  int rank_h = 0, rank_w = 0;
   int persist_spin = pngf::kPersistSpin;   // polls of one grid-barrier wait
   bool reform_c64 = false;   // reform_fields also writes C0^-1 (mixed refresh)
   bool persist_ok = false;   // a persistent launch of this search has run
@@ -636,14 +643,56 @@ int write_state_pinned(pngf_handle* h, const pngf::DbsState* st) {
 }
 
 
+// Ranked search: the keys that step `step` of the segment decides from, under
+// a fresh ranking of the state that step reads (buffer set and state of its
+// parity): the state's features, the network's scores (or the first-order
+// change), then the keys of the best-ranked improving pixels from the exact
+// scores the previous step (or the segment start) left, with the cursor back
+// at the top of the ranking.  Overwrites the key slots the previous step wrote.
+// Stream-ordered, no wait.
+int rank_chain(pngf_handle* h, int64_t step) {
+  const int nd = h->pc.n_d;
+  pngf::ProbDev Q = h->P;
+  if (step & 1) {
+    for (int f = 0; f < Q.nfreq; ++f) {
+      if (Q.CinvB[f]) std::swap(Q.Cinv[f], Q.CinvB[f]);
+      std::swap(Q.E[f], Q.EB[f]);
+      std::swap(Q.Rp[f], Q.RpB[f]);
+      std::swap(Q.tau[f], Q.tauB[f]);
+    }
+    std::swap(Q.bits, Q.bitsB);
+  }
+  pngf::DbsState* sin = (step & 1) ? h->P.stB : h->P.st;
+  Q.st = sin;   // the features read f and x of the state the next step reads
+  const int slot = int(step % 3);
+  Timer t(h, KID_OTHER);
+  const float* scores = nullptr;
+  if (h->rank_model) {
+    float* y = nullptr;
+    HIPCHK(h, pngf::model_score_state(h->rank_model, Q, &y));
+    scores = y;
+  } else {
+    float* feat = at<float>(h, h->lay.off_feat);
+    HIPCHK(h, pngf::launch_features(Q, h->rank_h, h->rank_w, feat, h->stream));
+    scores = feat + size_t(kFeatChannels - 1) * nd;
+  }
+  HIPCHK(h, pngf::launch_ranked_keys(Q, scores, sin, h->opt.precision == PNGF_MIXED ? 1 : 0,
+                                     h->P.keys + slot, h->P.keys + 3 + slot, h->stream));
+  t.end();
+  return PNGF_OK;
+}
+
 // Reset the rotating key slots (and, if asked, the panel bookkeeping of the
 // state) and score every candidate of the current (normalized) state into
 // slot 0; the next step of the search is step 0.  Stream-ordered, no wait.
 int start_segment(pngf_handle* h, bool reset_panel = false) {
   HIPCHK(h, pngf::launch_segment_start(h->P, reset_panel ? 1 : 0, h->stream));
-  Timer t(h, KID_SCORE);
-  HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, h->pc.n_d, h->P.keys, h->stream));
-  t.end();
+  {
+    Timer t(h, KID_SCORE);
+    HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, h->pc.n_d, h->P.keys, h->stream));
+    t.end();
+  }
+  if (h->ranked) return rank_chain(h, 0);
   return PNGF_OK;
 }
 
@@ -691,7 +740,13 @@ int run_steps(pngf_handle* h, L launch, int64_t t0, int n, pngf::DbsState* pinne
     }
   }
   if (!persist)
-    for (int b = 0; b < n; ++b) HIPCHK(h, launch(h->P, h->npl, int(t0 + b), h->stream));
+    for (int b = 0; b < n; ++b) {
+      HIPCHK(h, launch(h->P, h->npl, int(t0 + b), h->stream));
+      if (h->ranked) {
+        const int st = rank_chain(h, t0 + b + 1);
+        if (st) return st;
+      }
+    }
   t.end(n);
   h->bits_fresh = false;
   const int nd = h->pc.n_d;
@@ -884,7 +939,7 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
   int64_t since = 0, kpan = 0;   // host view of n_since / kpanel
   int64_t checked = 0;           // n_since at the last drift check
   for (int64_t round = 0; round < max_rounds; ++round) {
-    const bool persist = !h->persist_off && F == 1 && nd <= 2048 &&
+    const bool persist = !h->persist_off && !h->ranked && F == 1 && nd <= 2048 &&
                          h->P.kcap <= pngf::kPersistSlotsHost &&
                          !(h->opt.flags & PNGF_FLAG_STEP_LAUNCHES);
     // end the batch where a periodic re-inversion or a fold is due, so that
@@ -1084,6 +1139,10 @@ int run_rform(pngf_handle* h, pngf::DbsState* pinned) {
                                 pngf::kNoKey, pngf::kNoKey, pngf::kNoKey};
       HIPCHK(h, hipMemcpyAsync(h->P.keys, none, sizeof(none), hipMemcpyHostToDevice, h->stream));
       HIPCHK(h, pngf::launch_rform_score(h->P, h->stream));
+      if (h->ranked) {
+        st = rank_chain(h, 0);
+        if (st) return st;
+      }
       HIPCHK(h, hipStreamSynchronize(h->stream));
       t = 0;
     }
@@ -1717,6 +1776,62 @@ int pngf_destroy(pngf_handle* h) {
 // ------------------------------------------------------------------ learned
 namespace {
 
+// Ranked search with chunks of one pixel, on the device: a direct binary
+// search whose visiting order at every state is a fresh ranking (the network,
+// or the first-order change), restarted from the top after each accept, so
+// the first improving pixel of the ranking is accepted.  Runs on every form
+// (FP64 plain, mixed with its FP64 decisions in the error band, R-form) with
+// the same step kernels as pngf_dbs_run, all frequencies in each launch, and
+// no host round trip per state.
+int ranked_search(pngf_handle* h, pngf_model* m, int H, int W, int32_t max_accepts,
+                  int32_t* accepted, double* f_trace, pngf_dbs_result* res) {
+  const int nd = h->pc.n_d;
+  if (max_accepts > h->opt.max_accepts)
+    return fail(h, PNGF_EINVAL, "max_accepts exceeds the bound options' max_accepts");
+  if (max_accepts == 0) {
+    pngf::DbsState s;
+    int st = read_state(h, &s);
+    if (st) return st;
+    if (res) {
+      *res = pngf_dbs_result{};
+      res->f_initial = res->f_final = s.f;
+    }
+    return PNGF_OK;
+  }
+  std::vector<int32_t> ident(nd);
+  for (int i = 0; i < nd; ++i) ident[i] = i;
+  double f0 = 0.0;
+  int st = dbs_prologue(h, ident.data(), 1, &f0);
+  if (st) return st;
+  h->ranked = true;
+  h->rank_model = m;
+  h->rank_h = H;
+  h->rank_w = W;
+  const int32_t max_acc = h->P.max_acc;
+  h->P.max_acc = max_accepts;
+  pngf::DbsState* pinned = nullptr;
+  HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(pngf::DbsState)));
+  int64_t n_refresh = 0, n_band = 0;
+  int rc = (h->opt.precision == PNGF_MIXED)   ? run_mixed(h, pinned, &n_refresh, &n_band)
+           : (h->opt.precision == PNGF_RFORM) ? run_rform(h, pinned)
+                                              : run_plain(h, pinned);
+  pngf::DbsState fin = *pinned;
+  (void)hipHostFree(pinned);
+  h->ranked = false;
+  h->rank_model = nullptr;
+  h->P.max_acc = max_acc;
+  if (rc) return rc;
+  st = dbs_epilogue(h, fin, f0, n_refresh, n_band, accepted, f_trace, res);
+  if (st) return st;
+  if (res) {
+    // chunks scored beyond the first of each state (one per state visited)
+    const int64_t states = int64_t(fin.n_acc) + (fin.converged ? 1 : 0);
+    res->sweeps = int32_t(std::max<int64_t>(0, fin.attempts - states));
+  }
+  return PNGF_OK;
+}
+
+
 // Design region as an H x W rectangle in pixel order (needed by the CNN).
 bool design_grid(pngf_handle* h, int* H, int* W) {
   const auto& dn = h->pc.design_nodes;
@@ -1754,8 +1869,6 @@ int pngf_learned_dbs_run(pngf_handle* h, pngf_model* m, int32_t k, int32_t max_a
                          int32_t* accepted, double* f_trace, pngf_dbs_result* res) {
   int st = check_ready(h, true);
   if (st) return st;
-  if (h->opt.precision != PNGF_FP64_PLAIN)
-    return fail(h, PNGF_EINVAL, "the learned search runs on an FP64 handle");
   const int nd = h->pc.n_d;
   int H = 0, W = 0;
   if (!design_grid(h, &H, &W)) return fail(h, PNGF_EINVAL, "design region is not a rectangle");
@@ -1769,6 +1882,9 @@ int pngf_learned_dbs_run(pngf_handle* h, pngf_model* m, int32_t k, int32_t max_a
   }
   if (k < 1 || k > nd) return fail(h, PNGF_EINVAL, "k must be in [1, n_d]");
   if (max_accepts < 0) return fail(h, PNGF_EINVAL, "max_accepts must be >= 0");
+  if (k == 1) return ranked_search(h, m, H, W, max_accepts, accepted, f_trace, res);
+  if (h->opt.precision != PNGF_FP64_PLAIN)
+    return fail(h, PNGF_EINVAL, "the learned search with k > 1 runs on an FP64 handle");
   pngf::DbsState s;
   st = read_state(h, &s);
   if (st) return st;
