@@ -403,6 +403,24 @@ int pngf_model_set_params(pngf_model *m, const float *params, int32_t n);
 /* Host arrays: X[N][7][H][W] in, Y[N][1][H][W] out; 1 <= N <= max_batch. */
 int pngf_model_forward(pngf_model *m, const float *X, int32_t N, float *Y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * forward pass as pngf_model_forward, with no model object and no workspace.
+ * All pointers are device pointers owned by the caller: params[n_params]
+ * (the flat FP32 parameters, as pngf_model_get_params lays them out),
+ * X[N][7][H][W] in, Y[N][1][H][W] out.  Work is queued on hip_stream (no
+ * wait).  Its packed weights and activations live in a file-scope device
+ * array of 4 MiB + 64 KiB per GPU, kept until the process ends: N*H*W must
+ * not exceed 16384 pixels (PNGF_EINVAL otherwise).  Calls on one GPU share
+ * that array, so calls that overlap in time on one GPU (different streams,
+ * threads or processes' streams on it) race; each call clears and rewrites
+ * what it reads.  Calls no hipMalloc, hipFree or allocating library routine.
+ * Errors: PNGF_EINVAL for null pointers, sizes out of range or a parameter
+ * count that does not match the network; PNGF_EDEVICE for HIP errors
+ * (message: pngf_model_last_error(NULL)). */
+int pngf_model_forward_noalloc(const float *params, int32_t n_params, const float *X,
+                               int32_t N, int32_t H, int32_t W, float *Y, void *hip_stream);
+
 /* One step on a batch: forward, mean Huber loss against T[N][1][H][W],
  * backward; grads (optional, num_params floats) receive the gradient; an
  * Adam update with learning rate lr if lr > 0.  *loss = mean loss before the

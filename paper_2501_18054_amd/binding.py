@@ -113,6 +113,8 @@ EXPORTS = {
     "pngf_model_get_params": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "pngf_model_set_params": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "pngf_model_forward": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "pngf_model_forward_noalloc": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
+                                    C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "pngf_model_train_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
                                C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "pngf_model_destroy": ([C.c_void_p], C.c_int),
@@ -442,6 +444,24 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def model_forward_noalloc(params, X, Y, stream=None):
+    """pngf_model_forward_noalloc on device tensors: params (float32, flat),
+    X (float32 [N, 7, H, W]) in, Y (float32 [N, 1, H, W]) out; queued on
+    stream (torch's current one by default)."""
+    import torch
+    for t in (params, X, Y):
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    N, c, H, W = X.shape
+    assert c == Model.CHANNELS[0] and tuple(Y.shape) == (N, 1, H, W)
+    if stream is None:
+        stream = torch.cuda.current_stream(X.device)
+    rc = lib().pngf_model_forward_noalloc(C.c_void_p(params.data_ptr()), int(params.numel()),
+                                          C.c_void_p(X.data_ptr()), int(N), int(H), int(W),
+                                          C.c_void_p(Y.data_ptr()), C.c_void_p(stream.cuda_stream))
+    if rc != 0:
+        raise PngfError(rc, lib().pngf_model_last_error(None).decode())
 
 
 class Model:

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <random>
 #include <string>
@@ -222,7 +223,14 @@ __global__ __launch_bounds__(256) void k_pack(const float* Wl, int Cin, int Cout
   const int c = k / 9, r = k % 9;
   const short b = to_bf16(Wl[e]);
   Wb[size_t(o) * Kpad + k] = b;
-  Wt[size_t(c) * Ktpad + o * 9 + (8 - r)] = b;
+  if (Wt) Wt[size_t(c) * Ktpad + o * 9 + (8 - r)] = b;
+}
+
+// Zero n 32-bit words (a fill kernel rather than a memset node, so the
+// allocation-free forward can be captured in a graph).
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
 }
 
 // CNN inputs of the current PNGF state for an H x W pixel grid (pixel m at
@@ -757,3 +765,105 @@ int pngf_model_destroy(pngf_model* m) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- allocation-free forward
+//
+// Scratch of pngf_model_forward_noalloc in a file-scope device array (one
+// copy per GPU, held until the process ends): the BF16 weights of the four
+// layers (zero-padded to 16-multiples), then two activation buffers of
+// kNoAllocMaxPixels x 32 floats.  Host code uses only the per-device address
+// from hipGetSymbolAddress, never the array's name.
+namespace {
+constexpr int kNoAllocMaxPixels = 16384;                 // N * H * W per call
+constexpr size_t kNoAllocWeightBytes = size_t(64) << 10;
+constexpr size_t kNoAllocActFloats = size_t(kNoAllocMaxPixels) * 32;
+constexpr size_t kNoAllocScratchBytes =
+    kNoAllocWeightBytes + 2 * kNoAllocActFloats * sizeof(float);   // 4 MiB + 64 KiB
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (looked up once
+// per device, with that device current).
+hipError_t scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" int pngf_model_forward_noalloc(const float* params, int32_t n_params, const float* X,
+                                          int32_t N, int32_t H, int32_t W, float* Y,
+                                          void* stream) {
+  using namespace pngf;
+  if (!params || !X || !Y) return mfail(nullptr, PNGF_EINVAL, "null device pointer");
+  if (N < 1 || H < 1 || W < 1)
+    return mfail(nullptr, PNGF_EINVAL, "need N, H, W >= 1");
+  if (int64_t(N) * H * W > kNoAllocMaxPixels)
+    return mfail(nullptr, PNGF_EINVAL,
+                 "N*H*W exceeds the allocation-free forward's limit of 16384 pixels");
+  int off_w[kLayers], off_b[kLayers], kpad[kLayers], np = 0;
+  size_t wb_off[kLayers], wb_end = 0;
+  for (int l = 0; l < kLayers; ++l) {
+    off_w[l] = np;
+    np += kCh[l + 1] * kCh[l] * 9;
+    off_b[l] = np;
+    np += kCh[l + 1];
+    kpad[l] = pad16(kCh[l] * 9);
+    wb_off[l] = wb_end;
+    wb_end += a256(size_t(pad16(kCh[l + 1])) * kpad[l] * sizeof(short));
+  }
+  if (n_params != np) return mfail(nullptr, PNGF_EINVAL, "n_params does not match the network");
+  if (wb_end > kNoAllocWeightBytes) return mfail(nullptr, PNGF_EINVAL, "weights exceed scratch");
+  void* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess)
+    return mfail(nullptr, PNGF_EDEVICE,
+                 std::string("scratch address (hipGetSymbolAddress): ") + hipGetErrorString(e));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* sp = static_cast<char*>(base);
+  short* wb[kLayers];
+  for (int l = 0; l < kLayers; ++l) wb[l] = reinterpret_cast<short*>(sp + wb_off[l]);
+  float* act[2] = {reinterpret_cast<float*>(sp + kNoAllocWeightBytes),
+                   reinterpret_cast<float*>(sp + kNoAllocWeightBytes) + kNoAllocActFloats};
+  // the padded rows and columns of the packed weights must read as zero:
+  // clear the weight region, then pack
+  const int words = int(wb_end / 4);
+  hipLaunchKernelGGL(k_zero_words, dim3((words + 255) / 256), dim3(256), 0, st,
+                     reinterpret_cast<uint32_t*>(sp), words);
+  for (int l = 0; l < kLayers; ++l) {
+    const int cnt = kCh[l + 1] * kCh[l] * 9;
+    hipLaunchKernelGGL(k_pack, dim3((cnt + 255) / 256), dim3(256), 0, st, params + off_w[l],
+                       kCh[l], kCh[l + 1], wb[l], kpad[l], static_cast<short*>(nullptr), 0);
+  }
+  // X -> act0 -> act1 -> act0 -> Y (ReLU applied on read by the next layer)
+  const float* in = X;
+  for (int l = 0; l < kLayers; ++l) {
+    float* out = (l == kLayers - 1) ? Y : act[l & 1];
+    const int waves = N * H * ((W + 15) / 16) * (pad16(kCh[l + 1]) / 16);
+    hipLaunchKernelGGL(k_conv, dim3((waves + 3) / 4), dim3(256), 0, st, in, kCh[l],
+                       l > 0 ? 1 : 0, wb[l], kpad[l], params + off_b[l], out, kCh[l + 1], N, H,
+                       W, static_cast<const float*>(nullptr));
+    in = out;
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess)
+    return mfail(nullptr, PNGF_EDEVICE, std::string("forward launch: ") + hipGetErrorString(e));
+  return PNGF_OK;
+}
