@@ -608,7 +608,7 @@ def main():
     if a.config4_only:
         import torch  # noqa: F401
         import paper_2501_18054_amd as P
-        c4 = config4_form(P)
+        c4 = config4_form(P, learned=not a.no_learned)
         m = c4["mixed"]
         print(json.dumps({
             "metric": METRIC, "value": m["flip_evals_per_s"], "unit": "flip evals/s",

@@ -442,24 +442,25 @@ __device__ inline void mixed_step_group(const ProbDev& P, int g, int spar, int k
       if (vb) pb[q] = P.C0[0][size_t(rb) * P.ld + j];
     }
   }
-  // this pair's vectors (frequency 0), independent of the decision
+  // this pair's FP64 vectors at every frequency, independent of the decision:
+  // lane l < 6 F loads vector l % 3 (E, R', tau) of row l / 3 % 2 at
+  // frequency l / 6 into LDS, so the FP64 tail of each frequency below
+  // waits on no global load
+  __shared__ z64 vpre[kMixRows / 2][kMaxFreq][2][3];
   const uint8_t* bin = dp ? P.bitsB : P.bits;
   uint8_t* bout = dp ? P.bits : P.bitsB;
-  z64 e0a{0.0, 0.0}, r0a{0.0, 0.0}, t0a{0.0, 0.0}, e0b{0.0, 0.0}, r0b{0.0, 0.0}, t0b{0.0, 0.0};
+  if (lane < 6 * P.nfreq) {
+    const int f = lane / 6, h = (lane / 3) & 1, v = lane % 3;
+    if (h ? vb : va) {
+      const z64* src = v == 0 ? (dp ? P.EB[f] : P.E[f])
+                              : (v == 1 ? (dp ? P.RpB[f] : P.Rp[f]) : (dp ? P.tauB[f] : P.tau[f]));
+      vpre[w][f][h][v] = src[h ? rb : ra];
+    }
+  }
   uint8_t b0a = 0, b0b = 0;
   if (lane == 0) {
-    if (va) {
-      b0a = bin[ra];
-      e0a = (dp ? P.EB[0] : P.E[0])[ra];
-      r0a = (dp ? P.RpB[0] : P.Rp[0])[ra];
-      t0a = (dp ? P.tauB[0] : P.tau[0])[ra];
-    }
-    if (vb) {
-      b0b = bin[rb];
-      e0b = (dp ? P.EB[0] : P.E[0])[rb];
-      r0b = (dp ? P.RpB[0] : P.Rp[0])[rb];
-      t0b = (dp ? P.tauB[0] : P.tau[0])[rb];
-    }
+    if (va) b0a = bin[ra];
+    if (vb) b0b = bin[rb];
   }
   if (tid == 0) step_decide(P, spar, kslot, true, c);
   __syncthreads();
@@ -480,6 +481,12 @@ __device__ inline void mixed_step_group(const ProbDev& P, int g, int spar, int k
     const z32* cb = P.C0[f] + size_t(rb) * P.ld;
     const z32* gm = P.G32[f] + size_t(m) * P.ld;
     float par = 0.f, pai = 0.f, pbr = 0.f, pbi = 0.f;
+    // this row pair's panel entries, issued ahead of the stream
+    z32 pka{0.f, 0.f}, pkb{0.f, 0.f};
+    if (lane < slot) {
+      if (va) pka = P.Pp[f][size_t(lane) * P.ld + ra];
+      if (vb) pkb = P.Pp[f][size_t(lane) * P.ld + rb];
+    }
     int j0 = 0;
     if (pre) {
 #pragma unroll
@@ -508,14 +515,12 @@ __device__ inline void mixed_step_group(const ProbDev& P, int g, int spar, int k
     if (lane < slot) {
       const z64 cc = pc[f][lane];
       if (va) {
-        const z32 pk = P.Pp[f][size_t(lane) * P.ld + ra];
-        par += float(cc.re * pk.re - cc.im * pk.im);
-        pai += float(cc.re * pk.im + cc.im * pk.re);
+        par += float(cc.re * pka.re - cc.im * pka.im);
+        pai += float(cc.re * pka.im + cc.im * pka.re);
       }
       if (vb) {
-        const z32 pk = P.Pp[f][size_t(lane) * P.ld + rb];
-        pbr += float(cc.re * pk.re - cc.im * pk.im);
-        pbi += float(cc.re * pk.im + cc.im * pk.re);
+        pbr += float(cc.re * pkb.re - cc.im * pkb.im);
+        pbi += float(cc.re * pkb.im + cc.im * pkb.re);
       }
     }
     par = wave_sumf(par);
@@ -530,12 +535,9 @@ __device__ inline void mixed_step_group(const ProbDev& P, int g, int spar, int k
         P.Pp[f][size_t(slot) * P.ld + r] = p32;
         const z64 p = up32(p32);
         const z64 ap = zmul(c.alpha[f], p);
-        const z64* ebuf = (dp ? P.EB[f] : P.E[f]);
-        const z64* rbuf = (dp ? P.RpB[f] : P.Rp[f]);
-        const z64* tbuf = (dp ? P.tauB[f] : P.tau[f]);
-        const z64 Ein = pick0(f, h ? e0b : e0a, ebuf + r);
-        const z64 Rin = pick0(f, h ? r0b : r0a, rbuf + r);
-        const z64 Tin = pick0(f, h ? t0b : t0a, tbuf + r);
+        const z64 Ein = vpre[w][f][h][0];
+        const z64 Rin = vpre[w][f][h][1];
+        const z64 Tin = vpre[w][f][h][2];
         const z64 Ei = zadd(Ein, zmul(ap, c.Em[f]));
         const z64 Rpi = zadd(Rin, zmul(ap, c.Rpm[f]));
         const z64 tau = zadd(Tin, zmul(ap, p));
