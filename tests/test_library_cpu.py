@@ -145,3 +145,37 @@ def test_objective_norm_matches_oracle():
     with pytest.raises(P.PngfError):
         h.objective_norm(2)
     h.close()
+
+
+@pytest.mark.parametrize("shape", ["ring", "ell", "holes"])
+def test_precompute_irregular_design_masks(shape):
+    """The nested-dissection precompute on design regions that are not
+    rectangles (a ring around an exterior island, an L, a block with interior
+    exterior cells): G, b, G_OD and x_b against the oracle's column solves."""
+    p = workloads.tiny(seed=6, n=34, npml=5, side=12, nfreq=2)
+    i0, j0 = p.design_origin
+    m = p.design_mask
+    if shape == "ring":
+        m[j0 + 4:j0 + 8, i0 + 4:i0 + 8] = 0
+    elif shape == "ell":
+        m[j0:j0 + 6, i0 + 6:i0 + 12] = 0
+    else:
+        m[j0 + 2, i0 + 3] = 0
+        m[j0 + 7:j0 + 9, i0 + 8] = 0
+        m[j0 + 5, i0 + 5:i0 + 7] = 0
+    nd = int(m.sum())
+    p.init_bits = p.init_bits[:nd]
+    p.perms = np.stack([np.random.default_rng(1).permutation(nd).astype(np.int32)])
+    h = P.Handle(p)
+    assert h.n_d == nd
+    for fi in range(2):
+        G, b, god, xb = h.get_precompute(fi)
+        Go = oracle.green_dd(p, fi)
+        _, bo, xbo = background(p, fi)
+        assert np.abs(G - Go).max() < 1e-11 * np.abs(Go).max()
+        assert np.abs(G - G.T).max() == 0.0
+        assert np.abs(b - bo).max() < 1e-11 * np.abs(bo).max()
+        assert abs(xb - xbo) < 1e-11 * abs(xbo)
+        Godo = oracle.green_od(p, fi)
+        assert np.abs(god - Godo[0]).max() < 1e-11 * np.abs(Godo).max()
+    h.close()
