@@ -44,7 +44,9 @@ hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64
                            int splits, z64* work, hipStream_t s, int* nz_out = nullptr);
 
 constexpr int kGjNb = 16;
-constexpr int kUpdRows = 16;
+constexpr int kUpdRows = 16;      // rows per update workgroup (small systems)
+constexpr int kUpdRowsBig = 64;   // ... from kUpdBigFrom pivot rows on: the pivot rows'
+constexpr int kUpdBigFrom = 2048; // values and the panel factors are shared by more rows
 
 // K[a][b] = delta_ab - k2d G[s_a][s_b]; clears the pivot marks.
 __global__ __launch_bounds__(256) void k_gather_K(z64* K, const z64* G, int ld, const int32_t* sidx,
@@ -342,27 +344,28 @@ __global__ __launch_bounds__(256) void k_tsel_fused(const z64* Pb, int n, int k0
 // values go to PRc instead of S; the previous panel's pivot rows, held in
 // PRp, are read from there and written back to S.  Panel columns get Pt; the
 // next panel's columns (updated here) are also gathered into Pn.  A
-// workgroup covers 64 columns x kUpdRows rows; thread (g, c) owns column c
+// workgroup covers 64 columns x ROWS rows; thread (g, c) owns column c
 // and rows g, g+4, ...
+template <int ROWS>
 __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0, int ncols,
                                                    const int32_t* used, const int32_t* piv,
                                                    const z64* B11inv, const z64* Pb,
                                                    const z64* PRp, z64* PRc, z64* Pn) {
   static_assert(kGjNb * kGjNb == 256, "one B11^-1 entry per thread");
   __shared__ z64 Bi[kGjNb][kGjNb];
-  __shared__ z64 R[kUpdRows][kGjNb + 1];
-  __shared__ z64 Pt[kUpdRows][kGjNb + 1];
+  __shared__ z64 R[ROWS][kGjNb + 1];
+  __shared__ z64 Pt[ROWS][kGjNb + 1];
   // 1 + c: pivot c of this panel; -(1 + c): pivot c of the previous one; 0
-  __shared__ int kind[kUpdRows];
+  __shared__ int kind[ROWS];
   const int tid = threadIdx.x;
-  const int r0 = blockIdx.y * kUpdRows;
+  const int r0 = blockIdx.y * ROWS;
   Bi[tid / kGjNb][tid % kGjNb] = B11inv[tid];
-  for (int e = tid; e < kUpdRows * kGjNb; e += 256) {
+  for (int e = tid; e < ROWS * kGjNb; e += 256) {
     const int rr = e / kGjNb, c = e % kGjNb;
     const int r = r0 + rr;
     R[rr][c] = (r < n && c < ncols) ? Pb[size_t(r) * kGjNb + c] : z64{0.0, 0.0};
   }
-  if (tid < kUpdRows) {
+  if (tid < ROWS) {
     const int r = r0 + tid;
     const int u = (r < n) ? used[r] - 1 : -1;
     int kd = 0;
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0
     kind[tid] = kd;
   }
   __syncthreads();
-  for (int e = tid; e < kUpdRows * kGjNb; e += 256) {
+  for (int e = tid; e < ROWS * kGjNb; e += 256) {
     const int rr = e / kGjNb, cc = e % kGjNb;
     z64 out{0.0, 0.0};
     if (cc < ncols) {
@@ -391,7 +394,7 @@ __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0
   const int rg = tid >> 6;
   if (j >= n) return;
   if (j >= k0 && j < k0 + ncols) {
-    for (int rr = rg; rr < kUpdRows && r0 + rr < n; rr += 4) {
+    for (int rr = rg; rr < ROWS && r0 + rr < n; rr += 4) {
       const int kd = kind[rr];
       z64* dst = (kd > 0) ? PRc + size_t(kd - 1) * ld + j : S + size_t(r0 + rr) * ld + j;
       *dst = Pt[rr][j - k0];
@@ -404,7 +407,7 @@ __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0
 #pragma unroll
   for (int c = 0; c < kGjNb; ++c)
     b[c] = (c < ncols) ? S[size_t(piv[k0 + c]) * ld + j] : z64{0.0, 0.0};
-  for (int rr = rg; rr < kUpdRows && r0 + rr < n; rr += 4) {
+  for (int rr = rg; rr < ROWS && r0 + rr < n; rr += 4) {
     const int kd = kind[rr];
     z64* row = S + size_t(r0 + rr) * ld + j;
     z64 acc{0.0, 0.0};
@@ -587,9 +590,16 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
                            cand, cnt, g, piv, used, B11inv, status);
       }
       const bool odd = (k0 / kGjNb) & 1;
-      hipLaunchKernelGGL(k_gj_update, dim3((ns + 63) / 64, (ns + kUpdRows - 1) / kUpdRows),
-                         dim3(256), 0, s, S, ld, ns, k0, nc, used, piv, B11inv, Pb,
-                         odd ? PRa : PRb, odd ? PRb : PRa, Pn);
+      if (ns >= kUpdBigFrom)
+        hipLaunchKernelGGL(k_gj_update<kUpdRowsBig>,
+                           dim3((ns + 63) / 64, (ns + kUpdRowsBig - 1) / kUpdRowsBig), dim3(256),
+                           0, s, S, ld, ns, k0, nc, used, piv, B11inv, Pb, odd ? PRa : PRb,
+                           odd ? PRb : PRa, Pn);
+      else
+        hipLaunchKernelGGL(k_gj_update<kUpdRows>,
+                           dim3((ns + 63) / 64, (ns + kUpdRows - 1) / kUpdRows), dim3(256), 0, s,
+                           S, ld, ns, k0, nc, used, piv, B11inv, Pb, odd ? PRa : PRb,
+                           odd ? PRb : PRa, Pn);
       z64* t = Pb;
       Pb = Pn;
       Pn = t;

@@ -334,14 +334,15 @@ __device__ inline void plain_step_row(const ProbDev& P, int i, int spar, int ksl
   __shared__ double red[2 * (kRowThreads / 64)];
   const int tid = threadIdx.x;
   const int dp = spar;
-  z64 row[NPL], grow[NPL];
+  // the row of C^-1 lives in registers; G's row is read in the tau pass
+  // (holding both would halve the waves per SIMD at 32 entries per lane)
+  z64 row[NPL];
   if (P.nfreq == 1) {
     const z64* ci = (dp ? P.CinvB[0] : P.Cinv[0]) + size_t(i) * P.ld;
-    const z64* Gi = P.G[0] + size_t(i) * P.ld;
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
       const int j = tid + t * kRowThreads;
-      if (j < P.nd) { row[t] = ci[j]; grow[t] = Gi[j]; }
+      if (j < P.nd) row[t] = ci[j];
     }
   }
   // this row's vector entries, also independent of the decision
@@ -374,7 +375,7 @@ __device__ inline void plain_step_row(const ProbDev& P, int i, int spar, int ksl
 #pragma unroll
       for (int t = 0; t < NPL; ++t) {
         const int j = tid + t * kRowThreads;
-        if (j < P.nd) { row[t] = ci[j]; grow[t] = Gi[j]; }
+        if (j < P.nd) row[t] = ci[j];
       }
     }
     z64 acc{0.0, 0.0};
@@ -392,7 +393,7 @@ __device__ inline void plain_step_row(const ProbDev& P, int i, int spar, int ksl
       if (j < P.nd) {
         row[t] = zfma(ap, q[j], row[t]);
         co[j] = row[t];
-        acc = zfma(row[t], grow[t], acc);
+        acc = zfma(row[t], Gi[j], acc);
       }
     }
     const z64 tau = block_zsum(acc, red);

@@ -12,6 +12,12 @@ is unchanged.
     rocprofv3 --pmc FETCH_SIZE -d OUT/bf -o run -- python bench.py ...
     rocprofv3 --pmc WRITE_SIZE -d OUT/bw -o run -- python bench.py ...
     python -m paper_2501_18054_amd.profiling summarize --dir OUT --kernel k_mixed_step ...
+
+Matrix-core utilization of the MFMA kernels from one counter pass
+(SQ_INSTS_VALU_MFMA_MOPS_F64/F32/BF16, SQ_INSTS_VALU_FMA_F64,
+SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE):
+
+    python -m paper_2501_18054_amd.profiling mfma --dir OUT/c1 --workload ... --out ...
 """
 from __future__ import annotations
 
@@ -115,10 +121,124 @@ def summarize(a):
     print(json.dumps(rec, indent=1))
 
 
+# dense peaks of MI355X (TFLOP/s) for the fraction columns
+PEAK_TFLOPS = {"F64": 78.6, "F32": 157.3, "BF16": 2500.0}
+SIMDS = 256 * 4
+
+
+def _kname(n):
+    n = n.replace("pngf::", "").replace("void ", "")
+    i = n.find("(")
+    return n[:i] if i > 0 else n
+
+
+def mfma(a):
+    """Per-kernel matrix-core and FP64-VALU work from one counter pass:
+    SQ_INSTS_VALU_MFMA_MOPS_* count 512 FLOP each, SQ_INSTS_VALU_FMA_F64 one
+    wave-wide FP64 FMA (64 lanes x 2 FLOP); SQ_VALU_MFMA_BUSY_CYCLES over
+    GRBM_GUI_ACTIVE x SIMDs is the matrix cores' busy fraction while the
+    kernel ran.  Durations are the dispatches' own timestamps."""
+    rows = _counter_rows(a.dir)
+    disp = {}
+    for r in rows:
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        d = disp.setdefault(key, {"name": _kname(r["Kernel_Name"]),
+                                  "ns": float(r["End_Timestamp"]) - float(r["Start_Timestamp"])})
+        c = r["Counter_Name"]
+        v = float(r["Counter_Value"])
+        if c == "GRBM_GUI_ACTIVE":
+            d[c] = max(d.get(c, 0.0), v)
+        else:
+            d[c] = d.get(c, 0.0) + v
+    agg = {}
+    for d in disp.values():
+        g = agg.setdefault(d["name"], {"n": 0, "ns": 0.0, "F64": 0.0, "F32": 0.0, "BF16": 0.0,
+                                       "valu64": 0.0, "busy": 0.0, "active": 0.0})
+        g["n"] += 1
+        g["ns"] += d["ns"]
+        g["F64"] += 512.0 * d.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
+        g["F32"] += 512.0 * d.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)
+        g["BF16"] += 512.0 * d.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0)
+        g["valu64"] += 128.0 * d.get("SQ_INSTS_VALU_FMA_F64", 0.0)
+        g["busy"] += d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        g["active"] += d.get("GRBM_GUI_ACTIVE", 0.0) * SIMDS
+    keep = [(k, g) for k, g in agg.items()
+            if g["F64"] + g["F32"] + g["BF16"] + g["valu64"] > 0.0]
+    keep.sort(key=lambda kg: -kg[1]["ns"])
+    out = []
+    out.append(f"# Matrix-core and FP64-VALU work per kernel: {a.workload}\n\n")
+    out.append("Command (repository root, one MI355X, one counter pass):\n\n")
+    for c in a.commands:
+        out.append(f"    {c}\n")
+    out.append("\nFLOP from the counters (MFMA: 512 per SQ_INSTS_VALU_MFMA_MOPS_* count; FP64 "
+               "VALU: 128 per wave-wide SQ_INSTS_VALU_FMA_F64), divided by the dispatches' "
+               "own durations; peaks: FP64 78.6, FP32 157.3, BF16 2500 TFLOP/s (dense). "
+               "MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 1024 SIMDs). "
+               "Dispatches run one at a time under counter collection.\n\n")
+    out.append("| kernel | launches | total ms | MFMA F64 TFLOP/s (of peak) | MFMA F32 TFLOP/s | "
+               "MFMA BF16 TFLOP/s | VALU F64 TFLOP/s | MFMA busy |\n|---|---|---|---|---|---|---|---|\n")
+    for k, g in keep:
+        t = g["ns"] * 1e-9
+        def rate(x, peak=None):
+            if x <= 0.0:
+                return "-"
+            r = x / t / 1e12
+            return f"{r:.2f} ({100.0 * r / peak:.1f}%)" if peak else f"{r:.2f}"
+        busy = f"{100.0 * g['busy'] / g['active']:.1f}%" if g["active"] > 0 else "-"
+        out.append(f"| `{k}` | {g['n']} | {g['ns'] / 1e6:.2f} | {rate(g['F64'], PEAK_TFLOPS['F64'])} | "
+                   f"{rate(g['F32'], PEAK_TFLOPS['F32'])} | {rate(g['BF16'], PEAK_TFLOPS['BF16'])} | "
+                   f"{rate(g['valu64'], PEAK_TFLOPS['F64'])} | {busy} |\n")
+    text = "".join(out)
+    with open(os.path.join(ROOT, "profiles", a.out + ".md"), "w") as fh:
+        fh.write(text)
+    print(text)
+
+
+def stats(a):
+    """Kernel-time table from a rocprofv3 --kernel-trace --stats CSV run."""
+    files = glob.glob(os.path.join(a.dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_stats.csv under {a.dir}")
+    rows = []
+    with open(files[0]) as fh:
+        rows = list(csv.DictReader(fh))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"# Kernel-time summary: {a.workload}\n\n",
+           "Command (repository root, one MI355X):\n\n"]
+    for c in a.commands:
+        out.append(f"    {c}\n")
+    if a.note:
+        out.append("\n" + a.note + "\n")
+    out.append("\n| kernel | launches | total ms | avg us | share |\n|---|---|---|---|---|\n")
+    for r in rows[:a.top]:
+        t = float(r["TotalDurationNs"])
+        n = int(float(r["Calls"]))
+        out.append(f"| `{_kname(r['Name'])}` | {n} | {t / 1e6:.2f} | {t / n / 1e3:.2f} | "
+                   f"{100.0 * t / tot:.1f}% |\n")
+    out.append(f"\nTotal kernel time {tot / 1e9:.3f} s.\n")
+    text = "".join(out)
+    with open(os.path.join(ROOT, "profiles", a.out + ".md"), "w") as fh:
+        fh.write(text)
+    print(text)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     sub.add_parser("copy")
+    st = sub.add_parser("stats")
+    st.add_argument("--dir", required=True)
+    st.add_argument("--workload", required=True)
+    st.add_argument("--out", required=True)
+    st.add_argument("--note", default="")
+    st.add_argument("--top", type=int, default=30)
+    st.add_argument("--commands", nargs="*", default=[])
+    mf = sub.add_parser("mfma")
+    mf.add_argument("--dir", required=True)
+    mf.add_argument("--workload", required=True)
+    mf.add_argument("--out", required=True)
+    mf.add_argument("--commands", nargs="*", default=[])
     s = sub.add_parser("summarize")
     s.add_argument("--dir", required=True)
     s.add_argument("--kernel", required=True)
@@ -134,6 +254,10 @@ def main():
     a = ap.parse_args()
     if a.cmd == "copy":
         copy()
+    elif a.cmd == "mfma":
+        mfma(a)
+    elif a.cmd == "stats":
+        stats(a)
     else:
         summarize(a)
 
