@@ -105,6 +105,15 @@ enum { PNGF_FP64_PLAIN = 0, PNGF_MIXED = 1, PNGF_RFORM = 2 };
  * steps (kernel class "accept") are timed, which keeps the events' own cost
  * off every other launch. */
 #define PNGF_FLAG_TIMING_STEPS 4ull
+/* pngf_options.flags: invert the FP64 system matrix with the pivot search
+ * every time.  Without it, the S block of C (the pixels at eps_hi) is first
+ * inverted by blocked Gauss-Jordan on 64-column panels without row
+ * exchanges, whose rank-64 updates run on the FP64 matrix cores; a zero pivot
+ * of a diagonal block, or a probe residual ||K K^-1 v - v||_inf above
+ * tol (||K||_inf ||K^-1 v||_inf + ||v||_inf) for a fixed v (tol from
+ * pngf_set_inverse_check), sends that inversion to the pivot search
+ * instead.  Either way the result is C^-1 in FP64. */
+#define PNGF_FLAG_PIVOT_SEARCH 8ull
 
 typedef struct pngf_handle pngf_handle;
 
@@ -307,6 +316,16 @@ int pngf_kernel_times(pngf_handle *h, int32_t kernel_id, double *total_ms,
  * devices shared with other work and for tests of that path.  PNGF_EINVAL
  * unless polls >= 1. */
 int pngf_set_persist_spin(pngf_handle *h, int32_t polls);
+
+/* Bound of the probe residual that an inversion without row exchanges must
+ * meet (see PNGF_FLAG_PIVOT_SEARCH; default 1e-12).  tol = 0 sends every
+ * inversion to the pivot search, for tests of that path.  PNGF_EINVAL
+ * unless tol >= 0. */
+int pngf_set_inverse_check(pngf_handle *h, double tol);
+
+/* Counts of the FP64 inversions this handle finished without row exchanges
+ * and with the pivot search (either pointer may be NULL). */
+int pngf_inverse_stats(pngf_handle *h, int64_t *unpivoted, int64_t *pivoted);
 
 /* For tests of the recovery path: the next n FP64 block-Woodbury refreshes
  * of the mixed search report their capacitance matrix as singular, so the

@@ -20,6 +20,7 @@ PNGF_RFORM = 2
 PNGF_FLAG_TIMING = 1
 PNGF_FLAG_STEP_LAUNCHES = 2
 PNGF_FLAG_TIMING_STEPS = 4
+PNGF_FLAG_PIVOT_SEARCH = 8
 PNGF_PIXEL_DIELECTRIC = 0
 PNGF_PIXEL_PEC = 1
 
@@ -91,6 +92,8 @@ EXPORTS = {
     "pngf_kernel_times": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double),
                            C.POINTER(C.c_int64)], C.c_int),
     "pngf_set_persist_spin": ([C.c_void_p, C.c_int32], C.c_int),
+    "pngf_set_inverse_check": ([C.c_void_p, C.c_double], C.c_int),
+    "pngf_inverse_stats": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "pngf_force_singular_refresh": ([C.c_void_p, C.c_int32], C.c_int),
     "pngf_destroy": ([C.c_void_p], C.c_int),
     "pngf_batch_create": ([C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
@@ -157,16 +160,18 @@ def _cplx(a):
 
 def default_options(precision=PNGF_FP64_PLAIN, max_accepts=1 << 16, max_sweeps=32,
                     eta=1e-9, k_refresh=None, k_fold=0, guard=0.0, timing=False, max_tile=0,
-                    step_launches=False, timing_steps=False):
+                    step_launches=False, timing_steps=False, pivot_search=False):
     """Options of pngf_bind; k_refresh defaults to 32 for the mixed form and
     to 0 (no re-anchoring) for the others.  step_launches: one kernel launch
     per step of the mixed search instead of one launch per batch.  timing:
     events around every kernel class; timing_steps: around the step
-    launches only."""
+    launches only.  pivot_search: every FP64 inversion with the pivot search
+    (else without row exchanges first, checked)."""
     if k_refresh is None:
         k_refresh = 32 if precision == PNGF_MIXED else 0
     flags = ((PNGF_FLAG_TIMING if timing else 0) | (PNGF_FLAG_STEP_LAUNCHES if step_launches else 0)
-             | (PNGF_FLAG_TIMING_STEPS if timing_steps else 0))
+             | (PNGF_FLAG_TIMING_STEPS if timing_steps else 0)
+             | (PNGF_FLAG_PIVOT_SEARCH if pivot_search else 0))
     return Options(precision, k_refresh, k_fold, max_accepts, max_sweeps, max_tile, eta, guard,
                    flags)
 
@@ -359,6 +364,16 @@ class Handle:
     def force_singular_refresh(self, n):
         """Test hook: the next n block-Woodbury refreshes report singular."""
         self._check(lib().pngf_force_singular_refresh(self._h, int(n)))
+
+    def set_inverse_check(self, tol):
+        """Probe-residual bound of the inversion without row exchanges."""
+        self._check(lib().pngf_set_inverse_check(self._h, float(tol)))
+
+    def inverse_stats(self):
+        """(inversions without row exchanges, inversions with the pivot search)."""
+        a, b = C.c_int64(), C.c_int64()
+        self._check(lib().pngf_inverse_stats(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def set_persist_spin(self, polls):
         """Bound of a persistent-search grid-barrier wait, in polls."""

@@ -46,6 +46,21 @@ struct GemmIdx {
   const int32_t *rc = nullptr, *cc = nullptr;
 };
 
+// Workspace of the unpivoted blocked inversion (one per frequency): the
+// reduced panels of two consecutive panels (n_S x kNpNb each, row stride
+// kNpNb), the pivot rows of the current panel (kNpNb x ld), the inverse of
+// its diagonal block (kNpNb x kNpNb), the probe product y (n_S) and three
+// maxima of the residual check.
+constexpr int kNpNb = 64;
+struct NpWork {
+  z64* Pt[2];
+  z64* X;
+  z64* Bi;
+  z64* y;
+  unsigned long long* mx;
+  double tol;   // relative probe residual above which the result is rejected
+};
+
 // One output of a two-product GEMV pass:
 //   y[i] = beta w[i] + gamma w2[i] + alpha sum_j A[i,j] d_j v[j].
 struct GemvOut {

@@ -18,14 +18,15 @@
 // Pivoting is virtual (rows never move): column k uses pivot row p_k, so the
 // elimination is that of Pi K with (Pi K)[k,:] = K[p_k,:], the in-place result
 // M satisfies (Pi K)^-1[k,:] = M[p_k,:], and K^-1[i, p_l] = M[p_i, l].
-// A panel of kGjNb columns picks its pivot rows by tournament pivoting
-// (Grigori-Demmel-Xiang CALU): groups of 64 rows, one group per wave, each
-// propose kGjNb rows by partial-pivoting elimination in registers; the
-// proposals of four groups form the next level's group until one remains
-// (the first levels one wave per workgroup across the chip, the last ones in
-// one workgroup); the winners' block B11 is inverted and every row is reduced
-// independently, giving the Gauss-Jordan panel [-B01 B11^-1; B11^-1;
-// -B21 B11^-1].  Every column outside the panel then gets the rank-kGjNb
+// A panel of kGjNb columns picks its pivot rows by partial pivoting over
+// every candidate row in one workgroup (rows in registers, one LDS exchange
+// per column).  Above kGeppRows rows the candidates are first thinned by
+// tournament pivoting (Grigori-Demmel-Xiang CALU): groups of 64 rows, one
+// group per wave across the chip, each propose kGjNb rows by the same
+// elimination; the proposals of four groups form the next level's group
+// until one workgroup can take them all.  The winners' block B11 is inverted
+// and every row is reduced independently, giving the Gauss-Jordan panel
+// [-B01 B11^-1; B11^-1; -B21 B11^-1].  Every column outside the panel then gets the rank-kGjNb
 // update M[r,j] = (r pivot of this panel ? 0 : M[r,j]) + P[r,:] B1[:,j] with
 // B1 the panel's pivot rows before the update (the reduction of the panel
 // rows happens inside the update's workgroups, and the new pivot rows wait
@@ -47,26 +48,27 @@ constexpr int kGjNb = 16;
 constexpr int kUpdRows = 16;      // rows per update workgroup (small systems)
 constexpr int kUpdRowsBig = 64;   // ... from kUpdBigFrom pivot rows on: the pivot rows'
 constexpr int kUpdBigFrom = 2048; // values and the panel factors are shared by more rows
+constexpr int kGeppRows = 1024;   // candidates one partial-pivoting workgroup takes
 
 // K[a][b] = delta_ab - k2d G[s_a][s_b]; clears the pivot marks.
 __global__ __launch_bounds__(256) void k_gather_K(z64* K, const z64* G, int ld, const int32_t* sidx,
-                                                  int ns, double k2d, int32_t* used,
-                                                  int32_t* arrived) {
+                                                  int ns, double k2d, int32_t* used) {
   const int a = blockIdx.y;
   const int b = blockIdx.x * 256 + threadIdx.x;
-  if (a == 0 && b == 0) *arrived = 0;
   if (b >= ns) return;
   const z64 g = G[size_t(sidx[a]) * ld + sidx[b]];
   K[size_t(a) * ld + b] = z64{(a == b ? 1.0 : 0.0) - k2d * g.re, -k2d * g.im};
   if (a == 0) used[b] = 0;
 }
 
-// Panel columns [k0, k0+ncols) gathered into a contiguous n x kGjNb buffer.
+// Panel columns [k0, k0+ncols) gathered into a contiguous buffer, column
+// by column (entry (r, c) at Pb[c n + r]), so that consecutive rows of one
+// column are adjacent for the pivot search's loads.
 __global__ __launch_bounds__(256) void k_gj_panel_in(const z64* S, int ld, int n, int k0,
                                                      int ncols, z64* Pb) {
   const int e = blockIdx.x * 256 + threadIdx.x;
-  const int r = e / kGjNb, c = e % kGjNb;
-  if (r < n) Pb[e] = (c < ncols) ? S[size_t(r) * ld + k0 + c] : z64{0.0, 0.0};
+  const int c = e / n, r = e % n;
+  if (c < kGjNb) Pb[e] = (c < ncols) ? S[size_t(r) * ld + k0 + c] : z64{0.0, 0.0};
 }
 
 // Broadcast of lane p's value to the wave (p wave-uniform).
@@ -118,14 +120,14 @@ __device__ __forceinline__ void wt_columns(z32 (&a)[kGjNb], bool& alive, int lan
 // complex-FP32 copies of the panel rows; writes them in pivot order to
 // out[0..count) and the count to *cnt.  Returns whether a chosen pivot had
 // magnitude zero.
-__device__ __forceinline__ bool wave_tournament(const z64* Pb, int ncols, int row, int lane,
-                                                int* out, int* cnt) {
+__device__ __forceinline__ bool wave_tournament(const z64* Pb, int n, int ncols, int row,
+                                                int lane, int* out, int* cnt) {
   z32 a[kGjNb];
 #pragma unroll
   for (int c = 0; c < kGjNb; ++c) {
     z32 v{0.f, 0.f};
     if (row >= 0 && c < ncols) {
-      const z64 x = Pb[size_t(row) * kGjNb + c];
+      const z64 x = Pb[size_t(c) * n + row];
       v = z32{float(x.re), float(x.im)};
     }
     a[c] = v;
@@ -138,29 +140,6 @@ __device__ __forceinline__ bool wave_tournament(const z64* Pb, int ncols, int ro
   if (order >= 0) out[order] = row;
   if (lane == 0) *cnt = nsel;
   return zero;
-}
-
-// Gauss-Jordan column C of [B11 | I] held one column per lane (lane j holds
-// column j, rows in registers): the pivot row is every lane's own register C,
-// the factors column C come from lane C by readlane.
-template <int C>
-__device__ __forceinline__ void gj_lane_column(z64 (&w)[kGjNb]) {
-  const z64 pv{lane_d(w[C].re, C), lane_d(w[C].im, C)};
-  const z64 inv = (zabs2(pv) > 0.0) ? zdiv(z64{1.0, 0.0}, pv) : z64{0.0, 0.0};
-  const z64 prow = zmul(w[C], inv);
-#pragma unroll
-  for (int i = 0; i < kGjNb; ++i) {
-    if (i == C) continue;
-    const z64 f{lane_d(w[i].re, C), lane_d(w[i].im, C)};
-    w[i] = zsub(w[i], zmul(f, prow));
-  }
-  w[C] = prow;
-}
-
-template <int... Cs>
-__device__ __forceinline__ void gj_lane_columns(z64 (&w)[kGjNb],
-                                                std::integer_sequence<int, Cs...>) {
-  (gj_lane_column<Cs>(w), ...);
 }
 
 // One level of a panel's tournament spread over the chip, one group per
@@ -180,160 +159,207 @@ __global__ __launch_bounds__(64) void k_tsel_wave(const z64* Pb, int n, int ncol
     const int grp = g * 4 + lane / kGjNb, u = lane % kGjNb;
     if (grp < ngin && u < gcnt[grp]) row = gin[grp * kGjNb + u];
   }
-  wave_tournament(Pb, ncols, row, lane, cand + g * kGjNb, cnt + g);
+  wave_tournament(Pb, n, ncols, row, lane, cand + g * kGjNb, cnt + g);
 }
 
-// Device-coherent accesses of the proposal lists that workgroups of one
-// launch exchange (written through to memory, read around the caches).
-__device__ __forceinline__ void st_coh(int32_t* p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int32_t ld_coh(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// 1/z in FP64: the hardware reciprocal estimate of |z|^2 refined by two
+// Newton steps (each squares the relative error), 0 for z = 0.  Shorter
+// than the IEEE division sequence on the pivot chains below.
+__device__ __forceinline__ z64 zrecip_newton(z64 z) {
+  const double d = z.re * z.re + z.im * z.im;
+  double x = __builtin_amdgcn_rcp(d);
+  x = fma(x, fma(-d, x, 1.0), x);
+  x = fma(x, fma(-d, x, 1.0), x);
+  if (!(d > 0.0)) x = 0.0;
+  return z64{z.re * x, -z.im * x};
 }
 
-// Wave 0 of the workgroup that holds the winners (prop[0..nsel), in pivot
-// order): piv, used and B11^-1 (inverted in FP64, one column per lane), and
-// a zero pivot of the final level flagged in *status.
-__device__ __forceinline__ void tsel_finish(const z64* Pb, int k0, int ncols, const int* win,
-                                            int nsel, bool zero, int lane, int32_t* piv,
-                                            int32_t* used, z64* B11inv, int32_t* status) {
-  if (zero && lane == 0) atomicOr(status, 1);
-  const int j = lane;
-  z64 w[kGjNb];
+// Workgroup barrier that orders LDS accesses only: the pivot search's waves
+// exchange nothing else through it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Lane (16 g + q)'s value to every lane of its 16-lane row g (DPP
+// row_newbcast), for a z64 held one per lane.
+template <int Q>
+__device__ __forceinline__ z64 row_bcast(z64 v) {
+  const unsigned long long r = static_cast<unsigned long long>(__double_as_longlong(v.re));
+  const unsigned long long i = static_cast<unsigned long long>(__double_as_longlong(v.im));
+  auto b = [](uint32_t x) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x150 | Q, 0xF, 0xF, false));
+  };
+  const uint64_t r2 = (uint64_t(b(uint32_t(r >> 32))) << 32) | b(uint32_t(r));
+  const uint64_t i2 = (uint64_t(b(uint32_t(i >> 32))) << 32) | b(uint32_t(i));
+  return z64{__longlong_as_double(static_cast<long long>(r2)),
+             __longlong_as_double(static_cast<long long>(i2))};
+}
+
+// LDS of the one-workgroup pivot search.  The keys cycle through three
+// buffers (column C uses C % 3): a key is cleared by thread 0 right after
+// the barrier that follows its last reads, two barriers before its next
+// use.  Every wave's candidate row of every column is kept (val), so the
+// winners' rows are the in-place LU of B11 without a copy.
+struct GeppLds {
+  unsigned long long key[3];
+  int win[kGjNb];
+  int wsel[kGjNb];
+  z64 val[kGjNb][16][kGjNb];
+};
+
+// Column C of the one-workgroup partial pivoting below, in FP64 on in-place
+// LU rows (entries left of C hold the row's multipliers, the rest its
+// reduced values).  Each wave reduces its key (the high word of |a_C|^2 + 1
+// for a live row, 0 for none: a 20-bit mantissa suffices to pick a pivot)
+// by DPP, and its best lane posts the key with the wave id and the row id
+// below it by one LDS 64-bit max (largest magnitude, then lowest wave wins)
+// and its row by plain stores; after the barrier one LDS read names the
+// winner, whose row every thread reads by broadcast to form its multiplier
+// (kept in a[C]) and reduce the rest of its row.
+template <int C>
+__device__ __forceinline__ void gepp_column(z64 (&a)[kGjNb], int row, bool& alive, int lane,
+                                            int wid, int nsel, GeppLds& sh, bool& zero) {
+  if (C >= nsel) return;
+  constexpr int buf = C % 3;
+  const double m = a[C].re * a[C].re + a[C].im * a[C].im;
+  const uint32_t key = alive ? uint32_t(__double_as_longlong(m) >> 32) + 1u : 0u;
+  const uint32_t mx = wave_max_u32(key);
+  const int p = __builtin_amdgcn_readfirstlane(
+      __ffsll(static_cast<long long>(__ballot(key == mx))) - 1);
+  if (lane == p && mx != 0u) {
+    atomicMax(&sh.key[buf], (static_cast<unsigned long long>(mx) << 32) |
+                                (uint32_t(15 - wid) << 24) | uint32_t(row));
 #pragma unroll
-  for (int r = 0; r < kGjNb; ++r) {
-    z64 v{0.0, 0.0};
-    if (j < kGjNb) {
-      if (r < nsel && j < ncols) v = Pb[size_t(win[r]) * kGjNb + j];
-      else if (r == j) v = z64{1.0, 0.0};       // padding of a ragged panel
-    } else if (j - kGjNb == r) {
-      v = z64{1.0, 0.0};
-    }
-    w[r] = v;
+    for (int q = 0; q < kGjNb; ++q) sh.val[C][wid][q] = a[q];
   }
-  gj_lane_columns(w, std::make_integer_sequence<int, kGjNb>{});
-  if (j >= kGjNb && j < 2 * kGjNb)
+  lds_barrier();
+  const unsigned long long k64 = sh.key[buf];
+  const uint32_t gm = uint32_t(k64 >> 32);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(k64));
+  const int w = 15 - int(lo >> 24);
+  const int prow = int(lo & 0xFFFFFFu);
+  if (gm <= 1u) zero = true;
+  if (wid == 0 && lane == 0) {
+    sh.win[C] = prow;
+    sh.wsel[C] = w;
+    sh.key[(C + 2) % 3] = 0ull;
+  }
+  const z64 l = zmul(a[C], zrecip_newton(sh.val[C][w][C]));
+  if (row == prow) alive = false;
+  a[C] = l;
 #pragma unroll
-    for (int r = 0; r < kGjNb; ++r) B11inv[r * kGjNb + (j - kGjNb)] = w[r];
-  if (lane < nsel) {
-    const int rw = win[lane];
-    piv[k0 + lane] = rw;
-    used[rw] = k0 + lane + 1;
+  for (int cc = C + 1; cc < kGjNb; ++cc) {
+    const z64 u = sh.val[C][w][cc];
+    a[cc].re = fma(-l.re, u.re, fma(l.im, u.im, a[cc].re));
+    a[cc].im = fma(-l.re, u.im, fma(-l.im, u.re, a[cc].im));
   }
 }
 
-// The rest of a panel's tournament in one workgroup of nw = blockDim/64 <= 16
-// waves.  Its first level is either level 0 itself (gcand null, n <= 64 nw:
-// one group of 64 rows per wave) or a merge of the ngin <= 4 nw groups that
-// k_tsel_l0 proposed (four per wave).  Each further level merges the
-// proposals of four groups in one wave, with a barrier between levels, until
-// wave 0 holds the winners.  Wave 0 then writes piv, used and B11^-1
-// (inverted in FP64, one column per lane), and flags a zero pivot of the
-// final level in *status.
-__global__ __launch_bounds__(1024) void k_tsel_wg(const z64* Pb, int n, int k0, int ncols,
-                                                  const int32_t* gcand, const int32_t* gcnt,
-                                                  int ngin, int32_t* piv, int32_t* used,
-                                                  z64* B11inv, int32_t* status) {
-  __shared__ int prop[2][16 * kGjNb];
-  __shared__ int pcnt[2][16];
+template <int... Cs>
+__device__ __forceinline__ void gepp_columns(z64 (&a)[kGjNb], int row, bool& alive, int lane,
+                                             int wid, int nsel, GeppLds& sh, bool& zero,
+                                             std::integer_sequence<int, Cs...>) {
+  (gepp_column<Cs>(a, row, alive, lane, wid, nsel, sh, zero), ...);
+}
+
+// Step Q of the two triangular solves of the finish (one column per 16-lane
+// row, lane i of the row holding entry i): forward, x_i -= L[i][Q] x_Q for
+// i > Q (L unit lower); backward, y_Q = x_Q / U[Q][Q], then x_i -= U[i][Q]
+// y_Q for i < Q.
+template <int Q>
+__device__ __forceinline__ void fwd_step(z64& x, const z64 (&lu)[kGjNb], int i) {
+  const z64 xq = row_bcast<Q>(x);
+  if (i > Q) x = zsub(x, zmul(lu[Q], xq));
+}
+template <int Q>
+__device__ __forceinline__ void bwd_step(z64& x, const z64 (&lu)[kGjNb], z64 invd, int i) {
+  if (i == Q) x = zmul(x, invd);
+  const z64 yq = row_bcast<Q>(x);
+  if (i < Q) x = zsub(x, zmul(lu[Q], yq));
+}
+template <int... Qs>
+__device__ __forceinline__ void fwd_steps(z64& x, const z64 (&lu)[kGjNb], int i,
+                                          std::integer_sequence<int, Qs...>) {
+  (fwd_step<Qs>(x, lu, i), ...);
+}
+template <int... Qs>
+__device__ __forceinline__ void bwd_steps(z64& x, const z64 (&lu)[kGjNb], z64 invd, int i,
+                                          std::integer_sequence<int, Qs...>) {
+  (bwd_step<kGjNb - 1 - Qs>(x, lu, invd, i), ...);
+}
+
+// After the pivot search: B11^-1 = U^-1 L^-1 from the winners' LU rows
+// (identity rows and columns pad a ragged panel), four columns per wave,
+// column j in the 16-lane row j % 4 of wave j / 4 (waves take further
+// columns if there are fewer than four).  Lane i of a row keeps row i of L
+// and U in registers and solves L x = e_j, then U y = x, by broadcasts
+// within the row.  Thread 0 writes piv and used.
+__device__ __forceinline__ void gepp_finish(GeppLds& sh, int k0, int ncols, int nsel, int t,
+                                            int nthreads, int32_t* piv, int32_t* used,
+                                            z64* B11inv) {
+  const int lane = t & 63, i = lane & 15;
+  z64 lu[kGjNb];
+#pragma unroll
+  for (int q = 0; q < kGjNb; ++q) {
+    z64 v{i == q ? 1.0 : 0.0, 0.0};
+    if (i < nsel && q < nsel) v = sh.val[i][sh.wsel[i]][q];
+    lu[q] = v;
+  }
+  const z64 invd = zrecip_newton(i < nsel ? sh.val[i][sh.wsel[i]][i] : z64{1.0, 0.0});
+  for (int j = t >> 4; j < kGjNb; j += nthreads >> 4) {
+    z64 x{i == j ? 1.0 : 0.0, 0.0};
+    fwd_steps(x, lu, i, std::make_integer_sequence<int, kGjNb>{});
+    bwd_steps(x, lu, invd, i, std::make_integer_sequence<int, kGjNb>{});
+    B11inv[i * kGjNb + j] = x;
+  }
+  if (t < nsel) {
+    const int rw = sh.win[t];
+    piv[k0 + t] = rw;
+    used[rw] = k0 + t + 1;
+  }
+}
+
+// Partial pivoting of one panel in FP64 over every candidate row at once, in
+// one workgroup of up to 16 waves: thread t holds candidate t's panel row in
+// registers (the rows [0, n) that are not pivots yet if gin is null, else
+// the proposals (gin, gcnt) of ngin tournament groups); every live row is
+// reduced by each chosen pivot.  Then B11^-1, piv and used; a zero pivot is
+// flagged in *status.
+__global__ __launch_bounds__(1024) void k_tsel_gepp(const z64* Pb, int n, int k0, int ncols,
+                                                    const int32_t* gin, const int32_t* gcnt,
+                                                    int ngin, int32_t* piv, int32_t* used,
+                                                    z64* B11inv, int32_t* status) {
+  __shared__ GeppLds sh;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  int groups = int(blockDim.x) >> 6;
-  int row = -1;
-  if (gcand == nullptr) {
-    row = wid * 64 + lane;
-    if (row >= n || used[row]) row = -1;
+  if (t < 2) sh.key[t] = 0ull;
+  int r = -1;
+  if (gin == nullptr) {
+    if (t < n && !used[t]) r = t;
   } else {
-    const int grp = wid * 4 + lane / kGjNb, u = lane % kGjNb;
-    if (grp < ngin && u < gcnt[grp]) row = gcand[grp * kGjNb + u];
+    const int grp = t / kGjNb, u = t % kGjNb;
+    if (grp < ngin && u < gcnt[grp]) r = gin[grp * kGjNb + u];
   }
-  bool zero = wave_tournament(Pb, ncols, row, lane, &prop[0][wid * kGjNb], &pcnt[0][wid]);
-  int cur = 0;
-  while (groups > 1) {
-    __syncthreads();
-    const int ng = (groups + 3) / 4;
-    if (wid < ng) {
-      const int grp = wid * 4 + lane / kGjNb, u = lane % kGjNb;
-      const int r = (grp < groups && u < pcnt[cur][grp]) ? prop[cur][grp * kGjNb + u] : -1;
-      zero = wave_tournament(Pb, ncols, r, lane, &prop[cur ^ 1][wid * kGjNb], &pcnt[cur ^ 1][wid]);
-    }
-    cur ^= 1;
-    groups = ng;
-  }
+  z64 a[kGjNb];
+#pragma unroll
+  for (int q = 0; q < kGjNb; ++q)
+    a[q] = (r >= 0 && q < ncols) ? Pb[size_t(q) * n + r] : z64{0.0, 0.0};
+  bool alive = r >= 0;
+  const int nsel = min(ncols, __syncthreads_count(alive));
+  bool zero = false;
+  gepp_columns(a, r, alive, lane, wid, nsel, sh, zero, std::make_integer_sequence<int, kGjNb>{});
+  if (zero && t == 0) atomicOr(status, 1);
   __syncthreads();
-  if (wid != 0) return;
-  tsel_finish(Pb, k0, ncols, &prop[cur][0], pcnt[cur][0], zero, lane, piv, used, B11inv, status);
+  gepp_finish(sh, k0, ncols, nsel, t, int(blockDim.x), piv, used, B11inv);
 }
 
-
-// A panel's whole tournament in one launch for 64 < n <= 4096: workgroup g
-// (four waves, one per SIMD) runs level 0 on rows [256g, 256g + 256), one
-// group of 64 rows per wave, and wave 0 merges its four groups; the
-// proposals go to cand/cnt through device-coherent stores, and the last
-// workgroup to count itself in on *arrived (each waits for its stores first)
-// merges every workgroup's proposals, four groups per wave, and finishes.  It
-// also puts *arrived back to zero for the next panel.
-__global__ __launch_bounds__(256) void k_tsel_fused(const z64* Pb, int n, int k0, int ncols,
-                                                    int32_t* cand, int32_t* cnt,
-                                                    int32_t* arrived, int32_t* piv,
-                                                    int32_t* used, z64* B11inv,
-                                                    int32_t* status) {
-  __shared__ int prop[2][4 * kGjNb];
-  __shared__ int pcnt[2][4];
-  __shared__ int s_last;
-  const int t = threadIdx.x, lane = t & 63, wid = t >> 6, g = blockIdx.x;
-  const int G = gridDim.x;
-  int row = g * 256 + wid * 64 + lane;
-  if (row >= n || used[row]) row = -1;
-  wave_tournament(Pb, ncols, row, lane, &prop[0][wid * kGjNb], &pcnt[0][wid]);
-  __syncthreads();
-  bool zero = false;
-  if (wid == 0) {
-    const int grp = lane / kGjNb, u = lane % kGjNb;
-    const int r = (u < pcnt[0][grp]) ? prop[0][grp * kGjNb + u] : -1;
-    zero = wave_tournament(Pb, ncols, r, lane, &prop[1][0], &pcnt[1][0]);
-    if (G > 1) {
-      const int c = pcnt[1][0];
-      if (lane < c) st_coh(cand + g * kGjNb + lane, prop[1][lane]);
-      if (lane == 0) st_coh(cnt + g, c);
-      __builtin_amdgcn_s_waitcnt(0);
-      if (lane == 0) s_last = (atomicAdd(arrived, 1) == G - 1) ? 1 : 0;
-    }
-  }
-  __syncthreads();
-  if (G == 1) {
-    // one workgroup: its merge is the final level
-    if (wid == 0)
-      tsel_finish(Pb, k0, ncols, &prop[1][0], pcnt[1][0], zero, lane, piv, used, B11inv,
-                  status);
-    return;
-  }
-  if (!s_last) return;
-  // the last workgroup: merge the G <= 16 proposal lists, four per wave
-  int groups = (G + 3) / 4;
-  {
-    const int grp = wid * 4 + lane / kGjNb, u = lane % kGjNb;
-    int r = -1;
-    if (wid < groups && grp < G && u < ld_coh(cnt + grp)) r = ld_coh(cand + grp * kGjNb + u);
-    if (wid < groups)
-      zero = wave_tournament(Pb, ncols, r, lane, &prop[0][wid * kGjNb], &pcnt[0][wid]);
-  }
-  int cur = 0;
-  while (groups > 1) {
-    __syncthreads();
-    const int ng = (groups + 3) / 4;
-    if (wid < ng) {
-      const int grp = wid * 4 + lane / kGjNb, u = lane % kGjNb;
-      const int r = (grp < groups && u < pcnt[cur][grp]) ? prop[cur][grp * kGjNb + u] : -1;
-      zero = wave_tournament(Pb, ncols, r, lane, &prop[cur ^ 1][wid * kGjNb], &pcnt[cur ^ 1][wid]);
-    }
-    cur ^= 1;
-    groups = ng;
-  }
-  __syncthreads();
-  if (wid != 0) return;
-  if (lane == 0) st_coh(arrived, 0);
-  tsel_finish(Pb, k0, ncols, &prop[cur][0], pcnt[cur][0], zero, lane, piv, used, B11inv, status);
+// One partial-pivoting workgroup over m <= kGeppRows candidates.
+void launch_tsel_gepp(const z64* Pb, int n, int k0, int ncols, const int32_t* gin,
+                      const int32_t* gcnt, int ngin, int m, int32_t* piv, int32_t* used,
+                      z64* B11inv, int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_tsel_gepp, dim3(1), dim3(64 * ((m + 63) / 64)), 0, s, Pb, n, k0, ncols,
+                     gin, gcnt, ngin, piv, used, B11inv, status);
 }
 
 // Rank-ncols update of one panel, with the panel's reduction by B11^-1
@@ -361,9 +387,9 @@ __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0
   const int r0 = blockIdx.y * ROWS;
   Bi[tid / kGjNb][tid % kGjNb] = B11inv[tid];
   for (int e = tid; e < ROWS * kGjNb; e += 256) {
-    const int rr = e / kGjNb, c = e % kGjNb;
+    const int c = e / ROWS, rr = e % ROWS;
     const int r = r0 + rr;
-    R[rr][c] = (r < n && c < ncols) ? Pb[size_t(r) * kGjNb + c] : z64{0.0, 0.0};
+    R[rr][c] = (r < n && c < ncols) ? Pb[size_t(c) * n + r] : z64{0.0, 0.0};
   }
   if (tid < ROWS) {
     const int r = r0 + tid;
@@ -417,7 +443,7 @@ __global__ __launch_bounds__(256) void k_gj_update(z64* S, int ld, int n, int k0
     for (int c = 0; c < kGjNb; ++c) acc = zfma(Pt[rr][c], b[c], acc);
     if (kd > 0) PRc[size_t(kd - 1) * ld + j] = acc;
     else *row = acc;
-    if (in_next) Pn[size_t(r0 + rr) * kGjNb + (j - nxt)] = acc;
+    if (in_next) Pn[size_t(j - nxt) * n + r0 + rr] = acc;
   }
 }
 
@@ -532,21 +558,317 @@ __global__ __launch_bounds__(kRowThreads) void k_output(ProbDev P, int f, const 
 }
 
 
+// --------------------------------------------- unpivoted blocked inversion
+// Gauss-Jordan on panels of kNpNb columns in their natural order, without
+// row exchanges: for panel J with diagonal block B = M[J,J],
+//     Pt[r,:] = (r in J) ? (B^-1)[r,:] : -M[r,J] B^-1,
+//     M[:,j] <- D M[:,j] + Pt M[J,j]  (j outside J, D zeroes the rows J),
+//     M[:,J] <- Pt,
+// so after the last panel M = K^-1.  The rank-kNpNb update is one GEMM on
+// the FP64 matrix cores.  Its stability rests on the pivots of the diagonal
+// blocks, which is what the system matrices of this method give (the
+// self-coupling G_ii dominates each column); a zero block pivot and a probe
+// residual ||K K^-1 v - v|| checked at the end flag the result in *status
+// (bit 2), and the caller then inverts again with the pivot search.
+
+// The block inverse: B^-1 of M[k0..k0+nb, k0..k0+nb] (identity-padded to
+// NB x NB) by in-place Gauss-Jordan without pivoting, in one workgroup of
+// 256 threads, thread (ti, tj) = (t / 16, t % 16) holding the T x T tile of
+// rows T ti .., columns T tj .. in registers.  Step C: the pivot column's
+// entries of a thread's rows come from lane C / T of its own 16-lane row
+// (ds_bpermute), the pivot row through LDS (two buffers by parity, one
+// barrier per step).  The steps are a loop, not unrolled: straight-line code
+// for all of them would not fit the instruction cache.
+__device__ __forceinline__ z64 lane_bperm(z64 v, int src) {
+  const int addr = src << 2;
+  const long long r = __double_as_longlong(v.re), i = __double_as_longlong(v.im);
+  const uint32_t r0 = __builtin_amdgcn_ds_bpermute(addr, int(uint32_t(r)));
+  const uint32_t r1 = __builtin_amdgcn_ds_bpermute(addr, int(uint32_t(uint64_t(r) >> 32)));
+  const uint32_t i0 = __builtin_amdgcn_ds_bpermute(addr, int(uint32_t(i)));
+  const uint32_t i1 = __builtin_amdgcn_ds_bpermute(addr, int(uint32_t(uint64_t(i) >> 32)));
+  return z64{__longlong_as_double(static_cast<long long>((uint64_t(r1) << 32) | r0)),
+             __longlong_as_double(static_cast<long long>((uint64_t(i1) << 32) | i0))};
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_np_blockinv(const z64* S, int ld, int k0, int nb, z64* Bi,
+                                                     int32_t* status) {
+  constexpr int T = NB / 16;
+  __shared__ z64 rowbuf[2][NB];
+  const int t = threadIdx.x, ti = t >> 4, tj = t & 15, lane = t & 63;
+  z64 a[T][T];
+#pragma unroll
+  for (int r = 0; r < T; ++r)
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const int i = T * ti + r, j = T * tj + k;
+      a[r][k] = (i < nb && j < nb) ? S[size_t(k0 + i) * ld + k0 + j]
+                                   : z64{i == j ? 1.0 : 0.0, 0.0};
+    }
+  bool bad = false;
+#pragma unroll 1
+  for (int C = 0; C < NB; ++C) {
+    const int oc = C / T, rc = C % T, par = C & 1;
+    const int src = (lane & 48) | oc;
+    z64 col[T];
+#pragma unroll
+    for (int r = 0; r < T; ++r) {
+      z64 v = a[r][0];
+#pragma unroll
+      for (int k = 1; k < T; ++k)
+        if (rc == k) v = a[r][k];
+      col[r] = lane_bperm(v, src);
+    }
+    if (ti == oc) {
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        z64 v = a[0][k];
+#pragma unroll
+        for (int r = 1; r < T; ++r)
+          if (rc == r) v = a[r][k];
+        rowbuf[par][T * tj + k] = v;
+      }
+    }
+    lds_barrier();
+    z64 u[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) u[k] = rowbuf[par][T * tj + k];
+    const z64 pv = rowbuf[par][C];
+    if (!(pv.re * pv.re + pv.im * pv.im > 1e-280)) bad = true;
+    const z64 inv = zrecip_newton(pv);
+    // a <- alpha_i a' + beta_i u'_j with a' = 0 and u' = 1 in the pivot
+    // column, alpha = 0 and beta = 1/p for the pivot row, alpha = 1 and
+    // beta = -a_iC/p elsewhere: the pivot row scaled, the pivot column
+    // -a_iC/p (1/p at the pivot), every other entry reduced
+#pragma unroll
+    for (int k = 0; k < T; ++k)
+      if (T * tj + k == C) u[k] = z64{1.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < T; ++r) {
+      const bool prow = T * ti + r == C;
+      const z64 f = zmul(col[r], inv);
+      const z64 beta = prow ? inv : z64{-f.re, -f.im};
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        z64 x = a[r][k];
+        if (prow || T * tj + k == C) x = z64{0.0, 0.0};
+        a[r][k] = zfma(beta, u[k], x);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < T; ++r)
+#pragma unroll
+    for (int k = 0; k < T; ++k) Bi[(T * ti + r) * NB + T * tj + k] = a[r][k];
+  if (bad && t == 0) atomicOr(status, 2);
+}
+
+// The reduced panel of rows [16 b, 16 b + 16): Pt[r][c] = (B^-1)[r - k0][c]
+// for r in the panel's rows J, else -sum_q M[r][k0 + q] (B^-1)[q][c]; rows
+// outside J also get the previous panel's columns finished
+// (M[r][k0p + c] = Ptp[r][c], c < nbp), which the GEMM left undefined.
+template <int NB>
+__global__ __launch_bounds__(256) void k_np_panel(z64* S, int ld, int n, int k0, int nb,
+                                                  const z64* Bi, z64* Pt, const z64* Ptp, int k0p,
+                                                  int nbp) {
+  __shared__ z64 sB[NB][NB + 1];
+  __shared__ z64 sR[16][NB + 1];
+  const int t = threadIdx.x;
+  const int r0 = blockIdx.x * 16;
+  for (int e = t; e < NB * NB; e += 256) sB[e / NB][e % NB] = Bi[e];
+  for (int e = t; e < 16 * NB; e += 256) {
+    const int rr = e / NB, q = e % NB, r = r0 + rr;
+    sR[rr][q] = (r < n && q < nb && (r < k0 || r >= k0 + nb)) ? S[size_t(r) * ld + k0 + q]
+                                                              : z64{0.0, 0.0};
+  }
+  __syncthreads();
+  const int rr = t >> 4, r = r0 + rr;
+  if (r >= n) return;
+  const bool inJ = r >= k0 && r < k0 + nb;
+#pragma unroll
+  for (int m = 0; m < NB / 16; ++m) {
+    const int c = (t & 15) + 16 * m;
+    z64 v{0.0, 0.0};
+    if (c < nb) {
+      if (inJ) {
+        v = sB[r - k0][c];
+      } else {
+        z64 acc{0.0, 0.0};
+        for (int q = 0; q < nb; ++q) acc = zfma(sR[rr][q], sB[q][c], acc);
+        v = z64{-acc.re, -acc.im};
+      }
+    }
+    Pt[size_t(r) * NB + c] = v;
+    if (Ptp && !inJ && c < nbp) S[size_t(r) * ld + k0p + c] = Ptp[size_t(r) * NB + c];
+  }
+}
+
+// The panel's pivot rows: X[q][j] = M[k0 + q][j] (the previous panel's
+// columns from Ptp, which M does not hold yet), then those rows of M zeroed.
+__global__ __launch_bounds__(256) void k_np_rows(z64* S, int ld, int n, int k0, int nb, z64* X,
+                                                 const z64* Ptp, int k0p, int nbp) {
+  const int q = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n || q >= nb) return;
+  z64* row = S + size_t(k0 + q) * ld;
+  X[size_t(q) * ld + j] = (Ptp && j >= k0p && j < k0p + nbp)
+                              ? Ptp[size_t(k0 + q) * kNpNb + (j - k0p)]
+                              : row[j];
+  row[j] = z64{0.0, 0.0};
+}
+
+// The last panel's columns: M[r][k0 + c] = Pt[r][c].
+__global__ __launch_bounds__(256) void k_np_last(z64* S, int ld, int n, int k0, int nb,
+                                                 const z64* Pt) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int r = e / kNpNb, c = e % kNpNb;
+  if (r < n && c < nb) S[size_t(r) * ld + k0 + c] = Pt[size_t(r) * kNpNb + c];
+}
+
+// piv = inv_p = identity (the unpivoted result is K^-1 itself); clears the
+// residual check's maxima.
+__global__ __launch_bounds__(256) void k_np_ident(int32_t* piv, int32_t* inv_p, int n,
+                                                  unsigned long long* mx) {
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  if (l < n) {
+    piv[l] = l;
+    inv_p[l] = l;
+  }
+  if (l < 4) mx[l] = 0ull;
+}
+
+// The probe vector of the residual check: fixed, entries of modulus <= 1
+// from an integer hash of the index.
+__device__ __forceinline__ z64 np_probe(int b) {
+  uint32_t h = uint32_t(b) * 2654435761u + 0x9E3779B9u;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  const double re = double(h & 0xFFFFu) / 65536.0 - 0.5;
+  const double im = double(h >> 16) / 65536.0 - 0.5;
+  return z64{re, im};
+}
+
+// y = M v over the S block (M = K^-1 after the panels); one row per
+// workgroup.
+__global__ __launch_bounds__(kRowThreads) void k_np_resid_y(const z64* S, int ld, int n, z64* y) {
+  __shared__ double red[2 * (kRowThreads / 64)];
+  const int a = blockIdx.x;
+  z64 acc{0.0, 0.0};
+  for (int b = threadIdx.x; b < n; b += kRowThreads)
+    acc = zfma(S[size_t(a) * ld + b], np_probe(b), acc);
+  const z64 t = block_zsum(acc, red);
+  if (threadIdx.x == 0) y[a] = t;
+}
+
+// Row a of K y - v with K = I - k2d G[S,S], the row's sum of |K_ab| and the
+// largest |y_b|, into the maxima mx[0..2] (non-negative doubles compare as
+// their bit patterns).
+__global__ __launch_bounds__(kRowThreads) void k_np_resid_k(const z64* G, int ld,
+                                                            const int32_t* sidx, int n, double k2d,
+                                                            const z64* y,
+                                                            unsigned long long* mx) {
+  __shared__ double red[2 * (kRowThreads / 64)];
+  __shared__ double rmax[kRowThreads / 64], rsum[kRowThreads / 64];
+  const int a = blockIdx.x, t = threadIdx.x;
+  const z64* g = G + size_t(sidx[a]) * ld;
+  z64 acc{0.0, 0.0};
+  double ksum = 0.0, ymax = 0.0;
+  for (int b = t; b < n; b += kRowThreads) {
+    const z64 gv = g[sidx[b]];
+    const z64 kab{(a == b ? 1.0 : 0.0) - k2d * gv.re, -k2d * gv.im};
+    const z64 yb = y[b];
+    acc = zfma(kab, yb, acc);
+    ksum += sqrt(zabs2(kab));
+    ymax = fmax(ymax, sqrt(zabs2(yb)));
+  }
+  const z64 ky = block_zsum(acc, red);
+  const double s = wave_sum(ksum);
+  double m = ymax;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((t & 63) == 0) {
+    rsum[t >> 6] = s;
+    rmax[t >> 6] = m;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double ks = 0.0, ym = 0.0;
+    for (int w = 0; w < kRowThreads / 64; ++w) {
+      ks += rsum[w];
+      ym = fmax(ym, rmax[w]);
+    }
+    const z64 r = zsub(ky, np_probe(a));
+    atomicMax(&mx[0], static_cast<unsigned long long>(__double_as_longlong(sqrt(zabs2(r)))));
+    atomicMax(&mx[1], static_cast<unsigned long long>(__double_as_longlong(ks)));
+    atomicMax(&mx[2], static_cast<unsigned long long>(__double_as_longlong(ym)));
+  }
+}
+
+// ||K y - v||_inf <= tol (||K||_inf ||y||_inf + ||v||_inf), else status bit 2
+// (||v||_inf <= 1).
+__global__ void k_np_check(const unsigned long long* mx, double tol, int32_t* status) {
+  const double res = __longlong_as_double(static_cast<long long>(mx[0]));
+  const double kn = __longlong_as_double(static_cast<long long>(mx[1]));
+  const double ym = __longlong_as_double(static_cast<long long>(mx[2]));
+  if (!(res <= tol * (kn * ym + 1.0))) atomicOr(status, 2);
+}
+
+hipError_t launch_inverse_np(z64* S, const z64* G, int ld, const int32_t* sidx, int ns,
+                             double k2d, const NpWork& w, int32_t* piv, int32_t* inv_p,
+                             int32_t* status, hipStream_t s) {
+  constexpr int NB = kNpNb;
+  const dim3 gcols((ns + 255) / 256);
+  hipLaunchKernelGGL(k_np_ident, gcols, dim3(256), 0, s, piv, inv_p, ns, w.mx);
+  int cur = 0, k0p = 0, nbp = 0;
+  const z64* Ptp = nullptr;
+  for (int k0 = 0; k0 < ns; k0 += NB) {
+    const int nb = std::min(NB, ns - k0);
+    z64* Pt = w.Pt[cur];
+    hipLaunchKernelGGL(k_np_blockinv<NB>, dim3(1), dim3(256), 0, s, S, ld, k0, nb, w.Bi, status);
+    hipLaunchKernelGGL(k_np_panel<NB>, dim3((ns + 15) / 16), dim3(256), 0, s, S, ld, ns, k0, nb,
+                       w.Bi, Pt, Ptp, k0p, nbp);
+    hipLaunchKernelGGL(k_np_rows, dim3(gcols.x, nb), dim3(256), 0, s, S, ld, ns, k0, nb, w.X, Ptp,
+                       k0p, nbp);
+    hipError_t e = launch_zgemm_ix(ns, ns, nb, Pt, NB, w.X, ld, false, S, ld, GemmIdx{},
+                                   z64{1.0, 0.0}, z64{1.0, 0.0}, 1, nullptr, s);
+    if (e != hipSuccess) return e;
+    Ptp = Pt;
+    k0p = k0;
+    nbp = nb;
+    cur ^= 1;
+  }
+  hipLaunchKernelGGL(k_np_last, dim3((ns * NB + 255) / 256), dim3(256), 0, s, S, ld, ns, k0p, nbp,
+                     Ptp);
+  hipLaunchKernelGGL(k_np_resid_y, dim3(ns), dim3(kRowThreads), 0, s, S, ld, ns, w.y);
+  hipLaunchKernelGGL(k_np_resid_k, dim3(ns), dim3(kRowThreads), 0, s, G, ld, sidx, ns, k2d, w.y,
+                     w.mx);
+  hipLaunchKernelGGL(k_np_check, dim3(1), dim3(1), 0, s, w.mx, w.tol, status);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ launchers
 // C^-1 of C = I - k2d G diag(bits) into Cinv.  sidx/zidx/pos describe S and Z
 // (pos[i] = index of i in S, or -1).  S, Pb, Pn are scratch, B1 (2 kGjNb x ld)
-// too.
+// too.  With np, the S block is inverted without row exchanges (status bit 2
+// if that is not accurate: invert again without np); else with the pivot
+// search (status bit 1 for a zero pivot).
 hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const int32_t* sidx,
                           const int32_t* zidx, const int32_t* pos, int ns, double k2d, z64* B1,
                           z64* Pb, z64* Pn, int32_t* piv, int32_t* inv_p, int32_t* used,
-                          int32_t* status, int32_t* tsbuf, z64* B11inv, hipStream_t s) {
+                          int32_t* status, int32_t* tsbuf, z64* B11inv, const NpWork* np,
+                          hipStream_t s) {
   const int nz = nd - ns;
-  if (ns > 0) {
-    // the arrival count of the fused tournament, then two proposal lists
-    // (ids and counts) of (kGjNb + 1) ints per group
+  if (ns > 0 && np) {
+    hipLaunchKernelGGL(k_gather_K, dim3((ns + 255) / 256, ns), dim3(256), 0, s, S, G, ld, sidx, ns,
+                       k2d, used);
+    const hipError_t e = launch_inverse_np(S, G, ld, sidx, ns, k2d, *np, piv, inv_p, status, s);
+    if (e != hipSuccess) return e;
+  } else if (ns > 0) {
+    // two tournament proposal lists (ids and counts) of (kGjNb + 1) ints
+    // per group
     const int g0 = (ns + 63) / 64;
-    int32_t* arrived = tsbuf;
-    int32_t* candA = tsbuf + 64;
+    int32_t* candA = tsbuf;
     int32_t* candB = candA + g0 * (kGjNb + 1);
     const dim3 gcols((ns + 255) / 256);
     // pivot rows of the even and odd panels, kept out of S during the
@@ -554,29 +876,24 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
     z64* PRa = B1;
     z64* PRb = B1 + size_t(kGjNb) * ld;
     hipLaunchKernelGGL(k_gather_K, dim3(gcols.x, ns), dim3(256), 0, s, S, G, ld, sidx, ns, k2d,
-                       used, arrived);
+                       used);
     hipLaunchKernelGGL(k_gj_panel_in, dim3((ns * kGjNb + 255) / 256), dim3(256), 0, s, S, ld, ns,
                        0, min(kGjNb, ns), Pb);
     for (int k0 = 0; k0 < ns; k0 += kGjNb) {
       const int nc = min(kGjNb, ns - k0);
-      if (ns <= 64) {
-        hipLaunchKernelGGL(k_tsel_wg, dim3(1), dim3(64), 0, s, Pb, ns, k0, nc,
-                           static_cast<const int32_t*>(nullptr),
-                           static_cast<const int32_t*>(nullptr), 0, piv, used, B11inv, status);
-      } else if (ns <= 16 * 256) {
-        const int g = (ns + 255) / 256;
-        hipLaunchKernelGGL(k_tsel_fused, dim3(g), dim3(256), 0, s, Pb, ns, k0, nc, candA,
-                           candA + g * kGjNb, arrived, piv, used, B11inv, status);
+      if (ns <= kGeppRows) {
+        // partial pivoting over every row in one workgroup
+        launch_tsel_gepp(Pb, ns, k0, nc, nullptr, nullptr, 0, ns, piv, used, B11inv, status, s);
       } else {
-        // level 0, then merge levels on the chip until one workgroup's
-        // sixteen waves can merge the rest (<= 64 groups)
+        // tournament levels on the chip (64-row groups, then merges of four
+        // groups' proposals) until one workgroup can take every proposal
         int g = (ns + 63) / 64;
         int32_t* cand = candA;
         int32_t* cnt = candA + g * kGjNb;
         hipLaunchKernelGGL(k_tsel_wave, dim3(g), dim3(64), 0, s, Pb, ns, nc, used,
                            static_cast<const int32_t*>(nullptr),
                            static_cast<const int32_t*>(nullptr), 0, cand, cnt);
-        while (g > 64) {
+        while (g * kGjNb > kGeppRows) {
           const int ng = (g + 3) / 4;
           int32_t* ocand = (cand == candA) ? candB : candA;
           int32_t* ocnt = ocand + ng * kGjNb;
@@ -586,8 +903,7 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
           cnt = ocnt;
           g = ng;
         }
-        hipLaunchKernelGGL(k_tsel_wg, dim3(1), dim3(64 * ((g + 3) / 4)), 0, s, Pb, ns, k0, nc,
-                           cand, cnt, g, piv, used, B11inv, status);
+        launch_tsel_gepp(Pb, ns, k0, nc, cand, cnt, g, g * kGjNb, piv, used, B11inv, status, s);
       }
       const bool odd = (k0 / kGjNb) & 1;
       if (ns >= kUpdBigFrom)

@@ -63,7 +63,8 @@ hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const int32_t* sidx,
                           const int32_t* zidx, const int32_t* pos, int ns, double k2d, z64* B1,
                           z64* Pb, z64* Pn, int32_t* piv, int32_t* inv_p, int32_t* used,
-                          int32_t* status, int32_t* tsbuf, z64* B11inv, hipStream_t s);
+                          int32_t* status, int32_t* tsbuf, z64* B11inv, const NpWork* np,
+                          hipStream_t s);
 hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t* bits, double ds,
                        z64 alpha, z64 beta, const z64* w, double gamma, const z64* w2, z64* y,
                        hipStream_t s, z32* A32 = nullptr);
@@ -123,7 +124,8 @@ struct Layout {
   // frequencies' systems are independent and run on their own streams)
   size_t off_S[pngf::kMaxFreq], off_B1[pngf::kMaxFreq], off_Pb[pngf::kMaxFreq],
       off_Pn[pngf::kMaxFreq], off_ts[pngf::kMaxFreq], off_B11[pngf::kMaxFreq],
-      off_piv[pngf::kMaxFreq], off_invp[pngf::kMaxFreq], off_used[pngf::kMaxFreq];
+      off_piv[pngf::kMaxFreq], off_invp[pngf::kMaxFreq], off_used[pngf::kMaxFreq],
+      off_np[pngf::kMaxFreq];
   size_t off_status, off_pbar, off_flag, off_band, off_u[pngf::kMaxFreq], off_r[pngf::kMaxFreq];
   size_t off_wP[pngf::kMaxFreq], off_wQ[pngf::kMaxFreq], off_wW[pngf::kMaxFreq],
       off_wCap[pngf::kMaxFreq], off_wWork[pngf::kMaxFreq];
@@ -151,6 +153,8 @@ struct pngf_handle {
   pngf_model* rank_model = nullptr;
   int rank_h = 0, rank_w = 0;
   int persist_spin = pngf::kPersistSpin;   // polls of one grid-barrier wait
+  double np_tol = 1e-12;           // probe-residual bound of the unpivoted inversion
+  int64_t n_inv_np = 0, n_inv_piv = 0;   // inversions by each path
   bool reform_c64 = false;   // reform_fields also writes C0^-1 (mixed refresh)
   bool persist_ok = false;   // a persistent launch of this search has run
   bool persist_aborted = false;   // the last one found a pending refresh singular
@@ -284,6 +288,10 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_piv[f] = take(size_t(nd) * sizeof(int32_t));
     L.off_invp[f] = take(size_t(nd) * sizeof(int32_t));
     L.off_used[f] = take(size_t(nd) * sizeof(int32_t));
+    // unpivoted inversion: two reduced panels, the pivot rows, the block
+    // inverse, the probe product and the check's maxima
+    L.off_np[f] = take((3 * size_t(pngf::kNpNb) * ld + size_t(pngf::kNpNb) * pngf::kNpNb + nd) *
+                           sizeof(z64) + 4 * sizeof(unsigned long long));
   }
   L.off_sidx = take(size_t(nd) * sizeof(int32_t));
   L.off_zidx = take(size_t(nd) * sizeof(int32_t));
@@ -432,6 +440,21 @@ int reform_fields(pngf_handle* h) {
   return PNGF_OK;
 }
 
+// The unpivoted inversion's workspace of frequency f.
+pngf::NpWork np_work(pngf_handle* h, int f) {
+  const size_t ld = size_t(h->ld), nb = size_t(pngf::kNpNb);
+  z64* base = at<z64>(h, h->lay.off_np[f]);
+  pngf::NpWork w;
+  w.Pt[0] = base;
+  w.Pt[1] = base + nb * ld;
+  w.X = base + 2 * nb * ld;
+  w.Bi = base + 3 * nb * ld;
+  w.y = w.Bi + nb * nb;
+  w.mx = reinterpret_cast<unsigned long long*>(w.y + h->pc.n_d);
+  w.tol = h->np_tol;
+  return w;
+}
+
 // Re-form C^-1 (FP64, on the device) from G and the device design bits for
 // every frequency, then E, R', x and f (reform_fields).
 int device_reinvert(pngf_handle* h) {
@@ -457,31 +480,45 @@ int device_reinvert(pngf_handle* h) {
   if (nd - ns > 0)
     HIPCHK(h, hipMemcpyAsync(d_zidx, zidx.data(), (nd - ns) * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync(d_pos, pos.data(), nd * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-  {
-    // one inversion per frequency, each on its own stream (a chain of
-    // single-workgroup panel kernels: concurrent frequencies fill more CUs)
-    Timer t(h, KID_LU);
-    int st = fork_streams(h);
-    if (st) return st;
-    for (int f = 0; f < F; ++f)
-      HIPCHK(h, pngf::launch_inverse(at<z64>(h, L.off_S[f]), P.Cinv[f], P.G[f], nd, ld, d_sidx,
-                                     d_zidx, d_pos, ns, P.k0sq[f] * P.deps,
-                                     at<z64>(h, L.off_B1[f]), at<z64>(h, L.off_Pb[f]),
-                                     at<z64>(h, L.off_Pn[f]), at<int32_t>(h, L.off_piv[f]),
-                                     at<int32_t>(h, L.off_invp[f]), at<int32_t>(h, L.off_used[f]),
-                                     status, at<int32_t>(h, L.off_ts[f]),
-                                     at<z64>(h, L.off_B11[f]), fstream(h, f)));
-    st = join_streams(h);
-    if (st) return st;
-    t.end(F);
+  // one inversion per frequency, each on its own stream; first without row
+  // exchanges, and with the pivot search where that result fails its check
+  // (or always, with PNGF_FLAG_PIVOT_SEARCH)
+  const bool force_piv = (h->opt.flags & PNGF_FLAG_PIVOT_SEARCH) != 0;
+  for (int pass = force_piv ? 1 : 0; pass < 2; ++pass) {
+    const bool pivoted = pass == 1;
+    if (pivoted && !force_piv)
+      HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
+    {
+      Timer t(h, KID_LU);
+      int st = fork_streams(h);
+      if (st) return st;
+      for (int f = 0; f < F; ++f) {
+        const pngf::NpWork np = np_work(h, f);
+        HIPCHK(h, pngf::launch_inverse(at<z64>(h, L.off_S[f]), P.Cinv[f], P.G[f], nd, ld, d_sidx,
+                                       d_zidx, d_pos, ns, P.k0sq[f] * P.deps,
+                                       at<z64>(h, L.off_B1[f]), at<z64>(h, L.off_Pb[f]),
+                                       at<z64>(h, L.off_Pn[f]), at<int32_t>(h, L.off_piv[f]),
+                                       at<int32_t>(h, L.off_invp[f]),
+                                       at<int32_t>(h, L.off_used[f]), status,
+                                       at<int32_t>(h, L.off_ts[f]), at<z64>(h, L.off_B11[f]),
+                                       pivoted ? nullptr : &np, fstream(h, f)));
+      }
+      st = join_streams(h);
+      if (st) return st;
+      t.end(F);
+    }
+    int32_t st_host = 0;
+    HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (!pivoted && (st_host & 2)) continue;
+    if (st_host) return fail(h, PNGF_ESINGULAR, "zero pivot while inverting the PNGF system matrix");
+    ++(pivoted ? h->n_inv_piv : h->n_inv_np);
+    break;
   }
   int st = reform_fields(h);
   if (st) return st;
-  int32_t st_host = 0;
-  HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   if (h->opt.flags & (PNGF_FLAG_TIMING | PNGF_FLAG_TIMING_STEPS)) collect_times(h);
-  if (st_host) return fail(h, PNGF_ESINGULAR, "zero pivot while inverting the PNGF system matrix");
   h->bits_ref = h->bits;
   h->cinv_stale = false;
   return PNGF_OK;
@@ -1746,6 +1783,19 @@ int pngf_force_singular_refresh(pngf_handle* h, int32_t n) {
 int pngf_set_persist_spin(pngf_handle* h, int32_t polls) {
   if (!h || polls < 1) return PNGF_EINVAL;
   h->persist_spin = polls;
+  return PNGF_OK;
+}
+
+int pngf_set_inverse_check(pngf_handle* h, double tol) {
+  if (!h || !(tol >= 0.0)) return PNGF_EINVAL;
+  h->np_tol = tol;
+  return PNGF_OK;
+}
+
+int pngf_inverse_stats(pngf_handle* h, int64_t* unpivoted, int64_t* pivoted) {
+  if (!h) return PNGF_EINVAL;
+  if (unpivoted) *unpivoted = h->n_inv_np;
+  if (pivoted) *pivoted = h->n_inv_piv;
   return PNGF_OK;
 }
 
