@@ -59,6 +59,16 @@ struct NpWork {
   z64* y;
   unsigned long long* mx;
   double tol;   // relative probe residual above which the result is rejected
+  const int32_t* rowmap;   // row of the working matrix for each pixel (S rows, then Z rows)
+};
+
+// The diagonal tile that a GEMM of the unpivoted inversion inverts once its
+// 64 x 64 output tile (tile, tile) is done: block rows and columns
+// [k0, k0 + nb) into Bi, a zero pivot flagged in *status (tile < 0: none).
+struct NpDiag {
+  int tile = -1, k0 = 0, nb = 0;
+  z64* Bi = nullptr;
+  int32_t* status = nullptr;
 };
 
 // One output of a two-product GEMV pass:

@@ -22,6 +22,7 @@
 #include <utility>
 
 #include "dev_state.h"
+#include "np_block.h"
 
 namespace pngf {
 
@@ -30,11 +31,11 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kGemmBK = 16;
 
 
-template <int WM, int WN, bool TRANSB>
+template <int WM, int WN, bool TRANSB, bool DINV = false>
 __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A, int lda,
                                                const z64* B, int ldb, z64* C, int ldc,
                                                GemmIdx ix, z64 alpha, z64 beta, int kchunk,
-                                               z64* work) {
+                                               z64* work, NpDiag dg) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   __shared__ double sAr[BM][kGemmBK + 1], sAi[BM][kGemmBK + 1];
   __shared__ double sBr[kGemmBK][BN + 1], sBi[kGemmBK][BN + 1];
@@ -152,6 +153,14 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A
           *c = beta0 ? av : zfma(beta, *c, av);
         }
       }
+  if (DINV && dg.tile >= 0 && int(blockIdx.x) == dg.tile && int(blockIdx.y) == dg.tile) {
+    // this workgroup's tile is the next diagonal block of the unpivoted
+    // inversion: invert it now, from memory (the fence makes the tile's
+    // stores visible to this workgroup's loads)
+    __threadfence();
+    __syncthreads();
+    np_block_inverse<kNpNb>(C, ldc, dg.k0, dg.nb, dg.Bi, dg.status);
+  }
 }
 
 // C = beta C + alpha sum_z work[z] (fixed summation order).
@@ -379,18 +388,18 @@ hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64
     dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
     if (transb)
       hipLaunchKernelGGL((k_zgemm<2, 2, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
-                         ldc, ix, alpha, beta, kchunk, wk);
+                         ldc, ix, alpha, beta, kchunk, wk, NpDiag{});
     else
       hipLaunchKernelGGL((k_zgemm<2, 2, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
-                         ldc, ix, alpha, beta, kchunk, wk);
+                         ldc, ix, alpha, beta, kchunk, wk, NpDiag{});
   } else {
     dim3 grid((N + 31) / 32, (M + 31) / 32, splits);
     if (transb)
       hipLaunchKernelGGL((k_zgemm<1, 1, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
-                         ldc, ix, alpha, beta, kchunk, wk);
+                         ldc, ix, alpha, beta, kchunk, wk, NpDiag{});
     else
       hipLaunchKernelGGL((k_zgemm<1, 1, false>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
-                         ldc, ix, alpha, beta, kchunk, wk);
+                         ldc, ix, alpha, beta, kchunk, wk, NpDiag{});
   }
   if (nz_out) *nz_out = splits > 1 ? splits : 0;
   if (splits > 1 && !nz_out) {
@@ -398,6 +407,19 @@ hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64
     hipLaunchKernelGGL(k_zgemm_reduce, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, M, N,
                        splits, work, C, ldc, ix, alpha, beta);
   }
+  return hipGetLastError();
+}
+
+// The rank-nb update of the unpivoted inversion, C += A B (64 x 64 tiles,
+// which line up with its panels), with the diagonal tile dg inverted by its
+// own workgroup.
+hipError_t launch_zgemm_np(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
+                           z64* C, int ldc, const NpDiag& dg, hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  static_assert(kNpNb == 64, "panel width equals the GEMM tile");
+  dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
+  hipLaunchKernelGGL((k_zgemm<2, 2, false, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                     C, ldc, GemmIdx{}, z64{1.0, 0.0}, z64{1.0, 0.0}, K, nullptr, dg);
   return hipGetLastError();
 }
 

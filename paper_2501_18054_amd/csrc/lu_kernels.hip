@@ -37,18 +37,22 @@
 #include <utility>
 
 #include "dev_state.h"
+#include "np_block.h"
 
 namespace pngf {
 
 hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
                            bool transb, z64* C, int ldc, const GemmIdx& ix, z64 alpha, z64 beta,
                            int splits, z64* work, hipStream_t s, int* nz_out = nullptr);
+hipError_t launch_zgemm_np(int M, int N, int K, const z64* A, int lda, const z64* B, int ldb,
+                           z64* C, int ldc, const NpDiag& dg, hipStream_t s);
 
 constexpr int kGjNb = 16;
 constexpr int kUpdRows = 16;      // rows per update workgroup (small systems)
 constexpr int kUpdRowsBig = 64;   // ... from kUpdBigFrom pivot rows on: the pivot rows'
 constexpr int kUpdBigFrom = 2048; // values and the panel factors are shared by more rows
 constexpr int kGeppRows = 1024;   // candidates one partial-pivoting workgroup takes
+constexpr int kNpFoldMax = 2048;  // largest n_S whose Z rows ride along in the panel updates
 
 // K[a][b] = delta_ab - k2d G[s_a][s_b]; clears the pivot marks.
 __global__ __launch_bounds__(256) void k_gather_K(z64* K, const z64* G, int ld, const int32_t* sidx,
@@ -160,26 +164,6 @@ __global__ __launch_bounds__(64) void k_tsel_wave(const z64* Pb, int n, int ncol
     if (grp < ngin && u < gcnt[grp]) row = gin[grp * kGjNb + u];
   }
   wave_tournament(Pb, n, ncols, row, lane, cand + g * kGjNb, cnt + g);
-}
-
-// 1/z in FP64: the hardware reciprocal estimate of |z|^2 refined by two
-// Newton steps (each squares the relative error), 0 for z = 0.  Shorter
-// than the IEEE division sequence on the pivot chains below.
-__device__ __forceinline__ z64 zrecip_newton(z64 z) {
-  const double d = z.re * z.re + z.im * z.im;
-  double x = __builtin_amdgcn_rcp(d);
-  x = fma(x, fma(-d, x, 1.0), x);
-  x = fma(x, fma(-d, x, 1.0), x);
-  if (!(d > 0.0)) x = 0.0;
-  return z64{z.re * x, -z.im * x};
-}
-
-// Workgroup barrier that orders LDS accesses only: the pivot search's waves
-// exchange nothing else through it.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Lane (16 g + q)'s value to every lane of its 16-lane row g (DPP
@@ -565,115 +549,51 @@ __global__ __launch_bounds__(kRowThreads) void k_output(ProbDev P, int f, const 
 //     M[:,j] <- D M[:,j] + Pt M[J,j]  (j outside J, D zeroes the rows J),
 //     M[:,J] <- Pt,
 // so after the last panel M = K^-1.  The rank-kNpNb update is one GEMM on
-// the FP64 matrix cores.  Its stability rests on the pivots of the diagonal
+// the FP64 matrix cores.  For small systems the Z rows of C, [W, I] with
+// W = -k2d G[Z,S], ride along below the S rows: Gauss-Jordan with the pivots
+// of K turns [K; W] into [K^-1; -W K^-1], which is C^-1[:, S] (the Z columns
+// of C^-1 are those of the identity), so no separate product forms
+// C^-1[Z, S] (for large ones that product reads W once, cheaper than once
+// per panel).  Its stability rests on the pivots of the diagonal
 // blocks, which is what the system matrices of this method give (the
 // self-coupling G_ii dominates each column); a zero block pivot and a probe
 // residual ||K K^-1 v - v|| checked at the end flag the result in *status
 // (bit 2), and the caller then inverts again with the pivot search.
 
-// The block inverse: B^-1 of M[k0..k0+nb, k0..k0+nb] (identity-padded to
-// NB x NB) by in-place Gauss-Jordan without pivoting, in one workgroup of
-// 256 threads, thread (ti, tj) = (t / 16, t % 16) holding the T x T tile of
-// rows T ti .., columns T tj .. in registers.  Step C: the pivot column's
-// entries of a thread's rows come from lane C / T of its own 16-lane row
-// (ds_bpermute), the pivot row through LDS (two buffers by parity, one
-// barrier per step).  The steps are a loop, not unrolled: straight-line code
-// for all of them would not fit the instruction cache.
-__device__ __forceinline__ z64 lane_bperm(z64 v, int src) {
-  const int addr = src << 2;
-  const long long r = __double_as_longlong(v.re), i = __double_as_longlong(v.im);
-  const uint32_t r0 = __builtin_amdgcn_ds_bpermute(addr, int(uint32_t(r)));
-  const uint32_t r1 = __builtin_amdgcn_ds_bpermute(addr, int(uint32_t(uint64_t(r) >> 32)));
-  const uint32_t i0 = __builtin_amdgcn_ds_bpermute(addr, int(uint32_t(i)));
-  const uint32_t i1 = __builtin_amdgcn_ds_bpermute(addr, int(uint32_t(uint64_t(i) >> 32)));
-  return z64{__longlong_as_double(static_cast<long long>((uint64_t(r1) << 32) | r0)),
-             __longlong_as_double(static_cast<long long>((uint64_t(i1) << 32) | i0))};
-}
-
+// Panel 0's block inverse (the later ones run in the GEMM that forms their
+// block, see k_zgemm).
 template <int NB>
 __global__ __launch_bounds__(256) void k_np_blockinv(const z64* S, int ld, int k0, int nb, z64* Bi,
                                                      int32_t* status) {
-  constexpr int T = NB / 16;
-  __shared__ z64 rowbuf[2][NB];
-  const int t = threadIdx.x, ti = t >> 4, tj = t & 15, lane = t & 63;
-  z64 a[T][T];
-#pragma unroll
-  for (int r = 0; r < T; ++r)
-#pragma unroll
-    for (int k = 0; k < T; ++k) {
-      const int i = T * ti + r, j = T * tj + k;
-      a[r][k] = (i < nb && j < nb) ? S[size_t(k0 + i) * ld + k0 + j]
-                                   : z64{i == j ? 1.0 : 0.0, 0.0};
-    }
-  bool bad = false;
-#pragma unroll 1
-  for (int C = 0; C < NB; ++C) {
-    const int oc = C / T, rc = C % T, par = C & 1;
-    const int src = (lane & 48) | oc;
-    z64 col[T];
-#pragma unroll
-    for (int r = 0; r < T; ++r) {
-      z64 v = a[r][0];
-#pragma unroll
-      for (int k = 1; k < T; ++k)
-        if (rc == k) v = a[r][k];
-      col[r] = lane_bperm(v, src);
-    }
-    if (ti == oc) {
-#pragma unroll
-      for (int k = 0; k < T; ++k) {
-        z64 v = a[0][k];
-#pragma unroll
-        for (int r = 1; r < T; ++r)
-          if (rc == r) v = a[r][k];
-        rowbuf[par][T * tj + k] = v;
-      }
-    }
-    lds_barrier();
-    z64 u[T];
-#pragma unroll
-    for (int k = 0; k < T; ++k) u[k] = rowbuf[par][T * tj + k];
-    const z64 pv = rowbuf[par][C];
-    if (!(pv.re * pv.re + pv.im * pv.im > 1e-280)) bad = true;
-    const z64 inv = zrecip_newton(pv);
-    // a <- alpha_i a' + beta_i u'_j with a' = 0 and u' = 1 in the pivot
-    // column, alpha = 0 and beta = 1/p for the pivot row, alpha = 1 and
-    // beta = -a_iC/p elsewhere: the pivot row scaled, the pivot column
-    // -a_iC/p (1/p at the pivot), every other entry reduced
-#pragma unroll
-    for (int k = 0; k < T; ++k)
-      if (T * tj + k == C) u[k] = z64{1.0, 0.0};
-#pragma unroll
-    for (int r = 0; r < T; ++r) {
-      const bool prow = T * ti + r == C;
-      const z64 f = zmul(col[r], inv);
-      const z64 beta = prow ? inv : z64{-f.re, -f.im};
-#pragma unroll
-      for (int k = 0; k < T; ++k) {
-        z64 x = a[r][k];
-        if (prow || T * tj + k == C) x = z64{0.0, 0.0};
-        a[r][k] = zfma(beta, u[k], x);
-      }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < T; ++r)
-#pragma unroll
-    for (int k = 0; k < T; ++k) Bi[(T * ti + r) * NB + T * tj + k] = a[r][k];
-  if (bad && t == 0) atomicOr(status, 2);
+  np_block_inverse<NB>(S, ld, k0, nb, Bi, status);
 }
 
-// The reduced panel of rows [16 b, 16 b + 16): Pt[r][c] = (B^-1)[r - k0][c]
+// One launch per panel with two kinds of workgroup (n rows, nc columns).
+// The first nrw = n / 16 form the reduced panel of rows [16 b, 16 b + 16): Pt[r][c] = (B^-1)[r - k0][c]
 // for r in the panel's rows J, else -sum_q M[r][k0 + q] (B^-1)[q][c]; rows
 // outside J also get the previous panel's columns finished
-// (M[r][k0p + c] = Ptp[r][c], c < nbp), which the GEMM left undefined.
+// (M[r][k0p + c] = Ptp[r][c], c < nbp), which the GEMM left undefined.  The
+// others copy the panel's pivot rows, X[q][j] = M[k0 + q][j] (the previous
+// panel's columns from Ptp, which M does not hold yet), and zero those rows
+// of M.  The two kinds touch disjoint rows of M.
 template <int NB>
-__global__ __launch_bounds__(256) void k_np_panel(z64* S, int ld, int n, int k0, int nb,
+__global__ __launch_bounds__(256) void k_np_panel(z64* S, int ld, int n, int nc, int k0, int nb,
                                                   const z64* Bi, z64* Pt, const z64* Ptp, int k0p,
-                                                  int nbp) {
+                                                  int nbp, z64* X, int nrw) {
   __shared__ z64 sB[NB][NB + 1];
   __shared__ z64 sR[16][NB + 1];
   const int t = threadIdx.x;
+  if (int(blockIdx.x) >= nrw) {
+    const int e = int(blockIdx.x) - nrw, ncb = (nc + 255) / 256;
+    const int q = e / ncb, j = (e % ncb) * 256 + t;
+    if (q >= nb || j >= nc) return;
+    z64* row = S + size_t(k0 + q) * ld;
+    X[size_t(q) * ld + j] = (Ptp && j >= k0p && j < k0p + nbp)
+                                ? Ptp[size_t(k0 + q) * kNpNb + (j - k0p)]
+                                : row[j];
+    row[j] = z64{0.0, 0.0};
+    return;
+  }
   const int r0 = blockIdx.x * 16;
   for (int e = t; e < NB * NB; e += 256) sB[e / NB][e % NB] = Bi[e];
   for (int e = t; e < 16 * NB; e += 256) {
@@ -703,26 +623,38 @@ __global__ __launch_bounds__(256) void k_np_panel(z64* S, int ld, int n, int k0,
   }
 }
 
-// The panel's pivot rows: X[q][j] = M[k0 + q][j] (the previous panel's
-// columns from Ptp, which M does not hold yet), then those rows of M zeroed.
-__global__ __launch_bounds__(256) void k_np_rows(z64* S, int ld, int n, int k0, int nb, z64* X,
-                                                 const z64* Ptp, int k0p, int nbp) {
-  const int q = blockIdx.y;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n || q >= nb) return;
-  z64* row = S + size_t(k0 + q) * ld;
-  X[size_t(q) * ld + j] = (Ptp && j >= k0p && j < k0p + nbp)
-                              ? Ptp[size_t(k0 + q) * kNpNb + (j - k0p)]
-                              : row[j];
-  row[j] = z64{0.0, 0.0};
-}
-
 // The last panel's columns: M[r][k0 + c] = Pt[r][c].
 __global__ __launch_bounds__(256) void k_np_last(z64* S, int ld, int n, int k0, int nb,
                                                  const z64* Pt) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   const int r = e / kNpNb, c = e % kNpNb;
   if (r < n && c < nb) S[size_t(r) * ld + k0 + c] = Pt[size_t(r) * kNpNb + c];
+}
+
+// The working matrix of the unpivoted inversion: row a < ns is row s_a of C
+// restricted to the S columns (K), row ns + z the same for pixel z_z of Z
+// (W = -k2d G[Z,S]).
+__global__ __launch_bounds__(256) void k_np_gather(z64* M, const z64* G, int ld,
+                                                   const int32_t* sidx, const int32_t* zidx,
+                                                   int ns, double k2d) {
+  const int a = blockIdx.y;
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= ns) return;
+  const int gi = a < ns ? sidx[a] : zidx[a - ns];
+  const z64 g = G[size_t(gi) * ld + sidx[b]];
+  M[size_t(a) * ld + b] = z64{(a == b ? 1.0 : 0.0) - k2d * g.re, -k2d * g.im};
+}
+
+// C^-1 from the working matrix: C^-1[i][j] = M[rowmap[i]][pos[j]] for j in
+// S, delta_ij for j in Z.  One row per blockIdx.y.
+__global__ __launch_bounds__(256) void k_np_scatter(const z64* M, z64* Cinv, int ld, int nd,
+                                                    const int32_t* pos, const int32_t* rowmap) {
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= nd) return;
+  const int bj = pos[j];
+  Cinv[size_t(i) * ld + j] =
+      bj >= 0 ? M[size_t(rowmap[i]) * ld + bj] : z64{i == j ? 1.0 : 0.0, 0.0};
 }
 
 // piv = inv_p = identity (the unpivoted result is K^-1 itself); clears the
@@ -815,31 +747,39 @@ __global__ void k_np_check(const unsigned long long* mx, double tol, int32_t* st
 }
 
 hipError_t launch_inverse_np(z64* S, const z64* G, int ld, const int32_t* sidx, int ns,
-                             double k2d, const NpWork& w, int32_t* piv, int32_t* inv_p,
+                             int nrows, double k2d, const NpWork& w, int32_t* piv, int32_t* inv_p,
                              int32_t* status, hipStream_t s) {
   constexpr int NB = kNpNb;
   const dim3 gcols((ns + 255) / 256);
   hipLaunchKernelGGL(k_np_ident, gcols, dim3(256), 0, s, piv, inv_p, ns, w.mx);
   int cur = 0, k0p = 0, nbp = 0;
   const z64* Ptp = nullptr;
+  const int nrw = (nrows + 15) / 16;
+  hipLaunchKernelGGL(k_np_blockinv<NB>, dim3(1), dim3(256), 0, s, S, ld, 0, std::min(NB, ns),
+                     w.Bi, status);
   for (int k0 = 0; k0 < ns; k0 += NB) {
     const int nb = std::min(NB, ns - k0);
     z64* Pt = w.Pt[cur];
-    hipLaunchKernelGGL(k_np_blockinv<NB>, dim3(1), dim3(256), 0, s, S, ld, k0, nb, w.Bi, status);
-    hipLaunchKernelGGL(k_np_panel<NB>, dim3((ns + 15) / 16), dim3(256), 0, s, S, ld, ns, k0, nb,
-                       w.Bi, Pt, Ptp, k0p, nbp);
-    hipLaunchKernelGGL(k_np_rows, dim3(gcols.x, nb), dim3(256), 0, s, S, ld, ns, k0, nb, w.X, Ptp,
-                       k0p, nbp);
-    hipError_t e = launch_zgemm_ix(ns, ns, nb, Pt, NB, w.X, ld, false, S, ld, GemmIdx{},
-                                   z64{1.0, 0.0}, z64{1.0, 0.0}, 1, nullptr, s);
+    hipLaunchKernelGGL(k_np_panel<NB>, dim3(nrw + nb * int(gcols.x)), dim3(256), 0, s, S, ld,
+                       nrows, ns, k0, nb, w.Bi, Pt, Ptp, k0p, nbp, w.X, nrw);
+    // the update, whose workgroup of the next diagonal tile inverts it
+    NpDiag dg;
+    if (k0 + NB < ns) {
+      dg.tile = (k0 + NB) / NB;
+      dg.k0 = k0 + NB;
+      dg.nb = std::min(NB, ns - k0 - NB);
+      dg.Bi = w.Bi;
+      dg.status = status;
+    }
+    hipError_t e = launch_zgemm_np(nrows, ns, nb, Pt, NB, w.X, ld, S, ld, dg, s);
     if (e != hipSuccess) return e;
     Ptp = Pt;
     k0p = k0;
     nbp = nb;
     cur ^= 1;
   }
-  hipLaunchKernelGGL(k_np_last, dim3((ns * NB + 255) / 256), dim3(256), 0, s, S, ld, ns, k0p, nbp,
-                     Ptp);
+  hipLaunchKernelGGL(k_np_last, dim3((nrows * NB + 255) / 256), dim3(256), 0, s, S, ld, nrows,
+                     k0p, nbp, Ptp);
   hipLaunchKernelGGL(k_np_resid_y, dim3(ns), dim3(kRowThreads), 0, s, S, ld, ns, w.y);
   hipLaunchKernelGGL(k_np_resid_k, dim3(ns), dim3(kRowThreads), 0, s, G, ld, sidx, ns, k2d, w.y,
                      w.mx);
@@ -860,10 +800,20 @@ hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const
                           hipStream_t s) {
   const int nz = nd - ns;
   if (ns > 0 && np) {
-    hipLaunchKernelGGL(k_gather_K, dim3((ns + 255) / 256, ns), dim3(256), 0, s, S, G, ld, sidx, ns,
-                       k2d, used);
-    const hipError_t e = launch_inverse_np(S, G, ld, sidx, ns, k2d, *np, piv, inv_p, status, s);
+    // small systems carry the Z rows along (C^-1[:, S] in one pass, no
+    // separate product); large ones form C^-1[Z, S] by one GEMM below, which
+    // reads the Z rows once instead of once per panel
+    const bool fold = ns <= kNpFoldMax;
+    const int nrows = fold ? nd : ns;
+    hipLaunchKernelGGL(k_np_gather, dim3((ns + 255) / 256, nrows), dim3(256), 0, s, S, G, ld,
+                       sidx, zidx, ns, k2d);
+    hipError_t e = launch_inverse_np(S, G, ld, sidx, ns, nrows, k2d, *np, piv, inv_p, status, s);
     if (e != hipSuccess) return e;
+    if (fold) {
+      hipLaunchKernelGGL(k_np_scatter, dim3((nd + 255) / 256, nd), dim3(256), 0, s, S, Cinv, ld,
+                         nd, pos, np->rowmap);
+      return hipGetLastError();
+    }
   } else if (ns > 0) {
     // two tournament proposal lists (ids and counts) of (kGjNb + 1) ints
     // per group

@@ -116,7 +116,7 @@ struct Layout {
   size_t off_C0[pngf::kMaxFreq], off_G32[pngf::kMaxFreq], off_Pp[pngf::kMaxFreq],
       off_Qp[pngf::kMaxFreq], off_alph[pngf::kMaxFreq], off_pcoef[pngf::kMaxFreq];
   size_t off_df32, off_dfb, off_bandout;
-  size_t off_sidx, off_zidx, off_pos;
+  size_t off_sidx, off_zidx, off_pos, off_rowmap;
   size_t off_CB[pngf::kMaxFreq], off_EB[pngf::kMaxFreq], off_RpB[pngf::kMaxFreq],
       off_tauB[pngf::kMaxFreq];
   size_t off_bitsB, off_stateB, off_keys, off_pm, off_best, off_feat;
@@ -296,6 +296,7 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
   L.off_sidx = take(size_t(nd) * sizeof(int32_t));
   L.off_zidx = take(size_t(nd) * sizeof(int32_t));
   L.off_pos = take(size_t(nd) * sizeof(int32_t));
+  L.off_rowmap = take(size_t(nd) * sizeof(int32_t));
   L.off_status = take(sizeof(int32_t));
   L.off_band = take(sizeof(double));   // the error band as the device holds it
   L.off_pbar = take(pngf::kPersistBarBytes);   // grid-barrier words, then the time-out flag
@@ -452,6 +453,7 @@ pngf::NpWork np_work(pngf_handle* h, int f) {
   w.y = w.Bi + nb * nb;
   w.mx = reinterpret_cast<unsigned long long*>(w.y + h->pc.n_d);
   w.tol = h->np_tol;
+  w.rowmap = at<int32_t>(h, h->lay.off_rowmap);
   return w;
 }
 
@@ -466,12 +468,14 @@ int device_reinvert(pngf_handle* h) {
   // S (pixels at eps_hi) and Z from the device design bits
   HIPCHK(h, hipMemcpyAsync(h->bits.data(), P.bits, nd, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  std::vector<int32_t> sidx, zidx, pos(nd, -1);
+  std::vector<int32_t> sidx, zidx, pos(nd, -1), rowmap(nd);
   for (int i = 0; i < nd; ++i) {
     if (h->bits[i]) { pos[i] = int32_t(sidx.size()); sidx.push_back(i); }
     else zidx.push_back(i);
   }
   const int ns = int(sidx.size());
+  // the unpivoted inversion's working matrix: S rows, then Z rows
+  for (int i = 0, z = 0; i < nd; ++i) rowmap[i] = pos[i] >= 0 ? pos[i] : ns + z++;
   int32_t* d_sidx = at<int32_t>(h, L.off_sidx);
   int32_t* d_zidx = at<int32_t>(h, L.off_zidx);
   int32_t* d_pos = at<int32_t>(h, L.off_pos);
@@ -480,6 +484,8 @@ int device_reinvert(pngf_handle* h) {
   if (nd - ns > 0)
     HIPCHK(h, hipMemcpyAsync(d_zidx, zidx.data(), (nd - ns) * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync(d_pos, pos.data(), nd * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(at<int32_t>(h, L.off_rowmap), rowmap.data(), nd * sizeof(int32_t),
+                           hipMemcpyHostToDevice, h->stream));
   // one inversion per frequency, each on its own stream; first without row
   // exchanges, and with the pivot search where that result fails its check
   // (or always, with PNGF_FLAG_PIVOT_SEARCH)
