@@ -18,6 +18,9 @@ Matrix-core utilization of the MFMA kernels from one counter pass
 SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE):
 
     python -m paper_2501_18054_amd.profiling mfma --dir OUT/c1 --workload ... --out ...
+
+The initial FP64 inverse of a workload alone, for its kernel times and
+counters (``inverse``).
 """
 from __future__ import annotations
 
@@ -188,10 +191,50 @@ def mfma(a):
         out.append(f"| `{k}` | {g['n']} | {g['ns'] / 1e6:.2f} | {rate(g['F64'], PEAK_TFLOPS['F64'])} | "
                    f"{rate(g['F32'], PEAK_TFLOPS['F32'])} | {rate(g['BF16'], PEAK_TFLOPS['BF16'])} | "
                    f"{rate(g['valu64'], PEAK_TFLOPS['F64'])} | {busy} |\n")
+    f64 = sum(g["F64"] + g["valu64"] for _, g in keep)
+    kns = sum(g["ns"] for _, g in keep)
+    out.append(f"\nAll kernels: {f64 / 1e9:.1f} GFLOP of FP64 (matrix cores and vector ALUs) in "
+               f"{kns / 1e6:.2f} ms of kernel time ({f64 / kns / 1e3:.2f} TFLOP/s).\n")
+    if a.units > 0 and a.wall_ms > 0.0:
+        per = f64 / a.units
+        r = per / (a.wall_ms * 1e-3) / 1e12
+        out.append(f"Per {a.unit_name}: {per / 1e9:.1f} GFLOP of FP64; over its wall time without "
+                   f"counters, {a.wall_ms:.2f} ms, that is {r:.1f} TFLOP/s, "
+                   f"{100.0 * r / PEAK_TFLOPS['F64']:.1f}% of the FP64 peak.\n")
     text = "".join(out)
     with open(os.path.join(ROOT, "profiles", a.out + ".md"), "w") as fh:
         fh.write(text)
     print(text)
+
+
+def inverse(a):
+    """The FP64 initial inverse of a workload, a.reps times after one warm-up
+    (pngf_set_design: index lists, inversion, fields); prints one JSON line
+    with the wall times and the inversion's FLOP count 8 n_S^2 N_d per
+    frequency (Gauss-Jordan on the S block and C^-1[Z,S])."""
+    import sys
+    import time
+    import torch
+    sys.path.insert(0, ROOT)
+    import workloads
+    import paper_2501_18054_amd as P
+    p = getattr(workloads, a.workload)()
+    h = P.Handle(p).bind(P.default_options(pivot_search=a.pivot_search))
+    h.set_design(p.init_bits)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(a.reps):
+        t0 = time.perf_counter()
+        h.set_design(p.init_bits)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ns = int(p.init_bits.sum())
+    print(json.dumps({"workload": a.workload, "n_d": int(p.n_d), "n_s": ns, "nfreq": int(p.nfreq),
+                      "pivot_search": a.pivot_search, "reps": a.reps,
+                      "ms_min": 1e3 * min(ts), "ms_median": 1e3 * statistics.median(ts),
+                      "inversions": h.inverse_stats(),
+                      "flop": 8.0 * ns * ns * p.n_d * p.nfreq}), flush=True)
+    h.close()
 
 
 def stats(a):
@@ -239,6 +282,14 @@ def main():
     mf.add_argument("--workload", required=True)
     mf.add_argument("--out", required=True)
     mf.add_argument("--commands", nargs="*", default=[])
+    mf.add_argument("--units", type=int, default=0)
+    mf.add_argument("--unit-name", default="unit")
+    mf.add_argument("--wall-ms", type=float, default=0.0,
+                    help="wall time of one unit without counters, for the FP64 rate")
+    iv = sub.add_parser("inverse")
+    iv.add_argument("--workload", required=True)
+    iv.add_argument("--reps", type=int, default=3)
+    iv.add_argument("--pivot-search", action="store_true")
     s = sub.add_parser("summarize")
     s.add_argument("--dir", required=True)
     s.add_argument("--kernel", required=True)
@@ -256,6 +307,8 @@ def main():
         copy()
     elif a.cmd == "mfma":
         mfma(a)
+    elif a.cmd == "inverse":
+        inverse(a)
     elif a.cmd == "stats":
         stats(a)
     else:
