@@ -33,8 +33,9 @@ __device__ __forceinline__ void lds_barrier() {
 // rows T ti .., columns T tj .. in registers.  Step C: the pivot column's
 // entries of a thread's rows come from lane C / T of its own 16-lane row
 // (ds_bpermute), the pivot row through LDS (two buffers by parity, one
-// barrier per step).  The steps are a loop, not unrolled: straight-line code
-// for all of them would not fit the instruction cache.
+// barrier per step).  The tile columns are a loop, and only the four steps
+// within one are unrolled: straight-line code for all 64 steps would not fit
+// the instruction cache.
 __device__ __forceinline__ z64 lane_bperm(z64 v, int src) {
   const int addr = src << 2;
   const long long r = __double_as_longlong(v.re), i = __double_as_longlong(v.im);
@@ -46,10 +47,54 @@ __device__ __forceinline__ z64 lane_bperm(z64 v, int src) {
              __longlong_as_double(static_cast<long long>((uint64_t(i1) << 32) | i0))};
 }
 
+// Step C = T oc + RC of the block inverse (RC known at compile time, so the
+// pivot column's and row's registers are named directly).
+template <int NB, int RC>
+__device__ __forceinline__ void np_block_step(z64 (&a)[NB / 16][NB / 16], int oc, int ti, int tj,
+                                              int lane, z64 (&rowbuf)[2][NB], bool& bad) {
+  constexpr int T = NB / 16;
+  constexpr int par = RC & 1;   // C = T oc + RC has the parity of RC (T even)
+  const int C = T * oc + RC;
+  const int src = (lane & 48) | oc;
+  z64 col[T];
+#pragma unroll
+  for (int r = 0; r < T; ++r) col[r] = lane_bperm(a[r][RC], src);
+  if (ti == oc) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) rowbuf[par][T * tj + k] = a[RC][k];
+  }
+  lds_barrier();
+  z64 u[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) u[k] = rowbuf[par][T * tj + k];
+  const z64 pv = rowbuf[par][C];
+  if (!(pv.re * pv.re + pv.im * pv.im > 1e-280)) bad = true;
+  const z64 inv = zrecip_newton(pv);
+  // a <- alpha_i a' + beta_i u'_j with a' = 0 and u' = 1 in the pivot
+  // column, alpha = 0 and beta = 1/p for the pivot row, alpha = 1 and
+  // beta = -a_iC/p elsewhere: the pivot row scaled, the pivot column -a_iC/p
+  // (1/p at the pivot), every other entry reduced
+  const bool pcol = tj == oc;
+  if (pcol) u[RC] = z64{1.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < T; ++r) {
+    const bool prow = ti == oc && r == RC;
+    const z64 f = zmul(col[r], inv);
+    const z64 beta = prow ? inv : z64{-f.re, -f.im};
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      z64 x = a[r][k];
+      if (prow || (pcol && k == RC)) x = z64{0.0, 0.0};
+      a[r][k] = zfma(beta, u[k], x);
+    }
+  }
+}
+
 template <int NB>
 __device__ __forceinline__ void np_block_inverse(const z64* S, int ld, int k0, int nb, z64* Bi,
                                                  int32_t* status) {
   constexpr int T = NB / 16;
+  static_assert(T == 4, "four steps per tile column");
   __shared__ z64 rowbuf[2][NB];
   const int t = threadIdx.x, ti = t >> 4, tj = t & 15, lane = t & 63;
   z64 a[T][T];
@@ -63,60 +108,17 @@ __device__ __forceinline__ void np_block_inverse(const z64* S, int ld, int k0, i
     }
   bool bad = false;
 #pragma unroll 1
-  for (int C = 0; C < NB; ++C) {
-    const int oc = C / T, rc = C % T, par = C & 1;
-    const int src = (lane & 48) | oc;
-    z64 col[T];
-#pragma unroll
-    for (int r = 0; r < T; ++r) {
-      z64 v = a[r][0];
-#pragma unroll
-      for (int k = 1; k < T; ++k)
-        if (rc == k) v = a[r][k];
-      col[r] = lane_bperm(v, src);
-    }
-    if (ti == oc) {
-#pragma unroll
-      for (int k = 0; k < T; ++k) {
-        z64 v = a[0][k];
-#pragma unroll
-        for (int r = 1; r < T; ++r)
-          if (rc == r) v = a[r][k];
-        rowbuf[par][T * tj + k] = v;
-      }
-    }
-    lds_barrier();
-    z64 u[T];
-#pragma unroll
-    for (int k = 0; k < T; ++k) u[k] = rowbuf[par][T * tj + k];
-    const z64 pv = rowbuf[par][C];
-    if (!(pv.re * pv.re + pv.im * pv.im > 1e-280)) bad = true;
-    const z64 inv = zrecip_newton(pv);
-    // a <- alpha_i a' + beta_i u'_j with a' = 0 and u' = 1 in the pivot
-    // column, alpha = 0 and beta = 1/p for the pivot row, alpha = 1 and
-    // beta = -a_iC/p elsewhere: the pivot row scaled, the pivot column
-    // -a_iC/p (1/p at the pivot), every other entry reduced
-#pragma unroll
-    for (int k = 0; k < T; ++k)
-      if (T * tj + k == C) u[k] = z64{1.0, 0.0};
-#pragma unroll
-    for (int r = 0; r < T; ++r) {
-      const bool prow = T * ti + r == C;
-      const z64 f = zmul(col[r], inv);
-      const z64 beta = prow ? inv : z64{-f.re, -f.im};
-#pragma unroll
-      for (int k = 0; k < T; ++k) {
-        z64 x = a[r][k];
-        if (prow || T * tj + k == C) x = z64{0.0, 0.0};
-        a[r][k] = zfma(beta, u[k], x);
-      }
-    }
+  for (int oc = 0; oc < 16; ++oc) {
+    np_block_step<NB, 0>(a, oc, ti, tj, lane, rowbuf, bad);
+    np_block_step<NB, 1>(a, oc, ti, tj, lane, rowbuf, bad);
+    np_block_step<NB, 2>(a, oc, ti, tj, lane, rowbuf, bad);
+    np_block_step<NB, 3>(a, oc, ti, tj, lane, rowbuf, bad);
   }
 #pragma unroll
   for (int r = 0; r < T; ++r)
 #pragma unroll
     for (int k = 0; k < T; ++k) Bi[(T * ti + r) * NB + T * tj + k] = a[r][k];
-  if (bad && t == 0) atomicOr(status, 2);
+  if (bad && threadIdx.x == 0) atomicOr(status, 2);
 }
 
 }  // namespace pngf
