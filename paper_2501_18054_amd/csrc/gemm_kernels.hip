@@ -29,6 +29,7 @@ namespace pngf {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGemmBK = 16;
+constexpr size_t kNpSoloLds = 96 << 10;   // dynamic LDS that leaves room for one workgroup per CU
 
 
 template <int WM, int WN, bool TRANSB, bool DINV = false>
@@ -42,7 +43,18 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int i16 = lane & 15, k4 = lane >> 4;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  // with a diagonal tile to invert, that tile's workgroup swaps places with
+  // tile (0, 0), so it is dispatched first and its inverse starts earliest
+  int bx = int(blockIdx.x), by = int(blockIdx.y);
+  const bool diag = DINV && dg.tile >= 0;
+  if (diag && bx == 0 && by == 0) {
+    bx = dg.tile;
+    by = dg.tile;
+  } else if (diag && bx == dg.tile && by == dg.tile) {
+    bx = 0;
+    by = 0;
+  }
+  const int m0 = by * BM, n0 = bx * BN;
   const int kbeg = blockIdx.z * kchunk;
   const int kend = min(K, kbeg + kchunk);
   d4 accr[WM][WN], acci[WM][WN];
@@ -153,7 +165,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A
           *c = beta0 ? av : zfma(beta, *c, av);
         }
       }
-  if (DINV && dg.tile >= 0 && int(blockIdx.x) == dg.tile && int(blockIdx.y) == dg.tile) {
+  if (diag && bx == dg.tile && by == dg.tile) {
     // this workgroup's tile is the next diagonal block of the unpivoted
     // inversion: invert it now, from memory (the fence makes the tile's
     // stores visible to this workgroup's loads)
@@ -418,8 +430,13 @@ hipError_t launch_zgemm_np(int M, int N, int K, const z64* A, int lda, const z64
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
   static_assert(kNpNb == 64, "panel width equals the GEMM tile");
   dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
-  hipLaunchKernelGGL((k_zgemm<2, 2, false, true>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb,
-                     C, ldc, GemmIdx{}, z64{1.0, 0.0}, z64{1.0, 0.0}, K, nullptr, dg);
+  // a small update, whose tiles the chip runs in a round or two, reserves
+  // enough LDS for one workgroup per CU, so that no other tile shares the
+  // CU of the diagonal tile's inverse (on the critical path); a large one
+  // keeps its occupancy
+  const size_t lds = (dg.tile >= 0 && size_t(grid.x) * grid.y <= 512) ? kNpSoloLds : 0;
+  hipLaunchKernelGGL((k_zgemm<2, 2, false, true>), grid, dim3(256), lds, s, M, N, K, A, lda, B,
+                     ldb, C, ldc, GemmIdx{}, z64{1.0, 0.0}, z64{1.0, 0.0}, K, nullptr, dg);
   return hipGetLastError();
 }
 

@@ -605,19 +605,23 @@ __global__ __launch_bounds__(256) void k_np_panel(z64* S, int ld, int n, int nc,
   const int rr = t >> 4, r = r0 + rr;
   if (r >= n) return;
   const bool inJ = r >= k0 && r < k0 + nb;
+  // thread (rr, t % 16): columns t % 16 + 16 m, one read of the row entry
+  // per q for its NB / 16 products
+  constexpr int M = NB / 16;
+  z64 acc[M];
 #pragma unroll
-  for (int m = 0; m < NB / 16; ++m) {
+  for (int m = 0; m < M; ++m) acc[m] = z64{0.0, 0.0};
+  if (!inJ)
+    for (int q = 0; q < nb; ++q) {
+      const z64 x = sR[rr][q];
+#pragma unroll
+      for (int m = 0; m < M; ++m) acc[m] = zfma(x, sB[q][(t & 15) + 16 * m], acc[m]);
+    }
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
     const int c = (t & 15) + 16 * m;
     z64 v{0.0, 0.0};
-    if (c < nb) {
-      if (inJ) {
-        v = sB[r - k0][c];
-      } else {
-        z64 acc{0.0, 0.0};
-        for (int q = 0; q < nb; ++q) acc = zfma(sR[rr][q], sB[q][c], acc);
-        v = z64{-acc.re, -acc.im};
-      }
-    }
+    if (c < nb) v = inJ ? sB[r - k0][c] : z64{-acc[m].re, -acc[m].im};
     Pt[size_t(r) * NB + c] = v;
     if (Ptp && !inJ && c < nbp) S[size_t(r) * ld + k0p + c] = Ptp[size_t(r) * NB + c];
   }
