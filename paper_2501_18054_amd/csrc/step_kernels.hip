@@ -568,6 +568,140 @@ __device__ inline void mixed_step_group(const ProbDev& P, int g, int spar, int k
   }
 }
 
+// Mixed step over a group of kWideRows rows, four per wave: the wave streams
+// its four C0^-1 rows against g_m with 16-byte loads (two complex entries per
+// lane and row; g_m read once for all four), then lane h < 4 forms p for row
+// h, updates its FP64 E, R', tau and scores it.  Same products as
+// mixed_step_group (FP32 accumulation, FP64 vectors); the dot products sum
+// in another order.  For many frequencies and large N_d, where the step
+// streams C0^-1 from HBM: more bytes in flight per wave than two rows with
+// 8-byte loads.
+constexpr int kWideRpw = 2;
+constexpr int kWideRows = 4 * kWideRpw;
+
+__device__ inline void mixed_step_wide(const ProbDev& P, int g, int spar, int kslot, StepCtx& c,
+                                       z64 (*pc)[64], bool publish) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r0 = g * kWideRows + kWideRpw * w;   // the wave's first row
+  const int dp = spar;
+  // the wave's FP64 vectors (E, R', tau) at every frequency, independent of
+  // the decision, into LDS
+  __shared__ z64 vpre[4][kMaxFreq][kWideRpw][3];
+  for (int e = lane; e < 3 * kWideRpw * P.nfreq; e += 64) {
+    const int f = e / (3 * kWideRpw), h = (e / 3) % kWideRpw, v = e % 3;
+    const int r = r0 + h;
+    if (r < P.nd) {
+      const z64* src = v == 0 ? (dp ? P.EB[f] : P.E[f])
+                              : (v == 1 ? (dp ? P.RpB[f] : P.Rp[f]) : (dp ? P.tauB[f] : P.tau[f]));
+      vpre[w][f][h][v] = src[r];
+    }
+  }
+  const uint8_t* bin = dp ? P.bitsB : P.bits;
+  uint8_t* bout = dp ? P.bits : P.bitsB;
+  const int myr = r0 + lane;                 // lane h < 4 owns row r0 + h
+  const bool mine = lane < kWideRpw && myr < P.nd;
+  const uint8_t b0 = mine ? bin[myr] : 0;
+  if (tid == 0) step_decide(P, spar, kslot, true, c);
+  __syncthreads();
+  if (publish) step_publish(P, spar, kslot, true, c);
+  const int m = c.m;
+  if (m < 0) return;
+  const int slot = c.slot;
+  // panel coefficients alpha_k p_k[m] (reciprocity: q_k . g_m = p_k[m])
+  if (tid < slot)
+    for (int f = 0; f < P.nfreq; ++f)
+      pc[f][tid] = zmul(P.alph[f][tid], up32(P.Pp[f][size_t(tid) * P.ld + m]));
+  __syncthreads();
+  const uint8_t bit = b0 ^ (myr == m ? 1 : 0);
+  const double dl = bit ? -P.deps : P.deps;
+  double df = 0.0, bnd = 0.0;
+  const int nd2 = P.nd >> 1;
+  // rows past N_d (last group) read row N_d - 1 and are discarded
+  size_t roff[kWideRpw];
+#pragma unroll
+  for (int h = 0; h < kWideRpw; ++h) roff[h] = size_t(min(r0 + h, P.nd - 1)) * P.ld;
+  for (int f = 0; f < P.nfreq; ++f) {
+    const z32* gm = P.G32[f] + size_t(m) * P.ld;
+    const float4* g4 = reinterpret_cast<const float4*>(gm);
+    const float4* c4[kWideRpw];
+#pragma unroll
+    for (int h = 0; h < kWideRpw; ++h) c4[h] = reinterpret_cast<const float4*>(P.C0[f] + roff[h]);
+    // this group's panel entries, issued ahead of the stream
+    z32 pk[kWideRpw];
+#pragma unroll
+    for (int h = 0; h < kWideRpw; ++h)
+      pk[h] = lane < slot ? P.Pp[f][size_t(lane) * P.ld + min(r0 + h, P.nd - 1)] : z32{0.f, 0.f};
+    float pr[kWideRpw], pi[kWideRpw];
+#pragma unroll
+    for (int h = 0; h < kWideRpw; ++h) pr[h] = pi[h] = 0.f;
+#pragma unroll 4
+    for (int j = lane; j < nd2; j += 64) {
+      const float4 gv = g4[j];
+#pragma unroll
+      for (int h = 0; h < kWideRpw; ++h) {
+        const float4 cv = c4[h][j];
+        pr[h] = fmaf(cv.x, gv.x, fmaf(-cv.y, gv.y, pr[h]));
+        pi[h] = fmaf(cv.x, gv.y, fmaf(cv.y, gv.x, pi[h]));
+        pr[h] = fmaf(cv.z, gv.z, fmaf(-cv.w, gv.w, pr[h]));
+        pi[h] = fmaf(cv.z, gv.w, fmaf(cv.w, gv.z, pi[h]));
+      }
+    }
+    if ((P.nd & 1) && lane == 0) {   // the last entry of an odd row
+      const z32 gv = gm[P.nd - 1];
+#pragma unroll
+      for (int h = 0; h < kWideRpw; ++h) {
+        const z32 cv = P.C0[f][roff[h] + P.nd - 1];
+        pr[h] = fmaf(cv.re, gv.re, fmaf(-cv.im, gv.im, pr[h]));
+        pi[h] = fmaf(cv.re, gv.im, fmaf(cv.im, gv.re, pi[h]));
+      }
+    }
+    if (lane < slot) {
+      const z64 cc = pc[f][lane];
+#pragma unroll
+      for (int h = 0; h < kWideRpw; ++h) {
+        pr[h] += float(cc.re * pk[h].re - cc.im * pk[h].im);
+        pi[h] += float(cc.re * pk[h].im + cc.im * pk[h].re);
+      }
+    }
+    float sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int h = 0; h < kWideRpw; ++h) {
+      const float a = wave_sumf(pr[h]), b = wave_sumf(pi[h]);
+      if (lane == h) {
+        sr = a;
+        si = b;
+      }
+    }
+    if (mine) {
+      const z32 p32{sr, si};
+      P.Pp[f][size_t(slot) * P.ld + myr] = p32;
+      const z64 p = up32(p32);
+      const z64 ap = zmul(c.alpha[f], p);
+      const z64 Ein = vpre[w][f][lane][0];
+      const z64 Rin = vpre[w][f][lane][1];
+      const z64 Tin = vpre[w][f][lane][2];
+      const z64 Ei = zadd(Ein, zmul(ap, c.Em[f]));
+      const z64 Rpi = zadd(Rin, zmul(ap, c.Rpm[f]));
+      const z64 tau = zadd(Tin, zmul(ap, p));
+      (dp ? P.E[f] : P.EB[f])[myr] = Ei;
+      (dp ? P.Rp[f] : P.RpB[f])[myr] = Rpi;
+      (dp ? P.tau[f] : P.tauB[f])[myr] = tau;
+      score_terms(P, c, f, tau, Ei, Rpi, dl, df, bnd);
+    }
+  }
+  if (mine) {
+    bout[myr] = bit;
+    P.df32[myr] = df;
+    P.dfb[myr] = bnd;
+    const double margin = df - c.eta * c.f;
+    const double band = P.band * bnd;
+    if (margin >= -band) {
+      const uint32_t k = step_key(P, c, myr);
+      if (k != kNoKey) atomicMin(&P.keys[(margin > band ? 0 : 3) + (kslot + 1) % 3], k);
+    }
+  }
+}
+
 // Single-frequency mixed step for rows of at most 64 PRE columns, with the
 // decision split from the streaming: wave 0 only decides (its thread 0 issues
 // no loads ahead of the state and key reads, whose wait would otherwise also
@@ -1205,7 +1339,7 @@ __global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar,
 __global__ __launch_bounds__(256) void k_mixed_step(ProbDev P, int spar, int kslot) {
   __shared__ StepCtx c;
   __shared__ z64 pc[kMaxFreq][64];
-  mixed_step_group(P, blockIdx.x, spar, kslot, c, pc, blockIdx.x == 0);
+  mixed_step_wide(P, blockIdx.x, spar, kslot, c, pc, blockIdx.x == 0);
 }
 
 // Batched step: one launch advances every problem of a batch by one step.
@@ -1426,7 +1560,8 @@ hipError_t launch_mixed_step(const ProbDev& P, int npl, int step, hipStream_t s)
     hipLaunchKernelGGL(k_mixed_step_mf<16>, dim3((P.nd + 1) / 2), dim3(64 * (1 + P.nfreq)), 0, s,
                        P, sp, ks);
   else
-    hipLaunchKernelGGL(k_mixed_step, grid, dim3(256), 0, s, P, sp, ks);
+    hipLaunchKernelGGL(k_mixed_step, dim3((P.nd + kWideRows - 1) / kWideRows), dim3(256), 0, s,
+                       P, sp, ks);
   return hipGetLastError();
 }
 
