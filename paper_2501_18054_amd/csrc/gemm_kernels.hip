@@ -66,36 +66,58 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A
       acci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     }
   // the next K chunk is fetched into registers while the current one is
-  // multiplied out of LDS
+  // multiplied out of LDS.  The optional index maps are read first, then
+  // every element's load is issued unconditionally (an element outside the
+  // matrix loads a clamped in-range address and is replaced by zero), so that
+  // no wait for one load sits between the others.
   constexpr int kAe = BM * kGemmBK / 256, kBe = BN * kGemmBK / 256;
   z64 ra[kAe], rbv[kBe];
   auto fetch = [&](int k0) {
+    int ar_[kAe], ac_[kAe], br_[kBe], bc_[kBe];
+    bool aok[kAe], bok[kBe];
 #pragma unroll
     for (int q = 0; q < kAe; ++q) {
       const int e = tid + 256 * q;
-      const int r = e >> 4, c = e & 15;
-      const int gr = m0 + r, gc = k0 + c;
-      z64 v{0.0, 0.0};
-      if (gr < M && gc < kend)
-        v = A[size_t(ix.ra ? ix.ra[gr] : gr) * lda + (ix.ca ? ix.ca[gc] : gc)];
-      ra[q] = v;
+      const int gr = m0 + (e >> 4), gc = k0 + (e & 15);
+      aok[q] = gr < M && gc < kend;
+      ar_[q] = min(gr, M - 1);
+      ac_[q] = min(gc, K - 1);
     }
 #pragma unroll
     for (int q = 0; q < kBe; ++q) {
       const int e = tid + 256 * q;
-      z64 v{0.0, 0.0};
-      if (TRANSB) {
-        const int n = e >> 4, c = e & 15;
-        const int gn = n0 + n, gc = k0 + c;
-        if (gn < N && gc < kend)
-          v = B[size_t(ix.rb ? ix.rb[gn] : gn) * ldb + (ix.cb ? ix.cb[gc] : gc)];
-      } else {
-        const int r = e / BN, n = e % BN;
-        const int gr = k0 + r, gn = n0 + n;
-        if (gr < kend && gn < N)
-          v = B[size_t(ix.rb ? ix.rb[gr] : gr) * ldb + (ix.cb ? ix.cb[gn] : gn)];
-      }
-      rbv[q] = v;
+      // TRANSB: B is N x K (row n, column k); else K x N (row k, column n)
+      const int gr = TRANSB ? n0 + (e >> 4) : k0 + e / BN;
+      const int gc = TRANSB ? k0 + (e & 15) : n0 + e % BN;
+      bok[q] = TRANSB ? (gr < N && gc < kend) : (gr < kend && gc < N);
+      br_[q] = TRANSB ? min(gr, N - 1) : min(gr, K - 1);
+      bc_[q] = TRANSB ? min(gc, K - 1) : min(gc, N - 1);
+    }
+    if (ix.ra) {
+#pragma unroll
+      for (int q = 0; q < kAe; ++q) ar_[q] = ix.ra[ar_[q]];
+    }
+    if (ix.ca) {
+#pragma unroll
+      for (int q = 0; q < kAe; ++q) ac_[q] = ix.ca[ac_[q]];
+    }
+    if (ix.rb) {
+#pragma unroll
+      for (int q = 0; q < kBe; ++q) br_[q] = ix.rb[br_[q]];
+    }
+    if (ix.cb) {
+#pragma unroll
+      for (int q = 0; q < kBe; ++q) bc_[q] = ix.cb[bc_[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < kAe; ++q) {
+      const z64 v = A[size_t(ar_[q]) * lda + ac_[q]];
+      ra[q] = aok[q] ? v : z64{0.0, 0.0};
+    }
+#pragma unroll
+    for (int q = 0; q < kBe; ++q) {
+      const z64 v = B[size_t(br_[q]) * ldb + bc_[q]];
+      rbv[q] = bok[q] ? v : z64{0.0, 0.0};
     }
   };
   if (kbeg < kend) fetch(kbeg);
@@ -147,24 +169,59 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* A
     __syncthreads();
   }
   const bool beta0 = beta.re == 0.0 && beta.im == 0.0;
+  if (work) {
 #pragma unroll
-  for (int a = 0; a < WM; ++a)
+    for (int a = 0; a < WM; ++a)
 #pragma unroll
-    for (int b = 0; b < WN; ++b)
+      for (int b = 0; b < WN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * 16 * WM + a * 16 + k4 + 4 * r;
+          const int col = n0 + wn * 16 * WN + b * 16 + i16;
+          if (row < M && col < N)
+            work[(size_t(blockIdx.z) * M + row) * N + col] = z64{accr[a][b][r], acci[a][b][r]};
+        }
+  } else {
+    // the lane's old C values are all requested before any is used (one
+    // memory round trip, not one per element: a store to C could otherwise
+    // alias the next load); the optional index maps are read first, and a
+    // lane outside the matrix reads C[0] instead of branching around its load
+    int crow[WM][4], ccol[WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm * 16 * WM + a * 16 + k4 + 4 * r;
-        const int col = n0 + wn * 16 * WN + b * 16 + i16;
-        if (row >= M || col >= N) continue;
-        const z64 v{accr[a][b][r], acci[a][b][r]};
-        if (work) {
-          work[(size_t(blockIdx.z) * M + row) * N + col] = v;
-        } else {
-          z64* c = C + size_t(ix.rc ? ix.rc[row] : row) * ldc + (ix.cc ? ix.cc[col] : col);
-          const z64 av = zmul(alpha, v);
-          *c = beta0 ? av : zfma(beta, *c, av);
-        }
+        crow[a][r] = row < M ? (ix.rc ? ix.rc[row] : row) : -1;
       }
+#pragma unroll
+    for (int b = 0; b < WN; ++b) {
+      const int col = n0 + wn * 16 * WN + b * 16 + i16;
+      ccol[b] = col < N ? (ix.cc ? ix.cc[col] : col) : -1;
+    }
+    z64 old[WM][WN][4];
+    if (!beta0) {
+#pragma unroll
+      for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const bool ok = crow[a][r] >= 0 && ccol[b] >= 0;
+            old[a][b][r] = C[ok ? size_t(crow[a][r]) * ldc + ccol[b] : 0];
+          }
+    }
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+      for (int b = 0; b < WN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (crow[a][r] < 0 || ccol[b] < 0) continue;
+          const z64 av = zmul(alpha, z64{accr[a][b][r], acci[a][b][r]});
+          C[size_t(crow[a][r]) * ldc + ccol[b]] = beta0 ? av : zfma(beta, old[a][b][r], av);
+        }
+  }
   if (diag && bx == dg.tile && by == dg.tile) {
     // this workgroup's tile is the next diagonal block of the unpivoted
     // inversion: invert it now, from memory (the fence makes the tile's

@@ -24,8 +24,8 @@ hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint64_t* 
                                 int32_t* flag, int spin_limit, const double* bandp,
                                 const int32_t* wstat, hipStream_t s);
 hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
-hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
-                             int grid, int npl, int mixed, int step, hipStream_t s);
+hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, const int32_t* nact,
+                             int total, int grid, int npl, int mixed, int step, hipStream_t s);
 hipError_t launch_accept_only(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_gemv2(const z64* A, int ld, int n, const uint8_t* bits, double ds,
                         const GemvOut& o1, const GemvOut& o2, hipStream_t s);
@@ -88,6 +88,7 @@ constexpr size_t kPinUpload = 256;           // offset of the Woodbury upload in
 constexpr size_t kPinStage = kPinBytes;      // then the batch-end read (state .. bits)
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
+constexpr int kBatchRefreshStreams = 4;   // streams a batch spreads one round's refreshes over
 constexpr int kTilePartPerPixel = 512;   // tile-score partial blocks (complex) per pixel
 constexpr int kTileSlicesMax = 32;       // K slices of one tile's block
 constexpr int kWoodSplits = 8;     // split-K factor of its skinny GEMM
@@ -174,6 +175,7 @@ struct pngf_handle {
   std::vector<int32_t> w_fl;
   std::vector<double> w_sc;
   bool wood_pending = false;       // a Woodbury status not yet read
+  bool rescore_pending = false;    // refresh_rescore queued a read of that status
   double f_host = 0.0;
   // event timing
   double ktime_ms[KID_N] = {0};
@@ -867,6 +869,70 @@ int capture_ref_bits(pngf_handle* h) {
   return PNGF_OK;
 }
 
+// While it lives, reform_fields also writes C0^-1 (the complex-FP32 copy)
+// from its first pass over C^-1: every path of a mixed refresh ends there.
+struct C64Pass {
+  pngf_handle* h;
+  explicit C64Pass(pngf_handle* hh) : h(hh) { h->reform_c64 = true; }
+  ~C64Pass() { h->reform_c64 = false; }
+};
+
+// Rescore a refreshed state: segment start (exact FP64 keys), then, with
+// `measure`, the FP32 scores' error against them (the band kernel also
+// carries a pending block-Woodbury status), else the pending status alone,
+// read into the handle's pinned scratch.  Stream-ordered, no wait; the reads
+// are valid after the next wait on the bound stream (refresh_settle).
+int refresh_rescore(pngf_handle* h, bool measure) {
+  const int nd = h->pc.n_d;
+  int st = start_segment(h, true);
+  if (st) return st;
+  double* mo = reinterpret_cast<double*>(h->pin + 8);
+  mo[0] = 0.0;
+  mo[1] = 0.0;
+  int32_t& wst0 = *reinterpret_cast<int32_t*>(h->pin + 24);
+  wst0 = 0;
+  h->rescore_pending = h->wood_pending;
+  double* dband = (h->opt.guard <= 0.0) ? at<double>(h, h->lay.off_band) : nullptr;
+  int32_t* dstatus = at<int32_t>(h, h->lay.off_status);
+  if (measure) {
+    double* out = at<double>(h, h->lay.off_bandout);
+    HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd, out,
+                                        h->rescore_pending ? dstatus : nullptr, h->stream, dband));
+    HIPCHK(h, hipMemcpyAsync(mo, out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  } else if (h->rescore_pending) {
+    HIPCHK(h, hipMemcpyAsync(&wst0, dstatus, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  }
+  return PNGF_OK;
+}
+
+// After the wait that follows refresh_rescore: take the measured band, or,
+// if the deferred block-Woodbury update turned out singular, re-invert C^-1
+// from the design and rescore again (with a wait of its own).
+int refresh_settle(pngf_handle* h, bool measure) {
+  for (int pass = 0; pass < 2; ++pass) {
+    const double* mo = reinterpret_cast<const double*>(h->pin + 8);
+    const int32_t wst0 = *reinterpret_cast<const int32_t*>(h->pin + 24);
+    const double meas = mo[0];
+    const int32_t wst = measure ? int32_t(mo[1]) : wst0;
+    const bool pending = h->rescore_pending;
+    h->rescore_pending = false;
+    h->wood_pending = false;
+    if (pending && wst) {
+      C64Pass c64pass(h);
+      int st = device_reinvert(h);
+      if (st) return st;
+      st = refresh_rescore(h, measure);
+      if (st) return st;
+      if (measure) HIPCHK(h, hipStreamSynchronize(h->stream));
+      continue;
+    }
+    if (measure && std::isfinite(meas) && h->opt.guard <= 0.0)
+      h->P.band = std::min(1e-2, std::max(1e-6, 100.0 * meas));
+    return PNGF_OK;
+  }
+  return PNGF_OK;
+}
+
 // Re-form the FP64 state, cast C0^-1 to complex FP32, rescore every candidate
 // in FP64 (exact key) and, when the previous scores were FP32, measure their
 // error against the FP64 scores to set the error band.
@@ -876,17 +942,14 @@ int capture_ref_bits(pngf_handle* h) {
 int mixed_refresh(pngf_handle* h, bool measure, bool nosync = false) {
   const int nd = h->pc.n_d;
   h->wood_pending = false;
-  // every path of the refresh ends in reform_fields, whose first pass over
-  // C^-1 also writes C0^-1 while this guard lives
-  struct C64Pass {
-    pngf_handle* h;
-    explicit C64Pass(pngf_handle* hh) : h(hh) { h->reform_c64 = true; }
-    ~C64Pass() { h->reform_c64 = false; }
-  } c64pass(h);
-  int st = fp64_refresh(h, true);
+  int st;
+  {
+    C64Pass c64pass(h);
+    st = fp64_refresh(h, true);
+  }
   if (st) return st;
-  double* dband = (h->opt.guard <= 0.0) ? at<double>(h, h->lay.off_band) : nullptr;
   if (nosync) {
+    double* dband = (h->opt.guard <= 0.0) ? at<double>(h, h->lay.off_band) : nullptr;
     st = start_segment(h, true);
     if (st) return st;
     if (measure && dband)
@@ -895,42 +958,10 @@ int mixed_refresh(pngf_handle* h, bool measure, bool nosync = false) {
                                           dband));
     return PNGF_OK;
   }
-  for (int pass = 0; pass < 2; ++pass) {
-    st = start_segment(h, true);
-    if (st) return st;
-    // read into the pinned scratch with one wait; with a measurement the
-    // band kernel also carries the Woodbury status (one copy)
-    double* mo = reinterpret_cast<double*>(h->pin + 8);
-    mo[0] = 0.0;
-    mo[1] = 0.0;
-    int32_t& wst0 = *reinterpret_cast<int32_t*>(h->pin + 24);
-    wst0 = 0;
-    const bool pending = h->wood_pending;
-    int32_t* dstatus = at<int32_t>(h, h->lay.off_status);
-    if (measure) {
-      double* out = at<double>(h, h->lay.off_bandout);
-      HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd, out,
-                                          pending ? dstatus : nullptr, h->stream, dband));
-      HIPCHK(h, hipMemcpyAsync(mo, out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    } else if (pending) {
-      HIPCHK(h, hipMemcpyAsync(&wst0, dstatus, sizeof(int32_t), hipMemcpyDeviceToHost,
-                               h->stream));
-    }
-    if (measure || pending) HIPCHK(h, hipStreamSynchronize(h->stream));
-    const double meas = mo[0];
-    const int32_t wst = measure ? int32_t(mo[1]) : wst0;
-    h->wood_pending = false;
-    if (pending && wst) {
-      // the deferred block-Woodbury update was singular: re-invert instead
-      st = device_reinvert(h);
-      if (st) return st;
-      continue;
-    }
-    if (measure && std::isfinite(meas) && h->opt.guard <= 0.0)
-      h->P.band = std::min(1e-2, std::max(1e-6, 100.0 * meas));
-    return PNGF_OK;
-  }
-  return PNGF_OK;
+  st = refresh_rescore(h, measure);
+  if (st) return st;
+  if (measure || h->rescore_pending) HIPCHK(h, hipStreamSynchronize(h->stream));
+  return refresh_settle(h, measure);
 }
 
 // FP64 residual |b - C E| / |b| of frequency 0 (drift monitor).
@@ -2032,13 +2063,15 @@ struct pngf_batch {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   pngf::ProbDev* d_probs = nullptr;
-  int32_t* d_row0 = nullptr;
+  int32_t* d_row0 = nullptr;            // [n+1] item offsets of the active problems
+  int32_t* d_nact = nullptr;            // the active count the step kernel reads
   pngf::DbsState* d_states = nullptr;   // [2n]: A and B slot of every problem
+  int total_all = 0;                    // work items of all problems
   int npl = 1;
   int mixed = 0;
   int grid = 0;                         // 0 = one workgroup per row
   bool bound = false;
-  // captured 6-step graph for the current active set and grid
+  // captured 6-step graph for the launch shape (any active set)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int g_total = -1, g_grid = -1, g_nprob = -1;
@@ -2046,6 +2079,11 @@ struct pngf_batch {
   std::vector<int32_t> tune_grid;
   std::vector<double> tune_ms;
   double last_ms_per_step = 0.0;
+  // streams the refreshes of one round are spread over (default priority),
+  // one join event each, and the event they start after
+  std::vector<hipStream_t> rs;
+  std::vector<hipEvent_t> rev;
+  hipEvent_t ev_round = nullptr;
 };
 
 namespace {
@@ -2063,7 +2101,7 @@ int bfail(pngf_batch* b, int code, const std::string& msg) {
   } while (0)
 
 size_t batch_bytes(int n) {
-  return align256(size_t(n) * sizeof(pngf::ProbDev)) + align256(size_t(n + 1) * sizeof(int32_t)) +
+  return align256(size_t(n) * sizeof(pngf::ProbDev)) + align256(size_t(n + 2) * sizeof(int32_t)) +
          align256(size_t(2 * n) * sizeof(pngf::DbsState));
 }
 
@@ -2075,30 +2113,119 @@ void drop_graph(pngf_batch* b) {
   b->g_total = b->g_grid = b->g_nprob = -1;
 }
 
-// Upload the descriptors of the active problems and (re)capture the 6-step
-// graph (one full cycle of state parity and key slot) for the launch shape.
-int batch_prepare(pngf_batch* b, const std::vector<int>& active, int grid) {
-  std::vector<pngf::ProbDev> probs;
-  std::vector<int32_t> row0(1, 0);
-  for (int p : active) {
-    probs.push_back(b->hs[p]->P);
-    const int nd = b->hs[p]->pc.n_d;   // work items: rows (FP64), row groups (mixed)
-    row0.push_back(row0.back() + (b->mixed ? (nd + pngf::kMixRows - 1) / pngf::kMixRows : nd));
+void release_refresh_streams(pngf_batch* b) {
+  for (hipStream_t r : b->rs) (void)hipStreamDestroy(r);
+  for (hipEvent_t e : b->rev) (void)hipEventDestroy(e);
+  if (b->ev_round) (void)hipEventDestroy(b->ev_round);
+  b->rs.clear();
+  b->rev.clear();
+  b->ev_round = nullptr;
+}
+
+// FP64 refreshes of several problems of a batch, issued together: their
+// designs come up in one copy (one wait), then each problem's block-Woodbury
+// update, field re-formation and (rescore) FP64 rescoring + band measurement
+// are queued on one of the refresh streams, round-robin, after the work
+// queued so far on the batch stream, so that the small kernels of different
+// problems overlap each other and the batch's next steps.  Without rescore
+// (the end of a search) only the FP64 state is re-formed.  pbits: pinned host
+// memory for the designs (the sum of the problems' N_d bytes).  No wait for
+// the refreshes themselves: batch_refresh_settle.
+int batch_refresh_issue(pngf_batch* b, const std::vector<int>& ref, const std::vector<char>& meas,
+                        bool rescore, uint8_t* pbits) {
+  if (ref.empty()) return PNGF_OK;
+  std::vector<size_t> boff;
+  size_t off = 0;
+  for (int p : ref) {
+    pngf_handle* h = b->hs[p];
+    boff.push_back(off);
+    BHIPCHK(b, hipMemcpyAsync(pbits + off, h->P.bits, h->pc.n_d, hipMemcpyDeviceToHost, b->stream));
+    off += size_t(h->pc.n_d);
   }
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  BHIPCHK(b, hipEventRecord(b->ev_round, b->stream));
+  const int K = std::min<int>(int(b->rs.size()), int(ref.size()));
+  for (int k = 0; k < K; ++k) BHIPCHK(b, hipStreamWaitEvent(b->rs[k], b->ev_round, 0));
+  for (size_t j = 0; j < ref.size(); ++j) {
+    pngf_handle* h = b->hs[ref[j]];
+    h->bits.assign(pbits + boff[j], pbits + boff[j] + h->pc.n_d);
+    h->bits_fresh = true;
+    h->stream = b->rs[j % K];
+    h->wood_pending = false;
+    int st;
+    if (rescore) {
+      C64Pass c64pass(h);
+      st = fp64_refresh(h, true);
+    } else {
+      st = fp64_refresh(h, true);
+    }
+    if (st == PNGF_OK && rescore) st = refresh_rescore(h, meas[j] != 0);
+    if (st == PNGF_OK && !rescore && h->wood_pending) {
+      int32_t* wst = reinterpret_cast<int32_t*>(h->pin + 24);
+      *wst = 0;
+      h->rescore_pending = true;
+      if (hipMemcpyAsync(wst, at<int32_t>(h, h->lay.off_status), sizeof(int32_t),
+                         hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+        st = fail(h, PNGF_EDEVICE, "status read failed");
+    }
+    h->stream = b->stream;
+    if (st) return bfail(b, st, "problem " + std::to_string(ref[j]) + ": " + h->err);
+  }
+  for (int k = 0; k < K; ++k) BHIPCHK(b, hipEventRecord(b->rev[k], b->rs[k]));
+  return PNGF_OK;
+}
+
+// Wait for the refreshes batch_refresh_issue queued, then let each problem
+// take its band (or re-invert, on the batch stream, if its deferred update
+// was singular).
+int batch_refresh_settle(pngf_batch* b, const std::vector<int>& ref,
+                         const std::vector<char>& meas, bool rescore) {
+  if (ref.empty()) return PNGF_OK;
+  const int K = std::min<int>(int(b->rs.size()), int(ref.size()));
+  for (int k = 0; k < K; ++k) BHIPCHK(b, hipEventSynchronize(b->rev[k]));
+  for (size_t j = 0; j < ref.size(); ++j) {
+    pngf_handle* h = b->hs[ref[j]];
+    int st = PNGF_OK;
+    if (rescore) {
+      st = refresh_settle(h, meas[j] != 0);
+    } else {
+      const bool singular = h->rescore_pending && *reinterpret_cast<const int32_t*>(h->pin + 24);
+      h->rescore_pending = false;
+      h->wood_pending = false;
+      if (singular) st = device_reinvert(h);
+    }
+    if (st) return bfail(b, st, "problem " + std::to_string(ref[j]) + ": " + h->err);
+  }
+  return PNGF_OK;
+}
+
+// Upload the descriptors and item offsets of the active problems (and their
+// count, which the step kernel reads on the device) and, for a new launch
+// shape, capture the 6-step graph (one full cycle of state parity and key
+// slot).  The graph does not depend on the active set.
+int batch_prepare(pngf_batch* b, const std::vector<int>& active, int grid) {
   const int n = int(active.size());
   if (n == 0) return PNGF_OK;
+  std::vector<pngf::ProbDev> probs;
+  std::vector<int32_t> row0(b->hs.size() + 2, 0);
+  for (int q = 0; q < n; ++q) {
+    const pngf_handle* h = b->hs[active[q]];
+    probs.push_back(h->P);
+    const int nd = h->pc.n_d;   // work items: rows (FP64), row groups (mixed)
+    row0[q + 1] = row0[q] + (b->mixed ? (nd + pngf::kMixRows - 1) / pngf::kMixRows : nd);
+  }
+  row0[b->hs.size() + 1] = n;   // d_nact follows d_row0[0..n_all]
   BHIPCHK(b, hipMemcpyAsync(b->d_probs, probs.data(), n * sizeof(pngf::ProbDev),
                             hipMemcpyHostToDevice, b->stream));
-  BHIPCHK(b, hipMemcpyAsync(b->d_row0, row0.data(), (n + 1) * sizeof(int32_t),
+  BHIPCHK(b, hipMemcpyAsync(b->d_row0, row0.data(), row0.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, b->stream));
   BHIPCHK(b, hipStreamSynchronize(b->stream));
-  const int total = row0.back();
-  if (b->exec && b->g_total == total && b->g_grid == grid && b->g_nprob == n) return PNGF_OK;
+  if (b->exec && b->g_total == b->total_all && b->g_grid == grid) return PNGF_OK;
   drop_graph(b);
   BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   for (int t = 0; t < 6; ++t) {
-    hipError_t e = pngf::launch_batch_step(b->d_probs, b->d_row0, n, total, grid, b->npl,
-                                           b->mixed, t, b->stream);
+    hipError_t e = pngf::launch_batch_step(b->d_probs, b->d_row0, b->d_nact, b->total_all, grid,
+                                           b->npl, b->mixed, t, b->stream);
     if (e != hipSuccess) {
       hipGraph_t g = nullptr;
       hipStreamEndCapture(b->stream, &g);
@@ -2108,9 +2235,9 @@ int batch_prepare(pngf_batch* b, const std::vector<int>& active, int grid) {
   }
   BHIPCHK(b, hipStreamEndCapture(b->stream, &b->graph));
   BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-  b->g_total = total;
+  b->g_total = b->total_all;
   b->g_grid = grid;
-  b->g_nprob = n;
+  b->g_nprob = int(b->hs.size());
   return PNGF_OK;
 }
 
@@ -2164,6 +2291,17 @@ int pngf_batch_bind(pngf_batch* b, void* dev_ws, size_t bytes, void* stream) {
     npl = std::max(npl, h->npl);
   }
   drop_graph(b);
+  if (b->rs.empty()) {
+    for (int k = 0; k < pngf::kBatchRefreshStreams; ++k) {
+      hipStream_t r = nullptr;
+      hipEvent_t e = nullptr;
+      BHIPCHK(b, hipStreamCreateWithFlags(&r, hipStreamNonBlocking));
+      b->rs.push_back(r);
+      BHIPCHK(b, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b->rev.push_back(e);
+    }
+    BHIPCHK(b, hipEventCreateWithFlags(&b->ev_round, hipEventDisableTiming));
+  }
   b->ws = static_cast<char*>(dev_ws);
   b->ws_bytes = bytes;
   b->stream = static_cast<hipStream_t>(stream);
@@ -2171,10 +2309,14 @@ int pngf_batch_bind(pngf_batch* b, void* dev_ws, size_t bytes, void* stream) {
   b->d_probs = reinterpret_cast<pngf::ProbDev*>(b->ws + off);
   off += align256(size_t(n) * sizeof(pngf::ProbDev));
   b->d_row0 = reinterpret_cast<int32_t*>(b->ws + off);
-  off += align256(size_t(n + 1) * sizeof(int32_t));
+  b->d_nact = b->d_row0 + n + 1;
+  off += align256(size_t(n + 2) * sizeof(int32_t));
   b->d_states = reinterpret_cast<pngf::DbsState*>(b->ws + off);
   b->npl = npl;
   b->mixed = (prec == PNGF_MIXED) ? 1 : 0;
+  b->total_all = 0;
+  for (pngf_handle* h : b->hs)
+    b->total_all += b->mixed ? (h->pc.n_d + pngf::kMixRows - 1) / pngf::kMixRows : h->pc.n_d;
   b->bound = true;
   return PNGF_OK;
 }
@@ -2242,6 +2384,13 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
   for (int p = 0; p < n; ++p) active[p] = p;
   pngf::DbsState* host_states = nullptr;
   BHIPCHK(b, hipHostMalloc(reinterpret_cast<void**>(&host_states), 2 * n * sizeof(pngf::DbsState)));
+  size_t sum_nd = 0;
+  for (pngf_handle* h : b->hs) sum_nd += size_t(h->pc.n_d);
+  uint8_t* pbits = nullptr;
+  if (hipHostMalloc(reinterpret_cast<void**>(&pbits), sum_nd) != hipSuccess) {
+    hipHostFree(host_states);
+    return bfail(b, PNGF_ENOMEM, "pinned host memory for the designs");
+  }
   int rc = PNGF_OK;
   // autotuner: candidate launch shapes, each timed on one 6-step replay of
   // the live search (every shape gives bitwise the same per-row arithmetic)
@@ -2258,45 +2407,57 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
   hipEventCreate(&e1);
   int64_t max_rounds = 0;
   for (pngf_handle* h : b->hs) max_rounds = std::max<int64_t>(max_rounds, 4 * int64_t(h->opt.max_accepts) + 64);
-  for (int64_t round = 0; round < max_rounds && !active.empty(); ++round) {
-    const bool tuning = ci < cand.size();
-    if (tuning) grid = cand[ci];
-    rc = batch_prepare(b, active, grid);
-    if (rc) break;
-    hipEventRecord(e0, b->stream);
-    const int reps = tuning ? 1 : 5;   // 30 steps per round: about one refresh interval
-    for (int r = 0; r < reps && rc == PNGF_OK; ++r) {
-      hipError_t e = hipGraphLaunch(b->exec, b->stream);
-      if (e != hipSuccess) rc = bfail(b, PNGF_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
-    }
-    if (rc) break;
-    hipEventRecord(e1, b->stream);
-    hipError_t e = hipMemcpyAsync(host_states, b->d_states, 2 * n * sizeof(pngf::DbsState),
-                                  hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) { rc = bfail(b, PNGF_EDEVICE, hipGetErrorString(e)); break; }
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    b->last_ms_per_step = ms / (6.0 * reps);
-    if (tuning) {
-      b->tune_grid.push_back(cand[ci]);
-      b->tune_ms.push_back(ms / 6.0);
-      if (++ci == cand.size()) {
-        size_t best = 0;
-        for (size_t k = 1; k < b->tune_ms.size(); ++k)
-          if (b->tune_ms[k] < b->tune_ms[best]) best = k;
-        b->grid = grid = b->tune_grid[best];
+  // refreshes issued at the end of one round run beside the next round's
+  // steps of the other problems; their problems skip that round and rejoin
+  // the one after (a problem's own sequence does not depend on when its steps
+  // run)
+  std::vector<int> inflight;
+  std::vector<char> inflight_meas;
+  for (int64_t round = 0; round < max_rounds && !(active.empty() && inflight.empty()); ++round) {
+    if (!active.empty()) {
+      const bool tuning = ci < cand.size();
+      if (tuning) grid = cand[ci];
+      rc = batch_prepare(b, active, grid);
+      if (rc) break;
+      hipEventRecord(e0, b->stream);
+      const int reps = tuning ? 1 : 5;   // 30 steps per round: about one refresh interval
+      for (int r = 0; r < reps && rc == PNGF_OK; ++r) {
+        hipError_t e = hipGraphLaunch(b->exec, b->stream);
+        if (e != hipSuccess) rc = bfail(b, PNGF_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+      }
+      if (rc) break;
+      hipEventRecord(e1, b->stream);
+      hipError_t e = hipMemcpyAsync(host_states, b->d_states, 2 * n * sizeof(pngf::DbsState),
+                                    hipMemcpyDeviceToHost, b->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+      if (e != hipSuccess) { rc = bfail(b, PNGF_EDEVICE, hipGetErrorString(e)); break; }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      b->last_ms_per_step = ms / (6.0 * reps);
+      if (tuning) {
+        b->tune_grid.push_back(cand[ci]);
+        b->tune_ms.push_back(ms / 6.0);
+        if (++ci == cand.size()) {
+          size_t best = 0;
+          for (size_t k = 1; k < b->tune_ms.size(); ++k)
+            if (b->tune_ms[k] < b->tune_ms[best]) best = k;
+          b->grid = grid = b->tune_grid[best];
+        }
       }
     }
-    std::vector<int> next;
-    bool changed = false;
+    // last round's refreshes are done (they overlapped this round's steps)
+    std::vector<int> back;
+    rc = batch_refresh_settle(b, inflight, inflight_meas, true);
+    if (rc) break;
+    back.swap(inflight);
+    inflight_meas.clear();
+    std::vector<int> next, ref;
+    std::vector<char> meas;
     for (int p : active) {
       pngf_handle* h = b->hs[p];
       pngf::DbsState& s = host_states[2 * p];
-      const bool was_odd = s.flips & 1;
       if (normalize(h, &s)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
-      changed |= was_odd;
-      if (s.done) { changed = true; continue; }
+      if (s.done) continue;
       if (b->mixed) {
         bool refresh = s.need_refresh != 0;
         const bool band_hit = s.need_refresh == 2;
@@ -2306,12 +2467,14 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
           refresh = ratio > pngf::kDriftTol;
         }
         if (refresh) {
-          if (mixed_refresh(h, !s.exact)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
+          ref.push_back(p);
+          meas.push_back(s.exact ? 0 : 1);
           nref[p] += 1;
           if (band_hit) nband[p] += 1;
-          changed = true;
-        } else if (s.kpanel >= pngf::kPanelCap - 12 ||
-                   (h->opt.k_fold > 0 && s.kpanel >= h->opt.k_fold)) {
+          continue;
+        }
+        if (s.kpanel >= pngf::kPanelCap - 12 ||
+            (h->opt.k_fold > 0 && s.kpanel >= h->opt.k_fold)) {
           for (int f = 0; f < int(h->pc.freq.size()); ++f) {
             if (pngf::launch_fold_q(h->P, f, s.kpanel, b->stream) != hipSuccess ||
                 pngf::launch_fold(h->P, f, s.kpanel, b->stream) != hipSuccess) {
@@ -2327,17 +2490,34 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
       next.push_back(p);
     }
     if (rc) break;
-    if (next.size() != active.size()) changed = true;
+    rc = batch_refresh_issue(b, ref, meas, true, pbits);
+    if (rc) break;
+    inflight.swap(ref);
+    inflight_meas.swap(meas);
+    // descriptors keep the problems' order (they are re-uploaded every round)
+    next.insert(next.end(), back.begin(), back.end());
+    std::sort(next.begin(), next.end());
     active.swap(next);
-    (void)changed;   // descriptors are re-uploaded every round (pointers may swap)
+  }
+  if (rc) {
+    // leave no refresh running on the handles' memory
+    for (hipStream_t r : b->rs) (void)hipStreamSynchronize(r);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  if (rc == PNGF_OK && !active.empty()) rc = bfail(b, PNGF_ENUMERIC, "batch search did not terminate");
+  if (rc == PNGF_OK && !(active.empty() && inflight.empty()))
+    rc = bfail(b, PNGF_ENUMERIC, "batch search did not terminate");
   // final FP64 state (mixed), results, and states back to each handle
+  if (rc == PNGF_OK && b->mixed) {
+    std::vector<int> all(n);
+    for (int p = 0; p < n; ++p) all[p] = p;
+    const std::vector<char> none(n, 0);
+    rc = batch_refresh_issue(b, all, none, false, pbits);
+    if (rc == PNGF_OK) rc = batch_refresh_settle(b, all, none, false);
+    if (rc) for (hipStream_t r : b->rs) (void)hipStreamSynchronize(r);
+  }
   for (int p = 0; p < n && rc == PNGF_OK; ++p) {
     pngf_handle* h = b->hs[p];
-    if (b->mixed && fp64_refresh(h)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
     pngf::DbsState fin;
     if (read_state(h, &fin)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
     if (dbs_epilogue(h, fin, f0[p], nref[p], nband[p], accepted ? accepted[p] : nullptr,
@@ -2355,6 +2535,7 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
   }
   hipStreamSynchronize(b->stream);
   hipHostFree(host_states);
+  hipHostFree(pbits);
   return rc;
 }
 
@@ -2367,6 +2548,7 @@ int pngf_batch_ms_per_step(pngf_batch* b, double* ms) {
 int pngf_batch_destroy(pngf_batch* b) {
   if (!b) return PNGF_OK;
   drop_graph(b);
+  release_refresh_streams(b);
   delete b;
   return PNGF_OK;
 }

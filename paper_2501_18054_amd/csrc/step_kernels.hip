@@ -418,164 +418,14 @@ __device__ inline void plain_step_row(const ProbDev& P, int i, int spar, int ksl
   }
 }
 
-// Mixed step over a group of kMixRows rows: each wave handles two rows and
-// streams their C0^-1 rows against g_m (read once for both), then lane 0 of
-// the wave forms p, updates E, R', tau in FP64 and scores the two
-// candidates.  The first kMixPre column chunks of the two rows are fetched
-// before the decision.
-constexpr int kMixPre = 4;
-
-__device__ inline void mixed_step_group(const ProbDev& P, int g, int spar, int kslot, StepCtx& c,
-                                        z64 (*pc)[64], bool publish) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int ra = g * kMixRows + 2 * w, rb = ra + 1;
-  const bool va = ra < P.nd, vb = rb < P.nd;
-  const int dp = spar;
-  const bool pre = P.nfreq == 1;
-  z32 pa[kMixPre], pb[kMixPre];
-#pragma unroll
-  for (int q = 0; q < kMixPre; ++q) {
-    const int j = lane + 64 * q;
-    pa[q] = z32{0.f, 0.f};
-    pb[q] = z32{0.f, 0.f};
-    if (pre && j < P.nd) {
-      if (va) pa[q] = P.C0[0][size_t(ra) * P.ld + j];
-      if (vb) pb[q] = P.C0[0][size_t(rb) * P.ld + j];
-    }
-  }
-  // this pair's FP64 vectors at every frequency, independent of the decision:
-  // lane l < 6 F loads vector l % 3 (E, R', tau) of row l / 3 % 2 at
-  // frequency l / 6 into LDS, so the FP64 tail of each frequency below
-  // waits on no global load
-  __shared__ z64 vpre[kMixRows / 2][kMaxFreq][2][3];
-  const uint8_t* bin = dp ? P.bitsB : P.bits;
-  uint8_t* bout = dp ? P.bits : P.bitsB;
-  if (lane < 6 * P.nfreq) {
-    const int f = lane / 6, h = (lane / 3) & 1, v = lane % 3;
-    if (h ? vb : va) {
-      const z64* src = v == 0 ? (dp ? P.EB[f] : P.E[f])
-                              : (v == 1 ? (dp ? P.RpB[f] : P.Rp[f]) : (dp ? P.tauB[f] : P.tau[f]));
-      vpre[w][f][h][v] = src[h ? rb : ra];
-    }
-  }
-  uint8_t b0a = 0, b0b = 0;
-  if (lane == 0) {
-    if (va) b0a = bin[ra];
-    if (vb) b0b = bin[rb];
-  }
-  if (tid == 0) step_decide(P, spar, kslot, true, c);
-  __syncthreads();
-  if (publish) step_publish(P, spar, kslot, true, c);
-  const int m = c.m;
-  if (m < 0) return;
-  const int slot = c.slot;
-  // panel coefficients alpha_k p_k[m] (reciprocity: q_k . g_m = p_k[m])
-  if (tid < slot)
-    for (int f = 0; f < P.nfreq; ++f)
-      pc[f][tid] = zmul(P.alph[f][tid], up32(P.Pp[f][size_t(tid) * P.ld + m]));
-  __syncthreads();
-  const uint8_t bita = b0a ^ (ra == m ? 1 : 0), bitb = b0b ^ (rb == m ? 1 : 0);
-  const double dla = bita ? -P.deps : P.deps, dlb = bitb ? -P.deps : P.deps;
-  double dfa = 0.0, bnda = 0.0, dfb = 0.0, bndb = 0.0;
-  for (int f = 0; f < P.nfreq; ++f) {
-    const z32* ca = P.C0[f] + size_t(ra) * P.ld;
-    const z32* cb = P.C0[f] + size_t(rb) * P.ld;
-    const z32* gm = P.G32[f] + size_t(m) * P.ld;
-    float par = 0.f, pai = 0.f, pbr = 0.f, pbi = 0.f;
-    // this row pair's panel entries, issued ahead of the stream
-    z32 pka{0.f, 0.f}, pkb{0.f, 0.f};
-    if (lane < slot) {
-      if (va) pka = P.Pp[f][size_t(lane) * P.ld + ra];
-      if (vb) pkb = P.Pp[f][size_t(lane) * P.ld + rb];
-    }
-    int j0 = 0;
-    if (pre) {
-#pragma unroll
-      for (int q = 0; q < kMixPre; ++q) {
-        const int j = lane + 64 * q;
-        if (j < P.nd) {
-          const z32 gv = gm[j];
-          par = fmaf(pa[q].re, gv.re, fmaf(-pa[q].im, gv.im, par));
-          pai = fmaf(pa[q].re, gv.im, fmaf(pa[q].im, gv.re, pai));
-          pbr = fmaf(pb[q].re, gv.re, fmaf(-pb[q].im, gv.im, pbr));
-          pbi = fmaf(pb[q].re, gv.im, fmaf(pb[q].im, gv.re, pbi));
-        }
-      }
-      j0 = 64 * kMixPre;
-    }
-#pragma unroll 4
-    for (int j = j0 + lane; j < P.nd; j += 64) {
-      const z32 gv = gm[j];
-      const z32 av = va ? ca[j] : z32{0.f, 0.f};
-      const z32 bv = vb ? cb[j] : z32{0.f, 0.f};
-      par = fmaf(av.re, gv.re, fmaf(-av.im, gv.im, par));
-      pai = fmaf(av.re, gv.im, fmaf(av.im, gv.re, pai));
-      pbr = fmaf(bv.re, gv.re, fmaf(-bv.im, gv.im, pbr));
-      pbi = fmaf(bv.re, gv.im, fmaf(bv.im, gv.re, pbi));
-    }
-    if (lane < slot) {
-      const z64 cc = pc[f][lane];
-      if (va) {
-        par += float(cc.re * pka.re - cc.im * pka.im);
-        pai += float(cc.re * pka.im + cc.im * pka.re);
-      }
-      if (vb) {
-        pbr += float(cc.re * pkb.re - cc.im * pkb.im);
-        pbi += float(cc.re * pkb.im + cc.im * pkb.re);
-      }
-    }
-    par = wave_sumf(par);
-    pai = wave_sumf(pai);
-    pbr = wave_sumf(pbr);
-    pbi = wave_sumf(pbi);
-    if (lane == 0) {
-      for (int h = 0; h < 2; ++h) {
-        const int r = h ? rb : ra;
-        if (!(h ? vb : va)) continue;
-        const z32 p32{h ? pbr : par, h ? pbi : pai};
-        P.Pp[f][size_t(slot) * P.ld + r] = p32;
-        const z64 p = up32(p32);
-        const z64 ap = zmul(c.alpha[f], p);
-        const z64 Ein = vpre[w][f][h][0];
-        const z64 Rin = vpre[w][f][h][1];
-        const z64 Tin = vpre[w][f][h][2];
-        const z64 Ei = zadd(Ein, zmul(ap, c.Em[f]));
-        const z64 Rpi = zadd(Rin, zmul(ap, c.Rpm[f]));
-        const z64 tau = zadd(Tin, zmul(ap, p));
-        (dp ? P.E[f] : P.EB[f])[r] = Ei;
-        (dp ? P.Rp[f] : P.RpB[f])[r] = Rpi;
-        (dp ? P.tau[f] : P.tauB[f])[r] = tau;
-        if (h) score_terms(P, c, f, tau, Ei, Rpi, dlb, dfb, bndb);
-        else score_terms(P, c, f, tau, Ei, Rpi, dla, dfa, bnda);
-      }
-    }
-  }
-  if (lane == 0) {
-    for (int h = 0; h < 2; ++h) {
-      const int r = h ? rb : ra;
-      if (!(h ? vb : va)) continue;
-      const double df = h ? dfb : dfa, bnd = h ? bndb : bnda;
-      bout[r] = h ? bitb : bita;
-      P.df32[r] = df;
-      P.dfb[r] = bnd;
-      const double margin = df - c.eta * c.f;
-      const double band = P.band * bnd;
-      if (margin >= -band) {
-        const uint32_t k = step_key(P, c, r);
-        if (k != kNoKey) atomicMin(&P.keys[(margin > band ? 0 : 3) + (kslot + 1) % 3], k);
-      }
-    }
-  }
-}
-
-// Mixed step over a group of kWideRows rows, four per wave: the wave streams
-// its four C0^-1 rows against g_m with 16-byte loads (two complex entries per
-// lane and row; g_m read once for all four), then lane h < 4 forms p for row
-// h, updates its FP64 E, R', tau and scores it.  Same products as
-// mixed_step_group (FP32 accumulation, FP64 vectors); the dot products sum
-// in another order.  For many frequencies and large N_d, where the step
-// streams C0^-1 from HBM: more bytes in flight per wave than two rows with
-// 8-byte loads.
+// Mixed step over a group of kWideRows rows, kWideRpw per wave: the wave
+// streams its C0^-1 rows against g_m with 16-byte loads (two complex entries
+// per lane and row; g_m read once for the wave's rows), then lane h <
+// kWideRpw forms p for row h, updates its FP64 E, R', tau and scores it.
+// The products of the mixed search (complex FP32 with FP32 accumulation,
+// FP64 vectors).  Where the step streams C0^-1 from HBM
+// (many frequencies, large N_d, a batch of problems): more bytes in flight
+// per wave than 8-byte loads.
 constexpr int kWideRpw = 2;
 constexpr int kWideRows = 4 * kWideRpw;
 
@@ -708,7 +558,7 @@ __device__ inline void mixed_step_wide(const ProbDev& P, int g, int spar, int ks
 // cover every earlier load of the wave), while waves 1-4 load their two
 // C0^-1 rows whole into registers meanwhile.  After the decision the g_m
 // chunks are issued together, so the GEMV costs about one memory round trip.
-// Same arithmetic as mixed_step_group (FP32 products, FP64 vectors).
+// Same arithmetic as mixed_step_wide (FP32 products, FP64 vectors).
 constexpr int kSplitThreads = 64 * (1 + kMixRows / 2);
 
 template <int PRE>
@@ -1172,7 +1022,7 @@ __global__ __launch_bounds__(kPersistThreads, 1) void k_mixed_persist(ProbDev P,
 // workgroup per row pair, wave 0 decides, worker wave 1 + f handles frequency
 // f of both rows (its C0^-1 rows of that frequency are loaded whole during the
 // decision), and the frequencies' score terms meet in LDS, where wave 1 sums
-// them and publishes the keys.  Same arithmetic as mixed_step_group.
+// them and publishes the keys.  Same arithmetic as mixed_step_wide.
 constexpr int kMfMaxThreads = 64 * (1 + kMaxFreq);
 
 template <int PRE>
@@ -1342,19 +1192,24 @@ __global__ __launch_bounds__(256) void k_mixed_step(ProbDev P, int spar, int ksl
   mixed_step_wide(P, blockIdx.x, spar, kslot, c, pc, blockIdx.x == 0);
 }
 
-// Batched step: one launch advances every problem of a batch by one step.
-// Work item b (a row of one problem on the FP64 path, a group of kMixRows
-// rows on the mixed path) maps to problem p with row0[p] <= b < row0[p+1];
-// the grid is either one workgroup per item or a persistent grid that
-// strides over the items (launch shape chosen by the autotuner).  Problems
+// Batched step: one launch advances every active problem of a batch by one
+// step.  Work item b (a row of one problem on the FP64 path, a group of
+// kMixRows rows on the mixed path) maps to problem p with row0[p] <= b <
+// row0[p+1], p < *nact (the active count lives on the device, so that one
+// captured launch serves any active set); the grid is either one workgroup
+// per item of the whole batch (surplus workgroups exit) or a persistent grid
+// that strides over the items (launch shape chosen by the autotuner).  Problems
 // are independent (Results, Computational efficiency: per-frequency and
 // per-design systems need no communication).
+static_assert(kWideRows == kMixRows, "a batch work item is one group of kMixRows rows");
 template <int NPL, bool MIXED>
 __global__ __launch_bounds__(kRowThreads) void k_batch_step(const ProbDev* probs,
-                                                            const int32_t* row0, int nprob,
-                                                            int spar, int kslot) {
+                                                            const int32_t* row0,
+                                                            const int32_t* nact, int spar,
+                                                            int kslot) {
   __shared__ StepCtx c;
   __shared__ z64 pc[kMaxFreq][64];
+  const int nprob = *nact;          // problems stepped by this launch (descriptors 0..nprob-1)
   const int total = row0[nprob];
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
     int lo = 0, hi = nprob - 1;       // largest p with row0[p] <= b
@@ -1365,7 +1220,7 @@ __global__ __launch_bounds__(kRowThreads) void k_batch_step(const ProbDev* probs
     const ProbDev& P = probs[lo];
     const int i = b - row0[lo];
     __syncthreads();   // the previous item is done with the shared context
-    if (MIXED) mixed_step_group(P, i, spar, kslot, c, pc, i == 0);
+    if (MIXED) mixed_step_wide(P, i, spar, kslot, c, pc, i == 0);
     else plain_step_row<NPL>(P, i, spar, kslot, c);
   }
 }
@@ -1611,19 +1466,19 @@ hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint64_t* 
   return launch_persist_pre<32>(P, t0, nsteps, bar, flag, spin_limit, bandp, wstat, s);
 }
 
-hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, int nprob, int total,
-                             int grid, int npl, int mixed, int step, hipStream_t s) {
+hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, const int32_t* nact,
+                             int total, int grid, int npl, int mixed, int step, hipStream_t s) {
   const int g = (grid > 0 && grid < total) ? grid : total;
   if (g <= 0) return hipSuccess;
   if (mixed) {
     // separate instantiation: the mixed path needs far fewer registers
     hipLaunchKernelGGL((k_batch_step<1, true>), dim3(g), dim3(kRowThreads), 0, s, probs, row0,
-                       nprob, step & 1, step % 3);
+                       nact, step & 1, step % 3);
     return hipGetLastError();
   }
 #define L_(N)                                                                          \
   hipLaunchKernelGGL((k_batch_step<N, false>), dim3(g), dim3(kRowThreads), 0, s, probs, row0, \
-                     nprob, step & 1, step % 3)
+                     nact, step & 1, step % 3)
   switch (npl) {
     case 1: L_(1); break;
     case 2: L_(2); break;

@@ -1,7 +1,8 @@
 """Batched search (one launch per step over every problem, hipGraph replays)
 equals the solo search of each problem: identical accepted sequences and
-attempt counts, objectives to 1e-12 relative; the autotuner's launch shapes
-all give the same arithmetic."""
+attempt counts, final objectives to 1e-12 relative (objective traces to 1e-12
+for FP64 steps, to FP32 rounding for mixed ones); the autotuner's launch
+shapes all give the same arithmetic."""
 import numpy as np
 import pytest
 
@@ -50,8 +51,12 @@ def test_batch_equals_solo(problems, stream, prec):
         assert r["attempts"] == s["attempts"], k
         assert r["converged"] == s["converged"], k
         assert abs(r["f_final"] - s["f_final"]) <= 1e-12 * abs(s["f_final"]), k
-        # same kernels, same per-row arithmetic, same re-inversion points
-        tol = 1e-12
+        # same re-inversion points; FP64 steps run the same per-row arithmetic.
+        # The batch's mixed step sums its FP32 products in another order than
+        # the solo persistent / several-frequency kernels these sizes take, so
+        # the objective trace carries FP32 rounding; the decisions do not (the
+        # error band sends close calls to FP64), hence identical sequences
+        tol = 1e-12 if prec == "plain" else 1e-5
         assert r["n_refresh"] == s["n_refresh"], k
         if len(s["f_trace"]):
             assert rel(r["f_trace"], s["f_trace"]) < tol, (k, r["n_refresh"], s["n_refresh"],
