@@ -360,59 +360,69 @@ __global__ __launch_bounds__(kSmallInvThreads) void k_small_inverse(z64* A, int 
 // the row-permuted matrix, its rows left where they are).  Lane (r, h) =
 // (lane % 32, lane / 32) holds entries [16h, 16h + 16) of row r in
 // registers.  Per column: the pivot by a wave maximum of (|a|^2, row) keys,
-// the scaled pivot row and every row's factor through LDS (one barrier),
-// then 16 complex updates per lane.  status is set on a zero pivot.
+// the pivot row and every row's factor through LDS (one barrier), then 16
+// complex updates per lane.  status is set on a zero pivot.
 constexpr int kWaveInv = 32;
 
 struct WaveInvLds {
-  z64 prow[2][kWaveInv];   // scaled pivot row, by column parity
+  z64 prow[2][kWaveInv];   // pivot row (1 in the pivot column), by column parity
   z64 fac[2][kWaveInv];    // every row's entry in the pivot column
   int pv[kWaveInv];        // pivot row of each column
 };
 
-template <int C>
-__device__ __forceinline__ void wave_inv_column(z64 (&w)[16], int k, int r, int h, int lane,
-                                                int& myq, WaveInvLds& sm, int32_t* status) {
+// Column C = 16 hc + CC of the one-wave Gauss-Jordan inverse (CC fixed at
+// compile time, so the lanes holding column C read it from a fixed register;
+// the two halves hc run as a loop, which keeps the code small enough for the
+// instruction cache).  The pivot (largest |a|^2 among the rows not yet
+// pivoted) comes from a DPP maximum of (|a|^2, row) keys; its two lanes post
+// the raw pivot row to LDS, one lane puts 1 in its column C, and every lane
+// then forms a <- alpha a + beta u with u the posted row: alpha = 0 and beta
+// = 1/p for the pivot row (the row scaled, 1/p in column C), alpha = 1 and
+// beta = -a_iC/p elsewhere (column C becomes -a_iC/p, every other entry is
+// reduced).  1/p from the hardware reciprocal and two Newton steps.
+template <int CC>
+__device__ __forceinline__ void wave_inv_column(z64 (&w)[16], int hc, int k, int r, int h,
+                                                int lane, int& myq, WaveInvLds& sm,
+                                                int32_t* status) {
+  const int C = 16 * hc + CC;
   if (C >= k) return;
-  constexpr int hc = C / 16, cc = C % 16, buf = C & 1;
+  constexpr int buf = CC & 1;
   uint32_t key = 0;
   if (h == hc && r < k && myq < 0)
-    key = (__float_as_uint(float(zabs2(w[cc]))) & ~31u) | uint32_t(31 - r);
+    key = (__float_as_uint(float(zabs2(w[CC]))) & ~31u) | uint32_t(31 - r);
   const int p = 31 - int(wave_max_u32(key) & 31u);
   const int pl = p + kWaveInv * hc;
-  const z64 apc{lane_d(w[cc].re, pl), lane_d(w[cc].im, pl)};
-  const bool zero = !(zabs2(apc) > 0.0);
-  if (zero && lane == 0) atomicOr(status, 1);
-  const z64 inv = zero ? z64{0.0, 0.0} : zdiv(z64{1.0, 0.0}, apc);
-  if (r == p) {
-    // the pivot row scaled by 1/a_pc, with 1/a_pc in column C
+  const z64 apc{lane_d(w[CC].re, pl), lane_d(w[CC].im, pl)};
+  if (!(zabs2(apc) > 0.0) && lane == 0) atomicOr(status, 1);
+  const z64 inv = zrecip_newton(apc);   // 0 for a zero pivot
+  const bool piv = r == p;
+  if (piv) {
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj)
-      sm.prow[buf][16 * h + jj] = (16 * h + jj == C) ? inv : zmul(w[jj], inv);
+    for (int jj = 0; jj < 16; ++jj) sm.prow[buf][16 * h + jj] = w[jj];
     myq = C;
   }
-  if (h == hc) sm.fac[buf][r] = w[cc];
-  if (lane == 0) sm.pv[C] = p;
+  if (h == hc) sm.fac[buf][r] = w[CC];
+  if (lane == 0) {
+    sm.pv[C] = p;
+    sm.prow[buf][C] = z64{1.0, 0.0};   // after the pivot lanes' store (one wave: in order)
+  }
   __syncthreads();
-  if (r == p) {
+  const z64 fi = zmul(sm.fac[buf][r], inv);
+  const z64 beta = piv ? inv : z64{-fi.re, -fi.im};
+  const double alpha = piv ? 0.0 : 1.0;
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) w[jj] = sm.prow[buf][16 * h + jj];
-  } else {
-    const z64 f = sm.fac[buf][r];
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-      const int l = 16 * h + jj;
-      const z64 old = (l == C) ? z64{0.0, 0.0} : w[jj];
-      w[jj] = zsub(old, zmul(f, sm.prow[buf][l]));
-    }
+  for (int jj = 0; jj < 16; ++jj) {
+    z64 x = zscale(w[jj], alpha);
+    if (jj == CC && h == hc) x = z64{0.0, 0.0};
+    w[jj] = zfma(beta, sm.prow[buf][16 * h + jj], x);
   }
 }
 
-template <int... Cs>
-__device__ __forceinline__ void wave_inv_columns(z64 (&w)[16], int k, int r, int h, int lane,
-                                                 int& myq, WaveInvLds& sm, int32_t* status,
-                                                 std::integer_sequence<int, Cs...>) {
-  (wave_inv_column<Cs>(w, k, r, h, lane, myq, sm, status), ...);
+template <int... CCs>
+__device__ __forceinline__ void wave_inv_half(z64 (&w)[16], int hc, int k, int r, int h, int lane,
+                                              int& myq, WaveInvLds& sm, int32_t* status,
+                                              std::integer_sequence<int, CCs...>) {
+  (wave_inv_column<CCs>(w, hc, k, r, h, lane, myq, sm, status), ...);
 }
 
 __global__ __launch_bounds__(64) void k_small_inverse_wave(z64* A, int k, int32_t* status) {
@@ -426,7 +436,8 @@ __global__ __launch_bounds__(64) void k_small_inverse_wave(z64* A, int k, int32_
     w[jj] = (r < k && l < k) ? A[r * k + l] : z64{0.0, 0.0};
   }
   int myq = -1;   // the column this lane's row is the pivot of
-  wave_inv_columns(w, k, r, h, lane, myq, sm, status, std::make_integer_sequence<int, kWaveInv>{});
+  for (int hc = 0; hc < 2; ++hc)
+    wave_inv_half(w, hc, k, r, h, lane, myq, sm, status, std::make_integer_sequence<int, 16>{});
   __syncthreads();
   if (r < k && myq >= 0)
 #pragma unroll

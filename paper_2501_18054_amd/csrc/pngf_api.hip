@@ -2122,17 +2122,12 @@ void release_refresh_streams(pngf_batch* b) {
   b->ev_round = nullptr;
 }
 
-// FP64 refreshes of several problems of a batch, issued together: their
-// designs come up in one copy (one wait), then each problem's block-Woodbury
-// update, field re-formation and (rescore) FP64 rescoring + band measurement
-// are queued on one of the refresh streams, round-robin, after the work
-// queued so far on the batch stream, so that the small kernels of different
-// problems overlap each other and the batch's next steps.  Without rescore
-// (the end of a search) only the FP64 state is re-formed.  pbits: pinned host
-// memory for the designs (the sum of the problems' N_d bytes).  No wait for
-// the refreshes themselves: batch_refresh_settle.
-int batch_refresh_issue(pngf_batch* b, const std::vector<int>& ref, const std::vector<char>& meas,
-                        bool rescore, uint8_t* pbits) {
+// FP64 refreshes of several problems of a batch, in three parts.
+// batch_refresh_fetch: their designs come up in one copy (one wait on the
+// batch stream), and the refresh streams' start event is recorded there.
+// pbits: pinned host memory for the designs (the sum of the problems' N_d
+// bytes).
+int batch_refresh_fetch(pngf_batch* b, const std::vector<int>& ref, uint8_t* pbits) {
   if (ref.empty()) return PNGF_OK;
   std::vector<size_t> boff;
   size_t off = 0;
@@ -2144,12 +2139,28 @@ int batch_refresh_issue(pngf_batch* b, const std::vector<int>& ref, const std::v
   }
   BHIPCHK(b, hipStreamSynchronize(b->stream));
   BHIPCHK(b, hipEventRecord(b->ev_round, b->stream));
-  const int K = std::min<int>(int(b->rs.size()), int(ref.size()));
-  for (int k = 0; k < K; ++k) BHIPCHK(b, hipStreamWaitEvent(b->rs[k], b->ev_round, 0));
   for (size_t j = 0; j < ref.size(); ++j) {
     pngf_handle* h = b->hs[ref[j]];
     h->bits.assign(pbits + boff[j], pbits + boff[j] + h->pc.n_d);
     h->bits_fresh = true;
+  }
+  return PNGF_OK;
+}
+
+// batch_refresh_launch: each problem's block-Woodbury update, field
+// re-formation and (rescore) FP64 rescoring + band measurement are queued on
+// one of the refresh streams, round-robin, after the fetch's event, so that
+// the small kernels of different problems overlap each other and whatever
+// the batch stream runs meanwhile (the host's issue time overlaps it too).
+// Without rescore (the end of a search) only the FP64 state is re-formed.
+// No wait: batch_refresh_settle.
+int batch_refresh_launch(pngf_batch* b, const std::vector<int>& ref,
+                         const std::vector<char>& meas, bool rescore) {
+  if (ref.empty()) return PNGF_OK;
+  const int K = std::min<int>(int(b->rs.size()), int(ref.size()));
+  for (int k = 0; k < K; ++k) BHIPCHK(b, hipStreamWaitEvent(b->rs[k], b->ev_round, 0));
+  for (size_t j = 0; j < ref.size(); ++j) {
+    pngf_handle* h = b->hs[ref[j]];
     h->stream = b->rs[j % K];
     h->wood_pending = false;
     int st;
@@ -2175,7 +2186,8 @@ int batch_refresh_issue(pngf_batch* b, const std::vector<int>& ref, const std::v
   return PNGF_OK;
 }
 
-// Wait for the refreshes batch_refresh_issue queued, then let each problem
+// batch_refresh_settle: wait for the refreshes batch_refresh_launch queued,
+// then let each problem
 // take its band (or re-invert, on the batch stream, if its deferred update
 // was singular).
 int batch_refresh_settle(pngf_batch* b, const std::vector<int>& ref,
@@ -2407,29 +2419,44 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
   hipEventCreate(&e1);
   int64_t max_rounds = 0;
   for (pngf_handle* h : b->hs) max_rounds = std::max<int64_t>(max_rounds, 4 * int64_t(h->opt.max_accepts) + 64);
-  // refreshes issued at the end of one round run beside the next round's
-  // steps of the other problems; their problems skip that round and rejoin
-  // the one after (a problem's own sequence does not depend on when its steps
-  // run)
-  std::vector<int> inflight;
-  std::vector<char> inflight_meas;
-  for (int64_t round = 0; round < max_rounds && !(active.empty() && inflight.empty()); ++round) {
-    if (!active.empty()) {
-      const bool tuning = ci < cand.size();
+  // A problem that needs a refresh sits out one round: its refresh is queued
+  // on the refresh streams just after that round's steps (it runs beside
+  // them, and so does the host's issue time), settled after them, and the
+  // problem rejoins the round after (its own sequence does not depend on
+  // when its steps run).
+  std::vector<int> toissue, inflight;
+  std::vector<char> toissue_meas, inflight_meas;
+  for (int64_t round = 0; round < max_rounds && !(active.empty() && toissue.empty()); ++round) {
+    const bool stepping = !active.empty();
+    const bool tuning = stepping && ci < cand.size();
+    int reps = 0;
+    if (stepping) {
       if (tuning) grid = cand[ci];
       rc = batch_prepare(b, active, grid);
       if (rc) break;
       hipEventRecord(e0, b->stream);
-      const int reps = tuning ? 1 : 5;   // 30 steps per round: about one refresh interval
+      reps = tuning ? 1 : 5;   // 30 steps per round: about one refresh interval
       for (int r = 0; r < reps && rc == PNGF_OK; ++r) {
         hipError_t e = hipGraphLaunch(b->exec, b->stream);
         if (e != hipSuccess) rc = bfail(b, PNGF_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
       }
       if (rc) break;
       hipEventRecord(e1, b->stream);
-      hipError_t e = hipMemcpyAsync(host_states, b->d_states, 2 * n * sizeof(pngf::DbsState),
-                                    hipMemcpyDeviceToHost, b->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+      if (hipMemcpyAsync(host_states, b->d_states, 2 * n * sizeof(pngf::DbsState),
+                         hipMemcpyDeviceToHost, b->stream) != hipSuccess) {
+        rc = bfail(b, PNGF_EDEVICE, "state read failed");
+        break;
+      }
+    }
+    // the refreshes decided last round, beside this round's steps
+    rc = batch_refresh_launch(b, toissue, toissue_meas, true);
+    if (rc) break;
+    inflight.swap(toissue);
+    inflight_meas.swap(toissue_meas);
+    toissue.clear();
+    toissue_meas.clear();
+    if (stepping) {
+      const hipError_t e = hipStreamSynchronize(b->stream);
       if (e != hipSuccess) { rc = bfail(b, PNGF_EDEVICE, hipGetErrorString(e)); break; }
       float ms = 0.f;
       hipEventElapsedTime(&ms, e0, e1);
@@ -2445,14 +2472,12 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
         }
       }
     }
-    // last round's refreshes are done (they overlapped this round's steps)
-    std::vector<int> back;
     rc = batch_refresh_settle(b, inflight, inflight_meas, true);
     if (rc) break;
+    std::vector<int> back;
     back.swap(inflight);
     inflight_meas.clear();
-    std::vector<int> next, ref;
-    std::vector<char> meas;
+    std::vector<int> next;
     for (int p : active) {
       pngf_handle* h = b->hs[p];
       pngf::DbsState& s = host_states[2 * p];
@@ -2467,8 +2492,8 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
           refresh = ratio > pngf::kDriftTol;
         }
         if (refresh) {
-          ref.push_back(p);
-          meas.push_back(s.exact ? 0 : 1);
+          toissue.push_back(p);
+          toissue_meas.push_back(s.exact ? 0 : 1);
           nref[p] += 1;
           if (band_hit) nband[p] += 1;
           continue;
@@ -2490,10 +2515,8 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
       next.push_back(p);
     }
     if (rc) break;
-    rc = batch_refresh_issue(b, ref, meas, true, pbits);
+    rc = batch_refresh_fetch(b, toissue, pbits);
     if (rc) break;
-    inflight.swap(ref);
-    inflight_meas.swap(meas);
     // descriptors keep the problems' order (they are re-uploaded every round)
     next.insert(next.end(), back.begin(), back.end());
     std::sort(next.begin(), next.end());
@@ -2505,14 +2528,15 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  if (rc == PNGF_OK && !(active.empty() && inflight.empty()))
+  if (rc == PNGF_OK && !(active.empty() && toissue.empty()))
     rc = bfail(b, PNGF_ENUMERIC, "batch search did not terminate");
   // final FP64 state (mixed), results, and states back to each handle
   if (rc == PNGF_OK && b->mixed) {
     std::vector<int> all(n);
     for (int p = 0; p < n; ++p) all[p] = p;
     const std::vector<char> none(n, 0);
-    rc = batch_refresh_issue(b, all, none, false, pbits);
+    rc = batch_refresh_fetch(b, all, pbits);
+    if (rc == PNGF_OK) rc = batch_refresh_launch(b, all, none, false);
     if (rc == PNGF_OK) rc = batch_refresh_settle(b, all, none, false);
     if (rc) for (hipStream_t r : b->rs) (void)hipStreamSynchronize(r);
   }
