@@ -263,12 +263,22 @@ __global__ __launch_bounds__(256) void k_wood_scale(z64* P, int ldp, int nd, int
   const int i = int(e / k), c = int(e % k);
   P[size_t(i) * ldp + c] = zscale(P[size_t(i) * ldp + c], s[c]);
 }
+// kdev (nullable): the number of real flips on the device, the rest of the
+// k entries being padding (pixel 0, scale 0): their rows of Cap are identity
+// rows (their columns already are), and a count above k is reported as
+// status 4.
 __global__ __launch_bounds__(256) void k_wood_cap(const z64* P, int ldp, const int32_t* F, int k,
-                                                  z64* Cap, int32_t* status) {
+                                                  z64* Cap, int32_t* status,
+                                                  const int32_t* kdev) {
   const int e = blockIdx.x * 256 + threadIdx.x;
-  if (status && e == 0) *status = 0;   // before the capacitance inverse reports
+  // before the capacitance inverse reports
+  if (status && e == 0) *status = (kdev && *kdev > k) ? 4 : 0;
   if (e >= k * k) return;
   const int a = e / k, c = e % k;
+  if (kdev && a >= *kdev) {
+    Cap[e] = z64{a == c ? 1.0 : 0.0, 0.0};
+    return;
+  }
   const z64 p = P[size_t(F[a]) * ldp + c];
   Cap[e] = z64{(a == c ? 1.0 : 0.0) - p.re, -p.im};
 }
@@ -528,10 +538,10 @@ hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_
 __global__ __launch_bounds__(256) void k_wood_panel(const z64* work, int nz, int nd, int k,
                                                     const double* sc, z64* P, int ldp,
                                                     const int32_t* F, z64* Cap,
-                                                    int32_t* status) {
+                                                    int32_t* status, const int32_t* kdev) {
   const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
   const size_t np = size_t(nd) * k;
-  if (status && e == 0) *status = 0;
+  if (status && e == 0) *status = (kdev && *kdev > k) ? 4 : 0;
   if (e < np) {
     z64 v{0.0, 0.0};
     for (int z = 0; z < nz; ++z) v = zadd(v, work[size_t(z) * np + e]);
@@ -539,6 +549,10 @@ __global__ __launch_bounds__(256) void k_wood_panel(const z64* work, int nz, int
     P[size_t(i) * ldp + c] = zscale(zmul(z64{1.0, 0.0}, v), sc[c]);
   } else if (e < np + size_t(k) * k) {
     const int q = int(e - np), a = q / k, c = q % k;
+    if (kdev && a >= *kdev) {   // a padding row (see k_wood_cap)
+      Cap[q] = z64{a == c ? 1.0 : 0.0, 0.0};
+      return;
+    }
     const size_t src = size_t(F[a]) * k + c;
     z64 v{0.0, 0.0};
     for (int z = 0; z < nz; ++z) v = zadd(v, work[size_t(z) * np + src]);
@@ -548,11 +562,12 @@ __global__ __launch_bounds__(256) void k_wood_panel(const z64* work, int nz, int
 }
 
 hipError_t launch_wood_panel(const z64* work, int nz, int nd, int k, const double* sc, z64* P,
-                             int ldp, const int32_t* F, z64* Cap, int32_t* status, hipStream_t s) {
+                             int ldp, const int32_t* F, z64* Cap, int32_t* status, hipStream_t s,
+                             const int32_t* kdev) {
   if (k <= 0) return hipSuccess;
   const size_t n = size_t(nd) * k + size_t(k) * k;
   hipLaunchKernelGGL(k_wood_panel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, work, nz, nd,
-                     k, sc, P, ldp, F, Cap, status);
+                     k, sc, P, ldp, F, Cap, status, kdev);
   return hipGetLastError();
 }
 
@@ -566,13 +581,13 @@ hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int 
 
 // status (nullable) is cleared before the capacitance matrix is formed.
 hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, const double* sc,
-                           z64* Cap, int32_t* status, hipStream_t s) {
+                           z64* Cap, int32_t* status, hipStream_t s, const int32_t* kdev) {
   if (k <= 0) return hipSuccess;
   const size_t n = size_t(nd) * k;
   hipLaunchKernelGGL(k_wood_scale, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, P, ldp, nd, k,
                      sc);
   hipLaunchKernelGGL(k_wood_cap, dim3((k * k + 255) / 256), dim3(256), 0, s, P, ldp, F, k, Cap,
-                     status);
+                     status, kdev);
   return hipGetLastError();
 }
 

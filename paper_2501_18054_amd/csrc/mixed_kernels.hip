@@ -81,10 +81,13 @@ __global__ __launch_bounds__(256) void k_fold(ProbDev P, int f, int kp) {
 // out[0] = the measurement; out[1] = *status (nullable) as a double, so that
 // one read brings both to the host; bandp (nullable) receives the band the
 // measurement sets, min(1e-2, max(1e-6, 100 m)) when m is finite.
+// gate (nullable): the measurement is skipped while *gate is 0.
 __global__ __launch_bounds__(256) void k_band_measure(const double* df32, const double* bnd32,
                                                       const double* df64, int nd, double* out,
-                                                      const int32_t* status, double* bandp) {
+                                                      const int32_t* status, double* bandp,
+                                                      const int32_t* gate) {
   __shared__ double red[4];
+  if (gate && *gate == 0) return;
   double mx = 0.0;
   for (int i = threadIdx.x; i < nd; i += 256) {
     const double b = bnd32[i];
@@ -99,6 +102,72 @@ __global__ __launch_bounds__(256) void k_band_measure(const double* df32, const 
     out[0] = m;
     out[1] = status ? double(*status) : 0.0;
     if (bandp && isfinite(m)) *bandp = fmin(1e-2, fmax(1e-6, 100.0 * m));
+  }
+}
+
+// The device-side start of a refresh that the host queues behind a batch of
+// steps before it has read the batch's end state (one workgroup):
+//  * an odd number of updates since the last normalization leaves the
+//    current E, R', tau and design in the B buffers: they are copied to the
+//    A buffers (the state's flip count back to 0), so that the refresh and
+//    the next batch read the A set;
+//  * the pixels whose bit differs from the design bref of C^-1, ascending,
+//    with the scales k0^2 (+-delta eps) of each frequency (dS[f kpad + c]),
+//    padded to kpad entries with pixel 0 and scale 0 (zero columns of the
+//    block-Woodbury panel); bref becomes the current design (that of C^-1
+//    once the update is done);
+//  * wk[0] = their count (above kpad the capacitance kernel reports it),
+//    wk[1] = 1 when the scores are FP32 results to be measured (the state is
+//    not exact).
+__global__ __launch_bounds__(256) void k_wood_prep(ProbDev P, uint8_t* bref, int kpad,
+                                                   int32_t* dF, double* dS, int32_t* wk) {
+  __shared__ int wcnt[4];
+  __shared__ int base;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  DbsState* st = P.st;
+  const int odd = st->flips & 1;
+  if (odd) {
+    for (int i = tid; i < P.nd; i += 256) {
+      for (int f = 0; f < P.nfreq; ++f) {
+        P.E[f][i] = P.EB[f][i];
+        P.Rp[f][i] = P.RpB[f][i];
+        P.tau[f][i] = P.tauB[f][i];
+      }
+      P.bits[i] = P.bitsB[i];
+    }
+  }
+  if (tid == 0) base = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < P.nd; i0 += 256) {
+    const int i = i0 + tid;
+    const uint8_t b = i < P.nd ? P.bits[i] : 0;   // this thread copied bits[i]
+    const bool d = i < P.nd && b != bref[i];
+    if (d) bref[i] = b;   // the design of C^-1 once the update is done
+    const uint64_t bal = __ballot(d);
+    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[w] = __popcll(bal);
+    __syncthreads();
+    int off = base;
+    for (int v = 0; v < w; ++v) off += wcnt[v];
+    if (d && off + pre < kpad) {
+      const int c = off + pre;
+      dF[c] = i;
+      const double delta = b ? P.deps : -P.deps;
+      for (int f = 0; f < P.nfreq; ++f) dS[size_t(f) * kpad + c] = P.k0sq[f] * delta;
+    }
+    __syncthreads();
+    if (tid == 0) base += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  const int k = base;
+  for (int c = k + tid; c < kpad; c += 256) {
+    dF[c] = 0;
+    for (int f = 0; f < P.nfreq; ++f) dS[size_t(f) * kpad + c] = 0.0;
+  }
+  if (tid == 0) {
+    wk[0] = k;
+    wk[1] = st->exact ? 0 : 1;
+    if (odd) st->flips = 0;
   }
 }
 
@@ -117,9 +186,15 @@ hipError_t launch_fold(const ProbDev& P, int f, int kp, hipStream_t s) {
 
 hipError_t launch_band_measure(const double* df32, const double* bnd32, const double* df64,
                                int nd, double* out, const int32_t* status, hipStream_t s,
-                               double* bandp) {
+                               double* bandp, const int32_t* gate) {
   hipLaunchKernelGGL(k_band_measure, dim3(1), dim3(256), 0, s, df32, bnd32, df64, nd, out, status,
-                     bandp);
+                     bandp, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_wood_prep(const ProbDev& P, uint8_t* bref, int kpad, int32_t* dF,
+                            double* dS, int32_t* wk, hipStream_t s) {
+  hipLaunchKernelGGL(k_wood_prep, dim3(1), dim3(256), 0, s, P, bref, kpad, dF, dS, wk);
   return hipGetLastError();
 }
 

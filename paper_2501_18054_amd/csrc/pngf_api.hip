@@ -40,10 +40,14 @@ hipError_t launch_rform_t0_init(const ProbDev& P, int f, hipStream_t s);
 hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int k, int n, z64* dst,
                               int ldd, hipStream_t s);
 hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, const double* sc,
-                           z64* Cap, int32_t* status, hipStream_t s);
+                           z64* Cap, int32_t* status, hipStream_t s,
+                           const int32_t* kdev = nullptr);
 hipError_t launch_small_inverse(z64* A, int k, int32_t* status, hipStream_t s);
 hipError_t launch_wood_panel(const z64* work, int nz, int nd, int k, const double* sc, z64* P,
-                             int ldp, const int32_t* F, z64* Cap, int32_t* status, hipStream_t s);
+                             int ldp, const int32_t* F, z64* Cap, int32_t* status, hipStream_t s,
+                             const int32_t* kdev = nullptr);
+hipError_t launch_wood_prep(const ProbDev& P, uint8_t* bref, int kpad, int32_t* dF,
+                            double* dS, int32_t* wk, hipStream_t s);
 hipError_t launch_gradient(const ProbDev& P, double* out, hipStream_t s);
 hipError_t launch_tile_score(const ProbDev& P, const int32_t* tiles, int ntiles, int m, int ks,
                              z64* part, double* out, hipStream_t s);
@@ -74,7 +78,7 @@ hipError_t launch_to_c64(const z64* src, z32* dst, int nd, int ld, hipStream_t s
 hipError_t launch_fold(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_band_measure(const double* df32, const double* bnd32, const double* df64,
                                int nd, double* out, const int32_t* status, hipStream_t s,
-                               double* bandp = nullptr);
+                               double* bandp = nullptr, const int32_t* gate = nullptr);
 constexpr int kGjNbHost = 16;
 constexpr int kPanelCap = 64;      // deferred Sherman-Morrison terms (mixed)
 constexpr int kMixedBatch = 16;    // device steps between host checks (mixed)
@@ -89,6 +93,7 @@ constexpr size_t kPinStage = kPinBytes;      // then the batch-end read (state .
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
 constexpr int kBatchRefreshStreams = 4;   // streams a batch spreads one round's refreshes over
+constexpr int kAheadMaxK = 32;   // largest k_refresh whose refreshes are queued ahead of the host
 constexpr int kTilePartPerPixel = 512;   // tile-score partial blocks (complex) per pixel
 constexpr int kTileSlicesMax = 32;       // K slices of one tile's block
 constexpr int kWoodSplits = 8;     // split-K factor of its skinny GEMM
@@ -116,7 +121,7 @@ struct Layout {
   size_t off_bits, off_perm, off_rank, off_cand, off_df, off_logp, off_logf, off_state;
   size_t off_C0[pngf::kMaxFreq], off_G32[pngf::kMaxFreq], off_Pp[pngf::kMaxFreq],
       off_Qp[pngf::kMaxFreq], off_alph[pngf::kMaxFreq], off_pcoef[pngf::kMaxFreq];
-  size_t off_df32, off_dfb, off_bandout;
+  size_t off_df32, off_dfb, off_bandout, off_bref, off_wk;
   size_t off_sidx, off_zidx, off_pos, off_rowmap;
   size_t off_CB[pngf::kMaxFreq], off_EB[pngf::kMaxFreq], off_RpB[pngf::kMaxFreq],
       off_tauB[pngf::kMaxFreq];
@@ -172,6 +177,7 @@ struct pngf_handle {
   char* pin = nullptr;             // pinned scratch of small transfers, then a staging area
   size_t pin_bytes = 0;
   hipEvent_t ev_pin = nullptr;     // recorded after the last upload from `pin`
+  hipEvent_t ev_ahead = nullptr;   // after a batch's state read, ahead of its refresh
   std::vector<int32_t> w_fl;
   std::vector<double> w_sc;
   bool wood_pending = false;       // a Woodbury status not yet read
@@ -249,6 +255,10 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     L.off_df32 = take(size_t(nd) * sizeof(double));
     L.off_dfb = take(size_t(nd) * sizeof(double));
     L.off_bandout = take(2 * sizeof(double));
+    // a refresh queued ahead of the host: the design of C^-1 on the device,
+    // the flip count and the measurement gate
+    L.off_bref = take(size_t(nd));
+    L.off_wk = take(4 * sizeof(int32_t));
   }
   if (o->precision == PNGF_RFORM) {
     const size_t kr = size_t(pngf::kRPanel);
@@ -986,6 +996,168 @@ int mixed_residual(pngf_handle* h, double* ratio) {
   return PNGF_OK;
 }
 
+// The periodic refresh of the persistent mixed search, queued right behind
+// the batch of steps it follows, before the host has read that batch's end
+// state: the parity fix of the buffers, the flip list, its scales and the
+// measurement gate come from the device (k_wood_prep, which also records the
+// design C^-1 will hold); the block-Woodbury update runs on kpad = k_refresh
+// columns (padding entries: pixel 0 with scale 0, which leave the result
+// unchanged); then the field re-formation (which also writes C0^-1), the FP64
+// rescoring and, when the scores were FP32, the band measurement.  If the
+// batch ended the search, this re-forms the final design's state (which the
+// final refresh then finds done); a singular capacitance matrix or more
+// flips than kpad leave the status word set, and the next batch runs no step.
+int refresh_ahead(pngf_handle* h) {
+  const int nd = h->pc.n_d, ld = h->ld;
+  const Layout& L = h->lay;
+  pngf::ProbDev& P = h->P;
+  const int kpad = h->opt.k_refresh;
+  int32_t* dF = at<int32_t>(h, L.off_wF);
+  double* dS = at<double>(h, L.off_wS);
+  int32_t* wk = at<int32_t>(h, L.off_wk);
+  int32_t* status = at<int32_t>(h, L.off_status);
+  uint8_t* bref = at<uint8_t>(h, L.off_bref);
+  const z64 one{1.0, 0.0}, zero{0.0, 0.0};
+  HIPCHK(h, pngf::launch_wood_prep(P, bref, kpad, dF, dS, wk, h->stream));
+  {
+    Timer t(h, KID_WOOD);
+    z64* wP = at<z64>(h, L.off_wP[0]);
+    z64* wQ = at<z64>(h, L.off_wQ[0]);
+    z64* wW = at<z64>(h, L.off_wW[0]);
+    z64* cap = at<z64>(h, L.off_wCap[0]);
+    z64* work = at<z64>(h, L.off_wWork[0]);
+    int nzp = 0;
+    HIPCHK(h, pngf::launch_zgemm(nd, kpad, nd, P.Cinv[0], ld, nullptr, P.G[0], ld, true, dF, wP,
+                                 kpad, one, zero, pngf::kWoodSplits, work, h->stream, &nzp));
+    if (nzp > 0)
+      HIPCHK(h, pngf::launch_wood_panel(work, nzp, nd, kpad, dS, wP, kpad, dF, cap, status,
+                                        h->stream, wk));
+    else
+      HIPCHK(h, pngf::launch_wood_cap(wP, kpad, nd, dF, kpad, dS, cap, status, h->stream, wk));
+    HIPCHK(h, pngf::launch_small_inverse(cap, kpad, status, h->stream));
+    if (h->force_singular > 0) {
+      // test hook: this refresh reports a singular capacitance matrix
+      HIPCHK(h, hipMemsetAsync(status, 1, sizeof(int32_t), h->stream));
+      --h->force_singular;
+    }
+    HIPCHK(h, pngf::launch_gather_rows(P.Cinv[0], ld, dF, kpad, nd, wQ, nd, h->stream));
+    HIPCHK(h, pngf::launch_zgemm(kpad, nd, kpad, cap, kpad, nullptr, wQ, nd, false, nullptr, wW,
+                                 nd, one, zero, 1, nullptr, h->stream));
+    HIPCHK(h, pngf::launch_zgemm(nd, nd, kpad, wP, kpad, nullptr, wW, nd, false, nullptr,
+                                 P.Cinv[0], ld, one, one, 1, nullptr, h->stream));
+    t.end(1);
+  }
+  int st;
+  {
+    C64Pass c64pass(h);
+    st = reform_fields(h);
+  }
+  if (st) return st;
+  st = start_segment(h, true);
+  if (st) return st;
+  if (h->opt.guard <= 0.0)
+    HIPCHK(h, pngf::launch_band_measure(P.df32, P.dfb, P.df, nd, at<double>(h, L.off_bandout),
+                                        nullptr, h->stream, at<double>(h, L.off_band), wk + 1));
+  h->bits_fresh = false;
+  return PNGF_OK;
+}
+
+// The periodic persistent mixed search with each refresh queued ahead of the
+// host (refresh_ahead): per round, a batch that runs until the search asks
+// for its refresh (k_refresh accepts, a band hit) or ends, the read of its
+// end state, then the refresh; the host waits for the state read only, so
+// it queues the next batch while the refresh runs.  Returns 1 (nothing done)
+// if the grid of the persistent search cannot be resident here.
+int run_mixed_ahead(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_t* n_band) {
+  const int nd = h->pc.n_d;
+  const Layout& Y = h->lay;
+  int32_t* status = at<int32_t>(h, Y.off_status);
+  int32_t* pbar = at<int32_t>(h, Y.off_pbar);
+  uint8_t* bref = at<uint8_t>(h, Y.off_bref);
+  char* stg = h->pin + pngf::kPinStage;
+  const size_t span = Y.off_flag + 4 - Y.off_state;
+  // a batch asks for its refresh at the decision after k_refresh accepts
+  const int nl = (h->opt.k_refresh + 2) & ~1;
+  HIPCHK(h, hipMemcpyAsync(bref, h->P.bits, nd, hipMemcpyDeviceToDevice, h->stream));
+  bool after_refresh = false;   // a refresh is queued before this batch
+  const int64_t max_rounds = 4 * int64_t(h->opt.max_accepts) + 64;
+  for (int64_t round = 0; round < max_rounds; ++round) {
+    size_t tag = size_t(-1);   // the batch's entry in the event pool, if timed
+    {
+      Timer t(h, KID_ACCEPT);
+      const hipError_t e = pngf::launch_mixed_persist(
+          h->P, 0, nl, reinterpret_cast<uint64_t*>(pbar), at<int32_t>(h, Y.off_flag),
+          h->persist_spin, at<double>(h, Y.off_band), after_refresh ? status : nullptr,
+          h->stream);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (h->persist_ok || round > 0) return fail(h, PNGF_EDEVICE, "persistent search launch failed");
+        h->persist_off = true;
+        return 1;
+      }
+      h->persist_ok = true;
+      t.end(nl);
+      if (t.a) tag = h->ev_pool.size() - 1;
+    }
+    HIPCHK(h, hipMemcpyAsync(stg, h->ws + Y.off_state, span, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipEventRecord(h->ev_ahead, h->stream));
+    int st = refresh_ahead(h);
+    if (st) return st;
+    after_refresh = true;
+    HIPCHK(h, hipEventSynchronize(h->ev_ahead));
+    std::memcpy(pinned, stg, sizeof(pngf::DbsState));
+    const int32_t fl = *reinterpret_cast<const int32_t*>(stg + (Y.off_flag - Y.off_state));
+    if (tag != size_t(-1)) {
+      // count only the accepted flips of the batch
+      const int acc = std::max(0, pinned->n_acc - h->nacc_seen);
+      h->ev_pool[tag] = reinterpret_cast<hipEvent_t>(intptr_t(KID_ACCEPT) | (intptr_t(acc) << 8));
+    }
+    h->nacc_seen = pinned->n_acc;
+    if (fl == 2) {
+      // no step ran: the refresh before this batch was singular (or had more
+      // flips than it holds); the one queued behind it started from an
+      // unusable C^-1 too: re-invert from the design
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      HIPCHK(h, hipMemsetAsync(at<int32_t>(h, Y.off_flag), 0, sizeof(int32_t), h->stream));
+      h->reform_c64 = true;
+      st = device_reinvert(h);
+      h->reform_c64 = false;
+      if (st) return st;
+      HIPCHK(h, hipMemcpyAsync(bref, h->P.bits, nd, hipMemcpyDeviceToDevice, h->stream));
+      st = start_segment(h, true);
+      if (st) return st;
+      after_refresh = false;
+      continue;
+    }
+    if (fl) {
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      HIPCHK(h, hipMemsetAsync(pbar, 0, pngf::kPersistBarBytes, h->stream));
+      HIPCHK(h, hipMemsetAsync(at<int32_t>(h, Y.off_flag), 0, sizeof(int32_t), h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      return fail(h, PNGF_ENUMERIC, "a grid barrier of the persistent search timed out");
+    }
+    if (pinned->done) {
+      // the refresh queued behind the last batch brought C^-1 to the final
+      // design (the caller's final refresh starts from there), unless its
+      // update failed: then re-invert
+      int32_t& sth = *reinterpret_cast<int32_t*>(h->pin + 24);
+      sth = 0;
+      h->bits_ref.resize(nd);
+      HIPCHK(h, hipMemcpyAsync(&sth, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipMemcpyAsync(h->bits_ref.data(), bref, nd, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      if (sth) {
+        st = device_reinvert(h);
+        if (st) return st;
+      }
+      return PNGF_OK;
+    }
+    *n_refresh += 1;
+    if (pinned->need_refresh == 2) *n_band += 1;
+  }
+  return fail(h, PNGF_ENUMERIC, "DBS did not terminate");
+}
+
 // Mixed search: complex-FP32 steps in batches; between batches the host
 // re-inverts in FP64 when the device asks (interval, full panel, a band hit),
 // folds the panel into C0^-1 on the matrix cores, or checks the drift.
@@ -1008,6 +1180,25 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
   if (st) return st;
   st = start_segment(h);
   if (st) return st;
+  // a periodic persistent search queues each refresh ahead of the host
+  const bool ahead = !h->persist_off && !h->ranked && F == 1 && nd <= 2048 &&
+                     h->P.kcap <= pngf::kPersistSlotsHost &&
+                     !(h->opt.flags & PNGF_FLAG_STEP_LAUNCHES) && h->opt.k_refresh > 0 &&
+                     h->opt.k_refresh <= pngf::kAheadMaxK &&
+                     (h->opt.k_fold == 0 || h->opt.k_fold >= h->opt.k_refresh);
+  if (ahead) {
+    st = run_mixed_ahead(h, pinned, n_refresh, n_band);
+    if (st != 1) {
+      if (st) return st;
+      st = fp64_refresh(h);
+      if (st) return st;
+      HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
+                               h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      return PNGF_OK;
+    }
+    // the persistent grid cannot be resident: one launch per step below
+  }
   const int64_t max_rounds = 4 * int64_t(h->opt.max_accepts) + 64;
   int64_t t = 0;                 // step index within the segment
   int64_t since = 0, kpan = 0;   // host view of n_since / kpanel
@@ -1514,6 +1705,7 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   }
   HIPCHK(h, hipMemsetAsync(at<int32_t>(h, L.off_flag), 0, sizeof(int32_t), h->stream));
   if (!h->ev_pin) HIPCHK(h, hipEventCreateWithFlags(&h->ev_pin, hipEventDisableTiming));
+  if (!h->ev_ahead) HIPCHK(h, hipEventCreateWithFlags(&h->ev_ahead, hipEventDisableTiming));
   HIPCHK(h, hipEventRecord(h->ev_pin, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->bound = true;
@@ -1853,6 +2045,7 @@ int pngf_destroy(pngf_handle* h) {
   release_streams(h);
   if (h->pin) (void)hipHostFree(h->pin);
   if (h->ev_pin) (void)hipEventDestroy(h->ev_pin);
+  if (h->ev_ahead) (void)hipEventDestroy(h->ev_ahead);
   delete h;
   return PNGF_OK;
 }
