@@ -246,14 +246,6 @@ __global__ __launch_bounds__(256) void k_zgemm_reduce(int M, int N, int nz, cons
   *c = (beta.re == 0.0 && beta.im == 0.0) ? av : zfma(beta, *c, av);
 }
 
-// dst[a][:] = src[rows[a]][:] for a < k (n columns).
-__global__ __launch_bounds__(256) void k_gather_rows(const z64* src, int lds, const int32_t* rows,
-                                                     int n, z64* dst, int ldd) {
-  const int a = blockIdx.y;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j < n) dst[size_t(a) * ldd + j] = src[size_t(rows[a]) * lds + j];
-}
-
 // P[:, c] *= s_c for the N_d x k panel P (s_c = k0^2 delta_c), then
 // Cap[a][c] = delta_ac - P[F_a][c].
 __global__ __launch_bounds__(256) void k_wood_scale(z64* P, int ldp, int nd, int k,
@@ -473,7 +465,10 @@ hipError_t launch_zgemm_ix(int M, int N, int K, const z64* A, int lda, const z64
   kchunk = (kchunk + kGemmBK - 1) / kGemmBK * kGemmBK;
   splits = (K + kchunk - 1) / kchunk;
   z64* wk = splits > 1 ? work : nullptr;
-  const bool big = M >= 512 && N >= 512;
+  // 64 x 64 tiles for large products; a rank-k update (short K) is bound by
+  // reading and writing C, and its 32 x 32 tiles (fewer registers, four
+  // times the workgroups) keep more of them in flight
+  const bool big = M >= 512 && N >= 512 && K > 64;
   if (big) {
     dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
     if (transb)
@@ -568,14 +563,6 @@ hipError_t launch_wood_panel(const z64* work, int nz, int nd, int k, const doubl
   const size_t n = size_t(nd) * k + size_t(k) * k;
   hipLaunchKernelGGL(k_wood_panel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, work, nz, nd,
                      k, sc, P, ldp, F, Cap, status, kdev);
-  return hipGetLastError();
-}
-
-hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int k, int n, z64* dst,
-                              int ldd, hipStream_t s) {
-  if (k <= 0 || n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_rows, dim3((n + 255) / 256, k), dim3(256), 0, s, src, lds, rows, n,
-                     dst, ldd);
   return hipGetLastError();
 }
 

@@ -119,15 +119,18 @@ __global__ __launch_bounds__(256) void k_band_measure(const double* df32, const 
 //  * wk[0] = their count (above kpad the capacitance kernel reports it),
 //    wk[1] = 1 when the scores are FP32 results to be measured (the state is
 //    not exact).
-__global__ __launch_bounds__(256) void k_wood_prep(ProbDev P, uint8_t* bref, int kpad,
-                                                   int32_t* dF, double* dS, int32_t* wk) {
-  __shared__ int wcnt[4];
+constexpr int kPrepThreads = 1024;
+
+__global__ __launch_bounds__(kPrepThreads) void k_wood_prep(ProbDev P, uint8_t* bref, int kpad,
+                                                            int32_t* dF, double* dS, int32_t* wk) {
+  constexpr int kW = kPrepThreads / 64;
+  __shared__ int wcnt[kW];
   __shared__ int base;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   DbsState* st = P.st;
   const int odd = st->flips & 1;
   if (odd) {
-    for (int i = tid; i < P.nd; i += 256) {
+    for (int i = tid; i < P.nd; i += kPrepThreads) {
       for (int f = 0; f < P.nfreq; ++f) {
         P.E[f][i] = P.EB[f][i];
         P.Rp[f][i] = P.RpB[f][i];
@@ -138,7 +141,7 @@ __global__ __launch_bounds__(256) void k_wood_prep(ProbDev P, uint8_t* bref, int
   }
   if (tid == 0) base = 0;
   __syncthreads();
-  for (int i0 = 0; i0 < P.nd; i0 += 256) {
+  for (int i0 = 0; i0 < P.nd; i0 += kPrepThreads) {
     const int i = i0 + tid;
     const uint8_t b = i < P.nd ? P.bits[i] : 0;   // this thread copied bits[i]
     const bool d = i < P.nd && b != bref[i];
@@ -156,11 +159,15 @@ __global__ __launch_bounds__(256) void k_wood_prep(ProbDev P, uint8_t* bref, int
       for (int f = 0; f < P.nfreq; ++f) dS[size_t(f) * kpad + c] = P.k0sq[f] * delta;
     }
     __syncthreads();
-    if (tid == 0) base += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (tid == 0) {
+      int t = 0;
+      for (int v = 0; v < kW; ++v) t += wcnt[v];
+      base += t;
+    }
     __syncthreads();
   }
   const int k = base;
-  for (int c = k + tid; c < kpad; c += 256) {
+  for (int c = k + tid; c < kpad; c += kPrepThreads) {
     dF[c] = 0;
     for (int f = 0; f < P.nfreq; ++f) dS[size_t(f) * kpad + c] = 0.0;
   }
@@ -194,7 +201,7 @@ hipError_t launch_band_measure(const double* df32, const double* bnd32, const do
 
 hipError_t launch_wood_prep(const ProbDev& P, uint8_t* bref, int kpad, int32_t* dF,
                             double* dS, int32_t* wk, hipStream_t s) {
-  hipLaunchKernelGGL(k_wood_prep, dim3(1), dim3(256), 0, s, P, bref, kpad, dF, dS, wk);
+  hipLaunchKernelGGL(k_wood_prep, dim3(1), dim3(kPrepThreads), 0, s, P, bref, kpad, dF, dS, wk);
   return hipGetLastError();
 }
 

@@ -37,8 +37,6 @@ hipError_t launch_rform_step(const ProbDev& P, int npl, int step, hipStream_t s)
 hipError_t launch_rform_score(const ProbDev& P, hipStream_t s);
 hipError_t launch_rform_ut(const ProbDev& P, int f, int kp, z64* Ut, hipStream_t s);
 hipError_t launch_rform_t0_init(const ProbDev& P, int f, hipStream_t s);
-hipError_t launch_gather_rows(const z64* src, int lds, const int32_t* rows, int k, int n, z64* dst,
-                              int ldd, hipStream_t s);
 hipError_t launch_wood_cap(z64* P, int ldp, int nd, const int32_t* F, int k, const double* sc,
                            z64* Cap, int32_t* status, hipStream_t s,
                            const int32_t* kdev = nullptr);
@@ -133,7 +131,7 @@ struct Layout {
       off_piv[pngf::kMaxFreq], off_invp[pngf::kMaxFreq], off_used[pngf::kMaxFreq],
       off_np[pngf::kMaxFreq];
   size_t off_status, off_pbar, off_flag, off_band, off_u[pngf::kMaxFreq], off_r[pngf::kMaxFreq];
-  size_t off_wP[pngf::kMaxFreq], off_wQ[pngf::kMaxFreq], off_wW[pngf::kMaxFreq],
+  size_t off_wP[pngf::kMaxFreq], off_wW[pngf::kMaxFreq],
       off_wCap[pngf::kMaxFreq], off_wWork[pngf::kMaxFreq];
   size_t off_wF, off_wS, off_tiles, off_tpart;
   size_t off_T[pngf::kMaxFreq], off_Up[pngf::kMaxFreq], off_ralph[pngf::kMaxFreq], off_rpm, off_Ut;
@@ -280,7 +278,6 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     const size_t kw = size_t(pngf::kWoodMax);
     for (int f = 0; f < F; ++f) {
       L.off_wP[f] = take(size_t(nd) * kw * sizeof(z64));
-      L.off_wQ[f] = take(kw * nd * sizeof(z64));
       L.off_wW[f] = take(kw * nd * sizeof(z64));
       L.off_wCap[f] = take(kw * kw * sizeof(z64));
       L.off_wWork[f] = take(size_t(pngf::kWoodSplits) * nd * kw * sizeof(z64));
@@ -586,7 +583,6 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
     for (int f = 0; f < F; ++f) {
       const hipStream_t sf = fstream(h, f);
       z64* wP = at<z64>(h, L.off_wP[f]);
-      z64* wQ = at<z64>(h, L.off_wQ[f]);
       z64* wW = at<z64>(h, L.off_wW[f]);
       z64* cap = at<z64>(h, L.off_wCap[f]);
       // P = C_ref^-1 G[:,F] diag(k0^2 delta_F)   (G[:,F] = G[F,:]^T): split-K
@@ -608,10 +604,10 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
         HIPCHK(h, hipMemsetAsync(status, 1, sizeof(int32_t), sf));
         --h->force_singular;
       }
-      // W = Cap^-1 C_ref^-1[F,:];  C^-1 = C_ref^-1 + P W
-      HIPCHK(h, pngf::launch_gather_rows(P.Cinv[f], ld, dF, k, nd, wQ, nd, sf));
-      HIPCHK(h, pngf::launch_zgemm(k, nd, k, cap, k, nullptr, wQ, nd, false, nullptr, wW, nd, one,
-                                   zero, 1, nullptr, sf));
+      // W = Cap^-1 C_ref^-1[F,:] (the rows F gathered by the GEMM);
+      // C^-1 = C_ref^-1 + P W
+      HIPCHK(h, pngf::launch_zgemm(k, nd, k, cap, k, nullptr, P.Cinv[f], ld, false, dF, wW, nd,
+                                   one, zero, 1, nullptr, sf));
       HIPCHK(h, pngf::launch_zgemm(nd, nd, k, wP, k, nullptr, wW, nd, false, nullptr, P.Cinv[f],
                                    ld, one, one, 1, nullptr, sf));
     }
@@ -1022,7 +1018,6 @@ int refresh_ahead(pngf_handle* h) {
   {
     Timer t(h, KID_WOOD);
     z64* wP = at<z64>(h, L.off_wP[0]);
-    z64* wQ = at<z64>(h, L.off_wQ[0]);
     z64* wW = at<z64>(h, L.off_wW[0]);
     z64* cap = at<z64>(h, L.off_wCap[0]);
     z64* work = at<z64>(h, L.off_wWork[0]);
@@ -1040,9 +1035,8 @@ int refresh_ahead(pngf_handle* h) {
       HIPCHK(h, hipMemsetAsync(status, 1, sizeof(int32_t), h->stream));
       --h->force_singular;
     }
-    HIPCHK(h, pngf::launch_gather_rows(P.Cinv[0], ld, dF, kpad, nd, wQ, nd, h->stream));
-    HIPCHK(h, pngf::launch_zgemm(kpad, nd, kpad, cap, kpad, nullptr, wQ, nd, false, nullptr, wW,
-                                 nd, one, zero, 1, nullptr, h->stream));
+    HIPCHK(h, pngf::launch_zgemm(kpad, nd, kpad, cap, kpad, nullptr, P.Cinv[0], ld, false, dF,
+                                 wW, nd, one, zero, 1, nullptr, h->stream));
     HIPCHK(h, pngf::launch_zgemm(nd, nd, kpad, wP, kpad, nullptr, wW, nd, false, nullptr,
                                  P.Cinv[0], ld, one, one, 1, nullptr, h->stream));
     t.end(1);
