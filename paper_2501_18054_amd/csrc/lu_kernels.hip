@@ -468,6 +468,11 @@ __global__ __launch_bounds__(256) void k_scatter_inverse(const z64* M, z64* Cinv
 // d_j = (bits[j] ? ds : 0) when bits != nullptr, else 1.  One workgroup per
 // row; y may alias w (row i reads w[i] before writing y[i]).
 // A32 (nullable): also writes the complex-FP32 copy of the row it reads.
+// Each thread takes j = tid, tid + 256, ... in order, kGemvUnroll at a time:
+// their loads are issued together (clamped in-range addresses, results past
+// the row end unused), so a row costs a few memory round trips.
+constexpr int kGemvUnroll = 4;
+
 __global__ __launch_bounds__(kRowThreads) void k_gemv(const z64* A, int ld, int n, const z64* v,
                                                       const uint8_t* bits, double ds, z64 alpha,
                                                       z64 beta, const z64* w, double gamma,
@@ -476,12 +481,27 @@ __global__ __launch_bounds__(kRowThreads) void k_gemv(const z64* A, int ld, int 
   const int i = blockIdx.x;
   const z64* a = A + size_t(i) * ld;
   z64 acc{0.0, 0.0};
-  for (int j = threadIdx.x; j < n; j += kRowThreads) {
-    z64 vj = v[j];
-    if (bits) vj = zscale(vj, bits[j] ? ds : 0.0);
-    const z64 aij = a[j];
-    if (A32) A32[size_t(i) * ld + j] = z32{float(aij.re), float(aij.im)};
-    acc = zfma(aij, vj, acc);
+  for (int j0 = threadIdx.x; j0 < n; j0 += kGemvUnroll * kRowThreads) {
+    z64 aj[kGemvUnroll], vj[kGemvUnroll];
+    uint32_t bj[kGemvUnroll];
+    if (bits) {
+#pragma unroll
+      for (int u = 0; u < kGemvUnroll; ++u) bj[u] = bits[min(j0 + u * kRowThreads, n - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u) {
+      const int j = min(j0 + u * kRowThreads, n - 1);
+      aj[u] = a[j];
+      vj[u] = v[j];
+    }
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u) {
+      const int j = j0 + u * kRowThreads;
+      if (j < n) {
+        if (A32) A32[size_t(i) * ld + j] = z32{float(aj[u].re), float(aj[u].im)};
+        acc = zfma(aj[u], bits ? zscale(vj[u], bj[u] ? ds : 0.0) : vj[u], acc);
+      }
+    }
   }
   const z64 s = block_zsum(acc, red);
   if (threadIdx.x == 0) {
@@ -502,11 +522,28 @@ __global__ __launch_bounds__(kRowThreads) void k_gemv2(const z64* A, int ld, int
   const int i = blockIdx.x;
   const z64* a = A + size_t(i) * ld;
   z64 acc1{0.0, 0.0}, acc2{0.0, 0.0};
-  for (int j = threadIdx.x; j < n; j += kRowThreads) {
-    const double dj = bits ? (bits[j] ? ds : 0.0) : 1.0;
-    const z64 aj = a[j];
-    acc1 = zfma(aj, zscale(o1.v[j], dj), acc1);
-    acc2 = zfma(aj, zscale(o2.v[j], dj), acc2);
+  for (int j0 = threadIdx.x; j0 < n; j0 += kGemvUnroll * kRowThreads) {
+    z64 aj[kGemvUnroll], v1[kGemvUnroll], v2[kGemvUnroll];
+    uint32_t bj[kGemvUnroll];
+    if (bits) {
+#pragma unroll
+      for (int u = 0; u < kGemvUnroll; ++u) bj[u] = bits[min(j0 + u * kRowThreads, n - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u) {
+      const int j = min(j0 + u * kRowThreads, n - 1);
+      aj[u] = a[j];
+      v1[u] = o1.v[j];
+      v2[u] = o2.v[j];
+    }
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u) {
+      if (j0 + u * kRowThreads < n) {
+        const double dj = bits ? (bj[u] ? ds : 0.0) : 1.0;
+        acc1 = zfma(aj[u], zscale(v1[u], dj), acc1);
+        acc2 = zfma(aj[u], zscale(v2[u], dj), acc2);
+      }
+    }
   }
   const z64 s1 = block_zsum(acc1, red);
   const z64 s2 = block_zsum(acc2, red);
