@@ -468,15 +468,20 @@ pngf::NpWork np_work(pngf_handle* h, int f) {
 
 // Re-form C^-1 (FP64, on the device) from G and the device design bits for
 // every frequency, then E, R', x and f (reform_fields).
-int device_reinvert(pngf_handle* h) {
+// host_bits: h->bits already holds the device design (no read back).  The
+// fields are re-formed before the inversion's status is read (one wait for
+// both; the rare rejected result is re-formed again after the pivot search).
+int device_reinvert(pngf_handle* h, bool host_bits = false) {
   const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
   const Layout& L = h->lay;
   pngf::ProbDev& P = h->P;
   int32_t* status = at<int32_t>(h, L.off_status);
   HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
   // S (pixels at eps_hi) and Z from the device design bits
-  HIPCHK(h, hipMemcpyAsync(h->bits.data(), P.bits, nd, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (!host_bits) {
+    HIPCHK(h, hipMemcpyAsync(h->bits.data(), P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
   std::vector<int32_t> sidx, zidx, pos(nd, -1), rowmap(nd);
   for (int i = 0; i < nd; ++i) {
     if (h->bits[i]) { pos[i] = int32_t(sidx.size()); sidx.push_back(i); }
@@ -522,6 +527,8 @@ int device_reinvert(pngf_handle* h) {
       if (st) return st;
       t.end(F);
     }
+    int st = reform_fields(h);
+    if (st) return st;
     int32_t st_host = 0;
     HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -530,9 +537,6 @@ int device_reinvert(pngf_handle* h) {
     ++(pivoted ? h->n_inv_piv : h->n_inv_np);
     break;
   }
-  int st = reform_fields(h);
-  if (st) return st;
-  HIPCHK(h, hipStreamSynchronize(h->stream));
   if (h->opt.flags & (PNGF_FLAG_TIMING | PNGF_FLAG_TIMING_STEPS)) collect_times(h);
   h->bits_ref = h->bits;
   h->cinv_stale = false;
@@ -1157,32 +1161,28 @@ int run_mixed_ahead(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, 
 // folds the panel into C0^-1 on the matrix cores, or checks the drift.
 int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_t* n_band) {
   const int nd = h->pc.n_d, F = int(h->pc.freq.size());
-  int st0 = capture_ref_bits(h);
-  if (st0) return st0;
+  // the state's mixed bookkeeping was reset by the search prologue
   for (int f = 0; f < F; ++f)
     HIPCHK(h, pngf::launch_to_c64(h->P.Cinv[f], h->P.C0[f], nd, h->ld, h->stream));
-  pngf::DbsState s;
-  int st = read_state(h, &s);
+  int st = start_segment(h);
   if (st) return st;
-  s.kpanel = 0;
-  s.n_since = 0;
-  s.exact = 1;
-  s.need_refresh = 0;
-  s.n_band = 0;
-  s.flips = 0;
-  st = write_state(h, &s);
-  if (st) return st;
-  st = start_segment(h);
-  if (st) return st;
-  // a periodic persistent search queues each refresh ahead of the host
+  // a periodic persistent search queues each refresh ahead of the host (the
+  // design C^-1 holds is kept on the device); otherwise the host keeps it
   const bool ahead = !h->persist_off && !h->ranked && F == 1 && nd <= 2048 &&
                      h->P.kcap <= pngf::kPersistSlotsHost &&
                      !(h->opt.flags & PNGF_FLAG_STEP_LAUNCHES) && h->opt.k_refresh > 0 &&
                      h->opt.k_refresh <= pngf::kAheadMaxK &&
                      (h->opt.k_fold == 0 || h->opt.k_fold >= h->opt.k_refresh);
+  if (!ahead) {
+    st = capture_ref_bits(h);
+    if (st) return st;
+  }
   if (ahead) {
     st = run_mixed_ahead(h, pinned, n_refresh, n_band);
-    if (st != 1) {
+    if (st == 1) {
+      st = capture_ref_bits(h);
+      if (st) return st;
+    } else {
       if (st) return st;
       st = fp64_refresh(h);
       if (st) return st;
@@ -1447,6 +1447,10 @@ int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double*
   s.eta = h->opt.eta;
   s.need_refresh = 0;
   s.flips = 0;
+  s.kpanel = 0;   // the mixed search's panel and refresh bookkeeping
+  s.n_since = 0;
+  s.exact = 1;
+  s.n_band = 0;
   // every search starts from the initial error band (it is recalibrated at
   // each FP64 re-inversion), so repeated runs are identical
   h->P.band = (h->opt.guard > 0.0) ? h->opt.guard : 1e-3;
@@ -1456,7 +1460,12 @@ int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double*
   h->nacc_seen = 0;
   h->persist_ok = false;
   h->persist_aborted = false;
-  return write_state(h, &s);
+  // stream-ordered, from the pinned staging area (read back into only after
+  // this copy, on the same stream): no wait
+  auto* ps = reinterpret_cast<pngf::DbsState*>(h->pin + pngf::kPinStage);
+  *ps = s;
+  HIPCHK(h, hipMemcpyAsync(h->P.st, ps, sizeof(s), hipMemcpyHostToDevice, h->stream));
+  return PNGF_OK;
 }
 
 // Copy the accept log and fill the result summary.
@@ -1722,7 +1731,7 @@ int pngf_set_design(pngf_handle* h, const uint8_t* bits) {
   st = write_state(h, &s);
   if (st) return st;
   h->have_design = false;
-  st = device_reinvert(h);
+  st = device_reinvert(h, true);
   if (st) return st;
   h->have_design = true;
   return PNGF_OK;
