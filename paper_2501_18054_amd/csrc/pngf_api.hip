@@ -87,6 +87,10 @@ constexpr int kPersistBarWords = 2 * 16 * 18;   // grid-barrier words (as int32)
 constexpr size_t kPersistBarBytes = (kPersistBarWords + 32) * sizeof(int32_t);
 constexpr size_t kPinBytes = 16384;          // pinned scratch of small transfers
 constexpr size_t kPinUpload = 256;           // offset of the Woodbury upload in it
+constexpr size_t kPinState = 8192;           // offset of a search's state read
+static_assert(kPinUpload + 256 + kMaxFreq * 64 * sizeof(double) <= kPinState &&
+                  kPinState + sizeof(DbsState) <= kPinBytes,
+              "pinned scratch regions overlap");
 constexpr size_t kPinStage = kPinBytes;      // then the batch-end read (state .. bits)
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
@@ -1064,8 +1068,9 @@ int refresh_ahead(pngf_handle* h) {
 // host (refresh_ahead): per round, a batch that runs until the search asks
 // for its refresh (k_refresh accepts, a band hit) or ends, the read of its
 // end state, then the refresh; the host waits for the state read only, so
-// it queues the next batch while the refresh runs.  Returns 1 (nothing done)
-// if the grid of the persistent search cannot be resident here.
+// it queues the next batch while the refresh runs.  On return `pinned`
+// holds the final state, its FP64 fields re-formed.  Returns 1 (nothing
+// done) if the grid of the persistent search cannot be resident here.
 int run_mixed_ahead(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_t* n_band) {
   const int nd = h->pc.n_d;
   const Layout& Y = h->lay;
@@ -1135,18 +1140,25 @@ int run_mixed_ahead(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, 
       return fail(h, PNGF_ENUMERIC, "a grid barrier of the persistent search timed out");
     }
     if (pinned->done) {
-      // the refresh queued behind the last batch brought C^-1 to the final
-      // design (the caller's final refresh starts from there), unless its
-      // update failed: then re-invert
+      // the refresh queued behind the last batch re-formed the FP64 state of
+      // the final design (what the final refresh of a search computes), unless
+      // its update failed: then re-invert.  The final state comes with the
+      // same wait.
       int32_t& sth = *reinterpret_cast<int32_t*>(h->pin + 24);
       sth = 0;
-      h->bits_ref.resize(nd);
       HIPCHK(h, hipMemcpyAsync(&sth, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(h, hipMemcpyAsync(h->bits_ref.data(), bref, nd, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipMemcpyAsync(stg, bref, nd, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
+                               h->stream));
       HIPCHK(h, hipStreamSynchronize(h->stream));
+      h->bits_ref.assign(reinterpret_cast<const uint8_t*>(stg),
+                         reinterpret_cast<const uint8_t*>(stg) + nd);
       if (sth) {
         st = device_reinvert(h);
         if (st) return st;
+        HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState),
+                                 hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
       }
       return PNGF_OK;
     }
@@ -1183,13 +1195,7 @@ int run_mixed(pngf_handle* h, pngf::DbsState* pinned, int64_t* n_refresh, int64_
       st = capture_ref_bits(h);
       if (st) return st;
     } else {
-      if (st) return st;
-      st = fp64_refresh(h);
-      if (st) return st;
-      HIPCHK(h, hipMemcpyAsync(pinned, h->P.st, sizeof(pngf::DbsState), hipMemcpyDeviceToHost,
-                               h->stream));
-      HIPCHK(h, hipStreamSynchronize(h->stream));
-      return PNGF_OK;
+      return st;
     }
     // the persistent grid cannot be resident: one launch per step below
   }
@@ -1473,12 +1479,23 @@ int dbs_epilogue(pngf_handle* h, const pngf::DbsState& fin, double f0, int64_t n
                  int64_t n_band, int32_t* accepted, double* f_trace, pngf_dbs_result* res) {
   const int nd = h->pc.n_d;
   const int na = fin.n_acc;
+  // logs and design through the pinned staging area: three copies, one wait
+  const size_t lpb = (size_t(na) * sizeof(int32_t) + 7) & ~size_t(7);
+  char* stg = h->pin + pngf::kPinStage;
+  if (lpb + size_t(na) * sizeof(double) + nd > h->pin_bytes - pngf::kPinStage)
+    return fail(h, PNGF_EINVAL, "more accepts than the handle's max_accepts");
+  auto* lp = reinterpret_cast<int32_t*>(stg);
+  auto* lf = reinterpret_cast<double*>(stg + lpb);
+  auto* lb = reinterpret_cast<uint8_t*>(lf + na);
   if (accepted && na > 0)
-    HIPCHK(h, hipMemcpyAsync(accepted, h->P.log_pix, na * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(lp, h->P.log_pix, na * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   if (f_trace && na > 0)
-    HIPCHK(h, hipMemcpyAsync(f_trace, h->P.log_f, na * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipMemcpyAsync(h->bits.data(), h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(lf, h->P.log_f, na * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(lb, h->P.bits, nd, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (accepted && na > 0) std::memcpy(accepted, lp, na * sizeof(int32_t));
+  if (f_trace && na > 0) std::memcpy(f_trace, lf, na * sizeof(double));
+  std::memcpy(h->bits.data(), lb, nd);
   if (h->opt.flags & (PNGF_FLAG_TIMING | PNGF_FLAG_TIMING_STEPS)) collect_times(h);
   if (!std::isfinite(fin.f)) return fail(h, PNGF_ENUMERIC, "objective is not finite");
   if (res) {
@@ -1696,7 +1713,11 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   // the persistent search's barrier words start at generation 0
   HIPCHK(h, hipMemsetAsync(at<int32_t>(h, L.off_pbar), 0, pngf::kPersistBarBytes, h->stream));
   {
-    const size_t need = pngf::kPinStage + (L.off_bitsB + nd - L.off_state);
+    // the staging area holds a batch-end read (state .. design buffers) or,
+    // at a search's end, its logs and design
+    const size_t need = pngf::kPinStage +
+                        std::max(L.off_bitsB + nd - L.off_state,
+                                 12 * size_t(std::max(1, o->max_accepts)) + size_t(nd) + 16);
     if (h->pin && h->pin_bytes < need) {
       (void)hipHostFree(h->pin);
       h->pin = nullptr;
@@ -1860,14 +1881,13 @@ int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t
   double f0 = 0.0;
   int st = dbs_prologue(h, perms, n_sweeps, &f0);
   if (st) return st;
-  pngf::DbsState* pinned = nullptr;
-  HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(pngf::DbsState)));
+  // the state reads of the search land in the handle's pinned scratch
+  auto* pinned = reinterpret_cast<pngf::DbsState*>(h->pin + pngf::kPinState);
   int64_t n_refresh = 0, n_band = 0;
   int rc = (h->opt.precision == PNGF_MIXED)   ? run_mixed(h, pinned, &n_refresh, &n_band)
            : (h->opt.precision == PNGF_RFORM) ? run_rform(h, pinned)
                                               : run_plain(h, pinned);
   pngf::DbsState fin = *pinned;
-  hipHostFree(pinned);
   if (rc) return rc;
   return dbs_epilogue(h, fin, f0, n_refresh, n_band, accepted, f_trace, res);
 }
@@ -2092,14 +2112,12 @@ int ranked_search(pngf_handle* h, pngf_model* m, int H, int W, int32_t max_accep
   h->rank_w = W;
   const int32_t max_acc = h->P.max_acc;
   h->P.max_acc = max_accepts;
-  pngf::DbsState* pinned = nullptr;
-  HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(pngf::DbsState)));
+  auto* pinned = reinterpret_cast<pngf::DbsState*>(h->pin + pngf::kPinState);
   int64_t n_refresh = 0, n_band = 0;
   int rc = (h->opt.precision == PNGF_MIXED)   ? run_mixed(h, pinned, &n_refresh, &n_band)
            : (h->opt.precision == PNGF_RFORM) ? run_rform(h, pinned)
                                               : run_plain(h, pinned);
   pngf::DbsState fin = *pinned;
-  (void)hipHostFree(pinned);
   h->ranked = false;
   h->rank_model = nullptr;
   h->P.max_acc = max_acc;
