@@ -2288,7 +2288,7 @@ struct pngf_batch {
   // captured 6-step graph for the launch shape (any active set)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int g_total = -1, g_grid = -1, g_nprob = -1;
+  int g_total = -1, g_grid = -1;
   // autotuner record
   std::vector<int32_t> tune_grid;
   std::vector<double> tune_ms;
@@ -2324,7 +2324,7 @@ void drop_graph(pngf_batch* b) {
   if (b->graph) hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
-  b->g_total = b->g_grid = b->g_nprob = -1;
+  b->g_total = b->g_grid = -1;
 }
 
 void release_refresh_streams(pngf_batch* b) {
@@ -2463,7 +2463,6 @@ int batch_prepare(pngf_batch* b, const std::vector<int>& active, int grid) {
   BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   b->g_total = b->total_all;
   b->g_grid = grid;
-  b->g_nprob = int(b->hs.size());
   return PNGF_OK;
 }
 
@@ -2606,8 +2605,17 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
     h->P.st = &b->d_states[2 * p];
     h->P.stB = &b->d_states[2 * p + 1];
   }
+  // descriptors in decreasing order of a step's work (N_d^2 x frequencies),
+  // so that the largest problems' work items are dispatched first and the
+  // small ones fill in behind them
+  auto by_work = [&](int p, int q) {
+    const double wp = double(b->hs[p]->pc.n_d) * b->hs[p]->pc.n_d * b->hs[p]->pc.freq.size();
+    const double wq = double(b->hs[q]->pc.n_d) * b->hs[q]->pc.n_d * b->hs[q]->pc.freq.size();
+    return wp != wq ? wp > wq : p < q;
+  };
   std::vector<int> active(n);
   for (int p = 0; p < n; ++p) active[p] = p;
+  std::sort(active.begin(), active.end(), by_work);
   pngf::DbsState* host_states = nullptr;
   BHIPCHK(b, hipHostMalloc(reinterpret_cast<void**>(&host_states), 2 * n * sizeof(pngf::DbsState)));
   size_t sum_nd = 0;
@@ -2731,9 +2739,9 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
     if (rc) break;
     rc = batch_refresh_fetch(b, toissue, pbits);
     if (rc) break;
-    // descriptors keep the problems' order (they are re-uploaded every round)
+    // descriptors keep their order (they are re-uploaded every round)
     next.insert(next.end(), back.begin(), back.end());
-    std::sort(next.begin(), next.end());
+    std::sort(next.begin(), next.end(), by_work);
     active.swap(next);
   }
   if (rc) {
