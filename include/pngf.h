@@ -342,9 +342,14 @@ int pngf_destroy(pngf_handle *h);
  * Computational efficiency), so a batch advances every problem by one DBS
  * step per launch: one workgroup per row of every active problem (or a
  * persistent grid striding over them), captured as a hipGraph of 6 steps
- * that is replayed until every problem has converged.  FP64 re-inversions
- * (MIXED) are done per problem between replays.  Results equal the solo
- * pngf_dbs_run of each problem. */
+ * that is replayed until every problem has converged.  FP64 refreshes
+ * (MIXED) are done per problem between replays: a problem that asks for one
+ * skips a round while its refresh runs on one of four internal streams
+ * (created by pngf_batch_bind, default priority), beside the other problems'
+ * steps; all of their work is joined to the batch stream before
+ * pngf_batch_dbs_run returns.  Results equal the solo pngf_dbs_run of each
+ * problem (same accepted sequences; MIXED objective traces to FP32 rounding,
+ * final objectives to FP64 rounding). */
 typedef struct pngf_batch pngf_batch;
 
 /* handles[n]: distinct, each bound (same precision, same stream) before
@@ -358,7 +363,8 @@ int pngf_batch_workspace_bytes(pngf_batch *b, size_t *bytes);
 
 /* Bind caller-owned device memory (256-byte aligned) and the stream every
  * handle is bound to; it must not be the legacy default stream (the steps are
- * captured as a hipGraph).  PNGF_EINVAL otherwise. */
+ * captured as a hipGraph).  PNGF_EINVAL otherwise.  The first bind creates
+ * the batch's refresh streams (released by pngf_batch_destroy). */
 int pngf_batch_bind(pngf_batch *b, void *dev_ws, size_t bytes, void *hip_stream);
 
 /* Launch shape: 0 = one workgroup per row, g > 0 = persistent grid of g
