@@ -43,7 +43,7 @@ def test_mixed_config0_identical():
     h.close()
 
 
-@pytest.mark.parametrize("k_refresh,k_fold", [(32, 0), (0, 0), (0, 8), (64, 5)])
+@pytest.mark.parametrize("k_refresh,k_fold", [(32, 0), (12, 0), (0, 0), (0, 8), (64, 5)])
 def test_mixed_config1_identical(k_refresh, k_fold):
     g = golden(1)
     if g is None:
@@ -93,11 +93,14 @@ def test_mixed_then_plain_calls():
     h.close()
 
 
-@pytest.mark.parametrize("wl,k_refresh,k_fold", [("config1", 32, 0), ("config1", 0, 8),
-                                                   ("config0", 32, 0), ("metal", 32, 0)])
+@pytest.mark.parametrize("wl,k_refresh,k_fold", [("config1", 32, 0), ("config1", 12, 0),
+                                                   ("config1", 0, 8), ("config0", 32, 0),
+                                                   ("metal", 32, 0)])
 def test_persistent_batches_equal_step_launches(wl, k_refresh, k_fold):
     """One launch per batch (rows of C0^-1 held in registers, grid barriers
-    between steps) against one kernel per step, on one handle: the same
+    between steps; with a periodic refresh, each refresh queued behind its
+    batch before the host reads the batch's state, its flip list padded to
+    k_refresh columns) against one kernel per step, on one handle: the same
     arithmetic, so bit-identical searches, and a second persistent search
     identical to the first."""
     p = getattr(workloads, wl)()
