@@ -88,6 +88,7 @@ constexpr size_t kPersistBarBytes = (kPersistBarWords + 32) * sizeof(int32_t);
 constexpr size_t kPinBytes = 16384;          // pinned scratch of small transfers
 constexpr size_t kPinUpload = 256;           // offset of the Woodbury upload in it
 constexpr size_t kPinState = 8192;           // offset of a search's state read
+constexpr size_t kStageOrders = 1024;        // visiting orders in the staging area, after the state
 static_assert(kPinUpload + 256 + kMaxFreq * 64 * sizeof(double) <= kPinState &&
                   kPinState + sizeof(DbsState) <= kPinBytes,
               "pinned scratch regions overlap");
@@ -1432,10 +1433,24 @@ int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double*
         return fail(h, PNGF_EINVAL, "perms must hold permutations of the pixel ids");
       rank[size_t(s) * nd + m] = q;
     }
-  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.perm), perms, rank.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.rank), rank.data(), rank.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, h->stream));
+  // the visiting orders and their ranks go up from the pinned staging area
+  // when they fit behind the state (read back into only after these copies,
+  // on the same stream), else from the caller's memory
+  const size_t pb = rank.size() * sizeof(int32_t);
+  char* stg = h->pin + pngf::kPinStage;
+  const bool staged = pngf::kStageOrders + 2 * pb <= h->pin_bytes - pngf::kPinStage;
+  const void* src_p = perms;
+  const void* src_r = rank.data();
+  if (staged) {
+    std::memcpy(stg + pngf::kStageOrders, perms, pb);
+    std::memcpy(stg + pngf::kStageOrders + pb, rank.data(), pb);
+    src_p = stg + pngf::kStageOrders;
+    src_r = stg + pngf::kStageOrders + pb;
+  }
+  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.perm), src_p, pb, hipMemcpyHostToDevice,
+                           h->stream));
+  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.rank), src_r, pb, hipMemcpyHostToDevice,
+                           h->stream));
   pngf::DbsState s;
   st = read_state(h, &s);
   if (st) return st;
@@ -1468,6 +1483,7 @@ int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double*
   h->persist_aborted = false;
   // stream-ordered, from the pinned staging area (read back into only after
   // this copy, on the same stream): no wait
+  static_assert(sizeof(pngf::DbsState) <= pngf::kStageOrders, "state overlaps the orders");
   auto* ps = reinterpret_cast<pngf::DbsState*>(h->pin + pngf::kPinStage);
   *ps = s;
   HIPCHK(h, hipMemcpyAsync(h->P.st, ps, sizeof(s), hipMemcpyHostToDevice, h->stream));
