@@ -498,12 +498,30 @@ int device_reinvert(pngf_handle* h, bool host_bits = false) {
   int32_t* d_sidx = at<int32_t>(h, L.off_sidx);
   int32_t* d_zidx = at<int32_t>(h, L.off_zidx);
   int32_t* d_pos = at<int32_t>(h, L.off_pos);
+  // the index lists go up from the pinned staging area when they fit (this
+  // call waits before it returns, so the area is free again then)
+  const int32_t* src_s = sidx.data();
+  const int32_t* src_z = zidx.data();
+  const int32_t* src_p = pos.data();
+  const int32_t* src_m = rowmap.data();
+  if (3 * size_t(nd) * sizeof(int32_t) <= h->pin_bytes - pngf::kPinStage) {
+    auto* stg = reinterpret_cast<int32_t*>(h->pin + pngf::kPinStage);
+    std::copy(sidx.begin(), sidx.end(), stg);
+    std::copy(zidx.begin(), zidx.end(), stg + ns);
+    std::copy(pos.begin(), pos.end(), stg + nd);
+    std::copy(rowmap.begin(), rowmap.end(), stg + 2 * nd);
+    src_s = stg;
+    src_z = stg + ns;
+    src_p = stg + nd;
+    src_m = stg + 2 * nd;
+  }
   if (ns > 0)
-    HIPCHK(h, hipMemcpyAsync(d_sidx, sidx.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(d_sidx, src_s, ns * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   if (nd - ns > 0)
-    HIPCHK(h, hipMemcpyAsync(d_zidx, zidx.data(), (nd - ns) * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, hipMemcpyAsync(d_pos, pos.data(), nd * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, hipMemcpyAsync(at<int32_t>(h, L.off_rowmap), rowmap.data(), nd * sizeof(int32_t),
+    HIPCHK(h, hipMemcpyAsync(d_zidx, src_z, (nd - ns) * sizeof(int32_t), hipMemcpyHostToDevice,
+                             h->stream));
+  HIPCHK(h, hipMemcpyAsync(d_pos, src_p, nd * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(at<int32_t>(h, L.off_rowmap), src_m, nd * sizeof(int32_t),
                            hipMemcpyHostToDevice, h->stream));
   // one inversion per frequency, each on its own stream; first without row
   // exchanges, and with the pivot search where that result fails its check
