@@ -747,13 +747,28 @@ __global__ __launch_bounds__(kRowThreads) void k_np_resid_k(const z64* G, int ld
   const z64* g = G + size_t(sidx[a]) * ld;
   z64 acc{0.0, 0.0};
   double ksum = 0.0, ymax = 0.0;
-  for (int b = t; b < n; b += kRowThreads) {
-    const z64 gv = g[sidx[b]];
-    const z64 kab{(a == b ? 1.0 : 0.0) - k2d * gv.re, -k2d * gv.im};
-    const z64 yb = y[b];
-    acc = zfma(kab, yb, acc);
-    ksum += sqrt(zabs2(kab));
-    ymax = fmax(ymax, sqrt(zabs2(yb)));
+  // the column indices of kGemvUnroll entries first, then their loads
+  // together (clamped in-range, results past the row end unused)
+  for (int b0 = t; b0 < n; b0 += kGemvUnroll * kRowThreads) {
+    int cb[kGemvUnroll];
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u) cb[u] = sidx[min(b0 + u * kRowThreads, n - 1)];
+    z64 gv[kGemvUnroll], yv[kGemvUnroll];
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u) {
+      gv[u] = g[cb[u]];
+      yv[u] = y[min(b0 + u * kRowThreads, n - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u) {
+      const int b = b0 + u * kRowThreads;
+      if (b < n) {
+        const z64 kab{(a == b ? 1.0 : 0.0) - k2d * gv[u].re, -k2d * gv[u].im};
+        acc = zfma(kab, yv[u], acc);
+        ksum += sqrt(zabs2(kab));
+        ymax = fmax(ymax, sqrt(zabs2(yv[u])));
+      }
+    }
   }
   const z64 ky = block_zsum(acc, red);
   const double s = wave_sum(ksum);

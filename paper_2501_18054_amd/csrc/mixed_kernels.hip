@@ -118,11 +118,14 @@ __global__ __launch_bounds__(256) void k_band_measure(const double* df32, const 
 //    once the update is done);
 //  * wk[0] = their count (above kpad the capacitance kernel reports it),
 //    wk[1] = 1 when the scores are FP32 results to be measured (the state is
-//    not exact).
+//    not exact);
+//  * the state and key slots as a segment starts (what k_segment_start does
+//    with a panel reset; nothing before the rescoring reads them).
 constexpr int kPrepThreads = 1024;
 
 __global__ __launch_bounds__(kPrepThreads) void k_wood_prep(ProbDev P, uint8_t* bref, int kpad,
                                                             int32_t* dF, double* dS, int32_t* wk) {
+  uint32_t* keys = P.keys;
   constexpr int kW = kPrepThreads / 64;
   __shared__ int wcnt[kW];
   __shared__ int base;
@@ -171,10 +174,18 @@ __global__ __launch_bounds__(kPrepThreads) void k_wood_prep(ProbDev P, uint8_t* 
     dF[c] = 0;
     for (int f = 0; f < P.nfreq; ++f) dS[size_t(f) * kpad + c] = 0.0;
   }
+  if (tid < 6) keys[tid] = kNoKey;
   if (tid == 0) {
     wk[0] = k;
     wk[1] = st->exact ? 0 : 1;
-    if (odd) st->flips = 0;
+    // the start of the next segment: no pending update, an empty panel,
+    // exact scores (those the refresh computes), every key slot empty
+    st->m = -1;
+    st->kpanel = 0;
+    st->n_since = 0;
+    st->exact = 1;
+    st->need_refresh = 0;
+    st->flips = 0;
   }
 }
 

@@ -1023,7 +1023,8 @@ int mixed_residual(pngf_handle* h, double* ratio) {
 // the batch of steps it follows, before the host has read that batch's end
 // state: the parity fix of the buffers, the flip list, its scales and the
 // measurement gate come from the device (k_wood_prep, which also records the
-// design C^-1 will hold); the block-Woodbury update runs on kpad = k_refresh
+// design C^-1 will hold and starts the next segment: state bookkeeping and
+// key slots); the block-Woodbury update runs on kpad = k_refresh
 // columns (padding entries: pixel 0 with scale 0, which leave the result
 // unchanged); then the field re-formation (which also writes C0^-1), the FP64
 // rescoring and, when the scores were FP32, the band measurement.  If the
@@ -1074,8 +1075,12 @@ int refresh_ahead(pngf_handle* h) {
     st = reform_fields(h);
   }
   if (st) return st;
-  st = start_segment(h, true);
-  if (st) return st;
+  {
+    // the segment's start was done by k_wood_prep
+    Timer t(h, KID_SCORE);
+    HIPCHK(h, pngf::launch_score_rows(P, h->npl, nullptr, nd, P.keys, h->stream));
+    t.end();
+  }
   if (h->opt.guard <= 0.0)
     HIPCHK(h, pngf::launch_band_measure(P.df32, P.dfb, P.df, nd, at<double>(h, L.off_bandout),
                                         nullptr, h->stream, at<double>(h, L.off_band), wk + 1));
