@@ -355,98 +355,120 @@ __global__ __launch_bounds__(kSmallInvThreads) void k_small_inverse(z64* A, int 
   for (int e = tid; e < k * k; e += kSmallInvThreads) A[e] = M[cur][e / k][cmap[e % k]];
 }
 
-// The same inverse for k <= kWaveInv by one wave, with no row ever moved:
+// The same inverse for k <= kWaveInv by four waves, with no row ever moved:
 // column c takes as pivot p_c the row, not yet a pivot, with the largest
 // |a_rc| (compared as the float of |a_rc|^2; the first of equals), and the
 // in-place result M then satisfies A^-1[c][p_l] = M[p_c][l] (Gauss-Jordan on
-// the row-permuted matrix, its rows left where they are).  Lane (r, h) =
-// (lane % 32, lane / 32) holds entries [16h, 16h + 16) of row r in
-// registers.  Per column: the pivot by a wave maximum of (|a|^2, row) keys,
-// the pivot row and every row's factor through LDS (one barrier), then 16
-// complex updates per lane.  status is set on a zero pivot.
+// the row-permuted matrix, its rows left where they are).  Wave v holds
+// columns [8v, 8v + 8), lane (r, h) = (lane % 32, lane / 32) the four
+// entries [8v + 4h, 8v + 4h + 4) of row r in registers.  Column C is
+// prepared by the wave that holds it, right after its own update for column
+// C - 1: the pivot p (a DPP maximum of (|a|^2, row) keys), 1/a_pC (hardware
+// reciprocal and two Newton steps) and every row's entry a_rC go to LDS (two
+// copies by parity, so one barrier per column).  Every wave then takes the
+// pivot row's entries of its own columns from lanes p and p + 32
+// (cross-lane permute) and forms a <- alpha a + beta u for its four entries
+// per lane, u the pivot row: alpha = 0 and beta = 1/p for the pivot row (the
+// row scaled, 1/p in column C), alpha = 1 and beta = -a_iC/p elsewhere
+// (column C becomes -a_iC/p, every other entry is reduced).  Columns run in
+// groups of four (a loop), the four of a group unrolled so that a lane's
+// entry in column C is a fixed register.  status is set on a zero pivot.
 constexpr int kWaveInv = 32;
 
-struct WaveInvLds {
-  z64 prow[2][kWaveInv];   // pivot row (1 in the pivot column), by column parity
-  z64 fac[2][kWaveInv];    // every row's entry in the pivot column
-  int pv[kWaveInv];        // pivot row of each column
+struct WgInvLds {
+  z64 fac[2][kWaveInv];   // every row's entry in the pivot column
+  z64 inv[2];             // 1 / pivot
+  int p[2];               // pivot row
+  int pv[kWaveInv];       // pivot row of each column
+  int rowq[kWaveInv];     // column each row is the pivot of (-1: none)
 };
 
-// Column C = 16 hc + CC of the one-wave Gauss-Jordan inverse (CC fixed at
-// compile time, so the lanes holding column C read it from a fixed register;
-// the two halves hc run as a loop, which keeps the code small enough for the
-// instruction cache).  The pivot (largest |a|^2 among the rows not yet
-// pivoted) comes from a DPP maximum of (|a|^2, row) keys; its two lanes post
-// the raw pivot row to LDS, one lane puts 1 in its column C, and every lane
-// then forms a <- alpha a + beta u with u the posted row: alpha = 0 and beta
-// = 1/p for the pivot row (the row scaled, 1/p in column C), alpha = 1 and
-// beta = -a_iC/p elsewhere (column C becomes -a_iC/p, every other entry is
-// reduced).  1/p from the hardware reciprocal and two Newton steps.
-template <int CC>
-__device__ __forceinline__ void wave_inv_column(z64 (&w)[16], int hc, int k, int r, int h,
-                                                int lane, int& myq, WaveInvLds& sm,
-                                                int32_t* status) {
-  const int C = 16 * hc + CC;
-  if (C >= k) return;
-  constexpr int buf = CC & 1;
+// Posts column C's pivot row, 1 / pivot and the column's entries (run by
+// the wave holding column C; x = the lane's entry in column C).
+__device__ __forceinline__ void wg_inv_post(z64 x, int C, int k, int r, int h, int lane,
+                                            uint32_t used, WgInvLds& sm) {
+  const int b = C & 1;
+  const int hs = (C >> 2) & 1;
   uint32_t key = 0;
-  if (h == hc && r < k && myq < 0)
-    key = (__float_as_uint(float(zabs2(w[CC]))) & ~31u) | uint32_t(31 - r);
+  if (h == hs && r < k && !((used >> r) & 1u))
+    key = (__float_as_uint(float(zabs2(x))) & ~31u) | uint32_t(31 - r);
   const int p = 31 - int(wave_max_u32(key) & 31u);
-  const int pl = p + kWaveInv * hc;
-  const z64 apc{lane_d(w[CC].re, pl), lane_d(w[CC].im, pl)};
-  if (!(zabs2(apc) > 0.0) && lane == 0) atomicOr(status, 1);
-  const z64 inv = zrecip_newton(apc);   // 0 for a zero pivot
-  const bool piv = r == p;
-  if (piv) {
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) sm.prow[buf][16 * h + jj] = w[jj];
-    myq = C;
-  }
-  if (h == hc) sm.fac[buf][r] = w[CC];
+  const int pl = p + 32 * hs;
+  const z64 apc{lane_d(x.re, pl), lane_d(x.im, pl)};
+  if (h == hs) sm.fac[b][r] = x;
   if (lane == 0) {
+    sm.p[b] = p;
+    sm.inv[b] = zrecip_newton(apc);   // 0 for a zero pivot
+  }
+}
+
+// Column C = 4 g + RC.
+template <int RC>
+__device__ __forceinline__ void wg_inv_step(z64 (&a)[4], int g, int k, int r, int h, int lane,
+                                            int wv, int c0, uint32_t& used, WgInvLds& sm,
+                                            int32_t* status) {
+  const int C = 4 * g + RC;
+  if (C >= k) return;
+  lds_barrier();
+  const int b = C & 1;
+  const int p = sm.p[b];
+  const z64 inv = sm.inv[b];
+  const z64 f = sm.fac[b][r];
+  if (threadIdx.x == 0) {
+    if (!(zabs2(inv) > 0.0)) atomicOr(status, 1);   // zero pivot
     sm.pv[C] = p;
-    sm.prow[buf][C] = z64{1.0, 0.0};   // after the pivot lanes' store (one wave: in order)
+    sm.rowq[p] = C;
   }
-  __syncthreads();
-  const z64 fi = zmul(sm.fac[buf][r], inv);
+  // the next column's entry first: the wave holding that column posts it
+  // as soon as it is updated
+  const int src = p + 32 * h;
+  z64 u[4];
+#pragma unroll
+  for (int o = 1; o <= 4; ++o) u[(RC + o) & 3] = lane_bperm(a[(RC + o) & 3], src);
+  used |= 1u << p;
+  const bool piv = r == p;
+  const bool mycol = c0 == 4 * g;   // this lane holds column C (as entry RC)
+  const z64 fi = zmul(f, inv);
   const z64 beta = piv ? inv : z64{-fi.re, -fi.im};
-  const double alpha = piv ? 0.0 : 1.0;
 #pragma unroll
-  for (int jj = 0; jj < 16; ++jj) {
-    z64 x = zscale(w[jj], alpha);
-    if (jj == CC && h == hc) x = z64{0.0, 0.0};
-    w[jj] = zfma(beta, sm.prow[buf][16 * h + jj], x);
+  for (int o = 1; o <= 4; ++o) {
+    const int q = (RC + o) & 3;
+    const z64 x = piv ? z64{0.0, 0.0} : a[q];
+    const z64 y = zfma(beta, u[q], x);
+    // column C itself: 0 reduced by beta times the unit entry of the row
+    a[q] = (q == RC && mycol) ? beta : y;
   }
+  if (C + 1 < k && wv == ((C + 1) >> 3))
+    wg_inv_post(a[(RC + 1) & 3], C + 1, k, r, h, lane, used, sm);
 }
 
-template <int... CCs>
-__device__ __forceinline__ void wave_inv_half(z64 (&w)[16], int hc, int k, int r, int h, int lane,
-                                              int& myq, WaveInvLds& sm, int32_t* status,
-                                              std::integer_sequence<int, CCs...>) {
-  (wave_inv_column<CCs>(w, hc, k, r, h, lane, myq, sm, status), ...);
-}
-
-__global__ __launch_bounds__(64) void k_small_inverse_wave(z64* A, int k, int32_t* status) {
-  __shared__ WaveInvLds sm;
-  const int lane = threadIdx.x;
-  const int r = lane % kWaveInv, h = lane / kWaveInv;
-  z64 w[16];
+__global__ __launch_bounds__(256) void k_small_inverse_wg(z64* A, int k, int32_t* status) {
+  __shared__ WgInvLds sm;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  const int r = lane & 31, h = lane >> 5;
+  const int c0 = 8 * wv + 4 * h;   // this lane's first column
+  z64 a[4];
 #pragma unroll
-  for (int jj = 0; jj < 16; ++jj) {
-    const int l = 16 * h + jj;
-    w[jj] = (r < k && l < k) ? A[r * k + l] : z64{0.0, 0.0};
+  for (int q = 0; q < 4; ++q)
+    a[q] = (r < k && c0 + q < k) ? A[r * k + c0 + q] : z64{0.0, 0.0};
+  if (t < kWaveInv) sm.rowq[t] = -1;
+  uint32_t used = 0;   // rows already pivots (the same in every lane)
+  if (wv == 0) wg_inv_post(a[0], 0, k, r, h, lane, used, sm);
+#pragma unroll 1
+  for (int g = 0; 4 * g < k; ++g) {
+    wg_inv_step<0>(a, g, k, r, h, lane, wv, c0, used, sm, status);
+    wg_inv_step<1>(a, g, k, r, h, lane, wv, c0, used, sm, status);
+    wg_inv_step<2>(a, g, k, r, h, lane, wv, c0, used, sm, status);
+    wg_inv_step<3>(a, g, k, r, h, lane, wv, c0, used, sm, status);
   }
-  int myq = -1;   // the column this lane's row is the pivot of
-  for (int hc = 0; hc < 2; ++hc)
-    wave_inv_half(w, hc, k, r, h, lane, myq, sm, status, std::make_integer_sequence<int, 16>{});
-  __syncthreads();
-  if (r < k && myq >= 0)
+  lds_barrier();
+  if (r < k) {
+    const int q = sm.rowq[r];
+    if (q >= 0)
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-      const int l = 16 * h + jj;
-      if (l < k) A[myq * k + sm.pv[l]] = w[jj];
-    }
+      for (int e = 0; e < 4; ++e)
+        if (c0 + e < k) A[q * k + sm.pv[c0 + e]] = a[e];
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -582,7 +604,7 @@ hipError_t launch_small_inverse(z64* A, int k, int32_t* status, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   if (k > kSmallInv) return hipErrorInvalidValue;
   if (k <= kWaveInv)
-    hipLaunchKernelGGL(k_small_inverse_wave, dim3(1), dim3(64), 0, s, A, k, status);
+    hipLaunchKernelGGL(k_small_inverse_wg, dim3(1), dim3(256), 0, s, A, k, status);
   else
     hipLaunchKernelGGL(k_small_inverse, dim3(1), dim3(kSmallInvThreads), 0, s, A, k, status);
   return hipGetLastError();
