@@ -228,8 +228,12 @@ int pngf_bind(pngf_handle *h, const pngf_options *o, void *dev_ws, size_t bytes,
  * C0^-1 = (I - k0^2 G diag(deps))^-1 (its PEC counterpart above), E = C0^-1 b,
  * the output row
  * R' = G_OD (I + k0^2 diag(deps) C0^-1 G) and x (Direct binary search: the
- * inverse of the initial system matrix is found and stored).  FP64 LU with
- * partial pivoting on the GPU.  PNGF_ESINGULAR on a zero pivot. */
+ * inverse of the initial system matrix is found and stored).  FP64 on the
+ * GPU: blocked Gauss-Jordan without row exchanges, checked by a probe
+ * residual, and with the pivot search where that check fails.  Returns once
+ * the inversion is queued: the check runs when the handle is next used (any
+ * call below that needs a design, pngf_inverse_stats, pngf_kernel_times),
+ * which then reports PNGF_ESINGULAR for a zero pivot and drops the design. */
 int pngf_set_design(pngf_handle *h, const uint8_t *bits);
 
 /* Current objective f, outputs x cplx[nfreq] and (optional, may be NULL)

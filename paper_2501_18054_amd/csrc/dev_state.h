@@ -36,6 +36,7 @@ struct DbsState {
   int32_t flips;       // updates since the buffers were last normalized
                        // (odd: the current vectors/matrix live in the B set)
   int32_t pad1;
+  double f_start;      // objective when the current search started
 };
 
 // Optional index maps of a complex GEMM (nullptr = identity):

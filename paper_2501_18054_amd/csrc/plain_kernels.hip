@@ -305,6 +305,31 @@ __global__ void k_segment_start(DbsState* st, uint32_t* keys, int reset_panel) {
   }
 }
 
+// Start of a search: the bookkeeping of the state reset, its objective and
+// outputs (from the last re-formation of the fields) kept, the objective
+// also recorded as the search's starting value.
+__global__ void k_state_begin(DbsState* st, int n_sweeps, double eta) {
+  if (threadIdx.x != 0) return;
+  st->f_start = st->f;
+  st->m = -1;
+  st->done = 0;
+  st->cursor_s = 0;
+  st->cursor_pos = 0;
+  st->n_acc = 0;
+  st->sweeps = 0;
+  st->converged = 0;
+  st->n_sweeps = n_sweeps;
+  st->attempts = 0;
+  st->key = kNoKey;
+  st->eta = eta;
+  st->need_refresh = 0;
+  st->flips = 0;
+  st->kpanel = 0;   // the mixed search's panel and refresh bookkeeping
+  st->n_since = 0;
+  st->exact = 1;
+  st->n_band = 0;
+}
+
 // ------------------------------------------------------------------ launchers
 #define PNGF_NPL_SWITCH(npl, CALL) \
   switch (npl) {                   \
@@ -323,6 +348,11 @@ hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int
 #define L_(N) hipLaunchKernelGGL(k_score_rows<N>, dim3(ncand), dim3(kRowThreads), 0, s, P, cand, ncand, keyp)
   PNGF_NPL_SWITCH(npl, L_)
 #undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_state_begin(DbsState* st, int n_sweeps, double eta, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_begin, dim3(1), dim3(64), 0, s, st, n_sweeps, eta);
   return hipGetLastError();
 }
 

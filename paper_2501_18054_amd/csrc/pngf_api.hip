@@ -61,6 +61,7 @@ int model_hw(pngf_model* m, int* H, int* W);
 hipStream_t model_stream(pngf_model* m);
 hipError_t launch_select_prep(const ProbDev& P, int forced, hipStream_t s);
 hipError_t launch_segment_start(const ProbDev& P, int reset_panel, hipStream_t s);
+hipError_t launch_state_begin(DbsState* st, int n_sweeps, double eta, hipStream_t s);
 hipError_t launch_accept_rescore(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_inverse(z64* S, z64* Cinv, const z64* G, int nd, int ld, const int32_t* sidx,
                           const int32_t* zidx, const int32_t* pos, int ns, double k2d, z64* B1,
@@ -92,7 +93,9 @@ constexpr size_t kStageOrders = 1024;        // visiting orders in the staging a
 static_assert(kPinUpload + 256 + kMaxFreq * 64 * sizeof(double) <= kPinState &&
                   kPinState + sizeof(DbsState) <= kPinBytes,
               "pinned scratch regions overlap");
-constexpr size_t kPinStage = kPinBytes;      // then the batch-end read (state .. bits)
+constexpr size_t kPinInvStatus = 64;        // status of an initial inverse checked later
+constexpr size_t kPinStage = kPinBytes;      // then the batch-end read (state .. bits), then
+                                             // the index lists of an initial inverse
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
 constexpr int kWoodMax = 64;       // flips folded by one FP64 block-Woodbury refresh
 constexpr int kBatchRefreshStreams = 4;   // streams a batch spreads one round's refreshes over
@@ -181,6 +184,12 @@ struct pngf_handle {
   size_t pin_bytes = 0;
   hipEvent_t ev_pin = nullptr;     // recorded after the last upload from `pin`
   hipEvent_t ev_ahead = nullptr;   // after a batch's state read, ahead of its refresh
+  // an initial inverse queued by set_design and not yet checked: its status
+  // lands at pin + kPinInvStatus, ev_inv is recorded after that read, and its
+  // index lists go up from pin + pin_idx (a region nothing else writes)
+  bool inv_pending = false;
+  hipEvent_t ev_inv = nullptr;
+  size_t pin_idx = 0;
   std::vector<int32_t> w_fl;
   std::vector<double> w_sc;
   bool wood_pending = false;       // a Woodbury status not yet read
@@ -337,10 +346,15 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
 template <class T>
 T* at(pngf_handle* h, size_t off) { return reinterpret_cast<T*>(h->ws + off); }
 
-int check_ready(pngf_handle* h, bool need_design) {
+int settle_inverse(pngf_handle* h, bool* redone = nullptr);
+
+// A bound handle (with a design if need_design; its initial inverse then
+// checked, unless settle is false and the caller checks it later).
+int check_ready(pngf_handle* h, bool need_design, bool settle = true) {
   if (!h) return PNGF_EINVAL;
   if (!h->bound) return fail(h, PNGF_ESTATE, "handle is not bound to a workspace");
   if (need_design && !h->have_design) return fail(h, PNGF_ESTATE, "no design set");
+  if (need_design && settle) return settle_inverse(h);
   return PNGF_OK;
 }
 
@@ -476,10 +490,20 @@ pngf::NpWork np_work(pngf_handle* h, int f) {
 // host_bits: h->bits already holds the device design (no read back).  The
 // fields are re-formed before the inversion's status is read (one wait for
 // both; the rare rejected result is re-formed again after the pivot search).
-int device_reinvert(pngf_handle* h, bool host_bits = false) {
+// With defer (no kernel timing), the unpivoted result is not waited for: its
+// status goes to pinned memory behind an event, and settle_inverse checks it
+// when the handle is next used.  pivot_only skips the unpivoted attempt.
+int device_reinvert(pngf_handle* h, bool host_bits = false, bool defer = false,
+                    bool pivot_only = false) {
   const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
   const Layout& L = h->lay;
   pngf::ProbDev& P = h->P;
+  if (h->inv_pending) {
+    // a queued initial inverse this one replaces: its index-list copies must
+    // have run before the region is written again
+    HIPCHK(h, hipEventSynchronize(h->ev_inv));
+    h->inv_pending = false;
+  }
   int32_t* status = at<int32_t>(h, L.off_status);
   HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
   // S (pixels at eps_hi) and Z from the device design bits
@@ -498,23 +522,17 @@ int device_reinvert(pngf_handle* h, bool host_bits = false) {
   int32_t* d_sidx = at<int32_t>(h, L.off_sidx);
   int32_t* d_zidx = at<int32_t>(h, L.off_zidx);
   int32_t* d_pos = at<int32_t>(h, L.off_pos);
-  // the index lists go up from the pinned staging area when they fit (this
-  // call waits before it returns, so the area is free again then)
-  const int32_t* src_s = sidx.data();
-  const int32_t* src_z = zidx.data();
-  const int32_t* src_p = pos.data();
-  const int32_t* src_m = rowmap.data();
-  if (3 * size_t(nd) * sizeof(int32_t) <= h->pin_bytes - pngf::kPinStage) {
-    auto* stg = reinterpret_cast<int32_t*>(h->pin + pngf::kPinStage);
-    std::copy(sidx.begin(), sidx.end(), stg);
-    std::copy(zidx.begin(), zidx.end(), stg + ns);
-    std::copy(pos.begin(), pos.end(), stg + nd);
-    std::copy(rowmap.begin(), rowmap.end(), stg + 2 * nd);
-    src_s = stg;
-    src_z = stg + ns;
-    src_p = stg + nd;
-    src_m = stg + 2 * nd;
-  }
+  // the index lists go up from their own pinned region (written again only
+  // after this inversion's event, see above)
+  auto* stg = reinterpret_cast<int32_t*>(h->pin + h->pin_idx);
+  std::copy(sidx.begin(), sidx.end(), stg);
+  std::copy(zidx.begin(), zidx.end(), stg + ns);
+  std::copy(pos.begin(), pos.end(), stg + nd);
+  std::copy(rowmap.begin(), rowmap.end(), stg + 2 * nd);
+  const int32_t* src_s = stg;
+  const int32_t* src_z = stg + ns;
+  const int32_t* src_p = stg + nd;
+  const int32_t* src_m = stg + 2 * nd;
   if (ns > 0)
     HIPCHK(h, hipMemcpyAsync(d_sidx, src_s, ns * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   if (nd - ns > 0)
@@ -527,9 +545,9 @@ int device_reinvert(pngf_handle* h, bool host_bits = false) {
   // exchanges, and with the pivot search where that result fails its check
   // (or always, with PNGF_FLAG_PIVOT_SEARCH)
   const bool force_piv = (h->opt.flags & PNGF_FLAG_PIVOT_SEARCH) != 0;
-  for (int pass = force_piv ? 1 : 0; pass < 2; ++pass) {
+  for (int pass = (force_piv || pivot_only) ? 1 : 0; pass < 2; ++pass) {
     const bool pivoted = pass == 1;
-    if (pivoted && !force_piv)
+    if (pivoted && !force_piv && !pivot_only)
       HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
     {
       Timer t(h, KID_LU);
@@ -552,6 +570,15 @@ int device_reinvert(pngf_handle* h, bool host_bits = false) {
     }
     int st = reform_fields(h);
     if (st) return st;
+    if (defer && !pivoted && !(h->opt.flags & PNGF_FLAG_TIMING)) {
+      auto* sp = reinterpret_cast<int32_t*>(h->pin + pngf::kPinInvStatus);
+      HIPCHK(h, hipMemcpyAsync(sp, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipEventRecord(h->ev_inv, h->stream));
+      h->inv_pending = true;
+      h->bits_ref = h->bits;
+      h->cinv_stale = false;
+      return PNGF_OK;
+    }
     int32_t st_host = 0;
     HIPCHK(h, hipMemcpyAsync(&st_host, status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -564,6 +591,30 @@ int device_reinvert(pngf_handle* h, bool host_bits = false) {
   h->bits_ref = h->bits;
   h->cinv_stale = false;
   return PNGF_OK;
+}
+
+// The check of an initial inverse that set_design queued without waiting:
+// waits for its status, and where the unpivoted result failed its probe
+// residual inverts again with the pivot search (*redone then says that the
+// fields were formed again, after anything queued since).  A zero pivot
+// drops the design.
+int settle_inverse(pngf_handle* h, bool* redone) {
+  if (redone) *redone = false;
+  if (!h->inv_pending) return PNGF_OK;
+  h->inv_pending = false;
+  HIPCHK(h, hipEventSynchronize(h->ev_inv));
+  const int32_t st_host = *reinterpret_cast<const int32_t*>(h->pin + pngf::kPinInvStatus);
+  int st = PNGF_OK;
+  if (st_host == 0) {
+    ++h->n_inv_np;
+  } else if (st_host & 2) {
+    if (redone) *redone = true;
+    st = device_reinvert(h, true, false, true);
+  } else {
+    st = fail(h, PNGF_ESINGULAR, "zero pivot while inverting the PNGF system matrix");
+  }
+  if (st) h->have_design = false;
+  return st;
 }
 
 // Block-Woodbury update of the FP64 inverse in P.Cinv (eq. lru_woodbury,
@@ -1441,9 +1492,11 @@ int run_rform(pngf_handle* h, pngf::DbsState* pinned) {
 
 
 // Validate and upload the sweep orders and reset the search bookkeeping of a
-// bound handle with a design; returns the initial objective in *f0.
-int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double* f0) {
-  int st = check_ready(h, true);
+// bound handle with a design (queued, no wait; the state records the initial
+// objective as f_start).  The design's initial inverse is checked by the
+// caller, after this is queued.
+int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps) {
+  int st = check_ready(h, true, false);
   if (st) return st;
   const int nd = h->pc.n_d;
   if (!perms || n_sweeps < 1 || n_sweeps > h->opt.max_sweeps)
@@ -1474,27 +1527,6 @@ int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double*
                            h->stream));
   HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->P.rank), src_r, pb, hipMemcpyHostToDevice,
                            h->stream));
-  pngf::DbsState s;
-  st = read_state(h, &s);
-  if (st) return st;
-  *f0 = s.f;
-  s.m = -1;
-  s.done = 0;
-  s.cursor_s = 0;
-  s.cursor_pos = 0;
-  s.n_acc = 0;
-  s.sweeps = 0;
-  s.converged = 0;
-  s.n_sweeps = n_sweeps;
-  s.attempts = 0;
-  s.key = pngf::kNoKey;
-  s.eta = h->opt.eta;
-  s.need_refresh = 0;
-  s.flips = 0;
-  s.kpanel = 0;   // the mixed search's panel and refresh bookkeeping
-  s.n_since = 0;
-  s.exact = 1;
-  s.n_band = 0;
   // every search starts from the initial error band (it is recalibrated at
   // each FP64 re-inversion), so repeated runs are identical
   h->P.band = (h->opt.guard > 0.0) ? h->opt.guard : 1e-3;
@@ -1504,18 +1536,16 @@ int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, double*
   h->nacc_seen = 0;
   h->persist_ok = false;
   h->persist_aborted = false;
-  // stream-ordered, from the pinned staging area (read back into only after
-  // this copy, on the same stream): no wait
-  static_assert(sizeof(pngf::DbsState) <= pngf::kStageOrders, "state overlaps the orders");
-  auto* ps = reinterpret_cast<pngf::DbsState*>(h->pin + pngf::kPinStage);
-  *ps = s;
-  HIPCHK(h, hipMemcpyAsync(h->P.st, ps, sizeof(s), hipMemcpyHostToDevice, h->stream));
+  // the state's bookkeeping reset on the device (its objective, from the
+  // fields of the current design, becomes the search's starting value): no
+  // round trip
+  HIPCHK(h, pngf::launch_state_begin(h->P.st, n_sweeps, h->opt.eta, h->stream));
   return PNGF_OK;
 }
 
 // Copy the accept log and fill the result summary.
-int dbs_epilogue(pngf_handle* h, const pngf::DbsState& fin, double f0, int64_t n_refresh,
-                 int64_t n_band, int32_t* accepted, double* f_trace, pngf_dbs_result* res) {
+int dbs_epilogue(pngf_handle* h, const pngf::DbsState& fin, int64_t n_refresh, int64_t n_band,
+                 int32_t* accepted, double* f_trace, pngf_dbs_result* res) {
   const int nd = h->pc.n_d;
   const int na = fin.n_acc;
   // logs and design through the pinned staging area: three copies, one wait
@@ -1544,7 +1574,7 @@ int dbs_epilogue(pngf_handle* h, const pngf::DbsState& fin, double f0, int64_t n
     res->n_refresh = int32_t(n_refresh);
     res->attempts = fin.attempts;
     res->n_verified = n_band;
-    res->f_initial = f0;
+    res->f_initial = fin.f_start;
     res->f_final = fin.f;
   }
   h->f_host = fin.f;
@@ -1645,6 +1675,12 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
     return fail(h, PNGF_EINVAL, "workspace must be 256-byte aligned");
   Layout L = make_layout(h, o);
   if (bytes < L.total) return fail(h, PNGF_ENOMEM, "workspace too small");
+  if (h->inv_pending) {
+    // an initial inverse still queued on the old binding: let it finish (its
+    // result is dropped with the design)
+    HIPCHK(h, hipEventSynchronize(h->ev_inv));
+    h->inv_pending = false;
+  }
   h->opt = *o;
   h->lay = L;
   h->bits_fresh = false;
@@ -1753,10 +1789,13 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   HIPCHK(h, hipMemsetAsync(at<int32_t>(h, L.off_pbar), 0, pngf::kPersistBarBytes, h->stream));
   {
     // the staging area holds a batch-end read (state .. design buffers) or,
-    // at a search's end, its logs and design
-    const size_t need = pngf::kPinStage +
-                        std::max(L.off_bitsB + nd - L.off_state,
-                                 12 * size_t(std::max(1, o->max_accepts)) + size_t(nd) + 16);
+    // at a search's end, its logs and design; the index lists of an initial
+    // inverse follow in a region of their own
+    const size_t stage = pngf::kPinStage +
+                         std::max(L.off_bitsB + nd - L.off_state,
+                                  12 * size_t(std::max(1, o->max_accepts)) + size_t(nd) + 16);
+    h->pin_idx = (stage + 255) & ~size_t(255);
+    const size_t need = h->pin_idx + 3 * size_t(nd) * sizeof(int32_t);
     if (h->pin && h->pin_bytes < need) {
       (void)hipHostFree(h->pin);
       h->pin = nullptr;
@@ -1769,6 +1808,7 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   HIPCHK(h, hipMemsetAsync(at<int32_t>(h, L.off_flag), 0, sizeof(int32_t), h->stream));
   if (!h->ev_pin) HIPCHK(h, hipEventCreateWithFlags(&h->ev_pin, hipEventDisableTiming));
   if (!h->ev_ahead) HIPCHK(h, hipEventCreateWithFlags(&h->ev_ahead, hipEventDisableTiming));
+  if (!h->ev_inv) HIPCHK(h, hipEventCreateWithFlags(&h->ev_inv, hipEventDisableTiming));
   HIPCHK(h, hipEventRecord(h->ev_pin, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->bound = true;
@@ -1791,7 +1831,8 @@ int pngf_set_design(pngf_handle* h, const uint8_t* bits) {
   st = write_state(h, &s);
   if (st) return st;
   h->have_design = false;
-  st = device_reinvert(h, true);
+  // the unpivoted inverse is queued and checked when the handle is next used
+  st = device_reinvert(h, true, true);
   if (st) return st;
   h->have_design = true;
   return PNGF_OK;
@@ -1917,9 +1958,17 @@ int pngf_refresh(pngf_handle* h) {
 
 int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t* accepted,
                  double* f_trace, pngf_dbs_result* res) {
-  double f0 = 0.0;
-  int st = dbs_prologue(h, perms, n_sweeps, &f0);
+  int st = dbs_prologue(h, perms, n_sweeps);
   if (st) return st;
+  // the uploads above are queued behind a deferred initial inverse; its
+  // check comes now, and a re-inversion means starting the state again
+  bool redone = false;
+  st = settle_inverse(h, &redone);
+  if (st) return st;
+  if (redone) {
+    st = dbs_prologue(h, perms, n_sweeps);
+    if (st) return st;
+  }
   // the state reads of the search land in the handle's pinned scratch
   auto* pinned = reinterpret_cast<pngf::DbsState*>(h->pin + pngf::kPinState);
   int64_t n_refresh = 0, n_band = 0;
@@ -1928,7 +1977,7 @@ int pngf_dbs_run(pngf_handle* h, const int32_t* perms, int32_t n_sweeps, int32_t
                                               : run_plain(h, pinned);
   pngf::DbsState fin = *pinned;
   if (rc) return rc;
-  return dbs_epilogue(h, fin, f0, n_refresh, n_band, accepted, f_trace, res);
+  return dbs_epilogue(h, fin, n_refresh, n_band, accepted, f_trace, res);
 }
 
 int pngf_tile_dbs_run(pngf_handle* h, const int32_t* tiles, int32_t n_tiles, int32_t m,
@@ -2085,6 +2134,10 @@ int pngf_set_inverse_check(pngf_handle* h, double tol) {
 
 int pngf_inverse_stats(pngf_handle* h, int64_t* unpivoted, int64_t* pivoted) {
   if (!h) return PNGF_EINVAL;
+  if (h->inv_pending) {
+    const int st = settle_inverse(h);
+    if (st) return st;
+  }
   if (unpivoted) *unpivoted = h->n_inv_np;
   if (pivoted) *pivoted = h->n_inv_piv;
   return PNGF_OK;
@@ -2092,6 +2145,10 @@ int pngf_inverse_stats(pngf_handle* h, int64_t* unpivoted, int64_t* pivoted) {
 
 int pngf_kernel_times(pngf_handle* h, int32_t kid, double* total_ms, int64_t* launches) {
   if (!h || kid < 0 || kid >= KID_N) return PNGF_EINVAL;
+  if (h->inv_pending) {
+    const int st = settle_inverse(h);
+    if (st) return st;
+  }
   if (total_ms) *total_ms = h->ktime_ms[kid];
   if (launches) *launches = h->klaunch[kid];
   return PNGF_OK;
@@ -2099,6 +2156,7 @@ int pngf_kernel_times(pngf_handle* h, int32_t kid, double* total_ms, int64_t* la
 
 int pngf_destroy(pngf_handle* h) {
   if (!h) return PNGF_OK;
+  if (h->inv_pending) (void)hipEventSynchronize(h->ev_inv);   // its copy lands in `pin`
   for (size_t k = 0; k + 2 < h->ev_pool.size(); k += 3) {
     hipEventDestroy(h->ev_pool[k]);
     hipEventDestroy(h->ev_pool[k + 1]);
@@ -2108,6 +2166,7 @@ int pngf_destroy(pngf_handle* h) {
   if (h->pin) (void)hipHostFree(h->pin);
   if (h->ev_pin) (void)hipEventDestroy(h->ev_pin);
   if (h->ev_ahead) (void)hipEventDestroy(h->ev_ahead);
+  if (h->ev_inv) (void)hipEventDestroy(h->ev_inv);
   delete h;
   return PNGF_OK;
 }
@@ -2142,8 +2201,7 @@ int ranked_search(pngf_handle* h, pngf_model* m, int H, int W, int32_t max_accep
   }
   std::vector<int32_t> ident(nd);
   for (int i = 0; i < nd; ++i) ident[i] = i;
-  double f0 = 0.0;
-  int st = dbs_prologue(h, ident.data(), 1, &f0);
+  int st = dbs_prologue(h, ident.data(), 1);
   if (st) return st;
   h->ranked = true;
   h->rank_model = m;
@@ -2161,7 +2219,7 @@ int ranked_search(pngf_handle* h, pngf_model* m, int H, int W, int32_t max_accep
   h->rank_model = nullptr;
   h->P.max_acc = max_acc;
   if (rc) return rc;
-  st = dbs_epilogue(h, fin, f0, n_refresh, n_band, accepted, f_trace, res);
+  st = dbs_epilogue(h, fin, n_refresh, n_band, accepted, f_trace, res);
   if (st) return st;
   if (res) {
     // chunks scored beyond the first of each state (one per state visited)
@@ -2608,12 +2666,17 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
   if (!b || !b->bound) return bfail(b, PNGF_ESTATE, "batch is not bound");
   if (!perms || !n_sweeps) return bfail(b, PNGF_EINVAL, "null perms / n_sweeps");
   const int n = int(b->hs.size());
-  std::vector<double> f0(n, 0.0);
   std::vector<int64_t> nref(n, 0), nband(n, 0);
+  // every problem's initial inverse checked first
+  for (int p = 0; p < n; ++p) {
+    pngf_handle* h = b->hs[p];
+    int st = check_ready(h, true);
+    if (st) return bfail(b, st, std::string("problem ") + std::to_string(p) + ": " + h->err);
+  }
   // per-problem start: prologue, FP32 copies (mixed), scoring into key slot 0
   for (int p = 0; p < n; ++p) {
     pngf_handle* h = b->hs[p];
-    int st = dbs_prologue(h, perms[p], n_sweeps[p], &f0[p]);
+    int st = dbs_prologue(h, perms[p], n_sweeps[p]);
     if (st) return bfail(b, st, std::string("problem ") + std::to_string(p) + ": " + h->err);
     if (b->mixed) {
       st = capture_ref_bits(h);
@@ -2805,7 +2868,7 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
     pngf_handle* h = b->hs[p];
     pngf::DbsState fin;
     if (read_state(h, &fin)) { rc = bfail(b, PNGF_EDEVICE, h->err); break; }
-    if (dbs_epilogue(h, fin, f0[p], nref[p], nband[p], accepted ? accepted[p] : nullptr,
+    if (dbs_epilogue(h, fin, nref[p], nband[p], accepted ? accepted[p] : nullptr,
                      f_trace ? f_trace[p] : nullptr, results ? &results[p] : nullptr)) {
       rc = bfail(b, PNGF_ENUMERIC, h->err);
       break;

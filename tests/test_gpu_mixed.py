@@ -167,3 +167,36 @@ def test_singular_refresh_recovery(step_launches):
     _check(res, [a[2] for a in g["accepted"]], g["attempts"],
            [a[3] for a in g["accepted"]], g["f_final"])
     h.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "plain"])
+def test_search_after_failed_unpivoted_check(precision):
+    """set_design returns with its inverse queued; the search's start checks
+    it.  With the check forced to fail (zero tolerance) the search must run
+    on the pivot-searched inverse: the start state is formed again after the
+    re-inversion, so the trajectory, its initial objective and the final
+    fields equal the oracle's."""
+    g = golden(1)
+    if g is None:
+        pytest.skip("golden trajectory for workload 1 not generated")
+    p = workloads.config1()
+    prec = P.PNGF_MIXED if precision == "mixed" else P.PNGF_FP64_PLAIN
+    say(f"config1 {precision} search straight after a failed unpivoted check")
+    h = P.Handle(p).bind(P.default_options(precision=prec, k_refresh=32, max_accepts=8192,
+                                           max_sweeps=8))
+    h.set_inverse_check(0.0)
+    h.set_design(p.init_bits)
+    res = h.dbs_run(p.perms)
+    assert h.inverse_stats() == (0, 1)
+    tol = OBJ_TOL if precision == "mixed" else 1e-10
+    _check(res, [a[2] for a in g["accepted"]], g["attempts"],
+           [a[3] for a in g["accepted"]], g["f_final"])
+    assert rel(res["f_trace"], [a[3] for a in g["accepted"]]) < tol
+    assert abs(res["f_initial"] - g["f0"]) < 1e-10 * abs(g["f0"])
+    bits = p.init_bits.copy()
+    for m in res["accepted"]:
+        bits[m] ^= 1
+    f, x, E = h.evaluate(fields=True)
+    Eo, xo = oracle.pngf_state(p, bits, 0)
+    assert rel(E[0], Eo) < 1e-10
+    h.close()
