@@ -565,8 +565,23 @@ __global__ __launch_bounds__(kRowThreads) void k_output(ProbDev P, int f, const 
   __shared__ double red[2 * (kRowThreads / 64)];
   z64 acc{0.0, 0.0};
   const double s = P.k0sq[f] * P.deps;
-  for (int j = threadIdx.x; j < P.nd; j += kRowThreads)
-    if (P.bits[j]) acc = zfma(god[j], zscale(P.E[f][j], s), acc);
+  const z64* E = P.E[f];
+  // four entries per thread per pass, their loads issued together (same
+  // summation order as one at a time)
+  for (int j0 = threadIdx.x; j0 < P.nd; j0 += kGemvUnroll * kRowThreads) {
+    uint32_t bj[kGemvUnroll];
+    z64 gj[kGemvUnroll], ej[kGemvUnroll];
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u) {
+      const int j = min(j0 + u * kRowThreads, P.nd - 1);
+      bj[u] = P.bits[j];
+      gj[u] = god[j];
+      ej[u] = E[j];
+    }
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u)
+      if (j0 + u * kRowThreads < P.nd && bj[u]) acc = zfma(gj[u], zscale(ej[u], s), acc);
+  }
   const z64 t = block_zsum(acc, red);
   if (threadIdx.x == 0) {
     P.st->x[f] = zadd(xb, t);

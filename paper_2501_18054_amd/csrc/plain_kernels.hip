@@ -58,12 +58,19 @@ __global__ __launch_bounds__(kRowThreads) void k_score_rows(ProbDev P, const int
   for (int f = 0; f < P.nfreq; ++f) {
     const z64* C = P.Cinv[f] + size_t(i) * P.ld;
     const z64* Gi = P.G[f] + size_t(i) * P.ld;
-    z64 acc{0.0, 0.0};
+    // every load issued before the first product (an entry past the row
+    // loads a clamped address and is not summed): one memory round trip
+    z64 cv[NPL], gv[NPL];
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
-      const int j = tid + t * kRowThreads;
-      if (j < P.nd) acc = zfma(C[j], Gi[j], acc);
+      const int j = min(tid + t * kRowThreads, P.nd - 1);
+      cv[t] = C[j];
+      gv[t] = Gi[j];
     }
+    z64 acc{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < NPL; ++t)
+      if (tid + t * kRowThreads < P.nd) acc = zfma(cv[t], gv[t], acc);
     const z64 tau = block_zsum(acc, red);
     if (tid == 0) {
       P.tau[f][i] = tau;
