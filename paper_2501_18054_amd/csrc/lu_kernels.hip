@@ -558,6 +558,53 @@ __global__ __launch_bounds__(kRowThreads) void k_gemv2(const z64* A, int ld, int
   }
 }
 
+// The second pass of the re-formation fused with the candidates' tau: for
+// row i of A = C^-1 and row i of G, the products of k_gemv2 (o1, o2, no
+// design scaling) and tau[i] = sum_j A[i,j] G[i,j], all three sums in the
+// order k_gemv2 and the scoring pass use (one pass over both rows instead of
+// one over A and then one over A and G).
+__global__ __launch_bounds__(kRowThreads) void k_gemv2_tau(const z64* A, const z64* G, int ld,
+                                                           int n, GemvOut o1, GemvOut o2,
+                                                           z64* tau) {
+  __shared__ double red[2 * (kRowThreads / 64)];
+  const int i = blockIdx.x;
+  const z64* a = A + size_t(i) * ld;
+  const z64* g = G + size_t(i) * ld;
+  z64 acc1{0.0, 0.0}, acc2{0.0, 0.0}, acc3{0.0, 0.0};
+  for (int j0 = threadIdx.x; j0 < n; j0 += kGemvUnroll * kRowThreads) {
+    z64 aj[kGemvUnroll], gj[kGemvUnroll], v1[kGemvUnroll], v2[kGemvUnroll];
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u) {
+      const int j = min(j0 + u * kRowThreads, n - 1);
+      aj[u] = a[j];
+      gj[u] = g[j];
+      v1[u] = o1.v[j];
+      v2[u] = o2.v[j];
+    }
+#pragma unroll
+    for (int u = 0; u < kGemvUnroll; ++u) {
+      if (j0 + u * kRowThreads < n) {
+        acc1 = zfma(aj[u], v1[u], acc1);
+        acc2 = zfma(aj[u], v2[u], acc2);
+        acc3 = zfma(aj[u], gj[u], acc3);
+      }
+    }
+  }
+  const z64 s1 = block_zsum(acc1, red);
+  const z64 s2 = block_zsum(acc2, red);
+  const z64 s3 = block_zsum(acc3, red);
+  if (threadIdx.x == 0) {
+    for (int h = 0; h < 2; ++h) {
+      const GemvOut& o = h ? o2 : o1;
+      z64 out = zmul(o.alpha, h ? s2 : s1);
+      if (o.w) out = zfma(o.beta, o.w[i], out);
+      if (o.w2) out = zadd(out, zscale(o.w2[i], o.gamma));
+      o.y[i] = out;
+    }
+    tau[i] = s3;
+  }
+}
+
 // x = x_b + k0^2 sum_j god[j] deps_j E[j]; writes x into the DBS state slot f
 // and (on the last frequency) the objective.  One workgroup.
 __global__ __launch_bounds__(kRowThreads) void k_output(ProbDev P, int f, const z64* god, z64 xb,
@@ -983,6 +1030,12 @@ hipError_t launch_gemv(const z64* A, int ld, int n, const z64* v, const uint8_t*
 hipError_t launch_gemv2(const z64* A, int ld, int n, const uint8_t* bits, double ds,
                         const GemvOut& o1, const GemvOut& o2, hipStream_t s) {
   hipLaunchKernelGGL(k_gemv2, dim3(n), dim3(kRowThreads), 0, s, A, ld, n, bits, ds, o1, o2);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv2_tau(const z64* A, const z64* G, int ld, int n, const GemvOut& o1,
+                            const GemvOut& o2, z64* tau, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv2_tau, dim3(n), dim3(kRowThreads), 0, s, A, G, ld, n, o1, o2, tau);
   return hipGetLastError();
 }
 

@@ -86,6 +86,27 @@ __global__ __launch_bounds__(kRowThreads) void k_score_rows(ProbDev P, const int
   }
 }
 
+// The scoring epilogue of every pixel from tau, E and R' already formed (by
+// the fused re-formation pass): the same objective change and key as
+// k_score_rows, one thread per pixel, the keys of a wave reduced to one
+// atomic.
+__global__ __launch_bounds__(256) void k_score_tail(ProbDev P, uint32_t* keyp) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const DbsState* st = P.st;
+  uint32_t k = kNoKey;
+  if (i < P.nd) {
+    const double delta = P.bits[i] ? -P.deps : P.deps;
+    double df = 0.0;
+    for (int f = 0; f < P.nfreq; ++f)
+      df += flip_df(P, st, f, P.tau[f][i], P.E[f][i], P.Rp[f][i], delta);
+    P.df[i] = df;
+    if (keyp && df > st->eta * st->f) k = cand_key(P, st, i);
+  }
+  // wave minimum of the keys (the maximum of their complements)
+  k = ~wave_max_u32(~k);
+  if (keyp && (threadIdx.x & 63) == 0 && k != kNoKey) atomicMin(keyp, k);
+}
+
 // K2: select the first improving candidate in visiting order (the minimum
 // key), advance the cursor, form the update scalars of the accepted flip and
 // stage q = C^-1[m,:].  forced >= 0 accepts that pixel instead.
@@ -355,6 +376,11 @@ hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int
 #define L_(N) hipLaunchKernelGGL(k_score_rows<N>, dim3(ncand), dim3(kRowThreads), 0, s, P, cand, ncand, keyp)
   PNGF_NPL_SWITCH(npl, L_)
 #undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_score_tail(const ProbDev& P, uint32_t* keyp, hipStream_t s) {
+  hipLaunchKernelGGL(k_score_tail, dim3((P.nd + 255) / 256), dim3(256), 0, s, P, keyp);
   return hipGetLastError();
 }
 

@@ -29,6 +29,9 @@ hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, const in
 hipError_t launch_accept_only(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_gemv2(const z64* A, int ld, int n, const uint8_t* bits, double ds,
                         const GemvOut& o1, const GemvOut& o2, hipStream_t s);
+hipError_t launch_gemv2_tau(const z64* A, const z64* G, int ld, int n, const GemvOut& o1,
+                            const GemvOut& o2, z64* tau, hipStream_t s);
+hipError_t launch_score_tail(const ProbDev& P, uint32_t* keyp, hipStream_t s);
 hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_t* ca,
                         const z64* B, int ldb, bool transb, const int32_t* rb, z64* C, int ldc,
                         z64 alpha, z64 beta, int splits, z64* work, hipStream_t s,
@@ -435,8 +438,10 @@ void collect_times(pngf_handle* h) {
 
 // E = C^-1 b with one step of FP64 iterative refinement against C, then
 // R' = G_OD (I + k0^2 D C^-1 G) = G_OD + k0^2 C^-1 (G D G_OD) (reciprocity)
-// and the outputs, for the design in P.bits and the C^-1 in P.Cinv.
-int reform_fields(pngf_handle* h) {
+// and the outputs, for the design in P.bits and the C^-1 in P.Cinv.  With
+// tau, the second pass over C^-1 also forms every candidate's tau (reading
+// the rows of G beside those of C^-1), for k_score_tail.
+int reform_fields(pngf_handle* h, bool tau = false) {
   const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
   const Layout& L = h->lay;
   pngf::ProbDev& P = h->P;
@@ -461,7 +466,10 @@ int reform_fields(pngf_handle* h) {
     // one pass over C^-1:  E += C^-1 r,  R' = G_OD + k0^2 C^-1 u
     const pngf::GemvOut o_e{r, one, one, P.E[f], 0.0, nullptr, P.E[f]};
     const pngf::GemvOut o_p{u, z64{k2, 0.0}, one, god, 0.0, nullptr, P.Rp[f]};
-    HIPCHK(h, pngf::launch_gemv2(P.Cinv[f], ld, nd, nullptr, 0.0, o_e, o_p, h->stream));
+    if (tau)
+      HIPCHK(h, pngf::launch_gemv2_tau(P.Cinv[f], P.G[f], ld, nd, o_e, o_p, P.tau[f], h->stream));
+    else
+      HIPCHK(h, pngf::launch_gemv2(P.Cinv[f], ld, nd, nullptr, 0.0, o_e, o_p, h->stream));
     const cd xb = h->pc.freq[f].xb;
     HIPCHK(h, pngf::launch_output(P, f, god, z64{xb.real(), xb.imag()}, f == F - 1, h->stream));
     t.end();
@@ -1123,13 +1131,13 @@ int refresh_ahead(pngf_handle* h) {
   int st;
   {
     C64Pass c64pass(h);
-    st = reform_fields(h);
+    st = reform_fields(h, true);   // with every candidate's tau
   }
   if (st) return st;
   {
     // the segment's start was done by k_wood_prep
     Timer t(h, KID_SCORE);
-    HIPCHK(h, pngf::launch_score_rows(P, h->npl, nullptr, nd, P.keys, h->stream));
+    HIPCHK(h, pngf::launch_score_tail(P, P.keys, h->stream));
     t.end();
   }
   if (h->opt.guard <= 0.0)
