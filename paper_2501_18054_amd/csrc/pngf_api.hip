@@ -197,6 +197,7 @@ struct pngf_handle {
   std::vector<double> w_sc;
   bool wood_pending = false;       // a Woodbury status not yet read
   bool rescore_pending = false;    // refresh_rescore queued a read of that status
+  bool tau_fresh = false;          // the last fp64_refresh formed every candidate's tau
   double f_host = 0.0;
   // event timing
   double ktime_ms[KID_N] = {0};
@@ -722,9 +723,10 @@ int woodbury_update(pngf_handle* h, const std::vector<int32_t>& fl, const std::v
 // singular.  Then E (with one refinement step), R' and x are re-formed.
 // defer: the Woodbury status is left for the caller's next wait
 // (wood_pending), which must re-invert if it reports a singular update.
-int fp64_refresh(pngf_handle* h, bool defer = false) {
+int fp64_refresh(pngf_handle* h, bool defer = false, bool tau = false) {
   const int nd = h->pc.n_d;
   pngf::ProbDev& P = h->P;
+  h->tau_fresh = false;
   const bool fresh = h->bits_fresh;
   h->bits_fresh = false;
   if (h->opt.precision == PNGF_FP64_PLAIN || h->bits_ref.size() != size_t(nd))
@@ -747,8 +749,9 @@ int fp64_refresh(pngf_handle* h, bool defer = false) {
     if (st) return st;
     if (singular) return device_reinvert(h);
   }
-  int st = reform_fields(h);
+  int st = reform_fields(h, tau);
   if (st) return st;
+  h->tau_fresh = tau;
   h->bits_ref = cur;
   h->cinv_stale = false;
   return PNGF_OK;
@@ -827,6 +830,22 @@ int start_segment(pngf_handle* h, bool reset_panel = false) {
   {
     Timer t(h, KID_SCORE);
     HIPCHK(h, pngf::launch_score_rows(h->P, h->npl, nullptr, h->pc.n_d, h->P.keys, h->stream));
+    t.end();
+  }
+  if (h->ranked) return rank_chain(h, 0);
+  return PNGF_OK;
+}
+
+// start_segment(h, true) right after an FP64 refresh: when that refresh
+// formed every candidate's tau beside the fields, the scores come from it
+// (k_score_tail, no pass over C^-1 and G).
+int start_segment_refreshed(pngf_handle* h) {
+  if (!h->tau_fresh) return start_segment(h, true);
+  h->tau_fresh = false;
+  HIPCHK(h, pngf::launch_segment_start(h->P, 1, h->stream));
+  {
+    Timer t(h, KID_SCORE);
+    HIPCHK(h, pngf::launch_score_tail(h->P, h->P.keys, h->stream));
     t.end();
   }
   if (h->ranked) return rank_chain(h, 0);
@@ -976,7 +995,7 @@ struct C64Pass {
 // are valid after the next wait on the bound stream (refresh_settle).
 int refresh_rescore(pngf_handle* h, bool measure) {
   const int nd = h->pc.n_d;
-  int st = start_segment(h, true);
+  int st = start_segment_refreshed(h);
   if (st) return st;
   double* mo = reinterpret_cast<double*>(h->pin + 8);
   mo[0] = 0.0;
@@ -1037,12 +1056,12 @@ int mixed_refresh(pngf_handle* h, bool measure, bool nosync = false) {
   int st;
   {
     C64Pass c64pass(h);
-    st = fp64_refresh(h, true);
+    st = fp64_refresh(h, true, true);
   }
   if (st) return st;
   if (nosync) {
     double* dband = (h->opt.guard <= 0.0) ? at<double>(h, h->lay.off_band) : nullptr;
-    st = start_segment(h, true);
+    st = start_segment_refreshed(h);
     if (st) return st;
     if (measure && dband)
       HIPCHK(h, pngf::launch_band_measure(h->P.df32, h->P.dfb, h->P.df, nd,
@@ -2485,7 +2504,7 @@ int batch_refresh_launch(pngf_batch* b, const std::vector<int>& ref,
     int st;
     if (rescore) {
       C64Pass c64pass(h);
-      st = fp64_refresh(h, true);
+      st = fp64_refresh(h, true, true);
     } else {
       st = fp64_refresh(h, true);
     }
