@@ -107,6 +107,80 @@ __global__ __launch_bounds__(256) void k_score_tail(ProbDev P, uint32_t* keyp) {
   if (keyp && (threadIdx.x & 63) == 0 && k != kNoKey) atomicMin(keyp, k);
 }
 
+// The end of a single-frequency refresh in one workgroup, three passes in
+// one launch: x = x_b + k0^2 sum_j god_j deps_j E_j and f (the first 256
+// threads, in k_output's order), then every pixel's objective change and key
+// from tau, E and R' (as k_score_tail), and, with bandp, the error band from
+// the largest |df64 - df32| / bound over the pixels (as k_band_measure: out
+// = {max, 0}, band = clamp(100 max) when gate is unset or nonzero).
+constexpr int kTailThreads = 1024;
+__global__ __launch_bounds__(kTailThreads) void k_refresh_tail(ProbDev P, const z64* god, z64 xb,
+                                                               uint32_t* keyp, const double* df32,
+                                                               const double* dfb, double* out,
+                                                               double* bandp, const int32_t* gate) {
+  __shared__ double red[2 * (kTailThreads / 64)];
+  const int tid = threadIdx.x;
+  DbsState* st = P.st;
+  z64 acc{0.0, 0.0};
+  if (tid < kRowThreads) {
+    const double s = P.k0sq[0] * P.deps;
+    const z64* E = P.E[0];
+    for (int j0 = tid; j0 < P.nd; j0 += 4 * kRowThreads) {
+      uint32_t bj[4];
+      z64 gj[4], ej[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = min(j0 + u * kRowThreads, P.nd - 1);
+        bj[u] = P.bits[j];
+        gj[u] = god[j];
+        ej[u] = E[j];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j0 + u * kRowThreads < P.nd && bj[u]) acc = zfma(gj[u], zscale(ej[u], s), acc);
+    }
+  }
+  // the other waves add zeros after the first four's sums (the same result)
+  const z64 t = block_zsum(acc, red);
+  if (tid == 0) {
+    // f in the operation order k_output is compiled to (explicit fused
+    // multiply-adds, so that both give the same bits)
+    const z64 x = zadd(xb, t);
+    st->x[0] = x;
+    st->f = fma(P.coef[0], fma(x.re, x.re, x.im * x.im), 0.0);
+  }
+  __syncthreads();
+  const bool meas = bandp && (!gate || *gate != 0);
+  uint32_t kmin = kNoKey;
+  double mx = 0.0;
+  for (int i = tid; i < P.nd; i += kTailThreads) {
+    const double delta = P.bits[i] ? -P.deps : P.deps;
+    double df = 0.0;
+    df += flip_df(P, st, 0, P.tau[0][i], P.E[0][i], P.Rp[0][i], delta);
+    P.df[i] = df;
+    if (keyp && df > st->eta * st->f) kmin = min(kmin, cand_key(P, st, i));
+    if (meas) {
+      const double b = dfb[i];
+      if (b > 0.0) mx = fmax(mx, fabs(df - df32[i]) / b);
+    }
+  }
+  kmin = ~wave_max_u32(~kmin);
+  if (keyp && (tid & 63) == 0 && kmin != kNoKey) atomicMin(keyp, kmin);
+  if (meas) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    if (tid == 0) {
+      double m = 0.0;
+      for (int w = 0; w < kTailThreads / 64; ++w) m = fmax(m, red[w]);
+      out[0] = m;
+      out[1] = 0.0;
+      if (isfinite(m)) *bandp = fmin(1e-2, fmax(1e-6, 100.0 * m));
+    }
+  }
+}
+
 // K2: select the first improving candidate in visiting order (the minimum
 // key), advance the cursor, form the update scalars of the accepted flip and
 // stage q = C^-1[m,:].  forced >= 0 accepts that pixel instead.
@@ -381,6 +455,15 @@ hipError_t launch_score_rows(const ProbDev& P, int npl, const int32_t* cand, int
 
 hipError_t launch_score_tail(const ProbDev& P, uint32_t* keyp, hipStream_t s) {
   hipLaunchKernelGGL(k_score_tail, dim3((P.nd + 255) / 256), dim3(256), 0, s, P, keyp);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_tail(const ProbDev& P, const z64* god, z64 xb, uint32_t* keyp,
+                               const double* df32, const double* dfb, double* out, double* bandp,
+                               const int32_t* gate, hipStream_t s) {
+  if (P.nfreq != 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_refresh_tail, dim3(1), dim3(kTailThreads), 0, s, P, god, xb, keyp, df32,
+                     dfb, out, bandp, gate);
   return hipGetLastError();
 }
 

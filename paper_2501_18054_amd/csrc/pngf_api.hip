@@ -32,6 +32,9 @@ hipError_t launch_gemv2(const z64* A, int ld, int n, const uint8_t* bits, double
 hipError_t launch_gemv2_tau(const z64* A, const z64* G, int ld, int n, const GemvOut& o1,
                             const GemvOut& o2, z64* tau, hipStream_t s);
 hipError_t launch_score_tail(const ProbDev& P, uint32_t* keyp, hipStream_t s);
+hipError_t launch_refresh_tail(const ProbDev& P, const z64* god, z64 xb, uint32_t* keyp,
+                               const double* df32, const double* dfb, double* out, double* bandp,
+                               const int32_t* gate, hipStream_t s);
 hipError_t launch_zgemm(int M, int N, int K, const z64* A, int lda, const int32_t* ca,
                         const z64* B, int ldb, bool transb, const int32_t* rb, z64* C, int ldc,
                         z64 alpha, z64 beta, int splits, z64* work, hipStream_t s,
@@ -441,8 +444,9 @@ void collect_times(pngf_handle* h) {
 // R' = G_OD (I + k0^2 D C^-1 G) = G_OD + k0^2 C^-1 (G D G_OD) (reciprocity)
 // and the outputs, for the design in P.bits and the C^-1 in P.Cinv.  With
 // tau, the second pass over C^-1 also forms every candidate's tau (reading
-// the rows of G beside those of C^-1), for k_score_tail.
-int reform_fields(pngf_handle* h, bool tau = false) {
+// the rows of G beside those of C^-1), for k_score_tail.  Without output the
+// outputs x and f are left to the caller (k_refresh_tail).
+int reform_fields(pngf_handle* h, bool tau = false, bool output = true) {
   const int nd = h->pc.n_d, ld = h->ld, F = int(h->pc.freq.size());
   const Layout& L = h->lay;
   pngf::ProbDev& P = h->P;
@@ -472,7 +476,8 @@ int reform_fields(pngf_handle* h, bool tau = false) {
     else
       HIPCHK(h, pngf::launch_gemv2(P.Cinv[f], ld, nd, nullptr, 0.0, o_e, o_p, h->stream));
     const cd xb = h->pc.freq[f].xb;
-    HIPCHK(h, pngf::launch_output(P, f, god, z64{xb.real(), xb.imag()}, f == F - 1, h->stream));
+    if (output)
+      HIPCHK(h, pngf::launch_output(P, f, god, z64{xb.real(), xb.imag()}, f == F - 1, h->stream));
     t.end();
   }
   return PNGF_OK;
@@ -1150,18 +1155,22 @@ int refresh_ahead(pngf_handle* h) {
   int st;
   {
     C64Pass c64pass(h);
-    st = reform_fields(h, true);   // with every candidate's tau
+    st = reform_fields(h, true, false);   // with every candidate's tau, x left to the tail
   }
   if (st) return st;
   {
-    // the segment's start was done by k_wood_prep
+    // x and f, every candidate's score and key (the segment's start was done
+    // by k_wood_prep), and the band measurement when the scores were FP32
     Timer t(h, KID_SCORE);
-    HIPCHK(h, pngf::launch_score_tail(P, P.keys, h->stream));
+    const cd xb = h->pc.freq[0].xb;
+    const bool band = h->opt.guard <= 0.0;
+    HIPCHK(h, pngf::launch_refresh_tail(P, at<z64>(h, L.off_god[0]), z64{xb.real(), xb.imag()},
+                                        P.keys, P.df32, P.dfb,
+                                        band ? at<double>(h, L.off_bandout) : nullptr,
+                                        band ? at<double>(h, L.off_band) : nullptr, wk + 1,
+                                        h->stream));
     t.end();
   }
-  if (h->opt.guard <= 0.0)
-    HIPCHK(h, pngf::launch_band_measure(P.df32, P.dfb, P.df, nd, at<double>(h, L.off_bandout),
-                                        nullptr, h->stream, at<double>(h, L.off_band), wk + 1));
   h->bits_fresh = false;
   return PNGF_OK;
 }
