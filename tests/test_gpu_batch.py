@@ -144,6 +144,32 @@ def test_batch_matches_oracle(oracle_batch, stream, prec):
         h.close()
 
 
+def test_batch_after_failed_unpivoted_checks(oracle_batch, stream):
+    """set_design leaves each initial inverse to be checked when the handle
+    is next used; the batch checks every problem before its first step.  With
+    the check forced to fail (zero tolerance) on every other problem, those
+    are inverted again with the pivot search and the batch still follows
+    each oracle trajectory."""
+    g, probs = oracle_batch
+    k = g["max_accepts"]
+    say(f"batch of {len(probs)} vs oracle, mixed, every other inverse check forced to fail")
+    handles = [P.Handle(p).bind(P.default_options(precision=P.PNGF_MIXED, k_refresh=8,
+                                                  max_accepts=k, max_sweeps=2), stream=stream)
+               for p in probs]
+    for j, (h, p) in enumerate(zip(handles, probs)):
+        if j % 2 == 0:
+            h.set_inverse_check(0.0)
+        h.set_design(p.init_bits)
+    b = P.Batch(handles)
+    out = b.dbs_run([p.perms[:2] for p in probs])
+    for j, (q, r, h) in enumerate(zip(g["problems"], out, handles)):
+        assert h.inverse_stats() == ((0, 1) if j % 2 == 0 else (1, 0)), q["seed"]
+        _check_against_oracle(q, r, h, 1e-6)
+    b.close()
+    for h in handles:
+        h.close()
+
+
 @pytest.mark.parametrize("prec", ["plain", "mixed", "rform"])
 def test_large_solo_searches_match_oracle(oracle_batch, prec):
     """The same problems searched one at a time: every dispatch of the step
