@@ -378,15 +378,22 @@ int pngf_batch_set_grid(pngf_batch *b, int32_t grid);
 /* Run DBS on every problem: perms[p] / n_sweeps[p] as for pngf_dbs_run;
  * accepted[p], f_trace[p] (capacity max_accepts of handle p, may be NULL) and
  * results[p] receive each problem's outcome.  autotune != 0 times the
- * candidate launch shapes on the first replays (identical arithmetic) and
- * keeps the fastest; pngf_batch_tuning reports the timings. */
+ * candidate launch shapes (grid sizes; for MIXED handles also work items of
+ * eight or four rows) on the first replays (identical arithmetic), one shape
+ * per round, and keeps the fastest per streamed matrix entry (a round's time
+ * over the sum of N_d^2 x frequencies of its active problems, since problems
+ * sit out rounds for their refreshes); pngf_batch_tuning reports the
+ * timings. */
 int pngf_batch_dbs_run(pngf_batch *b, const int32_t *const *perms, const int32_t *n_sweeps,
                        int32_t *const *accepted, double *const *f_trace,
                        pngf_dbs_result *results, int32_t autotune);
 
-/* Autotuner record of the last run: grids[k] and device ms per step. */
-int pngf_batch_tuning(pngf_batch *b, int32_t *grids, double *ms_per_step, int32_t cap,
-                      int32_t *n);
+/* Autotuner record of the last run, one entry per launch shape tried:
+ * grids[k] (0 = one workgroup per work item), rows[k] (rows per work item:
+ * 8 or 4 for MIXED handles, 1 for FP64 rows) and device ms per step; any of
+ * the arrays may be NULL, *n receives the number of entries. */
+int pngf_batch_tuning(pngf_batch *b, int32_t *grids, int32_t *rows, double *ms_per_step,
+                      int32_t cap, int32_t *n);
 
 /* Device ms per batched step of the last replay (HIP events). */
 int pngf_batch_ms_per_step(pngf_batch *b, double *ms);

@@ -103,7 +103,7 @@ EXPORTS = {
     "pngf_batch_set_grid": ([C.c_void_p, C.c_int32], C.c_int),
     "pngf_batch_dbs_run": ([C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p, C.POINTER(C.c_void_p),
                             C.POINTER(C.c_void_p), C.c_void_p, C.c_int32], C.c_int),
-    "pngf_batch_tuning": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+    "pngf_batch_tuning": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                            C.POINTER(C.c_int32)], C.c_int),
     "pngf_batch_ms_per_step": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "pngf_batch_destroy": ([C.c_void_p], C.c_int),
@@ -438,11 +438,15 @@ class Batch:
         return out
 
     def tuning(self):
-        g = np.empty(16, np.int32)
-        ms = np.empty(16, np.float64)
+        """[(grid, rows per work item, device ms per step)] of the shapes tried."""
+        g = np.empty(32, np.int32)
+        rows = np.empty(32, np.int32)
+        ms = np.empty(32, np.float64)
         n = C.c_int32()
-        self._check(lib().pngf_batch_tuning(self._b, _ptr(g), _ptr(ms), 16, C.byref(n)))
-        return list(zip(g[:n.value].tolist(), ms[:n.value].tolist()))
+        self._check(lib().pngf_batch_tuning(self._b, _ptr(g), _ptr(rows), _ptr(ms), 32,
+                                            C.byref(n)))
+        k = n.value
+        return list(zip(g[:k].tolist(), rows[:k].tolist(), ms[:k].tolist()))
 
     def ms_per_step(self):
         v = C.c_double()

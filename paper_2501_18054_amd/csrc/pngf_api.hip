@@ -25,7 +25,8 @@ hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint64_t* 
                                 const int32_t* wstat, hipStream_t s);
 hipError_t launch_fold_q(const ProbDev& P, int f, int kp, hipStream_t s);
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, const int32_t* nact,
-                             int total, int grid, int npl, int mixed, int step, hipStream_t s);
+                             int total, int grid, int npl, int mixed, int rpw, int step,
+                             hipStream_t s);
 hipError_t launch_accept_only(const ProbDev& P, int npl, hipStream_t s);
 hipError_t launch_gemv2(const z64* A, int ld, int n, const uint8_t* bits, double ds,
                         const GemvOut& o1, const GemvOut& o2, hipStream_t s);
@@ -2413,17 +2414,18 @@ struct pngf_batch {
   int32_t* d_row0 = nullptr;            // [n+1] item offsets of the active problems
   int32_t* d_nact = nullptr;            // the active count the step kernel reads
   pngf::DbsState* d_states = nullptr;   // [2n]: A and B slot of every problem
-  int total_all = 0;                    // work items of all problems
   int npl = 1;
   int mixed = 0;
-  int grid = 0;                         // 0 = one workgroup per row
+  int grid = 0;                         // 0 = one workgroup per work item
+  int rpw = 2;                          // mixed: rows per wave (a work item is 4 rpw rows)
   bool bound = false;
   // captured 6-step graph for the launch shape (any active set)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int g_total = -1, g_grid = -1;
+  int g_total = -1, g_grid = -1, g_rpw = -1;
   // autotuner record
-  std::vector<int32_t> tune_grid;
+  std::vector<int32_t> tune_grid, tune_rpw;
+  std::vector<double> tune_work;        // streamed entries per step of each timed round
   std::vector<double> tune_ms;
   double last_ms_per_step = 0.0;
   // streams the refreshes of one round are spread over (default priority),
@@ -2457,7 +2459,7 @@ void drop_graph(pngf_batch* b) {
   if (b->graph) hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
-  b->g_total = b->g_grid = -1;
+  b->g_total = b->g_grid = b->g_rpw = -1;
 }
 
 void release_refresh_streams(pngf_batch* b) {
@@ -2562,7 +2564,12 @@ int batch_refresh_settle(pngf_batch* b, const std::vector<int>& ref,
 // count, which the step kernel reads on the device) and, for a new launch
 // shape, capture the 6-step graph (one full cycle of state parity and key
 // slot).  The graph does not depend on the active set.
-int batch_prepare(pngf_batch* b, const std::vector<int>& active, int grid) {
+int batch_items(const pngf_batch* b, int nd, int rpw) {
+  // work items of one problem: rows (FP64), groups of 4 rpw rows (mixed)
+  return b->mixed ? (nd + 4 * rpw - 1) / (4 * rpw) : nd;
+}
+
+int batch_prepare(pngf_batch* b, const std::vector<int>& active, int grid, int rpw) {
   const int n = int(active.size());
   if (n == 0) return PNGF_OK;
   std::vector<pngf::ProbDev> probs;
@@ -2570,21 +2577,22 @@ int batch_prepare(pngf_batch* b, const std::vector<int>& active, int grid) {
   for (int q = 0; q < n; ++q) {
     const pngf_handle* h = b->hs[active[q]];
     probs.push_back(h->P);
-    const int nd = h->pc.n_d;   // work items: rows (FP64), row groups (mixed)
-    row0[q + 1] = row0[q] + (b->mixed ? (nd + pngf::kMixRows - 1) / pngf::kMixRows : nd);
+    row0[q + 1] = row0[q] + batch_items(b, h->pc.n_d, rpw);
   }
+  int total = 0;   // items of every problem (the launch covers any active set)
+  for (const pngf_handle* h : b->hs) total += batch_items(b, h->pc.n_d, rpw);
   row0[b->hs.size() + 1] = n;   // d_nact follows d_row0[0..n_all]
   BHIPCHK(b, hipMemcpyAsync(b->d_probs, probs.data(), n * sizeof(pngf::ProbDev),
                             hipMemcpyHostToDevice, b->stream));
   BHIPCHK(b, hipMemcpyAsync(b->d_row0, row0.data(), row0.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, b->stream));
   BHIPCHK(b, hipStreamSynchronize(b->stream));
-  if (b->exec && b->g_total == b->total_all && b->g_grid == grid) return PNGF_OK;
+  if (b->exec && b->g_total == total && b->g_grid == grid && b->g_rpw == rpw) return PNGF_OK;
   drop_graph(b);
   BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   for (int t = 0; t < 6; ++t) {
-    hipError_t e = pngf::launch_batch_step(b->d_probs, b->d_row0, b->d_nact, b->total_all, grid,
-                                           b->npl, b->mixed, t, b->stream);
+    hipError_t e = pngf::launch_batch_step(b->d_probs, b->d_row0, b->d_nact, total, grid, b->npl,
+                                           b->mixed, rpw, t, b->stream);
     if (e != hipSuccess) {
       hipGraph_t g = nullptr;
       hipStreamEndCapture(b->stream, &g);
@@ -2594,8 +2602,9 @@ int batch_prepare(pngf_batch* b, const std::vector<int>& active, int grid) {
   }
   BHIPCHK(b, hipStreamEndCapture(b->stream, &b->graph));
   BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-  b->g_total = b->total_all;
+  b->g_total = total;
   b->g_grid = grid;
+  b->g_rpw = rpw;
   return PNGF_OK;
 }
 
@@ -2672,9 +2681,6 @@ int pngf_batch_bind(pngf_batch* b, void* dev_ws, size_t bytes, void* stream) {
   b->d_states = reinterpret_cast<pngf::DbsState*>(b->ws + off);
   b->npl = npl;
   b->mixed = (prec == PNGF_MIXED) ? 1 : 0;
-  b->total_all = 0;
-  for (pngf_handle* h : b->hs)
-    b->total_all += b->mixed ? (h->pc.n_d + pngf::kMixRows - 1) / pngf::kMixRows : h->pc.n_d;
   b->bound = true;
   return PNGF_OK;
 }
@@ -2685,12 +2691,13 @@ int pngf_batch_set_grid(pngf_batch* b, int32_t grid) {
   return PNGF_OK;
 }
 
-int pngf_batch_tuning(pngf_batch* b, int32_t* grids, double* ms_per_step, int32_t cap,
-                      int32_t* n) {
+int pngf_batch_tuning(pngf_batch* b, int32_t* grids, int32_t* rows, double* ms_per_step,
+                      int32_t cap, int32_t* n) {
   if (!b || !n) return PNGF_EINVAL;
   *n = int32_t(b->tune_grid.size());
   for (int k = 0; k < std::min<int>(cap, *n); ++k) {
     if (grids) grids[k] = b->tune_grid[k];
+    if (rows) rows[k] = b->mixed ? 4 * b->tune_rpw[k] : 1;
     if (ms_per_step) ms_per_step[k] = b->tune_ms[k];
   }
   return PNGF_OK;
@@ -2766,14 +2773,19 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
   int rc = PNGF_OK;
   // autotuner: candidate launch shapes, each timed on one 6-step replay of
   // the live search (every shape gives bitwise the same per-row arithmetic)
-  std::vector<int> cand;
+  // (grid, rows per wave); the mixed step also tries one row per wave (work
+  // items of four rows: twice the workgroups, each reading g_m per row)
+  std::vector<std::pair<int, int>> cand;
   if (autotune) {
-    cand = {0, 8192, 4096, 2048, 1024};
+    for (int rp : b->mixed ? std::vector<int>{2, 1} : std::vector<int>{2})
+      for (int g : {0, 8192, 4096, 2048, 1024}) cand.emplace_back(g, rp);
     b->tune_grid.clear();
+    b->tune_rpw.clear();
     b->tune_ms.clear();
+    b->tune_work.clear();
   }
   size_t ci = 0;
-  int grid = b->grid;
+  int grid = b->grid, rpw = b->rpw;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
@@ -2791,8 +2803,11 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
     const bool tuning = stepping && ci < cand.size();
     int reps = 0;
     if (stepping) {
-      if (tuning) grid = cand[ci];
-      rc = batch_prepare(b, active, grid);
+      if (tuning) {
+        grid = cand[ci].first;
+        rpw = cand[ci].second;
+      }
+      rc = batch_prepare(b, active, grid, rpw);
       if (rc) break;
       hipEventRecord(e0, b->stream);
       reps = tuning ? 1 : 5;   // 30 steps per round: about one refresh interval
@@ -2822,13 +2837,24 @@ int pngf_batch_dbs_run(pngf_batch* b, const int32_t* const* perms, const int32_t
       hipEventElapsedTime(&ms, e0, e1);
       b->last_ms_per_step = ms / (6.0 * reps);
       if (tuning) {
-        b->tune_grid.push_back(cand[ci]);
+        // the active set differs from round to round (problems sit out for
+        // their refreshes), so shapes are compared per streamed entry: a
+        // step reads N_d^2 entries of every active frequency
+        double work = 0.0;
+        for (int q : active) {
+          const pngf_handle* h = b->hs[q];
+          work += double(h->pc.n_d) * h->pc.n_d * double(h->pc.freq.size());
+        }
+        b->tune_grid.push_back(cand[ci].first);
+        b->tune_rpw.push_back(cand[ci].second);
         b->tune_ms.push_back(ms / 6.0);
+        b->tune_work.push_back(work);
         if (++ci == cand.size()) {
           size_t best = 0;
           for (size_t k = 1; k < b->tune_ms.size(); ++k)
-            if (b->tune_ms[k] < b->tune_ms[best]) best = k;
+            if (b->tune_ms[k] / b->tune_work[k] < b->tune_ms[best] / b->tune_work[best]) best = k;
           b->grid = grid = b->tune_grid[best];
+          b->rpw = rpw = b->tune_rpw[best];
         }
       }
     }

@@ -418,10 +418,11 @@ __device__ inline void plain_step_row(const ProbDev& P, int i, int spar, int ksl
   }
 }
 
-// Mixed step over a group of kWideRows rows, kWideRpw per wave: the wave
-// streams its C0^-1 rows against g_m with 16-byte loads (two complex entries
-// per lane and row; g_m read once for the wave's rows), then lane h <
-// kWideRpw forms p for row h, updates its FP64 E, R', tau and scores it.
+// Mixed step over a group of 4 RPW rows, RPW per wave: the wave streams its
+// C0^-1 rows against g_m with 16-byte loads (two complex entries per lane
+// and row; g_m read once for the wave's rows), then lane h < RPW forms p for
+// row h, updates its FP64 E, R', tau and scores it.  A row's arithmetic does
+// not depend on RPW.
 // The products of the mixed search (complex FP32 with FP32 accumulation,
 // FP64 vectors).  Where the step streams C0^-1 from HBM
 // (many frequencies, large N_d, a batch of problems): more bytes in flight
@@ -429,16 +430,17 @@ __device__ inline void plain_step_row(const ProbDev& P, int i, int spar, int ksl
 constexpr int kWideRpw = 2;
 constexpr int kWideRows = 4 * kWideRpw;
 
+template <int RPW>
 __device__ inline void mixed_step_wide(const ProbDev& P, int g, int spar, int kslot, StepCtx& c,
                                        z64 (*pc)[64], bool publish) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int r0 = g * kWideRows + kWideRpw * w;   // the wave's first row
+  const int r0 = g * (4 * RPW) + RPW * w;   // the wave's first row
   const int dp = spar;
   // the wave's FP64 vectors (E, R', tau) at every frequency, independent of
   // the decision, into LDS
-  __shared__ z64 vpre[4][kMaxFreq][kWideRpw][3];
-  for (int e = lane; e < 3 * kWideRpw * P.nfreq; e += 64) {
-    const int f = e / (3 * kWideRpw), h = (e / 3) % kWideRpw, v = e % 3;
+  __shared__ z64 vpre[4][kMaxFreq][RPW][3];
+  for (int e = lane; e < 3 * RPW * P.nfreq; e += 64) {
+    const int f = e / (3 * RPW), h = (e / 3) % RPW, v = e % 3;
     const int r = r0 + h;
     if (r < P.nd) {
       const z64* src = v == 0 ? (dp ? P.EB[f] : P.E[f])
@@ -449,7 +451,7 @@ __device__ inline void mixed_step_wide(const ProbDev& P, int g, int spar, int ks
   const uint8_t* bin = dp ? P.bitsB : P.bits;
   uint8_t* bout = dp ? P.bits : P.bitsB;
   const int myr = r0 + lane;                 // lane h < 4 owns row r0 + h
-  const bool mine = lane < kWideRpw && myr < P.nd;
+  const bool mine = lane < RPW && myr < P.nd;
   const uint8_t b0 = mine ? bin[myr] : 0;
   if (tid == 0) step_decide(P, spar, kslot, true, c);
   __syncthreads();
@@ -467,28 +469,28 @@ __device__ inline void mixed_step_wide(const ProbDev& P, int g, int spar, int ks
   double df = 0.0, bnd = 0.0;
   const int nd2 = P.nd >> 1;
   // rows past N_d (last group) read row N_d - 1 and are discarded
-  size_t roff[kWideRpw];
+  size_t roff[RPW];
 #pragma unroll
-  for (int h = 0; h < kWideRpw; ++h) roff[h] = size_t(min(r0 + h, P.nd - 1)) * P.ld;
+  for (int h = 0; h < RPW; ++h) roff[h] = size_t(min(r0 + h, P.nd - 1)) * P.ld;
   for (int f = 0; f < P.nfreq; ++f) {
     const z32* gm = P.G32[f] + size_t(m) * P.ld;
     const float4* g4 = reinterpret_cast<const float4*>(gm);
-    const float4* c4[kWideRpw];
+    const float4* c4[RPW];
 #pragma unroll
-    for (int h = 0; h < kWideRpw; ++h) c4[h] = reinterpret_cast<const float4*>(P.C0[f] + roff[h]);
+    for (int h = 0; h < RPW; ++h) c4[h] = reinterpret_cast<const float4*>(P.C0[f] + roff[h]);
     // this group's panel entries, issued ahead of the stream
-    z32 pk[kWideRpw];
+    z32 pk[RPW];
 #pragma unroll
-    for (int h = 0; h < kWideRpw; ++h)
+    for (int h = 0; h < RPW; ++h)
       pk[h] = lane < slot ? P.Pp[f][size_t(lane) * P.ld + min(r0 + h, P.nd - 1)] : z32{0.f, 0.f};
-    float pr[kWideRpw], pi[kWideRpw];
+    float pr[RPW], pi[RPW];
 #pragma unroll
-    for (int h = 0; h < kWideRpw; ++h) pr[h] = pi[h] = 0.f;
+    for (int h = 0; h < RPW; ++h) pr[h] = pi[h] = 0.f;
 #pragma unroll 4
     for (int j = lane; j < nd2; j += 64) {
       const float4 gv = g4[j];
 #pragma unroll
-      for (int h = 0; h < kWideRpw; ++h) {
+      for (int h = 0; h < RPW; ++h) {
         const float4 cv = c4[h][j];
         pr[h] = fmaf(cv.x, gv.x, fmaf(-cv.y, gv.y, pr[h]));
         pi[h] = fmaf(cv.x, gv.y, fmaf(cv.y, gv.x, pi[h]));
@@ -499,7 +501,7 @@ __device__ inline void mixed_step_wide(const ProbDev& P, int g, int spar, int ks
     if ((P.nd & 1) && lane == 0) {   // the last entry of an odd row
       const z32 gv = gm[P.nd - 1];
 #pragma unroll
-      for (int h = 0; h < kWideRpw; ++h) {
+      for (int h = 0; h < RPW; ++h) {
         const z32 cv = P.C0[f][roff[h] + P.nd - 1];
         pr[h] = fmaf(cv.re, gv.re, fmaf(-cv.im, gv.im, pr[h]));
         pi[h] = fmaf(cv.re, gv.im, fmaf(cv.im, gv.re, pi[h]));
@@ -508,14 +510,14 @@ __device__ inline void mixed_step_wide(const ProbDev& P, int g, int spar, int ks
     if (lane < slot) {
       const z64 cc = pc[f][lane];
 #pragma unroll
-      for (int h = 0; h < kWideRpw; ++h) {
+      for (int h = 0; h < RPW; ++h) {
         pr[h] += float(cc.re * pk[h].re - cc.im * pk[h].im);
         pi[h] += float(cc.re * pk[h].im + cc.im * pk[h].re);
       }
     }
     float sr = 0.f, si = 0.f;
 #pragma unroll
-    for (int h = 0; h < kWideRpw; ++h) {
+    for (int h = 0; h < RPW; ++h) {
       const float a = wave_sumf(pr[h]), b = wave_sumf(pi[h]);
       if (lane == h) {
         sr = a;
@@ -1189,20 +1191,20 @@ __global__ __launch_bounds__(kRowThreads) void k_plain_step(ProbDev P, int spar,
 __global__ __launch_bounds__(256) void k_mixed_step(ProbDev P, int spar, int kslot) {
   __shared__ StepCtx c;
   __shared__ z64 pc[kMaxFreq][64];
-  mixed_step_wide(P, blockIdx.x, spar, kslot, c, pc, blockIdx.x == 0);
+  mixed_step_wide<kWideRpw>(P, blockIdx.x, spar, kslot, c, pc, blockIdx.x == 0);
 }
 
 // Batched step: one launch advances every active problem of a batch by one
 // step.  Work item b (a row of one problem on the FP64 path, a group of
-// kMixRows rows on the mixed path) maps to problem p with row0[p] <= b <
+// 4 RPW rows on the mixed path, RPW a tuned launch shape) maps to problem p
+// with row0[p] <= b <
 // row0[p+1], p < *nact (the active count lives on the device, so that one
 // captured launch serves any active set); the grid is either one workgroup
 // per item of the whole batch (surplus workgroups exit) or a persistent grid
 // that strides over the items (launch shape chosen by the autotuner).  Problems
 // are independent (Results, Computational efficiency: per-frequency and
 // per-design systems need no communication).
-static_assert(kWideRows == kMixRows, "a batch work item is one group of kMixRows rows");
-template <int NPL, bool MIXED>
+template <int NPL, bool MIXED, int RPW = kWideRpw>
 __global__ __launch_bounds__(kRowThreads) void k_batch_step(const ProbDev* probs,
                                                             const int32_t* row0,
                                                             const int32_t* nact, int spar,
@@ -1220,7 +1222,7 @@ __global__ __launch_bounds__(kRowThreads) void k_batch_step(const ProbDev* probs
     const ProbDev& P = probs[lo];
     const int i = b - row0[lo];
     __syncthreads();   // the previous item is done with the shared context
-    if (MIXED) mixed_step_wide(P, i, spar, kslot, c, pc, i == 0);
+    if (MIXED) mixed_step_wide<RPW>(P, i, spar, kslot, c, pc, i == 0);
     else plain_step_row<NPL>(P, i, spar, kslot, c);
   }
 }
@@ -1467,13 +1469,20 @@ hipError_t launch_mixed_persist(const ProbDev& P, int t0, int nsteps, uint64_t* 
 }
 
 hipError_t launch_batch_step(const ProbDev* probs, const int32_t* row0, const int32_t* nact,
-                             int total, int grid, int npl, int mixed, int step, hipStream_t s) {
+                             int total, int grid, int npl, int mixed, int rpw, int step,
+                             hipStream_t s) {
   const int g = (grid > 0 && grid < total) ? grid : total;
   if (g <= 0) return hipSuccess;
   if (mixed) {
-    // separate instantiation: the mixed path needs far fewer registers
-    hipLaunchKernelGGL((k_batch_step<1, true>), dim3(g), dim3(kRowThreads), 0, s, probs, row0,
-                       nact, step & 1, step % 3);
+    // separate instantiations: the mixed path needs far fewer registers
+    if (rpw == 1)
+      hipLaunchKernelGGL((k_batch_step<1, true, 1>), dim3(g), dim3(kRowThreads), 0, s, probs,
+                         row0, nact, step & 1, step % 3);
+    else if (rpw == 2)
+      hipLaunchKernelGGL((k_batch_step<1, true, 2>), dim3(g), dim3(kRowThreads), 0, s, probs,
+                         row0, nact, step & 1, step % 3);
+    else
+      return hipErrorInvalidValue;
     return hipGetLastError();
   }
 #define L_(N)                                                                          \
