@@ -100,7 +100,13 @@ constexpr size_t kStageOrders = 1024;        // visiting orders in the staging a
 static_assert(kPinUpload + 256 + kMaxFreq * 64 * sizeof(double) <= kPinState &&
                   kPinState + sizeof(DbsState) <= kPinBytes,
               "pinned scratch regions overlap");
+constexpr size_t kPinBand = 32;             // the error band a search starts from
 constexpr size_t kPinInvStatus = 64;        // status of an initial inverse checked later
+// the small slots: band measurement {max, status} at 8, a Woodbury status at
+// 24, then the band and the inverse status, all below the Woodbury upload
+static_assert(kPinBand >= 28 && kPinBand + sizeof(double) <= kPinInvStatus &&
+                  kPinInvStatus + sizeof(int32_t) <= kPinUpload,
+              "pinned scratch slots overlap");
 constexpr size_t kPinStage = kPinBytes;      // then the batch-end read (state .. bits), then
                                              // the index lists of an initial inverse
 constexpr double kDriftTol = 1e-5; // relative FP64 residual of E that forces a re-inversion
@@ -1551,7 +1557,7 @@ int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps) {
   // on the same stream), else from the caller's memory
   const size_t pb = rank.size() * sizeof(int32_t);
   char* stg = h->pin + pngf::kPinStage;
-  const bool staged = pngf::kStageOrders + 2 * pb <= h->pin_bytes - pngf::kPinStage;
+  const bool staged = pngf::kStageOrders + 2 * pb <= h->pin_idx - pngf::kPinStage;
   const void* src_p = perms;
   const void* src_r = rank.data();
   if (staged) {
@@ -1567,7 +1573,10 @@ int dbs_prologue(pngf_handle* h, const int32_t* perms, int32_t n_sweeps) {
   // every search starts from the initial error band (it is recalibrated at
   // each FP64 re-inversion), so repeated runs are identical
   h->P.band = (h->opt.guard > 0.0) ? h->opt.guard : 1e-3;
-  HIPCHK(h, hipMemcpyAsync(at<double>(h, h->lay.off_band), &h->P.band, sizeof(double),
+  // from pinned memory (a copy from pageable memory can wait for the stream)
+  auto* pband = reinterpret_cast<double*>(h->pin + pngf::kPinBand);
+  *pband = h->P.band;
+  HIPCHK(h, hipMemcpyAsync(at<double>(h, h->lay.off_band), pband, sizeof(double),
                            hipMemcpyHostToDevice, h->stream));
   for (int k = 0; k < KID_N; ++k) { h->ktime_ms[k] = 0.0; h->klaunch[k] = 0; }
   h->nacc_seen = 0;
@@ -1588,7 +1597,7 @@ int dbs_epilogue(pngf_handle* h, const pngf::DbsState& fin, int64_t n_refresh, i
   // logs and design through the pinned staging area: three copies, one wait
   const size_t lpb = (size_t(na) * sizeof(int32_t) + 7) & ~size_t(7);
   char* stg = h->pin + pngf::kPinStage;
-  if (lpb + size_t(na) * sizeof(double) + nd > h->pin_bytes - pngf::kPinStage)
+  if (lpb + size_t(na) * sizeof(double) + nd > h->pin_idx - pngf::kPinStage)
     return fail(h, PNGF_EINVAL, "more accepts than the handle's max_accepts");
   auto* lp = reinterpret_cast<int32_t*>(stg);
   auto* lf = reinterpret_cast<double*>(stg + lpb);
@@ -1825,12 +1834,15 @@ int pngf_bind(pngf_handle* h, const pngf_options* o, void* dev_ws, size_t bytes,
   // the persistent search's barrier words start at generation 0
   HIPCHK(h, hipMemsetAsync(at<int32_t>(h, L.off_pbar), 0, pngf::kPersistBarBytes, h->stream));
   {
-    // the staging area holds a batch-end read (state .. design buffers) or,
-    // at a search's end, its logs and design; the index lists of an initial
-    // inverse follow in a region of their own
-    const size_t stage = pngf::kPinStage +
-                         std::max(L.off_bitsB + nd - L.off_state,
-                                  12 * size_t(std::max(1, o->max_accepts)) + size_t(nd) + 16);
+    // the staging area holds a batch-end read (state .. design buffers), a
+    // search's visiting orders and their ranks, or at a search's end its logs
+    // and design; the index lists of an initial inverse follow in a region of
+    // their own, which nothing else writes (staging stops at pin_idx)
+    const size_t stage =
+        pngf::kPinStage +
+        std::max({L.off_bitsB + nd - L.off_state,
+                  12 * size_t(std::max(1, o->max_accepts)) + size_t(nd) + 16,
+                  pngf::kStageOrders + 2 * size_t(o->max_sweeps) * nd * sizeof(int32_t)});
     h->pin_idx = (stage + 255) & ~size_t(255);
     const size_t need = h->pin_idx + 3 * size_t(nd) * sizeof(int32_t);
     if (h->pin && h->pin_bytes < need) {
