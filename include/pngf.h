@@ -220,7 +220,10 @@ int pngf_workspace_bytes(pngf_handle *h, const pngf_options *o, size_t *bytes);
 
 /* Bind caller-owned device memory (>= pngf_workspace_bytes, 256-byte aligned)
  * and a hipStream_t (NULL = default stream); uploads G, b, G_OD, x_b.
- * PNGF_ENOMEM if bytes is too small. */
+ * PNGF_ENOMEM if bytes is too small.  Memory of an earlier binding may still
+ * be written by an initial inverse that pngf_set_design queued: this call
+ * (and pngf_destroy) first waits for it, so the caller releases that memory
+ * only after either returns. */
 int pngf_bind(pngf_handle *h, const pngf_options *o, void *dev_ws, size_t bytes,
               void *hip_stream);
 

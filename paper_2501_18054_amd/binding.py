@@ -258,14 +258,20 @@ class Handle:
         import torch
         opts = opts or default_options()
         nbytes = self.workspace_bytes(opts)
+        # the old workspace is released only after pngf_bind, which first waits
+        # for work still queued on it (an initial inverse set_design left)
+        old = self._ws
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self._ws.data_ptr()
         aligned = (base + 255) & ~255
         if stream is None:
             stream = torch.cuda.current_stream(torch.device(device))
         self._stream = stream
-        self._check(lib().pngf_bind(self._h, C.byref(opts), C.c_void_p(aligned),
-                                    nbytes, C.c_void_p(stream.cuda_stream)))
+        try:
+            self._check(lib().pngf_bind(self._h, C.byref(opts), C.c_void_p(aligned),
+                                        nbytes, C.c_void_p(stream.cuda_stream)))
+        finally:
+            del old
         self.opts = opts
         return self
 
