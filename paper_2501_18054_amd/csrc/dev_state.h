@@ -47,6 +47,10 @@ struct GemmIdx {
   const int32_t *rc = nullptr, *cc = nullptr;
 };
 
+// Partitions of the unpivoted inversion's residual-check maxima (four words
+// each: the rows' workgroups spread their atomics over them).
+constexpr int kResidParts = 16;
+
 // Workspace of the unpivoted blocked inversion (one per frequency): the
 // reduced panels of two consecutive panels (n_S x kNpNb each, row stride
 // kNpNb), the pivot rows of the current panel (kNpNb x ld), the inverse of

@@ -769,7 +769,7 @@ __global__ __launch_bounds__(256) void k_np_ident(int32_t* piv, int32_t* inv_p, 
     piv[l] = l;
     inv_p[l] = l;
   }
-  if (l < 4) mx[l] = 0ull;
+  if (l < 4 * kResidParts) mx[l] = 0ull;
 }
 
 // The probe vector of the residual check: fixed, entries of modulus <= 1
@@ -797,8 +797,9 @@ __global__ __launch_bounds__(kRowThreads) void k_np_resid_y(const z64* S, int ld
 }
 
 // Row a of K y - v with K = I - k2d G[S,S], the row's sum of |K_ab| and the
-// largest |y_b|, into the maxima mx[0..2] (non-negative doubles compare as
-// their bit patterns).
+// largest |y_b|, into the maxima of partition a % kResidParts, mx[4 p + 0..2]
+// (non-negative doubles compare as their bit patterns; the partitions keep
+// the rows' atomics from queueing on three words).
 __global__ __launch_bounds__(kRowThreads) void k_np_resid_k(const z64* G, int ld,
                                                             const int32_t* sidx, int n, double k2d,
                                                             const z64* y,
@@ -849,18 +850,25 @@ __global__ __launch_bounds__(kRowThreads) void k_np_resid_k(const z64* G, int ld
       ym = fmax(ym, rmax[w]);
     }
     const z64 r = zsub(ky, np_probe(a));
-    atomicMax(&mx[0], static_cast<unsigned long long>(__double_as_longlong(sqrt(zabs2(r)))));
-    atomicMax(&mx[1], static_cast<unsigned long long>(__double_as_longlong(ks)));
-    atomicMax(&mx[2], static_cast<unsigned long long>(__double_as_longlong(ym)));
+    unsigned long long* m = mx + 4 * (a % kResidParts);
+    atomicMax(&m[0], static_cast<unsigned long long>(__double_as_longlong(sqrt(zabs2(r)))));
+    atomicMax(&m[1], static_cast<unsigned long long>(__double_as_longlong(ks)));
+    atomicMax(&m[2], static_cast<unsigned long long>(__double_as_longlong(ym)));
   }
 }
 
 // ||K y - v||_inf <= tol (||K||_inf ||y||_inf + ||v||_inf), else status bit 2
 // (||v||_inf <= 1).
 __global__ void k_np_check(const unsigned long long* mx, double tol, int32_t* status) {
-  const double res = __longlong_as_double(static_cast<long long>(mx[0]));
-  const double kn = __longlong_as_double(static_cast<long long>(mx[1]));
-  const double ym = __longlong_as_double(static_cast<long long>(mx[2]));
+  unsigned long long m0 = 0, m1 = 0, m2 = 0;
+  for (int q = 0; q < kResidParts; ++q) {
+    m0 = max(m0, mx[4 * q]);
+    m1 = max(m1, mx[4 * q + 1]);
+    m2 = max(m2, mx[4 * q + 2]);
+  }
+  const double res = __longlong_as_double(static_cast<long long>(m0));
+  const double kn = __longlong_as_double(static_cast<long long>(m1));
+  const double ym = __longlong_as_double(static_cast<long long>(m2));
   if (!(res <= tol * (kn * ym + 1.0))) atomicOr(status, 2);
 }
 

@@ -328,7 +328,7 @@ Layout make_layout(const pngf_handle* h, const pngf_options* o) {
     // unpivoted inversion: two reduced panels, the pivot rows, the block
     // inverse, the probe product and the check's maxima
     L.off_np[f] = take((3 * size_t(pngf::kNpNb) * ld + size_t(pngf::kNpNb) * pngf::kNpNb + nd) *
-                           sizeof(z64) + 4 * sizeof(unsigned long long));
+                           sizeof(z64) + 4 * pngf::kResidParts * sizeof(unsigned long long));
   }
   L.off_sidx = take(size_t(nd) * sizeof(int32_t));
   L.off_zidx = take(size_t(nd) * sizeof(int32_t));
