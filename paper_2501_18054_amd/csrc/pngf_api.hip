@@ -521,9 +521,11 @@ int device_reinvert(pngf_handle* h, bool host_bits = false, bool defer = false,
   pngf::ProbDev& P = h->P;
   if (h->inv_pending) {
     // a queued initial inverse this one replaces: its index-list copies must
-    // have run before the region is written again
+    // have run before the region is written again (it counts as an
+    // unpivoted inversion if it passed its check)
     HIPCHK(h, hipEventSynchronize(h->ev_inv));
     h->inv_pending = false;
+    if (*reinterpret_cast<const int32_t*>(h->pin + pngf::kPinInvStatus) == 0) ++h->n_inv_np;
   }
   int32_t* status = at<int32_t>(h, L.off_status);
   HIPCHK(h, hipMemsetAsync(status, 0, sizeof(int32_t), h->stream));
