@@ -618,8 +618,8 @@ def main():
                     help="run only the 640x640 / N_d 6400 / 8-frequency leg (for profiling)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py: this build measures one GPU only (the hot path runs on one "
-              "MI355X); multi-GPU runs are not supported", file=sys.stderr)
+        print("bench.py: measures one GPU only (the hot path runs on one MI355X); "
+              "multi-GPU runs are not supported", file=sys.stderr)
         sys.exit(2)
 
     if a.config4_only:

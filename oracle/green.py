@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Definitions (Results, Precomputation: G = B^T A^-1 B over the optimization
-region, G_obj = W^T A^-1 B, x_inc = W^T e_inc), written in this build's field
-form with the background operator L_b (design cells at eps_lo):
+region, G_obj = W^T A^-1 B, x_inc = W^T e_inc), written in the field form
+used throughout, with the background operator L_b (design cells at eps_lo):
 
     G_DD = -(L_b^-1)[D, D],   G_OD = -w^T L_b^-1[:, D],
     E_b = L_b^-1 (i k0 J),    b = E_b[D],   x_b = w^T E_b .
